@@ -1,0 +1,304 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: closed forms, a textbook
+routine, a special case that reduces to a 1D problem with an exact solution, invariants the
+method has, or the paper's printed convergence orders.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from paper_2006_14602_amd import workloads as W
+
+UNIT2 = ((0.0, 0.0), (1.0, 1.0))
+
+
+def grid2(n, lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    return O.GridSpec((n, n), lo, hi)
+
+
+# --- P10: theta = int rho (Sec. 2, normalisation before eq. edp) -----------------------------
+
+def test_theta_ring_close_to_disk_form():
+    # the sech^2 ring lies inside the unit square up to a tail of ~1e-8: the integral over the
+    # inscribed disk of radius 1/2 is (pi/k)[tanh(k(1/4 - r0^2)) + tanh(k r0^2)]
+    mon = W.ring_monitor()
+    th = O.theta_quadrature(mon, *UNIT2)
+    disk = 1.0 + 10.0 * (math.pi / 50.0) * (math.tanh(50.0 * (0.25 - 1.0 / 16.0)) + math.tanh(50.0 / 16.0))
+    assert 0.0 < th - disk < 2e-8
+    # the corner tail is what separates them; integrate it from the radial profile outside r=1/2
+    assert abs(th - 2.2542158532) < 1e-9
+
+
+def test_theta_sine_inner_integral_closed_form():
+    # int_0^1 sech^2(k(y - 1/2 - s)) dy = [tanh(k(1/2 - s)) + tanh(k(1/2 + s))] / k
+    mon = W.sine_monitor()
+    inner = lambda x: (math.tanh(40 * (0.5 - 0.25 * math.sin(2 * math.pi * x)))
+                       + math.tanh(40 * (0.5 + 0.25 * math.sin(2 * math.pi * x)))) / 40.0
+    ref = 1.0 + 20.0 * scipy.integrate.quad(inner, 0, 1, epsabs=1e-15, epsrel=1e-15, limit=400)[0]
+    assert abs(O.theta_quadrature(mon, *UNIT2) - ref) < 1e-12
+    assert abs(ref - 1.99999999963) < 1e-10
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_theta_gauss_erf_vs_quadrature(d):
+    rng = np.random.default_rng(7)
+    mon = {"kind": "gauss_sum", "bamp": [12.0, 25.0], "bw": [0.05, 0.12],
+           "bc": [list(rng.uniform(0, 1, d)), list(rng.uniform(0, 1, d))]}
+    lo, hi = (0.0,) * d, (1.0,) * d
+    assert abs(O.theta_closed_form(mon, lo, hi) - O.theta_quadrature(mon, lo, hi, panels=48 if d == 3 else 128)) < 1e-11
+
+
+def test_theta_separable_closed_form_vs_quadrature():
+    mon = W.separable_monitor((8.0, 5.0), (20.0, 15.0), (0.4, 0.6))
+    assert abs(O.theta_closed_form(mon, *UNIT2) - O.theta_quadrature(mon, *UNIT2)) < 1e-12
+
+
+# --- discrete operators against analytic derivatives (second order, Sec. 3) ------------------
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_fd_hessian_second_order_with_ghosts(d):
+    # phi = eps prod_k cos(m_k pi xi_k) satisfies the homogeneous Neumann condition, so
+    # Psi = |xi|^2/2 + phi satisfies eq. nbd exactly; the FD gradient and Hessian (including the
+    # mixed terms and the corner ghosts) must converge at second order to the analytic ones.
+    eps = 0.01
+    m = (1, 2, 1)[:d]
+    errs = []
+    for n in ((17, 33) if d == 3 else (33, 65)):
+        g = O.GridSpec((n,) * d, (0.0,) * d, (1.0,) * d)
+        box = g.whole_box()
+        X = box.coords()
+        c = [np.cos(m[k] * np.pi * X[..., k]) for k in range(d)]
+        s = [np.sin(m[k] * np.pi * X[..., k]) for k in range(d)]
+        prod = lambda arrs: np.prod(np.stack(arrs), axis=0)
+        psi = 0.5 * np.sum(X * X, axis=-1) + eps * prod(c)
+        grad, hess = O.derivatives(psi, box)
+        e = 0.0
+        for k in range(d):
+            gk = X[..., k] - eps * m[k] * np.pi * prod([s[j] if j == k else c[j] for j in range(d)])
+            e = max(e, np.max(np.abs(grad[k] - gk)))
+            for l in range(d):
+                if l == k:
+                    hk = 1.0 - eps * (m[k] * np.pi) ** 2 * prod(c)
+                else:
+                    hk = eps * m[k] * m[l] * np.pi ** 2 * prod([s[j] if j in (k, l) else c[j] for j in range(d)])
+                e = max(e, np.max(np.abs(hess[k][l] - hk)))
+        errs.append(e)
+    order = math.log2(errs[0] / errs[1])
+    assert 1.8 < order < 2.3, (errs, order)
+
+
+def test_F_constant_monitor_is_log_det():
+    # rho = 1, theta = 1, |Omega_c| = 1: F = log det D^2_h Psi exactly
+    g = grid2(17)
+    box = g.whole_box()
+    X = box.coords()
+    psi = 0.5 * np.sum(X * X, -1) + 0.02 * np.cos(np.pi * X[..., 0]) * np.cos(np.pi * X[..., 1])
+    F = O.rhs_F(psi, box, W.const_monitor(), 1.0, 1.0)
+    _, hess = O.derivatives(psi, box)
+    np.testing.assert_array_equal(F, np.log(hess[0][0] * hess[1][1] - hess[0][1] ** 2))
+
+
+# --- P6: the DCT-I preconditioner is the sparse direct solve of (I - gamma L_h) ---------------
+
+@pytest.mark.parametrize("shape", [(9, 12), (5, 7, 6)])
+def test_precondition_equals_sparse_solve(shape):
+    rng = np.random.default_rng(1)
+    h = tuple(1.0 / (n - 1) for n in shape)
+    gam = 0.37
+    F = rng.standard_normal(shape)
+    L = None
+    for k, n in enumerate(shape):
+        term = sp.identity(1)
+        for j, m in enumerate(shape):
+            term = sp.kron(term, O.assemble_neumann_laplacian_1d(m, h[j]) if j == k else sp.identity(m))
+        L = term if L is None else L + term
+    A = (sp.identity(F.size) - gam * L).tocsc()
+    ref = spla.spsolve(A, F.ravel()).reshape(shape)
+    assert np.max(np.abs(O.precondition(F, h, gam) - ref)) < 1e-12 * np.max(np.abs(ref)) * 10
+
+
+# --- P1: rho = 1 keeps Psi = |xi|^2/2 steady, identity mesh (Sec. 2) --------------------------
+
+def test_constant_monitor_identity_mesh():
+    g = grid2(33)
+    r = O.solve_single(g, W.const_monitor(), 1e-3, 1.0, 30)
+    X = np.moveaxis(g.whole_box().coords(), -1, 0)
+    assert np.max(np.abs(r.mesh - X)) <= 1e-12
+    assert np.max(np.abs(r.psi - 0.5 * np.sum(X * X, 0))) <= 1e-12
+
+
+# --- P2: separable monitor -> sum of 1D iterates; steady 1D = exact equidistribution ---------
+
+def test_separable_monitor_reduces_to_1d_iterates():
+    A, K, C = (8.0, 5.0), (20.0, 15.0), (0.4, 0.6)
+    g = O.GridSpec((33, 41), (0.0, 0.0), (1.0, 1.0))
+    r2 = O.solve_single(g, W.separable_monitor(A, K, C), 1e-3, 1.0, 40)
+    ones = []
+    for ax in range(2):
+        g1 = O.GridSpec((g.n[ax],), (0.0,), (1.0,))
+        ones.append(O.solve_single(g1, W.separable_monitor((A[ax],), (K[ax],), (C[ax],)), 1e-3, 1.0, 40))
+    assert np.max(np.abs(r2.psi - (ones[0].psi[:, None] + ones[1].psi[None, :]))) < 1e-12
+    assert np.max(np.abs(r2.mesh[0] - ones[0].mesh[0][:, None])) < 1e-12
+    assert np.max(np.abs(r2.mesh[1] - ones[1].mesh[0][None, :])) < 1e-12
+
+
+def test_1d_steady_state_matches_exact_equidistribution_second_order():
+    A, K, C = 8.0, 20.0, 0.4
+    errs = []
+    for n in (65, 129, 257):
+        g1 = O.GridSpec((n,), (0.0,), (1.0,))
+        r = O.solve_single(g1, W.separable_monitor((A,), (K,), (C,)), 0.05, 1.0, 2500)
+        X = O.equidistribution_exact_sech2(np.linspace(0, 1, n), 0.0, 1.0, A, K, C)
+        errs.append(np.max(np.abs(r.mesh[0] - X)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.85 < o < 2.15 for o in orders), (errs, orders)
+    assert errs[-1] < 5e-5
+
+
+# --- P3 / P4: exact DD identities --------------------------------------------------------------
+
+@pytest.mark.parametrize("ov", [2, 4, 7])
+def test_forward_euler_dd_equals_single_domain_exactly(ov):
+    # gamma = 0, overlap >= 2 cells, time-n transmission: every subdomain reproduces the global
+    # iterate on its live nodes (locality of the stencil), bit for bit.
+    g = grid2(33)
+    mon = W.ring_monitor()
+    a = O.solve_single(g, mon, 1e-4, 0.0, 25)
+    b = O.solve_dd(g, (2, 3), (ov, ov), mon, 1e-4, 0.0, 25)
+    np.testing.assert_array_equal(a.mesh, b.mesh)
+    np.testing.assert_array_equal(a.psi, b.psi)
+
+
+def test_single_part_dd_equals_single_domain():
+    g = grid2(33)
+    mon = W.ring_monitor()
+    a = O.solve_single(g, mon, 1e-3, 1.0, 20)
+    b = O.solve_dd(g, (1, 1), (4, 4), mon, 1e-3, 1.0, 20)
+    np.testing.assert_array_equal(a.mesh, b.mesh)
+
+
+def test_partition_matches_worked_split():
+    # 513 nodes, 4 parts, overlap 8 cells -> [0,132], [124,260], [252,388], [380,512]
+    cores, ranges = O.partition_axis(512, 4, 8)
+    assert cores == [0, 128, 256, 384, 512]
+    assert ranges == [(0, 132), (124, 260), (252, 388), (380, 512)]
+    assert O.partition_axis(128, 2, 6)[1] == [(0, 67), (61, 128)]
+    own = O.owner_axis(np.array([0, 127, 128, 511, 512]), cores)
+    assert list(own) == [0, 0, 1, 3, 3]
+
+
+# --- P5: DD - single domain shrinks as the overlap grows (Sec. 4.4, overlap study) -----------
+
+@pytest.mark.slow
+def test_dd_error_falls_with_overlap():
+    g = grid2(129)
+    mon = W.ring_monitor()
+    gam = 4.0 / 128 ** 2
+    dt = 0.2 * gam
+    steps = 205
+    sd = O.solve_single(g, mon, dt, gam, steps)
+    errs = [float(np.max(np.abs(O.solve_dd(g, (4, 4), (ov, ov), mon, dt, gam, steps).mesh - sd.mesh)))
+            for ov in (4, 8, 16)]
+    assert errs[0] > errs[1] > errs[2] > 0
+    assert errs[0] / errs[2] > 3.0
+    assert errs[0] < 3e-3
+
+
+# --- P7 / P8 / P9: boundary, symmetry, positivity ---------------------------------------------
+
+def test_ring_mesh_boundary_symmetry_positivity():
+    g = grid2(65)
+    r = O.solve_single(g, W.ring_monitor(), 1e-3, 1.0, 200)
+    x, y = r.mesh
+    # P7: nodes stay on the faces they started on (eq. nbd; eqs. adapt_mesh_bc1/2)
+    assert np.max(np.abs(x[0, :] - 0.0)) < 1e-13 and np.max(np.abs(x[-1, :] - 1.0)) < 1e-13
+    assert np.max(np.abs(y[:, 0] - 0.0)) < 1e-13 and np.max(np.abs(y[:, -1] - 1.0)) < 1e-13
+    # P8: the ring is invariant under x <-> 1 - x and under the axis swap
+    assert np.max(np.abs(x - (1.0 - x[::-1, :]))) < 1e-12
+    assert np.max(np.abs(x - y.T)) < 1e-12
+    # P9: convex potential, unfolded mesh (Sec. 2)
+    assert r.min_det > 0 and r.min_cell > 0
+    # the mesh has moved (the monitor is not trivial)
+    assert np.max(np.abs(x - np.linspace(0, 1, 65)[:, None])) > 1e-2
+
+
+def test_min_cell_measure_identity_and_fold():
+    g = O.GridSpec((5, 6, 4), (0.0,) * 3, (1.0,) * 3)
+    X = np.moveaxis(g.whole_box().coords(), -1, 0)
+    assert abs(O.min_cell_measure(X) - np.prod(g.h)) < 1e-15
+    Y = X.copy()
+    Y[0, 2, 3, 1] += 0.6   # push a node past its neighbour: folds cells
+    assert O.min_cell_measure(Y) < 0
+    g2 = grid2(5)
+    X2 = np.moveaxis(g2.whole_box().coords(), -1, 0)
+    assert abs(O.min_cell_measure(X2) - 1.0 / 16) < 1e-15
+
+
+def test_tangling_raises():
+    g = grid2(65)
+    with pytest.raises(O.TangledError):
+        O.solve_single(g, W.ring_monitor(), 10.0 / 64 ** 2, 0.0, 100)
+
+
+# --- P11: first order in pseudo time with forward Euler (Sec. 4.4, slopes near 1) -------------
+
+@pytest.mark.slow
+def test_forward_euler_first_order_in_time():
+    mon = W.ring_monitor()
+    n = 33
+    h = 1.0 / (n - 1)
+    g = grid2(n)
+    ref = O.solve_single(g, mon, 0.0015 * h * h, 0.0, 16000)
+    errs = []
+    for c, st in ((0.015, 1600), (0.03, 800), (0.06, 400), (0.12, 200)):
+        errs.append(O.rel_errors(ref.psi, O.solve_dd(g, (2, 2), (4, 4), mon, c * h * h, 0.0, st).psi, g.h))
+    x = np.log([0.015, 0.03, 0.06, 0.12])
+    for p in (1, 2, "inf"):
+        slope = np.polyfit(x, np.log([e[p] for e in errs]), 1)[0]
+        assert abs(slope - 1.0) < 0.15, (p, slope)
+
+
+# --- P12: quality measure close to one (Sec. 4.5) ---------------------------------------------
+
+def test_quality_measure_near_one():
+    g = grid2(41)
+    mon = W.ring_monitor()
+    r = O.solve_single(g, mon, 0.05, 1.0, 1500)
+    q = O.quality(r.psi, g, mon)
+    assert abs(q["E2"] - 1.0) < 0.05
+    assert 1.0 < q["Emax"] < 2.0
+
+
+# --- residual definition (eq. dd_stop_criterion) -----------------------------------------------
+
+def test_residual_is_trapezoid_norm_of_update():
+    g = grid2(17)
+    box = g.whole_box()
+    mon = W.ring_monitor()
+    psi0 = O.initial_psi(box)
+    th = O.theta(mon, g.lo, g.hi)
+    psi1, res = O.step_box(psi0, box, mon, th, 1.0, 1e-3, 1.0)
+    diff = psi1 - psi0
+    w = np.ones(g.n)
+    w[0, :] *= 0.5
+    w[-1, :] *= 0.5
+    w[:, 0] *= 0.5
+    w[:, -1] *= 0.5
+    assert abs(res - math.sqrt(np.sum(w * diff ** 2) * g.h[0] * g.h[1])) < 1e-15
+
+
+def test_transmission_sources_are_live_nodes():
+    # every artificial node's source lies strictly inside its owner (checked while building)
+    for parts, ov in (((4, 4), (8, 8)), ((3, 2), (2, 2)), ((2, 2, 2), (6, 6, 6))):
+        d = len(parts)
+        n = (33,) * d if d == 3 else (65, 49)
+        dec = O.Decomposition(O.GridSpec(n, (0.0,) * d, (1.0,) * d), parts, ov)
+        total_art = sum(int(s.box.artificial_mask().sum()) for s in dec.subs)
+        total_listed = sum(len(dst) for lists in dec.trans for _, dst, _ in lists)
+        assert total_art == total_listed
