@@ -1,0 +1,261 @@
+/*
+ * pma.h -- C ABI of the MI355X DD-PMA adaptive mesh library.
+ *
+ * The library computes adaptive meshes x = grad Psi by pseudo-time stepping the parabolic
+ * Monge-Ampere equation  dPsi/dtau = log(|Omega_c| rho(grad Psi) det D^2 Psi)  (Sulman, Nguyen,
+ * Haynes, Huang, arXiv 2006.14602, Sec. 2 eq. pmae) with Psi(xi,0) = |xi|^2/2 (eq. incond) and
+ * the sliding boundary condition grad Psi . n = xi . n (eq. nbd), on a uniform grid of a box,
+ * either on the whole box or on overlapping subdomains coupled by the non-iterative parallel
+ * transmission condition (Sec. 3, eq. transmission_condition3), then glues the subdomain
+ * meshes (Sec. 4.5).
+ *
+ * Discretisation and step (the paper integrates each step with an ODE solver; this library
+ * takes one preconditioned explicit step per pseudo-time step):
+ *   F     = log(|Omega_c| rho(grad_h Psi) det D^2_h Psi / theta),  theta = int_Omega rho
+ *           (centred differences, Sec. 3 eqs. pmae1d/pmae2d; rho normalised as in Sec. 2)
+ *   delta = (I - gamma L_h)^{-1} F  with L_h the Neumann Laplacian of each (sub)domain,
+ *           inverted by type-I DCTs applied as dense matrix products; gamma = 0 is forward Euler
+ *   Psi  += dt * delta   (not on artificial-boundary nodes, which hold transmitted values)
+ * Residual: ||Psi^{n+1} - Psi^n||_2 with the trapezoid rule (Sec. 2 eq. dd_stop_criterion),
+ * maximum over subdomains.
+ *
+ * Conventions for every entry point:
+ *   - Return value: PMA_OK (0) or a negative PMA_E_* code.  Nothing throws or aborts across
+ *     the ABI; pma_last_error() gives a readable message for the calling thread.
+ *   - Grid arrays are row-major with the LAST axis fastest: node (i0, i1[, i2]) of a grid with
+ *     n[] nodes per axis is element (i0 * n[1] + i1) [* n[2] + i2].  Node i of axis k sits at
+ *     lo[k] + i * (hi[k] - lo[k]) / (n[k] - 1).
+ *   - Meshes are returned as dim planes of prod(n) doubles: all x_0, then all x_1 [, x_2].
+ *   - Host buffers are owned by the caller and must hold the stated number of elements.
+ *   - A context serialises its own calls; different contexts may be used from different
+ *     threads.
+ */
+#ifndef PMA_H
+#define PMA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  PMA_OK = 0,
+  PMA_E_INVAL = -1,     /* invalid argument or shape */
+  PMA_E_NOMEM = -2,     /* device arena exhausted or allocation failed */
+  PMA_E_HIP = -3,       /* a HIP runtime call failed */
+  PMA_E_TANGLED = -4,   /* det D^2_h Psi <= 0 reached (the mesh folded) */
+  PMA_E_NONFINITE = -5, /* a non-finite right-hand side or update */
+  PMA_E_BUDGET = -6,    /* request larger than the whole HBM budget */
+  PMA_E_NOTFOUND = -7,  /* unknown or retired ticket */
+  PMA_E_BUSY = -8       /* server queue full */
+};
+
+/* arithmetic form of a solve */
+enum {
+  PMA_FP64 = 0,         /* FP64 state, FP64 stencils, FP64 matrix-core DCT products */
+  PMA_FP32 = 1,         /* FP32 state (Psi - |xi|^2/2), FP32 stencils and DCT products */
+  PMA_FP32_SPLIT16 = 2  /* FP32 state and stencils; DCT products as fp16 hi+lo pairs with
+                           FP32 accumulation (three matrix-core products per tile) */
+};
+
+/* execution form */
+enum {
+  PMA_EXEC_BATCHED = 0, /* every subdomain advanced by the same launches, replayed as a graph */
+  PMA_EXEC_PLAIN = 1    /* one subdomain per launch, no graph (the comparison baseline) */
+};
+
+/* decomposition coupling */
+enum {
+  PMA_DD_PARALLEL = 0   /* Sec. 3 eq. transmission_condition3: neighbours' time-n values */
+};
+
+enum { PMA_FACE_NEUMANN = 0, PMA_FACE_ARTIFICIAL = 1 };
+
+/* monitor (mesh density) functions rho(x); theta = int rho is computed when theta == 0 */
+enum {
+  PMA_MON_CONST = 0,          /* rho = amp */
+  PMA_MON_SECH2_RADIAL = 1,   /* rho = 1 + amp sech^2(k (|x - c|^2 - r0^2)) */
+  PMA_MON_SECH2_SINE = 2,     /* rho = 1 + amp sech^2(k (x_1 - c[1] - r0 sin(2 pi x_0))) */
+  PMA_MON_GAUSS_SUM = 3,      /* rho = 1 + sum_b bamp[b] exp(-|x - bc[b]|^2 / (2 bw[b]^2)) */
+  PMA_MON_SEPARABLE_SECH2 = 4 /* rho = prod_k (1 + amp_axes[k] sech^2(k_axes[k] (x_k - c[k]))) */
+};
+
+/* request states */
+enum { PMA_PENDING = 0, PMA_RUNNING = 1, PMA_DONE = 2, PMA_FAILED = 3 };
+
+typedef struct pma_ctx pma_ctx;
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int n[3];         /* nodes per axis (>= 5); n[2] ignored in 2D */
+  double lo[3];     /* box lower corner */
+  double hi[3];     /* box upper corner (hi > lo) */
+} pma_grid;
+
+typedef struct {
+  int kind;         /* PMA_MON_* */
+  int nbumps;       /* PMA_MON_GAUSS_SUM: 1..4 */
+  double amp, k, r0;
+  double c[3];
+  double amp_axes[3], k_axes[3];
+  double bamp[4], bw[4], bc[4][3];
+  double theta;     /* int_Omega rho; 0 -> computed by the library (FP64 quadrature) */
+} pma_monitor;
+
+typedef struct {
+  double dt;        /* pseudo-time step > 0 */
+  double gamma;     /* preconditioner weight >= 0 (0: forward Euler) */
+  double tol;       /* stop when the residual <= tol (0: run max_steps) */
+  int max_steps;    /* >= 0 */
+  int precision;    /* PMA_FP64 / PMA_FP32 / PMA_FP32_SPLIT16 */
+  int resid_every;  /* residual cadence R >= 1 (steps) */
+  int exec;         /* PMA_EXEC_BATCHED / PMA_EXEC_PLAIN */
+} pma_time;
+
+typedef struct {
+  int parts[3];         /* subdomains per axis (>= 1) */
+  int overlap_cells[3]; /* overlap in cells per axis (>= 2 where parts > 1) */
+  int mode;             /* PMA_DD_PARALLEL */
+} pma_dd;
+
+typedef struct {
+  int steps_done;
+  int status;           /* PMA_OK or the failure code */
+  double final_resid;   /* last computed residual (FP64) */
+  double min_det;       /* min over owned nodes of det D^2_h Psi (FP64) */
+  double min_cell;      /* min signed cell area (2D) / corner Jacobian (3D) of the mesh (FP64) */
+  double theta;         /* normalisation used */
+  double ms_total;      /* wall time of the solve; for served requests: submit -> done */
+  double ms_queue;      /* served requests: submit -> admission */
+} pma_stats;
+
+typedef struct {
+  pma_grid grid;
+  pma_dd dd;            /* parts all 1 -> single domain */
+  pma_monitor mon;
+  pma_time time;
+  double arrival_s;     /* caller's timestamp, echoed back; not used for scheduling */
+} pma_request;
+
+/* ---- context -------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device` with a device-memory budget of
+ * `hbm_budget_bytes` (0 -> 8 GiB).  The budget is one arena, allocated on first use through
+ * the allocator installed by pma_set_allocator (hipMalloc if none); every solve's arrays and
+ * the DCT bases are carved from it.  *out receives the context. */
+int pma_create(int hip_device, size_t hbm_budget_bytes, pma_ctx** out);
+
+/* Stop the server (finishing nothing further), release all device memory, free the context. */
+int pma_destroy(pma_ctx* ctx);
+
+/* Install the device allocator used for the arena (e.g. a framework's caching allocator).
+ * Must be called before the first solve.  alloc returns NULL on failure. */
+int pma_set_allocator(pma_ctx* ctx, void* (*alloc)(size_t bytes, void* stream, void* user),
+                      void (*free_)(void* ptr, void* stream, void* user), void* user);
+
+/* ---- one subdomain (Sec. 3 eqs. pmae1d/pmae2d on Omega_i) ------------------------------- */
+
+/* Advance one subdomain of `global` for time->max_steps steps (or to time->tol) in place.
+ * lo[k]..hi[k] are the subdomain's global node ranges (inclusive); face_kind[2k] / [2k+1] is the
+ * kind of its low / high face on axis k (PMA_FACE_NEUMANN on the box boundary, or
+ * PMA_FACE_ARTIFICIAL, whose nodes keep the Dirichlet values found in psi_dev: the transmission
+ * condition eq. pmae1cd held fixed).
+ * psi_dev: caller-owned DEVICE buffer of prod(hi-lo+1) doubles holding Psi (row-major, last axis
+ * fastest); it is read at the start and overwritten with the result.  hip_stream: caller's
+ * hipStream_t (NULL: the default stream); the call returns after the stream has finished the
+ * work.  st may be NULL. */
+int pma_solve_subdomain(pma_ctx* ctx, const pma_grid* global, const int lo[3], const int hi[3],
+                        const int face_kind[6], const pma_monitor* mon, const pma_time* time,
+                        void* psi_dev, void* hip_stream, pma_stats* st);
+
+/* ---- whole mesh (Sec. 3 parallel DD-PMA, Sec. 4.5 glue) ---------------------------------- */
+
+/* Compute the adaptive mesh of `grid`, single domain if dd is NULL or all parts are 1, else the
+ * overlapping block decomposition of dd (cores floor(m N / M), each subdomain extended by
+ * floor(ov/2) cells below and ceil(ov/2) above, clipped to the box; each node owned by the part
+ * whose core holds it, the last node by the last part).
+ * psi0: optional host array of prod(n) doubles, the initial Psi (warm start, Sec. 2); NULL means
+ * Psi^0 = |xi|^2/2.  mesh_out: host array of dim * prod(n) doubles.  psi_out: optional host
+ * array of prod(n) doubles receiving the glued Psi.  st may be NULL.
+ * Errors: PMA_E_INVAL for dim not 2/3, fewer than 5 nodes on an axis, a subdomain with fewer
+ * than 4 cells on an axis, or overlap < 2 cells where an axis is split; PMA_E_TANGLED /
+ * PMA_E_NONFINITE if the iteration breaks down (mesh_out is then unspecified). */
+int pma_dd_mesh(pma_ctx* ctx, const pma_grid* grid, const pma_dd* dd, const pma_monitor* mon,
+                const pma_time* time, const double* psi0, double* mesh_out, double* psi_out,
+                pma_stats* st);
+
+/* Many independent meshes advanced together (all subdomains of all requests in the same
+ * launches; each request stops at its own step count).  mesh_outs[i] receives request i's mesh
+ * (dim * prod(n) doubles); stats may be NULL.  Every request must use the same precision.
+ * Returns the first failure code, after finishing the others. */
+int pma_dd_mesh_batch(pma_ctx* ctx, int count, const pma_request* reqs, double* const* mesh_outs,
+                      pma_stats* stats);
+
+/* ---- resident solves (state kept in device memory between calls) ---------------------------- */
+
+/* A plan holds `count` requests (one precision) on the device, initialised to Psi^0, and lets
+ * the caller advance them step by step in the shared launches of pma_dd_mesh_batch (or one
+ * subdomain per launch when time.exec is PMA_EXEC_PLAIN).  Requests' max_steps and tol are not
+ * used: the caller decides how many steps to take.  *out receives the plan. */
+typedef struct pma_plan pma_plan;
+int pma_plan_create(pma_ctx* ctx, int count, const pma_request* reqs, pma_plan** out);
+
+/* Enqueue nsteps pseudo-time steps of every request on the context's stream and return without
+ * waiting. */
+int pma_plan_step(pma_plan* plan, int nsteps);
+
+/* Wait until every enqueued step has finished; PMA_E_TANGLED / PMA_E_NONFINITE if a request has
+ * broken down. */
+int pma_plan_sync(pma_plan* plan);
+
+/* Phases of one step, in launch order: 0 transmission, 1 stencil, 2 forward-Euler update,
+ * 3..8 mode products 0..5.  Runs nsteps steps with HIP events around every phase (on the stream
+ * the kernels run on) and returns the mean device milliseconds per step of each phase in ms[]
+ * (cap >= 9 entries); flops[] and bytes[] (may be NULL) receive each phase's algorithmic
+ * floating-point operations and compulsory HBM bytes per step.  *nphases receives 9. */
+int pma_plan_phase_times(pma_plan* plan, int nsteps, double* ms, double* flops, double* bytes, int cap,
+                         int* nphases);
+
+/* Glue request i's mesh (dim * prod(n) doubles) into host memory; st may be NULL. */
+int pma_plan_mesh(pma_plan* plan, int i, double* mesh_out, pma_stats* st);
+
+/* Release the plan's device memory. */
+int pma_plan_destroy(pma_plan* plan);
+
+/* ---- serving (continuous batching) ------------------------------------------------------- */
+
+/* Queue a request (copied) and return its ticket without blocking.  A background thread admits
+ * queued requests in arrival order while their bytes fit the HBM budget, advances every admitted
+ * request one step per tick in shared launches, and finishes each at its own step count.
+ * PMA_E_BUDGET if the request can never fit the budget. */
+int pma_submit(pma_ctx* ctx, const pma_request* req, uint64_t* ticket);
+
+/* State of a ticket.  When DONE, copies the mesh into mesh_out (dim * prod(n) doubles, may be
+ * NULL) and the stats into st, and retires the ticket: later calls return PMA_E_NOTFOUND.
+ * FAILED also retires it (st->status holds the cause). */
+int pma_poll(pma_ctx* ctx, uint64_t ticket, int* state, double* mesh_out, pma_stats* st);
+
+/* Server counters: requests queued, running, finished; device bytes in use by requests. */
+int pma_server_info(pma_ctx* ctx, int* queued, int* running, int* finished, size_t* bytes_in_use);
+
+/* ---- host-only helpers (no GPU needed) ------------------------------------------------------ */
+
+/* Partition as pma_dd_mesh does.  *nsub receives the number of subdomains; if ranges is not
+ * NULL it receives nsub*6 ints (lo0, hi0, lo1, hi1, lo2, hi2 per subdomain, subdomains in
+ * row-major part order) and faces (if not NULL) nsub*6 PMA_FACE_* values. cap bounds nsub. */
+int pma_partition(const pma_grid* grid, const pma_dd* dd, int cap, int* nsub, int* ranges,
+                  int* faces);
+
+/* theta = int_box rho in FP64 (closed forms where they exist, else Gauss-Legendre quadrature). */
+int pma_theta(const pma_grid* grid, const pma_monitor* mon, double* theta_out);
+
+/* Message describing the last failure on the calling thread (never NULL). */
+const char* pma_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMA_H */

@@ -1,0 +1,397 @@
+"""Thin Python binding of libpma.so (include/pma.h): argument marshalling only.
+
+Every step of the mesh computation runs in the HIP library; PyTorch is used for device memory
+(the arena comes from torch's caching allocator) and for caller-owned device buffers and
+streams.  There is no fallback: if the built library is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, c_double, c_int, c_size_t, c_uint64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpma.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pma.h")
+
+PMA_OK, PMA_E_INVAL, PMA_E_NOMEM, PMA_E_HIP, PMA_E_TANGLED, PMA_E_NONFINITE, PMA_E_BUDGET, \
+    PMA_E_NOTFOUND, PMA_E_BUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8
+PRECISION = {"fp64": 0, "fp32": 1, "split16": 2}
+EXEC = {"batched": 0, "plain": 1}
+PENDING, RUNNING, DONE, FAILED = 0, 1, 2, 3
+MON_KIND = {"const": 0, "sech2_radial": 1, "sech2_sine": 2, "gauss_sum": 3, "separable_sech2": 4}
+
+
+class PmaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pma error {code}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("n", c_int * 3), ("lo", c_double * 3), ("hi", c_double * 3)]
+
+
+class Monitor(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("nbumps", c_int), ("amp", c_double), ("k", c_double), ("r0", c_double),
+                ("c", c_double * 3), ("amp_axes", c_double * 3), ("k_axes", c_double * 3),
+                ("bamp", c_double * 4), ("bw", c_double * 4), ("bc", (c_double * 3) * 4), ("theta", c_double)]
+
+
+class Time(ctypes.Structure):
+    _fields_ = [("dt", c_double), ("gamma", c_double), ("tol", c_double), ("max_steps", c_int),
+                ("precision", c_int), ("resid_every", c_int), ("exec", c_int)]
+
+
+class DD(ctypes.Structure):
+    _fields_ = [("parts", c_int * 3), ("overlap_cells", c_int * 3), ("mode", c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps_done", c_int), ("status", c_int), ("final_resid", c_double), ("min_det", c_double),
+                ("min_cell", c_double), ("theta", c_double), ("ms_total", c_double), ("ms_queue", c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("dd", DD), ("mon", Monitor), ("time", Time), ("arrival_s", c_double)]
+
+
+ALLOC_CB = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
+FREE_CB = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+_lib = None
+
+
+def declared_symbols():
+    """Function names declared in include/pma.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(pma_\w+)\s*\(", text, flags=re.M)))
+
+
+def load():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    L.pma_last_error.restype = ctypes.c_char_p
+    L.pma_create.argtypes = [c_int, c_size_t, POINTER(c_void_p)]
+    L.pma_destroy.argtypes = [c_void_p]
+    L.pma_set_allocator.argtypes = [c_void_p, ALLOC_CB, FREE_CB, c_void_p]
+    L.pma_solve_subdomain.argtypes = [c_void_p, POINTER(Grid), POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                      POINTER(Monitor), POINTER(Time), c_void_p, c_void_p, POINTER(Stats)]
+    L.pma_dd_mesh.argtypes = [c_void_p, POINTER(Grid), POINTER(DD), POINTER(Monitor), POINTER(Time),
+                              POINTER(c_double), POINTER(c_double), POINTER(c_double), POINTER(Stats)]
+    L.pma_dd_mesh_batch.argtypes = [c_void_p, c_int, POINTER(Request), POINTER(POINTER(c_double)), POINTER(Stats)]
+    L.pma_submit.argtypes = [c_void_p, POINTER(Request), POINTER(c_uint64)]
+    L.pma_poll.argtypes = [c_void_p, c_uint64, POINTER(c_int), POINTER(c_double), POINTER(Stats)]
+    L.pma_server_info.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_size_t)]
+    L.pma_partition.argtypes = [POINTER(Grid), POINTER(DD), c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
+    L.pma_theta.argtypes = [POINTER(Grid), POINTER(Monitor), POINTER(c_double)]
+    L.pma_plan_create.argtypes = [c_void_p, c_int, POINTER(Request), POINTER(c_void_p)]
+    L.pma_plan_step.argtypes = [c_void_p, c_int]
+    L.pma_plan_sync.argtypes = [c_void_p]
+    L.pma_plan_phase_times.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                                       c_int, POINTER(c_int)]
+    L.pma_plan_mesh.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(Stats)]
+    L.pma_plan_destroy.argtypes = [c_void_p]
+    for f in declared_symbols():
+        if f != "pma_last_error":
+            getattr(L, f).restype = c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != PMA_OK:
+        raise PmaError(rc, load().pma_last_error().decode())
+
+
+# ---------------------------------------------------------------------------------------------
+# conversions from the workload dictionaries
+# ---------------------------------------------------------------------------------------------
+
+def make_grid(g: dict) -> Grid:
+    G = Grid()
+    G.dim = g["dim"]
+    for k in range(g["dim"]):
+        G.n[k] = int(g["n"][k])
+        G.lo[k] = float(g["lo"][k])
+        G.hi[k] = float(g["hi"][k])
+    for k in range(g["dim"], 3):
+        G.n[k] = 1
+    return G
+
+
+def make_monitor(m: dict, theta: float = 0.0) -> Monitor:
+    M = Monitor()
+    M.kind = MON_KIND[m["kind"]]
+    M.amp = float(m.get("amp", 1.0)) if m["kind"] in ("const", "sech2_radial", "sech2_sine") else 0.0
+    M.k = float(m.get("k", 0.0))
+    M.r0 = float(m.get("r0", 0.0))
+    for i, v in enumerate(m.get("c", [])[:3]):
+        M.c[i] = float(v)
+    if m["kind"] == "separable_sech2":
+        for i in range(len(m["amp_axes"])):
+            M.amp_axes[i] = float(m["amp_axes"][i])
+            M.k_axes[i] = float(m["k_axes"][i])
+    if m["kind"] == "gauss_sum":
+        M.nbumps = len(m["bamp"])
+        for b in range(M.nbumps):
+            M.bamp[b] = float(m["bamp"][b])
+            M.bw[b] = float(m["bw"][b])
+            for i, v in enumerate(m["bc"][b][:3]):
+                M.bc[b][i] = float(v)
+    M.theta = float(theta or m.get("theta", 0.0) or 0.0)
+    return M
+
+
+def make_time(t: dict, precision="fp32", exec_="batched", tol=0.0, resid_every=10) -> Time:
+    T = Time()
+    T.dt = float(t["dt"])
+    T.gamma = float(t["gamma"])
+    T.tol = float(t.get("tol", tol))
+    T.max_steps = int(t["steps"])
+    T.precision = PRECISION[precision]
+    T.resid_every = int(t.get("resid_every", resid_every))
+    T.exec = EXEC[exec_]
+    return T
+
+
+def make_dd(dd, dim) -> DD:
+    D = DD()
+    for k in range(3):
+        D.parts[k] = 1
+        D.overlap_cells[k] = 0
+    if dd:
+        for k in range(dim):
+            D.parts[k] = int(dd["parts"][k])
+            D.overlap_cells[k] = int(dd["overlap"][k])
+    D.mode = 0
+    return D
+
+
+def make_request(w: dict, precision="fp32", exec_="batched") -> Request:
+    R = Request()
+    R.grid = make_grid(w["grid"])
+    R.dd = make_dd(w.get("dd"), w["grid"]["dim"])
+    R.mon = make_monitor(w["monitor"])
+    R.time = make_time(w["time"], precision, exec_)
+    R.arrival_s = float(w.get("arrival_s", 0.0))
+    return R
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+# ---------------------------------------------------------------------------------------------
+# host-only helpers
+# ---------------------------------------------------------------------------------------------
+
+def partition(grid: dict, dd: dict | None):
+    L = load()
+    G = make_grid(grid)
+    D = make_dd(dd, grid["dim"])
+    n = c_int()
+    _check(L.pma_partition(ctypes.byref(G), ctypes.byref(D), 0, ctypes.byref(n), None, None))
+    ranges = (c_int * (6 * n.value))()
+    faces = (c_int * (6 * n.value))()
+    _check(L.pma_partition(ctypes.byref(G), ctypes.byref(D), n.value, ctypes.byref(n), ranges, faces))
+    return np.array(ranges[:], dtype=np.int64).reshape(n.value, 6), np.array(faces[:], dtype=np.int64).reshape(n.value, 6)
+
+
+def theta(grid: dict, mon: dict) -> float:
+    L = load()
+    out = c_double()
+    G, M = make_grid(grid), make_monitor(mon)
+    _check(L.pma_theta(ctypes.byref(G), ctypes.byref(M), ctypes.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------------------------
+
+class Context:
+    """A library context on one GPU.  The device arena (budget bytes) comes from torch's caching
+    allocator unless use_torch_allocator is False."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 8 << 30, use_torch_allocator: bool = True):
+        L = load()
+        self._L = L
+        self.device = device
+        h = c_void_p()
+        _check(L.pma_create(device, budget_bytes, ctypes.byref(h)))
+        self.h = h
+        self._cbs = None
+        if use_torch_allocator:
+            import torch
+
+            def _alloc(size, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(size), device=device)
+                except Exception:
+                    return None
+
+            def _free(ptr, stream, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._cbs = (ALLOC_CB(_alloc), FREE_CB(_free))
+            _check(L.pma_set_allocator(self.h, self._cbs[0], self._cbs[1], None))
+
+    def close(self):
+        if self.h:
+            _check(self._L.pma_destroy(self.h))
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- whole mesh ------------------------------------------------------------------------
+    def dd_mesh(self, w: dict, precision="fp32", exec_="batched", psi0=None, want_psi=False, tol=0.0,
+                resid_every=10, theta_override=0.0):
+        """Adaptive mesh of workload w: returns (mesh[d, *n], psi or None, stats dict)."""
+        g = w["grid"]
+        n = tuple(g["n"])
+        G = make_grid(g)
+        D = make_dd(w.get("dd"), g["dim"])
+        M = make_monitor(w["monitor"], theta_override)
+        T = make_time(w["time"], precision, exec_, tol, resid_every)
+        mesh = np.empty((g["dim"],) + n, dtype=np.float64)
+        psi = np.empty(n, dtype=np.float64) if want_psi else None
+        p0 = None
+        if psi0 is not None:
+            p0 = np.ascontiguousarray(psi0, dtype=np.float64)
+            assert p0.shape == n
+        st = Stats()
+        _check(self._L.pma_dd_mesh(self.h, ctypes.byref(G), ctypes.byref(D), ctypes.byref(M), ctypes.byref(T),
+                                   _dptr(p0) if p0 is not None else None, _dptr(mesh),
+                                   _dptr(psi) if psi is not None else None, ctypes.byref(st)))
+        return mesh, psi, st.as_dict()
+
+    def dd_mesh_batch(self, ws, precision="fp32", exec_="batched"):
+        """Many meshes advanced together; returns (list of meshes, list of stats dicts)."""
+        count = len(ws)
+        reqs = (Request * count)()
+        outs = []
+        for i, w in enumerate(ws):
+            reqs[i] = make_request(w, precision, exec_)
+            outs.append(np.empty((w["grid"]["dim"],) + tuple(w["grid"]["n"]), dtype=np.float64))
+        ptrs = (POINTER(c_double) * count)(*[_dptr(o) for o in outs])
+        stats = (Stats * count)()
+        _check(self._L.pma_dd_mesh_batch(self.h, count, reqs, ptrs, stats))
+        return outs, [s.as_dict() for s in stats]
+
+    # -- one subdomain ---------------------------------------------------------------------
+    def solve_subdomain(self, grid: dict, lo, hi, faces, mon: dict, time: dict, psi_dev, stream=None,
+                        precision="fp32", exec_="batched"):
+        """Advance one subdomain in place.  psi_dev: a contiguous float64 CUDA tensor of the
+        subdomain's nodes holding Psi (artificial faces hold the Dirichlet data)."""
+        import torch
+        assert psi_dev.is_cuda and psi_dev.dtype == torch.float64 and psi_dev.is_contiguous()
+        d = grid["dim"]
+        shape = tuple(hi[k] - lo[k] + 1 for k in range(d))
+        assert tuple(psi_dev.shape) == shape, (psi_dev.shape, shape)
+        G = make_grid(grid)
+        lo3 = (c_int * 3)(*(list(lo) + [0] * (3 - d)))
+        hi3 = (c_int * 3)(*(list(hi) + [0] * (3 - d)))
+        f6 = (c_int * 6)(*(list(faces) + [0] * (6 - len(faces))))
+        M = make_monitor(mon)
+        T = make_time(time, precision, exec_)
+        st = Stats()
+        s = stream if stream is not None else torch.cuda.current_stream(psi_dev.device)
+        _check(self._L.pma_solve_subdomain(self.h, ctypes.byref(G), lo3, hi3, f6, ctypes.byref(M), ctypes.byref(T),
+                                           c_void_p(psi_dev.data_ptr()), c_void_p(s.cuda_stream), ctypes.byref(st)))
+        return st.as_dict()
+
+    # -- serving ---------------------------------------------------------------------------
+    def submit(self, w: dict, precision="fp32") -> int:
+        R = make_request(w, precision, "batched")
+        t = c_uint64()
+        _check(self._L.pma_submit(self.h, ctypes.byref(R), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, shape=None):
+        """(state, mesh or None, stats or None).  shape = (dim, *n) to receive the mesh."""
+        stt = c_int()
+        mesh = np.empty(shape, dtype=np.float64) if shape is not None else None
+        st = Stats()
+        _check(self._L.pma_poll(self.h, ticket, ctypes.byref(stt), _dptr(mesh) if mesh is not None else None,
+                                ctypes.byref(st)))
+        if stt.value in (DONE, FAILED):
+            return stt.value, (mesh if stt.value == DONE else None), st.as_dict()
+        return stt.value, None, None
+
+    def server_info(self):
+        q, r, f = c_int(), c_int(), c_int()
+        b = c_size_t()
+        _check(self._L.pma_server_info(self.h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f), ctypes.byref(b)))
+        return {"queued": q.value, "running": r.value, "finished": f.value, "bytes_in_use": b.value}
+
+
+PHASES = ["transmit", "stencil", "euler", "gemm0", "gemm1", "gemm2", "gemm3", "gemm4", "gemm5"]
+
+
+class Plan:
+    """Requests kept resident on the device, stepped on demand (pma_plan_*)."""
+
+    def __init__(self, ctx: Context, ws, precision="fp32", exec_="batched"):
+        self._L = ctx._L
+        self.ctx = ctx
+        self.ws = list(ws)
+        reqs = (Request * len(self.ws))()
+        for i, w in enumerate(self.ws):
+            reqs[i] = make_request(w, precision, exec_)
+        h = c_void_p()
+        _check(self._L.pma_plan_create(ctx.h, len(self.ws), reqs, ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n: int):
+        _check(self._L.pma_plan_step(self.h, int(n)))
+
+    def sync(self):
+        _check(self._L.pma_plan_sync(self.h))
+
+    def phase_times(self, n: int):
+        ms = (c_double * 9)()
+        fl = (c_double * 9)()
+        by = (c_double * 9)()
+        nph = c_int()
+        _check(self._L.pma_plan_phase_times(self.h, int(n), ms, fl, by, 9, ctypes.byref(nph)))
+        return {PHASES[i]: {"ms": ms[i], "flops": fl[i], "bytes": by[i]} for i in range(nph.value)}
+
+    def mesh(self, i: int = 0):
+        w = self.ws[i]
+        out = np.empty((w["grid"]["dim"],) + tuple(w["grid"]["n"]), dtype=np.float64)
+        st = Stats()
+        _check(self._L.pma_plan_mesh(self.h, i, _dptr(out), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def close(self):
+        if self.h:
+            _check(self._L.pma_plan_destroy(self.h))
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,83 @@
+// Device-visible descriptors shared by the host runtime and the HIP kernels.
+//
+// Layout of a (sub)domain in HBM: node (i0, i1[, i2]) of an n0 x n1 [x n2] box is element
+// (i0 * n1 + i1) [* n2 + i2] (last axis fastest).  Each subdomain owns three arrays of that
+// shape in the working precision:
+//   phi  the state phi = Psi - |xi|^2 / 2 (so grad Psi = xi + grad phi, D^2 Psi = I + D^2 phi,
+//        and the Neumann condition of Sec. 2 eq. nbd becomes a plain mirror for phi)
+//   F    the right-hand side, then the spectral coefficients
+//   T    scratch for the mode products of the preconditioner
+#pragma once
+#include <stdint.h>
+
+namespace pma {
+
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_SPLIT16 = 2 };
+
+enum MonKind { MON_CONST = 0, MON_RADIAL = 1, MON_SINE = 2, MON_GAUSS = 3, MON_SEPARABLE = 4 };
+
+// status bits raised by kernels (per instance)
+enum { ST_TANGLED = 1, ST_NONFINITE = 2 };
+
+struct MonitorDev {
+  int kind;
+  int nb;
+  double amp, k, r0;
+  double c[3];
+  double amp_axes[3], k_axes[3];
+  double bamp[4], bw[4], bc[4][3];
+};
+
+struct SubDev {
+  int dim;
+  int n[3];            // nodes per axis (n[2] = 1 in 2D)
+  int off[3];          // global index of local node 0 per axis
+  int art;             // bit 2k: low face of axis k artificial; bit 2k+1: high face
+  int inst;            // instance slot
+  int part0, nparts;   // residual partial sums owned by this subdomain
+  int pad_;
+  void* phi;
+  void* F;
+  void* T;
+  double a[3];         // global box lower corner
+  double h[3];         // grid spacing
+  double gh2[3];       // gamma / h_k^2
+  const void* sig[3];  // per-axis 4 sin^2(pi k / (2 N)) in the working precision
+};
+
+struct InstDev {
+  MonitorDev mon;
+  double log_vol_theta;  // log(|Omega_c| / theta)
+  double dt;
+  int first_sub, nsub;
+  int pin;               // subtract the mean DC coefficient each step (gamma > 0)
+  int pad_;
+};
+
+enum Epi { EPI_NONE = 0, EPI_SCALE = 1, EPI_UPDATE = 2 };
+
+// One batched mode product C[b] = P[b] * Q[b] (row-major, all operands "NN").
+struct GemmJob {
+  int M, N, K, batch;
+  int ldp, ldq, ldc;
+  int epi;
+  long long sP, sQ, sC;  // batch strides in elements
+  const void* P;
+  const void* Q;
+  void* C;
+  int sub;
+  int tiles_n;           // tiles along N (for the tile decode)
+  float unscale;         // 2^-s undoing the pre-scaled basis of the split form (else 1)
+  int tile0;             // index of this job's first tile in its launch's tile range
+};
+
+struct StepArgs {
+  const SubDev* subs;
+  const InstDev* insts;
+  void* dc;              // per-subdomain DC coefficient of the current step (working precision)
+  double* partials;      // residual partial sums (FP64)
+  double* shift_acc;     // per-instance accumulated constant removed from phi (FP64)
+  int* status;           // per-instance status bits
+};
+
+}  // namespace pma

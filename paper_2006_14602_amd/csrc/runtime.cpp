@@ -1,0 +1,1978 @@
+// Host runtime of the DD-PMA library: device arena, DCT bases, theta, partition, per-request
+// plans, the batched / plain step executors, the serving loop and the C ABI of include/pma.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pma.h"
+#include "pma_device.h"
+
+namespace pma {
+
+// kernels.hip
+hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int count, hipStream_t s);
+hipError_t launch_stencil(int prec, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
+hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
+                        hipStream_t s);
+hipError_t launch_gemm(int prec, const GemmJob* jobs, const int4* tiles, int ntiles, int part_base,
+                       const StepArgs& sa, hipStream_t s);
+hipError_t launch_resid(const SubDev* subs, const InstDev* insts, int ninst, const double* partials,
+                        double* out, hipStream_t s);
+hipError_t launch_phi_from_psi(int prec, const SubDev& S, const double* psi, int global_layout, int g1,
+                               int g2, hipStream_t s);
+hipError_t launch_psi_from_phi(int prec, const SubDev& S, double* psi, const double* shift_acc,
+                               hipStream_t s);
+struct GlueArgs {
+  const SubDev* subs;
+  int first_sub;
+  int dim;
+  int parts[3];
+  int n[3];
+  const int* own[3];
+  double a[3], h[3];
+  double* mesh;
+  double* psi;
+  const double* shift_acc;
+  int inst;
+  double* minpart;
+};
+long glue_blocks(long nodes);
+hipError_t launch_glue(int prec, const GlueArgs& g, hipStream_t s);
+long cell_blocks(int dim, const int* n);
+hipError_t launch_cells(const double* mesh, int dim, const int* n, double* minpart, hipStream_t s);
+hipError_t launch_min_reduce(const double* x, long n, double* out, hipStream_t s);
+
+// ------------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------------
+
+static thread_local std::string g_err = "no error";
+
+struct Err {
+  int code;
+};
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) throw Err{fail(PMA_E_HIP, "%s failed: %s (%s:%d)", #expr,        \
+                                         hipGetErrorString(e_), __FILE__, __LINE__)};      \
+  } while (0)
+
+static void thr(int code, const char* msg) { throw Err{fail(code, "%s", msg)}; }
+
+// ------------------------------------------------------------------------------------------
+// device arena: one allocation of the whole budget, first-fit sub-allocation
+// ------------------------------------------------------------------------------------------
+
+class Arena {
+ public:
+  static constexpr size_t kAlign = 256;
+  bool ready() const { return base_ != nullptr; }
+  void init(char* base, size_t size) {
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    free_[0] = size;
+    used_ = 0;
+  }
+  char* base() const { return base_; }
+  size_t size() const { return size_; }
+  size_t used() const { return used_; }
+  // returns nullptr when no hole is large enough
+  void* alloc(size_t bytes) {
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    if (bytes == 0) bytes = kAlign;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        size_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > bytes) free_[off + bytes] = sz - bytes;
+        live_[off] = bytes;
+        used_ += bytes;
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(void* p) {
+    if (!p) return;
+    size_t off = (char*)p - base_;
+    auto it = live_.find(off);
+    if (it == live_.end()) return;
+    size_t sz = it->second;
+    live_.erase(it);
+    used_ -= sz;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + sz == nx->first) {
+      sz += nx->second;
+      free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(off);
+    if (pv != free_.begin()) {
+      --pv;
+      if (pv->first + pv->second == off) {
+        pv->second += sz;
+        return;
+      }
+    }
+    free_[off] = sz;
+  }
+  static size_t round(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_, live_;
+};
+
+// ------------------------------------------------------------------------------------------
+// DCT-I bases.  For an axis with nodes j = 0..N (n = N + 1):
+//   forward A_kj = (2/N) w_k w_j cos(pi k j / N),  inverse B_jk = cos(pi k j / N),
+//   w_0 = w_N = 1/2, else 1;  B A = I  and  B e_k is an eigenvector of the ghost-reflection
+//   Neumann second difference with eigenvalue -(4/h^2) sin^2(pi k / (2N)).
+// Both matrices are symmetric, so a mode product along any axis is an "NN" product.
+// ------------------------------------------------------------------------------------------
+
+struct Basis {
+  int n = 0;
+  double *A64 = nullptr, *B64 = nullptr, *sig64 = nullptr;
+  float *A32 = nullptr, *B32 = nullptr, *A32s = nullptr, *sig32 = nullptr;
+  int scale_exp = 0;  // A32s = A * 2^scale_exp
+  size_t bytes = 0;
+};
+
+static double cos_pi_frac(long p, long q) {
+  // cos(pi p / q) with p reduced mod 2q exactly
+  long r = p % (2 * q);
+  return std::cos(M_PI * (double)r / (double)q);
+}
+
+static void basis_host(int n, std::vector<double>& A, std::vector<double>& B, std::vector<double>& sig) {
+  const int N = n - 1;
+  A.assign((size_t)n * n, 0.0);
+  B.assign((size_t)n * n, 0.0);
+  sig.assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const double wk = (k == 0 || k == N) ? 0.5 : 1.0;
+    for (int j = 0; j < n; ++j) {
+      const double wj = (j == 0 || j == N) ? 0.5 : 1.0;
+      const double c = cos_pi_frac((long)k * j, N);
+      A[(size_t)k * n + j] = (2.0 / N) * wk * wj * c;
+      B[(size_t)j * n + k] = c;
+    }
+    const double s = std::sin(M_PI * k / (2.0 * N));
+    sig[k] = 4.0 * s * s;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// theta = int_box rho (FP64)
+// ------------------------------------------------------------------------------------------
+
+static double sech2_h(double z) {
+  double e = std::exp(-2.0 * std::fabs(z));
+  return 4.0 * e / ((1.0 + e) * (1.0 + e));
+}
+
+static double rho_host(const pma_monitor& m, int dim, const double* x) {
+  switch (m.kind) {
+    case PMA_MON_CONST:
+      return m.amp;
+    case PMA_MON_SECH2_RADIAL: {
+      double r2 = 0;
+      for (int k = 0; k < dim; ++k) r2 += (x[k] - m.c[k]) * (x[k] - m.c[k]);
+      return 1.0 + m.amp * sech2_h(m.k * (r2 - m.r0 * m.r0));
+    }
+    case PMA_MON_SECH2_SINE:
+      return 1.0 + m.amp * sech2_h(m.k * (x[1] - m.c[1] - m.r0 * std::sin(2.0 * M_PI * x[0])));
+    case PMA_MON_GAUSS_SUM: {
+      double s = 1.0;
+      for (int b = 0; b < m.nbumps; ++b) {
+        double r2 = 0;
+        for (int k = 0; k < dim; ++k) r2 += (x[k] - m.bc[b][k]) * (x[k] - m.bc[b][k]);
+        s += m.bamp[b] * std::exp(-r2 / (2.0 * m.bw[b] * m.bw[b]));
+      }
+      return s;
+    }
+    case PMA_MON_SEPARABLE_SECH2: {
+      double p = 1.0;
+      for (int k = 0; k < dim; ++k) p *= 1.0 + m.amp_axes[k] * sech2_h(m.k_axes[k] * (x[k] - m.c[k]));
+      return p;
+    }
+  }
+  return NAN;
+}
+
+static void gl8(double a, double b, int panels, std::vector<double>& x, std::vector<double>& w) {
+  static const double t[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290,
+                              -0.1834346424956498, 0.1834346424956498,  0.5255324099163290,
+                              0.7966664774136267,  0.9602898564975363};
+  static const double wt[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873,
+                               0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
+                               0.2223810344533745, 0.1012285362903763};
+  x.clear();
+  w.clear();
+  const double hp = (b - a) / panels;
+  for (int p = 0; p < panels; ++p) {
+    const double mid = a + (p + 0.5) * hp, half = 0.5 * hp;
+    for (int q = 0; q < 8; ++q) {
+      x.push_back(mid + half * t[q]);
+      w.push_back(half * wt[q]);
+    }
+  }
+}
+
+static double theta_host(const pma_grid& g, const pma_monitor& m) {
+  const int d = g.dim;
+  double vol = 1.0;
+  for (int k = 0; k < d; ++k) vol *= g.hi[k] - g.lo[k];
+  switch (m.kind) {
+    case PMA_MON_CONST:
+      return m.amp * vol;
+    case PMA_MON_GAUSS_SUM: {
+      double tot = vol;
+      for (int b = 0; b < m.nbumps; ++b) {
+        double p = m.bamp[b];
+        const double s = std::sqrt(2.0) * m.bw[b];
+        for (int k = 0; k < d; ++k)
+          p *= m.bw[b] * std::sqrt(M_PI / 2.0) *
+               (std::erf((g.hi[k] - m.bc[b][k]) / s) - std::erf((g.lo[k] - m.bc[b][k]) / s));
+        tot += p;
+      }
+      return tot;
+    }
+    case PMA_MON_SEPARABLE_SECH2: {
+      double p = 1.0;
+      for (int k = 0; k < d; ++k)
+        p *= (g.hi[k] - g.lo[k]) + (m.amp_axes[k] / m.k_axes[k]) *
+                                       (std::tanh(m.k_axes[k] * (g.hi[k] - m.c[k])) -
+                                        std::tanh(m.k_axes[k] * (g.lo[k] - m.c[k])));
+      return p;
+    }
+    case PMA_MON_SECH2_SINE: {
+      // the x_1 integral is elementary: int sech^2(k(y - c - s)) dy = tanh(k(y - c - s)) / k
+      std::vector<double> x, w;
+      const double L0 = g.hi[0] - g.lo[0];
+      const int panels = (int)std::ceil(4.0 * m.k * (1.0 + 2.0 * M_PI * std::fabs(m.r0)) * L0 / M_PI) + 16;
+      gl8(g.lo[0], g.hi[0], panels, x, w);
+      double acc = 0.0;
+      for (size_t q = 0; q < x.size(); ++q) {
+        const double s = m.c[1] + m.r0 * std::sin(2.0 * M_PI * x[q]);
+        acc += w[q] * (std::tanh(m.k * (g.hi[1] - s)) - std::tanh(m.k * (g.lo[1] - s))) / m.k;
+      }
+      double rest = 1.0;
+      for (int k = 2; k < d; ++k) rest *= g.hi[k] - g.lo[k];
+      return vol + m.amp * acc * rest;
+    }
+    case PMA_MON_SECH2_RADIAL: {
+      // tensor Gauss-Legendre; panels short against 1/(k r0), the width of the shell
+      double L = 0;
+      for (int k = 0; k < d; ++k) L = std::max(L, g.hi[k] - g.lo[k]);
+      const int panels = (int)std::ceil(3.0 * m.k * std::max(m.r0, 0.1) * L) + 8;
+      std::vector<double> xs[3], ws[3];
+      for (int k = 0; k < d; ++k) gl8(g.lo[k], g.hi[k], panels, xs[k], ws[k]);
+      const size_t n0 = xs[0].size();
+      const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+      std::vector<double> part(nth, 0.0);
+      std::vector<std::thread> th;
+      for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t]() {
+          double acc = 0.0;
+          double x[3];
+          for (size_t i = t; i < n0; i += nth) {
+            x[0] = xs[0][i];
+            double a1 = 0.0;
+            for (size_t j = 0; j < xs[1].size(); ++j) {
+              x[1] = xs[1][j];
+              if (d == 2) {
+                a1 += ws[1][j] * (rho_host(m, 2, x) - 1.0);
+              } else {
+                double a2 = 0.0;
+                for (size_t k = 0; k < xs[2].size(); ++k) {
+                  x[2] = xs[2][k];
+                  a2 += ws[2][k] * (rho_host(m, 3, x) - 1.0);
+                }
+                a1 += ws[1][j] * a2;
+              }
+            }
+            acc += ws[0][i] * a1;
+          }
+          part[t] = acc;
+        });
+      for (auto& t : th) t.join();
+      double s = 0.0;
+      for (double p : part) s += p;
+      return vol + s;
+    }
+  }
+  return NAN;
+}
+
+// ------------------------------------------------------------------------------------------
+// partition (Sec. 3): cores c_m = floor(m N / M), subdomain m spans
+// [max(0, c_m - floor(ov/2)), min(N, c_{m+1} + ceil(ov/2))], owner = part whose core holds the
+// node (the last node belongs to the last part)
+// ------------------------------------------------------------------------------------------
+
+struct AxisSplit {
+  std::vector<int> cores;            // M + 1
+  std::vector<std::pair<int, int>> ranges;
+  std::vector<int> owner;            // per node
+};
+
+static AxisSplit split_axis(int nnodes, int M, int ov) {
+  AxisSplit a;
+  const int N = nnodes - 1;
+  for (int m = 0; m <= M; ++m) a.cores.push_back((int)(((long)m * N) / M));
+  for (int m = 0; m < M; ++m)
+    a.ranges.push_back({std::max(0, a.cores[m] - ov / 2), std::min(N, a.cores[m + 1] + (ov + 1) / 2)});
+  a.owner.resize(nnodes);
+  for (int v = 0, m = 0; v < nnodes; ++v) {
+    while (m < M - 1 && v >= a.cores[m + 1]) ++m;
+    a.owner[v] = m;
+  }
+  return a;
+}
+
+static void validate_grid(const pma_grid& g) {
+  if (g.dim != 2 && g.dim != 3) thr(PMA_E_INVAL, "dim must be 2 or 3");
+  for (int k = 0; k < g.dim; ++k) {
+    if (g.n[k] < 5) thr(PMA_E_INVAL, "need at least 5 nodes per axis");
+    if (!(g.hi[k] > g.lo[k])) thr(PMA_E_INVAL, "box must have hi > lo");
+  }
+}
+
+static void validate_monitor(const pma_monitor& m, int dim) {
+  if (m.kind < PMA_MON_CONST || m.kind > PMA_MON_SEPARABLE_SECH2) thr(PMA_E_INVAL, "unknown monitor kind");
+  if (m.kind == PMA_MON_GAUSS_SUM && (m.nbumps < 1 || m.nbumps > 4)) thr(PMA_E_INVAL, "nbumps must be 1..4");
+  if (m.kind == PMA_MON_SECH2_SINE && dim < 2) thr(PMA_E_INVAL, "sine monitor needs dim >= 2");
+  if (m.kind == PMA_MON_CONST && !(m.amp > 0)) thr(PMA_E_INVAL, "constant monitor must be positive");
+}
+
+static void validate_time(const pma_time& t) {
+  if (!(t.dt > 0) || !(t.gamma >= 0) || t.max_steps < 0 || !(t.tol >= 0)) thr(PMA_E_INVAL, "bad time parameters");
+  if (t.precision < PMA_FP64 || t.precision > PMA_FP32_SPLIT16) thr(PMA_E_INVAL, "bad precision");
+  if (t.exec != PMA_EXEC_BATCHED && t.exec != PMA_EXEC_PLAIN) thr(PMA_E_INVAL, "bad exec form");
+}
+
+struct SubHost {
+  int lo[3] = {0, 0, 0}, n[3] = {1, 1, 1};
+  int art = 0;
+};
+
+static void partition_host(const pma_grid& g, const pma_dd* dd, std::vector<SubHost>& subs,
+                           int parts[3], std::vector<int> own[3]) {
+  validate_grid(g);
+  int P[3] = {1, 1, 1}, OV[3] = {0, 0, 0};
+  if (dd) {
+    for (int k = 0; k < g.dim; ++k) {
+      P[k] = dd->parts[k];
+      OV[k] = dd->overlap_cells[k];
+      if (P[k] < 1) thr(PMA_E_INVAL, "parts must be >= 1");
+      if (P[k] > 1 && OV[k] < 2) thr(PMA_E_INVAL, "overlap must be >= 2 cells on a split axis");
+      if (dd->mode != PMA_DD_PARALLEL) thr(PMA_E_INVAL, "only the parallel coupling is available");
+    }
+  }
+  AxisSplit ax[3];
+  for (int k = 0; k < 3; ++k) {
+    if (k < g.dim) ax[k] = split_axis(g.n[k], P[k], OV[k]);
+    else {
+      ax[k].cores = {0, 0};
+      ax[k].ranges = {{0, 0}};
+      ax[k].owner = {0};
+    }
+    parts[k] = k < g.dim ? P[k] : 1;
+    own[k] = ax[k].owner;
+  }
+  subs.clear();
+  for (int p0 = 0; p0 < parts[0]; ++p0)
+    for (int p1 = 0; p1 < parts[1]; ++p1)
+      for (int p2 = 0; p2 < parts[2]; ++p2) {
+        SubHost s;
+        const int pp[3] = {p0, p1, p2};
+        for (int k = 0; k < g.dim; ++k) {
+          auto r = ax[k].ranges[pp[k]];
+          s.lo[k] = r.first;
+          s.n[k] = r.second - r.first + 1;
+          if (r.second - r.first < 4) thr(PMA_E_INVAL, "a subdomain has fewer than 4 cells on an axis");
+          if (r.first > 0) s.art |= 1 << (2 * k);
+          if (r.second < g.n[k] - 1) s.art |= 1 << (2 * k + 1);
+        }
+        subs.push_back(s);
+      }
+  // every artificial node must lie strictly inside its owner's range (not on the owner's own
+  // artificial faces), so transmission reads only computed values
+  for (int k = 0; k < g.dim; ++k)
+    for (int m = 0; m < parts[k]; ++m) {
+      const auto r = ax[k].ranges[m];
+      const int ends[2] = {r.first, r.second};
+      for (int e = 0; e < 2; ++e) {
+        const int v = ends[e];
+        if (v == 0 || v == g.n[k] - 1) continue;
+        const int o = ax[k].owner[v];
+        const auto ro = ax[k].ranges[o];
+        if (!(v > ro.first || ro.first == 0) || !(v < ro.second || ro.second == g.n[k] - 1) || o == m)
+          thr(PMA_E_INVAL, "overlap too small for this split: a boundary node is not inside its owner");
+      }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// per-request plan and device state
+// ------------------------------------------------------------------------------------------
+
+struct Ctx;
+
+struct Instance {
+  // request
+  pma_grid grid{};
+  pma_dd dd{};
+  pma_monitor mon{};
+  pma_time tm{};
+  int prec = 0;
+  double theta = 0;
+  bool whole = true;  // single domain
+  // plan
+  int dim = 2;
+  int parts[3] = {1, 1, 1};
+  std::vector<SubHost> subs;
+  std::vector<int> own[3];
+  std::vector<int4> trans;  // (dst local sub, dst elem, src local sub, src elem)
+  std::vector<int> trans_first;  // per dst sub, into trans (size nsub + 1)
+  // device memory
+  char* block = nullptr;
+  size_t bytes = 0;
+  std::vector<void*> phi, F, T;
+  int* own_dev[3] = {nullptr, nullptr, nullptr};
+  double* mesh_dev = nullptr;
+  double* psi_dev = nullptr;
+  double* minpart = nullptr;
+  long minpart_n = 0;
+  double* stats_dev = nullptr;  // [min det, min cell]
+  // progress
+  int steps_done = 0;
+  int status = PMA_OK;
+  double resid = 0;
+  // solve-subdomain mode (no glue)
+  bool single_sub_mode = false;
+  // serving
+  uint64_t ticket = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  double arrival_s = 0;
+  std::vector<double> mesh_host;
+  std::vector<Basis*> bases_used;
+  bool initialized = false;
+  double shift_acc = 0;          // constant removed from phi so far (FP64)
+  double min_det = 0, min_cell = 0;
+  double stats_host[2] = {0, 0};
+  const double* psi0_dev = nullptr;  // warm start (global layout, device)
+  double* user_psi = nullptr;        // single-subdomain mode: caller's device buffer
+  size_t elem() const { return prec == PMA_FP64 ? 8 : 4; }
+  long gnodes() const { return (long)grid.n[0] * grid.n[1] * (dim == 3 ? grid.n[2] : 1); }
+};
+
+static long sub_nodes(const SubHost& s) { return (long)s.n[0] * s.n[1] * s.n[2]; }
+
+static void build_plan(Instance& I) {
+  I.dim = I.grid.dim;
+  validate_monitor(I.mon, I.dim);
+  validate_time(I.tm);
+  I.prec = I.tm.precision;
+  const pma_dd* ddp = nullptr;
+  I.whole = true;
+  for (int k = 0; k < I.dim; ++k)
+    if (I.dd.parts[k] > 1) I.whole = false;
+  if (!I.whole) ddp = &I.dd;
+  partition_host(I.grid, ddp, I.subs, I.parts, I.own);
+  I.theta = I.mon.theta > 0 ? I.mon.theta : theta_host(I.grid, I.mon);
+  if (!(I.theta > 0) || !std::isfinite(I.theta)) thr(PMA_E_INVAL, "theta must be positive and finite");
+  // transmission lists
+  const int ns = (int)I.subs.size();
+  I.trans.clear();
+  I.trans_first.assign(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    I.trans_first[s] = (int)I.trans.size();
+    const SubHost& S = I.subs[s];
+    if (S.art == 0) continue;
+    for (int i0 = 0; i0 < S.n[0]; ++i0)
+      for (int i1 = 0; i1 < S.n[1]; ++i1)
+        for (int i2 = 0; i2 < S.n[2]; ++i2) {
+          const int li[3] = {i0, i1, i2};
+          bool art = false;
+          for (int k = 0; k < I.dim; ++k) {
+            if (li[k] == 0 && (S.art >> (2 * k) & 1)) art = true;
+            if (li[k] == S.n[k] - 1 && (S.art >> (2 * k + 1) & 1)) art = true;
+          }
+          if (!art) continue;
+          int o[3] = {0, 0, 0}, gi[3] = {0, 0, 0};
+          for (int k = 0; k < I.dim; ++k) {
+            gi[k] = S.lo[k] + li[k];
+            o[k] = I.own[k][gi[k]];
+          }
+          const int src = (o[0] * I.parts[1] + o[1]) * I.parts[2] + o[2];
+          const SubHost& O = I.subs[src];
+          long se = 0, de = 0;
+          for (int k = 0; k < 3; ++k) {
+            const int ol = (k < I.dim) ? gi[k] - O.lo[k] : 0;
+            se = se * O.n[k] + ol;
+            de = de * S.n[k] + li[k];
+          }
+          I.trans.push_back(int4{s, (int)de, src, (int)se});
+        }
+  }
+  I.trans_first[ns] = (int)I.trans.size();
+}
+
+// bytes of the instance block (state arrays + glue buffers)
+static size_t instance_bytes(const Instance& I) {
+  size_t b = 0;
+  for (const auto& s : I.subs) b += 3 * Arena::round(sub_nodes(s) * I.elem());
+  if (!I.single_sub_mode) {
+    for (int k = 0; k < I.dim; ++k) b += Arena::round(I.grid.n[k] * sizeof(int));
+    b += Arena::round(I.dim * I.gnodes() * sizeof(double));   // mesh
+    b += Arena::round(I.gnodes() * sizeof(double));           // psi (in/out)
+    const long mp = std::max(glue_blocks(I.gnodes()), cell_blocks(I.dim, I.grid.n));
+    b += Arena::round(mp * sizeof(double));
+  }
+  b += Arena::round(2 * sizeof(double));
+  return b;
+}
+
+// ------------------------------------------------------------------------------------------
+// context
+// ------------------------------------------------------------------------------------------
+
+struct Batch;
+struct Server;
+
+}  // namespace pma
+
+struct pma_ctx {
+  int device = 0;
+  size_t budget = 0;
+  void* (*alloc_cb)(size_t, void*, void*) = nullptr;
+  void (*free_cb)(void*, void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+  void* arena_mem = nullptr;
+  bool arena_from_cb = false;
+  pma::Arena arena;
+  hipStream_t stream = nullptr;
+  std::recursive_mutex mu;  // guards arena, bases, stream work of synchronous calls
+  std::map<int, pma::Basis*> bases;
+  pma::Server* server = nullptr;
+};
+
+namespace pma {
+
+static void ensure_arena(pma_ctx* c) {
+  if (c->arena.ready()) return;
+  HIPCHK(hipSetDevice(c->device));
+  void* p = nullptr;
+  if (c->alloc_cb) {
+    p = c->alloc_cb(c->budget, (void*)c->stream, c->alloc_user);
+    if (!p) thr(PMA_E_NOMEM, "allocator callback could not provide the arena");
+    c->arena_from_cb = true;
+  } else {
+    if (hipMalloc(&p, c->budget) != hipSuccess) thr(PMA_E_NOMEM, "hipMalloc of the arena failed");
+    c->arena_from_cb = false;
+  }
+  c->arena_mem = p;
+  c->arena.init((char*)p, c->budget);
+}
+
+static void* arena_alloc(pma_ctx* c, size_t b) {
+  ensure_arena(c);
+  void* p = c->arena.alloc(b);
+  if (!p) thr(PMA_E_NOMEM, "device arena exhausted");
+  return p;
+}
+
+static size_t basis_bytes(int n) {
+  return 2 * Arena::round((size_t)n * n * 8) + Arena::round((size_t)n * 8) +
+         3 * Arena::round((size_t)n * n * 4) + Arena::round((size_t)n * 4);
+}
+
+static Basis* get_basis(pma_ctx* c, int n) {
+  auto it = c->bases.find(n);
+  if (it != c->bases.end()) return it->second;
+  std::vector<double> A, B, sig;
+  basis_host(n, A, B, sig);
+  Basis* b = new Basis;
+  b->n = n;
+  const size_t nn = (size_t)n * n;
+  std::vector<float> A32(nn), B32(nn), A32s(nn), sig32(n);
+  double amax = 0;
+  for (size_t i = 0; i < nn; ++i) amax = std::max(amax, std::fabs(A[i]));
+  b->scale_exp = -(int)std::floor(std::log2(amax));  // scaled max in [1, 2)
+  const double sc = std::ldexp(1.0, b->scale_exp);
+  for (size_t i = 0; i < nn; ++i) {
+    A32[i] = (float)A[i];
+    B32[i] = (float)B[i];
+    A32s[i] = (float)(A[i] * sc);
+  }
+  for (int i = 0; i < n; ++i) sig32[i] = (float)sig[i];
+  b->bytes = basis_bytes(n);
+  char* p = (char*)arena_alloc(c, b->bytes);
+  auto take = [&](size_t sz) {
+    char* q = p;
+    p += Arena::round(sz);
+    return q;
+  };
+  b->A64 = (double*)take(nn * 8);
+  b->B64 = (double*)take(nn * 8);
+  b->sig64 = (double*)take((size_t)n * 8);
+  b->A32 = (float*)take(nn * 4);
+  b->B32 = (float*)take(nn * 4);
+  b->A32s = (float*)take(nn * 4);
+  b->sig32 = (float*)take((size_t)n * 4);
+  HIPCHK(hipMemcpy(b->A64, A.data(), nn * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->B64, B.data(), nn * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->sig64, sig.data(), n * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->A32, A32.data(), nn * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->B32, B32.data(), nn * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->A32s, A32s.data(), nn * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->sig32, sig32.data(), n * 4, hipMemcpyHostToDevice));
+  c->bases[n] = b;
+  return b;
+}
+
+static size_t new_basis_bytes(pma_ctx* c, const Instance& I) {
+  std::vector<int> ns;
+  for (const auto& s : I.subs)
+    for (int k = 0; k < I.dim; ++k)
+      if (!c->bases.count(s.n[k]) && std::find(ns.begin(), ns.end(), s.n[k]) == ns.end()) ns.push_back(s.n[k]);
+  size_t b = 0;
+  for (int n : ns) b += basis_bytes(n);
+  return b;
+}
+
+static void alloc_instance(pma_ctx* c, Instance& I) {
+  I.bytes = instance_bytes(I);
+  I.block = (char*)arena_alloc(c, I.bytes);
+  char* p = I.block;
+  auto take = [&](size_t sz) {
+    char* q = p;
+    p += Arena::round(sz);
+    return q;
+  };
+  I.phi.clear();
+  I.F.clear();
+  I.T.clear();
+  for (const auto& s : I.subs) {
+    const size_t b = sub_nodes(s) * I.elem();
+    I.phi.push_back(take(b));
+    I.F.push_back(take(b));
+    I.T.push_back(take(b));
+  }
+  if (!I.single_sub_mode) {
+    for (int k = 0; k < I.dim; ++k) I.own_dev[k] = (int*)take(I.grid.n[k] * sizeof(int));
+    I.mesh_dev = (double*)take(I.dim * I.gnodes() * sizeof(double));
+    I.psi_dev = (double*)take(I.gnodes() * sizeof(double));
+    I.minpart_n = std::max(glue_blocks(I.gnodes()), cell_blocks(I.dim, I.grid.n));
+    I.minpart = (double*)take(I.minpart_n * sizeof(double));
+    for (int k = 0; k < I.dim; ++k)
+      HIPCHK(hipMemcpyAsync(I.own_dev[k], I.own[k].data(), I.grid.n[k] * sizeof(int),
+                            hipMemcpyHostToDevice, c->stream));
+  }
+  I.stats_dev = (double*)take(2 * sizeof(double));
+  I.bases_used.clear();
+  for (const auto& s : I.subs)
+    for (int k = 0; k < I.dim; ++k) I.bases_used.push_back(get_basis(c, s.n[k]));
+}
+
+static void free_instance(pma_ctx* c, Instance& I) {
+  if (I.block) c->arena.release(I.block);
+  I.block = nullptr;
+}
+
+// ------------------------------------------------------------------------------------------
+// batch: every subdomain of a set of instances (one precision) advanced by shared launches
+// ------------------------------------------------------------------------------------------
+
+static constexpr int kTileM = 64, kTileN = 64, kStRows = 4, kStCols = 64;
+static constexpr int kMaxPass = 6;
+
+struct SubRange {
+  int first, count;
+};
+
+struct Batch {
+  pma_ctx* ctx = nullptr;
+  int prec = 0;
+  std::vector<Instance*> insts;
+  // host tables
+  std::vector<SubDev> h_subs;
+  std::vector<InstDev> h_insts;
+  std::vector<int4> h_st_tiles, h_eu_tiles, h_trans;
+  std::vector<GemmJob> h_jobs;
+  std::vector<int4> h_pass_tiles[kMaxPass];
+  std::vector<SubRange> st_rng, eu_rng, tr_rng, pass_rng[kMaxPass];
+  int npass = 0;
+  int part_base_pass[kMaxPass] = {0}, part_base_eu = 0, npartials = 0;
+  // device tables (one arena block)
+  char* dmem = nullptr;
+  SubDev* d_subs = nullptr;
+  InstDev* d_insts = nullptr;
+  int4 *d_st = nullptr, *d_eu = nullptr, *d_tr = nullptr;
+  GemmJob* d_jobs = nullptr;
+  int4* d_pass[kMaxPass] = {nullptr};
+  void* d_dc = nullptr;
+  double *d_partials = nullptr, *d_shift = nullptr, *d_resid = nullptr;
+  int* d_status = nullptr;
+  // pinned host mirrors of the per-instance status / residual
+  double* h_resid = nullptr;
+  int* h_status = nullptr;
+  // graph of one step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  StepArgs sa{};
+
+  ~Batch() { clear_device(); }
+
+  void clear_device() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    if (dmem && ctx) ctx->arena.release(dmem);
+    dmem = nullptr;
+    if (h_resid) hipHostFree(h_resid);
+    if (h_status) hipHostFree(h_status);
+    h_resid = nullptr;
+    h_status = nullptr;
+  }
+
+  const void* basis_ptr(const Basis* b, bool forward, bool split) const {
+    if (prec == PMA_FP64) return forward ? (const void*)b->A64 : (const void*)b->B64;
+    if (split && forward) return b->A32s;
+    return forward ? (const void*)b->A32 : (const void*)b->B32;
+  }
+
+  void add_job(int pass, GemmJob j) {
+    const int tm = (j.M + kTileM - 1) / kTileM, tn = (j.N + kTileN - 1) / kTileN;
+    j.tiles_n = tn;
+    const int job_id = (int)h_jobs.size();
+    j.tile0 = (int)h_pass_tiles[pass].size();
+    h_jobs.push_back(j);
+    for (int b = 0; b < j.batch; ++b)
+      for (int a = 0; a < tm; ++a)
+        for (int c = 0; c < tn; ++c) h_pass_tiles[pass].push_back(int4{job_id, a * kTileM, c * kTileN, b});
+  }
+
+  // build host and device tables for the current instance set
+  void build() {
+    clear_device();
+    h_subs.clear();
+    h_insts.clear();
+    h_st_tiles.clear();
+    h_eu_tiles.clear();
+    h_trans.clear();
+    h_jobs.clear();
+    st_rng.clear();
+    eu_rng.clear();
+    tr_rng.clear();
+    npass = 0;
+    for (int p = 0; p < kMaxPass; ++p) {
+      h_pass_tiles[p].clear();
+      pass_rng[p].clear();
+    }
+    const bool split = prec == PMA_FP32_SPLIT16;
+    // pass 1: descriptors
+    for (size_t q = 0; q < insts.size(); ++q) {
+      Instance& I = *insts[q];
+      InstDev id{};
+      const pma_monitor& m = I.mon;
+      id.mon.kind = m.kind;
+      id.mon.nb = m.nbumps;
+      id.mon.amp = m.amp;
+      id.mon.k = m.k;
+      id.mon.r0 = m.r0;
+      for (int k = 0; k < 3; ++k) {
+        id.mon.c[k] = m.c[k];
+        id.mon.amp_axes[k] = m.amp_axes[k];
+        id.mon.k_axes[k] = m.k_axes[k];
+      }
+      for (int b = 0; b < 4; ++b) {
+        id.mon.bamp[b] = m.bamp[b];
+        id.mon.bw[b] = m.bw[b];
+        for (int k = 0; k < 3; ++k) id.mon.bc[b][k] = m.bc[b][k];
+      }
+      double vol = 1.0;
+      for (int k = 0; k < I.dim; ++k) vol *= I.grid.hi[k] - I.grid.lo[k];
+      id.log_vol_theta = std::log(vol / I.theta);
+      id.dt = I.tm.dt;
+      id.first_sub = (int)h_subs.size();
+      id.nsub = (int)I.subs.size();
+      id.pin = I.tm.gamma > 0 ? 1 : 0;
+      h_insts.push_back(id);
+      for (size_t s = 0; s < I.subs.size(); ++s) {
+        const SubHost& S = I.subs[s];
+        SubDev sd{};
+        sd.dim = I.dim;
+        for (int k = 0; k < 3; ++k) {
+          sd.n[k] = S.n[k];
+          sd.off[k] = S.lo[k];
+          if (k < I.dim) {
+            sd.a[k] = I.grid.lo[k];
+            sd.h[k] = (I.grid.hi[k] - I.grid.lo[k]) / (I.grid.n[k] - 1);
+            sd.gh2[k] = I.tm.gamma / (sd.h[k] * sd.h[k]);
+            const Basis* b = get_basis(ctx, S.n[k]);
+            sd.sig[k] = prec == PMA_FP64 ? (const void*)b->sig64 : (const void*)b->sig32;
+          } else {
+            sd.a[k] = 0;
+            sd.h[k] = 1;
+            sd.gh2[k] = 0;
+            sd.sig[k] = nullptr;
+          }
+        }
+        sd.art = S.art;
+        sd.inst = (int)q;
+        sd.phi = I.phi[s];
+        sd.F = I.F[s];
+        sd.T = I.T[s];
+        h_subs.push_back(sd);
+      }
+    }
+    // pass 2: tiles and jobs, subdomain by subdomain (each sub's tiles contiguous per table)
+    int npass_needed = 0;
+    for (size_t q = 0; q < insts.size(); ++q) {
+      Instance& I = *insts[q];
+      const int first = h_insts[q].first_sub;
+      for (size_t s = 0; s < I.subs.size(); ++s) {
+        const int gs = first + (int)s;
+        SubDev& sd = h_subs[gs];
+        const int n0 = sd.n[0], n1 = sd.n[1], n2 = sd.n[2];
+        const int R = I.dim == 2 ? n0 : n0 * n1, C = I.dim == 2 ? n1 : n2;
+        SubRange sr{(int)h_st_tiles.size(), 0};
+        for (int r = 0; r < R; r += kStRows)
+          for (int c = 0; c < C; c += kStCols) h_st_tiles.push_back(int4{gs, r, c, 0});
+        sr.count = (int)h_st_tiles.size() - sr.first;
+        st_rng.push_back(sr);
+        // transmission entries with batch-global sub indices
+        SubRange tr{(int)h_trans.size(), 0};
+        for (int e = I.trans_first[s]; e < I.trans_first[s + 1]; ++e) {
+          int4 t = I.trans[e];
+          h_trans.push_back(int4{first + t.x, t.y, first + t.z, t.w});
+        }
+        tr.count = (int)h_trans.size() - tr.first;
+        tr_rng.push_back(tr);
+        if (I.tm.gamma == 0.0) {
+          SubRange er{(int)h_eu_tiles.size(), 0};
+          for (int r = 0; r < R; r += kStRows)
+            for (int c = 0; c < C; c += kStCols) h_eu_tiles.push_back(int4{gs, r, c, 0});
+          er.count = (int)h_eu_tiles.size() - er.first;
+          eu_rng.push_back(er);
+          for (int p = 0; p < kMaxPass; ++p) pass_rng[p].push_back(SubRange{(int)h_pass_tiles[p].size(), 0});
+          continue;
+        }
+        eu_rng.push_back(SubRange{(int)h_eu_tiles.size(), 0});
+        const Basis* b0 = get_basis(ctx, n0);
+        const Basis* b1 = get_basis(ctx, n1);
+        const Basis* b2 = I.dim == 3 ? get_basis(ctx, n2) : nullptr;
+        auto us = [&](const Basis* b, bool fwd) {
+          return (split && fwd) ? (float)std::ldexp(1.0, -b->scale_exp) : 1.0f;
+        };
+        std::vector<GemmJob> js;
+        auto J = [&](int M, int N, int K, int batch, const void* P, int ldp, long long sP, const void* Q,
+                     int ldq, long long sQ, void* Cc, int ldc, long long sC, int epi, float unscale) {
+          GemmJob j{};
+          j.M = M; j.N = N; j.K = K; j.batch = batch;
+          j.P = P; j.ldp = ldp; j.sP = sP;
+          j.Q = Q; j.ldq = ldq; j.sQ = sQ;
+          j.C = Cc; j.ldc = ldc; j.sC = sC;
+          j.epi = epi; j.unscale = unscale; j.sub = gs;
+          js.push_back(j);
+        };
+        void *Fp = sd.F, *Tp = sd.T, *Pp = sd.phi;
+        if (I.dim == 2) {
+          J(n0, n1, n1, 1, Fp, n1, 0, basis_ptr(b1, true, split), n1, 0, Tp, n1, 0, EPI_NONE, us(b1, true));
+          J(n0, n1, n0, 1, basis_ptr(b0, true, split), n0, 0, Tp, n1, 0, Fp, n1, 0, EPI_SCALE, us(b0, true));
+          J(n0, n1, n0, 1, basis_ptr(b0, false, split), n0, 0, Fp, n1, 0, Tp, n1, 0, EPI_NONE, 1.0f);
+          J(n0, n1, n1, 1, Tp, n1, 0, basis_ptr(b1, false, split), n1, 0, Pp, n1, 0, EPI_UPDATE, 1.0f);
+        } else {
+          const long long pl = (long long)n1 * n2;
+          J(n0 * n1, n2, n2, 1, Fp, n2, 0, basis_ptr(b2, true, split), n2, 0, Tp, n2, 0, EPI_NONE, us(b2, true));
+          J(n1, n2, n1, n0, basis_ptr(b1, true, split), n1, 0, Tp, n2, pl, Fp, n2, pl, EPI_NONE, us(b1, true));
+          J(n0, n1 * n2, n0, 1, basis_ptr(b0, true, split), n0, 0, Fp, n1 * n2, 0, Tp, n1 * n2, 0, EPI_SCALE, us(b0, true));
+          J(n0, n1 * n2, n0, 1, basis_ptr(b0, false, split), n0, 0, Tp, n1 * n2, 0, Fp, n1 * n2, 0, EPI_NONE, 1.0f);
+          J(n1, n2, n1, n0, basis_ptr(b1, false, split), n1, 0, Fp, n2, pl, Tp, n2, pl, EPI_NONE, 1.0f);
+          J(n0 * n1, n2, n2, 1, Tp, n2, 0, basis_ptr(b2, false, split), n2, 0, Pp, n2, 0, EPI_UPDATE, 1.0f);
+        }
+        npass_needed = std::max(npass_needed, (int)js.size());
+        for (int p = 0; p < kMaxPass; ++p) {
+          SubRange pr{(int)h_pass_tiles[p].size(), 0};
+          if (p < (int)js.size()) add_job(p, js[p]);
+          pr.count = (int)h_pass_tiles[p].size() - pr.first;
+          pass_rng[p].push_back(pr);
+        }
+      }
+    }
+    npass = npass_needed;
+    // residual partial regions: update passes (2D: pass 3, 3D: pass 5) and Euler tiles
+    npartials = 0;
+    for (int p = 0; p < kMaxPass; ++p) {
+      part_base_pass[p] = npartials;
+      if (p == 3 || p == 5) npartials += (int)h_pass_tiles[p].size();
+    }
+    part_base_eu = npartials;
+    npartials += (int)h_eu_tiles.size();
+    for (size_t q = 0; q < insts.size(); ++q) {
+      Instance& I = *insts[q];
+      for (size_t s = 0; s < I.subs.size(); ++s) {
+        const int gs = h_insts[q].first_sub + (int)s;
+        SubDev& sd = h_subs[gs];
+        if (I.tm.gamma == 0.0) {
+          sd.part0 = part_base_eu + eu_rng[gs].first;
+          sd.nparts = eu_rng[gs].count;
+        } else {
+          const int up = I.dim == 2 ? 3 : 5;
+          sd.part0 = part_base_pass[up] + pass_rng[up][gs].first;
+          sd.nparts = pass_rng[up][gs].count;
+        }
+      }
+    }
+    // device block
+    const size_t nsub = h_subs.size(), ninst = h_insts.size();
+    const size_t el = prec == PMA_FP64 ? 8 : 4;
+    size_t bytes = Arena::round(nsub * sizeof(SubDev)) + Arena::round(ninst * sizeof(InstDev)) +
+                   Arena::round(h_st_tiles.size() * 16 + 16) + Arena::round(h_eu_tiles.size() * 16 + 16) +
+                   Arena::round(h_trans.size() * 16 + 16) + Arena::round(h_jobs.size() * sizeof(GemmJob) + 16) +
+                   Arena::round(nsub * el) + Arena::round((size_t)(npartials + 1) * 8) +
+                   Arena::round(ninst * 8) * 2 + Arena::round(ninst * 4);
+    for (int p = 0; p < kMaxPass; ++p) bytes += Arena::round(h_pass_tiles[p].size() * 16 + 16);
+    dmem = (char*)arena_alloc(ctx, bytes);
+    char* p = dmem;
+    auto take = [&](size_t sz) {
+      char* q = p;
+      p += Arena::round(sz);
+      return q;
+    };
+    hipStream_t st = ctx->stream;
+    auto up = [&](void* dst, const void* src, size_t sz) {
+      if (sz) HIPCHK(hipMemcpyAsync(dst, src, sz, hipMemcpyHostToDevice, st));
+    };
+    d_subs = (SubDev*)take(nsub * sizeof(SubDev));
+    d_insts = (InstDev*)take(ninst * sizeof(InstDev));
+    d_st = (int4*)take(h_st_tiles.size() * 16 + 16);
+    d_eu = (int4*)take(h_eu_tiles.size() * 16 + 16);
+    d_tr = (int4*)take(h_trans.size() * 16 + 16);
+    d_jobs = (GemmJob*)take(h_jobs.size() * sizeof(GemmJob) + 16);
+    for (int q = 0; q < kMaxPass; ++q) d_pass[q] = (int4*)take(h_pass_tiles[q].size() * 16 + 16);
+    d_dc = take(nsub * el);
+    d_partials = (double*)take((size_t)(npartials + 1) * 8);
+    d_shift = (double*)take(ninst * 8);
+    d_resid = (double*)take(ninst * 8);
+    d_status = (int*)take(ninst * 4);
+    up(d_subs, h_subs.data(), nsub * sizeof(SubDev));
+    up(d_insts, h_insts.data(), ninst * sizeof(InstDev));
+    up(d_st, h_st_tiles.data(), h_st_tiles.size() * 16);
+    up(d_eu, h_eu_tiles.data(), h_eu_tiles.size() * 16);
+    up(d_tr, h_trans.data(), h_trans.size() * 16);
+    up(d_jobs, h_jobs.data(), h_jobs.size() * sizeof(GemmJob));
+    for (int q = 0; q < kMaxPass; ++q) up(d_pass[q], h_pass_tiles[q].data(), h_pass_tiles[q].size() * 16);
+    HIPCHK(hipMemsetAsync(d_dc, 0, nsub * el, st));
+    HIPCHK(hipMemsetAsync(d_partials, 0, (size_t)(npartials + 1) * 8, st));
+    HIPCHK(hipMemsetAsync(d_status, 0, ninst * 4, st));
+    HIPCHK(hipMemsetAsync(d_resid, 0, ninst * 8, st));
+    // accumulated shifts continue across rebuilds
+    std::vector<double> sh(ninst, 0.0);
+    for (size_t q = 0; q < ninst; ++q) sh[q] = insts[q]->shift_acc;
+    up(d_shift, sh.data(), ninst * 8);
+    HIPCHK(hipHostMalloc((void**)&h_resid, ninst * 8 + 8, 0));
+    HIPCHK(hipHostMalloc((void**)&h_status, ninst * 4 + 4, 0));
+    sa.subs = d_subs;
+    sa.insts = d_insts;
+    sa.dc = d_dc;
+    sa.partials = d_partials;
+    sa.shift_acc = d_shift;
+    sa.status = d_status;
+    HIPCHK(hipStreamSynchronize(st));
+  }
+
+  // one step: all subdomains per launch (batched) or one subdomain per launch (plain baseline),
+  // phase by phase
+  void launch_step(bool plain, hipStream_t st) {
+    for (int ph = 0; ph < 9; ++ph) launch_phase(ph, plain, st);
+  }
+
+  // one phase of a step (see pma_plan_phase_times for the numbering)
+  void launch_phase(int ph, bool plain, hipStream_t st) {
+    const int nsub = (int)h_subs.size();
+    if (ph == 0) {
+      if (!plain) HIPCHK(launch_transmit(prec, d_subs, d_tr, (int)h_trans.size(), st));
+      else
+        for (int s = 0; s < nsub; ++s)
+          if (tr_rng[s].count) HIPCHK(launch_transmit(prec, d_subs, d_tr + tr_rng[s].first, tr_rng[s].count, st));
+    } else if (ph == 1) {
+      if (!plain) HIPCHK(launch_stencil(prec, d_st, (int)h_st_tiles.size(), sa, st));
+      else
+        for (int s = 0; s < nsub; ++s) HIPCHK(launch_stencil(prec, d_st + st_rng[s].first, st_rng[s].count, sa, st));
+    } else if (ph == 2) {
+      if (!plain) HIPCHK(launch_euler(prec, d_eu, (int)h_eu_tiles.size(), part_base_eu, sa, st));
+      else
+        for (int s = 0; s < nsub; ++s)
+          if (eu_rng[s].count)
+            HIPCHK(launch_euler(prec, d_eu + eu_rng[s].first, eu_rng[s].count, part_base_eu + eu_rng[s].first, sa, st));
+    } else {
+      const int p = ph - 3;
+      if (p >= npass) return;
+      if (!plain) HIPCHK(launch_gemm(prec, d_jobs, d_pass[p], (int)h_pass_tiles[p].size(), part_base_pass[p], sa, st));
+      else
+        for (int s = 0; s < nsub; ++s)
+          if (pass_rng[p][s].count)
+            HIPCHK(launch_gemm(prec, d_jobs, d_pass[p] + pass_rng[p][s].first, pass_rng[p][s].count,
+                               part_base_pass[p] + pass_rng[p][s].first, sa, st));
+    }
+  }
+
+  // algorithmic work per step of each phase: flops of the mode products (2 M N K per batch
+  // entry) and compulsory bytes (each operand and result touched once; the update reads and
+  // writes phi)
+  void phase_work(double* flops, double* bytes) const {
+    const double el = prec == PMA_FP64 ? 8.0 : 4.0;
+    for (int ph = 0; ph < 9; ++ph) flops[ph] = bytes[ph] = 0.0;
+    bytes[0] = (double)h_trans.size() * (2 * el + 16);
+    for (const auto& s : h_subs) {
+      const double nodes = (double)s.n[0] * s.n[1] * s.n[2];
+      bytes[1] += 2 * el * nodes;
+    }
+    for (const auto& t : h_eu_tiles) (void)t;
+    for (size_t q = 0; q < h_subs.size(); ++q)
+      if (eu_rng[q].count) bytes[2] += 3 * el * (double)h_subs[q].n[0] * h_subs[q].n[1] * h_subs[q].n[2];
+    for (int p = 0; p < npass; ++p) {
+      for (const auto& j : h_jobs) (void)j;
+    }
+    for (size_t q = 0; q < h_subs.size(); ++q)
+      for (int p = 0; p < npass; ++p) {
+        if (!pass_rng[p][q].count) continue;
+        const int t = pass_rng[p][q].first;
+        const GemmJob& j = h_jobs[h_pass_tiles[p][t].x];
+        flops[3 + p] += 2.0 * j.M * j.N * j.K * j.batch;
+        const bool basis_left = j.sP == 0 && j.batch > 1 ? true : (j.ldp == j.K && j.M == j.K && j.sP == 0);
+        (void)basis_left;
+        // data operand + result (+ phi read for the update); the basis is n x n and cached
+        double data = (double)j.M * j.N * j.batch;
+        bytes[3 + p] += el * (2 * data + (j.epi == EPI_UPDATE ? data : 0.0));
+      }
+  }
+
+  void capture() {
+    hipStream_t st = ctx->stream;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      launch_step(false, st);
+    } catch (...) {
+      hipGraph_t g;
+      hipStreamEndCapture(st, &g);
+      if (g) hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(st, &graph));
+    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
+
+  void step(bool plain) {
+    hipStream_t st = ctx->stream;
+    if (plain) {
+      launch_step(true, st);
+    } else {
+      if (!gexec) capture();
+      HIPCHK(hipGraphLaunch(gexec, st));
+    }
+  }
+
+  // residual + status to pinned host memory (asynchronous)
+  void read_progress() {
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_resid(d_subs, d_insts, (int)h_insts.size(), d_partials, d_resid, st));
+    HIPCHK(hipMemcpyAsync(h_resid, d_resid, h_insts.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_status, d_status, h_insts.size() * 4, hipMemcpyDeviceToHost, st));
+  }
+};
+
+static int status_code(int bits) {
+  if (bits & ST_TANGLED) return PMA_E_TANGLED;
+  if (bits & ST_NONFINITE) return PMA_E_NONFINITE;
+  return PMA_OK;
+}
+
+// initial state of every subdomain of instance q: phi = Psi0 - |xi|^2/2 from a global FP64 array
+// on the device (warm start), from the caller's subdomain buffer (single-subdomain mode), or 0
+// (Psi^0 = |xi|^2/2, Sec. 2 eq. incond)
+static void init_state(pma_ctx* c, Instance& I, const Batch& B, int q) {
+  const int first = B.h_insts[q].first_sub;
+  for (size_t s = 0; s < I.subs.size(); ++s) {
+    const SubDev& sd = B.h_subs[first + s];
+    if (I.single_sub_mode) {
+      HIPCHK(launch_phi_from_psi(I.prec, sd, I.user_psi, 0, 0, 0, c->stream));
+    } else if (I.psi0_dev) {
+      HIPCHK(launch_phi_from_psi(I.prec, sd, I.psi0_dev, 1, I.grid.n[1], I.dim == 3 ? I.grid.n[2] : 1, c->stream));
+    } else {
+      HIPCHK(hipMemsetAsync(I.phi[s], 0, sub_nodes(I.subs[s]) * I.elem(), c->stream));
+    }
+  }
+  I.initialized = true;
+}
+
+// glue + Jacobian checks of instance q (asynchronous).  Mesh, optional Psi and the two minima
+// land in the instance's device buffers; a single-subdomain solve writes Psi back instead.
+static void finalize_instance(pma_ctx* c, Instance& I, Batch& B, int q, bool want_psi) {
+  hipStream_t st = c->stream;
+  const int first = B.h_insts[q].first_sub;
+  if (I.single_sub_mode) {
+    HIPCHK(launch_psi_from_phi(I.prec, B.h_subs[first], I.user_psi, B.d_shift, st));
+    return;
+  }
+  // refresh the artificial nodes so owned nodes next to them see current neighbours
+  const int nsub = (int)I.subs.size();
+  const int t0 = B.tr_rng[first].first;
+  const int t1 = B.tr_rng[first + nsub - 1].first + B.tr_rng[first + nsub - 1].count;
+  if (t1 > t0) HIPCHK(launch_transmit(I.prec, B.d_subs, B.d_tr + t0, t1 - t0, st));
+  GlueArgs g{};
+  g.subs = B.d_subs;
+  g.first_sub = first;
+  g.dim = I.dim;
+  for (int k = 0; k < 3; ++k) {
+    g.parts[k] = I.parts[k];
+    g.n[k] = k < I.dim ? I.grid.n[k] : 1;
+    g.own[k] = k < I.dim ? I.own_dev[k] : nullptr;
+    g.a[k] = k < I.dim ? I.grid.lo[k] : 0;
+    g.h[k] = k < I.dim ? (I.grid.hi[k] - I.grid.lo[k]) / (I.grid.n[k] - 1) : 1;
+  }
+  g.mesh = I.mesh_dev;
+  g.psi = want_psi ? I.psi_dev : nullptr;
+  g.shift_acc = B.d_shift;
+  g.inst = q;
+  g.minpart = I.minpart;
+  HIPCHK(launch_glue(I.prec, g, st));
+  HIPCHK(launch_min_reduce(I.minpart, glue_blocks(I.gnodes()), I.stats_dev, st));
+  HIPCHK(launch_cells(I.mesh_dev, I.dim, I.grid.n, I.minpart, st));
+  HIPCHK(launch_min_reduce(I.minpart, cell_blocks(I.dim, I.grid.n), I.stats_dev + 1, st));
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static void save_shifts(Batch& B) {
+  if (!B.dmem || B.insts.empty()) return;
+  std::vector<double> sh(B.insts.size());
+  HIPCHK(hipMemcpy(sh.data(), B.d_shift, sh.size() * 8, hipMemcpyDeviceToHost));
+  for (size_t q = 0; q < sh.size(); ++q) B.insts[q]->shift_acc = sh[q];
+}
+
+// Run instances (one precision) to their step counts, finishing each as soon as it stops.
+// Instances that stop earlier than others leave the shared launches (the batch is rebuilt from
+// the survivors; their device state is untouched).
+static void run_to_end(pma_ctx* c, const std::vector<Instance*>& all, int prec, bool plain, bool want_psi) {
+  hipStream_t st = c->stream;
+  std::vector<Instance*> live = all;
+  while (!live.empty()) {
+    Batch B;
+    B.ctx = c;
+    B.prec = prec;
+    B.insts = live;
+    B.build();
+    for (size_t q = 0; q < live.size(); ++q)
+      if (!live[q]->initialized) init_state(c, *live[q], B, (int)q);
+    std::vector<char> fin(live.size(), 0);
+    bool any = false;
+    while (!any) {
+      int chunk = 1 << 30;
+      int R = 1 << 30;
+      for (auto* I : live) {
+        chunk = std::min(chunk, I->tm.max_steps - I->steps_done);
+        if (I->tm.tol > 0) R = std::min(R, std::max(1, I->tm.resid_every) - I->steps_done % std::max(1, I->tm.resid_every));
+      }
+      chunk = std::max(0, std::min(chunk, R));
+      for (int k = 0; k < chunk; ++k) B.step(plain);
+      for (auto* I : live) I->steps_done += chunk;
+      B.read_progress();
+      HIPCHK(hipStreamSynchronize(st));
+      for (size_t q = 0; q < live.size(); ++q) {
+        Instance& I = *live[q];
+        I.resid = B.h_resid[q];
+        const int code = status_code(B.h_status[q]);
+        if (code != PMA_OK && I.status == PMA_OK) I.status = code;
+        const bool conv = I.tm.tol > 0 && chunk > 0 && I.resid <= I.tm.tol;
+        if (I.status != PMA_OK || I.steps_done >= I.tm.max_steps || conv) {
+          fin[q] = 1;
+          any = true;
+        }
+      }
+    }
+    save_shifts(B);
+    std::vector<Instance*> rest;
+    for (size_t q = 0; q < live.size(); ++q) {
+      if (!fin[q]) {
+        rest.push_back(live[q]);
+        continue;
+      }
+      if (live[q]->status == PMA_OK) finalize_instance(c, *live[q], B, (int)q, want_psi);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    live.swap(rest);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// serving: continuous batching
+// ------------------------------------------------------------------------------------------
+
+struct Server {
+  pma_ctx* ctx = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<Instance*> queue;                 // submitted, not admitted
+  std::vector<Instance*> running;              // admitted (server thread only)
+  std::unordered_map<uint64_t, Instance*> all; // every live ticket
+  std::unordered_map<uint64_t, int> state;
+  int finished = 0;
+  std::unique_ptr<Batch> batch[3];             // per precision
+  bool dirty = true;
+
+  void start() { th = std::thread([this] { loop(); }); }
+
+  void shutdown() {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    if (th.joinable()) th.join();
+    std::lock_guard<std::recursive_mutex> cg(ctx->mu);
+    hipStreamSynchronize(ctx->stream);
+    for (auto& b : batch) b.reset();
+    for (auto& kv : all) {
+      free_instance(ctx, *kv.second);
+      delete kv.second;
+    }
+    all.clear();
+  }
+
+  size_t request_bytes(const Instance& I) {
+    return Arena::round(instance_bytes(I)) + new_basis_bytes(ctx, I) + (1 << 16);
+  }
+
+  // admit queued requests in arrival order while they fit (no overtaking); caller holds mu
+  void admit_locked() {
+    while (!queue.empty()) {
+      Instance* I = queue.front();
+      const size_t need = request_bytes(*I);
+      std::lock_guard<std::recursive_mutex> cg(ctx->mu);
+      try {
+        ensure_arena(ctx);
+        if (ctx->arena.used() + need > ctx->arena.size()) break;
+        alloc_instance(ctx, *I);
+      } catch (Err& e) {
+        if (e.code == PMA_E_NOMEM) break;  // fragmented or full: wait for frees
+        I->status = e.code;
+        I->t_done = now_s();
+        state[I->ticket] = PMA_FAILED;
+        queue.pop_front();
+        continue;
+      }
+      queue.pop_front();
+      I->t_admit = now_s();
+      running.push_back(I);
+      state[I->ticket] = PMA_RUNNING;
+      dirty = true;
+    }
+  }
+
+  void loop() {
+    while (true) {
+      {
+        std::unique_lock<std::mutex> g(mu);
+        cv.wait(g, [&] { return stop || !queue.empty() || !running.empty(); });
+        if (stop) return;
+        admit_locked();
+        if (running.empty()) {
+          g.unlock();
+          std::this_thread::sleep_for(std::chrono::microseconds(200));
+          continue;
+        }
+      }
+      try {
+        tick();
+      } catch (Err& e) {
+        std::lock_guard<std::recursive_mutex> cg(ctx->mu);
+        std::lock_guard<std::mutex> g(mu);
+        hipStreamSynchronize(ctx->stream);
+        for (auto* I : running) {
+          I->status = e.code;
+          I->t_done = now_s();
+          state[I->ticket] = PMA_FAILED;
+          free_instance(ctx, *I);
+          finished++;
+        }
+        running.clear();
+        for (auto& b : batch) b.reset();
+        dirty = true;
+      }
+    }
+  }
+
+  void rebuild() {
+    hipStream_t st = ctx->stream;
+    for (int p = 0; p < 3; ++p) {
+      if (batch[p]) save_shifts(*batch[p]);
+      batch[p].reset();
+      std::vector<Instance*> v;
+      for (auto* I : running)
+        if (I->prec == p) v.push_back(I);
+      if (v.empty()) continue;
+      batch[p].reset(new Batch);
+      batch[p]->ctx = ctx;
+      batch[p]->prec = p;
+      batch[p]->insts = v;
+      batch[p]->build();
+      for (size_t q = 0; q < v.size(); ++q)
+        if (!v[q]->initialized) init_state(ctx, *v[q], *batch[p], (int)q);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    dirty = false;
+  }
+
+  // advance every running request a few steps in shared launches; finish the ones that end
+  void tick() {
+    std::lock_guard<std::recursive_mutex> cg(ctx->mu);
+    hipStream_t st = ctx->stream;
+    if (dirty) rebuild();
+    int chunk = 1 << 30;
+    for (auto* I : running) chunk = std::min(chunk, I->tm.max_steps - I->steps_done);
+    chunk = std::max(0, std::min(chunk, 8));  // bounded so arrivals are admitted promptly
+    for (int k = 0; k < chunk; ++k)
+      for (int p = 0; p < 3; ++p)
+        if (batch[p]) batch[p]->step(false);
+    for (auto* I : running) I->steps_done += chunk;
+    for (int p = 0; p < 3; ++p)
+      if (batch[p]) batch[p]->read_progress();
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<Instance*> done;
+    for (int p = 0; p < 3; ++p) {
+      if (!batch[p]) continue;
+      for (size_t q = 0; q < batch[p]->insts.size(); ++q) {
+        Instance* I = batch[p]->insts[q];
+        const int code = status_code(batch[p]->h_status[q]);
+        if (code != PMA_OK && I->status == PMA_OK) I->status = code;
+        I->resid = batch[p]->h_resid[q];
+        const bool conv = I->tm.tol > 0 && chunk > 0 && I->resid <= I->tm.tol;
+        if (I->status != PMA_OK || I->steps_done >= I->tm.max_steps || conv) done.push_back(I);
+      }
+    }
+    if (!done.empty()) {
+      for (int p = 0; p < 3; ++p)
+        if (batch[p]) save_shifts(*batch[p]);
+      for (auto* I : done) {
+        if (I->status != PMA_OK) continue;
+        Batch& B = *batch[I->prec];
+        const int q = (int)(std::find(B.insts.begin(), B.insts.end(), I) - B.insts.begin());
+        finalize_instance(ctx, *I, B, q, false);
+        I->mesh_host.resize((size_t)I->dim * I->gnodes());
+        HIPCHK(hipMemcpyAsync(I->mesh_host.data(), I->mesh_dev, I->mesh_host.size() * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(I->stats_host, I->stats_dev, 16, hipMemcpyDeviceToHost, st));
+      }
+      HIPCHK(hipStreamSynchronize(st));
+      for (auto* I : done) {
+        if (I->status != PMA_OK) continue;
+        I->min_det = I->stats_host[0];
+        I->min_cell = I->stats_host[1];
+        if (!(I->min_det > 0) || !(I->min_cell > 0)) I->status = PMA_E_TANGLED;
+      }
+      // release the finished requests' memory only after the device is done with it
+      for (auto& b : batch) b.reset();
+      dirty = true;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    for (auto* I : done) {
+      I->t_done = now_s();
+      state[I->ticket] = I->status == PMA_OK ? PMA_DONE : PMA_FAILED;
+      running.erase(std::find(running.begin(), running.end(), I));
+      free_instance(ctx, *I);
+      finished++;
+    }
+    if (!queue.empty()) {
+      if (!dirty)
+        for (int p = 0; p < 3; ++p)
+          if (batch[p]) save_shifts(*batch[p]);
+      admit_locked();
+    }
+  }
+};
+
+}  // namespace pma
+
+// ------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------
+
+using namespace pma;
+
+#define API_BEGIN try {
+#define API_END                                              \
+  }                                                          \
+  catch (Err & e) {                                          \
+    return e.code;                                           \
+  }                                                          \
+  catch (std::bad_alloc&) {                                  \
+    return fail(PMA_E_NOMEM, "host allocation failed");      \
+  }                                                          \
+  catch (...) {                                              \
+    return fail(PMA_E_INVAL, "unexpected internal error");   \
+  }
+
+extern "C" {
+
+const char* pma_last_error(void) { return g_err.c_str(); }
+
+int pma_create(int hip_device, size_t hbm_budget_bytes, pma_ctx** out) {
+  API_BEGIN
+  if (!out) return fail(PMA_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int nd = 0;
+  if (hipGetDeviceCount(&nd) != hipSuccess || hip_device < 0 || hip_device >= nd)
+    return fail(PMA_E_HIP, "no such HIP device %d", hip_device);
+  HIPCHK(hipSetDevice(hip_device));
+  pma_ctx* c = new pma_ctx;
+  c->device = hip_device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)8 << 30);
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(PMA_E_HIP, "stream creation failed");
+  }
+  *out = c;
+  return PMA_OK;
+  API_END
+}
+
+int pma_destroy(pma_ctx* c) {
+  API_BEGIN
+  if (!c) return PMA_OK;
+  if (c->server) {
+    c->server->shutdown();
+    delete c->server;
+    c->server = nullptr;
+  }
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (auto& kv : c->bases) delete kv.second;
+  c->bases.clear();
+  if (c->arena_mem) {
+    if (c->arena_from_cb && c->free_cb) c->free_cb(c->arena_mem, (void*)c->stream, c->alloc_user);
+    else if (!c->arena_from_cb) hipFree(c->arena_mem);
+  }
+  if (c->stream) hipStreamDestroy(c->stream);
+  delete c;
+  return PMA_OK;
+  API_END
+}
+
+int pma_set_allocator(pma_ctx* c, void* (*alloc)(size_t, void*, void*), void (*free_)(void*, void*, void*),
+                      void* user) {
+  API_BEGIN
+  if (!c || !alloc || !free_) return fail(PMA_E_INVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (c->arena.ready()) return fail(PMA_E_INVAL, "allocator must be installed before the first solve");
+  c->alloc_cb = alloc;
+  c->free_cb = free_;
+  c->alloc_user = user;
+  return PMA_OK;
+  API_END
+}
+
+int pma_partition(const pma_grid* grid, const pma_dd* dd, int cap, int* nsub, int* ranges, int* faces) {
+  API_BEGIN
+  if (!grid || !nsub) return fail(PMA_E_INVAL, "NULL argument");
+  std::vector<SubHost> subs;
+  int parts[3];
+  std::vector<int> own[3];
+  partition_host(*grid, dd, subs, parts, own);
+  *nsub = (int)subs.size();
+  if ((ranges || faces) && (int)subs.size() > cap) return fail(PMA_E_INVAL, "cap too small");
+  for (size_t s = 0; s < subs.size(); ++s)
+    for (int k = 0; k < 3; ++k) {
+      if (ranges) {
+        ranges[s * 6 + 2 * k] = subs[s].lo[k];
+        ranges[s * 6 + 2 * k + 1] = subs[s].lo[k] + subs[s].n[k] - 1;
+      }
+      if (faces) {
+        faces[s * 6 + 2 * k] = (subs[s].art >> (2 * k)) & 1;
+        faces[s * 6 + 2 * k + 1] = (subs[s].art >> (2 * k + 1)) & 1;
+      }
+    }
+  return PMA_OK;
+  API_END
+}
+
+int pma_theta(const pma_grid* grid, const pma_monitor* mon, double* out) {
+  API_BEGIN
+  if (!grid || !mon || !out) return fail(PMA_E_INVAL, "NULL argument");
+  validate_grid(*grid);
+  validate_monitor(*mon, grid->dim);
+  *out = theta_host(*grid, *mon);
+  return PMA_OK;
+  API_END
+}
+
+static void fill_stats(pma_stats* st, const Instance& I, double ms) {
+  if (!st) return;
+  st->steps_done = I.steps_done;
+  st->status = I.status;
+  st->final_resid = I.resid;
+  st->min_det = I.min_det;
+  st->min_cell = I.min_cell;
+  st->theta = I.theta;
+  st->ms_total = ms;
+  st->ms_queue = 0;
+}
+
+static void default_dd(Instance& I, const pma_dd* dd) {
+  if (dd) I.dd = *dd;
+  else {
+    for (int k = 0; k < 3; ++k) {
+      I.dd.parts[k] = 1;
+      I.dd.overlap_cells[k] = 0;
+    }
+    I.dd.mode = PMA_DD_PARALLEL;
+  }
+  for (int k = I.grid.dim; k < 3; ++k) I.dd.parts[k] = 1;
+}
+
+// copy results of finished instances to the host and apply the final positivity check
+static void collect(pma_ctx* c, const std::vector<Instance*>& v, double* const* mesh_outs,
+                    double* const* psi_outs) {
+  for (size_t q = 0; q < v.size(); ++q) {
+    Instance& I = *v[q];
+    if (I.status != PMA_OK) continue;
+    if (mesh_outs && mesh_outs[q])
+      HIPCHK(hipMemcpyAsync(mesh_outs[q], I.mesh_dev, (size_t)I.dim * I.gnodes() * 8, hipMemcpyDeviceToHost, c->stream));
+    if (psi_outs && psi_outs[q])
+      HIPCHK(hipMemcpyAsync(psi_outs[q], I.psi_dev, I.gnodes() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(I.stats_host, I.stats_dev, 16, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (auto* I : v) {
+    if (I->status != PMA_OK) continue;
+    I->min_det = I->stats_host[0];
+    I->min_cell = I->stats_host[1];
+    if (!(I->min_det > 0) || !(I->min_cell > 0)) I->status = PMA_E_TANGLED;
+  }
+}
+
+static int status_fail(int code) {
+  return fail(code, code == PMA_E_TANGLED ? "mesh folded (det <= 0)" : "non-finite update");
+}
+
+int pma_dd_mesh(pma_ctx* c, const pma_grid* grid, const pma_dd* dd, const pma_monitor* mon, const pma_time* tm,
+                const double* psi0, double* mesh_out, double* psi_out, pma_stats* st) {
+  API_BEGIN
+  if (!c || !grid || !mon || !tm || !mesh_out) return fail(PMA_E_INVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  const double t0 = now_s();
+  Instance I;
+  I.grid = *grid;
+  default_dd(I, dd);
+  I.mon = *mon;
+  I.tm = *tm;
+  build_plan(I);
+  alloc_instance(c, I);
+  int rc = PMA_OK;
+  try {
+    if (psi0) {
+      HIPCHK(hipMemcpyAsync(I.psi_dev, psi0, I.gnodes() * 8, hipMemcpyHostToDevice, c->stream));
+      I.psi0_dev = I.psi_dev;
+    }
+    std::vector<Instance*> v{&I};
+    run_to_end(c, v, I.prec, tm->exec == PMA_EXEC_PLAIN, psi_out != nullptr);
+    double* mo[1] = {mesh_out};
+    double* po[1] = {psi_out};
+    collect(c, v, mo, po);
+  } catch (Err& e) {
+    rc = e.code;
+    hipStreamSynchronize(c->stream);
+  }
+  free_instance(c, I);
+  fill_stats(st, I, (now_s() - t0) * 1e3);
+  if (rc != PMA_OK) return rc;
+  if (I.status != PMA_OK) return status_fail(I.status);
+  return PMA_OK;
+  API_END
+}
+
+int pma_dd_mesh_batch(pma_ctx* c, int count, const pma_request* reqs, double* const* mesh_outs, pma_stats* stats) {
+  API_BEGIN
+  if (!c || count < 0 || (count && (!reqs || !mesh_outs))) return fail(PMA_E_INVAL, "bad arguments");
+  if (count == 0) return PMA_OK;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  const double t0 = now_s();
+  std::vector<std::unique_ptr<Instance>> insts;
+  const int prec = reqs[0].time.precision;
+  for (int i = 0; i < count; ++i) {
+    std::unique_ptr<Instance> I(new Instance);
+    I->grid = reqs[i].grid;
+    default_dd(*I, &reqs[i].dd);
+    I->mon = reqs[i].mon;
+    I->tm = reqs[i].time;
+    if (I->tm.precision != prec) return fail(PMA_E_INVAL, "all requests of a batch must share the precision");
+    build_plan(*I);
+    insts.push_back(std::move(I));
+  }
+  int rc = PMA_OK;
+  std::vector<Instance*> raw;
+  try {
+    for (auto& I : insts) {
+      alloc_instance(c, *I);
+      raw.push_back(I.get());
+    }
+    run_to_end(c, raw, prec, reqs[0].time.exec == PMA_EXEC_PLAIN, false);
+    collect(c, raw, mesh_outs, nullptr);
+  } catch (Err& e) {
+    rc = e.code;
+    hipStreamSynchronize(c->stream);
+  }
+  const double ms = (now_s() - t0) * 1e3;
+  for (int q = 0; q < (int)raw.size(); ++q) {
+    if (stats) fill_stats(&stats[q], *raw[q], ms);
+    if (raw[q]->status != PMA_OK && rc == PMA_OK) rc = raw[q]->status;
+  }
+  for (auto* I : raw) free_instance(c, *I);
+  if (rc != PMA_OK) return fail(rc, "at least one request of the batch failed (%d)", rc);
+  return PMA_OK;
+  API_END
+}
+
+int pma_solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], const int hi[3], const int face_kind[6],
+                        const pma_monitor* mon, const pma_time* tm, void* psi_dev, void* hip_stream, pma_stats* st) {
+  API_BEGIN
+  if (!c || !global || !lo || !hi || !face_kind || !mon || !tm || !psi_dev) return fail(PMA_E_INVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  const double t0 = now_s();
+  validate_grid(*global);
+  Instance I;
+  I.grid = *global;
+  I.mon = *mon;
+  I.tm = *tm;
+  I.single_sub_mode = true;
+  I.dim = global->dim;
+  validate_monitor(I.mon, I.dim);
+  validate_time(I.tm);
+  I.prec = tm->precision;
+  SubHost S;
+  for (int k = 0; k < I.dim; ++k) {
+    if (lo[k] < 0 || hi[k] > global->n[k] - 1 || hi[k] - lo[k] < 4) return fail(PMA_E_INVAL, "bad subdomain range");
+    S.lo[k] = lo[k];
+    S.n[k] = hi[k] - lo[k] + 1;
+    for (int e = 0; e < 2; ++e) {
+      const int fk = face_kind[2 * k + e];
+      const bool on_box = e == 0 ? lo[k] == 0 : hi[k] == global->n[k] - 1;
+      if (fk == PMA_FACE_ARTIFICIAL) S.art |= 1 << (2 * k + e);
+      else if (fk != PMA_FACE_NEUMANN || !on_box)
+        return fail(PMA_E_INVAL, "Neumann faces must lie on the box boundary");
+    }
+  }
+  I.subs = {S};
+  I.trans_first = {0, 0};
+  I.theta = mon->theta > 0 ? mon->theta : theta_host(I.grid, I.mon);
+  I.user_psi = (double*)psi_dev;
+  alloc_instance(c, I);
+  int rc = PMA_OK;
+  hipStream_t user = (hipStream_t)hip_stream;
+  hipEvent_t ev = nullptr;
+  try {
+    // the work runs after what the caller queued on its stream, and the caller's stream waits
+    // for the result
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, user));
+    HIPCHK(hipStreamWaitEvent(c->stream, ev, 0));
+    std::vector<Instance*> v{&I};
+    run_to_end(c, v, I.prec, tm->exec == PMA_EXEC_PLAIN, false);
+    HIPCHK(hipEventRecord(ev, c->stream));
+    HIPCHK(hipStreamWaitEvent(user, ev, 0));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipStreamSynchronize(user));
+  } catch (Err& e) {
+    rc = e.code;
+    hipStreamSynchronize(c->stream);
+  }
+  if (ev) hipEventDestroy(ev);
+  free_instance(c, I);
+  fill_stats(st, I, (now_s() - t0) * 1e3);
+  if (rc != PMA_OK) return rc;
+  if (I.status != PMA_OK) return status_fail(I.status);
+  return PMA_OK;
+  API_END
+}
+
+// ---- resident plans -------------------------------------------------------------------------
+
+}  // extern "C"
+
+struct pma_plan {
+  pma_ctx* ctx = nullptr;
+  std::vector<std::unique_ptr<pma::Instance>> insts;
+  std::unique_ptr<pma::Batch> batch;
+  bool plain = false;
+};
+
+extern "C" {
+
+int pma_plan_create(pma_ctx* c, int count, const pma_request* reqs, pma_plan** out) {
+  API_BEGIN
+  if (!c || count <= 0 || !reqs || !out) return fail(PMA_E_INVAL, "bad arguments");
+  *out = nullptr;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  std::unique_ptr<pma_plan> P(new pma_plan);
+  P->ctx = c;
+  const int prec = reqs[0].time.precision;
+  P->plain = reqs[0].time.exec == PMA_EXEC_PLAIN;
+  for (int i = 0; i < count; ++i) {
+    std::unique_ptr<Instance> I(new Instance);
+    I->grid = reqs[i].grid;
+    default_dd(*I, &reqs[i].dd);
+    I->mon = reqs[i].mon;
+    I->tm = reqs[i].time;
+    if (I->tm.precision != prec) return fail(PMA_E_INVAL, "all requests of a plan must share the precision");
+    build_plan(*I);
+    P->insts.push_back(std::move(I));
+  }
+  std::vector<Instance*> raw;
+  try {
+    for (auto& I : P->insts) {
+      alloc_instance(c, *I);
+      raw.push_back(I.get());
+    }
+    P->batch.reset(new Batch);
+    P->batch->ctx = c;
+    P->batch->prec = prec;
+    P->batch->insts = raw;
+    P->batch->build();
+    for (size_t q = 0; q < raw.size(); ++q) init_state(c, *raw[q], *P->batch, (int)q);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } catch (Err& e) {
+    hipStreamSynchronize(c->stream);
+    P->batch.reset();
+    for (auto* I : raw) free_instance(c, *I);
+    return e.code;
+  }
+  *out = P.release();
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_step(pma_plan* P, int nsteps) {
+  API_BEGIN
+  if (!P || nsteps < 0) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  for (int k = 0; k < nsteps; ++k) P->batch->step(P->plain);
+  for (auto& I : P->insts) I->steps_done += nsteps;
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_sync(pma_plan* P) {
+  API_BEGIN
+  if (!P) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  P->batch->read_progress();
+  HIPCHK(hipStreamSynchronize(P->ctx->stream));
+  int rc = PMA_OK;
+  for (size_t q = 0; q < P->insts.size(); ++q) {
+    Instance& I = *P->insts[q];
+    I.resid = P->batch->h_resid[q];
+    const int code = status_code(P->batch->h_status[q]);
+    if (code != PMA_OK && I.status == PMA_OK) I.status = code;
+    if (I.status != PMA_OK && rc == PMA_OK) rc = I.status;
+  }
+  if (rc != PMA_OK) return status_fail(rc);
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, double* bytes, int cap, int* nph) {
+  API_BEGIN
+  if (!P || nsteps <= 0 || !ms || cap < 9 || !nph) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  *nph = 9;
+  Batch& B = *P->batch;
+  hipStream_t st = P->ctx->stream;
+  std::vector<hipEvent_t> ev(10);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  std::vector<double> acc(9, 0.0);
+  for (int k = 0; k < nsteps; ++k) {
+    HIPCHK(hipEventRecord(ev[0], st));
+    for (int ph = 0; ph < 9; ++ph) {
+      B.launch_phase(ph, P->plain, st);
+      HIPCHK(hipEventRecord(ev[ph + 1], st));
+    }
+    HIPCHK(hipEventSynchronize(ev[9]));
+    for (int ph = 0; ph < 9; ++ph) {
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, ev[ph], ev[ph + 1]));
+      acc[ph] += t;
+    }
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  for (auto& I : P->insts) I->steps_done += nsteps;
+  for (int ph = 0; ph < 9; ++ph) ms[ph] = acc[ph] / nsteps;
+  std::vector<double> fl(9, 0.0), by(9, 0.0);
+  B.phase_work(fl.data(), by.data());
+  for (int ph = 0; ph < 9; ++ph) {
+    if (flops) flops[ph] = fl[ph];
+    if (bytes) bytes[ph] = by[ph];
+  }
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_mesh(pma_plan* P, int i, double* mesh_out, pma_stats* st) {
+  API_BEGIN
+  if (!P || i < 0 || i >= (int)P->insts.size() || !mesh_out) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  Instance& I = *P->insts[i];
+  P->batch->read_progress();
+  HIPCHK(hipStreamSynchronize(P->ctx->stream));
+  I.resid = P->batch->h_resid[i];
+  const int code = status_code(P->batch->h_status[i]);
+  if (code != PMA_OK && I.status == PMA_OK) I.status = code;
+  if (I.status == PMA_OK) {
+    finalize_instance(P->ctx, I, *P->batch, i, false);
+    std::vector<Instance*> v{&I};
+    double* mo[1] = {mesh_out};
+    collect(P->ctx, v, mo, nullptr);
+  }
+  fill_stats(st, I, 0.0);
+  if (I.status != PMA_OK) return status_fail(I.status);
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_destroy(pma_plan* P) {
+  API_BEGIN
+  if (!P) return PMA_OK;
+  {
+    std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+    hipStreamSynchronize(P->ctx->stream);
+    P->batch.reset();
+    for (auto& I : P->insts) free_instance(P->ctx, *I);
+  }
+  delete P;
+  return PMA_OK;
+  API_END
+}
+
+int pma_submit(pma_ctx* c, const pma_request* req, uint64_t* ticket) {
+  API_BEGIN
+  if (!c || !req || !ticket) return fail(PMA_E_INVAL, "NULL argument");
+  std::unique_ptr<Instance> I(new Instance);
+  I->grid = req->grid;
+  I->dd = req->dd;
+  for (int k = I->grid.dim; k < 3; ++k) I->dd.parts[k] = 1;
+  I->mon = req->mon;
+  I->tm = req->time;
+  I->arrival_s = req->arrival_s;
+  build_plan(*I);
+  {
+    std::lock_guard<std::recursive_mutex> g(c->mu);
+    HIPCHK(hipSetDevice(c->device));
+    if (!c->server) {
+      c->server = new Server;
+      c->server->ctx = c;
+      c->server->start();
+    }
+    const size_t need = c->server->request_bytes(*I);
+    if (need > c->budget) return fail(PMA_E_BUDGET, "request needs %zu bytes, budget is %zu", need, c->budget);
+  }
+  Server* s = c->server;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    I->ticket = s->next_ticket++;
+    I->t_submit = now_s();
+    *ticket = I->ticket;
+    s->state[I->ticket] = PMA_PENDING;
+    s->all[I->ticket] = I.get();
+    s->queue.push_back(I.release());
+  }
+  s->cv.notify_all();
+  return PMA_OK;
+  API_END
+}
+
+int pma_poll(pma_ctx* c, uint64_t ticket, int* state, double* mesh_out, pma_stats* st) {
+  API_BEGIN
+  if (!c || !state) return fail(PMA_E_INVAL, "NULL argument");
+  Server* s = c->server;
+  if (!s) return fail(PMA_E_NOTFOUND, "unknown ticket");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->state.find(ticket);
+  if (it == s->state.end()) return fail(PMA_E_NOTFOUND, "unknown ticket");
+  *state = it->second;
+  if (*state == PMA_DONE || *state == PMA_FAILED) {
+    Instance* I = s->all[ticket];
+    if (*state == PMA_DONE && mesh_out) std::memcpy(mesh_out, I->mesh_host.data(), I->mesh_host.size() * 8);
+    if (st) {
+      fill_stats(st, *I, (I->t_done - I->t_submit) * 1e3);
+      st->ms_queue = (I->t_admit > 0 ? I->t_admit - I->t_submit : 0) * 1e3;
+    }
+    s->all.erase(ticket);
+    s->state.erase(it);
+    delete I;
+  }
+  return PMA_OK;
+  API_END
+}
+
+int pma_server_info(pma_ctx* c, int* queued, int* running, int* finished, size_t* bytes) {
+  API_BEGIN
+  if (!c) return fail(PMA_E_INVAL, "NULL argument");
+  Server* s = c->server;
+  if (!s) {
+    if (queued) *queued = 0;
+    if (running) *running = 0;
+    if (finished) *finished = 0;
+    if (bytes) *bytes = 0;
+    return PMA_OK;
+  }
+  std::lock_guard<std::mutex> g(s->mu);
+  if (queued) *queued = (int)s->queue.size();
+  if (running) *running = (int)s->running.size();
+  if (finished) *finished = s->finished;
+  if (bytes) *bytes = c->arena.used();
+  return PMA_OK;
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every declared entry point,
+and its host-only helpers (partition, theta) agree with the oracle; invalid shapes are rejected
+with PMA_E_INVAL."""
+import ctypes
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_14602_amd import binding as B
+from paper_2006_14602_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2006_14602_amd import build
+        build.build()
+    return B.load()
+
+
+def test_exports_every_declared_symbol(L):
+    names = B.declared_symbols()
+    assert {"pma_create", "pma_destroy", "pma_set_allocator", "pma_solve_subdomain", "pma_dd_mesh",
+            "pma_dd_mesh_batch", "pma_submit", "pma_poll", "pma_server_info", "pma_partition", "pma_theta",
+            "pma_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("n,parts,ov", [((513, 513), (4, 4), 8), ((129, 129, 129), (2, 2, 2), 6),
+                                        ((65, 49), (3, 2), 2), ((200, 97), (5, 1), 5)])
+def test_partition_matches_oracle(L, n, parts, ov):
+    d = len(n)
+    g = W.grid(list(n))
+    ranges, faces = B.partition(g, {"parts": list(parts), "overlap": [ov] * d})
+    dec = O.Decomposition(O.GridSpec(n, (0.0,) * d, (1.0,) * d), parts, (ov,) * d)
+    assert len(ranges) == len(dec.subs)
+    for s, sub in enumerate(dec.subs):
+        for k in range(d):
+            assert ranges[s, 2 * k] == sub.box.off[k]
+            assert ranges[s, 2 * k + 1] == sub.box.off[k] + sub.box.n[k] - 1
+            assert faces[s, 2 * k] == int(sub.box.art_lo[k])
+            assert faces[s, 2 * k + 1] == int(sub.box.art_hi[k])
+
+
+def test_partition_worked_example(L):
+    ranges, faces = B.partition(W.grid([513, 513]), {"parts": [4, 4], "overlap": [8, 8]})
+    assert [tuple(ranges[i, 0:2]) for i in range(0, 16, 4)] == [(0, 132), (124, 260), (252, 388), (380, 512)]
+
+
+@pytest.mark.parametrize("mon,d", [(W.ring_monitor(), 2), (W.sine_monitor(), 2), (W.shell_monitor(), 3),
+                                   ({"kind": "gauss_sum", "bamp": [12.0, 25.0], "bw": [0.05, 0.12],
+                                     "bc": [[0.3, 0.6, 0.5], [0.8, 0.1, 0.4]]}, 3),
+                                   (W.separable_monitor((8.0, 5.0), (20.0, 15.0), (0.4, 0.6)), 2),
+                                   (W.const_monitor(2.5), 2)])
+def test_theta_matches_oracle(L, mon, d):
+    g = W.grid([9] * d)
+    lib = B.theta(g, mon)
+    ref = O.theta(mon, (0.0,) * d, (1.0,) * d)
+    assert abs(lib - ref) < 1e-11 * max(1.0, abs(ref)), (lib, ref)
+
+
+def test_theta_nonunit_box(L):
+    mon = W.ring_monitor(d=3, c=0.0, r0=math.sqrt(0.125), k=20.0)
+    g = W.grid([9, 9, 9], lo=[-1.0] * 3, hi=[1.0] * 3)
+    assert abs(B.theta(g, mon) - O.theta(mon, (-1.0,) * 3, (1.0,) * 3)) < 1e-10
+
+
+@pytest.mark.parametrize("grid,dd", [
+    (W.grid([4, 9]), None),                                       # too few nodes
+    (W.grid([65, 65]), {"parts": [4, 4], "overlap": [1, 1]}),     # overlap < 2 cells
+    (W.grid([17, 17]), {"parts": [8, 1], "overlap": [2, 2]}),     # subdomain < 4 cells
+])
+def test_invalid_shapes_rejected(L, grid, dd):
+    with pytest.raises(B.PmaError) as e:
+        B.partition(grid, dd)
+    assert e.value.code == B.PMA_E_INVAL
+    assert len(L.pma_last_error()) > 0
+
+
+def test_bad_dimension_rejected(L):
+    G = B.Grid()
+    G.dim = 4
+    n = ctypes.c_int()
+    assert L.pma_partition(ctypes.byref(G), None, 0, ctypes.byref(n), None, None) == B.PMA_E_INVAL
+
+
+def test_null_arguments_rejected(L):
+    assert L.pma_theta(None, None, None) == B.PMA_E_INVAL
+    assert L.pma_dd_mesh(None, None, None, None, None, None, None, None, None) == B.PMA_E_INVAL
+    st = ctypes.c_int()
+    assert L.pma_poll(None, 1, ctypes.byref(st), None, None) == B.PMA_E_INVAL
