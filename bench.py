@@ -49,14 +49,17 @@ def timed_form(ctx, binding, w, prec, exec_, steps, warmup, phase_steps):
 def roofline_of(phases, prec):
     name, ph = max(((k, v) for k, v in phases.items()), key=lambda kv: kv[1]["ms"])
     sec = ph["ms"] * 1e-3
-    if name.startswith("gemm"):
+    kern = {"fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel (single)", "pair0": "strip_kernel (pair)",
+            "inv_mid": "strip_kernel (single)", "inv_last": "inv_last_kernel", "transmit": "transmit_kernel",
+            "stencil": "stencil_kernel", "euler": "euler_kernel"}[name]
+    if ph["flops"] > 0:
         ach = ph["flops"] / sec / 1e12
         peak = MFMA_PEAK[prec]
-        return {"kernel": f"gemm_kernel ({name}, mode product)", "bound": "mfma", "achieved": ach, "peak": peak,
+        return {"kernel": f"{kern} ({name})", "bound": "mfma", "achieved": ach, "peak": peak,
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                 "algorithmic_per_launch": ph["flops"], "avg_ms": ph["ms"]}
     ach = ph["bytes"] / sec / 1e9
-    return {"kernel": f"{name}_kernel", "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+    return {"kernel": f"{kern} ({name})", "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
             "frac": ach / PEAK["hbm_GBs"], "traffic": None, "algorithmic_per_launch": ph["bytes"],
             "avg_ms": ph["ms"]}
 

@@ -211,11 +211,16 @@ int pma_plan_step(pma_plan* plan, int nsteps);
  * broken down. */
 int pma_plan_sync(pma_plan* plan);
 
-/* Phases of one step, in launch order: 0 transmission, 1 stencil, 2 forward-Euler update,
- * 3..8 mode products 0..5.  Runs nsteps steps with HIP events around every phase (on the stream
- * the kernels run on) and returns the mean device milliseconds per step of each phase in ms[]
- * (cap >= 9 entries); flops[] and bytes[] (may be NULL) receive each phase's algorithmic
- * floating-point operations and compulsory HBM bytes per step.  *nphases receives 9. */
+/* Phases of one step, in launch order:
+ *   0 transmission of artificial-boundary values     1 stencil: right-hand side F
+ *   2 forward-Euler update (gamma = 0)                3 forward DCT along the last axis
+ *   4 forward DCT along the middle axis (3D)          5 forward DCT + spectral scale + inverse DCT
+ *                                                       along axis 0
+ *   6 inverse DCT along the middle axis (3D)          7 inverse DCT along the last axis + update
+ * Runs nsteps steps with HIP events around every phase (on the stream the kernels run on) and
+ * returns the mean device milliseconds per step of each phase in ms[] (cap >= 8 entries);
+ * flops[] and bytes[] (may be NULL) receive each phase's algorithmic floating-point operations
+ * and compulsory HBM bytes per step.  *nphases receives 8. */
 int pma_plan_phase_times(pma_plan* plan, int nsteps, double* ms, double* flops, double* bytes, int cap,
                          int* nphases);
 

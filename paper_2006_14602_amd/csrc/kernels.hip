@@ -101,35 +101,22 @@ template <typename T>
 __device__ inline bool finite_(T x) { return isfinite(x); }
 
 // ------------------------------------------------------------------------------------------
-// K1/K2: stencil + monitor + log.  Tile = 4 rows x 64 columns of the [rows][last axis] view.
+// K1/K2: stencil + monitor + log at one node.  (row, col) index the [rows][last axis] view of
+// the subdomain (rows = n0 in 2D, n0 * n1 in 3D).  Returns F; raises the instance's status bits
+// on a non-positive determinant or a non-finite value.  Artificial-boundary nodes get F = 0.
 // ------------------------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ tiles, int ntiles,
-                                                      StepArgs sa) {
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
-  const SubDev& S = sa.subs[tl.x];
-  const InstDev& I = sa.insts[S.inst];
-  const int d = S.dim;
-  const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
-  const int R = (d == 2) ? n0 : n0 * n1;
-  const int C = (d == 2) ? n1 : n2;
-  const int row = tl.y + (threadIdx.x >> 6);
-  const int col = tl.z + (threadIdx.x & 63);
-  if (row >= R || col >= C) return;
+__device__ inline T stencil_point(const SubDev& S, const InstDev& I, int row, int col, int* status) {
   const T* __restrict__ phi = (const T*)S.phi;
-  T* __restrict__ F = (T*)S.F;
+  const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
   const T h0 = T(S.h[0]), h1 = T(S.h[1]), h2 = T(S.h[2]);
-  if (d == 2) {
+  T f, e;
+  if (S.dim == 2) {
     const int i = row, j = col;
-    const long v = (long)i * n1 + j;
-    if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1)) {
-      F[v] = T(0);
-      return;
-    }
+    if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1)) return T(0);
     const int im = mlo(i), ip = mhi(i, n0), jm = mlo(j), jp = mhi(j, n1);
-    const T c = phi[v];
+    const T c = phi[(long)i * n1 + j];
     const T xm = phi[(long)im * n1 + j], xp = phi[(long)ip * n1 + j];
     const T ym = phi[(long)i * n1 + jm], yp = phi[(long)i * n1 + jp];
     const T mm = phi[(long)im * n1 + jm], mp = phi[(long)im * n1 + jp];
@@ -139,27 +126,20 @@ __global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ t
     const T hxx = (xp - T(2) * c + xm) / (h0 * h0);
     const T hyy = (yp - T(2) * c + ym) / (h1 * h1);
     const T hxy = (pp - pm - mp + mm) / (T(4) * h0 * h1);
-    const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
+    e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
     const T x0 = T(S.a[0]) + T(S.off[0] + i) * h0 + gx;
     const T x1 = T(S.a[1]) + T(S.off[1] + j) * h1 + gy;
-    const T f = T(I.log_vol_theta) + log_rho<T>(I.mon, 2, x0, x1, T(0)) + dlog1p(e);
-    F[v] = f;
-    if (!(T(1) + e > T(0))) atomicOr(&sa.status[S.inst], ST_TANGLED);
-    else if (!finite_(f)) atomicOr(&sa.status[S.inst], ST_NONFINITE);
+    f = T(I.log_vol_theta) + log_rho<T>(I.mon, 2, x0, x1, T(0)) + dlog1p(e);
   } else {
     const int i = row / n1, j = row - (row / n1) * n1, k = col;
+    if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1) || is_artificial(S.art, 2, k, n2))
+      return T(0);
     const long s1 = n2, s0 = (long)n1 * n2;
-    const long v = i * s0 + j * s1 + k;
-    if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1) ||
-        is_artificial(S.art, 2, k, n2)) {
-      F[v] = T(0);
-      return;
-    }
     const long im = mlo(i) * s0, ip = mhi(i, n0) * s0;
     const long jm = mlo(j) * s1, jp = mhi(j, n1) * s1;
     const long km = mlo(k), kp = mhi(k, n2);
     const long I0 = i * s0, J0 = j * s1, K0 = k;
-    const T c = phi[v];
+    const T c = phi[I0 + J0 + K0];
     const T xm = phi[im + J0 + K0], xp = phi[ip + J0 + K0];
     const T ym = phi[I0 + jm + K0], yp = phi[I0 + jp + K0];
     const T zm = phi[I0 + J0 + km], zp = phi[I0 + J0 + kp];
@@ -179,15 +159,31 @@ __global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ t
     const T tr = a + b + q;
     const T m2 = (a * b - p * p) + (a * q - r * r) + (b * q - s * s);
     const T dt3 = a * (b * q - s * s) - p * (p * q - s * r) + r * (p * s - b * r);
-    const T e = tr + m2 + dt3;
+    e = tr + m2 + dt3;
     const T x0 = T(S.a[0]) + T(S.off[0] + i) * h0 + gx;
     const T x1 = T(S.a[1]) + T(S.off[1] + j) * h1 + gy;
     const T x2 = T(S.a[2]) + T(S.off[2] + k) * h2 + gz;
-    const T f = T(I.log_vol_theta) + log_rho<T>(I.mon, 3, x0, x1, x2) + dlog1p(e);
-    F[v] = f;
-    if (!(T(1) + e > T(0))) atomicOr(&sa.status[S.inst], ST_TANGLED);
-    else if (!finite_(f)) atomicOr(&sa.status[S.inst], ST_NONFINITE);
+    f = T(I.log_vol_theta) + log_rho<T>(I.mon, 3, x0, x1, x2) + dlog1p(e);
   }
+  if (!(T(1) + e > T(0))) atomicOr(&status[S.inst], ST_TANGLED);
+  else if (!finite_(f)) atomicOr(&status[S.inst], ST_NONFINITE);
+  return f;
+}
+
+// Stand-alone stencil (forward-Euler solves): tile = 4 rows x 64 columns, writes F.
+template <typename T>
+__global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ tiles, int ntiles,
+                                                      StepArgs sa) {
+  if ((int)blockIdx.x >= ntiles) return;
+  const int4 tl = tiles[blockIdx.x];
+  const SubDev& S = sa.subs[tl.x];
+  const InstDev& I = sa.insts[S.inst];
+  const int R = (S.dim == 2) ? S.n[0] : S.n[0] * S.n[1];
+  const int C = S.n[S.dim - 1];
+  const int row = tl.y + (threadIdx.x >> 6);
+  const int col = tl.z + (threadIdx.x & 63);
+  if (row >= R || col >= C) return;
+  ((T*)S.F)[(long)row * C + col] = stencil_point<T>(S, I, row, col, sa.status);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -214,6 +210,193 @@ __device__ inline double block_min256(double v, double* red) {
   return r;
 }
 
+// ------------------------------------------------------------------------------------------
+// K3/K4/K5: the preconditioner's mode products on the matrix cores.
+//
+// A mode product contracts one axis of a subdomain array with an n x n DCT matrix.  Both DCT
+// matrices are symmetric, so every operand is read as "row r of a row-major matrix": rows of the
+// A operand are its rows, columns of the B operand are rows of B^T = B.  A 16 x 16 output block
+// takes KB-deep fragments; lane l supplies row l % 16 at k offsets set by g = l / 16:
+//   fp16 (16x16x32):   k = 8 g .. 8 g + 7      f32 / f64 (16x16x4):   k = g
+// Data operands are staged whole-K in LDS (zero padded to ld); basis fragments stream from L2.
+//
+// Three kernels cover every product of a step:
+//   fwd_last   stencil of 16 rows -> LDS, then  T[rows, :] = F[rows, :] * A_last
+//   strip      a 16-column strip of the [n_axis][rest] view: Y = Bas * X (axis 0 or the middle
+//              axis in 3D); PAIR: Y = B_0 * (S o (A_0 * X)) with the spectral scale in between
+//   inv_last   16 rows: delta = T[rows, :] * B_last, then phi += dt (delta - shift) on live
+//              nodes and the FP64 residual partial sum
+// ------------------------------------------------------------------------------------------
+
+template <int KIND> struct Op;
+
+template <> struct Op<PREC_SPLIT16> {
+  typedef float T;
+  typedef float4_t acc_t;
+  enum { KB = 32, LDS_BYTES = 4, SCALED = 1 };
+  struct frag { half8_t hi, lo; };
+  // LDS holds the data operand in fp32; a fragment is scaled by the tile's power of two and
+  // split into fp16 hi + lo when it is read (block floating point: small entries keep their
+  // absolute accuracy relative to the tile's largest one instead of falling to fp16 subnormals)
+  static __device__ inline void put(char* lds, int ld, int r, int k, float x) { ((float*)lds)[r * ld + k] = x; }
+  static __device__ inline frag lds_frag(const char* lds, int ld, int r, int k0, int g, float sc) {
+    const float4_t* p = (const float4_t*)((const float*)lds + r * ld + k0 + 8 * g);
+    const float4_t u = p[0], v = p[1];
+    frag f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float x = u[i] * sc, y = v[i] * sc;
+      const _Float16 hx = (_Float16)x, hy = (_Float16)y;
+      f.hi[i] = hx;
+      f.hi[4 + i] = hy;
+      f.lo[i] = (_Float16)(x - (float)hx);
+      f.lo[4 + i] = (_Float16)(y - (float)hy);
+    }
+    return f;
+  }
+  static __device__ inline frag glob_frag(const void* hi, const void* lo, int ld, int r, int k0, int g) {
+    frag f;
+    f.hi = *(const half8_t*)((const _Float16*)hi + (long)r * ld + k0 + 8 * g);
+    f.lo = *(const half8_t*)((const _Float16*)lo + (long)r * ld + k0 + 8 * g);
+    return f;
+  }
+  static __device__ inline void mma(acc_t& c, const frag& a, const frag& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.lo, b.hi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.lo, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, c, 0, 0, 0);
+  }
+  static __device__ inline int crow(int g, int q) { return 4 * g + q; }
+};
+
+template <> struct Op<PREC_F32> {
+  typedef float T;
+  typedef float4_t acc_t;
+  enum { KB = 4, LDS_BYTES = 4, SCALED = 0 };
+  typedef float frag;
+  static __device__ inline void put(char* lds, int ld, int r, int k, float x) { ((float*)lds)[r * ld + k] = x; }
+  static __device__ inline frag lds_frag(const char* lds, int ld, int r, int k0, int g, float) {
+    return ((const float*)lds)[r * ld + k0 + g];
+  }
+  static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
+    return ((const float*)p)[(long)r * ld + k0 + g];
+  }
+  static __device__ inline void mma(acc_t& c, frag a, frag b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int crow(int g, int q) { return 4 * g + q; }
+};
+
+template <> struct Op<PREC_F64> {
+  typedef double T;
+  typedef double4_t acc_t;
+  enum { KB = 4, LDS_BYTES = 8, SCALED = 0 };
+  typedef double frag;
+  static __device__ inline void put(char* lds, int ld, int r, int k, double x) { ((double*)lds)[r * ld + k] = x; }
+  static __device__ inline frag lds_frag(const char* lds, int ld, int r, int k0, int g, float) {
+    return ((const double*)lds)[r * ld + k0 + g];
+  }
+  static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
+    return ((const double*)p)[(long)r * ld + k0 + g];
+  }
+  static __device__ inline void mma(acc_t& c, frag a, frag b) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the f64 product interleaves rows: register q of lane group g holds row g + 4 q
+  static __device__ inline int crow(int g, int q) { return g + 4 * q; }
+};
+
+// acc += rows of the LDS operand (16 x ld) times basis rows (as columns of B), and the mirror
+// image.  Basis fragments come from L2: four k steps are requested before any is used so their
+// latencies overlap (ld is a multiple of 32, so every group of four is complete for fp16 and a
+// multiple of four steps for the 4-deep products).
+template <int KIND>
+__device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, float sc,
+                                        const void* bh, const void* bl, int brow, int l16, int g) {
+  typedef Op<KIND> O;
+  constexpr int U = 4;
+  for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
+    typename O::frag b[U];
+    const int nu = min(U, (ld - k0) / (int)O::KB);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < nu) b[u] = O::glob_frag(bh, bl, ld, brow, k0 + u * O::KB, g);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < nu) O::mma(acc, O::lds_frag(lds, ld, l16, k0 + u * O::KB, g, sc), b[u]);
+  }
+}
+
+template <int KIND>
+__device__ inline void mma_basis_by_lds(typename Op<KIND>::acc_t& acc, const void* ah, const void* al,
+                                        const char* lds, int ld, float sc, int arow, int l16, int g) {
+  typedef Op<KIND> O;
+  constexpr int U = 4;
+  for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
+    typename O::frag a[U];
+    const int nu = min(U, (ld - k0) / (int)O::KB);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < nu) a[u] = O::glob_frag(ah, al, ld, arow, k0 + u * O::KB, g);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < nu) O::mma(acc, a[u], O::lds_frag(lds, ld, l16, k0 + u * O::KB, g, sc));
+  }
+}
+
+// power-of-two scale bringing the tile's largest magnitude to [2^13, 2^14) (1 for an all-zero
+// tile); every thread passes its own running maximum
+__device__ inline float tile_scale(float amax, float* red) {
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  __syncthreads();
+  if (!(m > 0.f) || !isfinite(m)) return 1.f;
+  int e;
+  frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  return ldexpf(1.f, 14 - e);
+}
+
+// forward transform along the last axis for 16 rows x up to 64 columns: T = F * A_last
+template <int KIND>
+__global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  if ((int)blockIdx.x >= ntiles) return;
+  const int4 tl = tiles[blockIdx.x];
+  const SubDev& S = sa.subs[tl.x];
+  const int la = S.dim - 1;
+  const int R = S.dim == 2 ? S.n[0] : S.n[0] * S.n[1];
+  const int C = S.n[la];
+  const AxisDev& A = S.ax[la];
+  const int ld = A.ld;
+  const int row0 = tl.y, col0 = tl.z;
+  __shared__ float red[4];
+  const T* __restrict__ src = (const T*)S.F;
+  float amax = 0.f;
+  for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
+    const int r = idx / ld, k = idx - r * ld;
+    const T x = (row0 + r < R && k < C) ? src[(long)(row0 + r) * C + k] : T(0);
+    O::put(lds, ld, r, k, x);
+    if (O::SCALED) amax = fmaxf(amax, fabsf((float)x));
+  }
+  const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int cb = (col0 >> 4) + wave;
+  if (cb * 16 >= C) return;
+  typename O::acc_t acc = {0, 0, 0, 0};
+  mma_lds_by_basis<KIND>(acc, lds, ld, sc, A.fwd, A.fwdl, cb * 16 + l16, l16, g);
+  T* __restrict__ out = (T*)S.T;
+  const T us = T(A.fwd_unscale) / T(sc);
+  const int c = cb * 16 + l16;
+  for (int q = 0; q < 4; ++q) {
+    const int r = row0 + O::crow(g, q);
+    if (r < R && c < C) out[(long)r * C + c] = acc[q] * us;
+  }
+}
+
 // shift removed from phi each step: mean over the instance's subdomains of the DC coefficient
 template <typename T>
 __device__ inline T instance_shift(const StepArgs& sa, const InstDev& I) {
@@ -232,6 +415,203 @@ __device__ inline void node_weight(const SubDev& S, int i0, int i1, int i2, doub
   for (int k = 0; k < S.dim; ++k) {
     if (idx[k] == 0 || idx[k] == S.n[k] - 1) w *= 0.5;
     if (is_artificial(S.art, k, idx[k], S.n[k])) live = false;
+  }
+}
+
+// inverse transform along the last axis for 16 rows x up to 64 columns, fused with the update
+// phi += dt (delta - shift) and the residual partial sum.  Input: F.
+template <int KIND>
+__global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
+                                                       StepArgs sa) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  __shared__ double red[4];
+  if ((int)blockIdx.x >= ntiles) return;
+  const int4 tl = tiles[blockIdx.x];
+  const SubDev& S = sa.subs[tl.x];
+  const InstDev& I = sa.insts[S.inst];
+  const int la = S.dim - 1;
+  const int R = S.dim == 2 ? S.n[0] : S.n[0] * S.n[1];
+  const int C = S.n[la];
+  const AxisDev& A = S.ax[la];
+  const int ld = A.ld;
+  const int row0 = tl.y, col0 = tl.z;
+  __shared__ float redf[4];
+  const T* __restrict__ src = (const T*)S.F;
+  float amax = 0.f;
+  for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
+    const int r = idx / ld, k = idx - r * ld;
+    const T x = (row0 + r < R && k < C) ? src[(long)(row0 + r) * C + k] : T(0);
+    O::put(lds, ld, r, k, x);
+    if (O::SCALED) amax = fmaxf(amax, fabsf((float)x));
+  }
+  const float sc = O::SCALED ? tile_scale(amax, redf) : 1.f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int cb = (col0 >> 4) + wave;
+  const T shift = instance_shift<T>(sa, I);
+  const T dt = T(I.dt);
+  const T isc = T(1) / T(sc);
+  double part = 0.0;
+  if (cb * 16 < C) {
+    typename O::acc_t acc = {0, 0, 0, 0};
+    mma_lds_by_basis<KIND>(acc, lds, ld, sc, A.inv, A.invl, cb * 16 + l16, l16, g);
+    T* __restrict__ phi = (T*)S.phi;
+    const int c = cb * 16 + l16;
+    bool bad = false;
+    for (int q = 0; q < 4; ++q) {
+      const int r = row0 + O::crow(g, q);
+      if (r < R && c < C) {
+        int i0, i1, i2;
+        if (S.dim == 2) {
+          i0 = r; i1 = c; i2 = 0;
+        } else {
+          i0 = r / S.n[1]; i1 = r - i0 * S.n[1]; i2 = c;
+        }
+        double w;
+        bool live;
+        node_weight(S, i0, i1, i2, w, live);
+        if (live) {
+          const T val = acc[q] * isc;
+          const T u = dt * val;
+          phi[(long)r * C + c] += dt * (val - shift);
+          part += w * (double)u * (double)u;
+          bad |= !finite_(u);
+        }
+      }
+    }
+    if (bad) atomicOr(&sa.status[S.inst], ST_NONFINITE);
+  }
+  const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
+  const double tot = block_sum256(part, red);
+  if (threadIdx.x == 0) {
+    sa.partials[part_base + blockIdx.x] = tot * hs;
+    if (I.pin && tl.x == I.first_sub && row0 == 0 && col0 == 0) sa.shift_acc[S.inst] += (double)dt * (double)shift;
+  }
+}
+
+// 16-column strip of the [n_axis][rest] view (axis 0), or of one [n1][n2] slab (axis 1, 3D;
+// tile.y = slab index i0).  src / dst: 0 = F, 1 = T.
+//   PAIR = false: dst = Bas * src, Bas the forward (inv = 0) or inverse (inv = 1) basis
+//   PAIR = true (axis 0): dst = B_0 * (S o (A_0 * src)), S the spectral scale
+//                         1 / (1 + sum_k gamma mu_k); the DC coefficient is recorded
+template <int KIND, bool PAIR>
+__global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
+                                                    int src_sel, StepArgs sa) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  constexpr int MAXRB = 9;  // row blocks per wave: n <= 9 * 4 * 16 = 576
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  if ((int)blockIdx.x >= ntiles) return;
+  const int4 tl = tiles[blockIdx.x];
+  const SubDev& S = sa.subs[tl.x];
+  const int K = S.n[axis];
+  const AxisDev& A = S.ax[axis];
+  const int ld = A.ld;
+  int ncol;
+  long base;
+  if (axis == 0) {
+    ncol = S.dim == 2 ? S.n[1] : S.n[1] * S.n[2];
+    base = 0;
+  } else {
+    ncol = S.n[2];
+    base = (long)tl.y * S.n[1] * S.n[2];
+  }
+  const int col0 = tl.z;
+  const T* __restrict__ src = (const T*)(src_sel ? S.T : S.F) + base;
+  T* __restrict__ dst = (T*)(src_sel ? S.F : S.T) + base;
+  __shared__ float red[4];
+  // strip transposed into LDS: operand row c = strip column, k = index along the axis
+  float amax = 0.f;
+  for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
+    const int k = idx >> 4, c = idx & 15;
+    const T x = (k < K && col0 + c < ncol) ? src[(long)k * ncol + col0 + c] : T(0);
+    O::put(lds, ld, c, k, x);
+    if (O::SCALED) amax = fmaxf(amax, fabsf((float)x));
+  }
+  const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int nrb = (K + 15) >> 4;
+  const int c = col0 + l16;
+  typename O::acc_t acc[MAXRB];
+  const void* b1h = (PAIR || !inv) ? A.fwd : A.inv;
+  const void* b1l = (PAIR || !inv) ? A.fwdl : A.invl;
+  const T us1 = ((PAIR || !inv) ? T(A.fwd_unscale) : T(1)) / T(sc);
+#pragma unroll
+  for (int t = 0; t < MAXRB; ++t) {
+    acc[t] = typename O::acc_t{0, 0, 0, 0};
+    const int rb = wave + 4 * t;
+    if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, lds, ld, sc, rb * 16 + l16, l16, g);
+  }
+  if constexpr (!PAIR) {
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb >= nrb) continue;
+      for (int q = 0; q < 4; ++q) {
+        const int i = rb * 16 + O::crow(g, q);
+        if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][q] * us1;
+      }
+    }
+  } else {
+    // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2
+    const T* s0 = (const T*)S.ax[0].sig;
+    const T* s1 = (const T*)S.ax[1].sig;
+    const T* s2 = (const T*)S.ax[2].sig;
+    const T g0 = T(S.gh2[0]), g1 = T(S.gh2[1]), g2 = T(S.gh2[2]);
+    T rest = T(0);
+    if (c < ncol) {
+      if (S.dim == 2) rest = g1 * s1[c];
+      else {
+        const int k1 = c / S.n[2], k2 = c - (c / S.n[2]) * S.n[2];
+        rest = g1 * s1[k1] + g2 * s2[k2];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      for (int q = 0; q < 4; ++q) {
+        const int i = rb * 16 + O::crow(g, q);
+        T y = T(0);
+        if (rb < nrb && i < K && c < ncol) {
+          const T val = acc[t][q] * us1;
+          if (i == 0 && c == 0) ((T*)sa.dc)[tl.x] = val;
+          y = val / (T(1) + g0 * s0[i] + rest);
+        }
+        acc[t][q] = y;
+      }
+    }
+    __syncthreads();  // every wave is done reading the strip
+    float ymax = 0.f;
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb >= nrb) continue;
+      for (int q = 0; q < 4; ++q) {
+        O::put(lds, ld, l16, rb * 16 + O::crow(g, q), acc[t][q]);
+        if (O::SCALED) ymax = fmaxf(ymax, fabsf((float)acc[t][q]));
+      }
+    }
+    const float sy = O::SCALED ? tile_scale(ymax, red) : 1.f;
+    // zero the padding rows nrb*16 .. ld of the operand
+    for (int idx = threadIdx.x; idx < 16 * (ld - nrb * 16); idx += 256) {
+      const int k = nrb * 16 + idx / 16, cc = idx & 15;
+      O::put(lds, ld, cc, k, T(0));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb >= nrb) continue;
+      typename O::acc_t z = {0, 0, 0, 0};
+      mma_basis_by_lds<KIND>(z, A.inv, A.invl, lds, ld, sy, rb * 16 + l16, l16, g);
+      for (int q = 0; q < 4; ++q) {
+        const int i = rb * 16 + O::crow(g, q);
+        if (i < K && c < ncol) dst[(long)i * ncol + c] = z[q] / T(sy);
+      }
+    }
   }
 }
 
@@ -273,211 +653,6 @@ __global__ __launch_bounds__(256) void euler_kernel(const int4* __restrict__ til
   double hs = S.h[0] * S.h[1] * (d == 3 ? S.h[2] : 1.0);
   double tot = block_sum256(acc, red);
   if (threadIdx.x == 0) sa.partials[part_base + blockIdx.x] = tot * hs;
-}
-
-// ------------------------------------------------------------------------------------------
-// K3/K4/K5: batched mode products on the matrix cores, 64 x 64 output tile, 4 waves of 32 x 32
-// ------------------------------------------------------------------------------------------
-
-template <int KIND> struct GemmTraits;
-template <> struct GemmTraits<PREC_F64> { typedef double T; enum { BK = 16 }; };
-template <> struct GemmTraits<PREC_F32> { typedef float T; enum { BK = 16 }; };
-template <> struct GemmTraits<PREC_SPLIT16> { typedef float T; enum { BK = 32 }; };
-
-template <typename T>
-__device__ inline void mfma4(T a, T b, typename std::conditional<sizeof(T) == 8, double4_t, float4_t>::type& c);
-
-template <>
-__device__ inline void mfma4<double>(double a, double b, double4_t& c) {
-  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-template <>
-__device__ inline void mfma4<float>(float a, float b, float4_t& c) {
-  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-template <int KIND>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmJob* __restrict__ jobs,
-                                                   const int4* __restrict__ tiles, int ntiles,
-                                                   int part_base, StepArgs sa) {
-  typedef typename GemmTraits<KIND>::T T;
-  typedef typename std::conditional<sizeof(T) == 8, double4_t, float4_t>::type acc_t;
-  constexpr int BK = GemmTraits<KIND>::BK;
-  __shared__ double red[4];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
-  const GemmJob& J = jobs[tl.x];
-  const int M = J.M, N = J.N, K = J.K;
-  const int m0 = tl.y, n0 = tl.z, b = tl.w;
-  const T* __restrict__ P = (const T*)J.P + (long)b * J.sP;
-  const T* __restrict__ Q = (const T*)J.Q + (long)b * J.sQ;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int l16 = lane & 15, lg = lane >> 4;
-
-  acc_t acc[2][2];
-  for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 2; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
-
-  if constexpr (KIND != PREC_SPLIT16) {
-    __shared__ T Ps[64][BK + 1];
-    __shared__ T Qs[BK][64 + 16];
-    const int prow = tid >> 2, pk = (tid & 3) * 4;
-    const int qk = tid >> 4, qn = (tid & 15) * 4;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      {
-        const int m = m0 + prow;
-        for (int j = 0; j < 4; ++j) {
-          const int k = k0 + pk + j;
-          Ps[prow][pk + j] = (m < M && k < K) ? P[(long)m * J.ldp + k] : T(0);
-        }
-        const int k = k0 + qk;
-        for (int j = 0; j < 4; ++j) {
-          const int n = n0 + qn + j;
-          Qs[qk][qn + j] = (k < K && n < N) ? Q[(long)k * J.ldq + n] : T(0);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        T a[2], bv[2];
-        for (int r = 0; r < 2; ++r) a[r] = Ps[wm * 32 + r * 16 + l16][kk * 4 + lg];
-        for (int c = 0; c < 2; ++c) bv[c] = Qs[kk * 4 + lg][wn * 32 + c * 16 + l16];
-        for (int r = 0; r < 2; ++r)
-          for (int c = 0; c < 2; ++c) mfma4<T>(a[r], bv[c], acc[r][c]);
-      }
-      __syncthreads();
-    }
-  } else {
-    // fp16 hi + lo split of both operands; three products per k block, FP32 accumulation
-    __shared__ _Float16 Ph[64][BK + 8], Pl[64][BK + 8];
-    __shared__ _Float16 Qh[64][BK + 8], Ql[64][BK + 8];  // transposed: [n][k]
-    const int prow = tid >> 2, pk = (tid & 3) * 8;
-    const int qk = tid >> 3, qn = (tid & 7) * 8;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      {
-        const int m = m0 + prow;
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + pk + j;
-          const float x = (m < M && k < K) ? P[(long)m * J.ldp + k] : 0.f;
-          const _Float16 hi = (_Float16)x;
-          Ph[prow][pk + j] = hi;
-          Pl[prow][pk + j] = (_Float16)(x - (float)hi);
-        }
-        const int k = k0 + qk;
-        for (int j = 0; j < 8; ++j) {
-          const int n = n0 + qn + j;
-          const float x = (k < K && n < N) ? Q[(long)k * J.ldq + n] : 0.f;
-          const _Float16 hi = (_Float16)x;
-          Qh[qn + j][qk] = hi;
-          Ql[qn + j][qk] = (_Float16)(x - (float)hi);
-        }
-      }
-      __syncthreads();
-      half8_t ah[2], al[2], bh[2], bl[2];
-      for (int r = 0; r < 2; ++r) {
-        ah[r] = *(const half8_t*)&Ph[wm * 32 + r * 16 + l16][lg * 8];
-        al[r] = *(const half8_t*)&Pl[wm * 32 + r * 16 + l16][lg * 8];
-      }
-      for (int c = 0; c < 2; ++c) {
-        bh[c] = *(const half8_t*)&Qh[wn * 32 + c * 16 + l16][lg * 8];
-        bl[c] = *(const half8_t*)&Ql[wn * 32 + c * 16 + l16][lg * 8];
-      }
-      for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) {
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], bh[c], acc[r][c], 0, 0, 0);
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bl[c], acc[r][c], 0, 0, 0);
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bh[c], acc[r][c], 0, 0, 0);
-        }
-      __syncthreads();
-    }
-  }
-
-  // ---------------- epilogue ----------------
-  // row of accumulator register q within a 16 x 16 block: the f64 product interleaves rows
-  // (row = lane/16 + 4 q), the f32-accumulating products keep them together (4 lane/16 + q)
-  auto crow = [](int g, int q) { return KIND == PREC_F64 ? g + 4 * q : 4 * g + q; };
-  const T us = T(J.unscale);
-  T* __restrict__ Cp = (T*)J.C + (long)b * J.sC;
-  const int epi = J.epi;
-  if (epi == EPI_NONE) {
-    for (int r = 0; r < 2; ++r)
-      for (int c = 0; c < 2; ++c)
-        for (int q = 0; q < 4; ++q) {
-          const int m = m0 + wm * 32 + r * 16 + crow(lg, q);
-          const int n = n0 + wn * 32 + c * 16 + l16;
-          if (m < M && n < N) Cp[(long)m * J.ldc + n] = acc[r][c][q] * us;
-        }
-    return;
-  }
-  const SubDev& S = sa.subs[J.sub];
-  if (epi == EPI_SCALE) {
-    // left product along axis 0 completes the forward transform: m = k0, n = (k1[, k2])
-    const T* s0 = (const T*)S.sig[0];
-    const T* s1 = (const T*)S.sig[1];
-    const T* s2 = (const T*)S.sig[2];
-    const T g0 = T(S.gh2[0]), g1 = T(S.gh2[1]), g2 = T(S.gh2[2]);
-    const int n2 = S.n[2];
-    for (int r = 0; r < 2; ++r)
-      for (int c = 0; c < 2; ++c)
-        for (int q = 0; q < 4; ++q) {
-          const int m = m0 + wm * 32 + r * 16 + crow(lg, q);
-          const int n = n0 + wn * 32 + c * 16 + l16;
-          if (m < M && n < N) {
-            const T val = acc[r][c][q] * us;
-            T den;
-            if (S.dim == 2) {
-              den = T(1) + g0 * s0[m] + g1 * s1[n];
-            } else {
-              const int k1 = n / n2, k2 = n - (n / n2) * n2;
-              den = T(1) + g0 * s0[m] + g1 * s1[k1] + g2 * s2[k2];
-            }
-            Cp[(long)m * J.ldc + n] = val / den;
-            if (m == 0 && n == 0) ((T*)sa.dc)[J.sub] = val;
-          }
-        }
-    return;
-  }
-  // EPI_UPDATE: right product along the last axis completes the inverse transform:
-  // m = flat index over the leading axes, n = last-axis index; C is phi.
-  const InstDev& I = sa.insts[S.inst];
-  const T shift = instance_shift<T>(sa, I);
-  const T dt = T(I.dt);
-  double part = 0.0;
-  bool bad = false;
-  for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 2; ++c)
-      for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm * 32 + r * 16 + crow(lg, q);
-        const int n = n0 + wn * 32 + c * 16 + l16;
-        if (m < M && n < N) {
-          const T val = acc[r][c][q] * us;
-          int i0, i1, i2;
-          if (S.dim == 2) {
-            i0 = m; i1 = n; i2 = 0;
-          } else {
-            i0 = m / S.n[1]; i1 = m - i0 * S.n[1]; i2 = n;
-          }
-          double w;
-          bool live;
-          node_weight(S, i0, i1, i2, w, live);
-          if (live) {
-            const T u = dt * val;
-            Cp[(long)m * J.ldc + n] += dt * (val - shift);
-            part += w * (double)u * (double)u;
-            bad |= !finite_(u);
-          }
-        }
-      }
-  if (bad) atomicOr(&sa.status[S.inst], ST_NONFINITE);
-  const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
-  const double tot = block_sum256(part, red);
-  if (tid == 0) {
-    sa.partials[part_base + blockIdx.x] = tot * hs;
-    if (I.pin && J.sub == I.first_sub && m0 == 0 && n0 == 0 && b == 0)
-      sa.shift_acc[S.inst] += (double)dt * (double)shift;
-  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -538,6 +713,7 @@ __global__ void phi_from_psi_kernel(SubDev S, const double* __restrict__ psi, in
   }
 }
 
+// artificial-boundary nodes are left untouched: they hold the caller's Dirichlet data
 template <typename T>
 __global__ void psi_from_phi_kernel(SubDev S, double* __restrict__ psi, const double* shift_acc) {
   const long tot = (long)S.n[0] * S.n[1] * S.n[2];
@@ -549,6 +725,9 @@ __global__ void psi_from_phi_kernel(SubDev S, double* __restrict__ psi, const do
     const int i0 = (int)(v / ((long)S.n[2] * S.n[1]));
     double q = 0.0;
     const int idx[3] = {i0, i1, i2};
+    bool art = false;
+    for (int k = 0; k < S.dim; ++k) art |= is_artificial(S.art, k, idx[k], S.n[k]);
+    if (art) continue;
     for (int k = 0; k < S.dim; ++k) {
       const double x = S.a[k] + (double)(S.off[k] + idx[k]) * S.h[k];
       q += x * x;
@@ -732,16 +911,72 @@ hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, 
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(int prec, const GemmJob* jobs, const int4* tiles, int ntiles, int part_base,
-                       const StepArgs& sa, hipStream_t s) {
+static inline size_t op_lds(int prec, int ld) {
+  return (size_t)16 * ld * (prec == PREC_F64 ? 8 : 4);
+}
+
+hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  const size_t sh = op_lds(prec, maxld);
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(gemm_kernel<PREC_F64>, dim3(ntiles), dim3(256), 0, s, jobs, tiles, ntiles, part_base, sa);
+    hipLaunchKernelGGL(fwd_last_kernel<PREC_F64>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, sa);
   else if (prec == PREC_F32)
-    hipLaunchKernelGGL(gemm_kernel<PREC_F32>, dim3(ntiles), dim3(256), 0, s, jobs, tiles, ntiles, part_base, sa);
+    hipLaunchKernelGGL(fwd_last_kernel<PREC_F32>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, sa);
   else
-    hipLaunchKernelGGL(gemm_kernel<PREC_SPLIT16>, dim3(ntiles), dim3(256), 0, s, jobs, tiles, ntiles, part_base, sa);
+    hipLaunchKernelGGL(fwd_last_kernel<PREC_SPLIT16>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, sa);
   return hipGetLastError();
+}
+
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
+                           hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const size_t sh = op_lds(prec, maxld);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(inv_last_kernel<PREC_F64>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, sa);
+  else if (prec == PREC_F32)
+    hipLaunchKernelGGL(inv_last_kernel<PREC_F32>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, sa);
+  else
+    hipLaunchKernelGGL(inv_last_kernel<PREC_SPLIT16>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
+                        int src_sel, const StepArgs& sa, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const size_t sh = op_lds(prec, maxld);
+#define PMA_STRIP(K, P) \
+  hipLaunchKernelGGL((strip_kernel<K, P>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, axis, inv, src_sel, sa)
+  if (prec == PREC_F64) {
+    if (pair) PMA_STRIP(PREC_F64, true); else PMA_STRIP(PREC_F64, false);
+  } else if (prec == PREC_F32) {
+    if (pair) PMA_STRIP(PREC_F32, true); else PMA_STRIP(PREC_F32, false);
+  } else {
+    if (pair) PMA_STRIP(PREC_SPLIT16, true); else PMA_STRIP(PREC_SPLIT16, false);
+  }
+#undef PMA_STRIP
+  return hipGetLastError();
+}
+
+// kernels using more than 64 KiB of dynamic LDS must say so once per process
+hipError_t enable_large_lds() {
+  static hipError_t rc = [] {
+    // 160 KiB per workgroup on gfx950, less room for the kernels' own static LDS
+    const int lim = 160 * 1024 - 4096;
+    hipError_t e = hipSuccess;
+    const void* ks[] = {(const void*)fwd_last_kernel<PREC_F64>, (const void*)fwd_last_kernel<PREC_F32>,
+                        (const void*)fwd_last_kernel<PREC_SPLIT16>, (const void*)inv_last_kernel<PREC_F64>,
+                        (const void*)inv_last_kernel<PREC_F32>, (const void*)inv_last_kernel<PREC_SPLIT16>,
+                        (const void*)strip_kernel<PREC_F64, true>, (const void*)strip_kernel<PREC_F64, false>,
+                        (const void*)strip_kernel<PREC_F32, true>, (const void*)strip_kernel<PREC_F32, false>,
+                        (const void*)strip_kernel<PREC_SPLIT16, true>, (const void*)strip_kernel<PREC_SPLIT16, false>};
+    for (const void* k : ks) {
+      hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+      if (r != hipSuccess) e = r;
+    }
+    (void)hipGetLastError();  // the status is returned, not left pending for the next launch
+    return e;
+  }();
+  return rc;
 }
 
 hipError_t launch_resid(const SubDev* subs, const InstDev* insts, int ninst, const double* partials,

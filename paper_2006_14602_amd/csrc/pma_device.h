@@ -28,6 +28,19 @@ struct MonitorDev {
   double bamp[4], bw[4], bc[4][3];
 };
 
+// DCT-I basis of one axis of a subdomain, in the precision of the solve.  Matrices have
+// round_up(n, 16) rows and ld = round_up(n, 32) columns, zero padded, row-major; both are
+// symmetric, so row j also serves as column j.
+struct AxisDev {
+  const void* fwd;     // forward transform (split form: fp16 hi part of 2^s * A)
+  const void* fwdl;    // split form: fp16 lo part of 2^s * A (else null)
+  const void* inv;     // inverse transform (split form: fp16 hi part)
+  const void* invl;    // split form: fp16 lo part
+  const void* sig;     // 4 sin^2(pi k / (2 N)), k = 0..n-1, working precision
+  int ld;              // padded row length (multiple of 32)
+  float fwd_unscale;   // 2^-s (split form), else 1
+};
+
 struct SubDev {
   int dim;
   int n[3];            // nodes per axis (n[2] = 1 in 2D)
@@ -42,7 +55,7 @@ struct SubDev {
   double a[3];         // global box lower corner
   double h[3];         // grid spacing
   double gh2[3];       // gamma / h_k^2
-  const void* sig[3];  // per-axis 4 sin^2(pi k / (2 N)) in the working precision
+  AxisDev ax[3];
 };
 
 struct InstDev {
@@ -52,23 +65,6 @@ struct InstDev {
   int first_sub, nsub;
   int pin;               // subtract the mean DC coefficient each step (gamma > 0)
   int pad_;
-};
-
-enum Epi { EPI_NONE = 0, EPI_SCALE = 1, EPI_UPDATE = 2 };
-
-// One batched mode product C[b] = P[b] * Q[b] (row-major, all operands "NN").
-struct GemmJob {
-  int M, N, K, batch;
-  int ldp, ldq, ldc;
-  int epi;
-  long long sP, sQ, sC;  // batch strides in elements
-  const void* P;
-  const void* Q;
-  void* C;
-  int sub;
-  int tiles_n;           // tiles along N (for the tile decode)
-  float unscale;         // 2^-s undoing the pre-scaled basis of the split form (else 1)
-  int tile0;             // index of this job's first tile in its launch's tile range
 };
 
 struct StepArgs {

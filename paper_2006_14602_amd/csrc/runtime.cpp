@@ -29,8 +29,12 @@ hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int co
 hipError_t launch_stencil(int prec, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
 hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
                         hipStream_t s);
-hipError_t launch_gemm(int prec, const GemmJob* jobs, const int4* tiles, int ntiles, int part_base,
-                       const StepArgs& sa, hipStream_t s);
+hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
+                           hipStream_t s);
+hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
+                        int src_sel, const StepArgs& sa, hipStream_t s);
+hipError_t enable_large_lds();
 hipError_t launch_resid(const SubDev* subs, const InstDev* insts, int ninst, const double* partials,
                         double* out, hipStream_t s);
 hipError_t launch_phi_from_psi(int prec, const SubDev& S, const double* psi, int global_layout, int g1,
@@ -160,10 +164,11 @@ class Arena {
 // ------------------------------------------------------------------------------------------
 
 struct Basis {
-  int n = 0;
+  int n = 0, rows = 0, ld = 0;  // rows = round_up(n, 16), ld = round_up(n, 32); zero padded
   double *A64 = nullptr, *B64 = nullptr, *sig64 = nullptr;
-  float *A32 = nullptr, *B32 = nullptr, *A32s = nullptr, *sig32 = nullptr;
-  int scale_exp = 0;  // A32s = A * 2^scale_exp
+  float *A32 = nullptr, *B32 = nullptr, *sig32 = nullptr;
+  _Float16 *Ahi = nullptr, *Alo = nullptr, *Bhi = nullptr, *Blo = nullptr;  // 2^s A and B split
+  int scale_exp = 0;
   size_t bytes = 0;
 };
 
@@ -340,6 +345,10 @@ static double theta_host(const pma_grid& g, const pma_monitor& m) {
 // node (the last node belongs to the last part)
 // ------------------------------------------------------------------------------------------
 
+// largest subdomain extent per axis: the axis-0 strip kernel keeps up to 9 row blocks of 16
+// per wave (4 waves) in registers
+static constexpr int kMaxAxisNodes = 545;
+
 struct AxisSplit {
   std::vector<int> cores;            // M + 1
   std::vector<std::pair<int, int>> ranges;
@@ -421,6 +430,8 @@ static void partition_host(const pma_grid& g, const pma_dd* dd, std::vector<SubH
           s.lo[k] = r.first;
           s.n[k] = r.second - r.first + 1;
           if (r.second - r.first < 4) thr(PMA_E_INVAL, "a subdomain has fewer than 4 cells on an axis");
+          if (r.second - r.first + 1 > kMaxAxisNodes)
+            thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: use more parts");
           if (r.first > 0) s.art |= 1 << (2 * k);
           if (r.second < g.n[k] - 1) s.art |= 1 << (2 * k + 1);
         }
@@ -613,29 +624,47 @@ static void* arena_alloc(pma_ctx* c, size_t b) {
   return p;
 }
 
+
+static int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
 static size_t basis_bytes(int n) {
-  return 2 * Arena::round((size_t)n * n * 8) + Arena::round((size_t)n * 8) +
-         3 * Arena::round((size_t)n * n * 4) + Arena::round((size_t)n * 4);
+  const size_t rl = (size_t)round_up(n, 16) * round_up(n, 32);
+  return 2 * Arena::round(rl * 8) + 2 * Arena::round(rl * 4) + 4 * Arena::round(rl * 2) +
+         Arena::round((size_t)n * 8) + Arena::round((size_t)n * 4);
 }
 
 static Basis* get_basis(pma_ctx* c, int n) {
   auto it = c->bases.find(n);
   if (it != c->bases.end()) return it->second;
+  if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: split it further");
   std::vector<double> A, B, sig;
   basis_host(n, A, B, sig);
   Basis* b = new Basis;
   b->n = n;
-  const size_t nn = (size_t)n * n;
-  std::vector<float> A32(nn), B32(nn), A32s(nn), sig32(n);
+  b->rows = round_up(n, 16);
+  b->ld = round_up(n, 32);
+  const size_t rl = (size_t)b->rows * b->ld;
+  std::vector<double> A64(rl, 0.0), B64(rl, 0.0);
+  std::vector<float> A32(rl, 0.f), B32(rl, 0.f), sig32(n);
+  std::vector<_Float16> Ahi(rl, (_Float16)0.f), Alo(rl, (_Float16)0.f), Bhi(rl, (_Float16)0.f),
+      Blo(rl, (_Float16)0.f);
   double amax = 0;
-  for (size_t i = 0; i < nn; ++i) amax = std::max(amax, std::fabs(A[i]));
-  b->scale_exp = -(int)std::floor(std::log2(amax));  // scaled max in [1, 2)
+  for (size_t i = 0; i < (size_t)n * n; ++i) amax = std::max(amax, std::fabs(A[i]));
+  b->scale_exp = -(int)std::floor(std::log2(amax));  // scaled maximum in [1, 2)
   const double sc = std::ldexp(1.0, b->scale_exp);
-  for (size_t i = 0; i < nn; ++i) {
-    A32[i] = (float)A[i];
-    B32[i] = (float)B[i];
-    A32s[i] = (float)(A[i] * sc);
-  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t src = (size_t)i * n + j, dst = (size_t)i * b->ld + j;
+      A64[dst] = A[src];
+      B64[dst] = B[src];
+      A32[dst] = (float)A[src];
+      B32[dst] = (float)B[src];
+      const double as = A[src] * sc;
+      Ahi[dst] = (_Float16)as;
+      Alo[dst] = (_Float16)(as - (double)Ahi[dst]);
+      Bhi[dst] = (_Float16)B[src];
+      Blo[dst] = (_Float16)(B[src] - (double)Bhi[dst]);
+    }
   for (int i = 0; i < n; ++i) sig32[i] = (float)sig[i];
   b->bytes = basis_bytes(n);
   char* p = (char*)arena_alloc(c, b->bytes);
@@ -644,20 +673,26 @@ static Basis* get_basis(pma_ctx* c, int n) {
     p += Arena::round(sz);
     return q;
   };
-  b->A64 = (double*)take(nn * 8);
-  b->B64 = (double*)take(nn * 8);
+  b->A64 = (double*)take(rl * 8);
+  b->B64 = (double*)take(rl * 8);
+  b->A32 = (float*)take(rl * 4);
+  b->B32 = (float*)take(rl * 4);
+  b->Ahi = (_Float16*)take(rl * 2);
+  b->Alo = (_Float16*)take(rl * 2);
+  b->Bhi = (_Float16*)take(rl * 2);
+  b->Blo = (_Float16*)take(rl * 2);
   b->sig64 = (double*)take((size_t)n * 8);
-  b->A32 = (float*)take(nn * 4);
-  b->B32 = (float*)take(nn * 4);
-  b->A32s = (float*)take(nn * 4);
   b->sig32 = (float*)take((size_t)n * 4);
-  HIPCHK(hipMemcpy(b->A64, A.data(), nn * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->B64, B.data(), nn * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->sig64, sig.data(), n * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->A32, A32.data(), nn * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->B32, B32.data(), nn * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->A32s, A32s.data(), nn * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->sig32, sig32.data(), n * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->A64, A64.data(), rl * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->B64, B64.data(), rl * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->A32, A32.data(), rl * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->B32, B32.data(), rl * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->Ahi, Ahi.data(), rl * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->Alo, Alo.data(), rl * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->Bhi, Bhi.data(), rl * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->Blo, Blo.data(), rl * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->sig64, sig.data(), (size_t)n * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(b->sig32, sig32.data(), (size_t)n * 4, hipMemcpyHostToDevice));
   c->bases[n] = b;
   return b;
 }
@@ -715,40 +750,51 @@ static void free_instance(pma_ctx* c, Instance& I) {
 // batch: every subdomain of a set of instances (one precision) advanced by shared launches
 // ------------------------------------------------------------------------------------------
 
-static constexpr int kTileM = 64, kTileN = 64, kStRows = 4, kStCols = 64;
-static constexpr int kMaxPass = 6;
+static constexpr int kStRows = 4, kStCols = 64;  // stand-alone stencil / Euler tiles
+static constexpr int kRows = 16, kCols = 64, kStrip = 16;  // mode-product tiles
+static constexpr int kPhases = 8;
 
 struct SubRange {
   int first, count;
 };
 
+// Tile table of one launch: entries plus, per subdomain, its contiguous range (plain form).
+struct Table {
+  std::vector<int4> h;
+  std::vector<SubRange> rng;
+  int4* d = nullptr;
+  int maxld = 32;
+  void begin_sub() { rng.push_back(SubRange{(int)h.size(), 0}); }
+  void end_sub() { rng.back().count = (int)h.size() - rng.back().first; }
+  int size() const { return (int)h.size(); }
+};
+
+// Phases of a step, in launch order:
+//   0 transmission                1 stencil (F)                       2 forward-Euler update
+//   3 forward product along the last axis
+//   4 forward product along the middle axis (3D)
+//   5 forward product + spectral scale + inverse product along axis 0
+//   6 inverse product along the middle axis (3D)
+//   7 inverse product along the last axis + update + residual partials
 struct Batch {
   pma_ctx* ctx = nullptr;
   int prec = 0;
   std::vector<Instance*> insts;
-  // host tables
   std::vector<SubDev> h_subs;
   std::vector<InstDev> h_insts;
-  std::vector<int4> h_st_tiles, h_eu_tiles, h_trans;
-  std::vector<GemmJob> h_jobs;
-  std::vector<int4> h_pass_tiles[kMaxPass];
-  std::vector<SubRange> st_rng, eu_rng, tr_rng, pass_rng[kMaxPass];
-  int npass = 0;
-  int part_base_pass[kMaxPass] = {0}, part_base_eu = 0, npartials = 0;
-  // device tables (one arena block)
+  std::vector<int4> h_trans;
+  std::vector<SubRange> tr_rng;
+  Table tab[kPhases];  // tab[0] unused (transmission has its own list)
+  int part_base_eu = 0, part_base_inv = 0, npartials = 0;
   char* dmem = nullptr;
   SubDev* d_subs = nullptr;
   InstDev* d_insts = nullptr;
-  int4 *d_st = nullptr, *d_eu = nullptr, *d_tr = nullptr;
-  GemmJob* d_jobs = nullptr;
-  int4* d_pass[kMaxPass] = {nullptr};
+  int4* d_tr = nullptr;
   void* d_dc = nullptr;
   double *d_partials = nullptr, *d_shift = nullptr, *d_resid = nullptr;
   int* d_status = nullptr;
-  // pinned host mirrors of the per-instance status / residual
   double* h_resid = nullptr;
   int* h_status = nullptr;
-  // graph of one step
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   StepArgs sa{};
@@ -768,42 +814,37 @@ struct Batch {
     h_status = nullptr;
   }
 
-  const void* basis_ptr(const Basis* b, bool forward, bool split) const {
-    if (prec == PMA_FP64) return forward ? (const void*)b->A64 : (const void*)b->B64;
-    if (split && forward) return b->A32s;
-    return forward ? (const void*)b->A32 : (const void*)b->B32;
+  AxisDev axis_dev(const Basis* b) const {
+    AxisDev a{};
+    a.ld = b->ld;
+    a.fwd_unscale = 1.0f;
+    if (prec == PMA_FP64) {
+      a.fwd = b->A64;
+      a.inv = b->B64;
+      a.sig = b->sig64;
+    } else if (prec == PMA_FP32) {
+      a.fwd = b->A32;
+      a.inv = b->B32;
+      a.sig = b->sig32;
+    } else {
+      a.fwd = b->Ahi;
+      a.fwdl = b->Alo;
+      a.inv = b->Bhi;
+      a.invl = b->Blo;
+      a.sig = b->sig32;
+      a.fwd_unscale = (float)std::ldexp(1.0, -b->scale_exp);
+    }
+    return a;
   }
 
-  void add_job(int pass, GemmJob j) {
-    const int tm = (j.M + kTileM - 1) / kTileM, tn = (j.N + kTileN - 1) / kTileN;
-    j.tiles_n = tn;
-    const int job_id = (int)h_jobs.size();
-    j.tile0 = (int)h_pass_tiles[pass].size();
-    h_jobs.push_back(j);
-    for (int b = 0; b < j.batch; ++b)
-      for (int a = 0; a < tm; ++a)
-        for (int c = 0; c < tn; ++c) h_pass_tiles[pass].push_back(int4{job_id, a * kTileM, c * kTileN, b});
-  }
-
-  // build host and device tables for the current instance set
   void build() {
+    HIPCHK(enable_large_lds());
     clear_device();
     h_subs.clear();
     h_insts.clear();
-    h_st_tiles.clear();
-    h_eu_tiles.clear();
     h_trans.clear();
-    h_jobs.clear();
-    st_rng.clear();
-    eu_rng.clear();
     tr_rng.clear();
-    npass = 0;
-    for (int p = 0; p < kMaxPass; ++p) {
-      h_pass_tiles[p].clear();
-      pass_rng[p].clear();
-    }
-    const bool split = prec == PMA_FP32_SPLIT16;
-    // pass 1: descriptors
+    for (auto& t : tab) t = Table();
     for (size_t q = 0; q < insts.size(); ++q) {
       Instance& I = *insts[q];
       InstDev id{};
@@ -829,7 +870,10 @@ struct Batch {
       id.dt = I.tm.dt;
       id.first_sub = (int)h_subs.size();
       id.nsub = (int)I.subs.size();
-      id.pin = I.tm.gamma > 0 ? 1 : 0;
+      // removing a constant from phi is invisible to every derivative only if every artificial
+      // node is refilled from the same instance (transmission); held Dirichlet data of a lone
+      // subdomain would be left behind by the shift
+      id.pin = (I.tm.gamma > 0 && !I.single_sub_mode) ? 1 : 0;
       h_insts.push_back(id);
       for (size_t s = 0; s < I.subs.size(); ++s) {
         const SubHost& S = I.subs[s];
@@ -842,13 +886,11 @@ struct Batch {
             sd.a[k] = I.grid.lo[k];
             sd.h[k] = (I.grid.hi[k] - I.grid.lo[k]) / (I.grid.n[k] - 1);
             sd.gh2[k] = I.tm.gamma / (sd.h[k] * sd.h[k]);
-            const Basis* b = get_basis(ctx, S.n[k]);
-            sd.sig[k] = prec == PMA_FP64 ? (const void*)b->sig64 : (const void*)b->sig32;
+            if (I.tm.gamma > 0) sd.ax[k] = axis_dev(get_basis(ctx, S.n[k]));
           } else {
             sd.a[k] = 0;
             sd.h[k] = 1;
             sd.gh2[k] = 0;
-            sd.sig[k] = nullptr;
           }
         }
         sd.art = S.art;
@@ -859,113 +901,74 @@ struct Batch {
         h_subs.push_back(sd);
       }
     }
-    // pass 2: tiles and jobs, subdomain by subdomain (each sub's tiles contiguous per table)
-    int npass_needed = 0;
+    // tiles, subdomain by subdomain
     for (size_t q = 0; q < insts.size(); ++q) {
       Instance& I = *insts[q];
       const int first = h_insts[q].first_sub;
       for (size_t s = 0; s < I.subs.size(); ++s) {
         const int gs = first + (int)s;
-        SubDev& sd = h_subs[gs];
+        const SubDev& sd = h_subs[gs];
         const int n0 = sd.n[0], n1 = sd.n[1], n2 = sd.n[2];
         const int R = I.dim == 2 ? n0 : n0 * n1, C = I.dim == 2 ? n1 : n2;
-        SubRange sr{(int)h_st_tiles.size(), 0};
-        for (int r = 0; r < R; r += kStRows)
-          for (int c = 0; c < C; c += kStCols) h_st_tiles.push_back(int4{gs, r, c, 0});
-        sr.count = (int)h_st_tiles.size() - sr.first;
-        st_rng.push_back(sr);
-        // transmission entries with batch-global sub indices
         SubRange tr{(int)h_trans.size(), 0};
         for (int e = I.trans_first[s]; e < I.trans_first[s + 1]; ++e) {
-          int4 t = I.trans[e];
+          const int4 t = I.trans[e];
           h_trans.push_back(int4{first + t.x, t.y, first + t.z, t.w});
         }
         tr.count = (int)h_trans.size() - tr.first;
         tr_rng.push_back(tr);
+        for (int ph = 1; ph < kPhases; ++ph) tab[ph].begin_sub();
+        for (int r = 0; r < R; r += kStRows)
+          for (int c = 0; c < C; c += kStCols) tab[1].h.push_back(int4{gs, r, c, 0});
         if (I.tm.gamma == 0.0) {
-          SubRange er{(int)h_eu_tiles.size(), 0};
           for (int r = 0; r < R; r += kStRows)
-            for (int c = 0; c < C; c += kStCols) h_eu_tiles.push_back(int4{gs, r, c, 0});
-          er.count = (int)h_eu_tiles.size() - er.first;
-          eu_rng.push_back(er);
-          for (int p = 0; p < kMaxPass; ++p) pass_rng[p].push_back(SubRange{(int)h_pass_tiles[p].size(), 0});
-          continue;
-        }
-        eu_rng.push_back(SubRange{(int)h_eu_tiles.size(), 0});
-        const Basis* b0 = get_basis(ctx, n0);
-        const Basis* b1 = get_basis(ctx, n1);
-        const Basis* b2 = I.dim == 3 ? get_basis(ctx, n2) : nullptr;
-        auto us = [&](const Basis* b, bool fwd) {
-          return (split && fwd) ? (float)std::ldexp(1.0, -b->scale_exp) : 1.0f;
-        };
-        std::vector<GemmJob> js;
-        auto J = [&](int M, int N, int K, int batch, const void* P, int ldp, long long sP, const void* Q,
-                     int ldq, long long sQ, void* Cc, int ldc, long long sC, int epi, float unscale) {
-          GemmJob j{};
-          j.M = M; j.N = N; j.K = K; j.batch = batch;
-          j.P = P; j.ldp = ldp; j.sP = sP;
-          j.Q = Q; j.ldq = ldq; j.sQ = sQ;
-          j.C = Cc; j.ldc = ldc; j.sC = sC;
-          j.epi = epi; j.unscale = unscale; j.sub = gs;
-          js.push_back(j);
-        };
-        void *Fp = sd.F, *Tp = sd.T, *Pp = sd.phi;
-        if (I.dim == 2) {
-          J(n0, n1, n1, 1, Fp, n1, 0, basis_ptr(b1, true, split), n1, 0, Tp, n1, 0, EPI_NONE, us(b1, true));
-          J(n0, n1, n0, 1, basis_ptr(b0, true, split), n0, 0, Tp, n1, 0, Fp, n1, 0, EPI_SCALE, us(b0, true));
-          J(n0, n1, n0, 1, basis_ptr(b0, false, split), n0, 0, Fp, n1, 0, Tp, n1, 0, EPI_NONE, 1.0f);
-          J(n0, n1, n1, 1, Tp, n1, 0, basis_ptr(b1, false, split), n1, 0, Pp, n1, 0, EPI_UPDATE, 1.0f);
+            for (int c = 0; c < C; c += kStCols) tab[2].h.push_back(int4{gs, r, c, 0});
         } else {
-          const long long pl = (long long)n1 * n2;
-          J(n0 * n1, n2, n2, 1, Fp, n2, 0, basis_ptr(b2, true, split), n2, 0, Tp, n2, 0, EPI_NONE, us(b2, true));
-          J(n1, n2, n1, n0, basis_ptr(b1, true, split), n1, 0, Tp, n2, pl, Fp, n2, pl, EPI_NONE, us(b1, true));
-          J(n0, n1 * n2, n0, 1, basis_ptr(b0, true, split), n0, 0, Fp, n1 * n2, 0, Tp, n1 * n2, 0, EPI_SCALE, us(b0, true));
-          J(n0, n1 * n2, n0, 1, basis_ptr(b0, false, split), n0, 0, Tp, n1 * n2, 0, Fp, n1 * n2, 0, EPI_NONE, 1.0f);
-          J(n1, n2, n1, n0, basis_ptr(b1, false, split), n1, 0, Fp, n2, pl, Tp, n2, pl, EPI_NONE, 1.0f);
-          J(n0 * n1, n2, n2, 1, Tp, n2, 0, basis_ptr(b2, false, split), n2, 0, Pp, n2, 0, EPI_UPDATE, 1.0f);
+          const int la = I.dim - 1;
+          for (int r = 0; r < R; r += kRows)
+            for (int c = 0; c < C; c += kCols) tab[3].h.push_back(int4{gs, r, c, 0});
+          tab[3].maxld = std::max(tab[3].maxld, sd.ax[la].ld);
+          if (I.dim == 3) {
+            for (int i0 = 0; i0 < n0; ++i0)
+              for (int c = 0; c < n2; c += kStrip) {
+                tab[4].h.push_back(int4{gs, i0, c, 0});
+                tab[6].h.push_back(int4{gs, i0, c, 0});
+              }
+            tab[4].maxld = std::max(tab[4].maxld, sd.ax[1].ld);
+            tab[6].maxld = std::max(tab[6].maxld, sd.ax[1].ld);
+          }
+          const int rest = I.dim == 2 ? n1 : n1 * n2;
+          for (int c = 0; c < rest; c += kStrip) tab[5].h.push_back(int4{gs, 0, c, 0});
+          tab[5].maxld = std::max(tab[5].maxld, sd.ax[0].ld);
+          for (int r = 0; r < R; r += kRows)
+            for (int c = 0; c < C; c += kCols) tab[7].h.push_back(int4{gs, r, c, 0});
+          tab[7].maxld = std::max(tab[7].maxld, sd.ax[la].ld);
         }
-        npass_needed = std::max(npass_needed, (int)js.size());
-        for (int p = 0; p < kMaxPass; ++p) {
-          SubRange pr{(int)h_pass_tiles[p].size(), 0};
-          if (p < (int)js.size()) add_job(p, js[p]);
-          pr.count = (int)h_pass_tiles[p].size() - pr.first;
-          pass_rng[p].push_back(pr);
-        }
+        for (int ph = 1; ph < kPhases; ++ph) tab[ph].end_sub();
       }
     }
-    npass = npass_needed;
-    // residual partial regions: update passes (2D: pass 3, 3D: pass 5) and Euler tiles
-    npartials = 0;
-    for (int p = 0; p < kMaxPass; ++p) {
-      part_base_pass[p] = npartials;
-      if (p == 3 || p == 5) npartials += (int)h_pass_tiles[p].size();
-    }
-    part_base_eu = npartials;
-    npartials += (int)h_eu_tiles.size();
-    for (size_t q = 0; q < insts.size(); ++q) {
-      Instance& I = *insts[q];
-      for (size_t s = 0; s < I.subs.size(); ++s) {
-        const int gs = h_insts[q].first_sub + (int)s;
-        SubDev& sd = h_subs[gs];
-        if (I.tm.gamma == 0.0) {
-          sd.part0 = part_base_eu + eu_rng[gs].first;
-          sd.nparts = eu_rng[gs].count;
-        } else {
-          const int up = I.dim == 2 ? 3 : 5;
-          sd.part0 = part_base_pass[up] + pass_rng[up][gs].first;
-          sd.nparts = pass_rng[up][gs].count;
-        }
+    // residual partial sums: inverse-last tiles, then Euler tiles
+    part_base_inv = 0;
+    part_base_eu = tab[7].size();
+    npartials = tab[7].size() + tab[2].size();
+    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
+      SubDev& sd = h_subs[gs];
+      const Instance& I = *insts[sd.inst];
+      if (I.tm.gamma == 0.0) {
+        sd.part0 = part_base_eu + tab[2].rng[gs].first;
+        sd.nparts = tab[2].rng[gs].count;
+      } else {
+        sd.part0 = part_base_inv + tab[7].rng[gs].first;
+        sd.nparts = tab[7].rng[gs].count;
       }
     }
     // device block
     const size_t nsub = h_subs.size(), ninst = h_insts.size();
     const size_t el = prec == PMA_FP64 ? 8 : 4;
     size_t bytes = Arena::round(nsub * sizeof(SubDev)) + Arena::round(ninst * sizeof(InstDev)) +
-                   Arena::round(h_st_tiles.size() * 16 + 16) + Arena::round(h_eu_tiles.size() * 16 + 16) +
-                   Arena::round(h_trans.size() * 16 + 16) + Arena::round(h_jobs.size() * sizeof(GemmJob) + 16) +
-                   Arena::round(nsub * el) + Arena::round((size_t)(npartials + 1) * 8) +
-                   Arena::round(ninst * 8) * 2 + Arena::round(ninst * 4);
-    for (int p = 0; p < kMaxPass; ++p) bytes += Arena::round(h_pass_tiles[p].size() * 16 + 16);
+                   Arena::round(h_trans.size() * 16 + 16) + Arena::round(nsub * el) +
+                   Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4);
+    for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round(tab[ph].h.size() * 16 + 16);
     dmem = (char*)arena_alloc(ctx, bytes);
     char* p = dmem;
     auto take = [&](size_t sz) {
@@ -979,11 +982,8 @@ struct Batch {
     };
     d_subs = (SubDev*)take(nsub * sizeof(SubDev));
     d_insts = (InstDev*)take(ninst * sizeof(InstDev));
-    d_st = (int4*)take(h_st_tiles.size() * 16 + 16);
-    d_eu = (int4*)take(h_eu_tiles.size() * 16 + 16);
     d_tr = (int4*)take(h_trans.size() * 16 + 16);
-    d_jobs = (GemmJob*)take(h_jobs.size() * sizeof(GemmJob) + 16);
-    for (int q = 0; q < kMaxPass; ++q) d_pass[q] = (int4*)take(h_pass_tiles[q].size() * 16 + 16);
+    for (int ph = 1; ph < kPhases; ++ph) tab[ph].d = (int4*)take(tab[ph].h.size() * 16 + 16);
     d_dc = take(nsub * el);
     d_partials = (double*)take((size_t)(npartials + 1) * 8);
     d_shift = (double*)take(ninst * 8);
@@ -991,11 +991,8 @@ struct Batch {
     d_status = (int*)take(ninst * 4);
     up(d_subs, h_subs.data(), nsub * sizeof(SubDev));
     up(d_insts, h_insts.data(), ninst * sizeof(InstDev));
-    up(d_st, h_st_tiles.data(), h_st_tiles.size() * 16);
-    up(d_eu, h_eu_tiles.data(), h_eu_tiles.size() * 16);
     up(d_tr, h_trans.data(), h_trans.size() * 16);
-    up(d_jobs, h_jobs.data(), h_jobs.size() * sizeof(GemmJob));
-    for (int q = 0; q < kMaxPass; ++q) up(d_pass[q], h_pass_tiles[q].data(), h_pass_tiles[q].size() * 16);
+    for (int ph = 1; ph < kPhases; ++ph) up(tab[ph].d, tab[ph].h.data(), tab[ph].h.size() * 16);
     HIPCHK(hipMemsetAsync(d_dc, 0, nsub * el, st));
     HIPCHK(hipMemsetAsync(d_partials, 0, (size_t)(npartials + 1) * 8, st));
     HIPCHK(hipMemsetAsync(d_status, 0, ninst * 4, st));
@@ -1015,13 +1012,25 @@ struct Batch {
     HIPCHK(hipStreamSynchronize(st));
   }
 
-  // one step: all subdomains per launch (batched) or one subdomain per launch (plain baseline),
-  // phase by phase
-  void launch_step(bool plain, hipStream_t st) {
-    for (int ph = 0; ph < 9; ++ph) launch_phase(ph, plain, st);
+  // launch one phase over the table range [first, first + count)
+  void launch_range(int ph, int first, int count, hipStream_t st) {
+    if (count <= 0) return;
+    const Table& t = tab[ph];
+    switch (ph) {
+      case 1: HIPCHK(launch_stencil(prec, t.d + first, count, sa, st)); break;
+      case 2: HIPCHK(launch_euler(prec, t.d + first, count, part_base_eu + first, sa, st)); break;
+      case 3: HIPCHK(launch_fwd_last(prec, t.d + first, count, t.maxld, sa, st)); break;
+      case 4: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, 1, 0, 1, sa, st)); break;
+      case 5:  // 2D: T -> F;  3D: F -> T (pair_src_ set by launch_phase)
+        HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, 0, 0, pair_src_, sa, st));
+        break;
+      case 6: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, 1, 1, 1, sa, st)); break;
+      case 7: HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, sa, st)); break;
+    }
   }
+  int pair_src_ = 1;
 
-  // one phase of a step (see pma_plan_phase_times for the numbering)
+  // one phase of a step: all subdomains in one launch, or one subdomain per launch (plain)
   void launch_phase(int ph, bool plain, hipStream_t st) {
     const int nsub = (int)h_subs.size();
     if (ph == 0) {
@@ -1029,57 +1038,71 @@ struct Batch {
       else
         for (int s = 0; s < nsub; ++s)
           if (tr_rng[s].count) HIPCHK(launch_transmit(prec, d_subs, d_tr + tr_rng[s].first, tr_rng[s].count, st));
-    } else if (ph == 1) {
-      if (!plain) HIPCHK(launch_stencil(prec, d_st, (int)h_st_tiles.size(), sa, st));
-      else
-        for (int s = 0; s < nsub; ++s) HIPCHK(launch_stencil(prec, d_st + st_rng[s].first, st_rng[s].count, sa, st));
-    } else if (ph == 2) {
-      if (!plain) HIPCHK(launch_euler(prec, d_eu, (int)h_eu_tiles.size(), part_base_eu, sa, st));
-      else
-        for (int s = 0; s < nsub; ++s)
-          if (eu_rng[s].count)
-            HIPCHK(launch_euler(prec, d_eu + eu_rng[s].first, eu_rng[s].count, part_base_eu + eu_rng[s].first, sa, st));
-    } else {
-      const int p = ph - 3;
-      if (p >= npass) return;
-      if (!plain) HIPCHK(launch_gemm(prec, d_jobs, d_pass[p], (int)h_pass_tiles[p].size(), part_base_pass[p], sa, st));
-      else
-        for (int s = 0; s < nsub; ++s)
-          if (pass_rng[p][s].count)
-            HIPCHK(launch_gemm(prec, d_jobs, d_pass[p] + pass_rng[p][s].first, pass_rng[p][s].count,
-                               part_base_pass[p] + pass_rng[p][s].first, sa, st));
+      return;
     }
+    if (ph == 5) {
+      // the axis-0 pair reads T in 2D and F in 3D: launch the two groups separately
+      for (int dim = 2; dim <= 3; ++dim) {
+        pair_src_ = dim == 2 ? 1 : 0;
+        if (!plain) {
+          // contiguous runs of subdomains of this dimension
+          int s = 0;
+          while (s < nsub) {
+            if (h_subs[s].dim != dim) {
+              ++s;
+              continue;
+            }
+            int e = s;
+            while (e < nsub && h_subs[e].dim == dim) ++e;
+            const int f = tab[5].rng[s].first, l = tab[5].rng[e - 1].first + tab[5].rng[e - 1].count;
+            launch_range(5, f, l - f, st);
+            s = e;
+          }
+        } else {
+          for (int s = 0; s < nsub; ++s)
+            if (h_subs[s].dim == dim) launch_range(5, tab[5].rng[s].first, tab[5].rng[s].count, st);
+        }
+      }
+      return;
+    }
+    if (!plain) launch_range(ph, 0, tab[ph].size(), st);
+    else
+      for (int s = 0; s < nsub; ++s) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
   }
 
-  // algorithmic work per step of each phase: flops of the mode products (2 M N K per batch
-  // entry) and compulsory bytes (each operand and result touched once; the update reads and
-  // writes phi)
+  void launch_step(bool plain, hipStream_t st) {
+    for (int ph = 0; ph < kPhases; ++ph) launch_phase(ph, plain, st);
+  }
+
+  // algorithmic work per step of each phase: 2 M N K flops per product; compulsory bytes with
+  // each operand and result touched once (the DCT matrices are n x n and stay in cache)
   void phase_work(double* flops, double* bytes) const {
     const double el = prec == PMA_FP64 ? 8.0 : 4.0;
-    for (int ph = 0; ph < 9; ++ph) flops[ph] = bytes[ph] = 0.0;
-    bytes[0] = (double)h_trans.size() * (2 * el + 16);
-    for (const auto& s : h_subs) {
-      const double nodes = (double)s.n[0] * s.n[1] * s.n[2];
+    for (int ph = 0; ph < kPhases; ++ph) flops[ph] = bytes[ph] = 0.0;
+    bytes[0] = (double)h_trans.size() * 2 * el;
+    for (size_t q = 0; q < h_subs.size(); ++q) {
+      const SubDev& s = h_subs[q];
+      const double n0 = s.n[0], n1 = s.n[1], n2 = s.n[2];
+      const double nodes = n0 * n1 * n2;
       bytes[1] += 2 * el * nodes;
-    }
-    for (const auto& t : h_eu_tiles) (void)t;
-    for (size_t q = 0; q < h_subs.size(); ++q)
-      if (eu_rng[q].count) bytes[2] += 3 * el * (double)h_subs[q].n[0] * h_subs[q].n[1] * h_subs[q].n[2];
-    for (int p = 0; p < npass; ++p) {
-      for (const auto& j : h_jobs) (void)j;
-    }
-    for (size_t q = 0; q < h_subs.size(); ++q)
-      for (int p = 0; p < npass; ++p) {
-        if (!pass_rng[p][q].count) continue;
-        const int t = pass_rng[p][q].first;
-        const GemmJob& j = h_jobs[h_pass_tiles[p][t].x];
-        flops[3 + p] += 2.0 * j.M * j.N * j.K * j.batch;
-        const bool basis_left = j.sP == 0 && j.batch > 1 ? true : (j.ldp == j.K && j.M == j.K && j.sP == 0);
-        (void)basis_left;
-        // data operand + result (+ phi read for the update); the basis is n x n and cached
-        double data = (double)j.M * j.N * j.batch;
-        bytes[3 + p] += el * (2 * data + (j.epi == EPI_UPDATE ? data : 0.0));
+      if (tab[2].rng[q].count) {
+        bytes[2] += 3 * el * nodes;
+        continue;
       }
+      const double nl = s.dim == 2 ? n1 : n2;
+      flops[3] += 2.0 * nodes * nl;
+      bytes[3] += 2 * el * nodes;
+      if (s.dim == 3) {
+        flops[4] += 2.0 * nodes * n1;
+        flops[6] += 2.0 * nodes * n1;
+        bytes[4] += 2 * el * nodes;
+        bytes[6] += 2 * el * nodes;
+      }
+      flops[5] += 4.0 * nodes * n0;
+      bytes[5] += 2 * el * nodes;
+      flops[7] += 2.0 * nodes * nl;
+      bytes[7] += 3 * el * nodes;
+    }
   }
 
   void capture() {
@@ -1088,7 +1111,7 @@ struct Batch {
     try {
       launch_step(false, st);
     } catch (...) {
-      hipGraph_t g;
+      hipGraph_t g = nullptr;
       hipStreamEndCapture(st, &g);
       if (g) hipGraphDestroy(g);
       throw;
@@ -1692,7 +1715,8 @@ int pma_solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], con
   I.prec = tm->precision;
   SubHost S;
   for (int k = 0; k < I.dim; ++k) {
-    if (lo[k] < 0 || hi[k] > global->n[k] - 1 || hi[k] - lo[k] < 4) return fail(PMA_E_INVAL, "bad subdomain range");
+    if (lo[k] < 0 || hi[k] > global->n[k] - 1 || hi[k] - lo[k] < 4 || hi[k] - lo[k] + 1 > kMaxAxisNodes)
+      return fail(PMA_E_INVAL, "bad subdomain range");
     S.lo[k] = lo[k];
     S.n[k] = hi[k] - lo[k] + 1;
     for (int e = 0; e < 2; ++e) {
@@ -1824,22 +1848,22 @@ int pma_plan_sync(pma_plan* P) {
 
 int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, double* bytes, int cap, int* nph) {
   API_BEGIN
-  if (!P || nsteps <= 0 || !ms || cap < 9 || !nph) return fail(PMA_E_INVAL, "bad arguments");
+  if (!P || nsteps <= 0 || !ms || cap < kPhases || !nph) return fail(PMA_E_INVAL, "bad arguments");
   std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
-  *nph = 9;
+  *nph = kPhases;
   Batch& B = *P->batch;
   hipStream_t st = P->ctx->stream;
-  std::vector<hipEvent_t> ev(10);
+  std::vector<hipEvent_t> ev(kPhases + 1);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  std::vector<double> acc(9, 0.0);
+  std::vector<double> acc(kPhases, 0.0);
   for (int k = 0; k < nsteps; ++k) {
     HIPCHK(hipEventRecord(ev[0], st));
-    for (int ph = 0; ph < 9; ++ph) {
+    for (int ph = 0; ph < kPhases; ++ph) {
       B.launch_phase(ph, P->plain, st);
       HIPCHK(hipEventRecord(ev[ph + 1], st));
     }
-    HIPCHK(hipEventSynchronize(ev[9]));
-    for (int ph = 0; ph < 9; ++ph) {
+    HIPCHK(hipEventSynchronize(ev[kPhases]));
+    for (int ph = 0; ph < kPhases; ++ph) {
       float t = 0;
       HIPCHK(hipEventElapsedTime(&t, ev[ph], ev[ph + 1]));
       acc[ph] += t;
@@ -1847,10 +1871,10 @@ int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, dou
   }
   for (auto& e : ev) hipEventDestroy(e);
   for (auto& I : P->insts) I->steps_done += nsteps;
-  for (int ph = 0; ph < 9; ++ph) ms[ph] = acc[ph] / nsteps;
-  std::vector<double> fl(9, 0.0), by(9, 0.0);
+  for (int ph = 0; ph < kPhases; ++ph) ms[ph] = acc[ph] / nsteps;
+  std::vector<double> fl(kPhases, 0.0), by(kPhases, 0.0);
   B.phase_work(fl.data(), by.data());
-  for (int ph = 0; ph < 9; ++ph) {
+  for (int ph = 0; ph < kPhases; ++ph) {
     if (flops) flops[ph] = fl[ph];
     if (bytes) bytes[ph] = by[ph];
   }

@@ -1,0 +1,51 @@
+"""Write the full-size expected meshes used by the GPU parity tests.
+
+Calls only the FP64 oracle on the seeded workloads and stores, per workload, a strided
+subsample of the glued mesh plus a seeded random sample of nodes (numpy .npz, no pickles):
+  sine_dd_513.npz   513 x 513, 4 x 4 subdomains, overlap 8 cells, 500 steps
+  shell_dd_129.npz  129^3, 2 x 2 x 2 subdomains, overlap 6 cells, 200 steps
+Run from the repository root:  python tests/golden/make_golden.py [name ...]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+from paper_2006_14602_amd import workloads as W  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CASES = {"sine_dd_513": (W.sine_dd, 8), "shell_dd_129": (W.shell_dd, 8)}
+
+
+def sample_index(n, stride, count, seed):
+    d = len(n)
+    strided = np.stack(np.meshgrid(*[np.arange(0, k, stride) for k in n], indexing="ij"), -1).reshape(-1, d)
+    rng = np.random.default_rng(seed)
+    rand = np.stack([rng.integers(0, k, count) for k in n], -1)
+    return np.concatenate([strided, rand], 0)
+
+
+def make(name):
+    fn, stride = CASES[name]
+    w = fn()
+    g = w["grid"]
+    gs = O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"]))
+    t = w["time"]
+    t0 = time.time()
+    r = O.solve_dd(gs, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], t["steps"])
+    idx = sample_index(g["n"], stride, 4000, 20060146)
+    vals = np.stack([r.mesh[k][tuple(idx.T)] for k in range(gs.d)], -1)
+    np.savez_compressed(os.path.join(HERE, name + ".npz"), idx=idx.astype(np.int32), mesh=vals,
+                        min_det=np.float64(r.min_det), min_cell=np.float64(r.min_cell),
+                        steps=np.int32(t["steps"]), seconds=np.float64(time.time() - t0))
+    print(f"{name}: {time.time() - t0:.1f} s, min det {r.min_det:.6f}, {len(idx)} samples")
+
+
+if __name__ == "__main__":
+    for n in (sys.argv[1:] or list(CASES)):
+        make(n)

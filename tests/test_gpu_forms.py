@@ -1,0 +1,303 @@
+"""GPU tests of the execution forms and of the method's invariants through the C ABI.
+
+Exact (bitwise) checks where the arithmetic is the same by construction:
+  - forward Euler (gamma = 0) on overlapping subdomains reproduces the single-domain iterate
+    (stencil locality + time-n transmission), node for node
+  - the plain form (one subdomain per launch) equals the batched graph-replayed form
+  - a request inside a batch or a served mix equals the same request alone
+  - stepping a resident plan in pieces equals one solve of the same total steps
+Oracle checks (tolerance per precision) for everything else.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_14602_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "split16": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    from paper_2006_14602_amd import binding
+    c = binding.Context(0, budget_bytes=2 << 30)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def B(lib):
+    from paper_2006_14602_amd import binding
+    return binding
+
+
+def gspec(w):
+    g = w["grid"]
+    return O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"]))
+
+
+def oracle_run(w):
+    t = w["time"]
+    if w.get("dd"):
+        return O.solve_dd(gspec(w), w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"],
+                          t["steps"])
+    return O.solve_single(gspec(w), w["monitor"], t["dt"], t["gamma"], t["steps"])
+
+
+def euler_pair(n=49, steps=40):
+    h = 1.0 / (n - 1)
+    sd = W.ring(steps=steps)
+    sd["grid"] = W.grid([n, n])
+    sd["time"] = {"dt": 0.05 * h * h, "gamma": 0.0, "steps": steps}
+    dd = dict(sd, dd={"parts": [3, 2], "overlap": [4, 4]})
+    return sd, dd
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_euler_dd_equals_single_domain_bitwise(ctx, prec):
+    sd, dd = euler_pair()
+    a, _, _ = ctx.dd_mesh(sd, precision=prec)
+    b, _, _ = ctx.dd_mesh(dd, precision=prec)
+    np.testing.assert_array_equal(a, b)
+    ref = oracle_run(sd)
+    assert np.max(np.abs(a - ref.mesh)) <= TOL[prec]
+
+
+def test_forward_euler_3d_dd_equals_single_domain_bitwise(ctx):
+    n, steps = 21, 10
+    h = 1.0 / (n - 1)
+    sd = W.shell_dd(n=n, steps=steps)
+    sd["dd"] = None
+    sd["time"] = {"dt": 0.05 * h * h, "gamma": 0.0, "steps": steps}
+    dd = dict(sd, dd={"parts": [2, 2, 2], "overlap": [4, 4, 4]})
+    a, _, _ = ctx.dd_mesh(sd, precision="fp64")
+    b, _, _ = ctx.dd_mesh(dd, precision="fp64")
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split16"])
+@pytest.mark.parametrize("wl", ["sine2d", "shell3d"])
+def test_plain_equals_batched_bitwise(ctx, prec, wl):
+    w = W.sine_dd(n=97, parts=(3, 2), overlap=6, steps=25) if wl == "sine2d" else \
+        W.shell_dd(n=29, parts=(2, 2, 1), overlap=4, steps=12)
+    a, _, sa = ctx.dd_mesh(w, precision=prec, exec_="batched")
+    b, _, sb = ctx.dd_mesh(w, precision=prec, exec_="plain")
+    np.testing.assert_array_equal(a, b)
+    assert sa["min_det"] == sb["min_det"]
+
+
+def bump_batch(count=6, n_lo=33, n_hi=97, steps=40):
+    return W.bumps_batch(count=count, n_lo=n_lo, n_hi=n_hi, steps=steps)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split16"])
+def test_batch_equals_alone_and_oracle(ctx, prec):
+    ws = bump_batch()
+    outs, stats = ctx.dd_mesh_batch(ws, precision=prec)
+    for w, m, st in zip(ws, outs, stats):
+        alone, _, _ = ctx.dd_mesh(w, precision=prec)
+        np.testing.assert_array_equal(m, alone)
+        assert st["min_det"] > 0 and st["min_cell"] > 0
+    for w, m in list(zip(ws, outs))[:3]:
+        ref = oracle_run(w)
+        err = np.max(np.abs(m - ref.mesh))
+        print(f"{w['name']} n={w['grid']['n'][0]} {prec}: err {err:.2e}")
+        assert err <= TOL[prec]
+
+
+def test_batch_uneven_steps(ctx):
+    ws = bump_batch(count=4)
+    for i, w in enumerate(ws):
+        w["time"]["steps"] = 10 + 7 * i
+    outs, stats = ctx.dd_mesh_batch(ws, precision="split16")
+    for w, m, st in zip(ws, outs, stats):
+        alone, _, _ = ctx.dd_mesh(w, precision="split16")
+        np.testing.assert_array_equal(m, alone)
+        assert st["steps_done"] == w["time"]["steps"]
+
+
+def test_plan_steps_in_pieces_equal_one_solve(ctx, B):
+    w = W.sine_dd(n=81, parts=(2, 2), overlap=6, steps=30)
+    whole, _, _ = ctx.dd_mesh(w, precision="split16")
+    with B.Plan(ctx, [w], "split16") as p:
+        p.step(7)
+        p.step(13)
+        p.sync()
+        p.step(10)
+        p.sync()
+        m, st = p.mesh(0)
+    np.testing.assert_array_equal(m, whole)
+
+
+def test_warm_start_and_psi_out(ctx):
+    # 30 steps, then 20 more from the oracle's Psi, against 50 oracle steps; Psi itself is
+    # returned with the constants the FP32 path removed added back
+    w = W.ring(steps=50)
+    w["grid"] = W.grid([49, 49])
+    ref = oracle_run(w)
+    w30 = dict(w, time=dict(w["time"], steps=30))
+    r30 = oracle_run(w30)
+    w20 = dict(w, time=dict(w["time"], steps=20))
+    for prec in ("fp64", "fp32"):
+        mesh, psi, _ = ctx.dd_mesh(w20, precision=prec, psi0=r30.psi, want_psi=True)
+        assert np.max(np.abs(mesh - ref.mesh)) <= TOL[prec]
+        assert np.max(np.abs(psi - ref.psi)) <= (1e-11 if prec == "fp64" else 2e-6)
+
+
+def test_psi_out_dd_matches_oracle(ctx):
+    w = W.sine_dd(n=65, parts=(2, 2), overlap=4, steps=40)
+    ref = oracle_run(w)
+    _, psi, _ = ctx.dd_mesh(w, precision="fp64", want_psi=True)
+    assert np.max(np.abs(psi - ref.psi)) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_subdomain_with_dirichlet_faces(ctx, prec):
+    import torch
+    # subdomain [10, 40] x [0, 32] of a 49 x 33 grid: artificial faces at i0 = 10 and 40,
+    # Neumann faces at i1 = 0 and 32; Dirichlet data = a perturbed Psi held fixed
+    g = W.grid([49, 33])
+    mon = W.ring_monitor()
+    steps = 25
+    t = {"dt": 1e-3, "gamma": 1.0, "steps": steps}
+    gs = O.GridSpec((49, 33), (0.0, 0.0), (1.0, 1.0))
+    box = O.Box((10, 0), (31, 33), gs.h, gs.lo, gs.hi, (True, False), (True, False))
+    X = box.coords()
+    psi0 = 0.5 * np.sum(X * X, -1) + 1e-3 * np.cos(np.pi * X[..., 1]) * np.sin(3 * np.pi * X[..., 0])
+    th = O.theta(mon, gs.lo, gs.hi)
+    p = psi0.copy()
+    for _ in range(steps):
+        p, _ = O.step_box(p, box, mon, th, gs.vol, t["dt"], t["gamma"])
+    dev = torch.tensor(psi0, dtype=torch.float64, device="cuda")
+    ctx.solve_subdomain(g, [10, 0], [40, 32], [1, 1, 0, 0], mon, t, dev, precision=prec)
+    out = dev.cpu().numpy()
+    # artificial faces keep their data exactly
+    np.testing.assert_array_equal(out[0, :], psi0[0, :])
+    np.testing.assert_array_equal(out[-1, :], psi0[-1, :])
+    assert np.max(np.abs(out - p)) <= (1e-11 if prec == "fp64" else 2e-6)
+
+
+def test_separable_monitor_matches_1d_oracle(ctx):
+    A, K, C = (8.0, 5.0), (20.0, 15.0), (0.4, 0.6)
+    w = {"name": "sep", "grid": W.grid([33, 41]), "dd": None, "monitor": W.separable_monitor(A, K, C),
+         "time": {"dt": 1e-3, "gamma": 1.0, "steps": 40}}
+    mesh, _, _ = ctx.dd_mesh(w, precision="fp64")
+    for ax in range(2):
+        g1 = O.GridSpec((w["grid"]["n"][ax],), (0.0,), (1.0,))
+        r1 = O.solve_single(g1, W.separable_monitor((A[ax],), (K[ax],), (C[ax],)), 1e-3, 1.0, 40)
+        x1 = r1.mesh[0]
+        ref = x1[:, None] if ax == 0 else x1[None, :]
+        assert np.max(np.abs(mesh[ax] - ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
+def test_boundary_nodes_exact_and_ring_symmetry(ctx, prec):
+    w = W.ring(steps=100)
+    w["grid"] = W.grid([65, 65])
+    mesh, _, st = ctx.dd_mesh(w, precision=prec)
+    x, y = mesh
+    assert np.all(x[0, :] == 0.0) and np.all(x[-1, :] == 1.0)
+    assert np.all(y[:, 0] == 0.0) and np.all(y[:, -1] == 1.0)
+    if prec == "fp64":
+        assert np.max(np.abs(x - (1.0 - x[::-1, :]))) < 1e-12
+        assert np.max(np.abs(x - y.T)) < 1e-12
+    assert st["min_det"] > 0 and st["min_cell"] > 0
+
+
+def test_tangled_mesh_reports_error(ctx, B):
+    w = W.ring(steps=100)
+    w["time"] = {"dt": 10.0 / 64 ** 2, "gamma": 0.0, "steps": 100}
+    with pytest.raises(B.PmaError) as e:
+        ctx.dd_mesh(w, precision="fp64")
+    assert e.value.code in (B.PMA_E_TANGLED, B.PMA_E_NONFINITE)
+
+
+def test_invalid_requests_rejected(ctx, B):
+    w = W.sine_dd(n=65, parts=(4, 4), overlap=1, steps=5)
+    with pytest.raises(B.PmaError) as e:
+        ctx.dd_mesh(w)
+    assert e.value.code == B.PMA_E_INVAL
+    w = W.ring(steps=5)
+    w["grid"] = W.grid([601, 65])
+    with pytest.raises(B.PmaError) as e:
+        ctx.dd_mesh(w)
+    assert e.value.code == B.PMA_E_INVAL
+
+
+def serve_all(c, ws, prec="split16", timeout=60.0):
+    tickets = [c.submit(w, prec) for w in ws]
+    res = {}
+    t0 = time.time()
+    while len(res) < len(ws):
+        for i, t in enumerate(tickets):
+            if i in res:
+                continue
+            state, mesh, st = c.poll(t, shape=(ws[i]["grid"]["dim"],) + tuple(ws[i]["grid"]["n"]))
+            if state in (2, 3):
+                res[i] = (state, mesh, st)
+        assert time.time() - t0 < timeout, "serving did not finish"
+        time.sleep(0.002)
+    return [res[i] for i in range(len(ws))]
+
+
+def small_stream(count=8):
+    ws = W.stream(count=count, seed=W.CFG5_SEED, steps=30)
+    for w in ws:   # keep sizes small for the test
+        d = w["grid"]["dim"]
+        n = 33 + (w["grid"]["n"][0] % 48) if d == 2 else 17 + (w["grid"]["n"][0] % 12)
+        w["grid"] = W.grid([n] * d)
+        if w["dd"]:
+            w["dd"] = {"parts": [2] * d, "overlap": [4] * d}
+            w["time"] = dict(W.dd_defaults(w["grid"]), steps=30)
+    return ws
+
+
+def test_served_requests_equal_alone(B):
+    ws = small_stream()
+    with B.Context(0, budget_bytes=1 << 30) as c:
+        out = serve_all(c, ws)
+        for w, (state, mesh, st) in zip(ws, out):
+            assert state == B.DONE, st
+            alone, _, _ = c.dd_mesh(w, precision="split16")
+            np.testing.assert_array_equal(mesh, alone)
+            assert st["ms_total"] >= st["ms_queue"] >= 0
+        info = c.server_info()
+        assert info["queued"] == 0 and info["running"] == 0
+
+
+def test_small_budget_queues_but_completes(B):
+    ws = small_stream(6)
+    with B.Context(0, budget_bytes=24 << 20) as c:
+        out = serve_all(c, ws)
+        assert all(s == B.DONE for s, _, _ in out)
+    with B.Context(0, budget_bytes=24 << 20) as c:
+        big = W.shell_dd(n=129, steps=2)
+        with pytest.raises(B.PmaError) as e:
+            c.submit(big)
+        assert e.value.code == B.PMA_E_BUDGET
+
+
+def test_failed_request_is_isolated(B):
+    ws = small_stream(5)
+    bad = W.ring(steps=60)
+    bad["grid"] = W.grid([49, 49])
+    bad["time"] = {"dt": 10.0 / 48 ** 2, "gamma": 0.0, "steps": 60}
+    ws.insert(2, bad)
+    with B.Context(0, budget_bytes=1 << 30) as c:
+        out = serve_all(c, ws)
+        assert out[2][0] == B.FAILED
+        assert out[2][2]["status"] in (B.PMA_E_TANGLED, B.PMA_E_NONFINITE)
+        for i, (w, (state, mesh, st)) in enumerate(zip(ws, out)):
+            if i == 2:
+                continue
+            assert state == B.DONE
+            alone, _, _ = c.dd_mesh(w, precision="split16")
+            np.testing.assert_array_equal(mesh, alone)
+        with pytest.raises(B.PmaError) as e:
+            c.poll(12345678)
+        assert e.value.code == B.PMA_E_NOTFOUND

@@ -1,0 +1,91 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times (resident
+plan, all subdomains per launch, graph replay).
+
+Expected values: tests/golden/*.npz, written by tests/golden/make_golden.py from the FP64 oracle
+alone (strided + seeded random node samples of the glued mesh).  The 256-instance batch is
+checked against live oracle runs of sampled instances.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2006_14602_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "split16": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    from paper_2006_14602_amd import binding
+    c = binding.Context(0, budget_bytes=8 << 30)
+    yield c
+    c.close()
+
+
+def golden(name):
+    return np.load(os.path.join(HERE, "golden", name + ".npz"))
+
+
+def plan_mesh(ctx, w, prec, exec_="batched"):
+    from paper_2006_14602_amd import binding
+    with binding.Plan(ctx, [w], prec, exec_) as p:
+        p.step(w["time"]["steps"])
+        p.sync()
+        return p.mesh(0)
+
+
+@pytest.mark.parametrize("prec", ["split16", "fp32", "fp64"])
+def test_sine_dd_513_full(ctx, prec):
+    w = W.sine_dd()
+    gd = golden("sine_dd_513")
+    mesh, st = plan_mesh(ctx, w, prec, "plain" if prec == "fp64" else "batched")
+    idx = gd["idx"]
+    got = np.stack([mesh[k][tuple(idx.T)] for k in range(2)], -1)
+    err = float(np.max(np.abs(got - gd["mesh"])))
+    print(f"sine_dd_513 {prec}: max err over {len(idx)} sampled nodes {err:.3e}, min det {st['min_det']:.6f}")
+    assert err <= TOL[prec]
+    assert abs(st["min_det"] - float(gd["min_det"])) <= (1e-9 if prec == "fp64" else 1e-3)
+    assert st["min_cell"] > 0
+    # faces stay put (Sec. 2, eq. nbd)
+    assert np.all(mesh[0][0, :] == 0.0) and np.all(mesh[0][-1, :] == 1.0)
+    assert np.all(mesh[1][:, 0] == 0.0) and np.all(mesh[1][:, -1] == 1.0)
+
+
+@pytest.mark.parametrize("prec", ["split16", "fp64"])
+def test_shell_dd_129_full(ctx, prec):
+    w = W.shell_dd()
+    gd = golden("shell_dd_129")
+    mesh, st = plan_mesh(ctx, w, prec)
+    idx = gd["idx"]
+    got = np.stack([mesh[k][tuple(idx.T)] for k in range(3)], -1)
+    err = float(np.max(np.abs(got - gd["mesh"])))
+    print(f"shell_dd_129 {prec}: max err {err:.3e}, min det {st['min_det']:.6f}")
+    assert err <= TOL[prec]
+    assert st["min_cell"] > 0 and st["min_det"] > 0
+    for k in range(3):
+        sl0 = [slice(None)] * 3
+        sl0[k] = 0
+        sl1 = [slice(None)] * 3
+        sl1[k] = -1
+        assert np.all(mesh[k][tuple(sl0)] == 0.0) and np.all(mesh[k][tuple(sl1)] == 1.0)
+
+
+def test_bumps_batch_256_full(ctx):
+    ws = W.bumps_batch()
+    outs, stats = ctx.dd_mesh_batch(ws, precision="split16")
+    assert all(s["min_det"] > 0 and s["min_cell"] > 0 and s["steps_done"] == 200 for s in stats)
+    rng = np.random.default_rng(5)
+    pick = sorted(set([int(np.argmin([w["grid"]["n"][0] for w in ws])), int(np.argmax([w["grid"]["n"][0] for w in ws]))]
+                      + list(rng.choice(len(ws), 2, replace=False))))
+    for i in pick:
+        w = ws[i]
+        g = w["grid"]
+        ref = O.solve_single(O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"])), w["monitor"],
+                             w["time"]["dt"], w["time"]["gamma"], w["time"]["steps"])
+        err = float(np.max(np.abs(outs[i] - ref.mesh)))
+        print(f"bump {i} n={g['n'][0]}: err {err:.3e}")
+        assert err <= TOL["split16"]
