@@ -1,21 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the DD-PMA hot path on one MI355X.
 
-Workload (one "step" = one pseudo-time step of the whole hot path over every subdomain):
+Headline workload (one "step" = one pseudo-time step of the whole hot path over every subdomain):
 513 x 513 grid on [0,1]^2, 4 x 4 overlapping subdomains (overlap 8 cells, 133/137 nodes per
 side), sine-layer monitor rho = 1 + 20 sech^2(40 (y - 1/2 - sin(2 pi x)/4)), gamma = 4 h^2,
 dt = gamma / 5.  State stays resident in HBM; exactly --steps steps are timed.
 
 value = global grid nodes x steps / wall time of the timed steps (grid-point updates/s) for the
 batched FP32 form (FP32 stencils, fp16-split matrix-core DCT products, graph-replayed shared
-launches).  The plain FP64 form (one subdomain per launch, FP64 everywhere, no graph) and the
-FP32 form with FP32 matrix-core products are timed beside it on the same workload.
+launches).  Beside it, on the same MI355X: the same workload in FP32 matrix-core products and in
+the plain FP64 form (one subdomain per launch, FP64 everywhere, no graph); the 65^2 ring
+(FP64), the 129^3 shell DD, the 256-instance batch (batched FP32 vs plain FP64), a Poisson
+serving stream (meshes/s, p50/p99 latency), and the stencil at a >= 1 GB working set.
 """
 import argparse
 import json
 import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -23,11 +26,23 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp16_TF": 2500.0, "fp32_TF": 157.3, "fp64_TF": 78.6}
 MFMA_PEAK = {"split16": PEAK["fp16_TF"], "fp32": PEAK["fp32_TF"], "fp64": PEAK["fp64_TF"]}
+KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil_kernel", "euler": "euler_kernel",
+          "fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel<single>", "pair0": "strip_kernel<pair>",
+          "inv_mid": "strip_kernel<single>", "inv_last": "inv_last_kernel"}
 
 
-def timed_form(ctx, binding, w, prec, exec_, steps, warmup, phase_steps):
+def log(*a):
+    print("#", *a, file=sys.stderr, flush=True)
+
+
+def nodes_of(ws):
+    return sum(math.prod(w["grid"]["n"]) for w in ws)
+
+
+def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0):
+    """Resident plan: warmup steps, then exactly `steps` timed steps bracketed by synchronize."""
     import torch
-    plan = binding.Plan(ctx, [w], prec, exec_)
+    plan = binding.Plan(ctx, ws, prec, exec_)
     try:
         plan.step(warmup)
         plan.sync()
@@ -37,31 +52,94 @@ def timed_form(ctx, binding, w, prec, exec_, steps, warmup, phase_steps):
         plan.sync()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        phases = plan.phase_times(phase_steps) if phase_steps > 0 else None
+        phases = plan.phase_times(phase_reps) if phase_reps > 0 else None
         mesh, st = plan.mesh(0)
     finally:
         plan.close()
-    nodes = math.prod(w["grid"]["n"])
-    return {"updates_per_s": nodes * steps / dt, "ms_per_step": 1e3 * dt / steps, "seconds": dt,
+    return {"updates_per_s": nodes_of(ws) * steps / dt, "ms_per_step": 1e3 * dt / steps, "seconds": dt,
             "steps": steps, "min_det": st["min_det"], "min_cell": st["min_cell"], "phases": phases}
 
 
 def roofline_of(phases, prec):
-    name, ph = max(((k, v) for k, v in phases.items()), key=lambda kv: kv[1]["ms"])
+    """Dominant kernel of a step: algorithmic work per launch / mean launch duration."""
+    name, ph = max(((k, v) for k, v in phases.items() if v["flops"] > 0 or v["bytes"] > 0),
+                   key=lambda kv: kv[1]["ms"])
     sec = ph["ms"] * 1e-3
-    kern = {"fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel (single)", "pair0": "strip_kernel (pair)",
-            "inv_mid": "strip_kernel (single)", "inv_last": "inv_last_kernel", "transmit": "transmit_kernel",
-            "stencil": "stencil_kernel", "euler": "euler_kernel"}[name]
     if ph["flops"] > 0:
         ach = ph["flops"] / sec / 1e12
         peak = MFMA_PEAK[prec]
-        return {"kernel": f"{kern} ({name})", "bound": "mfma", "achieved": ach, "peak": peak,
+        return {"kernel": KERNEL[name], "phase": name, "bound": "mfma", "achieved": ach, "peak": peak,
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                "algorithmic_per_launch": ph["flops"], "avg_ms": ph["ms"]}
+                "algorithmic_per_launch": ph["flops"], "avg_launch_ms": ph["ms"]}
     ach = ph["bytes"] / sec / 1e9
-    return {"kernel": f"{kern} ({name})", "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-            "frac": ach / PEAK["hbm_GBs"], "traffic": None, "algorithmic_per_launch": ph["bytes"],
-            "avg_ms": ph["ms"]}
+    return {"kernel": KERNEL[name], "phase": name, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"],
+            "unit": "GB/s", "frac": ach / PEAK["hbm_GBs"], "traffic": None,
+            "algorithmic_per_launch": ph["bytes"], "avg_launch_ms": ph["ms"]}
+
+
+def stencil_roofline(ctx, binding, workloads):
+    """Stencil phase alone over two 8193^2 DD requests (32 x 32 parts): 134 M nodes, 1.07 GB of
+    compulsory FP32 traffic per launch, far beyond the 256 MB last-level cache."""
+    w = workloads.sine_dd(n=8193, parts=(32, 32), overlap=8, steps=1)
+    plan = binding.Plan(ctx, [w, w], "split16", "batched")
+    try:
+        ph = plan.phase_times(10)
+    finally:
+        plan.close()
+    st = ph["stencil"]
+    gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+    return {"kernel": "stencil_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+            "frac": gbs / PEAK["hbm_GBs"], "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
+            "workload": "2 x 8193^2 sine layer, 32x32 parts, FP32 (8 B per node)"}
+
+
+def serve_stream(binding, workloads, count, budget):
+    """Open-loop Poisson stream (mean 200 req/s) through pma_submit / pma_poll.  Latency is taken
+    on the client: from the request's scheduled arrival to the poll that sees it DONE."""
+    ws = workloads.stream(count=count)
+    ctx = binding.Context(0, budget_bytes=budget)
+    tickets = [None] * len(ws)
+    late = [0.0] * len(ws)
+    t_start = time.perf_counter()
+
+    def producer():
+        for i, w in enumerate(ws):
+            d = w["arrival_s"] - (time.perf_counter() - t_start)
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = ctx.submit(w, "split16")
+            late[i] = (time.perf_counter() - t_start) - w["arrival_s"]
+
+    th = threading.Thread(target=producer)
+    th.start()
+    done = {}
+    last_note = time.perf_counter()
+    while len(done) < len(ws):
+        if time.perf_counter() - last_note > 5.0:
+            last_note = time.perf_counter()
+            log(f"serving: {len(done)}/{len(ws)} finished, {sum(t is not None for t in tickets)} submitted")
+        for i in range(len(ws)):
+            if i in done or tickets[i] is None:
+                continue
+            state, _, st = ctx.poll(tickets[i])
+            if state in (2, 3):
+                done[i] = (state, st, time.perf_counter() - t_start)
+        time.sleep(0.0005)
+        if time.perf_counter() - t_start > 300:
+            raise RuntimeError("serving stream did not drain")
+    th.join()
+    wall = max(v[2] for v in done.values())
+    ctx.close()
+    ok = [i for i, v in done.items() if v[0] == 2]
+    lat = sorted(1e3 * (done[i][2] - ws[i]["arrival_s"]) for i in ok)
+    upd = sum(math.prod(ws[i]["grid"]["n"]) * ws[i]["time"]["steps"] for i in ok)
+    pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100 * (len(lat) - 1))))]
+    return {"requests": len(ws), "done": len(ok), "failed": len(ws) - len(ok), "wall_s": wall,
+            "meshes_per_s": len(ok) / wall, "updates_per_s": upd / wall, "p50_ms": pct(50), "p99_ms": pct(99),
+            "max_submit_lag_ms": 1e3 * max(late),
+            "mean_server_queue_ms": sum(v[1]["ms_queue"] for v in done.values()) / len(done),
+            "budget_bytes": budget, "offered_rate_per_s": 200.0,
+            "arrival_window_s": ws[-1]["arrival_s"]}
 
 
 def cpu_baseline(w, steps):
@@ -82,11 +160,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve", type=int, default=600, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["split16", "fp32", "fp64plain"], default=None,
-                    help="time one form only (for profiler runs)")
+                    help="time one form of the headline workload only (profiler runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized float32 buffer 10 times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written": b.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is design-only.",
               file=sys.stderr)
@@ -95,16 +186,14 @@ def main():
     from paper_2006_14602_amd import binding, workloads
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = workloads.sine_dd()
-    ctx = binding.Context(0, budget_bytes=4 << 30)
+    ctx = binding.Context(0, budget_bytes=12 << 30)
     forms = {}
     todo = [args.only] if args.only else ["split16", "fp32", "fp64plain"]
     for f in todo:
         prec, ex = ("fp64", "plain") if f == "fp64plain" else (f, "batched")
         steps = args.steps if f != "fp64plain" else max(1, min(args.steps, 100))
-        forms[f] = timed_form(ctx, binding, w, prec, ex, steps, min(args.warmup, steps), 20)
-        print(f"# {f}: {forms[f]['updates_per_s']:.4e} updates/s, {forms[f]['ms_per_step']:.4f} ms/step",
-              file=sys.stderr, flush=True)
-    ctx.close()
+        forms[f] = timed_plan(ctx, binding, [w], prec, ex, steps, min(args.warmup, steps), phase_reps=50)
+        log(f"{f}: {forms[f]['updates_per_s']:.4e} updates/s, {forms[f]['ms_per_step']:.4f} ms/step")
     main_form = args.only or "split16"
     m = forms[main_form]
     prec = "fp64" if main_form == "fp64plain" else main_form
@@ -121,10 +210,42 @@ def main():
                    "exec": "plain" if main_form == "fp64plain" else "batched (graph replay)"},
         "roofline": roofline_of(m["phases"], prec),
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "phases"} for k, v in forms.items()},
-        "phases_ms": {k: {p: round(v["ms"], 5) for p, v in f["phases"].items()} for k, f in forms.items()},
+        "phases_ms_per_launch": {k: {p: round(v["ms"], 5) for p, v in f["phases"].items()}
+                                 for k, f in forms.items()},
     }
     if "fp64plain" in forms and main_form != "fp64plain":
         out["batched_fp32_over_plain_fp64"] = m["updates_per_s"] / forms["fp64plain"]["updates_per_s"]
+    if not args.quick and not args.only:
+        extra = {}
+        ring = workloads.ring()
+        r = timed_plan(ctx, binding, [ring], "fp64", "batched", 200, 10)
+        extra["ring_65_fp64"] = {k: r[k] for k in ("updates_per_s", "ms_per_step")}
+        log(f"ring 65^2 fp64: {r['updates_per_s']:.3e}")
+        shell = workloads.shell_dd()
+        r = timed_plan(ctx, binding, [shell], "split16", "batched", 200, 5, phase_reps=10)
+        extra["shell_dd_129_split16"] = {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
+                                         "roofline": roofline_of(r["phases"], "split16")}
+        log(f"shell 129^3 split16: {r['updates_per_s']:.3e}")
+        batch = workloads.bumps_batch()
+        rb = timed_plan(ctx, binding, batch, "split16", "batched", 200, 5, phase_reps=10)
+        rp = timed_plan(ctx, binding, batch, "fp64", "plain", 10, 1)
+        extra["bumps_batch_256"] = {"batched_split16_updates_per_s": rb["updates_per_s"],
+                                    "batched_ms_per_step": rb["ms_per_step"],
+                                    "plain_fp64_updates_per_s": rp["updates_per_s"],
+                                    "plain_ms_per_step": rp["ms_per_step"],
+                                    "speedup": rb["updates_per_s"] / rp["updates_per_s"],
+                                    "roofline": roofline_of(rb["phases"], "split16")}
+        log(f"batch 256: {rb['updates_per_s']:.3e} vs plain fp64 {rp['updates_per_s']:.3e}")
+        extra["stencil_hbm_large"] = stencil_roofline(ctx, binding, workloads)
+        log(f"stencil large: {extra['stencil_hbm_large']['achieved']:.0f} GB/s")
+        out["other_workloads"] = extra
+    ctx.close()
+    if args.serve > 0 and not args.quick and not args.only:
+        s8 = serve_stream(binding, workloads, args.serve, 8 << 30)
+        log(f"serve 8GB: {s8}")
+        s512 = serve_stream(binding, workloads, max(50, args.serve // 4), 512 << 20)
+        log(f"serve 512MB: {s512}")
+        out["serving"] = {"budget_8GiB": s8, "budget_512MiB": s512}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out))

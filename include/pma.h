@@ -217,10 +217,11 @@ int pma_plan_sync(pma_plan* plan);
  *   4 forward DCT along the middle axis (3D)          5 forward DCT + spectral scale + inverse DCT
  *                                                       along axis 0
  *   6 inverse DCT along the middle axis (3D)          7 inverse DCT along the last axis + update
- * Runs nsteps steps with HIP events around every phase (on the stream the kernels run on) and
- * returns the mean device milliseconds per step of each phase in ms[] (cap >= 8 entries);
- * flops[] and bytes[] (may be NULL) receive each phase's algorithmic floating-point operations
- * and compulsory HBM bytes per step.  *nphases receives 8. */
+ * Times each phase on its own: nsteps launches back to back between two HIP events on the
+ * stream the kernels run on; ms[ph] receives the mean device milliseconds per launch (cap >= 8
+ * entries).  flops[] and bytes[] (may be NULL) receive each phase's algorithmic floating-point
+ * operations and compulsory HBM bytes per launch.  The plan's state is saved before and
+ * restored after (the call needs device memory for one copy of it).  *nphases receives 8. */
 int pma_plan_phase_times(pma_plan* plan, int nsteps, double* ms, double* flops, double* bytes, int cap,
                          int* nphases);
 

@@ -38,6 +38,9 @@ __device__ inline float dlog(float x) { return logf(x); }
 __device__ inline double dlog(double x) { return log(x); }
 __device__ inline float dsinpi(float x) { return sinpif(x); }
 __device__ inline double dsinpi(double x) { return sinpi(x); }
+// sin(2 pi x): the FP32 form uses the hardware sine, whose argument is in revolutions
+__device__ inline float sin2pi(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ inline double sin2pi(double x) { return sinpi(2.0 * x); }
 
 // sech^2(z) = 4 e^{-2|z|} / (1 + e^{-2|z|})^2 (no overflow for large |z|)
 template <typename T>
@@ -47,47 +50,56 @@ __device__ inline T sech2(T z) {
   return T(4) * e / (q * q);
 }
 
+// the monitor parameters of an instance in the working precision
+__device__ inline const MonP<float>& mon_of(const InstDev& I, float) { return I.monf; }
+__device__ inline const MonP<double>& mon_of(const InstDev& I, double) { return I.mond; }
+
+// fast FP32 forms: v_exp / v_log / v_rcp based exp, log and reciprocal
+__device__ inline float fexp(float x) { return __expf(x); }
+__device__ inline double fexp(double x) { return exp(x); }
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double frcp(double x) { return 1.0 / x; }
+
 template <typename T>
-__device__ inline T log_rho(const MonitorDev& m, int dim, T x0, T x1, T x2) {
+__device__ inline T sech2_fast(T z) {
+  const T e = fexp(T(-2) * fabs(z));
+  const T q = T(1) + e;
+  return T(4) * e * frcp(q * q);
+}
+
+// rho - 1 (exact excess for the "1 + ..." monitors; the constant monitor returns amp - 1)
+template <typename T>
+__device__ inline T rho_excess(const MonP<T>& m, int dim, T x0, T x1, T x2) {
   switch (m.kind) {
     case MON_CONST:
-      return dlog(T(m.amp));
+      return m.amp - T(1);
     case MON_RADIAL: {
-      T d0 = x0 - T(m.c[0]), d1 = x1 - T(m.c[1]);
-      T r2 = d0 * d0 + d1 * d1;
-      if (dim == 3) {
-        T d2 = x2 - T(m.c[2]);
-        r2 += d2 * d2;
-      }
-      return dlog1p(T(m.amp) * sech2(T(m.k) * (r2 - T(m.r0) * T(m.r0))));
+      const T d0 = x0 - m.c[0], d1 = x1 - m.c[1], d2 = dim == 3 ? x2 - m.c[2] : T(0);
+      return m.amp * sech2_fast(m.k * ((d0 * d0 + d1 * d1 + d2 * d2) - m.r02));
     }
-    case MON_SINE: {
-      T s = x1 - T(m.c[1]) - T(m.r0) * dsinpi(T(2) * x0);
-      return dlog1p(T(m.amp) * sech2(T(m.k) * s));
-    }
+    case MON_SINE:
+      return m.amp * sech2_fast(m.k * (x1 - m.c[1] - m.r0 * sin2pi(x0)));
     case MON_GAUSS: {
       T acc = T(0);
       for (int b = 0; b < m.nb; ++b) {
-        T d0 = x0 - T(m.bc[b][0]), d1 = x1 - T(m.bc[b][1]);
-        T r2 = d0 * d0 + d1 * d1;
-        if (dim == 3) {
-          T d2 = x2 - T(m.bc[b][2]);
-          r2 += d2 * d2;
-        }
-        T w = T(m.bw[b]);
-        acc += T(m.bamp[b]) * dexp(-r2 / (T(2) * w * w));
+        const T d0 = x0 - m.bc[b][0], d1 = x1 - m.bc[b][1], d2 = dim == 3 ? x2 - m.bc[b][2] : T(0);
+        acc += m.bamp[b] * fexp((d0 * d0 + d1 * d1 + d2 * d2) * m.bnh[b]);
       }
-      return dlog1p(acc);
+      return acc;
     }
     case MON_SEPARABLE: {
-      T r = dlog1p(T(m.amp_axes[0]) * sech2(T(m.k_axes[0]) * (x0 - T(m.c[0])))) +
-            dlog1p(T(m.amp_axes[1]) * sech2(T(m.k_axes[1]) * (x1 - T(m.c[1]))));
-      if (dim == 3) r += dlog1p(T(m.amp_axes[2]) * sech2(T(m.k_axes[2]) * (x2 - T(m.c[2]))));
-      return r;
+      T p = (T(1) + m.aa[0] * sech2_fast(m.ka[0] * (x0 - m.c[0]))) *
+            (T(1) + m.aa[1] * sech2_fast(m.ka[1] * (x1 - m.c[1])));
+      if (dim == 3) p *= T(1) + m.aa[2] * sech2_fast(m.ka[2] * (x2 - m.c[2]));
+      return p - T(1);
     }
   }
   return T(0);
 }
+
+// log(rho (1 + e)): FP64 keeps log1p of both excesses; FP32 takes one hardware log of the product
+__device__ inline double log_rho_det(double rex, double e) { return log1p(rex) + log1p(e); }
+__device__ inline float log_rho_det(float rex, float e) { return __logf((1.f + rex) * (1.f + e)); }
 
 __device__ inline bool is_artificial(int art, int k, int i, int n) {
   return (i == 0 && ((art >> (2 * k)) & 1)) || (i == n - 1 && ((art >> (2 * k + 1)) & 1));
@@ -101,89 +113,142 @@ template <typename T>
 __device__ inline bool finite_(T x) { return isfinite(x); }
 
 // ------------------------------------------------------------------------------------------
-// K1/K2: stencil + monitor + log at one node.  (row, col) index the [rows][last axis] view of
-// the subdomain (rows = n0 in 2D, n0 * n1 in 3D).  Returns F; raises the instance's status bits
-// on a non-positive determinant or a non-finite value.  Artificial-boundary nodes get F = 0.
+// K1/K2: stencil + monitor + log (the right-hand side F), Neumann ghosts by mirroring.
 // ------------------------------------------------------------------------------------------
 
+// F from the 3 x 3 (2D) neighbourhood of node (i, j): c centre, xm/xp along axis 0, ym/yp along
+// axis 1, mm/mp/pm/pp the diagonal corners; r* are 1/(2h), 1/h^2 and 1/(4 h h) factors
 template <typename T>
-__device__ inline T stencil_point(const SubDev& S, const InstDev& I, int row, int col, int* status) {
-  const T* __restrict__ phi = (const T*)S.phi;
-  const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
-  const T h0 = T(S.h[0]), h1 = T(S.h[1]), h2 = T(S.h[2]);
-  T f, e;
-  if (S.dim == 2) {
-    const int i = row, j = col;
-    if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1)) return T(0);
-    const int im = mlo(i), ip = mhi(i, n0), jm = mlo(j), jp = mhi(j, n1);
-    const T c = phi[(long)i * n1 + j];
-    const T xm = phi[(long)im * n1 + j], xp = phi[(long)ip * n1 + j];
-    const T ym = phi[(long)i * n1 + jm], yp = phi[(long)i * n1 + jp];
-    const T mm = phi[(long)im * n1 + jm], mp = phi[(long)im * n1 + jp];
-    const T pm = phi[(long)ip * n1 + jm], pp = phi[(long)ip * n1 + jp];
-    const T gx = (xp - xm) / (T(2) * h0);
-    const T gy = (yp - ym) / (T(2) * h1);
-    const T hxx = (xp - T(2) * c + xm) / (h0 * h0);
-    const T hyy = (yp - T(2) * c + ym) / (h1 * h1);
-    const T hxy = (pp - pm - mp + mm) / (T(4) * h0 * h1);
-    e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
-    const T x0 = T(S.a[0]) + T(S.off[0] + i) * h0 + gx;
-    const T x1 = T(S.a[1]) + T(S.off[1] + j) * h1 + gy;
-    f = T(I.log_vol_theta) + log_rho<T>(I.mon, 2, x0, x1, T(0)) + dlog1p(e);
-  } else {
-    const int i = row / n1, j = row - (row / n1) * n1, k = col;
-    if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1) || is_artificial(S.art, 2, k, n2))
-      return T(0);
-    const long s1 = n2, s0 = (long)n1 * n2;
-    const long im = mlo(i) * s0, ip = mhi(i, n0) * s0;
-    const long jm = mlo(j) * s1, jp = mhi(j, n1) * s1;
-    const long km = mlo(k), kp = mhi(k, n2);
-    const long I0 = i * s0, J0 = j * s1, K0 = k;
-    const T c = phi[I0 + J0 + K0];
-    const T xm = phi[im + J0 + K0], xp = phi[ip + J0 + K0];
-    const T ym = phi[I0 + jm + K0], yp = phi[I0 + jp + K0];
-    const T zm = phi[I0 + J0 + km], zp = phi[I0 + J0 + kp];
-    const T xy = (phi[ip + jp + K0] - phi[ip + jm + K0] - phi[im + jp + K0] + phi[im + jm + K0]);
-    const T xz = (phi[ip + J0 + kp] - phi[ip + J0 + km] - phi[im + J0 + kp] + phi[im + J0 + km]);
-    const T yz = (phi[I0 + jp + kp] - phi[I0 + jp + km] - phi[I0 + jm + kp] + phi[I0 + jm + km]);
-    const T gx = (xp - xm) / (T(2) * h0);
-    const T gy = (yp - ym) / (T(2) * h1);
-    const T gz = (zp - zm) / (T(2) * h2);
-    const T a = (xp - T(2) * c + xm) / (h0 * h0);
-    const T b = (yp - T(2) * c + ym) / (h1 * h1);
-    const T q = (zp - T(2) * c + zm) / (h2 * h2);
-    const T p = xy / (T(4) * h0 * h1);
-    const T r = xz / (T(4) * h0 * h2);
-    const T s = yz / (T(4) * h1 * h2);
-    // det(I + H) - 1 = tr H + (sum of principal 2x2 minors) + det H
-    const T tr = a + b + q;
-    const T m2 = (a * b - p * p) + (a * q - r * r) + (b * q - s * s);
-    const T dt3 = a * (b * q - s * s) - p * (p * q - s * r) + r * (p * s - b * r);
-    e = tr + m2 + dt3;
-    const T x0 = T(S.a[0]) + T(S.off[0] + i) * h0 + gx;
-    const T x1 = T(S.a[1]) + T(S.off[1] + j) * h1 + gy;
-    const T x2 = T(S.a[2]) + T(S.off[2] + k) * h2 + gz;
-    f = T(I.log_vol_theta) + log_rho<T>(I.mon, 3, x0, x1, x2) + dlog1p(e);
-  }
+__device__ inline T rhs2(const SubDev& S, const MonP<T>& mon, T lvt, T a0, T a1, T h0, T h1, int i, int j, T c,
+                         T xm, T xp, T ym, T yp, T mm, T mp, T pm, T pp, T r2h0, T r2h1, T rh00, T rh11, T r4h01,
+                         int* status) {
+  const T gx = (xp - xm) * r2h0;
+  const T gy = (yp - ym) * r2h1;
+  const T hxx = (xp - T(2) * c + xm) * rh00;
+  const T hyy = (yp - T(2) * c + ym) * rh11;
+  const T hxy = (pp - pm - mp + mm) * r4h01;
+  const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
+  const T x0 = a0 + T(S.off[0] + i) * h0 + gx;
+  const T x1 = a1 + T(S.off[1] + j) * h1 + gy;
+  const T f = lvt + log_rho_det(rho_excess(mon, 2, x0, x1, T(0)), e);
   if (!(T(1) + e > T(0))) atomicOr(&status[S.inst], ST_TANGLED);
   else if (!finite_(f)) atomicOr(&status[S.inst], ST_NONFINITE);
   return f;
 }
 
-// Stand-alone stencil (forward-Euler solves): tile = 4 rows x 64 columns, writes F.
+// mirror an index across a face (Neumann ghost), then keep it inside the array (rows beyond the
+// array's end only feed outputs that are not stored)
+__device__ inline int mirror_clamp(int i, int n) {
+  if (i < 0) i = -i;
+  if (i > n - 1) i = 2 * (n - 1) - i;
+  return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+// Stencil into F.  A tile is 16 rows x 64 columns of one plane (2D: the array; 3D: plane i0 of
+// the [n0][n1][n2] array, rows = i1, columns = i2); it is staged with a one-node halo in LDS
+// (three planes in 3D), mirror ghosts applied while loading, and each thread computes 4 nodes.
+// tile = (sub, row0, col0, 0) in 2D, (sub, i0, row0, col0) in 3D.
 template <typename T>
-__global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ tiles, int ntiles,
-                                                      StepArgs sa) {
+__global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
+  constexpr int TR = 16, TC = 64, HR = TR + 2, HC = TC + 2;
+  __shared__ T sm[3][HR][HC];
   if ((int)blockIdx.x >= ntiles) return;
   const int4 tl = tiles[blockIdx.x];
   const SubDev& S = sa.subs[tl.x];
   const InstDev& I = sa.insts[S.inst];
-  const int R = (S.dim == 2) ? S.n[0] : S.n[0] * S.n[1];
-  const int C = S.n[S.dim - 1];
-  const int row = tl.y + (threadIdx.x >> 6);
-  const int col = tl.z + (threadIdx.x & 63);
-  if (row >= R || col >= C) return;
-  ((T*)S.F)[(long)row * C + col] = stencil_point<T>(S, I, row, col, sa.status);
+  const T* __restrict__ phi = (const T*)S.phi;
+  T* __restrict__ F = (T*)S.F;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const T h0 = T(S.h[0]), h1 = T(S.h[1]), h2 = T(S.h[2]);
+  if (S.dim == 2) {
+    const int n0 = S.n[0], n1 = S.n[1];
+    const int row0 = tl.y, col0 = tl.z;
+    if (row0 >= 1 && row0 + TR < n0 && col0 >= 1 && col0 + TC < n1) {
+      // interior tile: the halo never crosses a face
+      const T* base = phi + (long)(row0 - 1) * n1 + (col0 - 1);
+      for (int idx = tid; idx < HR * HC; idx += 256) {
+        const int r = idx / HC, c = idx - r * HC;
+        sm[0][r][c] = base[(long)r * n1 + c];
+      }
+    } else {
+      for (int idx = tid; idx < HR * HC; idx += 256) {
+        const int r = idx / HC, c = idx - r * HC;
+        const int gi = mirror_clamp(row0 + r - 1, n0), gj = mirror_clamp(col0 + c - 1, n1);
+        sm[0][r][c] = phi[(long)gi * n1 + gj];
+      }
+    }
+    __syncthreads();
+    const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
+    const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
+    const MonP<T>& mon = mon_of(I, T(0));
+    const T lvt = T(I.log_vol_theta), a0 = T(S.a[0]), a1 = T(S.a[1]);
+    const int j = col0 + tx;
+    if (j >= n1) return;
+    for (int m = 0; m < TR / 4; ++m) {
+      const int rr = ty + 4 * m, i = row0 + rr;
+      if (i >= n0) break;
+      const long v = (long)i * n1 + j;
+      if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1)) {
+        F[v] = T(0);
+        continue;
+      }
+      const int r = rr + 1, c = tx + 1;
+      F[v] = rhs2<T>(S, mon, lvt, a0, a1, h0, h1, i, j, sm[0][r][c], sm[0][r - 1][c], sm[0][r + 1][c], sm[0][r][c - 1], sm[0][r][c + 1],
+                     sm[0][r - 1][c - 1], sm[0][r - 1][c + 1], sm[0][r + 1][c - 1], sm[0][r + 1][c + 1], r2h0, r2h1,
+                     rh00, rh11, r4h01, sa.status);
+    }
+    return;
+  }
+  const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
+  const int i0 = tl.y, row0 = tl.z, col0 = tl.w;
+  for (int idx = tid; idx < 3 * HR * HC; idx += 256) {
+    const int p = idx / (HR * HC), rem = idx - p * (HR * HC);
+    const int r = rem / HC, c = rem - r * HC;
+    const int gp = mirror_clamp(i0 + p - 1, n0), gi = mirror_clamp(row0 + r - 1, n1), gj = mirror_clamp(col0 + c - 1, n2);
+    sm[p][r][c] = phi[((long)gp * n1 + gi) * n2 + gj];
+  }
+  __syncthreads();
+  const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1), r2h2 = T(1) / (T(2) * h2);
+  const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), rh22 = T(1) / (h2 * h2);
+  const T r4h01 = T(1) / (T(4) * h0 * h1), r4h02 = T(1) / (T(4) * h0 * h2), r4h12 = T(1) / (T(4) * h1 * h2);
+  const MonP<T>& mon = mon_of(I, T(0));
+  const T lvt = T(I.log_vol_theta), a0 = T(S.a[0]), a1 = T(S.a[1]), a2 = T(S.a[2]);
+  const int k = col0 + tx;
+  if (k >= n2) return;
+  const bool art0 = is_artificial(S.art, 0, i0, n0);
+  for (int m = 0; m < TR / 4; ++m) {
+    const int rr = ty + 4 * m, j = row0 + rr;
+    if (j >= n1) break;
+    const long v = ((long)i0 * n1 + j) * n2 + k;
+    if (art0 || is_artificial(S.art, 1, j, n1) || is_artificial(S.art, 2, k, n2)) {
+      F[v] = T(0);
+      continue;
+    }
+    const int r = rr + 1, c = tx + 1;
+    const T cc = sm[1][r][c];
+    const T xm = sm[0][r][c], xp = sm[2][r][c];
+    const T ym = sm[1][r - 1][c], yp = sm[1][r + 1][c];
+    const T zm = sm[1][r][c - 1], zp = sm[1][r][c + 1];
+    const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1, gz = (zp - zm) * r2h2;
+    const T a = (xp - T(2) * cc + xm) * rh00;
+    const T b = (yp - T(2) * cc + ym) * rh11;
+    const T q = (zp - T(2) * cc + zm) * rh22;
+    const T p = (sm[2][r + 1][c] - sm[2][r - 1][c] - sm[0][r + 1][c] + sm[0][r - 1][c]) * r4h01;
+    const T rx = (sm[2][r][c + 1] - sm[2][r][c - 1] - sm[0][r][c + 1] + sm[0][r][c - 1]) * r4h02;
+    const T sy = (sm[1][r + 1][c + 1] - sm[1][r + 1][c - 1] - sm[1][r - 1][c + 1] + sm[1][r - 1][c - 1]) * r4h12;
+    // det(I + H) - 1 = tr H + (sum of principal 2x2 minors) + det H
+    const T tr = a + b + q;
+    const T m2 = (a * b - p * p) + (a * q - rx * rx) + (b * q - sy * sy);
+    const T d3 = a * (b * q - sy * sy) - p * (p * q - sy * rx) + rx * (p * sy - b * rx);
+    const T e = tr + m2 + d3;
+    const T x0 = a0 + T(S.off[0] + i0) * h0 + gx;
+    const T x1 = a1 + T(S.off[1] + j) * h1 + gy;
+    const T x2 = a2 + T(S.off[2] + k) * h2 + gz;
+    const T f = lvt + log_rho_det(rho_excess(mon, 3, x0, x1, x2), e);
+    F[v] = f;
+    if (!(T(1) + e > T(0))) atomicOr(&sa.status[S.inst], ST_TANGLED);
+    else if (!finite_(f)) atomicOr(&sa.status[S.inst], ST_NONFINITE);
+  }
 }
 
 // ------------------------------------------------------------------------------------------

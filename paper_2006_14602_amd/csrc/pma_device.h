@@ -19,13 +19,18 @@ enum MonKind { MON_CONST = 0, MON_RADIAL = 1, MON_SINE = 2, MON_GAUSS = 3, MON_S
 // status bits raised by kernels (per instance)
 enum { ST_TANGLED = 1, ST_NONFINITE = 2 };
 
-struct MonitorDev {
-  int kind;
-  int nb;
-  double amp, k, r0;
-  double c[3];
-  double amp_axes[3], k_axes[3];
-  double bamp[4], bw[4], bc[4][3];
+// Monitor parameters, precomputed on the host in the working precision:
+//   rho = amp                                              (MON_CONST)
+//   rho = 1 + amp sech^2(k (|x - c|^2 - r02))              (MON_RADIAL, r02 = r0^2)
+//   rho = 1 + amp sech^2(k (x_1 - c_1 - r0 sin(2 pi x_0)))  (MON_SINE)
+//   rho = 1 + sum_b bamp_b exp(bnh_b |x - bc_b|^2)          (MON_GAUSS, bnh = -1 / (2 w^2))
+//   rho = prod_k (1 + aa_k sech^2(ka_k (x_k - c_k)))        (MON_SEPARABLE)
+template <typename T>
+struct MonP {
+  int kind, nb;
+  T amp, k, r0, r02;
+  T c[3], aa[3], ka[3];
+  T bamp[4], bnh[4], bc[4][3];
 };
 
 // DCT-I basis of one axis of a subdomain, in the precision of the solve.  Matrices have
@@ -59,7 +64,8 @@ struct SubDev {
 };
 
 struct InstDev {
-  MonitorDev mon;
+  MonP<double> mond;
+  MonP<float> monf;
   double log_vol_theta;  // log(|Omega_c| / theta)
   double dt;
   int first_sub, nsub;

@@ -163,13 +163,16 @@ class Arena {
 // Both matrices are symmetric, so a mode product along any axis is an "NN" product.
 // ------------------------------------------------------------------------------------------
 
+// DCT-I matrices of one axis length n in one precision, kept in the arena while requests use
+// them (refs) and afterwards as a cache, evicted least recently used when the arena is full
 struct Basis {
-  int n = 0, rows = 0, ld = 0;  // rows = round_up(n, 16), ld = round_up(n, 32); zero padded
-  double *A64 = nullptr, *B64 = nullptr, *sig64 = nullptr;
-  float *A32 = nullptr, *B32 = nullptr, *sig32 = nullptr;
-  _Float16 *Ahi = nullptr, *Alo = nullptr, *Bhi = nullptr, *Blo = nullptr;  // 2^s A and B split
-  int scale_exp = 0;
+  int n = 0, prec = 0, rows = 0, ld = 0;  // rows = round_up(n, 16), ld = round_up(n, 32)
+  int refs = 0;
+  uint64_t last_use = 0;
+  char* mem = nullptr;
   size_t bytes = 0;
+  const void *fwd = nullptr, *fwdl = nullptr, *inv = nullptr, *invl = nullptr, *sig = nullptr;
+  float fwd_unscale = 1.0f;
 };
 
 static double cos_pi_frac(long p, long q) {
@@ -523,7 +526,8 @@ static void build_plan(Instance& I) {
   partition_host(I.grid, ddp, I.subs, I.parts, I.own);
   I.theta = I.mon.theta > 0 ? I.mon.theta : theta_host(I.grid, I.mon);
   if (!(I.theta > 0) || !std::isfinite(I.theta)) thr(PMA_E_INVAL, "theta must be positive and finite");
-  // transmission lists
+  // transmission lists: walk the artificial faces only; a node on several artificial faces is
+  // listed once, under the first face (axis order, low side first) that holds it
   const int ns = (int)I.subs.size();
   I.trans.clear();
   I.trans_first.assign(ns + 1, 0);
@@ -531,31 +535,41 @@ static void build_plan(Instance& I) {
     I.trans_first[s] = (int)I.trans.size();
     const SubHost& S = I.subs[s];
     if (S.art == 0) continue;
-    for (int i0 = 0; i0 < S.n[0]; ++i0)
-      for (int i1 = 0; i1 < S.n[1]; ++i1)
-        for (int i2 = 0; i2 < S.n[2]; ++i2) {
-          const int li[3] = {i0, i1, i2};
-          bool art = false;
-          for (int k = 0; k < I.dim; ++k) {
-            if (li[k] == 0 && (S.art >> (2 * k) & 1)) art = true;
-            if (li[k] == S.n[k] - 1 && (S.art >> (2 * k + 1) & 1)) art = true;
-          }
-          if (!art) continue;
-          int o[3] = {0, 0, 0}, gi[3] = {0, 0, 0};
-          for (int k = 0; k < I.dim; ++k) {
-            gi[k] = S.lo[k] + li[k];
-            o[k] = I.own[k][gi[k]];
-          }
-          const int src = (o[0] * I.parts[1] + o[1]) * I.parts[2] + o[2];
-          const SubHost& O = I.subs[src];
-          long se = 0, de = 0;
-          for (int k = 0; k < 3; ++k) {
-            const int ol = (k < I.dim) ? gi[k] - O.lo[k] : 0;
-            se = se * O.n[k] + ol;
-            de = de * S.n[k] + li[k];
-          }
-          I.trans.push_back(int4{s, (int)de, src, (int)se});
-        }
+    for (int k = 0; k < I.dim; ++k)
+      for (int e = 0; e < 2; ++e) {
+        if (!(S.art >> (2 * k + e) & 1)) continue;
+        const int fixed = e == 0 ? 0 : S.n[k] - 1;
+        int lo[3] = {0, 0, 0}, hi[3] = {S.n[0], S.n[1], S.n[2]};
+        lo[k] = fixed;
+        hi[k] = fixed + 1;
+        for (int i0 = lo[0]; i0 < hi[0]; ++i0)
+          for (int i1 = lo[1]; i1 < hi[1]; ++i1)
+            for (int i2 = lo[2]; i2 < hi[2]; ++i2) {
+              const int li[3] = {i0, i1, i2};
+              bool earlier = false;
+              for (int k2 = 0; k2 < I.dim && !earlier; ++k2)
+                for (int e2 = 0; e2 < 2; ++e2) {
+                  if (k2 * 2 + e2 >= k * 2 + e) break;
+                  if (!(S.art >> (2 * k2 + e2) & 1)) continue;
+                  if (li[k2] == (e2 == 0 ? 0 : S.n[k2] - 1)) earlier = true;
+                }
+              if (earlier) continue;
+              int o[3] = {0, 0, 0}, gi[3] = {0, 0, 0};
+              for (int kk = 0; kk < I.dim; ++kk) {
+                gi[kk] = S.lo[kk] + li[kk];
+                o[kk] = I.own[kk][gi[kk]];
+              }
+              const int src = (o[0] * I.parts[1] + o[1]) * I.parts[2] + o[2];
+              const SubHost& O = I.subs[src];
+              long se = 0, de = 0;
+              for (int kk = 0; kk < 3; ++kk) {
+                const int ol = (kk < I.dim) ? gi[kk] - O.lo[kk] : 0;
+                se = se * O.n[kk] + ol;
+                de = de * S.n[kk] + li[kk];
+              }
+              I.trans.push_back(int4{s, (int)de, src, (int)se});
+            }
+      }
   }
   I.trans_first[ns] = (int)I.trans.size();
 }
@@ -595,8 +609,10 @@ struct pma_ctx {
   pma::Arena arena;
   hipStream_t stream = nullptr;
   std::recursive_mutex mu;  // guards arena, bases, stream work of synchronous calls
-  std::map<int, pma::Basis*> bases;
+  std::map<std::pair<int, int>, pma::Basis*> bases;  // (n, precision)
+  uint64_t basis_clock = 0;
   pma::Server* server = nullptr;
+  std::mutex server_mu;  // creation of the server thread
 };
 
 namespace pma {
@@ -617,93 +633,142 @@ static void ensure_arena(pma_ctx* c) {
   c->arena.init((char*)p, c->budget);
 }
 
+// drop the least recently used basis no request is using; false if there is none
+static bool evict_basis(pma_ctx* c) {
+  auto victim = c->bases.end();
+  for (auto it = c->bases.begin(); it != c->bases.end(); ++it)
+    if (it->second->refs == 0 && (victim == c->bases.end() || it->second->last_use < victim->second->last_use))
+      victim = it;
+  if (victim == c->bases.end()) return false;
+  c->arena.release(victim->second->mem);
+  delete victim->second;
+  c->bases.erase(victim);
+  return true;
+}
+
 static void* arena_alloc(pma_ctx* c, size_t b) {
   ensure_arena(c);
-  void* p = c->arena.alloc(b);
-  if (!p) thr(PMA_E_NOMEM, "device arena exhausted");
-  return p;
+  while (true) {
+    void* p = c->arena.alloc(b);
+    if (p) return p;
+    if (!evict_basis(c)) thr(PMA_E_NOMEM, "device arena exhausted");
+  }
 }
 
 
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-static size_t basis_bytes(int n) {
+static size_t basis_bytes(int n, int prec) {
   const size_t rl = (size_t)round_up(n, 16) * round_up(n, 32);
-  return 2 * Arena::round(rl * 8) + 2 * Arena::round(rl * 4) + 4 * Arena::round(rl * 2) +
-         Arena::round((size_t)n * 8) + Arena::round((size_t)n * 4);
+  if (prec == PMA_FP64) return 2 * Arena::round(rl * 8) + Arena::round((size_t)n * 8);
+  if (prec == PMA_FP32) return 2 * Arena::round(rl * 4) + Arena::round((size_t)n * 4);
+  return 4 * Arena::round(rl * 2) + Arena::round((size_t)n * 4);
 }
 
-static Basis* get_basis(pma_ctx* c, int n) {
-  auto it = c->bases.find(n);
-  if (it != c->bases.end()) return it->second;
+static Basis* get_basis(pma_ctx* c, int n, int prec) {
+  auto key = std::make_pair(n, prec);
+  auto it = c->bases.find(key);
+  if (it != c->bases.end()) {
+    it->second->last_use = ++c->basis_clock;
+    return it->second;
+  }
   if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: split it further");
   std::vector<double> A, B, sig;
   basis_host(n, A, B, sig);
-  Basis* b = new Basis;
+  std::unique_ptr<Basis> b(new Basis);
   b->n = n;
+  b->prec = prec;
   b->rows = round_up(n, 16);
   b->ld = round_up(n, 32);
   const size_t rl = (size_t)b->rows * b->ld;
-  std::vector<double> A64(rl, 0.0), B64(rl, 0.0);
-  std::vector<float> A32(rl, 0.f), B32(rl, 0.f), sig32(n);
-  std::vector<_Float16> Ahi(rl, (_Float16)0.f), Alo(rl, (_Float16)0.f), Bhi(rl, (_Float16)0.f),
-      Blo(rl, (_Float16)0.f);
-  double amax = 0;
-  for (size_t i = 0; i < (size_t)n * n; ++i) amax = std::max(amax, std::fabs(A[i]));
-  b->scale_exp = -(int)std::floor(std::log2(amax));  // scaled maximum in [1, 2)
-  const double sc = std::ldexp(1.0, b->scale_exp);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      const size_t src = (size_t)i * n + j, dst = (size_t)i * b->ld + j;
-      A64[dst] = A[src];
-      B64[dst] = B[src];
-      A32[dst] = (float)A[src];
-      B32[dst] = (float)B[src];
-      const double as = A[src] * sc;
-      Ahi[dst] = (_Float16)as;
-      Alo[dst] = (_Float16)(as - (double)Ahi[dst]);
-      Bhi[dst] = (_Float16)B[src];
-      Blo[dst] = (_Float16)(B[src] - (double)Bhi[dst]);
-    }
-  for (int i = 0; i < n; ++i) sig32[i] = (float)sig[i];
-  b->bytes = basis_bytes(n);
-  char* p = (char*)arena_alloc(c, b->bytes);
-  auto take = [&](size_t sz) {
-    char* q = p;
+  b->bytes = basis_bytes(n, prec);
+  b->mem = (char*)arena_alloc(c, b->bytes);
+  char* p = b->mem;
+  auto put = [&](const void* src, size_t sz) {
+    HIPCHK(hipMemcpy(p, src, sz, hipMemcpyHostToDevice));
+    const void* q = p;
     p += Arena::round(sz);
     return q;
   };
-  b->A64 = (double*)take(rl * 8);
-  b->B64 = (double*)take(rl * 8);
-  b->A32 = (float*)take(rl * 4);
-  b->B32 = (float*)take(rl * 4);
-  b->Ahi = (_Float16*)take(rl * 2);
-  b->Alo = (_Float16*)take(rl * 2);
-  b->Bhi = (_Float16*)take(rl * 2);
-  b->Blo = (_Float16*)take(rl * 2);
-  b->sig64 = (double*)take((size_t)n * 8);
-  b->sig32 = (float*)take((size_t)n * 4);
-  HIPCHK(hipMemcpy(b->A64, A64.data(), rl * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->B64, B64.data(), rl * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->A32, A32.data(), rl * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->B32, B32.data(), rl * 4, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->Ahi, Ahi.data(), rl * 2, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->Alo, Alo.data(), rl * 2, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->Bhi, Bhi.data(), rl * 2, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->Blo, Blo.data(), rl * 2, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->sig64, sig.data(), (size_t)n * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(b->sig32, sig32.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-  c->bases[n] = b;
-  return b;
+  try {
+    if (prec == PMA_FP64) {
+      std::vector<double> A64(rl, 0.0), B64(rl, 0.0);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          A64[(size_t)i * b->ld + j] = A[(size_t)i * n + j];
+          B64[(size_t)i * b->ld + j] = B[(size_t)i * n + j];
+        }
+      b->fwd = put(A64.data(), rl * 8);
+      b->inv = put(B64.data(), rl * 8);
+      b->sig = put(sig.data(), (size_t)n * 8);
+    } else {
+      std::vector<float> sig32(n);
+      for (int i = 0; i < n; ++i) sig32[i] = (float)sig[i];
+      if (prec == PMA_FP32) {
+        std::vector<float> A32(rl, 0.f), B32(rl, 0.f);
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) {
+            A32[(size_t)i * b->ld + j] = (float)A[(size_t)i * n + j];
+            B32[(size_t)i * b->ld + j] = (float)B[(size_t)i * n + j];
+          }
+        b->fwd = put(A32.data(), rl * 4);
+        b->inv = put(B32.data(), rl * 4);
+      } else {
+        // forward matrix pre-scaled by 2^s (largest entry in [1, 2)), both split into fp16 hi + lo
+        double amax = 0;
+        for (size_t i = 0; i < (size_t)n * n; ++i) amax = std::max(amax, std::fabs(A[i]));
+        const int se = -(int)std::floor(std::log2(amax));
+        const double sc = std::ldexp(1.0, se);
+        b->fwd_unscale = (float)std::ldexp(1.0, -se);
+        std::vector<_Float16> Ahi(rl, (_Float16)0.f), Alo(rl, (_Float16)0.f), Bhi(rl, (_Float16)0.f),
+            Blo(rl, (_Float16)0.f);
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) {
+            const size_t src = (size_t)i * n + j, dst = (size_t)i * b->ld + j;
+            const double as = A[src] * sc;
+            Ahi[dst] = (_Float16)as;
+            Alo[dst] = (_Float16)(as - (double)Ahi[dst]);
+            Bhi[dst] = (_Float16)B[src];
+            Blo[dst] = (_Float16)(B[src] - (double)Bhi[dst]);
+          }
+        b->fwd = put(Ahi.data(), rl * 2);
+        b->fwdl = put(Alo.data(), rl * 2);
+        b->inv = put(Bhi.data(), rl * 2);
+        b->invl = put(Blo.data(), rl * 2);
+      }
+      b->sig = put(sig32.data(), (size_t)n * 4);
+    }
+  } catch (...) {
+    c->arena.release(b->mem);
+    throw;
+  }
+  b->last_use = ++c->basis_clock;
+  Basis* raw = b.release();
+  c->bases[key] = raw;
+  return raw;
 }
 
-static size_t new_basis_bytes(pma_ctx* c, const Instance& I) {
+static std::vector<int> distinct_axis_sizes(const Instance& I) {
   std::vector<int> ns;
   for (const auto& s : I.subs)
     for (int k = 0; k < I.dim; ++k)
-      if (!c->bases.count(s.n[k]) && std::find(ns.begin(), ns.end(), s.n[k]) == ns.end()) ns.push_back(s.n[k]);
+      if (std::find(ns.begin(), ns.end(), s.n[k]) == ns.end()) ns.push_back(s.n[k]);
+  return ns;
+}
+
+// arena bytes the instance's bases still need (0 for cached ones); none for forward Euler
+static size_t new_basis_bytes(pma_ctx* c, const Instance& I) {
+  if (I.tm.gamma == 0.0) return 0;
   size_t b = 0;
-  for (int n : ns) b += basis_bytes(n);
+  for (int n : distinct_axis_sizes(I))
+    if (!c->bases.count(std::make_pair(n, I.prec))) b += basis_bytes(n, I.prec);
+  return b;
+}
+
+static size_t all_basis_bytes(const Instance& I) {
+  if (I.tm.gamma == 0.0) return 0;
+  size_t b = 0;
+  for (int n : distinct_axis_sizes(I)) b += basis_bytes(n, I.tm.precision);
   return b;
 }
 
@@ -737,11 +802,26 @@ static void alloc_instance(pma_ctx* c, Instance& I) {
   }
   I.stats_dev = (double*)take(2 * sizeof(double));
   I.bases_used.clear();
-  for (const auto& s : I.subs)
-    for (int k = 0; k < I.dim; ++k) I.bases_used.push_back(get_basis(c, s.n[k]));
+  if (I.tm.gamma > 0) {
+    try {
+      for (int n : distinct_axis_sizes(I)) {
+        Basis* b = get_basis(c, n, I.prec);
+        b->refs++;
+        I.bases_used.push_back(b);
+      }
+    } catch (...) {
+      for (auto* b : I.bases_used) b->refs--;
+      I.bases_used.clear();
+      c->arena.release(I.block);
+      I.block = nullptr;
+      throw;
+    }
+  }
 }
 
 static void free_instance(pma_ctx* c, Instance& I) {
+  for (auto* b : I.bases_used) b->refs--;
+  I.bases_used.clear();
   if (I.block) c->arena.release(I.block);
   I.block = nullptr;
 }
@@ -750,7 +830,8 @@ static void free_instance(pma_ctx* c, Instance& I) {
 // batch: every subdomain of a set of instances (one precision) advanced by shared launches
 // ------------------------------------------------------------------------------------------
 
-static constexpr int kStRows = 4, kStCols = 64;  // stand-alone stencil / Euler tiles
+static constexpr int kStRows = 4, kStCols = 64;     // forward-Euler tiles
+static constexpr int kStTileR = 16, kStTileC = 64;  // stencil tiles (per plane in 3D)
 static constexpr int kRows = 16, kCols = 64, kStrip = 16;  // mode-product tiles
 static constexpr int kPhases = 8;
 
@@ -768,6 +849,26 @@ struct Table {
   void end_sub() { rng.back().count = (int)h.size() - rng.back().first; }
   int size() const { return (int)h.size(); }
 };
+
+template <typename T>
+static void fill_monitor(const pma_monitor& m, MonP<T>& p) {
+  p.kind = m.kind;
+  p.nb = m.nbumps;
+  p.amp = (T)m.amp;
+  p.k = (T)m.k;
+  p.r0 = (T)m.r0;
+  p.r02 = (T)(m.r0 * m.r0);
+  for (int q = 0; q < 3; ++q) {
+    p.c[q] = (T)m.c[q];
+    p.aa[q] = (T)m.amp_axes[q];
+    p.ka[q] = (T)m.k_axes[q];
+  }
+  for (int b = 0; b < 4; ++b) {
+    p.bamp[b] = (T)m.bamp[b];
+    p.bnh[b] = b < m.nbumps ? (T)(-1.0 / (2.0 * m.bw[b] * m.bw[b])) : (T)0;
+    for (int q = 0; q < 3; ++q) p.bc[b][q] = (T)m.bc[b][q];
+  }
+}
 
 // Phases of a step, in launch order:
 //   0 transmission                1 stencil (F)                       2 forward-Euler update
@@ -795,45 +896,40 @@ struct Batch {
   int* d_status = nullptr;
   double* h_resid = nullptr;
   int* h_status = nullptr;
+  size_t pinned_cap = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;  // replay one captured step; false: launch the phases directly
   StepArgs sa{};
 
-  ~Batch() { clear_device(); }
+  size_t dcap = 0;  // capacity of dmem: launch tables live outside the request arena
 
+  ~Batch() {
+    clear_device();
+    if (dmem) hipFree(dmem);
+    if (h_resid) hipHostFree(h_resid);
+    if (h_status) hipHostFree(h_status);
+  }
+
+  // forget the launch set (the table buffer is kept for the next build)
   void clear_device() {
     if (gexec) hipGraphExecDestroy(gexec);
     if (graph) hipGraphDestroy(graph);
     gexec = nullptr;
     graph = nullptr;
-    if (dmem && ctx) ctx->arena.release(dmem);
-    dmem = nullptr;
-    if (h_resid) hipHostFree(h_resid);
-    if (h_status) hipHostFree(h_status);
-    h_resid = nullptr;
-    h_status = nullptr;
+    built = false;
   }
+  bool built = false;
 
-  AxisDev axis_dev(const Basis* b) const {
+  static AxisDev axis_dev(const Basis* b) {
     AxisDev a{};
     a.ld = b->ld;
-    a.fwd_unscale = 1.0f;
-    if (prec == PMA_FP64) {
-      a.fwd = b->A64;
-      a.inv = b->B64;
-      a.sig = b->sig64;
-    } else if (prec == PMA_FP32) {
-      a.fwd = b->A32;
-      a.inv = b->B32;
-      a.sig = b->sig32;
-    } else {
-      a.fwd = b->Ahi;
-      a.fwdl = b->Alo;
-      a.inv = b->Bhi;
-      a.invl = b->Blo;
-      a.sig = b->sig32;
-      a.fwd_unscale = (float)std::ldexp(1.0, -b->scale_exp);
-    }
+    a.fwd = b->fwd;
+    a.fwdl = b->fwdl;
+    a.inv = b->inv;
+    a.invl = b->invl;
+    a.sig = b->sig;
+    a.fwd_unscale = b->fwd_unscale;
     return a;
   }
 
@@ -848,22 +944,8 @@ struct Batch {
     for (size_t q = 0; q < insts.size(); ++q) {
       Instance& I = *insts[q];
       InstDev id{};
-      const pma_monitor& m = I.mon;
-      id.mon.kind = m.kind;
-      id.mon.nb = m.nbumps;
-      id.mon.amp = m.amp;
-      id.mon.k = m.k;
-      id.mon.r0 = m.r0;
-      for (int k = 0; k < 3; ++k) {
-        id.mon.c[k] = m.c[k];
-        id.mon.amp_axes[k] = m.amp_axes[k];
-        id.mon.k_axes[k] = m.k_axes[k];
-      }
-      for (int b = 0; b < 4; ++b) {
-        id.mon.bamp[b] = m.bamp[b];
-        id.mon.bw[b] = m.bw[b];
-        for (int k = 0; k < 3; ++k) id.mon.bc[b][k] = m.bc[b][k];
-      }
+      fill_monitor(I.mon, id.mond);
+      fill_monitor(I.mon, id.monf);
       double vol = 1.0;
       for (int k = 0; k < I.dim; ++k) vol *= I.grid.hi[k] - I.grid.lo[k];
       id.log_vol_theta = std::log(vol / I.theta);
@@ -886,7 +968,7 @@ struct Batch {
             sd.a[k] = I.grid.lo[k];
             sd.h[k] = (I.grid.hi[k] - I.grid.lo[k]) / (I.grid.n[k] - 1);
             sd.gh2[k] = I.tm.gamma / (sd.h[k] * sd.h[k]);
-            if (I.tm.gamma > 0) sd.ax[k] = axis_dev(get_basis(ctx, S.n[k]));
+            if (I.tm.gamma > 0) sd.ax[k] = axis_dev(get_basis(ctx, S.n[k], prec));
           } else {
             sd.a[k] = 0;
             sd.h[k] = 1;
@@ -918,8 +1000,14 @@ struct Batch {
         tr.count = (int)h_trans.size() - tr.first;
         tr_rng.push_back(tr);
         for (int ph = 1; ph < kPhases; ++ph) tab[ph].begin_sub();
-        for (int r = 0; r < R; r += kStRows)
-          for (int c = 0; c < C; c += kStCols) tab[1].h.push_back(int4{gs, r, c, 0});
+        if (I.dim == 2) {
+          for (int r = 0; r < n0; r += kStTileR)
+            for (int c = 0; c < n1; c += kStTileC) tab[1].h.push_back(int4{gs, r, c, 0});
+        } else {
+          for (int i0 = 0; i0 < n0; ++i0)
+            for (int r = 0; r < n1; r += kStTileR)
+              for (int c = 0; c < n2; c += kStTileC) tab[1].h.push_back(int4{gs, i0, r, c});
+        }
         if (I.tm.gamma == 0.0) {
           for (int r = 0; r < R; r += kStRows)
             for (int c = 0; c < C; c += kStCols) tab[2].h.push_back(int4{gs, r, c, 0});
@@ -969,7 +1057,19 @@ struct Batch {
                    Arena::round(h_trans.size() * 16 + 16) + Arena::round(nsub * el) +
                    Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4);
     for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round(tab[ph].h.size() * 16 + 16);
-    dmem = (char*)arena_alloc(ctx, bytes);
+    if (bytes > dcap) {
+      if (dmem) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipFree(dmem));
+        dmem = nullptr;
+      }
+      dcap = std::max(bytes, 2 * dcap);
+      if (hipMalloc((void**)&dmem, dcap) != hipSuccess) {
+        dmem = nullptr;
+        dcap = 0;
+        thr(PMA_E_NOMEM, "launch tables: device allocation failed");
+      }
+    }
     char* p = dmem;
     auto take = [&](size_t sz) {
       char* q = p;
@@ -1001,8 +1101,15 @@ struct Batch {
     std::vector<double> sh(ninst, 0.0);
     for (size_t q = 0; q < ninst; ++q) sh[q] = insts[q]->shift_acc;
     up(d_shift, sh.data(), ninst * 8);
-    HIPCHK(hipHostMalloc((void**)&h_resid, ninst * 8 + 8, 0));
-    HIPCHK(hipHostMalloc((void**)&h_status, ninst * 4 + 4, 0));
+    if (ninst + 1 > pinned_cap) {
+      if (h_resid) hipHostFree(h_resid);
+      if (h_status) hipHostFree(h_status);
+      h_resid = nullptr;
+      h_status = nullptr;
+      pinned_cap = std::max<size_t>(64, 2 * (ninst + 1));
+      HIPCHK(hipHostMalloc((void**)&h_resid, pinned_cap * 8, 0));
+      HIPCHK(hipHostMalloc((void**)&h_status, pinned_cap * 4, 0));
+    }
     sa.subs = d_subs;
     sa.insts = d_insts;
     sa.dc = d_dc;
@@ -1010,6 +1117,7 @@ struct Batch {
     sa.shift_acc = d_shift;
     sa.status = d_status;
     HIPCHK(hipStreamSynchronize(st));
+    built = true;
   }
 
   // launch one phase over the table range [first, first + count)
@@ -1122,8 +1230,8 @@ struct Batch {
 
   void step(bool plain) {
     hipStream_t st = ctx->stream;
-    if (plain) {
-      launch_step(true, st);
+    if (plain || !use_graph) {
+      launch_step(plain, st);
     } else {
       if (!gexec) capture();
       HIPCHK(hipGraphLaunch(gexec, st));
@@ -1204,7 +1312,7 @@ static double now_s() {
 }
 
 static void save_shifts(Batch& B) {
-  if (!B.dmem || B.insts.empty()) return;
+  if (!B.built || B.insts.empty()) return;
   std::vector<double> sh(B.insts.size());
   HIPCHK(hipMemcpy(sh.data(), B.d_shift, sh.size() * 8, hipMemcpyDeviceToHost));
   for (size_t q = 0; q < sh.size(); ++q) B.insts[q]->shift_acc = sh[q];
@@ -1302,9 +1410,7 @@ struct Server {
     all.clear();
   }
 
-  size_t request_bytes(const Instance& I) {
-    return Arena::round(instance_bytes(I)) + new_basis_bytes(ctx, I) + (1 << 16);
-  }
+  size_t request_bytes(const Instance& I) { return Arena::round(instance_bytes(I)) + new_basis_bytes(ctx, I); }
 
   // admit queued requests in arrival order while they fit (no overtaking); caller holds mu
   void admit_locked() {
@@ -1365,18 +1471,26 @@ struct Server {
     }
   }
 
+  // membership changed: rebuild the launch tables in place (direct launches, no graph: the set of
+  // requests changes every few milliseconds under load)
   void rebuild() {
     hipStream_t st = ctx->stream;
     for (int p = 0; p < 3; ++p) {
       if (batch[p]) save_shifts(*batch[p]);
-      batch[p].reset();
       std::vector<Instance*> v;
       for (auto* I : running)
         if (I->prec == p) v.push_back(I);
-      if (v.empty()) continue;
-      batch[p].reset(new Batch);
+      if (v.empty()) {
+        if (batch[p]) {
+          batch[p]->clear_device();
+          batch[p]->insts.clear();
+        }
+        continue;
+      }
+      if (!batch[p]) batch[p].reset(new Batch);
       batch[p]->ctx = ctx;
       batch[p]->prec = p;
+      batch[p]->use_graph = false;
       batch[p]->insts = v;
       batch[p]->build();
       for (size_t q = 0; q < v.size(); ++q)
@@ -1396,14 +1510,14 @@ struct Server {
     chunk = std::max(0, std::min(chunk, 8));  // bounded so arrivals are admitted promptly
     for (int k = 0; k < chunk; ++k)
       for (int p = 0; p < 3; ++p)
-        if (batch[p]) batch[p]->step(false);
+        if (batch[p] && !batch[p]->insts.empty()) batch[p]->step(false);
     for (auto* I : running) I->steps_done += chunk;
     for (int p = 0; p < 3; ++p)
-      if (batch[p]) batch[p]->read_progress();
+      if (batch[p] && !batch[p]->insts.empty()) batch[p]->read_progress();
     HIPCHK(hipStreamSynchronize(st));
     std::vector<Instance*> done;
     for (int p = 0; p < 3; ++p) {
-      if (!batch[p]) continue;
+      if (!batch[p] || batch[p]->insts.empty()) continue;
       for (size_t q = 0; q < batch[p]->insts.size(); ++q) {
         Instance* I = batch[p]->insts[q];
         const int code = status_code(batch[p]->h_status[q]);
@@ -1415,7 +1529,7 @@ struct Server {
     }
     if (!done.empty()) {
       for (int p = 0; p < 3; ++p)
-        if (batch[p]) save_shifts(*batch[p]);
+        if (batch[p] && !batch[p]->insts.empty()) save_shifts(*batch[p]);
       for (auto* I : done) {
         if (I->status != PMA_OK) continue;
         Batch& B = *batch[I->prec];
@@ -1432,8 +1546,12 @@ struct Server {
         I->min_cell = I->stats_host[1];
         if (!(I->min_det > 0) || !(I->min_cell > 0)) I->status = PMA_E_TANGLED;
       }
-      // release the finished requests' memory only after the device is done with it
-      for (auto& b : batch) b.reset();
+      // the finished requests' memory is released below, after the device is done with it
+      for (auto& b : batch)
+        if (b) {
+          b->clear_device();
+          b->insts.clear();
+        }
       dirty = true;
     }
     std::lock_guard<std::mutex> g(mu);
@@ -1444,12 +1562,7 @@ struct Server {
       free_instance(ctx, *I);
       finished++;
     }
-    if (!queue.empty()) {
-      if (!dirty)
-        for (int p = 0; p < 3; ++p)
-          if (batch[p]) save_shifts(*batch[p]);
-      admit_locked();
-    }
+    if (!queue.empty()) admit_locked();
   }
 };
 
@@ -1508,7 +1621,7 @@ int pma_destroy(pma_ctx* c) {
   }
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
-  for (auto& kv : c->bases) delete kv.second;
+  for (auto& kv : c->bases) delete kv.second;  // memory goes with the arena
   c->bases.clear();
   if (c->arena_mem) {
     if (c->arena_from_cb && c->free_cb) c->free_cb(c->arena_mem, (void*)c->stream, c->alloc_user);
@@ -1852,26 +1965,53 @@ int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, dou
   std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
   *nph = kPhases;
   Batch& B = *P->batch;
-  hipStream_t st = P->ctx->stream;
-  std::vector<hipEvent_t> ev(kPhases + 1);
-  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  std::vector<double> acc(kPhases, 0.0);
-  for (int k = 0; k < nsteps; ++k) {
-    HIPCHK(hipEventRecord(ev[0], st));
+  pma_ctx* c = P->ctx;
+  hipStream_t st = c->stream;
+  // snapshot the state every phase may change (phi, accumulated shifts), restored afterwards
+  size_t snap = 0;
+  for (auto& I : P->insts)
+    for (auto& sub : I->subs) snap += Arena::round(sub_nodes(sub) * I->elem());
+  snap += Arena::round(P->insts.size() * 8);
+  char* save = (char*)arena_alloc(c, snap);
+  auto copy_state = [&](bool out) {
+    char* q = save;
+    for (auto& I : P->insts)
+      for (size_t s = 0; s < I->subs.size(); ++s) {
+        const size_t b = sub_nodes(I->subs[s]) * I->elem();
+        HIPCHK(hipMemcpyAsync(out ? (void*)q : I->phi[s], out ? I->phi[s] : (void*)q, b, hipMemcpyDeviceToDevice, st));
+        q += Arena::round(b);
+      }
+    HIPCHK(hipMemcpyAsync(out ? (void*)q : (void*)B.d_shift, out ? (void*)B.d_shift : (void*)q, P->insts.size() * 8,
+                          hipMemcpyDeviceToDevice, st));
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    copy_state(true);
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    // each phase alone, nsteps launches back to back between two events on the kernels' stream
     for (int ph = 0; ph < kPhases; ++ph) {
-      B.launch_phase(ph, P->plain, st);
-      HIPCHK(hipEventRecord(ev[ph + 1], st));
-    }
-    HIPCHK(hipEventSynchronize(ev[kPhases]));
-    for (int ph = 0; ph < kPhases; ++ph) {
+      B.launch_phase(ph, P->plain, st);  // warm
+      HIPCHK(hipEventRecord(e0, st));
+      for (int k = 0; k < nsteps; ++k) B.launch_phase(ph, P->plain, st);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
       float t = 0;
-      HIPCHK(hipEventElapsedTime(&t, ev[ph], ev[ph + 1]));
-      acc[ph] += t;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      ms[ph] = t / nsteps;
     }
+    copy_state(false);
+    HIPCHK(hipStreamSynchronize(st));
+  } catch (Err&) {
+    hipStreamSynchronize(st);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    c->arena.release(save);
+    throw;
   }
-  for (auto& e : ev) hipEventDestroy(e);
-  for (auto& I : P->insts) I->steps_done += nsteps;
-  for (int ph = 0; ph < kPhases; ++ph) ms[ph] = acc[ph] / nsteps;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->arena.release(save);
   std::vector<double> fl(kPhases, 0.0), by(kPhases, 0.0);
   B.phase_work(fl.data(), by.data());
   for (int ph = 0; ph < kPhases; ++ph) {
@@ -1929,16 +2069,17 @@ int pma_submit(pma_ctx* c, const pma_request* req, uint64_t* ticket) {
   I->tm = req->time;
   I->arrival_s = req->arrival_s;
   build_plan(*I);
+  // budget check without the context lock (the server thread holds it while it steps): the
+  // bound counts every DCT basis the request uses, cached or not
+  const size_t need = Arena::round(instance_bytes(*I)) + all_basis_bytes(*I);
+  if (need > c->budget) return fail(PMA_E_BUDGET, "request needs %zu bytes, budget is %zu", need, c->budget);
   {
-    std::lock_guard<std::recursive_mutex> g(c->mu);
-    HIPCHK(hipSetDevice(c->device));
+    std::lock_guard<std::mutex> g(c->server_mu);
     if (!c->server) {
       c->server = new Server;
       c->server->ctx = c;
       c->server->start();
     }
-    const size_t need = c->server->request_bytes(*I);
-    if (need > c->budget) return fail(PMA_E_BUDGET, "request needs %zu bytes, budget is %zu", need, c->budget);
   }
   Server* s = c->server;
   {
