@@ -116,26 +116,6 @@ __device__ inline bool finite_(T x) { return isfinite(x); }
 // K1/K2: stencil + monitor + log (the right-hand side F), Neumann ghosts by mirroring.
 // ------------------------------------------------------------------------------------------
 
-// F from the 3 x 3 (2D) neighbourhood of node (i, j): c centre, xm/xp along axis 0, ym/yp along
-// axis 1, mm/mp/pm/pp the diagonal corners; r* are 1/(2h), 1/h^2 and 1/(4 h h) factors
-template <typename T>
-__device__ inline T rhs2(const SubDev& S, const MonP<T>& mon, T lvt, T a0, T a1, T h0, T h1, int i, int j, T c,
-                         T xm, T xp, T ym, T yp, T mm, T mp, T pm, T pp, T r2h0, T r2h1, T rh00, T rh11, T r4h01,
-                         int* status) {
-  const T gx = (xp - xm) * r2h0;
-  const T gy = (yp - ym) * r2h1;
-  const T hxx = (xp - T(2) * c + xm) * rh00;
-  const T hyy = (yp - T(2) * c + ym) * rh11;
-  const T hxy = (pp - pm - mp + mm) * r4h01;
-  const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
-  const T x0 = a0 + T(S.off[0] + i) * h0 + gx;
-  const T x1 = a1 + T(S.off[1] + j) * h1 + gy;
-  const T f = lvt + log_rho_det(rho_excess(mon, 2, x0, x1, T(0)), e);
-  if (!(T(1) + e > T(0))) atomicOr(&status[S.inst], ST_TANGLED);
-  else if (!finite_(f)) atomicOr(&status[S.inst], ST_NONFINITE);
-  return f;
-}
-
 // mirror an index across a face (Neumann ghost), then keep it inside the array (rows beyond the
 // array's end only feed outputs that are not stored)
 __device__ inline int mirror_clamp(int i, int n) {
@@ -144,27 +124,93 @@ __device__ inline int mirror_clamp(int i, int n) {
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
 
-// Stencil into F.  A tile is 16 rows x 64 columns of one plane (2D: the array; 3D: plane i0 of
-// the [n0][n1][n2] array, rows = i1, columns = i2); it is staged with a one-node halo in LDS
-// (three planes in 3D), mirror ghosts applied while loading, and each thread computes 4 nodes.
-// tile = (sub, row0, col0, 0) in 2D, (sub, i0, row0, col0) in 3D.
+// Per-workgroup constants of a subdomain, copied into registers once: the stores to F below
+// could otherwise alias the descriptor tables, forcing a reload of every field per node.
+template <typename T>
+struct StencilCtx {
+  const MonP<T>* __restrict__ mon;  // stays in global memory (a private copy would go to scratch)
+  T lvt, a0, a1, a2, h0, h1, h2;
+  int n0, n1, n2, off0, off1, off2, art, inst;
+  const int* own0;
+  const int* own1;
+  const int* own2;
+  int p1, p2, first;
+};
+
+// phi at an artificial-boundary node (li, lj[, lk]) of a subdomain, read from its owner: the value
+// the parallel transmission condition gives the node at the start of the step
+template <typename T>
+__device__ inline T owner_phi(const StencilCtx<T>& K, const SubDev* __restrict__ subs, int dim, int li, int lj,
+                              int lk) {
+  const int g0 = K.off0 + li, g1 = K.off1 + lj, g2 = K.off2 + lk;
+  int q = K.own0[g0] * K.p1 + K.own1[g1];
+  if (dim == 3) q = q * K.p2 + K.own2[g2];
+  const SubDev& O = subs[K.first + q];
+  const long idx = dim == 2 ? (long)(g0 - O.off[0]) * O.n[1] + (g1 - O.off[1])
+                            : ((long)(g0 - O.off[0]) * O.n[1] + (g1 - O.off[1])) * O.n[2] + (g2 - O.off[2]);
+  return ((const T*)O.phi)[idx];
+}
+
+template <typename T>
+__device__ inline T finish_rhs(const StencilCtx<T>& K, int* status, T e, T x0, T x1, T x2, int dim) {
+  const T f = K.lvt + log_rho_det(rho_excess(*K.mon, dim, x0, x1, x2), e);
+  if (!(T(1) + e > T(0))) atomicOr(&status[K.inst], ST_TANGLED);
+  else if (!finite_(f)) atomicOr(&status[K.inst], ST_NONFINITE);
+  return f;
+}
+
+// Stencil into F.  A tile is staged with a one-node halo in LDS, mirror ghosts applied while
+// loading.  2D: 16 rows x 64 columns, 4 nodes per thread, artificial faces read from their owners;
+// tile = (sub, row0, col0, 0).  3D: 16 rows (i1) x up to 72 columns (i2) of plane i0 with the two
+// neighbouring planes; tile = (sub, i0, row0, col0).
 template <typename T>
 __global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
   constexpr int TR = 16, TC = 64, HR = TR + 2, HC = TC + 2;
-  __shared__ T sm[3][HR][HC];
+  __shared__ T sm3_raw[3 * HR * 74];  // 3D: three halo planes of 18 x 74; 2D uses the front
+  T(*sm)[HR][HC] = reinterpret_cast<T(*)[HR][HC]>(&sm3_raw[0]);
   if ((int)blockIdx.x >= ntiles) return;
   const int4 tl = tiles[blockIdx.x];
-  const SubDev& S = sa.subs[tl.x];
-  const InstDev& I = sa.insts[S.inst];
-  const T* __restrict__ phi = (const T*)S.phi;
-  T* __restrict__ F = (T*)S.F;
+  StencilCtx<T> K;
+  const T* __restrict__ phi;
+  T* __restrict__ F;
+  int dim;
+  {
+    const SubDev& S = sa.subs[tl.x];
+    const InstDev& I = sa.insts[S.inst];
+    K.mon = &mon_of(I, T(0));
+    K.lvt = T(I.log_vol_theta);
+    K.a0 = T(S.a[0]);
+    K.a1 = T(S.a[1]);
+    K.a2 = T(S.a[2]);
+    K.h0 = T(S.h[0]);
+    K.h1 = T(S.h[1]);
+    K.h2 = T(S.h[2]);
+    K.n0 = S.n[0];
+    K.n1 = S.n[1];
+    K.n2 = S.n[2];
+    K.off0 = S.off[0];
+    K.off1 = S.off[1];
+    K.off2 = S.off[2];
+    K.art = S.art;
+    K.inst = S.inst;
+    K.own0 = I.own[0];
+    K.own1 = I.own[1];
+    K.own2 = I.own[2];
+    K.p1 = I.parts[1];
+    K.p2 = I.parts[2];
+    K.first = I.first_sub;
+    phi = (const T*)S.phi;
+    F = (T*)S.F;
+    dim = S.dim;
+  }
+  int* __restrict__ status = sa.status;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  const T h0 = T(S.h[0]), h1 = T(S.h[1]), h2 = T(S.h[2]);
-  if (S.dim == 2) {
-    const int n0 = S.n[0], n1 = S.n[1];
+  const T h0 = K.h0, h1 = K.h1, h2 = K.h2;
+  if (dim == 2) {
+    const int n0 = K.n0, n1 = K.n1;
     const int row0 = tl.y, col0 = tl.z;
-    if (row0 >= 1 && row0 + TR < n0 && col0 >= 1 && col0 + TC < n1) {
-      // interior tile: the halo never crosses a face
+    if (row0 >= 2 && row0 + TR + 1 < n0 && col0 >= 2 && col0 + TC + 1 < n1) {
+      // interior tile: the halo touches no face of the subdomain
       const T* base = phi + (long)(row0 - 1) * n1 + (col0 - 1);
       for (int idx = tid; idx < HR * HC; idx += 256) {
         const int r = idx / HC, c = idx - r * HC;
@@ -176,78 +222,108 @@ __global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ t
         const int gi = mirror_clamp(row0 + r - 1, n0), gj = mirror_clamp(col0 + c - 1, n1);
         sm[0][r][c] = phi[(long)gi * n1 + gj];
       }
+      if (K.own0 && K.art) {
+        // artificial faces inside the halo take their owners' values (one line per face)
+        __syncthreads();
+        for (int idx = tid; idx < 2 * HC + 2 * HR; idx += 256) {
+          int r, c;
+          bool on;
+          if (idx < 2 * HC) {  // rows at local index 0 / n0 - 1
+            const int li = idx < HC ? 0 : n0 - 1;
+            r = li - (row0 - 1);
+            c = idx < HC ? idx : idx - HC;
+            on = is_artificial(K.art, 0, li, n0) && r >= 0 && r < HR;
+          } else {             // columns at local index 0 / n1 - 1
+            const int t = idx - 2 * HC;
+            const int lj = t < HR ? 0 : n1 - 1;
+            c = lj - (col0 - 1);
+            r = t < HR ? t : t - HR;
+            on = is_artificial(K.art, 1, lj, n1) && c >= 0 && c < HC;
+          }
+          if (on) {
+            const int li = mirror_clamp(row0 + r - 1, n0), lj = mirror_clamp(col0 + c - 1, n1);
+            if (is_artificial(K.art, 0, li, n0) || is_artificial(K.art, 1, lj, n1))
+              sm[0][r][c] = owner_phi(K, sa.subs, 2, li, lj, 0);
+          }
+        }
+      }
     }
     __syncthreads();
     const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
     const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
-    const MonP<T>& mon = mon_of(I, T(0));
-    const T lvt = T(I.log_vol_theta), a0 = T(S.a[0]), a1 = T(S.a[1]);
     const int j = col0 + tx;
     if (j >= n1) return;
+    const bool artj = is_artificial(K.art, 1, j, n1);
+    const T x1b = K.a1 + T(K.off1 + j) * h1;
     for (int m = 0; m < TR / 4; ++m) {
       const int rr = ty + 4 * m, i = row0 + rr;
       if (i >= n0) break;
       const long v = (long)i * n1 + j;
-      if (is_artificial(S.art, 0, i, n0) || is_artificial(S.art, 1, j, n1)) {
+      if (artj || is_artificial(K.art, 0, i, n0)) {
         F[v] = T(0);
         continue;
       }
       const int r = rr + 1, c = tx + 1;
-      F[v] = rhs2<T>(S, mon, lvt, a0, a1, h0, h1, i, j, sm[0][r][c], sm[0][r - 1][c], sm[0][r + 1][c], sm[0][r][c - 1], sm[0][r][c + 1],
-                     sm[0][r - 1][c - 1], sm[0][r - 1][c + 1], sm[0][r + 1][c - 1], sm[0][r + 1][c + 1], r2h0, r2h1,
-                     rh00, rh11, r4h01, sa.status);
+      const T cc = sm[0][r][c];
+      const T xm = sm[0][r - 1][c], xp = sm[0][r + 1][c], ym = sm[0][r][c - 1], yp = sm[0][r][c + 1];
+      const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
+      const T hxx = (xp - T(2) * cc + xm) * rh00;
+      const T hyy = (yp - T(2) * cc + ym) * rh11;
+      const T hxy = (sm[0][r + 1][c + 1] - sm[0][r + 1][c - 1] - sm[0][r - 1][c + 1] + sm[0][r - 1][c - 1]) * r4h01;
+      const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
+      const T x0 = K.a0 + T(K.off0 + i) * h0 + gx;
+      F[v] = finish_rhs(K, status, e, x0, x1b + gy, T(0), 2);
     }
     return;
   }
-  const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
+  // 3D: tile = 16 rows (i1) x up to 72 columns (i2) of plane i0, three halo planes in LDS; the
+  // artificial nodes were filled by the transmission gather before this launch
+  constexpr int TC3 = 72, HC3 = TC3 + 2;
+  T(*sm3)[HR][HC3] = reinterpret_cast<T(*)[HR][HC3]>(&sm3_raw[0]);
+  const int n0 = K.n0, n1 = K.n1, n2 = K.n2;
   const int i0 = tl.y, row0 = tl.z, col0 = tl.w;
-  for (int idx = tid; idx < 3 * HR * HC; idx += 256) {
-    const int p = idx / (HR * HC), rem = idx - p * (HR * HC);
-    const int r = rem / HC, c = rem - r * HC;
-    const int gp = mirror_clamp(i0 + p - 1, n0), gi = mirror_clamp(row0 + r - 1, n1), gj = mirror_clamp(col0 + c - 1, n2);
-    sm[p][r][c] = phi[((long)gp * n1 + gi) * n2 + gj];
+  const int w = min(TC3, n2 - col0);
+  for (int idx = tid; idx < 3 * HR * HC3; idx += 256) {
+    const int p = idx / (HR * HC3), rem = idx - p * (HR * HC3);
+    const int r = rem / HC3, c = rem - r * HC3;
+    const int gp = mirror_clamp(i0 + p - 1, n0), gi = mirror_clamp(row0 + r - 1, n1),
+              gj = mirror_clamp(col0 + c - 1, n2);
+    sm3[p][r][c] = phi[((long)gp * n1 + gi) * n2 + gj];
   }
   __syncthreads();
   const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1), r2h2 = T(1) / (T(2) * h2);
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), rh22 = T(1) / (h2 * h2);
   const T r4h01 = T(1) / (T(4) * h0 * h1), r4h02 = T(1) / (T(4) * h0 * h2), r4h12 = T(1) / (T(4) * h1 * h2);
-  const MonP<T>& mon = mon_of(I, T(0));
-  const T lvt = T(I.log_vol_theta), a0 = T(S.a[0]), a1 = T(S.a[1]), a2 = T(S.a[2]);
-  const int k = col0 + tx;
-  if (k >= n2) return;
-  const bool art0 = is_artificial(S.art, 0, i0, n0);
-  for (int m = 0; m < TR / 4; ++m) {
-    const int rr = ty + 4 * m, j = row0 + rr;
-    if (j >= n1) break;
+  const bool art0 = is_artificial(K.art, 0, i0, n0);
+  const T x0b = K.a0 + T(K.off0 + i0) * h0;
+  const int rows = min(TR, n1 - row0);
+  for (int idx = tid; idx < rows * w; idx += 256) {
+    const int rr = idx / w, cc0 = idx - rr * w;
+    const int j = row0 + rr, k = col0 + cc0;
     const long v = ((long)i0 * n1 + j) * n2 + k;
-    if (art0 || is_artificial(S.art, 1, j, n1) || is_artificial(S.art, 2, k, n2)) {
+    if (art0 || is_artificial(K.art, 1, j, n1) || is_artificial(K.art, 2, k, n2)) {
       F[v] = T(0);
       continue;
     }
-    const int r = rr + 1, c = tx + 1;
-    const T cc = sm[1][r][c];
-    const T xm = sm[0][r][c], xp = sm[2][r][c];
-    const T ym = sm[1][r - 1][c], yp = sm[1][r + 1][c];
-    const T zm = sm[1][r][c - 1], zp = sm[1][r][c + 1];
+    const int r = rr + 1, c = cc0 + 1;
+    const T cc = sm3[1][r][c];
+    const T xm = sm3[0][r][c], xp = sm3[2][r][c];
+    const T ym = sm3[1][r - 1][c], yp = sm3[1][r + 1][c];
+    const T zm = sm3[1][r][c - 1], zp = sm3[1][r][c + 1];
     const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1, gz = (zp - zm) * r2h2;
     const T a = (xp - T(2) * cc + xm) * rh00;
     const T b = (yp - T(2) * cc + ym) * rh11;
     const T q = (zp - T(2) * cc + zm) * rh22;
-    const T p = (sm[2][r + 1][c] - sm[2][r - 1][c] - sm[0][r + 1][c] + sm[0][r - 1][c]) * r4h01;
-    const T rx = (sm[2][r][c + 1] - sm[2][r][c - 1] - sm[0][r][c + 1] + sm[0][r][c - 1]) * r4h02;
-    const T sy = (sm[1][r + 1][c + 1] - sm[1][r + 1][c - 1] - sm[1][r - 1][c + 1] + sm[1][r - 1][c - 1]) * r4h12;
+    const T p = (sm3[2][r + 1][c] - sm3[2][r - 1][c] - sm3[0][r + 1][c] + sm3[0][r - 1][c]) * r4h01;
+    const T rx = (sm3[2][r][c + 1] - sm3[2][r][c - 1] - sm3[0][r][c + 1] + sm3[0][r][c - 1]) * r4h02;
+    const T sy = (sm3[1][r + 1][c + 1] - sm3[1][r + 1][c - 1] - sm3[1][r - 1][c + 1] + sm3[1][r - 1][c - 1]) * r4h12;
     // det(I + H) - 1 = tr H + (sum of principal 2x2 minors) + det H
     const T tr = a + b + q;
     const T m2 = (a * b - p * p) + (a * q - rx * rx) + (b * q - sy * sy);
     const T d3 = a * (b * q - sy * sy) - p * (p * q - sy * rx) + rx * (p * sy - b * rx);
-    const T e = tr + m2 + d3;
-    const T x0 = a0 + T(S.off[0] + i0) * h0 + gx;
-    const T x1 = a1 + T(S.off[1] + j) * h1 + gy;
-    const T x2 = a2 + T(S.off[2] + k) * h2 + gz;
-    const T f = lvt + log_rho_det(rho_excess(mon, 3, x0, x1, x2), e);
-    F[v] = f;
-    if (!(T(1) + e > T(0))) atomicOr(&sa.status[S.inst], ST_TANGLED);
-    else if (!finite_(f)) atomicOr(&sa.status[S.inst], ST_NONFINITE);
+    const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
+    const T x2 = K.a2 + T(K.off2 + k) * h2 + gz;
+    F[v] = finish_rhs(K, status, tr + m2 + d3, x0b + gx, x1, x2, 3);
   }
 }
 
@@ -372,8 +448,7 @@ template <> struct Op<PREC_F64> {
 
 // acc += rows of the LDS operand (16 x ld) times basis rows (as columns of B), and the mirror
 // image.  Basis fragments come from L2: four k steps are requested before any is used so their
-// latencies overlap (ld is a multiple of 32, so every group of four is complete for fp16 and a
-// multiple of four steps for the 4-deep products).
+// latencies overlap (deeper groups cost occupancy on the larger batches without helping).
 template <int KIND>
 __device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, float sc,
                                         const void* bh, const void* bl, int brow, int l16, int g) {
@@ -520,10 +595,16 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const T isc = T(1) / T(sc);
   double part = 0.0;
   if (cb * 16 < C) {
-    typename O::acc_t acc = {0, 0, 0, 0};
-    mma_lds_by_basis<KIND>(acc, lds, ld, sc, A.inv, A.invl, cb * 16 + l16, l16, g);
     T* __restrict__ phi = (T*)S.phi;
     const int c = cb * 16 + l16;
+    // the update's phi values are requested before the product so their latency overlaps it
+    T old[4];
+    for (int q = 0; q < 4; ++q) {
+      const int r = row0 + O::crow(g, q);
+      old[q] = (r < R && c < C) ? phi[(long)r * C + c] : T(0);
+    }
+    typename O::acc_t acc = {0, 0, 0, 0};
+    mma_lds_by_basis<KIND>(acc, lds, ld, sc, A.inv, A.invl, cb * 16 + l16, l16, g);
     bool bad = false;
     for (int q = 0; q < 4; ++q) {
       const int r = row0 + O::crow(g, q);
@@ -540,7 +621,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
         if (live) {
           const T val = acc[q] * isc;
           const T u = dt * val;
-          phi[(long)r * C + c] += dt * (val - shift);
+          phi[(long)r * C + c] = old[q] + dt * (val - shift);
           part += w * (double)u * (double)u;
           bad |= !finite_(u);
         }
@@ -603,6 +684,27 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   typename O::acc_t acc[MAXRB];
   const void* b1h = (PAIR || !inv) ? A.fwd : A.inv;
   const void* b1l = (PAIR || !inv) ? A.fwdl : A.invl;
+  // PAIR: spectral factors of this lane's coefficients, requested before the product
+  T sig0[PAIR ? MAXRB * 4 : 1];
+  T rest = T(0);
+  if constexpr (PAIR) {
+    const T* s0 = (const T*)S.ax[0].sig;
+    const T* s1 = (const T*)S.ax[1].sig;
+    const T* s2 = (const T*)S.ax[2].sig;
+    if (c < ncol) {
+      if (S.dim == 2) rest = T(S.gh2[1]) * s1[c];
+      else {
+        const int k1 = c / S.n[2], k2 = c - (c / S.n[2]) * S.n[2];
+        rest = T(S.gh2[1]) * s1[k1] + T(S.gh2[2]) * s2[k2];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t)
+      for (int q = 0; q < 4; ++q) {
+        const int i = (wave + 4 * t) * 16 + O::crow(g, q);
+        sig0[t * 4 + q] = i < K ? s0[i] : T(0);
+      }
+  }
   const T us1 = ((PAIR || !inv) ? T(A.fwd_unscale) : T(1)) / T(sc);
 #pragma unroll
   for (int t = 0; t < MAXRB; ++t) {
@@ -622,18 +724,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
     }
   } else {
     // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2
-    const T* s0 = (const T*)S.ax[0].sig;
-    const T* s1 = (const T*)S.ax[1].sig;
-    const T* s2 = (const T*)S.ax[2].sig;
-    const T g0 = T(S.gh2[0]), g1 = T(S.gh2[1]), g2 = T(S.gh2[2]);
-    T rest = T(0);
-    if (c < ncol) {
-      if (S.dim == 2) rest = g1 * s1[c];
-      else {
-        const int k1 = c / S.n[2], k2 = c - (c / S.n[2]) * S.n[2];
-        rest = g1 * s1[k1] + g2 * s2[k2];
-      }
-    }
+    const T g0 = T(S.gh2[0]);
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
       const int rb = wave + 4 * t;
@@ -643,7 +734,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
         if (rb < nrb && i < K && c < ncol) {
           const T val = acc[t][q] * us1;
           if (i == 0 && c == 0) ((T*)sa.dc)[tl.x] = val;
-          y = val / (T(1) + g0 * s0[i] + rest);
+          y = val / (T(1) + g0 * sig0[t * 4 + q] + rest);
         }
         acc[t][q] = y;
       }

@@ -831,7 +831,7 @@ static void free_instance(pma_ctx* c, Instance& I) {
 // ------------------------------------------------------------------------------------------
 
 static constexpr int kStRows = 4, kStCols = 64;     // forward-Euler tiles
-static constexpr int kStTileR = 16, kStTileC = 64;  // stencil tiles (per plane in 3D)
+static constexpr int kStTileR = 16, kStTileC = 64, kStTileC3 = 72;  // stencil tiles (3D: per plane)
 static constexpr int kRows = 16, kCols = 64, kStrip = 16;  // mode-product tiles
 static constexpr int kPhases = 8;
 
@@ -956,6 +956,11 @@ struct Batch {
       // node is refilled from the same instance (transmission); held Dirichlet data of a lone
       // subdomain would be left behind by the shift
       id.pin = (I.tm.gamma > 0 && !I.single_sub_mode) ? 1 : 0;
+      // 2D stencils read artificial-boundary values from their owners; 3D runs the gather first
+      for (int k = 0; k < 3; ++k) {
+        id.own[k] = (!I.single_sub_mode && I.dim == 2 && k < I.dim) ? I.own_dev[k] : nullptr;
+        id.parts[k] = I.parts[k];
+      }
       h_insts.push_back(id);
       for (size_t s = 0; s < I.subs.size(); ++s) {
         const SubHost& S = I.subs[s];
@@ -1006,7 +1011,7 @@ struct Batch {
         } else {
           for (int i0 = 0; i0 < n0; ++i0)
             for (int r = 0; r < n1; r += kStTileR)
-              for (int c = 0; c < n2; c += kStTileC) tab[1].h.push_back(int4{gs, i0, r, c});
+              for (int c = 0; c < n2; c += kStTileC3) tab[1].h.push_back(int4{gs, i0, r, c});
         }
         if (I.tm.gamma == 0.0) {
           for (int r = 0; r < R; r += kStRows)
@@ -1178,8 +1183,27 @@ struct Batch {
       for (int s = 0; s < nsub; ++s) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
   }
 
+  // 2D stencils read artificial-boundary values from their owners, so only 3D subdomains need the
+  // gather before the stencil (all of them are refreshed before the glue)
   void launch_step(bool plain, hipStream_t st) {
-    for (int ph = 0; ph < kPhases; ++ph) launch_phase(ph, plain, st);
+    launch_gather3(plain, st);
+    for (int ph = 1; ph < kPhases; ++ph) launch_phase(ph, plain, st);
+  }
+
+  void launch_gather3(bool plain, hipStream_t st) {
+    const int nsub = (int)h_subs.size();
+    int s = 0;
+    while (s < nsub) {
+      if (h_subs[s].dim != 3) {
+        ++s;
+        continue;
+      }
+      int e = s + 1;
+      while (e < nsub && h_subs[e].dim == 3 && !plain) ++e;
+      const int f = tr_rng[s].first, l = tr_rng[e - 1].first + tr_rng[e - 1].count;
+      if (l > f) HIPCHK(launch_transmit(prec, d_subs, d_tr + f, l - f, st));
+      s = e;
+    }
   }
 
   // algorithmic work per step of each phase: 2 M N K flops per product; compulsory bytes with
