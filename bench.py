@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp16_TF": 2500.0, "fp32_TF": 157.3, "fp64_TF": 78.6}
 MFMA_PEAK = {"split16": PEAK["fp16_TF"], "fp32": PEAK["fp32_TF"], "fp64": PEAK["fp64_TF"]}
-KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil_kernel", "euler": "euler_kernel",
+KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil2_kernel / stencil3_kernel", "euler": "euler_kernel",
           "fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel<single>", "pair0": "strip_kernel<pair>",
           "inv_mid": "strip_kernel<single>", "inv_last": "inv_last_kernel"}
 
@@ -39,11 +39,15 @@ def nodes_of(ws):
     return sum(math.prod(w["grid"]["n"]) for w in ws)
 
 
-def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0):
-    """Resident plan: warmup steps, then exactly `steps` timed steps bracketed by synchronize."""
+def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0, tune=False):
+    """Resident plan: warmup steps, then exactly `steps` timed steps bracketed by synchronize.
+    tune: pick the stencil's launch shape with the plan's autotuner first (outside the timing)."""
     import torch
     plan = binding.Plan(ctx, ws, prec, exec_)
+    march = None
     try:
+        if tune:
+            march, _ = plan.autotune(10)
         plan.step(warmup)
         plan.sync()
         torch.cuda.synchronize()
@@ -57,7 +61,8 @@ def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0):
     finally:
         plan.close()
     return {"updates_per_s": nodes_of(ws) * steps / dt, "ms_per_step": 1e3 * dt / steps, "seconds": dt,
-            "steps": steps, "min_det": st["min_det"], "min_cell": st["min_cell"], "phases": phases}
+            "steps": steps, "min_det": st["min_det"], "min_cell": st["min_cell"], "stencil_march": march,
+            "phases": phases}
 
 
 def roofline_of(phases, prec):
@@ -83,13 +88,15 @@ def stencil_roofline(ctx, binding, workloads):
     w = workloads.sine_dd(n=8193, parts=(32, 32), overlap=8, steps=1)
     plan = binding.Plan(ctx, [w, w], "split16", "batched")
     try:
+        march, cand = plan.autotune(5)
         ph = plan.phase_times(10)
     finally:
         plan.close()
     st = ph["stencil"]
     gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9
-    return {"kernel": "stencil_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+    return {"kernel": "stencil2_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
             "frac": gbs / PEAK["hbm_GBs"], "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
+            "stencil_march": march, "autotune_ms": [round(t, 4) for t in cand],
             "workload": "2 x 8193^2 sine layer, 32x32 parts, FP32 (8 B per node)"}
 
 
@@ -192,7 +199,8 @@ def main():
     for f in todo:
         prec, ex = ("fp64", "plain") if f == "fp64plain" else (f, "batched")
         steps = args.steps if f != "fp64plain" else max(1, min(args.steps, 100))
-        forms[f] = timed_plan(ctx, binding, [w], prec, ex, steps, min(args.warmup, steps), phase_reps=50)
+        forms[f] = timed_plan(ctx, binding, [w], prec, ex, steps, min(args.warmup, steps), phase_reps=50,
+                              tune=ex == "batched")
         log(f"{f}: {forms[f]['updates_per_s']:.4e} updates/s, {forms[f]['ms_per_step']:.4f} ms/step")
     main_form = args.only or "split16"
     m = forms[main_form]
@@ -222,18 +230,20 @@ def main():
         extra["ring_65_fp64"] = {k: r[k] for k in ("updates_per_s", "ms_per_step")}
         log(f"ring 65^2 fp64: {r['updates_per_s']:.3e}")
         shell = workloads.shell_dd()
-        r = timed_plan(ctx, binding, [shell], "split16", "batched", 200, 5, phase_reps=10)
+        r = timed_plan(ctx, binding, [shell], "split16", "batched", 200, 5, phase_reps=10, tune=True)
         extra["shell_dd_129_split16"] = {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
+                                         "stencil_march": r["stencil_march"],
                                          "roofline": roofline_of(r["phases"], "split16")}
         log(f"shell 129^3 split16: {r['updates_per_s']:.3e}")
         batch = workloads.bumps_batch()
-        rb = timed_plan(ctx, binding, batch, "split16", "batched", 200, 5, phase_reps=10)
+        rb = timed_plan(ctx, binding, batch, "split16", "batched", 200, 5, phase_reps=10, tune=True)
         rp = timed_plan(ctx, binding, batch, "fp64", "plain", 10, 1)
         extra["bumps_batch_256"] = {"batched_split16_updates_per_s": rb["updates_per_s"],
                                     "batched_ms_per_step": rb["ms_per_step"],
                                     "plain_fp64_updates_per_s": rp["updates_per_s"],
                                     "plain_ms_per_step": rp["ms_per_step"],
                                     "speedup": rb["updates_per_s"] / rp["updates_per_s"],
+                                    "stencil_march": rb["stencil_march"],
                                     "roofline": roofline_of(rb["phases"], "split16")}
         log(f"batch 256: {rb['updates_per_s']:.3e} vs plain fp64 {rp['updates_per_s']:.3e}")
         extra["stencil_hbm_large"] = stencil_roofline(ctx, binding, workloads)

@@ -225,6 +225,25 @@ int pma_plan_sync(pma_plan* plan);
 int pma_plan_phase_times(pma_plan* plan, int nsteps, double* ms, double* flops, double* bytes, int cap,
                          int* nphases);
 
+/* Autotuner of the stencil's launch shape (phase 1).  A stencil workgroup marches over `march`
+ * consecutive chunks of a block: 16-row chunks of axis 0 in 2D, planes of axis 0 in 3D (over
+ * 16 rows of axis 1); longer marches amortise the block's set-up and keep the next chunk's loads
+ * in flight, shorter ones give more workgroups.  Candidates march = 1, 2, 4, .. 64 (capped at
+ * the longest useful value) are each timed over `reps` back-to-back launches on the plan's own
+ * state between two HIP events; the fastest is kept for every later step (the captured step
+ * graph is rebuilt).  The stencil reads phi and writes only F, which every step recomputes,
+ * so the results of the plan do not change (bitwise).  *march receives the choice; ms[k]
+ * (may be NULL, cap entries) the mean milliseconds per launch of candidate k; *ncand (may be
+ * NULL) the number of candidates timed.  Errors: PMA_E_INVAL for a NULL plan or march, or
+ * reps <= 0. */
+int pma_plan_autotune(pma_plan* plan, int reps, int* march, double* ms, int cap, int* ncand);
+
+/* Fix the stencil's march length (see pma_plan_autotune) for every later step of the plan;
+ * values beyond a subdomain's extent cover that subdomain's whole axis 0 in one workgroup.
+ * Results do not depend on it (bitwise).  Errors: PMA_E_INVAL for a NULL plan or march outside
+ * 1..4096. */
+int pma_plan_set_march(pma_plan* plan, int march);
+
 /* Glue request i's mesh (dim * prod(n) doubles) into host memory; st may be NULL. */
 int pma_plan_mesh(pma_plan* plan, int i, double* mesh_out, pma_stats* st);
 

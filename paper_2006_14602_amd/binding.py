@@ -101,6 +101,8 @@ def load():
     L.pma_plan_sync.argtypes = [c_void_p]
     L.pma_plan_phase_times.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                        c_int, POINTER(c_int)]
+    L.pma_plan_autotune.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_double), c_int, POINTER(c_int)]
+    L.pma_plan_set_march.argtypes = [c_void_p, c_int]
     L.pma_plan_mesh.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(Stats)]
     L.pma_plan_destroy.argtypes = [c_void_p]
     for f in declared_symbols():
@@ -377,6 +379,18 @@ class Plan:
         nph = c_int()
         _check(self._L.pma_plan_phase_times(self.h, int(n), ms, fl, by, 8, ctypes.byref(nph)))
         return {PHASES[i]: {"ms": ms[i], "flops": fl[i], "bytes": by[i]} for i in range(nph.value)}
+
+    def autotune(self, reps: int = 10):
+        """Stencil march length picked by timing (pma_plan_autotune): (choice, [ms per candidate
+        march 1, 2, 4, .. capped at the longest useful one])."""
+        march = c_int()
+        ms = (c_double * 8)()
+        nc = c_int()
+        _check(self._L.pma_plan_autotune(self.h, int(reps), ctypes.byref(march), ms, 8, ctypes.byref(nc)))
+        return march.value, [ms[k] for k in range(nc.value)]
+
+    def set_march(self, march: int):
+        _check(self._L.pma_plan_set_march(self.h, int(march)))
 
     def mesh(self, i: int = 0):
         w = self.ws[i]

@@ -26,6 +26,16 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// Global-memory view of a pointer taken from a descriptor.  Accesses through a plain pointer
+// loaded from memory compile to flat instructions, which also count as LDS operations: every
+// wait for an LDS read would then drain the loads in flight as well.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ inline const gmem<T>* gp(const void* p) { return (const gmem<T>*)p; }
+template <typename T>
+__device__ inline gmem<T>* gpw(void* p) { return (gmem<T>*)p; }
+
 // ------------------------------------------------------------------------------------------
 // monitor: log rho(x), computed as log1p of the excess over 1 where rho = 1 + (...)
 // ------------------------------------------------------------------------------------------
@@ -97,9 +107,12 @@ __device__ inline T rho_excess(const MonP<T>& m, int dim, T x0, T x1, T x2) {
   return T(0);
 }
 
-// log(rho (1 + e)): FP64 keeps log1p of both excesses; FP32 takes one hardware log of the product
+// log(rho (1 + e)): FP64 keeps log1p of both excesses; FP32 takes one hardware log2 of the product
+// (the product stays far from the denormal range while the mesh is untangled)
 __device__ inline double log_rho_det(double rex, double e) { return log1p(rex) + log1p(e); }
-__device__ inline float log_rho_det(float rex, float e) { return __logf((1.f + rex) * (1.f + e)); }
+__device__ inline float log_rho_det(float rex, float e) {
+  return __builtin_amdgcn_logf((1.f + rex) * (1.f + e)) * 0.693147180559945309f;
+}
 
 __device__ inline bool is_artificial(int art, int k, int i, int n) {
   return (i == 0 && ((art >> (2 * k)) & 1)) || (i == n - 1 && ((art >> (2 * k + 1)) & 1));
@@ -124,207 +137,359 @@ __device__ inline int mirror_clamp(int i, int n) {
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
 
-// Per-workgroup constants of a subdomain, copied into registers once: the stores to F below
-// could otherwise alias the descriptor tables, forcing a reload of every field per node.
-template <typename T>
-struct StencilCtx {
-  const MonP<T>* __restrict__ mon;  // stays in global memory (a private copy would go to scratch)
-  T lvt, a0, a1, a2, h0, h1, h2;
-  int n0, n1, n2, off0, off1, off2, art, inst;
-  const int* own0;
-  const int* own1;
-  const int* own2;
-  int p1, p2, first;
+// Monitor parameters of one kind, held in registers for a whole tile so that evaluating rho at a
+// node reads no memory (the stores to F could alias the descriptors, which would otherwise force
+// a reload of every parameter per node).  excess<DIM>(x) = rho(x) - 1.
+template <typename T, int MK> struct MonReg;
+
+template <typename T> struct MonReg<T, MON_CONST> {
+  T ex;
+  __device__ explicit MonReg(const MonP<T>& m) : ex(m.amp - T(1)) {}
+  template <int DIM> __device__ T excess(T, T, T) const { return ex; }
 };
 
-// phi at an artificial-boundary node (li, lj[, lk]) of a subdomain, read from its owner: the value
-// the parallel transmission condition gives the node at the start of the step
-template <typename T>
-__device__ inline T owner_phi(const StencilCtx<T>& K, const SubDev* __restrict__ subs, int dim, int li, int lj,
-                              int lk) {
-  const int g0 = K.off0 + li, g1 = K.off1 + lj, g2 = K.off2 + lk;
-  int q = K.own0[g0] * K.p1 + K.own1[g1];
-  if (dim == 3) q = q * K.p2 + K.own2[g2];
-  const SubDev& O = subs[K.first + q];
-  const long idx = dim == 2 ? (long)(g0 - O.off[0]) * O.n[1] + (g1 - O.off[1])
-                            : ((long)(g0 - O.off[0]) * O.n[1] + (g1 - O.off[1])) * O.n[2] + (g2 - O.off[2]);
-  return ((const T*)O.phi)[idx];
-}
+template <typename T> struct MonReg<T, MON_RADIAL> {
+  T amp, k, c0, c1, c2, r02;
+  __device__ explicit MonReg(const MonP<T>& m)
+      : amp(m.amp), k(m.k), c0(m.c[0]), c1(m.c[1]), c2(m.c[2]), r02(m.r02) {}
+  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
+    const T d0 = x0 - c0, d1 = x1 - c1;
+    T r2 = d0 * d0 + d1 * d1;
+    if (DIM == 3) r2 += (x2 - c2) * (x2 - c2);
+    return amp * sech2_fast(k * (r2 - r02));
+  }
+};
 
+template <typename T> struct MonReg<T, MON_SINE> {
+  T amp, k, c1, r0;
+  __device__ explicit MonReg(const MonP<T>& m) : amp(m.amp), k(m.k), c1(m.c[1]), r0(m.r0) {}
+  template <int DIM> __device__ T excess(T x0, T x1, T) const {
+    return amp * sech2_fast(k * (x1 - c1 - r0 * sin2pi(x0)));
+  }
+};
+
+template <typename T> struct MonReg<T, MON_GAUSS> {
+  int nb;
+  T amp[4], nh[4], c0[4], c1[4], c2[4];
+  __device__ explicit MonReg(const MonP<T>& m) : nb(m.nb) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      amp[b] = m.bamp[b];
+      nh[b] = m.bnh[b];
+      c0[b] = m.bc[b][0];
+      c1[b] = m.bc[b][1];
+      c2[b] = m.bc[b][2];
+    }
+  }
+  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
+    T acc = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b < nb) {
+        const T d0 = x0 - c0[b], d1 = x1 - c1[b];
+        T r2 = d0 * d0 + d1 * d1;
+        if (DIM == 3) r2 += (x2 - c2[b]) * (x2 - c2[b]);
+        acc += amp[b] * fexp(r2 * nh[b]);
+      }
+    return acc;
+  }
+};
+
+template <typename T> struct MonReg<T, MON_SEPARABLE> {
+  T aa[3], ka[3], c[3];
+  __device__ explicit MonReg(const MonP<T>& m) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      aa[q] = m.aa[q];
+      ka[q] = m.ka[q];
+      c[q] = m.c[q];
+    }
+  }
+  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
+    T p = (T(1) + aa[0] * sech2_fast(ka[0] * (x0 - c[0]))) * (T(1) + aa[1] * sech2_fast(ka[1] * (x1 - c[1])));
+    if (DIM == 3) p *= T(1) + aa[2] * sech2_fast(ka[2] * (x2 - c[2]));
+    return p - T(1);
+  }
+};
+
+// F at a live node from rho - 1 and det(I + D^2 phi) - 1; status bits collect in `bad`
 template <typename T>
-__device__ inline T finish_rhs(const StencilCtx<T>& K, int* status, T e, T x0, T x1, T x2, int dim) {
-  const T f = K.lvt + log_rho_det(rho_excess(*K.mon, dim, x0, x1, x2), e);
-  if (!(T(1) + e > T(0))) atomicOr(&status[K.inst], ST_TANGLED);
-  else if (!finite_(f)) atomicOr(&status[K.inst], ST_NONFINITE);
+__device__ inline T rhs_value(T lvt, T rex, T e, int& bad) {
+  const T f = lvt + log_rho_det(rex, e);
+  bad |= !(T(1) + e > T(0)) ? ST_TANGLED : (finite_(f) ? 0 : ST_NONFINITE);
   return f;
 }
 
-// Stencil into F.  A tile is staged with a one-node halo in LDS, mirror ghosts applied while
-// loading.  2D: 16 rows x 64 columns, 4 nodes per thread, artificial faces read from their owners;
-// tile = (sub, row0, col0, 0).  3D: 16 rows (i1) x up to 72 columns (i2) of plane i0 with the two
-// neighbouring planes; tile = (sub, i0, row0, col0).
+// Per-workgroup constants of a subdomain, copied into registers once.
 template <typename T>
-__global__ __launch_bounds__(256) void stencil_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
-  constexpr int TR = 16, TC = 64, HR = TR + 2, HC = TC + 2;
-  __shared__ T sm3_raw[3 * HR * 74];  // 3D: three halo planes of 18 x 74; 2D uses the front
-  T(*sm)[HR][HC] = reinterpret_cast<T(*)[HR][HC]>(&sm3_raw[0]);
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
-  StencilCtx<T> K;
-  const T* __restrict__ phi;
-  T* __restrict__ F;
-  int dim;
-  {
-    const SubDev& S = sa.subs[tl.x];
-    const InstDev& I = sa.insts[S.inst];
-    K.mon = &mon_of(I, T(0));
-    K.lvt = T(I.log_vol_theta);
-    K.a0 = T(S.a[0]);
-    K.a1 = T(S.a[1]);
-    K.a2 = T(S.a[2]);
-    K.h0 = T(S.h[0]);
-    K.h1 = T(S.h[1]);
-    K.h2 = T(S.h[2]);
-    K.n0 = S.n[0];
-    K.n1 = S.n[1];
-    K.n2 = S.n[2];
-    K.off0 = S.off[0];
-    K.off1 = S.off[1];
-    K.off2 = S.off[2];
-    K.art = S.art;
-    K.inst = S.inst;
-    K.own0 = I.own[0];
-    K.own1 = I.own[1];
-    K.own2 = I.own[2];
-    K.p1 = I.parts[1];
-    K.p2 = I.parts[2];
-    K.first = I.first_sub;
-    phi = (const T*)S.phi;
-    F = (T*)S.F;
-    dim = S.dim;
+struct StencilCtx {
+  T lvt, a0, a1, a2, h0, h1, h2;
+  int n0, n1, n2, off0, off1, off2, art, inst;
+};
+
+constexpr int kStR = 16;                               // output rows per chunk (2D: i0, 3D: i1)
+constexpr int kStWmax = 72;                            // widest tile along the last axis
+constexpr int kStS = kStWmax + 2;                      // LDS row stride
+constexpr int kStHR = kStR + 2;                        // staged rows per chunk
+constexpr int kStPts = (kStR * kStWmax + 255) / 256;   // output nodes per thread per chunk
+constexpr int kStLd = (kStHR + 3) / 4;                 // staged rows per wave
+
+// Halo staging of one 18 x (W + 2) block: wave w stages rows w, w + 4, ..; lane l column l and,
+// for blocks wider than a wave, column 64 + l.  Values land in registers first, so the next
+// chunk's loads are in flight while the current chunk is computed.
+struct HaloCols {
+  int gjA, gjB;   // mirrored index along the last axis of the two columns
+  bool okA, okB;  // column inside the block
+};
+
+__device__ inline HaloCols halo_cols(int col0, int W, int n) {
+  const int lane = threadIdx.x & 63;
+  HaloCols h;
+  h.okA = lane < W + 2;
+  h.okB = 64 + lane < W + 2;
+  h.gjA = mirror_clamp(col0 + lane - 1, n);
+  h.gjB = mirror_clamp(col0 + 63 + lane, n);
+  return h;
+}
+
+template <typename T>
+__device__ inline void halo_commit(T* slot, const HaloCols& hc, const T (&pre)[2 * kStLd]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kStLd; ++k) {
+    const int r = wave + 4 * k;
+    if (r < kStHR) {
+      if (hc.okA) slot[r * kStS + lane] = pre[2 * k];
+      if (hc.okB) slot[r * kStS + 64 + lane] = pre[2 * k + 1];
+    }
   }
-  int* __restrict__ status = sa.status;
-  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  const T h0 = K.h0, h1 = K.h1, h2 = K.h2;
-  if (dim == 2) {
-    const int n0 = K.n0, n1 = K.n1;
-    const int row0 = tl.y, col0 = tl.z;
-    if (row0 >= 2 && row0 + TR + 1 < n0 && col0 >= 2 && col0 + TC + 1 < n1) {
-      // interior tile: the halo touches no face of the subdomain
-      const T* base = phi + (long)(row0 - 1) * n1 + (col0 - 1);
-      for (int idx = tid; idx < HR * HC; idx += 256) {
-        const int r = idx / HC, c = idx - r * HC;
-        sm[0][r][c] = base[(long)r * n1 + c];
-      }
-    } else {
-      for (int idx = tid; idx < HR * HC; idx += 256) {
-        const int r = idx / HC, c = idx - r * HC;
-        const int gi = mirror_clamp(row0 + r - 1, n0), gj = mirror_clamp(col0 + c - 1, n1);
-        sm[0][r][c] = phi[(long)gi * n1 + gj];
-      }
-      if (K.own0 && K.art) {
-        // artificial faces inside the halo take their owners' values (one line per face)
-        __syncthreads();
-        for (int idx = tid; idx < 2 * HC + 2 * HR; idx += 256) {
-          int r, c;
-          bool on;
-          if (idx < 2 * HC) {  // rows at local index 0 / n0 - 1
-            const int li = idx < HC ? 0 : n0 - 1;
-            r = li - (row0 - 1);
-            c = idx < HC ? idx : idx - HC;
-            on = is_artificial(K.art, 0, li, n0) && r >= 0 && r < HR;
-          } else {             // columns at local index 0 / n1 - 1
-            const int t = idx - 2 * HC;
-            const int lj = t < HR ? 0 : n1 - 1;
-            c = lj - (col0 - 1);
-            r = t < HR ? t : t - HR;
-            on = is_artificial(K.art, 1, lj, n1) && c >= 0 && c < HC;
-          }
-          if (on) {
-            const int li = mirror_clamp(row0 + r - 1, n0), lj = mirror_clamp(col0 + c - 1, n1);
-            if (is_artificial(K.art, 0, li, n0) || is_artificial(K.art, 1, lj, n1))
-              sm[0][r][c] = owner_phi(K, sa.subs, 2, li, lj, 0);
-          }
-        }
+}
+
+// this thread's output nodes of a 16 x W chunk: linear index tid + 256 m -> (row << 8) | column
+__device__ inline void chunk_nodes(int W, int (&pk)[kStPts]) {
+#pragma unroll
+  for (int m = 0; m < kStPts; ++m) {
+    const int idx = (int)threadIdx.x + 256 * m;
+    const int rr = idx / W;
+    pk[m] = idx < kStR * W ? (rr << 8) | (idx - rr * W) : -1;
+  }
+}
+
+// 2D: rows [row0, row0 + nrows) x columns [col0, col0 + W) of a subdomain, 16 rows per chunk.
+// The artificial nodes were filled by the transmission gather before the launch.
+template <typename T, int MK>
+__device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp, const T* phi_, T* F_, T* sm,
+                                      int row0, int nrows, int col0, int W, int& bad) {
+  const gmem<T>* __restrict__ phi = (const gmem<T>*)phi_;
+  gmem<T>* __restrict__ F = (gmem<T>*)F_;
+  const MonReg<T, MK> M(mp);
+  const int wave = threadIdx.x >> 6;
+  const int n0 = K.n0, n1 = K.n1;
+  const HaloCols hc = halo_cols(col0, W, n1);
+  T pre[2 * kStLd];
+  auto issue = [&](int rb) {
+#pragma unroll
+    for (int k = 0; k < kStLd; ++k) {
+      const int r = wave + 4 * k;
+      if (r < kStHR) {
+        const gmem<T>* row = phi + (long)mirror_clamp(rb + r - 1, n0) * n1;
+        if (hc.okA) pre[2 * k] = row[hc.gjA];
+        if (hc.okB) pre[2 * k + 1] = row[hc.gjB];
       }
     }
+  };
+  int pk[kStPts];
+  chunk_nodes(W, pk);
+  const T h0 = K.h0, h1 = K.h1;
+  const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
+  const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
+  const int rend = row0 + nrows;
+  issue(row0);
+  for (int rb = row0; rb < rend; rb += kStR) {
+    if (rb != row0) __syncthreads();  // every thread is done reading the previous chunk
+    halo_commit(sm, hc, pre);
     __syncthreads();
-    const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
-    const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
-    const int j = col0 + tx;
-    if (j >= n1) return;
-    const bool artj = is_artificial(K.art, 1, j, n1);
-    const T x1b = K.a1 + T(K.off1 + j) * h1;
-    for (int m = 0; m < TR / 4; ++m) {
-      const int rr = ty + 4 * m, i = row0 + rr;
-      if (i >= n0) break;
+    if (rb + kStR < rend) issue(rb + kStR);
+#pragma unroll
+    for (int m = 0; m < kStPts; ++m) {
+      if (pk[m] < 0) continue;
+      const int rr = pk[m] >> 8, cc = pk[m] & 255;
+      const int i = rb + rr, j = col0 + cc;
+      if (i >= rend) continue;
       const long v = (long)i * n1 + j;
-      if (artj || is_artificial(K.art, 0, i, n0)) {
+      if (is_artificial(K.art, 0, i, n0) || is_artificial(K.art, 1, j, n1)) {
         F[v] = T(0);
         continue;
       }
-      const int r = rr + 1, c = tx + 1;
-      const T cc = sm[0][r][c];
-      const T xm = sm[0][r - 1][c], xp = sm[0][r + 1][c], ym = sm[0][r][c - 1], yp = sm[0][r][c + 1];
+      const int o = (rr + 1) * kStS + cc + 1;
+      const T c0 = sm[o];
+      const T xm = sm[o - kStS], xp = sm[o + kStS], ym = sm[o - 1], yp = sm[o + 1];
       const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
-      const T hxx = (xp - T(2) * cc + xm) * rh00;
-      const T hyy = (yp - T(2) * cc + ym) * rh11;
-      const T hxy = (sm[0][r + 1][c + 1] - sm[0][r + 1][c - 1] - sm[0][r - 1][c + 1] + sm[0][r - 1][c - 1]) * r4h01;
+      const T hxx = (xp - T(2) * c0 + xm) * rh00;
+      const T hyy = (yp - T(2) * c0 + ym) * rh11;
+      const T hxy = (sm[o + kStS + 1] - sm[o + kStS - 1] - sm[o - kStS + 1] + sm[o - kStS - 1]) * r4h01;
       const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
       const T x0 = K.a0 + T(K.off0 + i) * h0 + gx;
-      F[v] = finish_rhs(K, status, e, x0, x1b + gy, T(0), 2);
+      const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
+      F[v] = rhs_value(K.lvt, M.template excess<2>(x0, x1, T(0)), e, bad);
     }
-    return;
   }
-  // 3D: tile = 16 rows (i1) x up to 72 columns (i2) of plane i0, three halo planes in LDS; the
-  // artificial nodes were filled by the transmission gather before this launch
-  constexpr int TC3 = 72, HC3 = TC3 + 2;
-  T(*sm3)[HR][HC3] = reinterpret_cast<T(*)[HR][HC3]>(&sm3_raw[0]);
+}
+
+// 3D: planes [p0, p0 + np) of a 16-row (i1) x W-column (i2) block; a ring of three staged planes
+// in LDS, the next plane loading while the current one is computed.  The artificial nodes were
+// filled by the transmission gather before the launch.
+template <typename T, int MK>
+__device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp, const T* phi_, T* F_, T* sm,
+                                      int p0, int np, int row0, int col0, int W, int& bad) {
+  const gmem<T>* __restrict__ phi = (const gmem<T>*)phi_;
+  gmem<T>* __restrict__ F = (gmem<T>*)F_;
+  const MonReg<T, MK> M(mp);
+  const int wave = threadIdx.x >> 6;
   const int n0 = K.n0, n1 = K.n1, n2 = K.n2;
-  const int i0 = tl.y, row0 = tl.z, col0 = tl.w;
-  const int w = min(TC3, n2 - col0);
-  for (int idx = tid; idx < 3 * HR * HC3; idx += 256) {
-    const int p = idx / (HR * HC3), rem = idx - p * (HR * HC3);
-    const int r = rem / HC3, c = rem - r * HC3;
-    const int gp = mirror_clamp(i0 + p - 1, n0), gi = mirror_clamp(row0 + r - 1, n1),
-              gj = mirror_clamp(col0 + c - 1, n2);
-    sm3[p][r][c] = phi[((long)gp * n1 + gi) * n2 + gj];
-  }
-  __syncthreads();
+  const HaloCols hc = halo_cols(col0, W, n2);
+  constexpr int PL = kStHR * kStS;
+  T pre[2 * kStLd];
+  auto issue = [&](int p) {
+    const int gp = mirror_clamp(p, n0);
+#pragma unroll
+    for (int k = 0; k < kStLd; ++k) {
+      const int r = wave + 4 * k;
+      if (r < kStHR) {
+        const int gi = mirror_clamp(row0 + r - 1, n1);
+        const gmem<T>* row = phi + ((long)gp * n1 + gi) * n2;
+        if (hc.okA) pre[2 * k] = row[hc.gjA];
+        if (hc.okB) pre[2 * k + 1] = row[hc.gjB];
+      }
+    }
+  };
+  int pk[kStPts];
+  chunk_nodes(W, pk);
+  const T h0 = K.h0, h1 = K.h1, h2 = K.h2;
   const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1), r2h2 = T(1) / (T(2) * h2);
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), rh22 = T(1) / (h2 * h2);
   const T r4h01 = T(1) / (T(4) * h0 * h1), r4h02 = T(1) / (T(4) * h0 * h2), r4h12 = T(1) / (T(4) * h1 * h2);
-  const bool art0 = is_artificial(K.art, 0, i0, n0);
-  const T x0b = K.a0 + T(K.off0 + i0) * h0;
-  const int rows = min(TR, n1 - row0);
-  for (int idx = tid; idx < rows * w; idx += 256) {
-    const int rr = idx / w, cc0 = idx - rr * w;
-    const int j = row0 + rr, k = col0 + cc0;
-    const long v = ((long)i0 * n1 + j) * n2 + k;
-    if (art0 || is_artificial(K.art, 1, j, n1) || is_artificial(K.art, 2, k, n2)) {
-      F[v] = T(0);
-      continue;
+  // plane p0 - 1 -> slot 0, p0 -> slot 1, p0 + q + 1 -> slot (q + 2) % 3
+  issue(p0 - 1);
+  halo_commit(sm, hc, pre);
+  issue(p0);
+  halo_commit(sm + PL, hc, pre);
+  issue(p0 + 1);
+  for (int q = 0; q < np; ++q) {
+    const int p = p0 + q;
+    __syncthreads();  // the slot about to be refilled is no longer read
+    halo_commit(sm + ((q + 2) % 3) * PL, hc, pre);
+    __syncthreads();
+    if (q + 1 < np) issue(p + 2);
+    const T* sp = sm + (q % 3) * PL;
+    const T* sc = sm + ((q + 1) % 3) * PL;
+    const T* sn = sm + ((q + 2) % 3) * PL;
+    const bool art0 = is_artificial(K.art, 0, p, n0);
+    const T x0b = K.a0 + T(K.off0 + p) * h0;
+#pragma unroll
+    for (int m = 0; m < kStPts; ++m) {
+      if (pk[m] < 0) continue;
+      const int rr = pk[m] >> 8, cc = pk[m] & 255;
+      const int j = row0 + rr, k = col0 + cc;
+      if (j >= n1) continue;
+      const long v = ((long)p * n1 + j) * n2 + k;
+      if (art0 || is_artificial(K.art, 1, j, n1) || is_artificial(K.art, 2, k, n2)) {
+        F[v] = T(0);
+        continue;
+      }
+      const int o = (rr + 1) * kStS + cc + 1;
+      const T c0 = sc[o];
+      const T xm = sp[o], xp = sn[o];
+      const T ym = sc[o - kStS], yp = sc[o + kStS];
+      const T zm = sc[o - 1], zp = sc[o + 1];
+      const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1, gz = (zp - zm) * r2h2;
+      const T a = (xp - T(2) * c0 + xm) * rh00;
+      const T b = (yp - T(2) * c0 + ym) * rh11;
+      const T c = (zp - T(2) * c0 + zm) * rh22;
+      const T d01 = (sn[o + kStS] - sn[o - kStS] - sp[o + kStS] + sp[o - kStS]) * r4h01;
+      const T d02 = (sn[o + 1] - sn[o - 1] - sp[o + 1] + sp[o - 1]) * r4h02;
+      const T d12 = (sc[o + kStS + 1] - sc[o + kStS - 1] - sc[o - kStS + 1] + sc[o - kStS - 1]) * r4h12;
+      // det(I + H) - 1 = tr H + (sum of principal 2x2 minors) + det H
+      const T tr = a + b + c;
+      const T m2 = (a * b - d01 * d01) + (a * c - d02 * d02) + (b * c - d12 * d12);
+      const T d3 = a * (b * c - d12 * d12) - d01 * (d01 * c - d12 * d02) + d02 * (d01 * d12 - b * d02);
+      const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
+      const T x2 = K.a2 + T(K.off2 + k) * h2 + gz;
+      F[v] = rhs_value(K.lvt, M.template excess<3>(x0b + gx, x1, x2), tr + m2 + d3, bad);
     }
-    const int r = rr + 1, c = cc0 + 1;
-    const T cc = sm3[1][r][c];
-    const T xm = sm3[0][r][c], xp = sm3[2][r][c];
-    const T ym = sm3[1][r - 1][c], yp = sm3[1][r + 1][c];
-    const T zm = sm3[1][r][c - 1], zp = sm3[1][r][c + 1];
-    const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1, gz = (zp - zm) * r2h2;
-    const T a = (xp - T(2) * cc + xm) * rh00;
-    const T b = (yp - T(2) * cc + ym) * rh11;
-    const T q = (zp - T(2) * cc + zm) * rh22;
-    const T p = (sm3[2][r + 1][c] - sm3[2][r - 1][c] - sm3[0][r + 1][c] + sm3[0][r - 1][c]) * r4h01;
-    const T rx = (sm3[2][r][c + 1] - sm3[2][r][c - 1] - sm3[0][r][c + 1] + sm3[0][r][c - 1]) * r4h02;
-    const T sy = (sm3[1][r + 1][c + 1] - sm3[1][r + 1][c - 1] - sm3[1][r - 1][c + 1] + sm3[1][r - 1][c - 1]) * r4h12;
-    // det(I + H) - 1 = tr H + (sum of principal 2x2 minors) + det H
-    const T tr = a + b + q;
-    const T m2 = (a * b - p * p) + (a * q - rx * rx) + (b * q - sy * sy);
-    const T d3 = a * (b * q - sy * sy) - p * (p * q - sy * rx) + rx * (p * sy - b * rx);
-    const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
-    const T x2 = K.a2 + T(K.off2 + k) * h2 + gz;
-    F[v] = finish_rhs(K, status, tr + m2 + d3, x0b + gx, x1, x2, 3);
   }
+}
+
+template <typename T>
+__device__ inline const MonP<T>* load_ctx(const StepArgs& sa, int sub, StencilCtx<T>& K, const T*& phi, T*& F) {
+  const SubDev& S = sa.subs[sub];
+  const InstDev& I = sa.insts[S.inst];
+  K.lvt = T(I.log_vol_theta);
+  K.a0 = T(S.a[0]);
+  K.a1 = T(S.a[1]);
+  K.a2 = T(S.a[2]);
+  K.h0 = T(S.h[0]);
+  K.h1 = T(S.h[1]);
+  K.h2 = T(S.h[2]);
+  K.n0 = S.n[0];
+  K.n1 = S.n[1];
+  K.n2 = S.n[2];
+  K.off0 = S.off[0];
+  K.off1 = S.off[1];
+  K.off2 = S.off[2];
+  K.art = S.art;
+  K.inst = S.inst;
+  phi = (const T*)S.phi;
+  F = (T*)S.F;
+  return &mon_of(I, T(0));
+}
+
+// Stencil into F (2D subdomains).  tile = (sub, row0, col0 | W << 16, nrows): the block of rows
+// [row0, row0 + nrows) and columns [col0, col0 + W), W <= 72, marched 16 rows at a time.  Mirror
+// ghosts are applied while staging; the node loop is specialised per monitor kind.  A step
+// launches the transmission gather first, so every halo value is the local array's.
+template <typename T>
+__global__ __launch_bounds__(256) void stencil2_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
+  __shared__ T sm[kStHR * kStS];
+  if ((int)blockIdx.x >= ntiles) return;
+  const int4 tl = tiles[blockIdx.x];
+  StencilCtx<T> K;
+  const T* phi;
+  T* F;
+  const MonP<T>* mp = load_ctx(sa, tl.x, K, phi, F);
+  const int row0 = tl.y, col0 = tl.z & 0xffff, W = tl.z >> 16, nrows = tl.w;
+  int bad = 0;
+  switch (mp->kind) {
+    case MON_CONST: stencil_march2<T, MON_CONST>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+    case MON_RADIAL: stencil_march2<T, MON_RADIAL>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+    case MON_SINE: stencil_march2<T, MON_SINE>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+    case MON_GAUSS: stencil_march2<T, MON_GAUSS>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+    default: stencil_march2<T, MON_SEPARABLE>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+  }
+  if (bad) atomicOr(&sa.status[K.inst], bad);
+}
+
+// Stencil into F (3D subdomains).  tile = (sub, p0 | np << 16, row0, col0 | W << 16): planes
+// [p0, p0 + np) of the block of 16 rows (i1) from row0 and W <= 72 columns (i2) from col0.
+template <typename T>
+__global__ __launch_bounds__(256) void stencil3_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
+  __shared__ T sm[3 * kStHR * kStS];
+  if ((int)blockIdx.x >= ntiles) return;
+  const int4 tl = tiles[blockIdx.x];
+  StencilCtx<T> K;
+  const T* phi;
+  T* F;
+  const MonP<T>* mp = load_ctx(sa, tl.x, K, phi, F);
+  const int p0 = tl.y & 0xffff, np = tl.y >> 16, row0 = tl.z, col0 = tl.w & 0xffff, W = tl.w >> 16;
+  int bad = 0;
+  switch (mp->kind) {
+    case MON_CONST: stencil_march3<T, MON_CONST>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+    case MON_RADIAL: stencil_march3<T, MON_RADIAL>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+    case MON_SINE: stencil_march3<T, MON_SINE>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+    case MON_GAUSS: stencil_march3<T, MON_GAUSS>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+    default: stencil_march3<T, MON_SEPARABLE>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+  }
+  if (bad) atomicOr(&sa.status[K.inst], bad);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -397,8 +562,8 @@ template <> struct Op<PREC_SPLIT16> {
   }
   static __device__ inline frag glob_frag(const void* hi, const void* lo, int ld, int r, int k0, int g) {
     frag f;
-    f.hi = *(const half8_t*)((const _Float16*)hi + (long)r * ld + k0 + 8 * g);
-    f.lo = *(const half8_t*)((const _Float16*)lo + (long)r * ld + k0 + 8 * g);
+    f.hi = *(const gmem<half8_t>*)(gp<_Float16>(hi) + (long)r * ld + k0 + 8 * g);
+    f.lo = *(const gmem<half8_t>*)(gp<_Float16>(lo) + (long)r * ld + k0 + 8 * g);
     return f;
   }
   static __device__ inline void mma(acc_t& c, const frag& a, const frag& b) {
@@ -419,7 +584,7 @@ template <> struct Op<PREC_F32> {
     return ((const float*)lds)[r * ld + k0 + g];
   }
   static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
-    return ((const float*)p)[(long)r * ld + k0 + g];
+    return gp<float>(p)[(long)r * ld + k0 + g];
   }
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -437,7 +602,7 @@ template <> struct Op<PREC_F64> {
     return ((const double*)lds)[r * ld + k0 + g];
   }
   static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
-    return ((const double*)p)[(long)r * ld + k0 + g];
+    return gp<double>(p)[(long)r * ld + k0 + g];
   }
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -513,7 +678,7 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   const int ld = A.ld;
   const int row0 = tl.y, col0 = tl.z;
   __shared__ float red[4];
-  const T* __restrict__ src = (const T*)S.F;
+  const gmem<T>* __restrict__ src = gp<T>(S.F);
   float amax = 0.f;
   for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
     const int r = idx / ld, k = idx - r * ld;
@@ -528,7 +693,7 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   if (cb * 16 >= C) return;
   typename O::acc_t acc = {0, 0, 0, 0};
   mma_lds_by_basis<KIND>(acc, lds, ld, sc, A.fwd, A.fwdl, cb * 16 + l16, l16, g);
-  T* __restrict__ out = (T*)S.T;
+  gmem<T>* __restrict__ out = gpw<T>(S.T);
   const T us = T(A.fwd_unscale) / T(sc);
   const int c = cb * 16 + l16;
   for (int q = 0; q < 4; ++q) {
@@ -541,7 +706,7 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
 template <typename T>
 __device__ inline T instance_shift(const StepArgs& sa, const InstDev& I) {
   if (!I.pin) return T(0);
-  const T* dc = (const T*)sa.dc;
+  const gmem<T>* dc = gp<T>(sa.dc);
   T s = T(0);
   for (int q = 0; q < I.nsub; ++q) s += dc[I.first_sub + q];
   return s / T(I.nsub);
@@ -578,7 +743,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const int ld = A.ld;
   const int row0 = tl.y, col0 = tl.z;
   __shared__ float redf[4];
-  const T* __restrict__ src = (const T*)S.F;
+  const gmem<T>* __restrict__ src = gp<T>(S.F);
   float amax = 0.f;
   for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
     const int r = idx / ld, k = idx - r * ld;
@@ -595,7 +760,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const T isc = T(1) / T(sc);
   double part = 0.0;
   if (cb * 16 < C) {
-    T* __restrict__ phi = (T*)S.phi;
+    gmem<T>* __restrict__ phi = gpw<T>(S.phi);
     const int c = cb * 16 + l16;
     // the update's phi values are requested before the product so their latency overlaps it
     T old[4];
@@ -665,8 +830,8 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
     base = (long)tl.y * S.n[1] * S.n[2];
   }
   const int col0 = tl.z;
-  const T* __restrict__ src = (const T*)(src_sel ? S.T : S.F) + base;
-  T* __restrict__ dst = (T*)(src_sel ? S.F : S.T) + base;
+  const gmem<T>* __restrict__ src = gp<T>(src_sel ? S.T : S.F) + base;
+  gmem<T>* __restrict__ dst = gpw<T>(src_sel ? S.F : S.T) + base;
   __shared__ float red[4];
   // strip transposed into LDS: operand row c = strip column, k = index along the axis
   float amax = 0.f;
@@ -688,9 +853,9 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   T sig0[PAIR ? MAXRB * 4 : 1];
   T rest = T(0);
   if constexpr (PAIR) {
-    const T* s0 = (const T*)S.ax[0].sig;
-    const T* s1 = (const T*)S.ax[1].sig;
-    const T* s2 = (const T*)S.ax[2].sig;
+    const gmem<T>* s0 = gp<T>(S.ax[0].sig);
+    const gmem<T>* s1 = gp<T>(S.ax[1].sig);
+    const gmem<T>* s2 = gp<T>(S.ax[2].sig);
     if (c < ncol) {
       if (S.dim == 2) rest = T(S.gh2[1]) * s1[c];
       else {
@@ -733,7 +898,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
         T y = T(0);
         if (rb < nrb && i < K && c < ncol) {
           const T val = acc[t][q] * us1;
-          if (i == 0 && c == 0) ((T*)sa.dc)[tl.x] = val;
+          if (i == 0 && c == 0) gpw<T>(sa.dc)[tl.x] = val;
           y = val / (T(1) + g0 * sig0[t * 4 + q] + rest);
         }
         acc[t][q] = y;
@@ -799,8 +964,8 @@ __global__ __launch_bounds__(256) void euler_kernel(const int4* __restrict__ til
     node_weight(S, i0, i1, i2, w, live);
     if (live) {
       const long v = (long)row * C + col;
-      T* phi = (T*)S.phi;
-      const T u = T(I.dt) * ((const T*)S.F)[v];
+      gmem<T>* phi = gpw<T>(S.phi);
+      const T u = T(I.dt) * gp<T>(S.F)[v];
       phi[v] += u;
       acc = w * (double)u * (double)u;
       if (!finite_(u)) atomicOr(&sa.status[S.inst], ST_NONFINITE);
@@ -822,7 +987,7 @@ __global__ __launch_bounds__(256) void transmit_kernel(const SubDev* __restrict_
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
   const int4 e = ent[i];
-  ((T*)subs[e.x].phi)[e.y] = ((const T*)subs[e.z].phi)[e.w];
+  gpw<T>(subs[e.x].phi)[e.y] = gp<T>(subs[e.z].phi)[e.w];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1048,12 +1213,19 @@ hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int co
   return hipGetLastError();
 }
 
-hipError_t launch_stencil(int prec, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s) {
+hipError_t launch_stencil(int prec, int dim, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (prec == PREC_F64)
-    hipLaunchKernelGGL(stencil_kernel<double>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, sa);
-  else
-    hipLaunchKernelGGL(stencil_kernel<float>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, sa);
+  if (dim == 2) {
+    if (prec == PREC_F64)
+      hipLaunchKernelGGL(stencil2_kernel<double>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, sa);
+    else
+      hipLaunchKernelGGL(stencil2_kernel<float>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, sa);
+  } else {
+    if (prec == PREC_F64)
+      hipLaunchKernelGGL(stencil3_kernel<double>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, sa);
+    else
+      hipLaunchKernelGGL(stencil3_kernel<float>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, sa);
+  }
   return hipGetLastError();
 }
 

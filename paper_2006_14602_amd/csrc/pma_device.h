@@ -71,11 +71,6 @@ struct InstDev {
   int first_sub, nsub;
   int pin;               // subtract the mean DC coefficient each step (gamma > 0)
   int pad_;
-  // owner of each global node index per axis (null: artificial faces hold external data), and
-  // the parts per axis: the stencil reads artificial-boundary values from their owners directly
-  const int* own[3];
-  int parts[3];
-  int pad2_;
 };
 
 struct StepArgs {

@@ -26,7 +26,7 @@ namespace pma {
 
 // kernels.hip
 hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int count, hipStream_t s);
-hipError_t launch_stencil(int prec, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
+hipError_t launch_stencil(int prec, int dim, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
 hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
                         hipStream_t s);
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
@@ -831,7 +831,7 @@ static void free_instance(pma_ctx* c, Instance& I) {
 // ------------------------------------------------------------------------------------------
 
 static constexpr int kStRows = 4, kStCols = 64;     // forward-Euler tiles
-static constexpr int kStTileR = 16, kStTileC = 64, kStTileC3 = 72;  // stencil tiles (3D: per plane)
+static constexpr int kStChunk = 16, kStWmax = 72;  // stencil: rows per chunk, widest block
 static constexpr int kRows = 16, kCols = 64, kStrip = 16;  // mode-product tiles
 static constexpr int kPhases = 8;
 
@@ -933,6 +933,60 @@ struct Batch {
     return a;
   }
 
+  // Stencil blocks of subdomain gs: W <= 72 columns of the last axis (balanced over the axis),
+  // marching `march` chunks (2D: 16-row chunks of axis 0; 3D: planes of axis 0 over 16 rows of
+  // axis 1) per workgroup.
+  void stencil_tiles(int gs, int march, std::vector<int4>& out) const {
+    const SubDev& sd = h_subs[gs];
+    const int n0 = sd.n[0], n1 = sd.n[1], nl = sd.n[sd.dim - 1];
+    const int nct = (nl + kStWmax - 1) / kStWmax;
+    const int W = (nl + nct - 1) / nct;
+    if (sd.dim == 2) {
+      const int rows = kStChunk * march;
+      for (int r = 0; r < n0; r += rows)
+        for (int c = 0; c < n1; c += W)
+          out.push_back(int4{gs, r, c | (std::min(W, n1 - c) << 16), std::min(rows, n0 - r)});
+    } else {
+      for (int p = 0; p < n0; p += march)
+        for (int r = 0; r < n1; r += kStChunk)
+          for (int c = 0; c < nl; c += W)
+            out.push_back(int4{gs, p | (std::min(march, n0 - p) << 16), r, c | (std::min(W, nl - c) << 16)});
+    }
+  }
+  // chunks per workgroup when not tuned: enough workgroups to fill the chip several times over
+  int st_march = 1;
+  int stencil_march_default() const {
+    size_t t1 = 0;
+    std::vector<int4> tmp;
+    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
+      tmp.clear();
+      stencil_tiles((int)gs, 1, tmp);
+      t1 += tmp.size();
+    }
+    return (int)std::max<size_t>(1, std::min<size_t>(64, t1 / 8192));
+  }
+  // the stencil tile table rebuilt for another march length (same device buffer: march 1 is the
+  // largest table); the captured step is dropped
+  void set_stencil_march(int march) {
+    st_march = march;
+    Table& t = tab[1];
+    t.h.clear();
+    t.rng.clear();
+    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
+      t.begin_sub();
+      stencil_tiles((int)gs, march, t.h);
+      t.end_sub();
+    }
+    if (t.h.size() > st_cap) thr(PMA_E_HIP, "stencil table exceeds its buffer");
+    HIPCHK(hipMemcpyAsync(t.d, t.h.data(), t.h.size() * 16, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
+  size_t st_cap = 0;
+
   void build() {
     HIPCHK(enable_large_lds());
     clear_device();
@@ -956,11 +1010,6 @@ struct Batch {
       // node is refilled from the same instance (transmission); held Dirichlet data of a lone
       // subdomain would be left behind by the shift
       id.pin = (I.tm.gamma > 0 && !I.single_sub_mode) ? 1 : 0;
-      // 2D stencils read artificial-boundary values from their owners; 3D runs the gather first
-      for (int k = 0; k < 3; ++k) {
-        id.own[k] = (!I.single_sub_mode && I.dim == 2 && k < I.dim) ? I.own_dev[k] : nullptr;
-        id.parts[k] = I.parts[k];
-      }
       h_insts.push_back(id);
       for (size_t s = 0; s < I.subs.size(); ++s) {
         const SubHost& S = I.subs[s];
@@ -988,6 +1037,12 @@ struct Batch {
         h_subs.push_back(sd);
       }
     }
+    st_march = stencil_march_default();
+    {
+      std::vector<int4> tmp;
+      for (size_t gs = 0; gs < h_subs.size(); ++gs) stencil_tiles((int)gs, 1, tmp);
+      st_cap = tmp.size();
+    }
     // tiles, subdomain by subdomain
     for (size_t q = 0; q < insts.size(); ++q) {
       Instance& I = *insts[q];
@@ -1005,14 +1060,7 @@ struct Batch {
         tr.count = (int)h_trans.size() - tr.first;
         tr_rng.push_back(tr);
         for (int ph = 1; ph < kPhases; ++ph) tab[ph].begin_sub();
-        if (I.dim == 2) {
-          for (int r = 0; r < n0; r += kStTileR)
-            for (int c = 0; c < n1; c += kStTileC) tab[1].h.push_back(int4{gs, r, c, 0});
-        } else {
-          for (int i0 = 0; i0 < n0; ++i0)
-            for (int r = 0; r < n1; r += kStTileR)
-              for (int c = 0; c < n2; c += kStTileC3) tab[1].h.push_back(int4{gs, i0, r, c});
-        }
+        stencil_tiles(gs, st_march, tab[1].h);
         if (I.tm.gamma == 0.0) {
           for (int r = 0; r < R; r += kStRows)
             for (int c = 0; c < C; c += kStCols) tab[2].h.push_back(int4{gs, r, c, 0});
@@ -1061,7 +1109,7 @@ struct Batch {
     size_t bytes = Arena::round(nsub * sizeof(SubDev)) + Arena::round(ninst * sizeof(InstDev)) +
                    Arena::round(h_trans.size() * 16 + 16) + Arena::round(nsub * el) +
                    Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4);
-    for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round(tab[ph].h.size() * 16 + 16);
+    for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
     if (bytes > dcap) {
       if (dmem) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1088,7 +1136,7 @@ struct Batch {
     d_subs = (SubDev*)take(nsub * sizeof(SubDev));
     d_insts = (InstDev*)take(ninst * sizeof(InstDev));
     d_tr = (int4*)take(h_trans.size() * 16 + 16);
-    for (int ph = 1; ph < kPhases; ++ph) tab[ph].d = (int4*)take(tab[ph].h.size() * 16 + 16);
+    for (int ph = 1; ph < kPhases; ++ph) tab[ph].d = (int4*)take((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
     d_dc = take(nsub * el);
     d_partials = (double*)take((size_t)(npartials + 1) * 8);
     d_shift = (double*)take(ninst * 8);
@@ -1130,7 +1178,7 @@ struct Batch {
     if (count <= 0) return;
     const Table& t = tab[ph];
     switch (ph) {
-      case 1: HIPCHK(launch_stencil(prec, t.d + first, count, sa, st)); break;
+      case 1: HIPCHK(launch_stencil(prec, stencil_dim_, t.d + first, count, sa, st)); break;
       case 2: HIPCHK(launch_euler(prec, t.d + first, count, part_base_eu + first, sa, st)); break;
       case 3: HIPCHK(launch_fwd_last(prec, t.d + first, count, t.maxld, sa, st)); break;
       case 4: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, 1, 0, 1, sa, st)); break;
@@ -1142,6 +1190,7 @@ struct Batch {
     }
   }
   int pair_src_ = 1;
+  int stencil_dim_ = 2;
 
   // one phase of a step: all subdomains in one launch, or one subdomain per launch (plain)
   void launch_phase(int ph, bool plain, hipStream_t st) {
@@ -1153,10 +1202,12 @@ struct Batch {
           if (tr_rng[s].count) HIPCHK(launch_transmit(prec, d_subs, d_tr + tr_rng[s].first, tr_rng[s].count, st));
       return;
     }
-    if (ph == 5) {
-      // the axis-0 pair reads T in 2D and F in 3D: launch the two groups separately
+    if (ph == 1 || ph == 5) {
+      // 2D and 3D subdomains take different stencil kernels, and the axis-0 pair reads T in 2D
+      // and F in 3D: launch the two groups separately
       for (int dim = 2; dim <= 3; ++dim) {
         pair_src_ = dim == 2 ? 1 : 0;
+        stencil_dim_ = dim;
         if (!plain) {
           // contiguous runs of subdomains of this dimension
           int s = 0;
@@ -1167,13 +1218,13 @@ struct Batch {
             }
             int e = s;
             while (e < nsub && h_subs[e].dim == dim) ++e;
-            const int f = tab[5].rng[s].first, l = tab[5].rng[e - 1].first + tab[5].rng[e - 1].count;
-            launch_range(5, f, l - f, st);
+            const int f = tab[ph].rng[s].first, l = tab[ph].rng[e - 1].first + tab[ph].rng[e - 1].count;
+            launch_range(ph, f, l - f, st);
             s = e;
           }
         } else {
           for (int s = 0; s < nsub; ++s)
-            if (h_subs[s].dim == dim) launch_range(5, tab[5].rng[s].first, tab[5].rng[s].count, st);
+            if (h_subs[s].dim == dim) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
         }
       }
       return;
@@ -1183,27 +1234,9 @@ struct Batch {
       for (int s = 0; s < nsub; ++s) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
   }
 
-  // 2D stencils read artificial-boundary values from their owners, so only 3D subdomains need the
-  // gather before the stencil (all of them are refreshed before the glue)
+  // a step: transmission gather (artificial nodes <- owners' time-n values), then the rest
   void launch_step(bool plain, hipStream_t st) {
-    launch_gather3(plain, st);
-    for (int ph = 1; ph < kPhases; ++ph) launch_phase(ph, plain, st);
-  }
-
-  void launch_gather3(bool plain, hipStream_t st) {
-    const int nsub = (int)h_subs.size();
-    int s = 0;
-    while (s < nsub) {
-      if (h_subs[s].dim != 3) {
-        ++s;
-        continue;
-      }
-      int e = s + 1;
-      while (e < nsub && h_subs[e].dim == 3 && !plain) ++e;
-      const int f = tr_rng[s].first, l = tr_rng[e - 1].first + tr_rng[e - 1].count;
-      if (l > f) HIPCHK(launch_transmit(prec, d_subs, d_tr + f, l - f, st));
-      s = e;
-    }
+    for (int ph = 0; ph < kPhases; ++ph) launch_phase(ph, plain, st);
   }
 
   // algorithmic work per step of each phase: 2 M N K flops per product; compulsory bytes with
@@ -2042,6 +2075,64 @@ int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, dou
     if (flops) flops[ph] = fl[ph];
     if (bytes) bytes[ph] = by[ph];
   }
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_set_march(pma_plan* P, int march) {
+  API_BEGIN
+  if (!P || march < 1 || march > 4096) return fail(PMA_E_INVAL, "march must be in 1..4096");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  P->batch->set_stencil_march(march);
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_autotune(pma_plan* P, int reps, int* march, double* ms, int cap, int* ncand) {
+  API_BEGIN
+  if (!P || reps <= 0 || !march) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  Batch& B = *P->batch;
+  hipStream_t st = P->ctx->stream;
+  // the longest useful march: every subdomain's axis 0 in one workgroup
+  int most = 1;
+  for (const SubDev& sd : B.h_subs) most = std::max(most, sd.dim == 2 ? (sd.n[0] + kStChunk - 1) / kStChunk : sd.n[0]);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = B.st_march, k = 0;
+  double best_ms = 1e300;
+  try {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int m = 1;; m *= 2) {
+      const int cand = std::min(m, most);
+      B.set_stencil_march(cand);
+      B.launch_phase(1, P->plain, st);  // warm
+      HIPCHK(hipEventRecord(e0, st));
+      for (int r = 0; r < reps; ++r) B.launch_phase(1, P->plain, st);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      const double per = (double)t / reps;
+      if (ms && k < cap) ms[k] = per;
+      ++k;
+      if (per < best_ms) {
+        best_ms = per;
+        best = cand;
+      }
+      if (cand == most || m >= 64) break;
+    }
+    B.set_stencil_march(best);
+  } catch (Err&) {
+    hipStreamSynchronize(st);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    throw;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *march = best;
+  if (ncand) *ncand = k;
   return PMA_OK;
   API_END
 }

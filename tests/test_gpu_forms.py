@@ -134,6 +134,31 @@ def test_plan_steps_in_pieces_equal_one_solve(ctx, B):
     np.testing.assert_array_equal(m, whole)
 
 
+@pytest.mark.parametrize("wl", ["sine2d", "shell3d", "bumps"])
+def test_stencil_march_and_autotune_bitwise(ctx, B, wl):
+    # the stencil's launch shape (chunks per workgroup) changes no result
+    if wl == "sine2d":
+        ws = [W.sine_dd(n=161, parts=(2, 3), overlap=6, steps=12)]
+    elif wl == "shell3d":
+        ws = [W.shell_dd(n=41, parts=(2, 2, 2), overlap=4, steps=8)]
+    else:
+        ws = W.bumps_batch(6, steps=10, n_lo=33, n_hi=97)
+    outs = []
+    for march in (None, 1, 2, 3, 64, "tune"):
+        with B.Plan(ctx, ws, "split16") as p:
+            if march == "tune":
+                choice, ms = p.autotune(3)
+                assert choice >= 1 and len(ms) >= 1 and all(t > 0 for t in ms)
+            elif march is not None:
+                p.set_march(march)
+            p.step(ws[0]["time"]["steps"])
+            p.sync()
+            outs.append([p.mesh(i)[0] for i in range(len(ws))])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_warm_start_and_psi_out(ctx):
     # 30 steps, then 20 more from the oracle's Psi, against 50 oracle steps; Psi itself is
     # returned with the constants the FP32 path removed added back
