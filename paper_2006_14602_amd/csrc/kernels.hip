@@ -265,6 +265,12 @@ __device__ inline void halo_commit(T* slot, const HaloCols& hc, const T (&pre)[2
   }
 }
 
+// Wait until every vector-memory load of this wave has returned (s_waitcnt vmcnt(0); expcnt and
+// lgkmcnt left free).  Issued once after the per-block parameter loads: the in-order vmcnt
+// counter could otherwise make the first use of a parameter inside the chunk loop wait for the
+// next chunk's prefetch as well.
+__device__ inline void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // this thread's output nodes of a 16 x W chunk: linear index tid + 256 m -> (row << 8) | column
 __device__ inline void chunk_nodes(int W, int (&pk)[kStPts]) {
 #pragma unroll
@@ -304,6 +310,7 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
   const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
   const int rend = row0 + nrows;
+  vmem_drain();
   issue(row0);
   for (int rb = row0; rb < rend; rb += kStR) {
     if (rb != row0) __syncthreads();  // every thread is done reading the previous chunk
@@ -370,6 +377,7 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), rh22 = T(1) / (h2 * h2);
   const T r4h01 = T(1) / (T(4) * h0 * h1), r4h02 = T(1) / (T(4) * h0 * h2), r4h12 = T(1) / (T(4) * h1 * h2);
   // plane p0 - 1 -> slot 0, p0 -> slot 1, p0 + q + 1 -> slot (q + 2) % 3
+  vmem_drain();
   issue(p0 - 1);
   halo_commit(sm, hc, pre);
   issue(p0);
