@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", type=int, default=600, help="requests in the serving stream (0: skip)")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["split16", "fp32", "fp64plain"], default=None,
+    ap.add_argument("--only", choices=["split16", "fp32", "fp64plain", "stencil_large"], default=None,
                     help="time one form of the headline workload only (profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 10 times (calibrates HBM byte counters)")
@@ -192,6 +192,11 @@ def main():
     import torch
     from paper_2006_14602_amd import binding, workloads
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only == "stencil_large":
+        ctx = binding.Context(0, budget_bytes=12 << 30)
+        print(json.dumps({"stencil_hbm_large": stencil_roofline(ctx, binding, workloads)}))
+        ctx.close()
+        return
     w = workloads.sine_dd()
     ctx = binding.Context(0, budget_bytes=12 << 30)
     forms = {}

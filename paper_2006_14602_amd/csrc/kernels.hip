@@ -40,71 +40,33 @@ __device__ inline gmem<T>* gpw(void* p) { return (gmem<T>*)p; }
 // monitor: log rho(x), computed as log1p of the excess over 1 where rho = 1 + (...)
 // ------------------------------------------------------------------------------------------
 
-__device__ inline float dexp(float x) { return expf(x); }
-__device__ inline double dexp(double x) { return exp(x); }
-__device__ inline float dlog1p(float x) { return log1pf(x); }
-__device__ inline double dlog1p(double x) { return log1p(x); }
-__device__ inline float dlog(float x) { return logf(x); }
-__device__ inline double dlog(double x) { return log(x); }
-__device__ inline float dsinpi(float x) { return sinpif(x); }
-__device__ inline double dsinpi(double x) { return sinpi(x); }
 // sin(2 pi x): the FP32 form uses the hardware sine, whose argument is in revolutions
 __device__ inline float sin2pi(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ inline double sin2pi(double x) { return sinpi(2.0 * x); }
-
-// sech^2(z) = 4 e^{-2|z|} / (1 + e^{-2|z|})^2 (no overflow for large |z|)
-template <typename T>
-__device__ inline T sech2(T z) {
-  T e = dexp(T(-2) * fabs(z));
-  T q = T(1) + e;
-  return T(4) * e / (q * q);
-}
 
 // the monitor parameters of an instance in the working precision
 __device__ inline const MonP<float>& mon_of(const InstDev& I, float) { return I.monf; }
 __device__ inline const MonP<double>& mon_of(const InstDev& I, double) { return I.mond; }
 
-// fast FP32 forms: v_exp / v_log / v_rcp based exp, log and reciprocal
-__device__ inline float fexp(float x) { return __expf(x); }
-__device__ inline double fexp(double x) { return exp(x); }
+// e^x as expk(x * kLog2e): FP32 takes the hardware 2^x with the factor log2(e) folded into the
+// monitor constants; FP64 calls exp.  frcp: hardware reciprocal (FP32), division (FP64).
+template <typename T> struct ExpK;
+template <> struct ExpK<float> {
+  static constexpr float kLog2e = 1.44269504088896341f;
+  static __device__ inline float ex(float x) { return __builtin_amdgcn_exp2f(x); }
+};
+template <> struct ExpK<double> {
+  static constexpr double kLog2e = 1.0;
+  static __device__ inline double ex(double x) { return exp(x); }
+};
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double frcp(double x) { return 1.0 / x; }
 
+// 4 a e / (1 + e)^2 = a sech^2(z) for e = e^{-2|z|} (no overflow for large |z|)
 template <typename T>
-__device__ inline T sech2_fast(T z) {
-  const T e = fexp(T(-2) * fabs(z));
+__device__ inline T sech2_of(T a4, T e) {
   const T q = T(1) + e;
-  return T(4) * e * frcp(q * q);
-}
-
-// rho - 1 (exact excess for the "1 + ..." monitors; the constant monitor returns amp - 1)
-template <typename T>
-__device__ inline T rho_excess(const MonP<T>& m, int dim, T x0, T x1, T x2) {
-  switch (m.kind) {
-    case MON_CONST:
-      return m.amp - T(1);
-    case MON_RADIAL: {
-      const T d0 = x0 - m.c[0], d1 = x1 - m.c[1], d2 = dim == 3 ? x2 - m.c[2] : T(0);
-      return m.amp * sech2_fast(m.k * ((d0 * d0 + d1 * d1 + d2 * d2) - m.r02));
-    }
-    case MON_SINE:
-      return m.amp * sech2_fast(m.k * (x1 - m.c[1] - m.r0 * sin2pi(x0)));
-    case MON_GAUSS: {
-      T acc = T(0);
-      for (int b = 0; b < m.nb; ++b) {
-        const T d0 = x0 - m.bc[b][0], d1 = x1 - m.bc[b][1], d2 = dim == 3 ? x2 - m.bc[b][2] : T(0);
-        acc += m.bamp[b] * fexp((d0 * d0 + d1 * d1 + d2 * d2) * m.bnh[b]);
-      }
-      return acc;
-    }
-    case MON_SEPARABLE: {
-      T p = (T(1) + m.aa[0] * sech2_fast(m.ka[0] * (x0 - m.c[0]))) *
-            (T(1) + m.aa[1] * sech2_fast(m.ka[1] * (x1 - m.c[1])));
-      if (dim == 3) p *= T(1) + m.aa[2] * sech2_fast(m.ka[2] * (x2 - m.c[2]));
-      return p - T(1);
-    }
-  }
-  return T(0);
+  return a4 * e * frcp(q * q);
 }
 
 // log(rho (1 + e)): FP64 keeps log1p of both excesses; FP32 takes one hardware log2 of the product
@@ -117,10 +79,6 @@ __device__ inline float log_rho_det(float rex, float e) {
 __device__ inline bool is_artificial(int art, int k, int i, int n) {
   return (i == 0 && ((art >> (2 * k)) & 1)) || (i == n - 1 && ((art >> (2 * k + 1)) & 1));
 }
-
-// mirror index for the Neumann ghost of phi: -1 -> 1, n -> n - 2
-__device__ inline int mlo(int i) { return i > 0 ? i - 1 : 1; }
-__device__ inline int mhi(int i, int n) { return i < n - 1 ? i + 1 : n - 2; }
 
 template <typename T>
 __device__ inline bool finite_(T x) { return isfinite(x); }
@@ -137,9 +95,13 @@ __device__ inline int mirror_clamp(int i, int n) {
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
 
-// Monitor parameters of one kind, held in registers for a whole tile so that evaluating rho at a
-// node reads no memory (the stores to F could alias the descriptors, which would otherwise force
-// a reload of every parameter per node).  excess<DIM>(x) = rho(x) - 1.
+// mirror index for the Neumann ghost of phi: -1 -> 1, n -> n - 2
+__device__ inline int mlo(int i) { return i > 0 ? i - 1 : 1; }
+__device__ inline int mhi(int i, int n) { return i < n - 1 ? i + 1 : n - 2; }
+
+// Monitor parameters of one kind, held in registers for a whole block so that evaluating rho at
+// a node reads no memory, with the constants of the exponentials pre-scaled (nk = -2 k log2 e for
+// the sech^2 kinds).  excess<DIM>(x) = rho(x) - 1.
 template <typename T, int MK> struct MonReg;
 
 template <typename T> struct MonReg<T, MON_CONST> {
@@ -149,22 +111,23 @@ template <typename T> struct MonReg<T, MON_CONST> {
 };
 
 template <typename T> struct MonReg<T, MON_RADIAL> {
-  T amp, k, c0, c1, c2, r02;
+  T a4, nk, c0, c1, c2, r02;
   __device__ explicit MonReg(const MonP<T>& m)
-      : amp(m.amp), k(m.k), c0(m.c[0]), c1(m.c[1]), c2(m.c[2]), r02(m.r02) {}
+      : a4(T(4) * m.amp), nk(T(-2) * m.k * ExpK<T>::kLog2e), c0(m.c[0]), c1(m.c[1]), c2(m.c[2]), r02(m.r02) {}
   template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
     const T d0 = x0 - c0, d1 = x1 - c1;
     T r2 = d0 * d0 + d1 * d1;
     if (DIM == 3) r2 += (x2 - c2) * (x2 - c2);
-    return amp * sech2_fast(k * (r2 - r02));
+    return sech2_of(a4, ExpK<T>::ex(nk * fabs(r2 - r02)));
   }
 };
 
 template <typename T> struct MonReg<T, MON_SINE> {
-  T amp, k, c1, r0;
-  __device__ explicit MonReg(const MonP<T>& m) : amp(m.amp), k(m.k), c1(m.c[1]), r0(m.r0) {}
+  T a4, nk, c1, r0;
+  __device__ explicit MonReg(const MonP<T>& m)
+      : a4(T(4) * m.amp), nk(T(-2) * m.k * ExpK<T>::kLog2e), c1(m.c[1]), r0(m.r0) {}
   template <int DIM> __device__ T excess(T x0, T x1, T) const {
-    return amp * sech2_fast(k * (x1 - c1 - r0 * sin2pi(x0)));
+    return sech2_of(a4, ExpK<T>::ex(nk * fabs(x1 - c1 - r0 * sin2pi(x0))));
   }
 };
 
@@ -175,7 +138,7 @@ template <typename T> struct MonReg<T, MON_GAUSS> {
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       amp[b] = m.bamp[b];
-      nh[b] = m.bnh[b];
+      nh[b] = m.bnh[b] * ExpK<T>::kLog2e;
       c0[b] = m.bc[b][0];
       c1[b] = m.bc[b][1];
       c2[b] = m.bc[b][2];
@@ -189,36 +152,44 @@ template <typename T> struct MonReg<T, MON_GAUSS> {
         const T d0 = x0 - c0[b], d1 = x1 - c1[b];
         T r2 = d0 * d0 + d1 * d1;
         if (DIM == 3) r2 += (x2 - c2[b]) * (x2 - c2[b]);
-        acc += amp[b] * fexp(r2 * nh[b]);
+        acc += amp[b] * ExpK<T>::ex(r2 * nh[b]);
       }
     return acc;
   }
 };
 
 template <typename T> struct MonReg<T, MON_SEPARABLE> {
-  T aa[3], ka[3], c[3];
+  T a4[3], nk[3], c[3];
   __device__ explicit MonReg(const MonP<T>& m) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      aa[q] = m.aa[q];
-      ka[q] = m.ka[q];
+      a4[q] = T(4) * m.aa[q];
+      nk[q] = T(-2) * m.ka[q] * ExpK<T>::kLog2e;
       c[q] = m.c[q];
     }
   }
+  __device__ T factor(int q, T x) const { return T(1) + sech2_of(a4[q], ExpK<T>::ex(nk[q] * fabs(x - c[q]))); }
   template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
-    T p = (T(1) + aa[0] * sech2_fast(ka[0] * (x0 - c[0]))) * (T(1) + aa[1] * sech2_fast(ka[1] * (x1 - c[1])));
-    if (DIM == 3) p *= T(1) + aa[2] * sech2_fast(ka[2] * (x2 - c[2]));
+    T p = factor(0, x0) * factor(1, x1);
+    if (DIM == 3) p *= factor(2, x2);
     return p - T(1);
   }
 };
 
-// F at a live node from rho - 1 and det(I + D^2 phi) - 1; status bits collect in `bad`
+// Status of the nodes of a block, folded into two registers per thread: the least 1 + e seen
+// (det(I + D^2 phi) <= 0 is a tangled mesh) and a sum of 0 * F (inf or NaN stays non-finite).
 template <typename T>
-__device__ inline T rhs_value(T lvt, T rex, T e, int& bad) {
-  const T f = lvt + log_rho_det(rex, e);
-  bad |= !(T(1) + e > T(0)) ? ST_TANGLED : (finite_(f) ? 0 : ST_NONFINITE);
-  return f;
-}
+struct NodeCheck {
+  T min_det = T(1);
+  T nonfin = T(0);
+  __device__ inline void add(T e, T f) {
+    min_det = fmin(min_det, T(1) + e);
+    nonfin = fma(f, T(0), nonfin);
+  }
+  __device__ inline int bits() const {
+    return (!(min_det > T(0)) ? ST_TANGLED : 0) | (finite_(nonfin) ? 0 : ST_NONFINITE);
+  }
+};
 
 // Per-workgroup constants of a subdomain, copied into registers once.
 template <typename T>
@@ -227,42 +198,70 @@ struct StencilCtx {
   int n0, n1, n2, off0, off1, off2, art, inst;
 };
 
+// Global-memory view of a pointer taken from a descriptor (see gmem): loads and stores through it
+// are global (not flat), and a wave-uniform base keeps their addresses in scalar registers.
+template <typename T>
+__device__ inline const gmem<T>* byte_off(const gmem<T>* base, unsigned off) {
+  return (const gmem<T>*)((const gmem<char>*)base + off);
+}
+template <typename T>
+__device__ inline gmem<T>* byte_off(gmem<T>* base, unsigned off) {
+  return (gmem<T>*)((gmem<char>*)base + off);
+}
+
 constexpr int kStR = 16;                               // output rows per chunk (2D: i0, 3D: i1)
-constexpr int kStWmax = 72;                            // widest tile along the last axis
+constexpr int kStWmax = 72;                            // widest block along the last axis
 constexpr int kStS = kStWmax + 2;                      // LDS row stride
 constexpr int kStHR = kStR + 2;                        // staged rows per chunk
 constexpr int kStPts = (kStR * kStWmax + 255) / 256;   // output nodes per thread per chunk
 constexpr int kStLd = (kStHR + 3) / 4;                 // staged rows per wave
 
-// Halo staging of one 18 x (W + 2) block: wave w stages rows w, w + 4, ..; lane l column l and,
-// for blocks wider than a wave, column 64 + l.  Values land in registers first, so the next
-// chunk's loads are in flight while the current chunk is computed.
+// Halo staging of one 18 x (W + 2) block, a fixed number of loads per thread so that the wait
+// before a commit only has to cover that block's loads: wave w loads rows w, w + 4, .., w + 16
+// at column lane (a row past the 18th is loaded clamped and not staged), and thread t < 180
+// loads element (t / 10, 64 + t % 10) of the columns beyond the wave width (clamped when the
+// block is narrower).  Values land in registers first, so later chunks' loads are in flight
+// while the current chunk is computed.  Column offsets (bytes) are fixed for the block.
+constexpr int kStPre = kStLd + 1;  // loads per thread per chunk
+
 struct HaloCols {
-  int gjA, gjB;   // mirrored index along the last axis of the two columns
-  bool okA, okB;  // column inside the block
+  unsigned bA;  // byte offset of column `lane` (mirrored index along the last axis)
+  unsigned bE;  // byte offset of this thread's element beyond the wave width
+  int rE;       // its row within the block (clamped to the last staged row)
+  int sE;       // its LDS offset within the block, or -1 (no such element)
 };
 
+template <typename T>
 __device__ inline HaloCols halo_cols(int col0, int W, int n) {
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, t = threadIdx.x;
   HaloCols h;
-  h.okA = lane < W + 2;
-  h.okB = 64 + lane < W + 2;
-  h.gjA = mirror_clamp(col0 + lane - 1, n);
-  h.gjB = mirror_clamp(col0 + 63 + lane, n);
+  h.bA = (unsigned)mirror_clamp(col0 + lane - 1, n) * sizeof(T);
+  const int re = t / 10, ce = 64 + t % 10;
+  const bool ok = re < kStHR && ce < W + 2;
+  h.rE = min(re, kStHR - 1);
+  h.bE = (unsigned)mirror_clamp(col0 + ce - 1, n) * sizeof(T);
+  h.sE = ok ? re * kStS + ce : -1;
   return h;
 }
 
+// rowp[k]: base of staged row wave + 4 k; rowE: base of the row of this thread's extra element
 template <typename T>
-__device__ inline void halo_commit(T* slot, const HaloCols& hc, const T (&pre)[2 * kStLd]) {
+__device__ inline void halo_issue(T (&pre)[kStPre], const HaloCols& hc, const gmem<T>* const (&rowp)[kStLd],
+                                  const gmem<T>* rowE) {
+#pragma unroll
+  for (int k = 0; k < kStLd; ++k) pre[k] = *byte_off(rowp[k], hc.bA);
+  pre[kStLd] = *byte_off(rowE, hc.bE);
+}
+
+template <typename T>
+__device__ inline void halo_commit(T* slot, const HaloCols& hc, const T (&pre)[kStPre]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kStLd; ++k) {
     const int r = wave + 4 * k;
-    if (r < kStHR) {
-      if (hc.okA) slot[r * kStS + lane] = pre[2 * k];
-      if (hc.okB) slot[r * kStS + 64 + lane] = pre[2 * k + 1];
-    }
+    if (r < kStHR) slot[r * kStS + lane] = pre[k];
   }
+  if (hc.sE >= 0) slot[hc.sE] = pre[kStLd];
 }
 
 // Wait until every vector-memory load of this wave has returned (s_waitcnt vmcnt(0); expcnt and
@@ -271,14 +270,27 @@ __device__ inline void halo_commit(T* slot, const HaloCols& hc, const T (&pre)[2
 // next chunk's prefetch as well.
 __device__ inline void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// this thread's output nodes of a 16 x W chunk: linear index tid + 256 m -> (row << 8) | column
-__device__ inline void chunk_nodes(int W, int (&pk)[kStPts]) {
+// The output nodes of a thread within a 16-row x W-column chunk: slot m is linear index
+// tid + 256 m, fixed for every chunk of the block.  Every slot is evaluated (an absent one reads
+// a valid LDS cell) and masked afterwards, so the node loop has no divergent branch but the
+// store's.
+template <typename T>
+struct Slots {
+  int lds[kStPts];       // LDS element offset of the node's centre
+  unsigned out[kStPts];  // byte offset in the chunk's output block
+  int row[kStPts];       // row within the chunk (kStR: no node)
+  T xc[kStPts];          // coordinate along the last axis: a + (global index) h
+  int valid;             // bit m: slot m holds a node
+  int live;              // bit m: ... whose column (3D: row and column) is not artificial
+  int wave;              // bit m: some lane of this wave holds a node in slot m (uniform)
+};
+
+// bit m of the result: some lane of the wave has bit m set in `bits`
+__device__ inline int wave_any_bits(int bits) {
+  int r = 0;
 #pragma unroll
-  for (int m = 0; m < kStPts; ++m) {
-    const int idx = (int)threadIdx.x + 256 * m;
-    const int rr = idx / W;
-    pk[m] = idx < kStR * W ? (rr << 8) | (idx - rr * W) : -1;
-  }
+  for (int m = 0; m < kStPts; ++m) r |= (__ballot((bits >> m) & 1) != 0) ? 1 << m : 0;
+  return __builtin_amdgcn_readfirstlane(r);
 }
 
 // 2D: rows [row0, row0 + nrows) x columns [col0, col0 + W) of a subdomain, 16 rows per chunk.
@@ -289,58 +301,92 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
   const gmem<T>* __restrict__ phi = (const gmem<T>*)phi_;
   gmem<T>* __restrict__ F = (gmem<T>*)F_;
   const MonReg<T, MK> M(mp);
-  const int wave = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int n0 = K.n0, n1 = K.n1;
-  const HaloCols hc = halo_cols(col0, W, n1);
-  T pre[2 * kStLd];
-  auto issue = [&](int rb) {
-#pragma unroll
-    for (int k = 0; k < kStLd; ++k) {
-      const int r = wave + 4 * k;
-      if (r < kStHR) {
-        const gmem<T>* row = phi + (long)mirror_clamp(rb + r - 1, n0) * n1;
-        if (hc.okA) pre[2 * k] = row[hc.gjA];
-        if (hc.okB) pre[2 * k + 1] = row[hc.gjB];
-      }
-    }
-  };
-  int pk[kStPts];
-  chunk_nodes(W, pk);
+  const HaloCols hc = halo_cols<T>(col0, W, n1);
   const T h0 = K.h0, h1 = K.h1;
+  Slots<T> sl;
+  sl.valid = 0;
+  sl.live = 0;
+#pragma unroll
+  for (int m = 0; m < kStPts; ++m) {
+    const int idx = (int)threadIdx.x + 256 * m;
+    const int rr = idx / W, cc = idx - rr * W;
+    const bool ok = idx < kStR * W;
+    sl.lds[m] = ok ? (rr + 1) * kStS + cc + 1 : kStS + 1;
+    sl.out[m] = (unsigned)(rr * n1 + cc) * sizeof(T);
+    sl.row[m] = ok ? rr : kStR;
+    sl.xc[m] = K.a1 + T(K.off1 + col0 + cc) * h1;
+    sl.valid |= ok ? 1 << m : 0;
+    sl.live |= (ok && !is_artificial(K.art, 1, col0 + cc, n1)) ? 1 << m : 0;
+  }
+  sl.wave = wave_any_bits(sl.valid);
   const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
+  NodeCheck<T> chk;
   const int rend = row0 + nrows;
-  vmem_drain();
-  issue(row0);
-  for (int rb = row0; rb < rend; rb += kStR) {
+  // two chunks' loads in flight: the registers of chunk k are reloaded with chunk k + 2 as soon
+  // as chunk k is in LDS (the loop is unrolled by two so each register set has fixed names)
+  T preA[kStPre], preB[kStPre];
+  auto issue = [&](T (&pre)[kStPre], int rb) {
+    const gmem<T>* rowp[kStLd];
+#pragma unroll
+    for (int k = 0; k < kStLd; ++k) rowp[k] = phi + (long)mirror_clamp(rb + wv + 4 * k - 1, n0) * n1;
+    halo_issue(pre, hc, rowp, phi + (long)mirror_clamp(rb + hc.rE - 1, n0) * n1);
+  };
+  auto chunk = [&](T (&pre)[kStPre], int rb) {
     if (rb != row0) __syncthreads();  // every thread is done reading the previous chunk
     halo_commit(sm, hc, pre);
     __syncthreads();
-    if (rb + kStR < rend) issue(rb + kStR);
+    // issued unconditionally (past the block it loads clamped rows just read): the number of
+    // memory operations between a load and its use must not depend on the path, or the wait
+    // before the commit would have to drain the other register set's loads as well
+    issue(pre, rb + 2 * kStR);
+    gmem<T>* Fc = F + (long)rb * n1 + col0;
+    const int g0 = K.off0 + rb;  // global row index of the chunk's first row
+    // the first and last chunks may hold rows beyond the block or on an artificial face
+    int store = sl.valid, live = sl.live;
+    const int rlim = min(kStR, rend - rb);
+    const int rlo = (rb == 0 && (K.art & 1)) ? 0 : -1;
+    const int rhi = (rb + kStR > n0 - 1 && (K.art & 2)) ? n0 - 1 - rb : -1;
+    if (rlim < kStR || rlo >= 0 || rhi >= 0) {
+#pragma unroll
+      for (int m = 0; m < kStPts; ++m) {
+        const int rr = sl.row[m];
+        if (rr >= rlim) store &= ~(1 << m);
+        if (rr >= rlim || rr == rlo || rr == rhi) live &= ~(1 << m);
+      }
+    }
 #pragma unroll
     for (int m = 0; m < kStPts; ++m) {
-      if (pk[m] < 0) continue;
-      const int rr = pk[m] >> 8, cc = pk[m] & 255;
-      const int i = rb + rr, j = col0 + cc;
-      if (i >= rend) continue;
-      const long v = (long)i * n1 + j;
-      if (is_artificial(K.art, 0, i, n0) || is_artificial(K.art, 1, j, n1)) {
-        F[v] = T(0);
-        continue;
-      }
-      const int o = (rr + 1) * kStS + cc + 1;
-      const T c0 = sm[o];
-      const T xm = sm[o - kStS], xp = sm[o + kStS], ym = sm[o - 1], yp = sm[o + 1];
+      if (!((sl.wave >> m) & 1)) continue;  // no node of this wave in slot m (uniform branch)
+      const T* c = sm + sl.lds[m];
+      const T c0 = c[0];
+      const T xm = c[-kStS], xp = c[kStS], ym = c[-1], yp = c[1];
       const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
       const T hxx = (xp - T(2) * c0 + xm) * rh00;
       const T hyy = (yp - T(2) * c0 + ym) * rh11;
-      const T hxy = (sm[o + kStS + 1] - sm[o + kStS - 1] - sm[o - kStS + 1] + sm[o - kStS - 1]) * r4h01;
+      const T hxy = (c[kStS + 1] - c[kStS - 1] - c[-kStS + 1] + c[-kStS - 1]) * r4h01;
       const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
-      const T x0 = K.a0 + T(K.off0 + i) * h0 + gx;
-      const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
-      F[v] = rhs_value(K.lvt, M.template excess<2>(x0, x1, T(0)), e, bad);
+      // a + (global index) h, rounded as for any other tiling of the same grid
+      const T x0 = K.a0 + T(g0 + sl.row[m]) * h0 + gx;
+      const T fv = K.lvt + log_rho_det(M.template excess<2>(x0, sl.xc[m] + gy, T(0)), e);
+      const bool lv = (live >> m) & 1;
+      const T f = lv ? fv : T(0);
+      chk.add(lv ? e : T(0), f);
+      if ((store >> m) & 1) *byte_off(Fc, sl.out[m]) = f;
     }
+  };
+  vmem_drain();
+  issue(preA, row0);
+  issue(preB, row0 + kStR);
+  int rb = row0;
+  for (; rb + kStR < rend; rb += 2 * kStR) {  // both chunks of a pair on every path
+    chunk(preA, rb);
+    chunk(preB, rb + kStR);
   }
+  if (rb < rend) chunk(preA, rb);
+  bad |= chk.bits();
 }
 
 // 3D: planes [p0, p0 + np) of a 16-row (i1) x W-column (i2) block; a ring of three staged planes
@@ -352,80 +398,97 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
   const gmem<T>* __restrict__ phi = (const gmem<T>*)phi_;
   gmem<T>* __restrict__ F = (gmem<T>*)F_;
   const MonReg<T, MK> M(mp);
-  const int wave = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int n0 = K.n0, n1 = K.n1, n2 = K.n2;
-  const HaloCols hc = halo_cols(col0, W, n2);
+  const HaloCols hc = halo_cols<T>(col0, W, n2);
   constexpr int PL = kStHR * kStS;
-  T pre[2 * kStLd];
-  auto issue = [&](int p) {
-    const int gp = mirror_clamp(p, n0);
-#pragma unroll
-    for (int k = 0; k < kStLd; ++k) {
-      const int r = wave + 4 * k;
-      if (r < kStHR) {
-        const int gi = mirror_clamp(row0 + r - 1, n1);
-        const gmem<T>* row = phi + ((long)gp * n1 + gi) * n2;
-        if (hc.okA) pre[2 * k] = row[hc.gjA];
-        if (hc.okB) pre[2 * k + 1] = row[hc.gjB];
-      }
-    }
-  };
-  int pk[kStPts];
-  chunk_nodes(W, pk);
   const T h0 = K.h0, h1 = K.h1, h2 = K.h2;
+  Slots<T> sl;
+  T x1s[kStPts];
+  sl.valid = 0;
+  sl.live = 0;
+#pragma unroll
+  for (int m = 0; m < kStPts; ++m) {
+    const int idx = (int)threadIdx.x + 256 * m;
+    const int rr = idx / W, cc = idx - rr * W;
+    const int j = row0 + rr, k = col0 + cc;
+    const bool ok = idx < kStR * W && j < n1;
+    sl.lds[m] = ok ? (rr + 1) * kStS + cc + 1 : kStS + 1;
+    sl.out[m] = (unsigned)(rr * n2 + cc) * sizeof(T);
+    sl.row[m] = ok ? rr : kStR;
+    sl.xc[m] = K.a2 + T(K.off2 + k) * h2;
+    x1s[m] = K.a1 + T(K.off1 + j) * h1;
+    sl.valid |= ok ? 1 << m : 0;
+    sl.live |= (ok && !is_artificial(K.art, 1, j, n1) && !is_artificial(K.art, 2, k, n2)) ? 1 << m : 0;
+  }
+  sl.wave = wave_any_bits(sl.valid);
   const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1), r2h2 = T(1) / (T(2) * h2);
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), rh22 = T(1) / (h2 * h2);
   const T r4h01 = T(1) / (T(4) * h0 * h1), r4h02 = T(1) / (T(4) * h0 * h2), r4h12 = T(1) / (T(4) * h1 * h2);
-  // plane p0 - 1 -> slot 0, p0 -> slot 1, p0 + q + 1 -> slot (q + 2) % 3
-  vmem_drain();
-  issue(p0 - 1);
-  halo_commit(sm, hc, pre);
-  issue(p0);
-  halo_commit(sm + PL, hc, pre);
-  issue(p0 + 1);
-  for (int q = 0; q < np; ++q) {
+  NodeCheck<T> chk;
+  // plane p0 - 1 -> LDS slot 0, p0 -> slot 1, p0 + q + 1 -> slot (q + 2) % 3; two planes' loads in
+  // flight (register sets A / B alternate, the loop is unrolled by two)
+  T preA[kStPre], preB[kStPre];
+  auto issue = [&](T (&pre)[kStPre], int p) {
+    const long pbase = (long)mirror_clamp(p, n0) * n1;
+    const gmem<T>* rowp[kStLd];
+#pragma unroll
+    for (int k = 0; k < kStLd; ++k) rowp[k] = phi + (pbase + mirror_clamp(row0 + wv + 4 * k - 1, n1)) * n2;
+    halo_issue(pre, hc, rowp, phi + (pbase + mirror_clamp(row0 + hc.rE - 1, n1)) * n2);
+  };
+  auto plane = [&](T (&pre)[kStPre], int q) {
     const int p = p0 + q;
     __syncthreads();  // the slot about to be refilled is no longer read
     halo_commit(sm + ((q + 2) % 3) * PL, hc, pre);
     __syncthreads();
-    if (q + 1 < np) issue(p + 2);
-    const T* sp = sm + (q % 3) * PL;
-    const T* sc = sm + ((q + 1) % 3) * PL;
-    const T* sn = sm + ((q + 2) % 3) * PL;
-    const bool art0 = is_artificial(K.art, 0, p, n0);
+    issue(pre, p + 3);  // unconditional, as in the 2D march
+    const int sp = (q % 3) * PL, scur = ((q + 1) % 3) * PL, sn = ((q + 2) % 3) * PL;
+    const int live = is_artificial(K.art, 0, p, n0) ? 0 : sl.live;
     const T x0b = K.a0 + T(K.off0 + p) * h0;
+    gmem<T>* Fc = F + ((long)p * n1 + row0) * n2 + col0;
 #pragma unroll
     for (int m = 0; m < kStPts; ++m) {
-      if (pk[m] < 0) continue;
-      const int rr = pk[m] >> 8, cc = pk[m] & 255;
-      const int j = row0 + rr, k = col0 + cc;
-      if (j >= n1) continue;
-      const long v = ((long)p * n1 + j) * n2 + k;
-      if (art0 || is_artificial(K.art, 1, j, n1) || is_artificial(K.art, 2, k, n2)) {
-        F[v] = T(0);
-        continue;
-      }
-      const int o = (rr + 1) * kStS + cc + 1;
-      const T c0 = sc[o];
-      const T xm = sp[o], xp = sn[o];
-      const T ym = sc[o - kStS], yp = sc[o + kStS];
-      const T zm = sc[o - 1], zp = sc[o + 1];
+      if (!((sl.wave >> m) & 1)) continue;  // no node of this wave in slot m (uniform branch)
+      const T* c = sm + scur + sl.lds[m];
+      const T* a = sm + sp + sl.lds[m];
+      const T* b = sm + sn + sl.lds[m];
+      const T c0 = c[0];
+      const T xm = a[0], xp = b[0];
+      const T ym = c[-kStS], yp = c[kStS];
+      const T zm = c[-1], zp = c[1];
       const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1, gz = (zp - zm) * r2h2;
-      const T a = (xp - T(2) * c0 + xm) * rh00;
-      const T b = (yp - T(2) * c0 + ym) * rh11;
-      const T c = (zp - T(2) * c0 + zm) * rh22;
-      const T d01 = (sn[o + kStS] - sn[o - kStS] - sp[o + kStS] + sp[o - kStS]) * r4h01;
-      const T d02 = (sn[o + 1] - sn[o - 1] - sp[o + 1] + sp[o - 1]) * r4h02;
-      const T d12 = (sc[o + kStS + 1] - sc[o + kStS - 1] - sc[o - kStS + 1] + sc[o - kStS - 1]) * r4h12;
+      const T d00 = (xp - T(2) * c0 + xm) * rh00;
+      const T d11 = (yp - T(2) * c0 + ym) * rh11;
+      const T d22 = (zp - T(2) * c0 + zm) * rh22;
+      const T d01 = (b[kStS] - b[-kStS] - a[kStS] + a[-kStS]) * r4h01;
+      const T d02 = (b[1] - b[-1] - a[1] + a[-1]) * r4h02;
+      const T d12 = (c[kStS + 1] - c[kStS - 1] - c[-kStS + 1] + c[-kStS - 1]) * r4h12;
       // det(I + H) - 1 = tr H + (sum of principal 2x2 minors) + det H
-      const T tr = a + b + c;
-      const T m2 = (a * b - d01 * d01) + (a * c - d02 * d02) + (b * c - d12 * d12);
-      const T d3 = a * (b * c - d12 * d12) - d01 * (d01 * c - d12 * d02) + d02 * (d01 * d12 - b * d02);
-      const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
-      const T x2 = K.a2 + T(K.off2 + k) * h2 + gz;
-      F[v] = rhs_value(K.lvt, M.template excess<3>(x0b + gx, x1, x2), tr + m2 + d3, bad);
+      const T tr = d00 + d11 + d22;
+      const T m2 = (d00 * d11 - d01 * d01) + (d00 * d22 - d02 * d02) + (d11 * d22 - d12 * d12);
+      const T d3 = d00 * (d11 * d22 - d12 * d12) - d01 * (d01 * d22 - d12 * d02) + d02 * (d01 * d12 - d11 * d02);
+      const T e = tr + m2 + d3;
+      const T fv = K.lvt + log_rho_det(M.template excess<3>(x0b + gx, x1s[m] + gy, sl.xc[m] + gz), e);
+      const bool lv = (live >> m) & 1;
+      const T f = lv ? fv : T(0);
+      chk.add(lv ? e : T(0), f);
+      if ((sl.valid >> m) & 1) *byte_off(Fc, sl.out[m]) = f;
     }
+  };
+  vmem_drain();
+  issue(preA, p0 - 1);
+  halo_commit(sm, hc, preA);
+  issue(preA, p0);
+  halo_commit(sm + PL, hc, preA);
+  issue(preA, p0 + 1);
+  issue(preB, p0 + 2);
+  int q = 0;
+  for (; q + 1 < np; q += 2) {  // both planes of a pair on every path
+    plane(preA, q);
+    plane(preB, q + 1);
   }
+  if (q < np) plane(preA, q);
+  bad |= chk.bits();
 }
 
 template <typename T>
