@@ -719,6 +719,82 @@ __device__ inline void mma_basis_by_lds(typename Op<KIND>::acc_t& acc, const voi
   }
 }
 
+constexpr int kMaxLd = 576;            // widest padded axis (9 row blocks of 64)
+constexpr int kColU = kMaxLd / 64;      // column loads per row and lane
+
+// Stage rows [row0, row0 + 16) x columns [0, ld) of a row-major R x C array into LDS as the data
+// operand (zero beyond R and C); returns this thread's largest magnitude.  Wave w takes rows
+// w + 4 j, lane l columns l + 64 u; the loads of two rows are issued before any is used, so a
+// tile costs two memory round trips rather than one per element.
+template <int KIND>
+__device__ inline float stage_rows16(char* lds, int ld, const gmem<typename Op<KIND>::T>* src, int row0, int R,
+                                     int C) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float amax = 0.f;
+#pragma unroll
+  for (int jp = 0; jp < 2; ++jp) {
+    T v[2][kColU];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int r = wave + 4 * (2 * jp + j);
+      const bool rok = row0 + r < R;
+      const gmem<T>* rp = src + (long)(rok ? row0 + r : 0) * C;
+#pragma unroll
+      for (int u = 0; u < kColU; ++u) {
+        const int k = lane + 64 * u;
+        v[j][u] = (rok && k < C) ? rp[k] : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int r = wave + 4 * (2 * jp + j);
+#pragma unroll
+      for (int u = 0; u < kColU; ++u) {
+        const int k = lane + 64 * u;
+        if (k < ld) {
+          O::put(lds, ld, r, k, v[j][u]);
+          if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j][u]));
+        }
+      }
+    }
+  }
+  return amax;
+}
+
+// Stage the 16-column strip [col0, col0 + 16) of a row-major K x ncol array transposed into LDS
+// (operand row c = strip column, k = index along the axis; zero beyond K and ncol); returns this
+// thread's largest magnitude.  Thread t takes column t % 16 and rows t / 16 + 16 j; twelve loads
+// are in flight per batch.
+template <int KIND>
+__device__ inline float stage_strip16(char* lds, int ld, const gmem<typename Op<KIND>::T>* src, int K, int ncol,
+                                      int col0) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  constexpr int B = 12;
+  const int c = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+  const bool cok = col0 + c < ncol;
+  float amax = 0.f;
+  for (int kb = 0; kb < ld; kb += 16 * B) {
+    T v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int k = kb + k0 + 16 * j;
+      v[j] = (cok && k < K) ? src[(long)k * ncol + col0 + c] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int k = kb + k0 + 16 * j;
+      if (k < ld) {
+        O::put(lds, ld, c, k, v[j]);
+        if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j]));
+      }
+    }
+  }
+  return amax;
+}
+
 // power-of-two scale bringing the tile's largest magnitude to [2^13, 2^14) (1 for an all-zero
 // tile); every thread passes its own running maximum
 __device__ inline float tile_scale(float amax, float* red) {
@@ -750,13 +826,7 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   const int row0 = tl.y, col0 = tl.z;
   __shared__ float red[4];
   const gmem<T>* __restrict__ src = gp<T>(S.F);
-  float amax = 0.f;
-  for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
-    const int r = idx / ld, k = idx - r * ld;
-    const T x = (row0 + r < R && k < C) ? src[(long)(row0 + r) * C + k] : T(0);
-    O::put(lds, ld, r, k, x);
-    if (O::SCALED) amax = fmaxf(amax, fabsf((float)x));
-  }
+  const float amax = stage_rows16<KIND>(lds, ld, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
@@ -783,14 +853,20 @@ __device__ inline T instance_shift(const StepArgs& sa, const InstDev& I) {
   return s / T(I.nsub);
 }
 
+// shape and artificial faces of a subdomain, copied into registers (stores to the state arrays
+// could otherwise alias the descriptor and force reloads)
+struct BoxReg {
+  int dim, n0, n1, n2, art;
+};
+__device__ inline BoxReg box_of(const SubDev& S) { return BoxReg{S.dim, S.n[0], S.n[1], S.n[2], S.art}; }
+
 // trapezoid weight (without prod h) and live flag of a node
-__device__ inline void node_weight(const SubDev& S, int i0, int i1, int i2, double& w, bool& live) {
-  w = 1.0;
-  live = true;
-  const int idx[3] = {i0, i1, i2};
-  for (int k = 0; k < S.dim; ++k) {
-    if (idx[k] == 0 || idx[k] == S.n[k] - 1) w *= 0.5;
-    if (is_artificial(S.art, k, idx[k], S.n[k])) live = false;
+__device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, double& w, bool& live) {
+  w = ((i0 == 0 || i0 == B.n0 - 1) ? 0.5 : 1.0) * ((i1 == 0 || i1 == B.n1 - 1) ? 0.5 : 1.0);
+  live = !is_artificial(B.art, 0, i0, B.n0) && !is_artificial(B.art, 1, i1, B.n1);
+  if (B.dim == 3) {
+    if (i2 == 0 || i2 == B.n2 - 1) w *= 0.5;
+    if (is_artificial(B.art, 2, i2, B.n2)) live = false;
   }
 }
 
@@ -815,13 +891,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const int row0 = tl.y, col0 = tl.z;
   __shared__ float redf[4];
   const gmem<T>* __restrict__ src = gp<T>(S.F);
-  float amax = 0.f;
-  for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
-    const int r = idx / ld, k = idx - r * ld;
-    const T x = (row0 + r < R && k < C) ? src[(long)(row0 + r) * C + k] : T(0);
-    O::put(lds, ld, r, k, x);
-    if (O::SCALED) amax = fmaxf(amax, fabsf((float)x));
-  }
+  const float amax = stage_rows16<KIND>(lds, ld, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale(amax, redf) : 1.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
@@ -829,6 +899,9 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const T shift = instance_shift<T>(sa, I);
   const T dt = T(I.dt);
   const T isc = T(1) / T(sc);
+  const BoxReg box = box_of(S);
+  const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
+  const int inst = S.inst;
   double part = 0.0;
   if (cb * 16 < C) {
     gmem<T>* __restrict__ phi = gpw<T>(S.phi);
@@ -846,14 +919,14 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
       const int r = row0 + O::crow(g, q);
       if (r < R && c < C) {
         int i0, i1, i2;
-        if (S.dim == 2) {
+        if (box.dim == 2) {
           i0 = r; i1 = c; i2 = 0;
         } else {
-          i0 = r / S.n[1]; i1 = r - i0 * S.n[1]; i2 = c;
+          i0 = r / box.n1; i1 = r - i0 * box.n1; i2 = c;
         }
         double w;
         bool live;
-        node_weight(S, i0, i1, i2, w, live);
+        node_weight(box, i0, i1, i2, w, live);
         if (live) {
           const T val = acc[q] * isc;
           const T u = dt * val;
@@ -863,13 +936,12 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
         }
       }
     }
-    if (bad) atomicOr(&sa.status[S.inst], ST_NONFINITE);
+    if (bad) atomicOr(&sa.status[inst], ST_NONFINITE);
   }
-  const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
   const double tot = block_sum256(part, red);
   if (threadIdx.x == 0) {
     sa.partials[part_base + blockIdx.x] = tot * hs;
-    if (I.pin && tl.x == I.first_sub && row0 == 0 && col0 == 0) sa.shift_acc[S.inst] += (double)dt * (double)shift;
+    if (I.pin && tl.x == I.first_sub && row0 == 0 && col0 == 0) sa.shift_acc[inst] += (double)dt * (double)shift;
   }
 }
 
@@ -905,13 +977,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   gmem<T>* __restrict__ dst = gpw<T>(src_sel ? S.F : S.T) + base;
   __shared__ float red[4];
   // strip transposed into LDS: operand row c = strip column, k = index along the axis
-  float amax = 0.f;
-  for (int idx = threadIdx.x; idx < 16 * ld; idx += 256) {
-    const int k = idx >> 4, c = idx & 15;
-    const T x = (k < K && col0 + c < ncol) ? src[(long)k * ncol + col0 + c] : T(0);
-    O::put(lds, ld, c, k, x);
-    if (O::SCALED) amax = fmaxf(amax, fabsf((float)x));
-  }
+  const float amax = stage_strip16<KIND>(lds, ld, src, K, ncol, col0);
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
@@ -1032,7 +1098,7 @@ __global__ __launch_bounds__(256) void euler_kernel(const int4* __restrict__ til
     const int i2 = (d == 2) ? 0 : col;
     double w;
     bool live;
-    node_weight(S, i0, i1, i2, w, live);
+    node_weight(box_of(S), i0, i1, i2, w, live);
     if (live) {
       const long v = (long)row * C + col;
       gmem<T>* phi = gpw<T>(S.phi);
