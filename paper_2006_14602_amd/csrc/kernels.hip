@@ -637,6 +637,14 @@ template <> struct Op<PREC_SPLIT16> {
     f.lo = *(const gmem<half8_t>*)(gp<_Float16>(lo) + (long)r * ld + k0 + 8 * g);
     return f;
   }
+  // basis fragment from a copy of the basis in LDS (same layout as in global memory)
+  static __device__ inline frag lbasis_frag(const char* hi, const char* lo, int ld, int r, int k0, int g) {
+    frag f;
+    f.hi = *(const half8_t*)((const _Float16*)hi + r * ld + k0 + 8 * g);
+    f.lo = *(const half8_t*)((const _Float16*)lo + r * ld + k0 + 8 * g);
+    return f;
+  }
+  enum { BASIS_BYTES = 4 };  // LDS bytes per basis entry (hi + lo)
   static __device__ inline void mma(acc_t& c, const frag& a, const frag& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.lo, b.hi, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.lo, c, 0, 0, 0);
@@ -657,6 +665,10 @@ template <> struct Op<PREC_F32> {
   static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
     return gp<float>(p)[(long)r * ld + k0 + g];
   }
+  static __device__ inline frag lbasis_frag(const char* p, const char*, int ld, int r, int k0, int g) {
+    return ((const float*)p)[r * ld + k0 + g];
+  }
+  enum { BASIS_BYTES = 4 };
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -675,6 +687,10 @@ template <> struct Op<PREC_F64> {
   static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
     return gp<double>(p)[(long)r * ld + k0 + g];
   }
+  static __device__ inline frag lbasis_frag(const char* p, const char*, int ld, int r, int k0, int g) {
+    return ((const double*)p)[r * ld + k0 + g];
+  }
+  enum { BASIS_BYTES = 8 };
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -717,6 +733,25 @@ __device__ inline void mma_basis_by_lds(typename Op<KIND>::acc_t& acc, const voi
     for (int u = 0; u < U; ++u)
       if (u < nu) O::mma(acc, a[u], O::lds_frag(lds, ld, l16, k0 + u * O::KB, g, sc));
   }
+}
+
+// acc += basis rows (a copy in LDS) times the LDS data operand: no global-memory latency
+template <int KIND>
+__device__ inline void mma_lbasis_by_lds(typename Op<KIND>::acc_t& acc, const char* bh, const char* bl,
+                                         const char* lds, int ld, float sc, int arow, int l16, int g) {
+  typedef Op<KIND> O;
+  for (int k0 = 0; k0 < ld; k0 += O::KB) O::mma(acc, O::lbasis_frag(bh, bl, ld, arow, k0, g), O::lds_frag(lds, ld, l16, k0, g, sc));
+}
+
+// Copy `bytes` (a multiple of 1 KiB) from global memory into LDS with direct-to-LDS loads, which
+// need no registers and are all in flight together: wave w copies the 1 KiB chunks w, w + 4, ..,
+// lane l bytes [16 l, 16 l + 16) of a chunk.  Complete after vmem_drain() and a barrier.
+__device__ inline void lds_dma(char* dst, const void* src, int bytes) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  for (int ch = wave; ch * 1024 < bytes; ch += 4)
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((const char*)src + ch * 1024 + lane * 16),
+                                     (__attribute__((address_space(3))) void*)(dst + ch * 1024), 16, 0, 0);
 }
 
 constexpr int kMaxLd = 576;            // widest padded axis (9 row blocks of 64)
@@ -950,9 +985,14 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
 //   PAIR = false: dst = Bas * src, Bas the forward (inv = 0) or inverse (inv = 1) basis
 //   PAIR = true (axis 0): dst = B_0 * (S o (A_0 * src)), S the spectral scale
 //                         1 / (1 + sum_k gamma mu_k); the DC coefficient is recorded
+// When the strip and the basis fit in the launch's LDS (lcap bytes), the basis is copied into LDS
+// once (direct-to-LDS loads, in flight together with the strip) and every product reads LDS only.
+// The pair then reuses the forward matrix for the inverse: with D = diag(w) (w = 1/2 at both ends,
+// else 1) the DCT-I matrices satisfy B = (N / 2) D^-1 A D^-1, and the powers of two D^-1 and N / 2
+// fold exactly into the spectral scale and the store.
 template <int KIND, bool PAIR>
 __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
-                                                    int src_sel, StepArgs sa) {
+                                                    int src_sel, int lcap, StepArgs sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   constexpr int MAXRB = 9;  // row blocks per wave: n <= 9 * 4 * 16 = 576
@@ -976,17 +1016,22 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   const gmem<T>* __restrict__ src = gp<T>(src_sel ? S.T : S.F) + base;
   gmem<T>* __restrict__ dst = gpw<T>(src_sel ? S.F : S.T) + base;
   __shared__ float red[4];
-  // strip transposed into LDS: operand row c = strip column, k = index along the axis
-  const float amax = stage_strip16<KIND>(lds, ld, src, K, ncol, col0);
-  const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
   const int nrb = (K + 15) >> 4;
   const int c = col0 + l16;
-  typename O::acc_t acc[MAXRB];
   const void* b1h = (PAIR || !inv) ? A.fwd : A.inv;
   const void* b1l = (PAIR || !inv) ? A.fwdl : A.invl;
-  // PAIR: spectral factors of this lane's coefficients, requested before the product
+  // basis copy in LDS after the strip: nrb * 16 rows of ld entries (split form: hi, then lo)
+  const int dbytes = 16 * ld * O::LDS_BYTES;
+  const int bbytes = nrb * 16 * ld * (O::BASIS_BYTES / (O::SCALED ? 2 : 1));
+  const bool lbasis = dbytes + (O::SCALED ? 2 : 1) * bbytes <= lcap;
+  char* lbh = lds + dbytes;
+  char* lbl = lbh + bbytes;
+  if (lbasis) {
+    lds_dma(lbh, b1h, bbytes);
+    if (O::SCALED) lds_dma(lbl, b1l, bbytes);
+  }
+  // PAIR: spectral factors of this lane's coefficients, requested before the products
   T sig0[PAIR ? MAXRB * 4 : 1];
   T rest = T(0);
   if constexpr (PAIR) {
@@ -1007,12 +1052,21 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
         sig0[t * 4 + q] = i < K ? s0[i] : T(0);
       }
   }
+  // strip transposed into LDS: operand row c = strip column, k = index along the axis
+  const float amax = stage_strip16<KIND>(lds, ld, src, K, ncol, col0);
+  const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
+  if (lbasis) vmem_drain();
+  __syncthreads();
+  typename O::acc_t acc[MAXRB];
   const T us1 = ((PAIR || !inv) ? T(A.fwd_unscale) : T(1)) / T(sc);
 #pragma unroll
   for (int t = 0; t < MAXRB; ++t) {
     acc[t] = typename O::acc_t{0, 0, 0, 0};
     const int rb = wave + 4 * t;
-    if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, lds, ld, sc, rb * 16 + l16, l16, g);
+    if (rb < nrb) {
+      if (lbasis) mma_lbasis_by_lds<KIND>(acc[t], lbh, lbl, lds, ld, sc, rb * 16 + l16, l16, g);
+      else mma_basis_by_lds<KIND>(acc[t], b1h, b1l, lds, ld, sc, rb * 16 + l16, l16, g);
+    }
   }
   if constexpr (!PAIR) {
 #pragma unroll
@@ -1025,7 +1079,8 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
       }
     }
   } else {
-    // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2
+    // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2.
+    // LDS path: also D^-1 (x 2 at i = 0 and i = K - 1) ahead of the forward matrix reused.
     const T g0 = T(S.gh2[0]);
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
@@ -1037,6 +1092,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
           const T val = acc[t][q] * us1;
           if (i == 0 && c == 0) gpw<T>(sa.dc)[tl.x] = val;
           y = val / (T(1) + g0 * sig0[t * 4 + q] + rest);
+          if (lbasis && (i == 0 || i == K - 1)) y *= T(2);
         }
         acc[t][q] = y;
       }
@@ -1059,15 +1115,19 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
       O::put(lds, ld, cc, k, T(0));
     }
     __syncthreads();
+    // store scale: 1 / sy, and on the LDS path (N / 2) D^-1 and the split form's 2^-s
+    const T half_n = T(K - 1) / T(2);
+    const T os = lbasis ? T(A.fwd_unscale) * half_n / T(sy) : T(1) / T(sy);
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
       const int rb = wave + 4 * t;
       if (rb >= nrb) continue;
       typename O::acc_t z = {0, 0, 0, 0};
-      mma_basis_by_lds<KIND>(z, A.inv, A.invl, lds, ld, sy, rb * 16 + l16, l16, g);
+      if (lbasis) mma_lbasis_by_lds<KIND>(z, lbh, lbl, lds, ld, sy, rb * 16 + l16, l16, g);
+      else mma_basis_by_lds<KIND>(z, A.inv, A.invl, lds, ld, sy, rb * 16 + l16, l16, g);
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
-        if (i < K && c < ncol) dst[(long)i * ncol + c] = z[q] / T(sy);
+        if (i < K && c < ncol) dst[(long)i * ncol + c] = z[q] * ((lbasis && (i == 0 || i == K - 1)) ? T(2) * os : os);
       }
     }
   }
@@ -1405,12 +1465,15 @@ hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, i
   return hipGetLastError();
 }
 
-hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
+// lneed: the largest LDS footprint (strip + basis copy) among the launch's subdomains whose copy
+// fits in a workgroup's LDS (0: none); such tiles take the LDS-basis path
+hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
                         int src_sel, const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  const size_t sh = op_lds(prec, maxld);
+  const size_t sh = std::max<size_t>(op_lds(prec, maxld), (size_t)lneed);
+  const int lcap = (int)sh;
 #define PMA_STRIP(K, P) \
-  hipLaunchKernelGGL((strip_kernel<K, P>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, axis, inv, src_sel, sa)
+  hipLaunchKernelGGL((strip_kernel<K, P>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, axis, inv, src_sel, lcap, sa)
   if (prec == PREC_F64) {
     if (pair) PMA_STRIP(PREC_F64, true); else PMA_STRIP(PREC_F64, false);
   } else if (prec == PREC_F32) {

@@ -32,7 +32,7 @@ hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, 
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
 hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
                            hipStream_t s);
-hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
+hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
                         int src_sel, const StepArgs& sa, hipStream_t s);
 hipError_t enable_large_lds();
 hipError_t launch_resid(const SubDev* subs, const InstDev* insts, int ninst, const double* partials,
@@ -834,6 +834,11 @@ static constexpr int kStRows = 4, kStCols = 64;     // forward-Euler tiles
 static constexpr int kStChunk = 16, kStWmax = 72;  // stencil: rows per chunk, widest block
 static constexpr int kRows = 16, kCols = 64, kStrip = 16;  // mode-product tiles
 static constexpr int kPhases = 8;
+static constexpr int kLdsBasisCap = 160 * 1024 - 4096;  // dynamic LDS a workgroup may take
+// Copying the basis into LDS removes the basis loads from a strip workgroup's critical path but
+// leaves room for one workgroup per CU: worth it while a launch has at most about two
+// workgroups per CU (latency-bound), not for large batches that rely on occupancy.
+static constexpr int kLdsBasisMaxTiles = 512;
 
 struct SubRange {
   int first, count;
@@ -845,6 +850,7 @@ struct Table {
   std::vector<SubRange> rng;
   int4* d = nullptr;
   int maxld = 32;
+  int lneed = 0;  // strip launches: largest LDS footprint with the basis copied in (if it fits)
   void begin_sub() { rng.push_back(SubRange{(int)h.size(), 0}); }
   void end_sub() { rng.back().count = (int)h.size() - rng.back().first; }
   int size() const { return (int)h.size(); }
@@ -987,6 +993,17 @@ struct Batch {
   }
   size_t st_cap = 0;
 
+  static int lds_basis(const Table& t, int count) { return count <= kLdsBasisMaxTiles ? t.lneed : 0; }
+
+  // strip launches copy an axis' basis into LDS when strip + basis fit in a workgroup's LDS:
+  // 16 x ld operand entries and round_up(n, 16) x ld basis entries (split form: hi + lo)
+  void note_lds(Table& t, int n, int ld) const {
+    const int ob = prec == PMA_FP64 ? 8 : 4;
+    const int bb = prec == PMA_FP64 ? 8 : 4;
+    const int need = 16 * ld * ob + ((n + 15) / 16) * 16 * ld * bb;
+    if (need <= kLdsBasisCap) t.lneed = std::max(t.lneed, need);
+  }
+
   void build() {
     HIPCHK(enable_large_lds());
     clear_device();
@@ -1077,10 +1094,13 @@ struct Batch {
               }
             tab[4].maxld = std::max(tab[4].maxld, sd.ax[1].ld);
             tab[6].maxld = std::max(tab[6].maxld, sd.ax[1].ld);
+            note_lds(tab[4], n1, sd.ax[1].ld);
+            note_lds(tab[6], n1, sd.ax[1].ld);
           }
           const int rest = I.dim == 2 ? n1 : n1 * n2;
           for (int c = 0; c < rest; c += kStrip) tab[5].h.push_back(int4{gs, 0, c, 0});
           tab[5].maxld = std::max(tab[5].maxld, sd.ax[0].ld);
+          note_lds(tab[5], n0, sd.ax[0].ld);
           for (int r = 0; r < R; r += kRows)
             for (int c = 0; c < C; c += kCols) tab[7].h.push_back(int4{gs, r, c, 0});
           tab[7].maxld = std::max(tab[7].maxld, sd.ax[la].ld);
@@ -1181,11 +1201,11 @@ struct Batch {
       case 1: HIPCHK(launch_stencil(prec, stencil_dim_, t.d + first, count, sa, st)); break;
       case 2: HIPCHK(launch_euler(prec, t.d + first, count, part_base_eu + first, sa, st)); break;
       case 3: HIPCHK(launch_fwd_last(prec, t.d + first, count, t.maxld, sa, st)); break;
-      case 4: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, 1, 0, 1, sa, st)); break;
+      case 4: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 0, 1, sa, st)); break;
       case 5:  // 2D: T -> F;  3D: F -> T (pair_src_ set by launch_phase)
-        HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, 0, 0, pair_src_, sa, st));
+        HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, lds_basis(t, count), 0, 0, pair_src_, sa, st));
         break;
-      case 6: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, 1, 1, 1, sa, st)); break;
+      case 6: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 1, 1, sa, st)); break;
       case 7: HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, sa, st)); break;
     }
   }
