@@ -907,13 +907,19 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 
 // inverse transform along the last axis for 16 rows x up to 64 columns, fused with the update
 // phi += dt (delta - shift) and the residual partial sum.  Input: F.
+// Push transmission: push_first[tile] .. push_first[tile + 1] index the entries (dst sub, dst
+// node, row, column within the tile) of push[] whose source node lies in the tile; after the
+// update each such node's new value is written into the artificial node of the other subdomain,
+// which is the owner's value the transmission condition gives it for the next step.
 template <int KIND>
 __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
-                                                       StepArgs sa) {
+                                                       const int* __restrict__ push_first,
+                                                       const int4* __restrict__ push, StepArgs sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   __shared__ double red[4];
+  __shared__ T stash[16][64];
   if ((int)blockIdx.x >= ntiles) return;
   const int4 tl = tiles[blockIdx.x];
   const SubDev& S = sa.subs[tl.x];
@@ -937,6 +943,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const BoxReg box = box_of(S);
   const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
   const int inst = S.inst;
+  const int pf0 = push_first[blockIdx.x], pf1 = push_first[blockIdx.x + 1];
   double part = 0.0;
   if (cb * 16 < C) {
     gmem<T>* __restrict__ phi = gpw<T>(S.phi);
@@ -965,13 +972,22 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
         if (live) {
           const T val = acc[q] * isc;
           const T u = dt * val;
-          phi[(long)r * C + c] = old[q] + dt * (val - shift);
+          const T nv = old[q] + dt * (val - shift);
+          phi[(long)r * C + c] = nv;
+          if (pf1 > pf0) stash[O::crow(g, q)][wave * 16 + l16] = nv;
           part += w * (double)u * (double)u;
           bad |= !finite_(u);
         }
       }
     }
     if (bad) atomicOr(&sa.status[inst], ST_NONFINITE);
+  }
+  if (pf1 > pf0) {
+    __syncthreads();
+    for (int e = pf0 + (int)threadIdx.x; e < pf1; e += 256) {
+      const int4 P = push[e];
+      gpw<T>(sa.subs[P.x].phi)[P.y] = stash[P.z][P.w];
+    }
   }
   const double tot = block_sum256(part, red);
   if (threadIdx.x == 0) {
@@ -1452,16 +1468,19 @@ hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, c
   return hipGetLastError();
 }
 
-hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
-                           hipStream_t s) {
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const int* push_first,
+                           const int4* push, const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const size_t sh = op_lds(prec, maxld);
+#define PMA_INV(K) \
+  hipLaunchKernelGGL(inv_last_kernel<K>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, push_first, push, sa)
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(inv_last_kernel<PREC_F64>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, sa);
+    PMA_INV(PREC_F64);
   else if (prec == PREC_F32)
-    hipLaunchKernelGGL(inv_last_kernel<PREC_F32>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, sa);
+    PMA_INV(PREC_F32);
   else
-    hipLaunchKernelGGL(inv_last_kernel<PREC_SPLIT16>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, sa);
+    PMA_INV(PREC_SPLIT16);
+#undef PMA_INV
   return hipGetLastError();
 }
 
@@ -1488,7 +1507,7 @@ hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int 
 // kernels using more than 64 KiB of dynamic LDS must say so once per process
 hipError_t enable_large_lds() {
   static hipError_t rc = [] {
-    // 160 KiB per workgroup on gfx950, less room for the kernels' own static LDS
+    // 160 KiB per workgroup on gfx950; the strip kernels' LDS-basis path asks for at most lim
     const int lim = 160 * 1024 - 4096;
     hipError_t e = hipSuccess;
     const void* ks[] = {(const void*)fwd_last_kernel<PREC_F64>, (const void*)fwd_last_kernel<PREC_F32>,
@@ -1498,7 +1517,12 @@ hipError_t enable_large_lds() {
                         (const void*)strip_kernel<PREC_F32, true>, (const void*)strip_kernel<PREC_F32, false>,
                         (const void*)strip_kernel<PREC_SPLIT16, true>, (const void*)strip_kernel<PREC_SPLIT16, false>};
     for (const void* k : ks) {
-      hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+      // whatever the kernel's static LDS leaves of the 160 KiB (at most lim)
+      hipFuncAttributes fa{};
+      hipError_t r = hipFuncGetAttributes(&fa, k);
+      if (r == hipSuccess)
+        r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                std::min(lim, 160 * 1024 - (int)fa.sharedSizeBytes));
       if (r != hipSuccess) e = r;
     }
     (void)hipGetLastError();  // the status is returned, not left pending for the next launch

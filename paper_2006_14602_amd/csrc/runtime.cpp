@@ -30,7 +30,8 @@ hipError_t launch_stencil(int prec, int dim, const int4* tiles, int ntiles, cons
 hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
                         hipStream_t s);
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
-hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const int* push_first,
+                           const int4* push, const StepArgs& sa,
                            hipStream_t s);
 hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
                         int src_sel, const StepArgs& sa, hipStream_t s);
@@ -891,6 +892,13 @@ struct Batch {
   std::vector<InstDev> h_insts;
   std::vector<int4> h_trans;
   std::vector<SubRange> tr_rng;
+  // a step's transmission: pushed by the inverse-last kernel of the owner (gamma > 0), or pulled
+  // by the gather before the stencil (forward-Euler instances)
+  std::vector<int4> h_push, h_pull;
+  std::vector<int> h_pfirst;
+  std::vector<SubRange> pull_rng;
+  int4 *d_push = nullptr, *d_pull = nullptr;
+  int* d_pfirst = nullptr;
   Table tab[kPhases];  // tab[0] unused (transmission has its own list)
   int part_base_eu = 0, part_base_inv = 0, npartials = 0;
   char* dmem = nullptr;
@@ -1004,6 +1012,42 @@ struct Batch {
     if (need <= kLdsBasisCap) t.lneed = std::max(t.lneed, need);
   }
 
+  // Split the transmission list: entries of instances that take the preconditioned update are
+  // pushed by the inverse-last tile holding the source node (bucketed per tile, with the node's
+  // row and column inside the tile); forward-Euler instances keep the gather.
+  void build_push_lists() {
+    const int nt = tab[7].size();
+    std::vector<int> cnt(nt + 1, 0);
+    std::vector<int4> ent;
+    std::vector<int> tile_of;
+    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
+      const bool euler = insts[h_subs[gs].inst]->tm.gamma == 0.0;
+      SubRange pr{(int)h_pull.size(), 0};
+      for (int e = tr_rng[gs].first; e < tr_rng[gs].first + tr_rng[gs].count; ++e) {
+        const int4 t = h_trans[e];  // (dst sub, dst node, src sub, src node)
+        if (euler) {
+          h_pull.push_back(t);
+          continue;
+        }
+        const SubDev& src = h_subs[t.z];
+        const int C = src.dim == 2 ? src.n[1] : src.n[2];
+        const int r = t.w / C, c = t.w - (t.w / C) * C;
+        const int nct = (C + kCols - 1) / kCols;
+        const int tile = tab[7].rng[t.z].first + (r / kRows) * nct + c / kCols;
+        ent.push_back(int4{t.x, t.y, r % kRows, c % kCols});
+        tile_of.push_back(tile);
+        ++cnt[tile + 1];
+      }
+      pr.count = (int)h_pull.size() - pr.first;
+      pull_rng.push_back(pr);
+    }
+    for (int i = 0; i < nt; ++i) cnt[i + 1] += cnt[i];
+    h_pfirst = cnt;
+    h_push.assign(ent.size(), int4{0, 0, 0, 0});
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (size_t i = 0; i < ent.size(); ++i) h_push[pos[tile_of[i]]++] = ent[i];
+  }
+
   void build() {
     HIPCHK(enable_large_lds());
     clear_device();
@@ -1011,6 +1055,10 @@ struct Batch {
     h_insts.clear();
     h_trans.clear();
     tr_rng.clear();
+    h_push.clear();
+    h_pull.clear();
+    h_pfirst.clear();
+    pull_rng.clear();
     for (auto& t : tab) t = Table();
     for (size_t q = 0; q < insts.size(); ++q) {
       Instance& I = *insts[q];
@@ -1123,11 +1171,13 @@ struct Batch {
         sd.nparts = tab[7].rng[gs].count;
       }
     }
+    build_push_lists();
     // device block
     const size_t nsub = h_subs.size(), ninst = h_insts.size();
     const size_t el = prec == PMA_FP64 ? 8 : 4;
     size_t bytes = Arena::round(nsub * sizeof(SubDev)) + Arena::round(ninst * sizeof(InstDev)) +
-                   Arena::round(h_trans.size() * 16 + 16) + Arena::round(nsub * el) +
+                   Arena::round(h_trans.size() * 16 + 16) + Arena::round(h_push.size() * 16 + 16) +
+                   Arena::round(h_pull.size() * 16 + 16) + Arena::round(h_pfirst.size() * 4 + 16) + Arena::round(nsub * el) +
                    Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4);
     for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
     if (bytes > dcap) {
@@ -1156,6 +1206,9 @@ struct Batch {
     d_subs = (SubDev*)take(nsub * sizeof(SubDev));
     d_insts = (InstDev*)take(ninst * sizeof(InstDev));
     d_tr = (int4*)take(h_trans.size() * 16 + 16);
+    d_push = (int4*)take(h_push.size() * 16 + 16);
+    d_pull = (int4*)take(h_pull.size() * 16 + 16);
+    d_pfirst = (int*)take(h_pfirst.size() * 4 + 16);
     for (int ph = 1; ph < kPhases; ++ph) tab[ph].d = (int4*)take((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
     d_dc = take(nsub * el);
     d_partials = (double*)take((size_t)(npartials + 1) * 8);
@@ -1165,6 +1218,9 @@ struct Batch {
     up(d_subs, h_subs.data(), nsub * sizeof(SubDev));
     up(d_insts, h_insts.data(), ninst * sizeof(InstDev));
     up(d_tr, h_trans.data(), h_trans.size() * 16);
+    up(d_push, h_push.data(), h_push.size() * 16);
+    up(d_pull, h_pull.data(), h_pull.size() * 16);
+    up(d_pfirst, h_pfirst.data(), h_pfirst.size() * 4);
     for (int ph = 1; ph < kPhases; ++ph) up(tab[ph].d, tab[ph].h.data(), tab[ph].h.size() * 16);
     HIPCHK(hipMemsetAsync(d_dc, 0, nsub * el, st));
     HIPCHK(hipMemsetAsync(d_partials, 0, (size_t)(npartials + 1) * 8, st));
@@ -1206,7 +1262,9 @@ struct Batch {
         HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, lds_basis(t, count), 0, 0, pair_src_, sa, st));
         break;
       case 6: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 1, 1, sa, st)); break;
-      case 7: HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, sa, st)); break;
+      case 7:
+        HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, d_pfirst + first, d_push, sa, st));
+        break;
     }
   }
   int pair_src_ = 1;
@@ -1254,9 +1312,16 @@ struct Batch {
       for (int s = 0; s < nsub; ++s) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
   }
 
-  // a step: transmission gather (artificial nodes <- owners' time-n values), then the rest
+  // a step: the gather of forward-Euler instances (the others received their owners' values from
+  // the previous step's inverse-last kernels), then the stencil and the update
   void launch_step(bool plain, hipStream_t st) {
-    for (int ph = 0; ph < kPhases; ++ph) launch_phase(ph, plain, st);
+    if (!plain) {
+      if (!h_pull.empty()) HIPCHK(launch_transmit(prec, d_subs, d_pull, (int)h_pull.size(), st));
+    } else {
+      for (size_t s = 0; s < pull_rng.size(); ++s)
+        if (pull_rng[s].count) HIPCHK(launch_transmit(prec, d_subs, d_pull + pull_rng[s].first, pull_rng[s].count, st));
+    }
+    for (int ph = 1; ph < kPhases; ++ph) launch_phase(ph, plain, st);
   }
 
   // algorithmic work per step of each phase: 2 M N K flops per product; compulsory bytes with
