@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp16_TF": 2500.0, "fp32_TF": 157.3, "fp64_TF": 78.6}
 MFMA_PEAK = {"split16": PEAK["fp16_TF"], "fp32": PEAK["fp32_TF"], "fp64": PEAK["fp64_TF"]}
-KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil2_kernel / stencil3_kernel", "euler": "euler_kernel",
+KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil_fwd2_kernel / stencil2_kernel / stencil3_kernel",
+          "euler": "euler_kernel",
           "fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel<single>", "pair0": "strip_kernel<pair>",
           "inv_mid": "strip_kernel<single>", "inv_last": "inv_last_kernel"}
 
@@ -88,6 +89,7 @@ def stencil_roofline(ctx, binding, workloads):
     w = workloads.sine_dd(n=8193, parts=(32, 32), overlap=8, steps=1)
     plan = binding.Plan(ctx, [w, w], "split16", "batched")
     try:
+        plan.set_fusion(False)  # the stencil alone (phi -> F), not fused with the first product
         march, cand = plan.autotune(5)
         ph = plan.phase_times(10)
     finally:

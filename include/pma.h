@@ -212,7 +212,8 @@ int pma_plan_step(pma_plan* plan, int nsteps);
 int pma_plan_sync(pma_plan* plan);
 
 /* Phases of one step, in launch order:
- *   0 transmission of artificial-boundary values     1 stencil: right-hand side F
+ *   0 transmission of artificial-boundary values     1 stencil: right-hand side F (fused 2D:
+ *                                                       and its forward last-axis product)
  *   2 forward-Euler update (gamma = 0)                3 forward DCT along the last axis
  *   4 forward DCT along the middle axis (3D)          5 forward DCT + spectral scale + inverse DCT
  *                                                       along axis 0
@@ -243,6 +244,15 @@ int pma_plan_autotune(pma_plan* plan, int reps, int* march, double* ms, int cap,
  * Results do not depend on it (bitwise).  Errors: PMA_E_INVAL for a NULL plan or march outside
  * 1..4096. */
 int pma_plan_set_march(pma_plan* plan, int march);
+
+/* Turn the fused stencil on (default) or off for the plan's 2D subdomains of preconditioned
+ * requests whose last axis is at most 320 wide (padded): the stencil of 16 full rows is computed
+ * into LDS and multiplied by the forward last-axis DCT matrix in the same kernel (phase 1 then
+ * also does phase 3's product for them).  Off: separate stencil and product launches, F through
+ * HBM.  Results are the same up to the order of rounding (both paths evaluate the same formulas);
+ * the switch exists to time the stencil on its own.  Only before the plan's first step.
+ * Errors: PMA_E_INVAL for a NULL plan or a plan that has already stepped. */
+int pma_plan_set_fusion(pma_plan* plan, int on);
 
 /* Glue request i's mesh (dim * prod(n) doubles) into host memory; st may be NULL. */
 int pma_plan_mesh(pma_plan* plan, int i, double* mesh_out, pma_stats* st);

@@ -743,6 +743,14 @@ __device__ inline void mma_lbasis_by_lds(typename Op<KIND>::acc_t& acc, const ch
   for (int k0 = 0; k0 < ld; k0 += O::KB) O::mma(acc, O::lbasis_frag(bh, bl, ld, arow, k0, g), O::lds_frag(lds, ld, l16, k0, g, sc));
 }
 
+// acc += rows of the LDS operand times basis rows of a basis copy in LDS (as columns of B)
+template <int KIND>
+__device__ inline void mma_lds_by_lbasis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, float sc,
+                                         const char* bh, const char* bl, int brow, int l16, int g) {
+  typedef Op<KIND> O;
+  for (int k0 = 0; k0 < ld; k0 += O::KB) O::mma(acc, O::lds_frag(lds, ld, l16, k0, g, sc), O::lbasis_frag(bh, bl, ld, brow, k0, g));
+}
+
 // Copy `bytes` (a multiple of 1 KiB) from global memory into LDS with direct-to-LDS loads, which
 // need no registers and are all in flight together: wave w copies the 1 KiB chunks w, w + 4, ..,
 // lane l bytes [16 l, 16 l + 16) of a chunk.  Complete after vmem_drain() and a barrier.
@@ -1150,6 +1158,150 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
 }
 
 // ------------------------------------------------------------------------------------------
+// Stencil fused with the forward product along the last axis (2D): a workgroup takes 16 full
+// rows [row0, row0 + 16) of a subdomain, computes F there straight into the LDS operand of the
+// mode product, and writes T[rows, :] = F[rows, :] * A_1.  F never goes through HBM, and a step
+// saves a launch.  The axis-1 basis is copied into LDS alongside the halo when it fits (lcap).
+// ------------------------------------------------------------------------------------------
+
+constexpr int kFuseMaxLd = 320;           // widest last axis (padded) the fused kernel takes
+constexpr int kFuseU = kFuseMaxLd / 64;   // column groups per lane
+
+// LDS layout of the fused kernel: operand [16][ld] | halo [18][ld + 4] (rounded to 1 KiB) | basis
+template <int KIND>
+__host__ __device__ inline int fused_halo_bytes(int ld) {
+  return ((18 * (ld + 4) * (int)sizeof(typename Op<KIND>::T) + 1023) / 1024) * 1024;
+}
+
+template <int KIND, int MK>
+__device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K, const MonP<typename Op<KIND>::T>& mp,
+                                    const typename Op<KIND>::T* halo, int HS, char* op, int ld, int row0,
+                                    NodeCheck<typename Op<KIND>::T>& chk, float& amax) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  const MonReg<T, MK> M(mp);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n0 = K.n0, n1 = K.n1;
+  const T h0 = K.h0, h1 = K.h1;
+  const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
+  const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int rr = wave + 4 * k, i = row0 + rr;
+    const bool rlive = i < n0 && !is_artificial(K.art, 0, i, n0);
+    const T x0b = K.a0 + T(K.off0 + i) * h0;
+#pragma unroll
+    for (int u = 0; u < kFuseU; ++u) {
+      const int j = lane + 64 * u;
+      if (j >= ld) continue;
+      T f = T(0);
+      if (rlive && j < n1 && !is_artificial(K.art, 1, j, n1)) {
+        const T* c = halo + (rr + 1) * HS + j + 1;
+        const T c0 = c[0];
+        const T xm = c[-HS], xp = c[HS], ym = c[-1], yp = c[1];
+        const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
+        const T hxx = (xp - T(2) * c0 + xm) * rh00;
+        const T hyy = (yp - T(2) * c0 + ym) * rh11;
+        const T hxy = (c[HS + 1] - c[HS - 1] - c[-HS + 1] + c[-HS - 1]) * r4h01;
+        const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
+        const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
+        f = K.lvt + log_rho_det(M.template excess<2>(x0b + gx, x1, T(0)), e);
+        chk.add(e, f);
+      }
+      O::put(op, ld, rr, j, f);
+      if (O::SCALED) amax = fmaxf(amax, fabsf((float)f));
+    }
+  }
+}
+
+// tile = (sub, row0, 0, 0)
+template <int KIND>
+__global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restrict__ tiles, int ntiles, int lcap,
+                                                           StepArgs sa) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  __shared__ float red[4];
+  if ((int)blockIdx.x >= ntiles) return;
+  const int4 tl = tiles[blockIdx.x];
+  StencilCtx<T> K;
+  const T* phi_;
+  T* F_;
+  const MonP<T>* mp = load_ctx(sa, tl.x, K, phi_, F_);
+  const SubDev& S = sa.subs[tl.x];
+  const AxisDev& A = S.ax[1];
+  const int ld = A.ld, n0 = K.n0, n1 = K.n1, row0 = tl.y;
+  const int HS = ld + 4;
+  char* op = lds;
+  T* halo = (T*)(lds + 16 * ld * O::LDS_BYTES);
+  const int nrb = (n1 + 15) >> 4;
+  const int bbytes = nrb * 16 * ld * (O::BASIS_BYTES / (O::SCALED ? 2 : 1));
+  char* lbh = (char*)halo + fused_halo_bytes<KIND>(ld);
+  char* lbl = lbh + bbytes;
+  const bool lbasis = 16 * ld * O::LDS_BYTES + fused_halo_bytes<KIND>(ld) + (O::SCALED ? 2 : 1) * bbytes <= lcap;
+  if (lbasis) {
+    lds_dma(lbh, A.fwd, bbytes);
+    if (O::SCALED) lds_dma(lbl, A.fwdl, bbytes);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  // halo rows row0 - 1 .. row0 + 16, columns -1 .. n1 (mirror ghosts): wave w rows w + 4 k, lane
+  // columns lane + 64 u, all loads in flight before the first LDS write
+  {
+    const gmem<T>* phi = (const gmem<T>*)phi_;
+    T v[5][kFuseU];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int r = wave + 4 * k;
+      const gmem<T>* row = phi + (long)mirror_clamp(row0 + r - 1, n0) * n1;
+#pragma unroll
+      for (int u = 0; u < kFuseU; ++u) {
+        const int c = lane + 64 * u;
+        v[k][u] = (r < 18 && c < n1 + 2) ? row[mirror_clamp(c - 1, n1)] : T(0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int r = wave + 4 * k;
+#pragma unroll
+      for (int u = 0; u < kFuseU; ++u) {
+        const int c = lane + 64 * u;
+        if (r < 18 && c < n1 + 2) halo[r * HS + c] = v[k][u];
+      }
+    }
+  }
+  __syncthreads();
+  NodeCheck<T> chk;
+  float amax = 0.f;
+  switch (mp->kind) {
+    case MON_CONST: fused_nodes2<KIND, MON_CONST>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
+    case MON_RADIAL: fused_nodes2<KIND, MON_RADIAL>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
+    case MON_SINE: fused_nodes2<KIND, MON_SINE>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
+    case MON_GAUSS: fused_nodes2<KIND, MON_GAUSS>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
+    default: fused_nodes2<KIND, MON_SEPARABLE>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
+  }
+  const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
+  if (lbasis) vmem_drain();
+  __syncthreads();
+  gmem<T>* out = gpw<T>(S.T);
+  const T us = T(A.fwd_unscale) / T(sc);
+#pragma unroll
+  for (int t = 0; t < (kFuseMaxLd / 16 + 3) / 4; ++t) {
+    const int cb = wave + 4 * t;
+    if (cb >= nrb) break;
+    typename O::acc_t acc = {0, 0, 0, 0};
+    if (lbasis) mma_lds_by_lbasis<KIND>(acc, op, ld, sc, lbh, lbl, cb * 16 + l16, l16, g);
+    else mma_lds_by_basis<KIND>(acc, op, ld, sc, A.fwd, A.fwdl, cb * 16 + l16, l16, g);
+    const int c = cb * 16 + l16;
+    for (int q = 0; q < 4; ++q) {
+      const int r = row0 + O::crow(g, q);
+      if (r < n0 && c < n1) out[(long)r * n1 + c] = acc[q] * us;
+    }
+  }
+  const int bad = chk.bits();
+  if (bad) atomicOr(&sa.status[K.inst], bad);
+}
+
+// ------------------------------------------------------------------------------------------
 // forward Euler update (gamma = 0): phi += dt F on live nodes, residual partials
 // ------------------------------------------------------------------------------------------
 
@@ -1484,6 +1636,26 @@ hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, i
   return hipGetLastError();
 }
 
+// fused stencil + forward last-axis product (2D); lneed: the launch's largest LDS footprint
+hipError_t launch_stencil_fwd2(int prec, const int4* tiles, int ntiles, int lneed, const StepArgs& sa, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const size_t sh = (size_t)lneed;
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_F64>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, lneed, sa);
+  else if (prec == PREC_F32)
+    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_F32>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, lneed, sa);
+  else
+    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_SPLIT16>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, lneed, sa);
+  return hipGetLastError();
+}
+
+// LDS bytes of the fused kernel for a last axis of padded length ld with n nodes (basis copied or not)
+int fused_lds_bytes(int prec, int ld, int n, bool basis) {
+  const int ob = prec == PREC_F64 ? 8 : 4;
+  const int hb = prec == PREC_F64 ? fused_halo_bytes<PREC_F64>(ld) : fused_halo_bytes<PREC_F32>(ld);
+  return 16 * ld * ob + hb + (basis ? ((n + 15) / 16) * 16 * ld * ob : 0);
+}
+
 // lneed: the largest LDS footprint (strip + basis copy) among the launch's subdomains whose copy
 // fits in a workgroup's LDS (0: none); such tiles take the LDS-basis path
 hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
@@ -1515,7 +1687,9 @@ hipError_t enable_large_lds() {
                         (const void*)inv_last_kernel<PREC_F32>, (const void*)inv_last_kernel<PREC_SPLIT16>,
                         (const void*)strip_kernel<PREC_F64, true>, (const void*)strip_kernel<PREC_F64, false>,
                         (const void*)strip_kernel<PREC_F32, true>, (const void*)strip_kernel<PREC_F32, false>,
-                        (const void*)strip_kernel<PREC_SPLIT16, true>, (const void*)strip_kernel<PREC_SPLIT16, false>};
+                        (const void*)strip_kernel<PREC_SPLIT16, true>, (const void*)strip_kernel<PREC_SPLIT16, false>,
+                        (const void*)stencil_fwd2_kernel<PREC_F64>, (const void*)stencil_fwd2_kernel<PREC_F32>,
+                        (const void*)stencil_fwd2_kernel<PREC_SPLIT16>};
     for (const void* k : ks) {
       // whatever the kernel's static LDS leaves of the 160 KiB (at most lim)
       hipFuncAttributes fa{};

@@ -27,6 +27,8 @@ namespace pma {
 // kernels.hip
 hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int count, hipStream_t s);
 hipError_t launch_stencil(int prec, int dim, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
+hipError_t launch_stencil_fwd2(int prec, const int4* tiles, int ntiles, int lneed, const StepArgs& sa, hipStream_t s);
+int fused_lds_bytes(int prec, int ld, int n, bool basis);
 hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
                         hipStream_t s);
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
@@ -851,7 +853,8 @@ struct Table {
   std::vector<SubRange> rng;
   int4* d = nullptr;
   int maxld = 32;
-  int lneed = 0;  // strip launches: largest LDS footprint with the basis copied in (if it fits)
+  int lneed = 0;     // strip / fused launches: largest LDS footprint with the basis copied in (if it fits)
+  int lneed_nb = 0;  // fused launches: largest LDS footprint without the basis copy
   void begin_sub() { rng.push_back(SubRange{(int)h.size(), 0}); }
   void end_sub() { rng.back().count = (int)h.size() - rng.back().first; }
   int size() const { return (int)h.size(); }
@@ -952,6 +955,10 @@ struct Batch {
   // axis 1) per workgroup.
   void stencil_tiles(int gs, int march, std::vector<int4>& out) const {
     const SubDev& sd = h_subs[gs];
+    if (fused_[gs]) {  // 16 full rows per workgroup, stencil + forward last-axis product
+      for (int r = 0; r < sd.n[0]; r += kStChunk) out.push_back(int4{gs, r, 0, 0});
+      return;
+    }
     const int n0 = sd.n[0], n1 = sd.n[1], nl = sd.n[sd.dim - 1];
     const int nct = (nl + kStWmax - 1) / kStWmax;
     const int W = (nl + nct - 1) / nct;
@@ -967,6 +974,11 @@ struct Batch {
             out.push_back(int4{gs, p | (std::min(march, n0 - p) << 16), r, c | (std::min(W, nl - c) << 16)});
     }
   }
+  // 2D subdomains of preconditioned instances take the stencil fused with the forward product
+  // along the last axis when that axis is at most 320 wide (padded)
+  bool fuse = true;
+  std::vector<char> fused_;
+  int stencil_kind(int gs) const { return fused_[gs] ? 4 : h_subs[gs].dim; }
   // chunks per workgroup when not tuned: enough workgroups to fill the chip several times over
   int st_march = 1;
   int stencil_march_default() const {
@@ -1102,6 +1114,11 @@ struct Batch {
         h_subs.push_back(sd);
       }
     }
+    fused_.assign(h_subs.size(), 0);
+    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
+      const SubDev& sd = h_subs[gs];
+      fused_[gs] = fuse && sd.dim == 2 && insts[sd.inst]->tm.gamma > 0 && sd.ax[1].ld <= 320;
+    }
     st_march = stencil_march_default();
     {
       std::vector<int4> tmp;
@@ -1131,9 +1148,15 @@ struct Batch {
             for (int c = 0; c < C; c += kStCols) tab[2].h.push_back(int4{gs, r, c, 0});
         } else {
           const int la = I.dim - 1;
-          for (int r = 0; r < R; r += kRows)
-            for (int c = 0; c < C; c += kCols) tab[3].h.push_back(int4{gs, r, c, 0});
-          tab[3].maxld = std::max(tab[3].maxld, sd.ax[la].ld);
+          if (!fused_[gs]) {
+            for (int r = 0; r < R; r += kRows)
+              for (int c = 0; c < C; c += kCols) tab[3].h.push_back(int4{gs, r, c, 0});
+            tab[3].maxld = std::max(tab[3].maxld, sd.ax[la].ld);
+          } else {
+            const int nb = fused_lds_bytes(prec, sd.ax[1].ld, n1, false), wb = fused_lds_bytes(prec, sd.ax[1].ld, n1, true);
+            tab[1].lneed = std::max(tab[1].lneed, wb <= kLdsBasisCap ? wb : nb);
+            tab[1].lneed_nb = std::max(tab[1].lneed_nb, nb);
+          }
           if (I.dim == 3) {
             for (int i0 = 0; i0 < n0; ++i0)
               for (int c = 0; c < n2; c += kStrip) {
@@ -1254,7 +1277,12 @@ struct Batch {
     if (count <= 0) return;
     const Table& t = tab[ph];
     switch (ph) {
-      case 1: HIPCHK(launch_stencil(prec, stencil_dim_, t.d + first, count, sa, st)); break;
+      case 1:
+        if (stencil_kind_ == 4)
+          HIPCHK(launch_stencil_fwd2(prec, t.d + first, count, count <= kLdsBasisMaxTiles ? t.lneed : t.lneed_nb, sa, st));
+        else
+          HIPCHK(launch_stencil(prec, stencil_kind_, t.d + first, count, sa, st));
+        break;
       case 2: HIPCHK(launch_euler(prec, t.d + first, count, part_base_eu + first, sa, st)); break;
       case 3: HIPCHK(launch_fwd_last(prec, t.d + first, count, t.maxld, sa, st)); break;
       case 4: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 0, 1, sa, st)); break;
@@ -1268,7 +1296,7 @@ struct Batch {
     }
   }
   int pair_src_ = 1;
-  int stencil_dim_ = 2;
+  int stencil_kind_ = 2;
 
   // one phase of a step: all subdomains in one launch, or one subdomain per launch (plain)
   void launch_phase(int ph, bool plain, hipStream_t st) {
@@ -1281,28 +1309,29 @@ struct Batch {
       return;
     }
     if (ph == 1 || ph == 5) {
-      // 2D and 3D subdomains take different stencil kernels, and the axis-0 pair reads T in 2D
-      // and F in 3D: launch the two groups separately
-      for (int dim = 2; dim <= 3; ++dim) {
-        pair_src_ = dim == 2 ? 1 : 0;
-        stencil_dim_ = dim;
+      // 2D, fused 2D and 3D subdomains take different stencil kernels, and the axis-0 pair reads
+      // T in 2D and F in 3D: launch the groups separately
+      auto key = [&](int q) { return ph == 1 ? stencil_kind(q) : h_subs[q].dim; };
+      for (int kv = 2; kv <= 4; ++kv) {
+        pair_src_ = kv == 2 ? 1 : 0;
+        stencil_kind_ = kv;
         if (!plain) {
-          // contiguous runs of subdomains of this dimension
+          // contiguous runs of subdomains of this kind
           int s = 0;
           while (s < nsub) {
-            if (h_subs[s].dim != dim) {
+            if (key(s) != kv) {
               ++s;
               continue;
             }
             int e = s;
-            while (e < nsub && h_subs[e].dim == dim) ++e;
+            while (e < nsub && key(e) == kv) ++e;
             const int f = tab[ph].rng[s].first, l = tab[ph].rng[e - 1].first + tab[ph].rng[e - 1].count;
             launch_range(ph, f, l - f, st);
             s = e;
           }
         } else {
           for (int s = 0; s < nsub; ++s)
-            if (h_subs[s].dim == dim) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
+            if (key(s) == kv) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
         }
       }
       return;
@@ -1340,8 +1369,12 @@ struct Batch {
         continue;
       }
       const double nl = s.dim == 2 ? n1 : n2;
-      flops[3] += 2.0 * nodes * nl;
-      bytes[3] += 2 * el * nodes;
+      if (fused_[q]) {
+        flops[1] += 2.0 * nodes * nl;  // the stencil writes T = F A_1 instead of F
+      } else {
+        flops[3] += 2.0 * nodes * nl;
+        bytes[3] += 2 * el * nodes;
+      }
       if (s.dim == 3) {
         flops[4] += 2.0 * nodes * n1;
         flops[6] += 2.0 * nodes * n1;
@@ -1471,6 +1504,7 @@ static void run_to_end(pma_ctx* c, const std::vector<Instance*>& all, int prec, 
     B.ctx = c;
     B.prec = prec;
     B.insts = live;
+    B.fuse = !plain;  // the plain method keeps one launch per kernel
     B.build();
     for (size_t q = 0; q < live.size(); ++q)
       if (!live[q]->initialized) init_state(c, *live[q], B, (int)q);
@@ -2055,6 +2089,7 @@ int pma_plan_create(pma_ctx* c, int count, const pma_request* reqs, pma_plan** o
       raw.push_back(I.get());
     }
     P->batch.reset(new Batch);
+    P->batch->fuse = !P->plain;  // the plain method keeps one launch per kernel
     P->batch->ctx = c;
     P->batch->prec = prec;
     P->batch->insts = raw;
@@ -2160,6 +2195,18 @@ int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, dou
     if (flops) flops[ph] = fl[ph];
     if (bytes) bytes[ph] = by[ph];
   }
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_set_fusion(pma_plan* P, int on) {
+  API_BEGIN
+  if (!P) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  for (auto& I : P->insts)
+    if (I->steps_done > 0) return fail(PMA_E_INVAL, "fusion can only be changed before the first step");
+  P->batch->fuse = on != 0;
+  P->batch->build();
   return PMA_OK;
   API_END
 }

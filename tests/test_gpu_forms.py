@@ -159,6 +159,21 @@ def test_stencil_march_and_autotune_bitwise(ctx, B, wl):
             np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["split16", "fp32", "fp64"])
+def test_fused_stencil_equals_separate_launches_bitwise(ctx, B, prec):
+    # stencil fused with the forward last-axis product vs the two separate launches
+    ws = [W.sine_dd(n=161, parts=(2, 3), overlap=6, steps=12)] + W.bumps_batch(4, steps=12, n_lo=33, n_hi=97)
+    outs = []
+    for fuse in (True, False):
+        with B.Plan(ctx, ws, prec) as p:
+            p.set_fusion(fuse)
+            p.step(12)
+            p.sync()
+            outs.append([p.mesh(i)[0] for i in range(len(ws))])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_warm_start_and_psi_out(ctx):
     # 30 steps, then 20 more from the oracle's Psi, against 50 oracle steps; Psi itself is
     # returned with the constants the FP32 path removed added back
