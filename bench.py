@@ -14,6 +14,7 @@ the plain FP64 form (one subdomain per launch, FP64 everywhere, no graph); the 6
 serving stream (meshes/s, p50/p99 latency), and the stencil at a >= 1 GB working set.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -26,6 +27,22 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBs": 8000.0, "fp16_TF": 2500.0, "fp32_TF": 157.3, "fp64_TF": 78.6}
 MFMA_PEAK = {"split16": PEAK["fp16_TF"], "fp32": PEAK["fp32_TF"], "fp64": PEAK["fp64_TF"]}
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def traffic_of(workload, phase):
+    """HBM bytes per launch of a step phase's kernel on `workload` from the committed rocprofv3 counters
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
+    calibration), or None when the kernel source has changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    with open(os.path.join(ROOT, "paper_2006_14602_amd", "csrc", "kernels.hip"), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("kernels_hip_sha256"):
+            return None
+    e = rec.get("entries", {}).get(workload, {}).get(phase)
+    return None if e is None else e["fetch_bytes"] + e["write_bytes"]
 KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil_fwd2_kernel / stencil2_kernel / stencil3_kernel",
           "euler": "euler_kernel",
           "fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel<single>", "pair0": "strip_kernel<pair>",
@@ -66,8 +83,9 @@ def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0, tune=
             "phases": phases}
 
 
-def roofline_of(phases, prec):
-    """Dominant kernel of a step: algorithmic work per launch / mean launch duration."""
+def roofline_of(phases, prec, workload=None):
+    """Dominant kernel of a step: algorithmic work per launch / mean launch duration; traffic from
+    the committed counters of `workload` when they are current."""
     name, ph = max(((k, v) for k, v in phases.items() if v["flops"] > 0 or v["bytes"] > 0),
                    key=lambda kv: kv[1]["ms"])
     sec = ph["ms"] * 1e-3
@@ -75,11 +93,11 @@ def roofline_of(phases, prec):
         ach = ph["flops"] / sec / 1e12
         peak = MFMA_PEAK[prec]
         return {"kernel": KERNEL[name], "phase": name, "bound": "mfma", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_of(workload, name),
                 "algorithmic_per_launch": ph["flops"], "avg_launch_ms": ph["ms"]}
     ach = ph["bytes"] / sec / 1e9
     return {"kernel": KERNEL[name], "phase": name, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"],
-            "unit": "GB/s", "frac": ach / PEAK["hbm_GBs"], "traffic": None,
+            "unit": "GB/s", "frac": ach / PEAK["hbm_GBs"], "traffic": traffic_of(workload, name),
             "algorithmic_per_launch": ph["bytes"], "avg_launch_ms": ph["ms"]}
 
 
@@ -97,7 +115,8 @@ def stencil_roofline(ctx, binding, workloads):
     st = ph["stencil"]
     gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9
     return {"kernel": "stencil2_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-            "frac": gbs / PEAK["hbm_GBs"], "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
+            "frac": gbs / PEAK["hbm_GBs"], "traffic": traffic_of("stencil_large", "stencil"),
+            "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
             "stencil_march": march, "autotune_ms": [round(t, 4) for t in cand],
             "workload": "2 x 8193^2 sine layer, 32x32 parts, FP32 (8 B per node)"}
 
@@ -223,7 +242,7 @@ def main():
                    "precision": {"split16": "fp32 state/stencil, fp16 hi+lo matrix-core DCT, fp32 accumulate",
                                  "fp32": "fp32 everywhere", "fp64": "fp64 everywhere"}[prec],
                    "exec": "plain" if main_form == "fp64plain" else "batched (graph replay)"},
-        "roofline": roofline_of(m["phases"], prec),
+        "roofline": roofline_of(m["phases"], prec, "sine_dd_513_" + main_form),
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "phases"} for k, v in forms.items()},
         "phases_ms_per_launch": {k: {p: round(v["ms"], 5) for p, v in f["phases"].items()}
                                  for k, f in forms.items()},

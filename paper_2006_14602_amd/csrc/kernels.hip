@@ -644,7 +644,16 @@ template <> struct Op<PREC_SPLIT16> {
     f.lo = *(const half8_t*)((const _Float16*)lo + r * ld + k0 + 8 * g);
     return f;
   }
+  static __device__ inline frag zero_frag() {
+    frag f;
+    f.hi = half8_t{0, 0, 0, 0, 0, 0, 0, 0};
+    f.lo = half8_t{0, 0, 0, 0, 0, 0, 0, 0};
+    return f;
+  }
   enum { BASIS_BYTES = 4 };  // LDS bytes per basis entry (hi + lo)
+  // row strides pad 16 bytes beyond the padded axis length: the 16 rows of a fragment then start
+  // in distinct LDS bank groups (operand: fp32 entries; basis: fp16 entries per array)
+  enum { OPAD = 4, BPAD = 8 };
   static __device__ inline void mma(acc_t& c, const frag& a, const frag& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.lo, b.hi, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.lo, c, 0, 0, 0);
@@ -668,7 +677,8 @@ template <> struct Op<PREC_F32> {
   static __device__ inline frag lbasis_frag(const char* p, const char*, int ld, int r, int k0, int g) {
     return ((const float*)p)[r * ld + k0 + g];
   }
-  enum { BASIS_BYTES = 4 };
+  static __device__ inline frag zero_frag() { return 0.f; }
+  enum { BASIS_BYTES = 4, OPAD = 4, BPAD = 4 };
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -690,7 +700,8 @@ template <> struct Op<PREC_F64> {
   static __device__ inline frag lbasis_frag(const char* p, const char*, int ld, int r, int k0, int g) {
     return ((const double*)p)[r * ld + k0 + g];
   }
-  enum { BASIS_BYTES = 8 };
+  static __device__ inline frag zero_frag() { return 0.0; }
+  enum { BASIS_BYTES = 8, OPAD = 2, BPAD = 2 };
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -698,80 +709,120 @@ template <> struct Op<PREC_F64> {
   static __device__ inline int crow(int g, int q) { return g + 4 * q; }
 };
 
-// acc += rows of the LDS operand (16 x ld) times basis rows (as columns of B), and the mirror
-// image.  Basis fragments come from L2: four k steps are requested before any is used so their
-// latencies overlap (deeper groups cost occupancy on the larger batches without helping).
+// acc += rows of the LDS operand (16 x ld, row stride ldo) times basis rows (as columns of B; row
+// stride ldb), and the mirror image.  Basis fragments come from L2: four k steps are requested
+// before any is used so their latencies overlap.  Every product is issued: a k step past the end
+// of the axis multiplies a zero basis fragment with valid data, so the accumulator chain has no
+// branch (a conditional product would make the compiler copy the accumulator out and back,
+// waiting for each product to finish).
 template <int KIND>
-__device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, float sc,
-                                        const void* bh, const void* bl, int brow, int l16, int g) {
+__device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, int ldo, float sc,
+                                        const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
   typedef Op<KIND> O;
   constexpr int U = 4;
   for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
     typename O::frag b[U];
-    const int nu = min(U, (ld - k0) / (int)O::KB);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (u < nu) b[u] = O::glob_frag(bh, bl, ld, brow, k0 + u * O::KB, g);
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * O::KB;
+      b[u] = k < ld ? O::glob_frag(bh, bl, ldb, brow, k, g) : O::zero_frag();
+    }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (u < nu) O::mma(acc, O::lds_frag(lds, ld, l16, k0 + u * O::KB, g, sc), b[u]);
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * O::KB;
+      O::mma(acc, O::lds_frag(lds, ldo, l16, k < ld ? k : k0, g, sc), b[u]);
+    }
   }
 }
 
 template <int KIND>
-__device__ inline void mma_basis_by_lds(typename Op<KIND>::acc_t& acc, const void* ah, const void* al,
-                                        const char* lds, int ld, float sc, int arow, int l16, int g) {
+__device__ inline void mma_basis_by_lds(typename Op<KIND>::acc_t& acc, const void* ah, const void* al, int ldb,
+                                        const char* lds, int ld, int ldo, float sc, int arow, int l16, int g) {
   typedef Op<KIND> O;
   constexpr int U = 4;
   for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
     typename O::frag a[U];
-    const int nu = min(U, (ld - k0) / (int)O::KB);
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (u < nu) a[u] = O::glob_frag(ah, al, ld, arow, k0 + u * O::KB, g);
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * O::KB;
+      a[u] = k < ld ? O::glob_frag(ah, al, ldb, arow, k, g) : O::zero_frag();
+    }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (u < nu) O::mma(acc, a[u], O::lds_frag(lds, ld, l16, k0 + u * O::KB, g, sc));
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * O::KB;
+      O::mma(acc, a[u], O::lds_frag(lds, ldo, l16, k < ld ? k : k0, g, sc));
+    }
   }
 }
 
-// acc += basis rows (a copy in LDS) times the LDS data operand: no global-memory latency
+// Products with a basis copy in LDS take at most 12 row (column) blocks: three per wave.
+constexpr int kLdsRb = 3;
+
+// acc[t] += basis rows (row block wave + 4 t, a basis copy in LDS) x the LDS data operand, k
+// outermost: the data fragment of a k step is read (and split) once for all row blocks, the basis
+// fragments of all row blocks are requested before the first product, and the independent
+// accumulators keep the matrix cores busy.  All kLdsRb products are issued every k step (no branch
+// in the accumulator chains); the caller uses the row blocks that exist.
 template <int KIND>
-__device__ inline void mma_lbasis_by_lds(typename Op<KIND>::acc_t& acc, const char* bh, const char* bl,
-                                         const char* lds, int ld, float sc, int arow, int l16, int g) {
+__device__ inline void mma_lbasis_rows(typename Op<KIND>::acc_t (&acc)[kLdsRb], const char* bh, const char* bl,
+                                       int ldb, const char* lds, int ld, int ldo, float sc, int wave, int nrb,
+                                       int l16, int g) {
   typedef Op<KIND> O;
-  for (int k0 = 0; k0 < ld; k0 += O::KB) O::mma(acc, O::lbasis_frag(bh, bl, ld, arow, k0, g), O::lds_frag(lds, ld, l16, k0, g, sc));
+  // a row block beyond the axis reads the last basis row (valid memory); its result is unused
+  int row[kLdsRb];
+#pragma unroll
+  for (int t = 0; t < kLdsRb; ++t) row[t] = min((wave + 4 * t) * 16 + l16, nrb * 16 - 1);
+  for (int k0 = 0; k0 < ld; k0 += O::KB) {
+    typename O::frag a[kLdsRb];
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) a[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
+    const typename O::frag b = O::lds_frag(lds, ldo, l16, k0, g, sc);
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) O::mma(acc[t], a[t], b);
+  }
 }
 
-// acc += rows of the LDS operand times basis rows of a basis copy in LDS (as columns of B)
+// acc[t] += LDS data rows x basis rows (column block wave + 4 t) of a basis copy in LDS, k outermost
 template <int KIND>
-__device__ inline void mma_lds_by_lbasis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, float sc,
-                                         const char* bh, const char* bl, int brow, int l16, int g) {
+__device__ inline void mma_rows_lbasis(typename Op<KIND>::acc_t (&acc)[kLdsRb], const char* lds, int ld, int ldo,
+                                       float sc, const char* bh, const char* bl, int ldb, int wave, int nrb, int l16,
+                                       int g) {
   typedef Op<KIND> O;
-  for (int k0 = 0; k0 < ld; k0 += O::KB) O::mma(acc, O::lds_frag(lds, ld, l16, k0, g, sc), O::lbasis_frag(bh, bl, ld, brow, k0, g));
+  int row[kLdsRb];
+#pragma unroll
+  for (int t = 0; t < kLdsRb; ++t) row[t] = min((wave + 4 * t) * 16 + l16, nrb * 16 - 1);
+  for (int k0 = 0; k0 < ld; k0 += O::KB) {
+    typename O::frag b[kLdsRb];
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) b[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
+    const typename O::frag a = O::lds_frag(lds, ldo, l16, k0, g, sc);
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) O::mma(acc[t], a, b[t]);
+  }
 }
 
-// Copy `bytes` (a multiple of 1 KiB) from global memory into LDS with direct-to-LDS loads, which
+// Copy `bytes` (a multiple of 16) from global memory into LDS with direct-to-LDS loads, which
 // need no registers and are all in flight together: wave w copies the 1 KiB chunks w, w + 4, ..,
 // lane l bytes [16 l, 16 l + 16) of a chunk.  Complete after vmem_drain() and a barrier.
 __device__ inline void lds_dma(char* dst, const void* src, int bytes) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   for (int ch = wave; ch * 1024 < bytes; ch += 4)
-    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((const char*)src + ch * 1024 + lane * 16),
-                                     (__attribute__((address_space(3))) void*)(dst + ch * 1024), 16, 0, 0);
+    if (ch * 1024 + lane * 16 < bytes)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((const char*)src + ch * 1024 + lane * 16),
+                                       (__attribute__((address_space(3))) void*)(dst + ch * 1024), 16, 0, 0);
 }
 
 constexpr int kMaxLd = 576;            // widest padded axis (9 row blocks of 64)
 constexpr int kColU = kMaxLd / 64;      // column loads per row and lane
 
 // Stage rows [row0, row0 + 16) x columns [0, ld) of a row-major R x C array into LDS as the data
-// operand (zero beyond R and C); returns this thread's largest magnitude.  Wave w takes rows
-// w + 4 j, lane l columns l + 64 u; the loads of two rows are issued before any is used, so a
-// tile costs two memory round trips rather than one per element.
+// operand (row stride ldo; zero beyond R and C); returns this thread's largest magnitude.  Wave w
+// takes rows w + 4 j, lane l columns l + 64 u; the loads of two rows are issued before any is
+// used, so a tile costs two memory round trips rather than one per element.
 template <int KIND>
-__device__ inline float stage_rows16(char* lds, int ld, const gmem<typename Op<KIND>::T>* src, int row0, int R,
-                                     int C) {
+__device__ inline float stage_rows16(char* lds, int ld, int ldo, const gmem<typename Op<KIND>::T>* src, int row0,
+                                     int R, int C) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -797,7 +848,7 @@ __device__ inline float stage_rows16(char* lds, int ld, const gmem<typename Op<K
       for (int u = 0; u < kColU; ++u) {
         const int k = lane + 64 * u;
         if (k < ld) {
-          O::put(lds, ld, r, k, v[j][u]);
+          O::put(lds, ldo, r, k, v[j][u]);
           if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j][u]));
         }
       }
@@ -807,12 +858,12 @@ __device__ inline float stage_rows16(char* lds, int ld, const gmem<typename Op<K
 }
 
 // Stage the 16-column strip [col0, col0 + 16) of a row-major K x ncol array transposed into LDS
-// (operand row c = strip column, k = index along the axis; zero beyond K and ncol); returns this
-// thread's largest magnitude.  Thread t takes column t % 16 and rows t / 16 + 16 j; twelve loads
-// are in flight per batch.
+// (operand row c = strip column, k = index along the axis, row stride ldo; zero beyond K and
+// ncol); returns this thread's largest magnitude.  Thread t takes column t % 16 and rows
+// t / 16 + 16 j; twelve loads are in flight per batch.
 template <int KIND>
-__device__ inline float stage_strip16(char* lds, int ld, const gmem<typename Op<KIND>::T>* src, int K, int ncol,
-                                      int col0) {
+__device__ inline float stage_strip16(char* lds, int ld, int ldo, const gmem<typename Op<KIND>::T>* src, int K,
+                                      int ncol, int col0) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   constexpr int B = 12;
@@ -830,7 +881,7 @@ __device__ inline float stage_strip16(char* lds, int ld, const gmem<typename Op<
     for (int j = 0; j < B; ++j) {
       const int k = kb + k0 + 16 * j;
       if (k < ld) {
-        O::put(lds, ld, c, k, v[j]);
+        O::put(lds, ldo, c, k, v[j]);
         if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j]));
       }
     }
@@ -869,14 +920,15 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   const int row0 = tl.y, col0 = tl.z;
   __shared__ float red[4];
   const gmem<T>* __restrict__ src = gp<T>(S.F);
-  const float amax = stage_rows16<KIND>(lds, ld, src, row0, R, C);
+  const int ldo = ld + O::OPAD;
+  const float amax = stage_rows16<KIND>(lds, ld, ldo, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
   const int cb = (col0 >> 4) + wave;
   if (cb * 16 >= C) return;
   typename O::acc_t acc = {0, 0, 0, 0};
-  mma_lds_by_basis<KIND>(acc, lds, ld, sc, A.fwd, A.fwdl, cb * 16 + l16, l16, g);
+  mma_lds_by_basis<KIND>(acc, lds, ld, ldo, sc, A.fwd, A.fwdl, A.ldb, cb * 16 + l16, l16, g);
   gmem<T>* __restrict__ out = gpw<T>(S.T);
   const T us = T(A.fwd_unscale) / T(sc);
   const int c = cb * 16 + l16;
@@ -940,7 +992,8 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const int row0 = tl.y, col0 = tl.z;
   __shared__ float redf[4];
   const gmem<T>* __restrict__ src = gp<T>(S.F);
-  const float amax = stage_rows16<KIND>(lds, ld, src, row0, R, C);
+  const int ldo = ld + O::OPAD;
+  const float amax = stage_rows16<KIND>(lds, ld, ldo, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale(amax, redf) : 1.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
@@ -963,7 +1016,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
       old[q] = (r < R && c < C) ? phi[(long)r * C + c] : T(0);
     }
     typename O::acc_t acc = {0, 0, 0, 0};
-    mma_lds_by_basis<KIND>(acc, lds, ld, sc, A.inv, A.invl, cb * 16 + l16, l16, g);
+    mma_lds_by_basis<KIND>(acc, lds, ld, ldo, sc, A.inv, A.invl, A.ldb, cb * 16 + l16, l16, g);
     bool bad = false;
     for (int q = 0; q < 4; ++q) {
       const int r = row0 + O::crow(g, q);
@@ -1041,14 +1094,16 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   gmem<T>* __restrict__ dst = gpw<T>(src_sel ? S.F : S.T) + base;
   __shared__ float red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int uwave = __builtin_amdgcn_readfirstlane(wave);  // the same, known uniform
   const int nrb = (K + 15) >> 4;
   const int c = col0 + l16;
   const void* b1h = (PAIR || !inv) ? A.fwd : A.inv;
   const void* b1l = (PAIR || !inv) ? A.fwdl : A.invl;
-  // basis copy in LDS after the strip: nrb * 16 rows of ld entries (split form: hi, then lo)
-  const int dbytes = 16 * ld * O::LDS_BYTES;
-  const int bbytes = nrb * 16 * ld * (O::BASIS_BYTES / (O::SCALED ? 2 : 1));
-  const bool lbasis = dbytes + (O::SCALED ? 2 : 1) * bbytes <= lcap;
+  // basis copy in LDS after the strip: nrb * 16 rows of stride ldb (split form: hi, then lo)
+  const int ldo = ld + O::OPAD, ldb = A.ldb;
+  const int dbytes = 16 * ldo * O::LDS_BYTES;
+  const int bbytes = nrb * 16 * ldb * (O::BASIS_BYTES / (O::SCALED ? 2 : 1));
+  const bool lbasis = nrb <= 4 * kLdsRb && dbytes + (O::SCALED ? 2 : 1) * bbytes <= lcap;
   char* lbh = lds + dbytes;
   char* lbl = lbh + bbytes;
   if (lbasis) {
@@ -1077,19 +1132,26 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
       }
   }
   // strip transposed into LDS: operand row c = strip column, k = index along the axis
-  const float amax = stage_strip16<KIND>(lds, ld, src, K, ncol, col0);
+  const float amax = stage_strip16<KIND>(lds, ld, ldo, src, K, ncol, col0);
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   if (lbasis) vmem_drain();
   __syncthreads();
   typename O::acc_t acc[MAXRB];
   const T us1 = ((PAIR || !inv) ? T(A.fwd_unscale) : T(1)) / T(sc);
 #pragma unroll
-  for (int t = 0; t < MAXRB; ++t) {
-    acc[t] = typename O::acc_t{0, 0, 0, 0};
-    const int rb = wave + 4 * t;
-    if (rb < nrb) {
-      if (lbasis) mma_lbasis_by_lds<KIND>(acc[t], lbh, lbl, lds, ld, sc, rb * 16 + l16, l16, g);
-      else mma_basis_by_lds<KIND>(acc[t], b1h, b1l, lds, ld, sc, rb * 16 + l16, l16, g);
+  for (int t = 0; t < MAXRB; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
+  if (lbasis) {
+    typename O::acc_t a3[kLdsRb];
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
+    mma_lbasis_rows<KIND>(a3, lbh, lbl, ldb, lds, ld, ldo, sc, uwave, nrb, l16, g);
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) acc[t] = a3[t];
+  } else {
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, ld, ldo, sc, rb * 16 + l16, l16, g);
     }
   }
   if constexpr (!PAIR) {
@@ -1128,7 +1190,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
       const int rb = wave + 4 * t;
       if (rb >= nrb) continue;
       for (int q = 0; q < 4; ++q) {
-        O::put(lds, ld, l16, rb * 16 + O::crow(g, q), acc[t][q]);
+        O::put(lds, ldo, l16, rb * 16 + O::crow(g, q), acc[t][q]);
         if (O::SCALED) ymax = fmaxf(ymax, fabsf((float)acc[t][q]));
       }
     }
@@ -1136,22 +1198,35 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
     // zero the padding rows nrb*16 .. ld of the operand
     for (int idx = threadIdx.x; idx < 16 * (ld - nrb * 16); idx += 256) {
       const int k = nrb * 16 + idx / 16, cc = idx & 15;
-      O::put(lds, ld, cc, k, T(0));
+      O::put(lds, ldo, cc, k, T(0));
     }
     __syncthreads();
     // store scale: 1 / sy, and on the LDS path (N / 2) D^-1 and the split form's 2^-s
     const T half_n = T(K - 1) / T(2);
     const T os = lbasis ? T(A.fwd_unscale) * half_n / T(sy) : T(1) / T(sy);
 #pragma unroll
+    for (int t = 0; t < MAXRB; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
+    if (lbasis) {
+      typename O::acc_t a3[kLdsRb];
+#pragma unroll
+      for (int t = 0; t < kLdsRb; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
+      mma_lbasis_rows<KIND>(a3, lbh, lbl, ldb, lds, ld, ldo, sy, uwave, nrb, l16, g);
+#pragma unroll
+      for (int t = 0; t < kLdsRb; ++t) acc[t] = a3[t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < MAXRB; ++t) {
+        const int rb = wave + 4 * t;
+        if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], A.inv, A.invl, ldb, lds, ld, ldo, sy, rb * 16 + l16, l16, g);
+      }
+    }
+#pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
       const int rb = wave + 4 * t;
       if (rb >= nrb) continue;
-      typename O::acc_t z = {0, 0, 0, 0};
-      if (lbasis) mma_lbasis_by_lds<KIND>(z, lbh, lbl, lds, ld, sy, rb * 16 + l16, l16, g);
-      else mma_basis_by_lds<KIND>(z, A.inv, A.invl, lds, ld, sy, rb * 16 + l16, l16, g);
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
-        if (i < K && c < ncol) dst[(long)i * ncol + c] = z[q] * ((lbasis && (i == 0 || i == K - 1)) ? T(2) * os : os);
+        if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][q] * ((lbasis && (i == 0 || i == K - 1)) ? T(2) * os : os);
       }
     }
   }
@@ -1167,7 +1242,8 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
 constexpr int kFuseMaxLd = 320;           // widest last axis (padded) the fused kernel takes
 constexpr int kFuseU = kFuseMaxLd / 64;   // column groups per lane
 
-// LDS layout of the fused kernel: operand [16][ld] | halo [18][ld + 4] (rounded to 1 KiB) | basis
+// LDS layout of the fused kernel: operand [16][ld + OPAD] | halo [18][ld + 4] (rounded to 1 KiB)
+// | basis copy (rows of stride ldb)
 template <int KIND>
 __host__ __device__ inline int fused_halo_bytes(int ld) {
   return ((18 * (ld + 4) * (int)sizeof(typename Op<KIND>::T) + 1023) / 1024) * 1024;
@@ -1175,7 +1251,7 @@ __host__ __device__ inline int fused_halo_bytes(int ld) {
 
 template <int KIND, int MK>
 __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K, const MonP<typename Op<KIND>::T>& mp,
-                                    const typename Op<KIND>::T* halo, int HS, char* op, int ld, int row0,
+                                    const typename Op<KIND>::T* halo, int HS, char* op, int ld, int ldo, int row0,
                                     NodeCheck<typename Op<KIND>::T>& chk, float& amax) {
   typedef Op<KIND> O;
   typedef typename O::T T;
@@ -1208,7 +1284,7 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K, c
         f = K.lvt + log_rho_det(M.template excess<2>(x0b + gx, x1, T(0)), e);
         chk.add(e, f);
       }
-      O::put(op, ld, rr, j, f);
+      O::put(op, ldo, rr, j, f);
       if (O::SCALED) amax = fmaxf(amax, fabsf((float)f));
     }
   }
@@ -1230,15 +1306,16 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
   const MonP<T>* mp = load_ctx(sa, tl.x, K, phi_, F_);
   const SubDev& S = sa.subs[tl.x];
   const AxisDev& A = S.ax[1];
-  const int ld = A.ld, n0 = K.n0, n1 = K.n1, row0 = tl.y;
+  const int ld = A.ld, ldo = ld + O::OPAD, ldb = A.ldb, n0 = K.n0, n1 = K.n1, row0 = tl.y;
   const int HS = ld + 4;
   char* op = lds;
-  T* halo = (T*)(lds + 16 * ld * O::LDS_BYTES);
+  T* halo = (T*)(lds + 16 * ldo * O::LDS_BYTES);
   const int nrb = (n1 + 15) >> 4;
-  const int bbytes = nrb * 16 * ld * (O::BASIS_BYTES / (O::SCALED ? 2 : 1));
+  const int bbytes = nrb * 16 * ldb * (O::BASIS_BYTES / (O::SCALED ? 2 : 1));
   char* lbh = (char*)halo + fused_halo_bytes<KIND>(ld);
   char* lbl = lbh + bbytes;
-  const bool lbasis = 16 * ld * O::LDS_BYTES + fused_halo_bytes<KIND>(ld) + (O::SCALED ? 2 : 1) * bbytes <= lcap;
+  const bool lbasis =
+      nrb <= 4 * kLdsRb && 16 * ldo * O::LDS_BYTES + fused_halo_bytes<KIND>(ld) + (O::SCALED ? 2 : 1) * bbytes <= lcap;
   if (lbasis) {
     lds_dma(lbh, A.fwd, bbytes);
     if (O::SCALED) lds_dma(lbl, A.fwdl, bbytes);
@@ -1273,28 +1350,43 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
   NodeCheck<T> chk;
   float amax = 0.f;
   switch (mp->kind) {
-    case MON_CONST: fused_nodes2<KIND, MON_CONST>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
-    case MON_RADIAL: fused_nodes2<KIND, MON_RADIAL>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
-    case MON_SINE: fused_nodes2<KIND, MON_SINE>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
-    case MON_GAUSS: fused_nodes2<KIND, MON_GAUSS>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
-    default: fused_nodes2<KIND, MON_SEPARABLE>(K, *mp, halo, HS, op, ld, row0, chk, amax); break;
+    case MON_CONST: fused_nodes2<KIND, MON_CONST>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
+    case MON_RADIAL: fused_nodes2<KIND, MON_RADIAL>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
+    case MON_SINE: fused_nodes2<KIND, MON_SINE>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
+    case MON_GAUSS: fused_nodes2<KIND, MON_GAUSS>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
+    default: fused_nodes2<KIND, MON_SEPARABLE>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
   }
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   if (lbasis) vmem_drain();
   __syncthreads();
   gmem<T>* out = gpw<T>(S.T);
   const T us = T(A.fwd_unscale) / T(sc);
+  constexpr int NT = (kFuseMaxLd / 16 + 3) / 4;
+  typename O::acc_t acc[NT];
 #pragma unroll
-  for (int t = 0; t < (kFuseMaxLd / 16 + 3) / 4; ++t) {
+  for (int t = 0; t < NT; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
+  if (lbasis) {
+    typename O::acc_t a3[kLdsRb];
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
+    mma_rows_lbasis<KIND>(a3, op, ld, ldo, sc, lbh, lbl, ldb, __builtin_amdgcn_readfirstlane(wave), nrb, l16, g);
+#pragma unroll
+    for (int t = 0; t < kLdsRb; ++t) acc[t] = a3[t];
+  } else {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int cb = wave + 4 * t;
+      if (cb < nrb) mma_lds_by_basis<KIND>(acc[t], op, ld, ldo, sc, A.fwd, A.fwdl, ldb, cb * 16 + l16, l16, g);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
     const int cb = wave + 4 * t;
     if (cb >= nrb) break;
-    typename O::acc_t acc = {0, 0, 0, 0};
-    if (lbasis) mma_lds_by_lbasis<KIND>(acc, op, ld, sc, lbh, lbl, cb * 16 + l16, l16, g);
-    else mma_lds_by_basis<KIND>(acc, op, ld, sc, A.fwd, A.fwdl, cb * 16 + l16, l16, g);
     const int c = cb * 16 + l16;
     for (int q = 0; q < 4; ++q) {
       const int r = row0 + O::crow(g, q);
-      if (r < n0 && c < n1) out[(long)r * n1 + c] = acc[q] * us;
+      if (r < n0 && c < n1) out[(long)r * n1 + c] = acc[t][q] * us;
     }
   }
   const int bad = chk.bits();
@@ -1604,8 +1696,9 @@ hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, 
   return hipGetLastError();
 }
 
+// LDS bytes of a 16-row data operand for a padded axis length ld (row stride ld + 16 bytes)
 static inline size_t op_lds(int prec, int ld) {
-  return (size_t)16 * ld * (prec == PREC_F64 ? 8 : 4);
+  return (size_t)16 * (ld + (prec == PREC_F64 ? 2 : 4)) * (prec == PREC_F64 ? 8 : 4);
 }
 
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s) {
@@ -1649,11 +1742,13 @@ hipError_t launch_stencil_fwd2(int prec, const int4* tiles, int ntiles, int lnee
   return hipGetLastError();
 }
 
-// LDS bytes of the fused kernel for a last axis of padded length ld with n nodes (basis copied or not)
-int fused_lds_bytes(int prec, int ld, int n, bool basis) {
+// LDS bytes of the fused kernel for a last axis of padded length ld and basis row stride ldb with
+// n nodes (basis copied or not)
+int fused_lds_bytes(int prec, int ld, int ldb, int n, bool basis) {
   const int ob = prec == PREC_F64 ? 8 : 4;
   const int hb = prec == PREC_F64 ? fused_halo_bytes<PREC_F64>(ld) : fused_halo_bytes<PREC_F32>(ld);
-  return 16 * ld * ob + hb + (basis ? ((n + 15) / 16) * 16 * ld * ob : 0);
+  const int bb = prec == PREC_F64 ? 8 : 4;  // basis bytes per entry (split form: hi + lo)
+  return (int)op_lds(prec, ld) + hb + (basis ? ((n + 15) / 16) * 16 * ldb * bb : 0);
 }
 
 // lneed: the largest LDS footprint (strip + basis copy) among the launch's subdomains whose copy

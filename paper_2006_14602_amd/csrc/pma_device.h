@@ -34,15 +34,16 @@ struct MonP {
 };
 
 // DCT-I basis of one axis of a subdomain, in the precision of the solve.  Matrices have
-// round_up(n, 16) rows and ld = round_up(n, 32) columns, zero padded, row-major; both are
-// symmetric, so row j also serves as column j.
+// round_up(n, 16) rows of ld = round_up(n, 32) entries, zero padded, row-major with row stride
+// ldb; both are symmetric, so row j also serves as column j.
 struct AxisDev {
   const void* fwd;     // forward transform (split form: fp16 hi part of 2^s * A)
   const void* fwdl;    // split form: fp16 lo part of 2^s * A (else null)
   const void* inv;     // inverse transform (split form: fp16 hi part)
   const void* invl;    // split form: fp16 lo part
   const void* sig;     // 4 sin^2(pi k / (2 N)), k = 0..n-1, working precision
-  int ld;              // padded row length (multiple of 32)
+  int ld;              // padded axis length (multiple of 32): the products' K extent
+  int ldb;             // row stride of the matrices: ld plus 16 bytes (LDS bank spread)
   float fwd_unscale;   // 2^-s (split form), else 1
 };
 

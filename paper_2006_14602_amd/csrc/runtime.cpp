@@ -28,7 +28,7 @@ namespace pma {
 hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int count, hipStream_t s);
 hipError_t launch_stencil(int prec, int dim, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
 hipError_t launch_stencil_fwd2(int prec, const int4* tiles, int ntiles, int lneed, const StepArgs& sa, hipStream_t s);
-int fused_lds_bytes(int prec, int ld, int n, bool basis);
+int fused_lds_bytes(int prec, int ld, int ldb, int n, bool basis);
 hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
                         hipStream_t s);
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
@@ -170,6 +170,7 @@ class Arena {
 // them (refs) and afterwards as a cache, evicted least recently used when the arena is full
 struct Basis {
   int n = 0, prec = 0, rows = 0, ld = 0;  // rows = round_up(n, 16), ld = round_up(n, 32)
+  int ldb = 0;                             // row stride: ld plus 16 bytes
   int refs = 0;
   uint64_t last_use = 0;
   char* mem = nullptr;
@@ -661,8 +662,14 @@ static void* arena_alloc(pma_ctx* c, size_t b) {
 
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// row stride of the DCT matrices: the padded length plus 16 bytes, so that the 16 rows of a
+// matrix-core fragment start in distinct LDS bank groups when the matrix is copied into LDS
+static int basis_stride(int n, int prec) {
+  return round_up(n, 32) + (prec == PMA_FP64 ? 2 : prec == PMA_FP32 ? 4 : 8);
+}
+
 static size_t basis_bytes(int n, int prec) {
-  const size_t rl = (size_t)round_up(n, 16) * round_up(n, 32);
+  const size_t rl = (size_t)round_up(n, 16) * basis_stride(n, prec);
   if (prec == PMA_FP64) return 2 * Arena::round(rl * 8) + Arena::round((size_t)n * 8);
   if (prec == PMA_FP32) return 2 * Arena::round(rl * 4) + Arena::round((size_t)n * 4);
   return 4 * Arena::round(rl * 2) + Arena::round((size_t)n * 4);
@@ -683,7 +690,8 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
   b->prec = prec;
   b->rows = round_up(n, 16);
   b->ld = round_up(n, 32);
-  const size_t rl = (size_t)b->rows * b->ld;
+  b->ldb = basis_stride(n, prec);
+  const size_t rl = (size_t)b->rows * b->ldb;
   b->bytes = basis_bytes(n, prec);
   b->mem = (char*)arena_alloc(c, b->bytes);
   char* p = b->mem;
@@ -698,8 +706,8 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
       std::vector<double> A64(rl, 0.0), B64(rl, 0.0);
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
-          A64[(size_t)i * b->ld + j] = A[(size_t)i * n + j];
-          B64[(size_t)i * b->ld + j] = B[(size_t)i * n + j];
+          A64[(size_t)i * b->ldb + j] = A[(size_t)i * n + j];
+          B64[(size_t)i * b->ldb + j] = B[(size_t)i * n + j];
         }
       b->fwd = put(A64.data(), rl * 8);
       b->inv = put(B64.data(), rl * 8);
@@ -711,8 +719,8 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
         std::vector<float> A32(rl, 0.f), B32(rl, 0.f);
         for (int i = 0; i < n; ++i)
           for (int j = 0; j < n; ++j) {
-            A32[(size_t)i * b->ld + j] = (float)A[(size_t)i * n + j];
-            B32[(size_t)i * b->ld + j] = (float)B[(size_t)i * n + j];
+            A32[(size_t)i * b->ldb + j] = (float)A[(size_t)i * n + j];
+            B32[(size_t)i * b->ldb + j] = (float)B[(size_t)i * n + j];
           }
         b->fwd = put(A32.data(), rl * 4);
         b->inv = put(B32.data(), rl * 4);
@@ -727,7 +735,7 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
             Blo(rl, (_Float16)0.f);
         for (int i = 0; i < n; ++i)
           for (int j = 0; j < n; ++j) {
-            const size_t src = (size_t)i * n + j, dst = (size_t)i * b->ld + j;
+            const size_t src = (size_t)i * n + j, dst = (size_t)i * b->ldb + j;
             const double as = A[src] * sc;
             Ahi[dst] = (_Float16)as;
             Alo[dst] = (_Float16)(as - (double)Ahi[dst]);
@@ -941,6 +949,7 @@ struct Batch {
   static AxisDev axis_dev(const Basis* b) {
     AxisDev a{};
     a.ld = b->ld;
+    a.ldb = b->ldb;
     a.fwd = b->fwd;
     a.fwdl = b->fwdl;
     a.inv = b->inv;
@@ -1019,8 +1028,8 @@ struct Batch {
   // 16 x ld operand entries and round_up(n, 16) x ld basis entries (split form: hi + lo)
   void note_lds(Table& t, int n, int ld) const {
     const int ob = prec == PMA_FP64 ? 8 : 4;
-    const int bb = prec == PMA_FP64 ? 8 : 4;
-    const int need = 16 * ld * ob + ((n + 15) / 16) * 16 * ld * bb;
+    const int bb = prec == PMA_FP64 ? 8 : 4;  // basis bytes per entry (split form: hi + lo)
+    const int need = 16 * (ld + 16 / ob) * ob + ((n + 15) / 16) * 16 * basis_stride(n, prec) * bb;
     if (need <= kLdsBasisCap) t.lneed = std::max(t.lneed, need);
   }
 
@@ -1153,7 +1162,8 @@ struct Batch {
               for (int c = 0; c < C; c += kCols) tab[3].h.push_back(int4{gs, r, c, 0});
             tab[3].maxld = std::max(tab[3].maxld, sd.ax[la].ld);
           } else {
-            const int nb = fused_lds_bytes(prec, sd.ax[1].ld, n1, false), wb = fused_lds_bytes(prec, sd.ax[1].ld, n1, true);
+            const int nb = fused_lds_bytes(prec, sd.ax[1].ld, sd.ax[1].ldb, n1, false);
+            const int wb = fused_lds_bytes(prec, sd.ax[1].ld, sd.ax[1].ldb, n1, true);
             tab[1].lneed = std::max(tab[1].lneed, wb <= kLdsBasisCap ? wb : nb);
             tab[1].lneed_nb = std::max(tab[1].lneed_nb, nb);
           }
