@@ -115,7 +115,7 @@ def stencil_roofline(ctx, binding, workloads):
     st = ph["stencil"]
     gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9
     return {"kernel": "stencil2_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-            "frac": gbs / PEAK["hbm_GBs"], "traffic": traffic_of("stencil_large", "stencil"),
+            "frac": gbs / PEAK["hbm_GBs"], "traffic": traffic_of("stencil_large", f"stencil@march={march}"),
             "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
             "stencil_march": march, "autotune_ms": [round(t, 4) for t in cand],
             "workload": "2 x 8193^2 sine layer, 32x32 parts, FP32 (8 B per node)"}
