@@ -30,6 +30,12 @@ Readings of points the paper leaves open (listed again in the design notes):
   * Subdomain preconditioner: homogeneous Neumann on every subdomain face; F := 0 and no update
     on artificial-boundary nodes.
   * Stop rule (Algorithm 1, step 6): the maximum over subdomains (all converged) by default.
+  * Alternating DD (Algorithm 1) with more than two subdomains: the subdomains are updated one
+    after another within a step, each first taking its artificial-boundary values from the
+    owners' latest values (time n+1 for owners already updated in this step, time n for the
+    rest).  The sweep order is the lexicographic order of the block index ("alternating"), or
+    the 2^d parity classes of the block index in lexicographic order of the parity tuple, each
+    class in block order ("coloured").  With two subdomains both are Algorithm 1 exactly.
 """
 from __future__ import annotations
 
@@ -575,13 +581,24 @@ def solve_single(grid: GridSpec, mon: dict, dt: float, gamma: float, steps: int,
     return Result(psi, mesh, hist, n, min_det_hessian(psi, box), min_cell_measure(mesh))
 
 
+def sweep_order(dec: Decomposition, mode: str) -> list:
+    """Order in which the alternating form (Algorithm 1) visits the subdomains."""
+    M = len(dec.subs)
+    if mode == "alternating":
+        return list(range(M))
+    if mode == "coloured":
+        return sorted(range(M), key=lambda si: (tuple(i % 2 for i in dec.subs[si].index), si))
+    raise ValueError(mode)
+
+
 def solve_dd(grid: GridSpec, parts, overlap_cells, mon: dict, dt: float, gamma: float, steps: int,
              tol: float = 0.0, mode: str = "parallel", stop: str = "max", psi0=None, theta_val=None,
              refresh: bool = True) -> Result:
     """Overlapping DD-PMA.  mode="parallel": eq. transmission_condition3, every subdomain reads
-    its neighbours' time-n values.  mode="alternating": Algorithm 1, subdomains swept in order,
-    each reading the latest values.  Glue (Sec. 4.5, "combining" the subdomain meshes): refresh
-    the artificial nodes, then take each global node from its owner."""
+    its neighbours' time-n values.  mode="alternating" / "coloured": Algorithm 1, subdomains swept
+    in the order of sweep_order, each reading the latest values.  Glue (Sec. 4.5, "combining"
+    the subdomain meshes): refresh the artificial nodes, then take each global node from its
+    owner."""
     dec = Decomposition(grid, parts, overlap_cells)
     th = theta(mon, grid.lo, grid.hi) if theta_val is None else theta_val
     if psi0 is None:
@@ -604,8 +621,9 @@ def solve_dd(grid: GridSpec, parts, overlap_cells, mon: dict, dt: float, gamma: 
                 new.append(p)
                 res.append(r)
             states = new
-        elif mode == "alternating":
-            for si, s in enumerate(dec.subs):
+        elif mode in ("alternating", "coloured"):
+            for si in sweep_order(dec, mode):
+                s = dec.subs[si]
                 for o, dst, src in dec.trans[si]:
                     states[si].reshape(-1)[dst] = states[o].reshape(-1)[src]
                 states[si], r = step_box(states[si], s.box, mon, th, grid.vol, dt, gamma)

@@ -302,3 +302,183 @@ def test_transmission_sources_are_live_nodes():
         total_art = sum(int(s.box.artificial_mask().sum()) for s in dec.subs)
         total_listed = sum(len(dst) for lists in dec.trans for _, dst, _ in lists)
         assert total_art == total_listed
+
+
+# --- Alternating DD (Algorithm 1): subdomains updated in turn, each reading the latest values --
+
+def _boxes_and_owner(n, parts, ov):
+    """Node ranges per axis, subdomain boxes (block order) and the global owner array, from the
+    partition rule alone (pinned above by the worked split)."""
+    d = len(n)
+    axes = [O.partition_axis(n[k] - 1, parts[k], ov[k]) for k in range(d)]
+    boxes = []
+    for idx in np.ndindex(*parts):
+        boxes.append(tuple(axes[k][1][idx[k]] for k in range(d)))
+    own_axes = [O.owner_axis(np.arange(n[k]), axes[k][0]) for k in range(d)]
+    own = np.ravel_multi_index(np.meshgrid(*own_axes, indexing="ij"), parts)
+    return boxes, own
+
+
+def _masks(n, box):
+    """Global masks of a box's nodes and of its artificial (inner-face) nodes."""
+    d = len(n)
+    inside = np.ones(n, dtype=bool)
+    art = np.zeros(n, dtype=bool)
+    for k in range(d):
+        idx = np.arange(n[k])
+        lo, hi = box[k]
+        shape = [1] * d
+        shape[k] = -1
+        inside &= ((idx >= lo) & (idx <= hi)).reshape(shape)
+        face = np.zeros(n[k], dtype=bool)
+        if lo > 0:
+            face[lo] = True
+        if hi < n[k] - 1:
+            face[hi] = True
+        art |= face.reshape(shape)
+    art &= inside
+    return inside, art
+
+
+def _alternating_by_whole_domain_steps(g, parts, ov, mon, dt, steps, order):
+    """Forward-Euler alternating DD written with whole-domain steps: every subdomain keeps a
+    whole-grid field that is valid on its box.  Its turn: artificial nodes <- owners' latest
+    values; one whole-domain Euler step of (other nodes from their owners, own box from its own
+    field); keep the result on the box's non-artificial nodes.  The Euler stencil of a node
+    that is not artificial stays inside the box, so this is the subdomain step exactly."""
+    n = g.n
+    boxes, own = _boxes_and_owner(n, parts, ov)
+    th = O.theta(mon, g.lo, g.hi)
+    psi0 = O.initial_psi(g.whole_box())
+    fields = [psi0.copy() for _ in boxes]
+    masks = [_masks(n, b) for b in boxes]
+
+    def glued():
+        out = np.empty(n)
+        for s in range(len(boxes)):
+            out[own == s] = fields[s][own == s]
+        return out
+
+    for _ in range(steps):
+        for s in order:
+            inside, art = masks[s]
+            for o in range(len(boxes)):
+                sel = art & (own == o)
+                fields[s][sel] = fields[o][sel]
+            G = glued()
+            G[inside] = fields[s][inside]
+            E = O.solve_single(g, mon, dt, 0.0, 1, psi0=G, theta_val=th).psi
+            live = inside & ~art
+            fields[s][live] = E[live]
+    for s in range(len(boxes)):  # refresh before the glue
+        inside, art = masks[s]
+        for o in range(len(boxes)):
+            sel = art & (own == o)
+            fields[s][sel] = fields[o][sel]
+    return glued(), fields, boxes
+
+
+@pytest.mark.parametrize("n,parts,ov,mode", [
+    ((25, 25), (2, 1), (4, 4), "alternating"),
+    ((25, 25), (3, 1), (4, 4), "coloured"),
+    ((25, 25), (2, 2), (3, 4), "alternating"),
+    ((25, 29), (3, 2), (4, 3), "alternating"),
+    ((25, 29), (3, 2), (4, 3), "coloured"),
+    ((13, 13, 13), (2, 1, 2), (3, 3, 3), "alternating"),
+])
+def test_alternating_euler_equals_whole_domain_steps(n, parts, ov, mode):
+    g = O.GridSpec(n, (0.0,) * len(n), (1.0,) * len(n))
+    mon = W.ring_monitor(d=len(n))
+    dt, steps = 2e-4, 4
+    r = O.solve_dd(g, parts, ov, mon, dt, 0.0, steps, mode=mode)
+    dec = O.Decomposition(g, parts, ov)
+    order = O.sweep_order(dec, mode)
+    want, fields, boxes = _alternating_by_whole_domain_steps(g, parts, ov, mon, dt, steps, order)
+    np.testing.assert_array_equal(r.psi, want)
+    for s, b in enumerate(boxes):
+        sl = tuple(slice(lo, hi + 1) for lo, hi in b)
+        np.testing.assert_array_equal(r.sub_psi[s], fields[s][sl])
+    # reading the owners' newest values matters: the parallel form differs
+    par = O.solve_dd(g, parts, ov, mon, dt, 0.0, steps)
+    assert np.max(np.abs(par.psi - r.psi)) > 1e-12
+
+
+def test_sweep_orders():
+    dec = O.Decomposition(O.GridSpec((33, 33), (0.0, 0.0), (1.0, 1.0)), (4, 1), (4, 4))
+    assert O.sweep_order(dec, "alternating") == [0, 1, 2, 3]
+    assert O.sweep_order(dec, "coloured") == [0, 2, 1, 3]
+    dec = O.Decomposition(O.GridSpec((33, 33), (0.0, 0.0), (1.0, 1.0)), (3, 3), (4, 4))
+    assert O.sweep_order(dec, "coloured") == [0, 2, 6, 8, 1, 7, 3, 5, 4]
+    # 2 x 2 (x 2): every parity class is one subdomain, so both orders are the block order
+    for shape, parts in (((17, 17), (2, 2)), ((9, 9, 9), (2, 2, 2))):
+        dec = O.Decomposition(O.GridSpec(shape, (0.0,) * len(shape), (1.0,) * len(shape)), parts, (3,) * len(shape))
+        assert O.sweep_order(dec, "coloured") == O.sweep_order(dec, "alternating")
+
+
+def _alternating_1d_bruteforce(n, parts, ov, A, K, C, dt, gamma, steps, order):
+    """1D alternating DD by loops: Neumann ghosts Psi_{-1} = Psi_1 - 2 h a, Psi_{N+1} =
+    Psi_{N-1} + 2 h b at the physical ends, F = log(rho(Psi') Psi'' / theta) with the exact
+    theta of 1 + A sech^2(K (x - C)) on [0, 1], and (I - gamma L) delta = F solved with the
+    assembled subdomain matrix (Neumann reflection at both ends of the subdomain)."""
+    h = 1.0 / (n - 1)
+    xi = np.linspace(0.0, 1.0, n)
+    cores, ranges = O.partition_axis(n - 1, parts, ov)
+    own = O.owner_axis(np.arange(n), cores)
+    th = 1.0 + (A / K) * (math.tanh(K * (1.0 - C)) - math.tanh(K * (0.0 - C)))
+    states = [0.5 * xi[lo:hi + 1] ** 2 for lo, hi in ranges]
+
+    def refresh(m):
+        lo, hi = ranges[m]
+        for v in (lo, hi):
+            if 0 < v < n - 1:
+                o = own[v]
+                states[m][v - lo] = states[o][v - ranges[o][0]]
+
+    for _ in range(steps):
+        for m in order:
+            refresh(m)
+            lo, hi = ranges[m]
+            P = states[m]
+            L = len(P)
+            F = np.zeros(L)
+            for j in range(L):
+                v = lo + j
+                if (j == 0 and v > 0) or (j == L - 1 and v < n - 1):
+                    continue
+                left = P[j - 1] if j > 0 else P[1] - 2.0 * h * 0.0
+                right = P[j + 1] if j < L - 1 else P[j - 1] + 2.0 * h * 1.0
+                d1 = (right - left) / (2.0 * h)
+                d2 = (right - 2.0 * P[j] + left) / (h * h)
+                rho = 1.0 + A / math.cosh(K * (d1 - C)) ** 2
+                F[j] = math.log(rho * d2 / th)
+            M = np.eye(L)
+            for j in range(L):
+                M[j, j] += 2.0 * gamma / (h * h)
+                if j > 0:
+                    M[j, j - 1] -= (2.0 if j == L - 1 else 1.0) * gamma / (h * h)
+                if j < L - 1:
+                    M[j, j + 1] -= (2.0 if j == 0 else 1.0) * gamma / (h * h)
+            delta = np.linalg.solve(M, F)
+            for j in range(L):
+                v = lo + j
+                if not ((j == 0 and v > 0) or (j == L - 1 and v < n - 1)):
+                    P[j] += dt * delta[j]
+    for m in range(len(ranges)):
+        refresh(m)
+    out = np.empty(n)
+    for v in range(n):
+        o = own[v]
+        out[v] = states[o][v - ranges[o][0]]
+    return out
+
+
+@pytest.mark.parametrize("parts,mode", [(2, "alternating"), (3, "alternating"), (4, "coloured")])
+def test_alternating_1d_matches_bruteforce(parts, mode):
+    n, ov, A, K, C = 41, 4, 6.0, 12.0, 0.37
+    h = 1.0 / (n - 1)
+    gamma, dt, steps = 4 * h * h, 0.8 * h * h, 12
+    g1 = O.GridSpec((n,), (0.0,), (1.0,))
+    r = O.solve_dd(g1, (parts,), (ov,), W.separable_monitor((A,), (K,), (C,)), dt, gamma, steps, mode=mode)
+    order = O.sweep_order(O.Decomposition(g1, (parts,), (ov,)), mode)
+    want = _alternating_1d_bruteforce(n, parts, ov, A, K, C, dt, gamma, steps, order)
+    assert np.max(np.abs(r.psi - want)) < 1e-13
