@@ -69,7 +69,12 @@ enum {
 
 /* decomposition coupling */
 enum {
-  PMA_DD_PARALLEL = 0   /* Sec. 3 eq. transmission_condition3: neighbours' time-n values */
+  PMA_DD_PARALLEL = 0,    /* Sec. 3 eq. transmission_condition3: neighbours' time-n values */
+  PMA_DD_ALTERNATING = 1, /* Algorithm 1 (eqs. transmission_condition1/2): the subdomains are
+                             updated in turn within a step, in block order (axis 0 slowest),
+                             each taking the owners' latest values at its artificial nodes */
+  PMA_DD_COLOURED = 2     /* Algorithm 1 with the 2^d parity classes of the block index as the
+                             sweep: classes in lexicographic order of the parity tuple */
 };
 
 enum { PMA_FACE_NEUMANN = 0, PMA_FACE_ARTIFICIAL = 1 };
@@ -118,7 +123,9 @@ typedef struct {
 typedef struct {
   int parts[3];         /* subdomains per axis (>= 1) */
   int overlap_cells[3]; /* overlap in cells per axis (>= 2 where parts > 1) */
-  int mode;             /* PMA_DD_PARALLEL */
+  int mode;             /* PMA_DD_PARALLEL / PMA_DD_ALTERNATING / PMA_DD_COLOURED; two subdomains
+                           are never updated together if one reads the other, so the alternating
+                           forms equal the one-subdomain-at-a-time sweep exactly */
 } pma_dd;
 
 typedef struct {
@@ -283,6 +290,14 @@ int pma_server_info(pma_ctx* ctx, int* queued, int* running, int* finished, size
  * row-major part order) and faces (if not NULL) nsub*6 PMA_FACE_* values. cap bounds nsub. */
 int pma_partition(const pma_grid* grid, const pma_dd* dd, int cap, int* nsub, int* ranges,
                   int* faces);
+
+/* Sweep level of every subdomain (row-major part order) under dd->mode, as the solver uses it:
+ * 0 for all in the parallel form; in the alternating forms (Algorithm 1) a subdomain's level is
+ * one more than the highest level among the subdomains it exchanges artificial-node values with
+ * that precede it in the sweep, and the solver advances the levels in order, each in one launch
+ * set.  *nsub receives the number of subdomains; levels (if not NULL) receives nsub ints; cap
+ * bounds nsub.  Errors: PMA_E_INVAL for an invalid grid or decomposition. */
+int pma_sweep_levels(const pma_grid* grid, const pma_dd* dd, int cap, int* nsub, int* levels);
 
 /* theta = int_box rho in FP64 (closed forms where they exist, else Gauss-Legendre quadrature). */
 int pma_theta(const pma_grid* grid, const pma_monitor* mon, double* theta_out);

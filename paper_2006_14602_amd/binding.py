@@ -95,6 +95,7 @@ def load():
     L.pma_poll.argtypes = [c_void_p, c_uint64, POINTER(c_int), POINTER(c_double), POINTER(Stats)]
     L.pma_server_info.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_size_t)]
     L.pma_partition.argtypes = [POINTER(Grid), POINTER(DD), c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
+    L.pma_sweep_levels.argtypes = [POINTER(Grid), POINTER(DD), c_int, POINTER(c_int), POINTER(c_int)]
     L.pma_theta.argtypes = [POINTER(Grid), POINTER(Monitor), POINTER(c_double)]
     L.pma_plan_create.argtypes = [c_void_p, c_int, POINTER(Request), POINTER(c_void_p)]
     L.pma_plan_step.argtypes = [c_void_p, c_int]
@@ -169,6 +170,9 @@ def make_time(t: dict, precision="fp32", exec_="batched", tol=0.0, resid_every=1
     return T
 
 
+DD_MODE = {"parallel": 0, "alternating": 1, "coloured": 2}
+
+
 def make_dd(dd, dim) -> DD:
     D = DD()
     for k in range(3):
@@ -178,7 +182,7 @@ def make_dd(dd, dim) -> DD:
         for k in range(dim):
             D.parts[k] = int(dd["parts"][k])
             D.overlap_cells[k] = int(dd["overlap"][k])
-    D.mode = 0
+    D.mode = DD_MODE[(dd or {}).get("mode", "parallel")]
     return D
 
 
@@ -210,6 +214,17 @@ def partition(grid: dict, dd: dict | None):
     faces = (c_int * (6 * n.value))()
     _check(L.pma_partition(ctypes.byref(G), ctypes.byref(D), n.value, ctypes.byref(n), ranges, faces))
     return np.array(ranges[:], dtype=np.int64).reshape(n.value, 6), np.array(faces[:], dtype=np.int64).reshape(n.value, 6)
+
+
+def sweep_levels(grid: dict, dd: dict) -> np.ndarray:
+    L = load()
+    G = make_grid(grid)
+    D = make_dd(dd, grid["dim"])
+    n = c_int()
+    _check(L.pma_sweep_levels(ctypes.byref(G), ctypes.byref(D), 0, ctypes.byref(n), None))
+    out = (c_int * n.value)()
+    _check(L.pma_sweep_levels(ctypes.byref(G), ctypes.byref(D), n.value, ctypes.byref(n), out))
+    return np.array(out[:], dtype=np.int64)
 
 
 def theta(grid: dict, mon: dict) -> float:

@@ -938,14 +938,16 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   }
 }
 
-// shift removed from phi each step: mean over the instance's subdomains of the DC coefficient
+// shift removed from phi each step: mean of the DC coefficient over the instance's first I.pin
+// subdomains (all of them in the parallel form; the first one, which opens every sweep, in the
+// alternating forms, so that every subdomain of a sweep removes the same constant)
 template <typename T>
 __device__ inline T instance_shift(const StepArgs& sa, const InstDev& I) {
   if (!I.pin) return T(0);
   const gmem<T>* dc = gp<T>(sa.dc);
   T s = T(0);
-  for (int q = 0; q < I.nsub; ++q) s += dc[I.first_sub + q];
-  return s / T(I.nsub);
+  for (int q = 0; q < I.pin; ++q) s += dc[I.first_sub + q];
+  return s / T(I.pin);
 }
 
 // shape and artificial faces of a subdomain, copied into registers (stores to the state arrays
@@ -968,9 +970,12 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 // inverse transform along the last axis for 16 rows x up to 64 columns, fused with the update
 // phi += dt (delta - shift) and the residual partial sum.  Input: F.
 // Push transmission: push_first[tile] .. push_first[tile + 1] index the entries (dst sub, dst
-// node, row, column within the tile) of push[] whose source node lies in the tile; after the
-// update each such node's new value is written into the artificial node of the other subdomain,
-// which is the owner's value the transmission condition gives it for the next step.
+// node, row | later << 8, column within the tile) of push[] whose source node lies in the tile;
+// after the update each such node's new value is written into the artificial node of the other
+// subdomain, which is the owner's value the transmission condition gives it for the next step.
+// In an alternating sweep a destination that is updated later in the same step has not removed
+// this step's shift yet: later = 1 entries add dt * shift back, so every subdomain sees its
+// neighbours' values relative to the same constant.
 template <int KIND>
 __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
                                                        const int* __restrict__ push_first,
@@ -1047,7 +1052,9 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
     __syncthreads();
     for (int e = pf0 + (int)threadIdx.x; e < pf1; e += 256) {
       const int4 P = push[e];
-      gpw<T>(sa.subs[P.x].phi)[P.y] = stash[P.z][P.w];
+      T v = stash[P.z & 0xFF][P.w];
+      if (P.z >> 8) v += dt * shift;
+      gpw<T>(sa.subs[P.x].phi)[P.y] = v;
     }
   }
   const double tot = block_sum256(part, red);

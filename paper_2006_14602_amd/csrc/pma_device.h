@@ -70,7 +70,8 @@ struct InstDev {
   double log_vol_theta;  // log(|Omega_c| / theta)
   double dt;
   int first_sub, nsub;
-  int pin;               // subtract the mean DC coefficient each step (gamma > 0)
+  int pin;               // > 0: subtract each step the mean DC coefficient of subdomains
+                         // first_sub .. first_sub + pin - 1 (gamma > 0)
   int pad_;
 };
 

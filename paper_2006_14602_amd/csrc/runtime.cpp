@@ -407,12 +407,13 @@ static void partition_host(const pma_grid& g, const pma_dd* dd, std::vector<SubH
   validate_grid(g);
   int P[3] = {1, 1, 1}, OV[3] = {0, 0, 0};
   if (dd) {
+    if (dd->mode != PMA_DD_PARALLEL && dd->mode != PMA_DD_ALTERNATING && dd->mode != PMA_DD_COLOURED)
+      thr(PMA_E_INVAL, "unknown decomposition coupling mode");
     for (int k = 0; k < g.dim; ++k) {
       P[k] = dd->parts[k];
       OV[k] = dd->overlap_cells[k];
       if (P[k] < 1) thr(PMA_E_INVAL, "parts must be >= 1");
       if (P[k] > 1 && OV[k] < 2) thr(PMA_E_INVAL, "overlap must be >= 2 cells on a split axis");
-      if (dd->mode != PMA_DD_PARALLEL) thr(PMA_E_INVAL, "only the parallel coupling is available");
     }
   }
   AxisSplit ax[3];
@@ -483,6 +484,9 @@ struct Instance {
   std::vector<int> own[3];
   std::vector<int4> trans;  // (dst local sub, dst elem, src local sub, src elem)
   std::vector<int> trans_first;  // per dst sub, into trans (size nsub + 1)
+  std::vector<int> level;        // sweep level per subdomain (all 0 in the parallel form)
+  int nlevels = 1;
+  bool alternating = false;
   // device memory
   char* block = nullptr;
   size_t bytes = 0;
@@ -517,6 +521,8 @@ struct Instance {
 
 static long sub_nodes(const SubHost& s) { return (long)s.n[0] * s.n[1] * s.n[2]; }
 
+static void build_coupling(Instance& I);
+
 static void build_plan(Instance& I) {
   I.dim = I.grid.dim;
   validate_monitor(I.mon, I.dim);
@@ -530,6 +536,11 @@ static void build_plan(Instance& I) {
   partition_host(I.grid, ddp, I.subs, I.parts, I.own);
   I.theta = I.mon.theta > 0 ? I.mon.theta : theta_host(I.grid, I.mon);
   if (!(I.theta > 0) || !std::isfinite(I.theta)) thr(PMA_E_INVAL, "theta must be positive and finite");
+  build_coupling(I);
+}
+
+// transmission lists and sweep levels of a partitioned instance
+static void build_coupling(Instance& I) {
   // transmission lists: walk the artificial faces only; a node on several artificial faces is
   // listed once, under the first face (axis order, low side first) that holds it
   const int ns = (int)I.subs.size();
@@ -576,6 +587,39 @@ static void build_plan(Instance& I) {
       }
   }
   I.trans_first[ns] = (int)I.trans.size();
+  // Sweep levels of the alternating forms (Algorithm 1).  The subdomains are visited one at a
+  // time in the sweep order; a subdomain's level is one more than the highest level among the
+  // subdomains it exchanges values with that come before it in the sweep.  Two subdomains of
+  // one level never exchange values, so advancing a whole level at once gives exactly the
+  // one-at-a-time sweep, while a subdomain still reads the latest values of every neighbour.
+  I.level.assign(ns, 0);
+  I.nlevels = 1;
+  I.alternating = !I.whole && I.dd.mode != PMA_DD_PARALLEL;
+  if (I.alternating) {
+    std::vector<int> sweep(ns), pos(ns);
+    for (int q = 0; q < ns; ++q) sweep[q] = q;  // block order, axis 0 slowest
+    if (I.dd.mode == PMA_DD_COLOURED) {
+      auto parity = [&](int q) {
+        const int p2 = q % I.parts[2], p1 = (q / I.parts[2]) % I.parts[1], p0 = q / (I.parts[1] * I.parts[2]);
+        return (p0 % 2) * 4 + (p1 % 2) * 2 + (p2 % 2);
+      };
+      std::stable_sort(sweep.begin(), sweep.end(), [&](int a, int b) { return parity(a) < parity(b); });
+    }
+    for (int i = 0; i < ns; ++i) pos[sweep[i]] = i;
+    std::vector<std::vector<int>> nb(ns);
+    for (const int4& t : I.trans) {
+      nb[t.x].push_back(t.z);
+      nb[t.z].push_back(t.x);
+    }
+    for (int i = 0; i < ns; ++i) {
+      const int q = sweep[i];
+      int lv = 0;
+      for (int o : nb[q])
+        if (pos[o] < i) lv = std::max(lv, I.level[o] + 1);
+      I.level[q] = lv;
+      I.nlevels = std::max(I.nlevels, lv + 1);
+    }
+  }
 }
 
 // bytes of the instance block (state arrays + glue buffers)
@@ -863,8 +907,9 @@ struct Table {
   int maxld = 32;
   int lneed = 0;     // strip / fused launches: largest LDS footprint with the basis copied in (if it fits)
   int lneed_nb = 0;  // fused launches: largest LDS footprint without the basis copy
-  void begin_sub() { rng.push_back(SubRange{(int)h.size(), 0}); }
-  void end_sub() { rng.back().count = (int)h.size() - rng.back().first; }
+  // rng is indexed by batch subdomain; subdomains are laid out in the batch's launch order
+  void begin_sub(int gs) { rng[gs] = SubRange{(int)h.size(), 0}; }
+  void end_sub(int gs) { rng[gs].count = (int)h.size() - rng[gs].first; }
   int size() const { return (int)h.size(); }
 };
 
@@ -908,6 +953,11 @@ struct Batch {
   std::vector<int4> h_push, h_pull;
   std::vector<int> h_pfirst;
   std::vector<SubRange> pull_rng;
+  // launch order: subdomains sorted by sweep level (stable); level L holds positions
+  // lvl_first[L] .. lvl_first[L + 1] - 1 of `order`, and every launch table and the pull list
+  // are laid out in this order, so one level is one contiguous range of each
+  std::vector<int> glevel, order, lvl_first;
+  int nlev = 1;
   int4 *d_push = nullptr, *d_pull = nullptr;
   int* d_pfirst = nullptr;
   Table tab[kPhases];  // tab[0] unused (transmission has its own list)
@@ -1006,11 +1056,11 @@ struct Batch {
     st_march = march;
     Table& t = tab[1];
     t.h.clear();
-    t.rng.clear();
-    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
-      t.begin_sub();
-      stencil_tiles((int)gs, march, t.h);
-      t.end_sub();
+    t.rng.assign(h_subs.size(), SubRange{0, 0});
+    for (int gs : order) {
+      t.begin_sub(gs);
+      stencil_tiles(gs, march, t.h);
+      t.end_sub(gs);
     }
     if (t.h.size() > st_cap) thr(PMA_E_HIP, "stencil table exceeds its buffer");
     HIPCHK(hipMemcpyAsync(t.d, t.h.data(), t.h.size() * 16, hipMemcpyHostToDevice, ctx->stream));
@@ -1041,7 +1091,8 @@ struct Batch {
     std::vector<int> cnt(nt + 1, 0);
     std::vector<int4> ent;
     std::vector<int> tile_of;
-    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
+    pull_rng.assign(h_subs.size(), SubRange{0, 0});
+    for (int gs : order) {
       const bool euler = insts[h_subs[gs].inst]->tm.gamma == 0.0;
       SubRange pr{(int)h_pull.size(), 0};
       for (int e = tr_rng[gs].first; e < tr_rng[gs].first + tr_rng[gs].count; ++e) {
@@ -1055,12 +1106,13 @@ struct Batch {
         const int r = t.w / C, c = t.w - (t.w / C) * C;
         const int nct = (C + kCols - 1) / kCols;
         const int tile = tab[7].rng[t.z].first + (r / kRows) * nct + c / kCols;
-        ent.push_back(int4{t.x, t.y, r % kRows, c % kCols});
+        const int later = glevel[t.x] > glevel[t.z] ? 1 : 0;  // destination updated later this step
+        ent.push_back(int4{t.x, t.y, (r % kRows) | (later << 8), c % kCols});
         tile_of.push_back(tile);
         ++cnt[tile + 1];
       }
       pr.count = (int)h_pull.size() - pr.first;
-      pull_rng.push_back(pr);
+      pull_rng[gs] = pr;
     }
     for (int i = 0; i < nt; ++i) cnt[i + 1] += cnt[i];
     h_pfirst = cnt;
@@ -1094,8 +1146,10 @@ struct Batch {
       id.nsub = (int)I.subs.size();
       // removing a constant from phi is invisible to every derivative only if every artificial
       // node is refilled from the same instance (transmission); held Dirichlet data of a lone
-      // subdomain would be left behind by the shift
-      id.pin = (I.tm.gamma > 0 && !I.single_sub_mode) ? 1 : 0;
+      // subdomain would be left behind by the shift.  The parallel form removes the mean DC
+      // coefficient of all subdomains; an alternating sweep must remove one constant known
+      // before its later levels run: the DC coefficient of subdomain 0, the first of the sweep
+      id.pin = (I.tm.gamma > 0 && !I.single_sub_mode) ? (I.alternating ? 1 : (int)I.subs.size()) : 0;
       h_insts.push_back(id);
       for (size_t s = 0; s < I.subs.size(); ++s) {
         const SubHost& S = I.subs[s];
@@ -1123,6 +1177,22 @@ struct Batch {
         h_subs.push_back(sd);
       }
     }
+    // sweep levels and the launch order
+    glevel.assign(h_subs.size(), 0);
+    nlev = 1;
+    for (size_t q = 0; q < insts.size(); ++q) {
+      if (insts[q]->level.size() != insts[q]->subs.size()) thr(PMA_E_HIP, "internal: plan without sweep levels");
+      for (size_t s = 0; s < insts[q]->subs.size(); ++s) {
+        glevel[h_insts[q].first_sub + s] = insts[q]->level[s];
+        nlev = std::max(nlev, insts[q]->nlevels);
+      }
+    }
+    order.resize(h_subs.size());
+    for (size_t gs = 0; gs < order.size(); ++gs) order[gs] = (int)gs;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return glevel[a] < glevel[b]; });
+    lvl_first.assign(nlev + 1, (int)order.size());
+    for (int p = (int)order.size() - 1; p >= 0; --p) lvl_first[glevel[order[p]]] = p;
+    for (int L = nlev - 1; L >= 0; --L) lvl_first[L] = std::min(lvl_first[L], lvl_first[L + 1]);
     fused_.assign(h_subs.size(), 0);
     for (size_t gs = 0; gs < h_subs.size(); ++gs) {
       const SubDev& sd = h_subs[gs];
@@ -1134,15 +1204,11 @@ struct Batch {
       for (size_t gs = 0; gs < h_subs.size(); ++gs) stencil_tiles((int)gs, 1, tmp);
       st_cap = tmp.size();
     }
-    // tiles, subdomain by subdomain
+    // transmission lists, subdomain by subdomain (an instance's entries stay contiguous)
     for (size_t q = 0; q < insts.size(); ++q) {
       Instance& I = *insts[q];
       const int first = h_insts[q].first_sub;
       for (size_t s = 0; s < I.subs.size(); ++s) {
-        const int gs = first + (int)s;
-        const SubDev& sd = h_subs[gs];
-        const int n0 = sd.n[0], n1 = sd.n[1], n2 = sd.n[2];
-        const int R = I.dim == 2 ? n0 : n0 * n1, C = I.dim == 2 ? n1 : n2;
         SubRange tr{(int)h_trans.size(), 0};
         for (int e = I.trans_first[s]; e < I.trans_first[s + 1]; ++e) {
           const int4 t = I.trans[e];
@@ -1150,7 +1216,17 @@ struct Batch {
         }
         tr.count = (int)h_trans.size() - tr.first;
         tr_rng.push_back(tr);
-        for (int ph = 1; ph < kPhases; ++ph) tab[ph].begin_sub();
+      }
+    }
+    // tiles, subdomain by subdomain in launch order
+    for (int ph = 1; ph < kPhases; ++ph) tab[ph].rng.assign(h_subs.size(), SubRange{0, 0});
+    {
+      for (int gs : order) {
+        const SubDev& sd = h_subs[gs];
+        const Instance& I = *insts[sd.inst];
+        const int n0 = sd.n[0], n1 = sd.n[1], n2 = sd.n[2];
+        const int R = I.dim == 2 ? n0 : n0 * n1, C = I.dim == 2 ? n1 : n2;
+        for (int ph = 1; ph < kPhases; ++ph) tab[ph].begin_sub(gs);
         stencil_tiles(gs, st_march, tab[1].h);
         if (I.tm.gamma == 0.0) {
           for (int r = 0; r < R; r += kStRows)
@@ -1186,7 +1262,7 @@ struct Batch {
             for (int c = 0; c < C; c += kCols) tab[7].h.push_back(int4{gs, r, c, 0});
           tab[7].maxld = std::max(tab[7].maxld, sd.ax[la].ld);
         }
-        for (int ph = 1; ph < kPhases; ++ph) tab[ph].end_sub();
+        for (int ph = 1; ph < kPhases; ++ph) tab[ph].end_sub(gs);
       }
     }
     // residual partial sums: inverse-last tiles, then Euler tiles
@@ -1308,8 +1384,9 @@ struct Batch {
   int pair_src_ = 1;
   int stencil_kind_ = 2;
 
-  // one phase of a step: all subdomains in one launch, or one subdomain per launch (plain)
-  void launch_phase(int ph, bool plain, hipStream_t st) {
+  // one phase of a step over sweep level L (-1: every level in turn): the level's subdomains in
+  // one launch, or one subdomain per launch (plain)
+  void launch_phase(int ph, bool plain, hipStream_t st, int L = -1) {
     const int nsub = (int)h_subs.size();
     if (ph == 0) {
       if (!plain) HIPCHK(launch_transmit(prec, d_subs, d_tr, (int)h_trans.size(), st));
@@ -1318,49 +1395,67 @@ struct Batch {
           if (tr_rng[s].count) HIPCHK(launch_transmit(prec, d_subs, d_tr + tr_rng[s].first, tr_rng[s].count, st));
       return;
     }
+    if (L < 0) {
+      for (int l = 0; l < nlev; ++l) launch_phase(ph, plain, st, l);
+      return;
+    }
+    const int p0 = lvl_first[L], p1 = lvl_first[L + 1];
+    if (p1 <= p0) return;
+    const Table& t = tab[ph];
     if (ph == 1 || ph == 5) {
       // 2D, fused 2D and 3D subdomains take different stencil kernels, and the axis-0 pair reads
       // T in 2D and F in 3D: launch the groups separately
-      auto key = [&](int q) { return ph == 1 ? stencil_kind(q) : h_subs[q].dim; };
+      auto key = [&](int p) { return ph == 1 ? stencil_kind(order[p]) : h_subs[order[p]].dim; };
       for (int kv = 2; kv <= 4; ++kv) {
         pair_src_ = kv == 2 ? 1 : 0;
         stencil_kind_ = kv;
-        if (!plain) {
-          // contiguous runs of subdomains of this kind
-          int s = 0;
-          while (s < nsub) {
-            if (key(s) != kv) {
-              ++s;
-              continue;
-            }
-            int e = s;
-            while (e < nsub && key(e) == kv) ++e;
-            const int f = tab[ph].rng[s].first, l = tab[ph].rng[e - 1].first + tab[ph].rng[e - 1].count;
-            launch_range(ph, f, l - f, st);
-            s = e;
+        int p = p0;
+        while (p < p1) {
+          if (key(p) != kv) {
+            ++p;
+            continue;
           }
-        } else {
-          for (int s = 0; s < nsub; ++s)
-            if (key(s) == kv) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
+          if (plain) {
+            launch_range(ph, t.rng[order[p]].first, t.rng[order[p]].count, st);
+            ++p;
+            continue;
+          }
+          int e = p;  // contiguous run of subdomains of this kind
+          while (e < p1 && key(e) == kv) ++e;
+          const int f = t.rng[order[p]].first, l = t.rng[order[e - 1]].first + t.rng[order[e - 1]].count;
+          launch_range(ph, f, l - f, st);
+          p = e;
         }
       }
       return;
     }
-    if (!plain) launch_range(ph, 0, tab[ph].size(), st);
-    else
-      for (int s = 0; s < nsub; ++s) launch_range(ph, tab[ph].rng[s].first, tab[ph].rng[s].count, st);
+    if (!plain) {
+      const int f = t.rng[order[p0]].first, l = t.rng[order[p1 - 1]].first + t.rng[order[p1 - 1]].count;
+      launch_range(ph, f, l - f, st);
+    } else {
+      for (int p = p0; p < p1; ++p) launch_range(ph, t.rng[order[p]].first, t.rng[order[p]].count, st);
+    }
   }
 
-  // a step: the gather of forward-Euler instances (the others received their owners' values from
-  // the previous step's inverse-last kernels), then the stencil and the update
+  // a step, sweep level by sweep level (one level in the parallel form): the gather of
+  // forward-Euler subdomains (the others received their owners' values from the inverse-last
+  // kernels that updated those owners), then the stencil and the update
   void launch_step(bool plain, hipStream_t st) {
-    if (!plain) {
-      if (!h_pull.empty()) HIPCHK(launch_transmit(prec, d_subs, d_pull, (int)h_pull.size(), st));
-    } else {
-      for (size_t s = 0; s < pull_rng.size(); ++s)
-        if (pull_rng[s].count) HIPCHK(launch_transmit(prec, d_subs, d_pull + pull_rng[s].first, pull_rng[s].count, st));
+    for (int L = 0; L < nlev; ++L) {
+      const int p0 = lvl_first[L], p1 = lvl_first[L + 1];
+      if (p1 <= p0) continue;
+      if (!plain) {
+        const int f = pull_rng[order[p0]].first;
+        const int l = pull_rng[order[p1 - 1]].first + pull_rng[order[p1 - 1]].count;
+        if (l > f) HIPCHK(launch_transmit(prec, d_subs, d_pull + f, l - f, st));
+      } else {
+        for (int p = p0; p < p1; ++p) {
+          const SubRange& r = pull_rng[order[p]];
+          if (r.count) HIPCHK(launch_transmit(prec, d_subs, d_pull + r.first, r.count, st));
+        }
+      }
+      for (int ph = 1; ph < kPhases; ++ph) launch_phase(ph, plain, st, L);
     }
-    for (int ph = 1; ph < kPhases; ++ph) launch_phase(ph, plain, st);
   }
 
   // algorithmic work per step of each phase: 2 M N K flops per product; compulsory bytes with
@@ -1856,6 +1951,27 @@ int pma_partition(const pma_grid* grid, const pma_dd* dd, int cap, int* nsub, in
   API_END
 }
 
+int pma_sweep_levels(const pma_grid* grid, const pma_dd* dd, int cap, int* nsub, int* levels) {
+  API_BEGIN
+  if (!grid || !dd || !nsub) return fail(PMA_E_INVAL, "NULL argument");
+  Instance I;
+  I.grid = *grid;
+  I.dd = *dd;
+  I.dim = grid->dim;
+  I.whole = true;
+  for (int k = 0; k < grid->dim && k < 3; ++k)
+    if (dd->parts[k] > 1) I.whole = false;
+  partition_host(I.grid, dd, I.subs, I.parts, I.own);
+  build_coupling(I);
+  *nsub = (int)I.subs.size();
+  if (levels) {
+    if ((int)I.subs.size() > cap) return fail(PMA_E_INVAL, "cap too small");
+    for (size_t q = 0; q < I.subs.size(); ++q) levels[q] = I.level[q];
+  }
+  return PMA_OK;
+  API_END
+}
+
 int pma_theta(const pma_grid* grid, const pma_monitor* mon, double* out) {
   API_BEGIN
   if (!grid || !mon || !out) return fail(PMA_E_INVAL, "NULL argument");
@@ -2028,6 +2144,8 @@ int pma_solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], con
   }
   I.subs = {S};
   I.trans_first = {0, 0};
+  I.level = {0};
+  I.nlevels = 1;
   I.theta = mon->theta > 0 ? mon->theta : theta_host(I.grid, I.mon);
   I.user_psi = (double*)psi_dev;
   alloc_instance(c, I);

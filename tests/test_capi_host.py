@@ -93,3 +93,39 @@ def test_null_arguments_rejected(L):
     assert L.pma_dd_mesh(None, None, None, None, None, None, None, None, None) == B.PMA_E_INVAL
     st = ctypes.c_int()
     assert L.pma_poll(None, 1, ctypes.byref(st), None, None) == B.PMA_E_INVAL
+
+
+@pytest.mark.parametrize("n,parts,ov", [((513, 513), (4, 4), (8, 8)), ((65, 65), (4, 1), (3, 3)),
+                                        ((65, 49), (3, 2), (4, 2)), ((49, 49, 49), (2, 2, 2), (6, 6, 6)),
+                                        ((49, 49, 49), (3, 1, 2), (4, 4, 4))])
+@pytest.mark.parametrize("mode", ["alternating", "coloured"])
+def test_sweep_levels_reproduce_the_sweep(L, n, parts, ov, mode):
+    # every pair of subdomains that exchange values is ordered by level as the sweep orders them,
+    # so advancing level by level is the one-at-a-time sweep of Algorithm 1
+    d = len(n)
+    lv = B.sweep_levels(W.grid(list(n)), {"parts": list(parts), "overlap": list(ov), "mode": mode})
+    dec = O.Decomposition(O.GridSpec(n, (0.0,) * d, (1.0,) * d), parts, ov)
+    order = O.sweep_order(dec, mode)
+    pos = {s: i for i, s in enumerate(order)}
+    pairs = 0
+    for dst, lists in enumerate(dec.trans):
+        for src, _, _ in lists:
+            pairs += 1
+            assert lv[src] != lv[dst]
+            assert (lv[src] < lv[dst]) == (pos[src] < pos[dst])
+    assert pairs > 0
+    assert lv[order[0]] == 0
+    par = B.sweep_levels(W.grid(list(n)), {"parts": list(parts), "overlap": list(ov)})
+    assert not par.any()
+
+
+def test_sweep_level_counts(L):
+    g = W.grid([513, 513])
+    lv = B.sweep_levels(g, {"parts": [4, 4], "overlap": [8, 8], "mode": "alternating"})
+    assert list(lv) == [2 * i + j for i in range(4) for j in range(4)]
+    lv = B.sweep_levels(g, {"parts": [4, 4], "overlap": [8, 8], "mode": "coloured"})
+    assert list(lv) == [2 * (i % 2) + (j % 2) for i in range(4) for j in range(4)]
+    lv = B.sweep_levels(W.grid([65, 65]), {"parts": [4, 1], "overlap": [3, 3], "mode": "coloured"})
+    assert list(lv) == [0, 1, 0, 1]
+    lv = B.sweep_levels(W.grid([49, 49, 49]), {"parts": [2, 2, 2], "overlap": [6, 6, 6], "mode": "alternating"})
+    assert list(lv) == list(range(8))
