@@ -91,7 +91,58 @@ def rho(mon: dict, X: np.ndarray) -> np.ndarray:
         for ax in range(d):
             out = out * (1.0 + mon["amp_axes"][ax] * _sech2(mon["k_axes"][ax] * (X[..., ax] - mon["c"][ax])))
         return out
+    if kind in ARCLEN_KINDS:
+        # arc-length monitor of a given solution u (Sec. 4, eq. monitfn)
+        G = grad_u(mon, X)
+        return np.sqrt(1.0 + np.sum(G * G, axis=-1))
     raise ValueError(f"unknown monitor kind {kind!r}")
+
+
+ARCLEN_KINDS = ("arclen_front", "arclen_spiral", "arclen_spheres")
+
+
+def grad_u(mon: dict, X: np.ndarray) -> np.ndarray:
+    """Gradient of the physical solution u behind an arc-length monitor, at X[..., d].
+
+    arclen_front   u = 1 / (1 + exp((x_0 + x_1 - s0) / (2 eps)))      (Sec. 4.1, eq. test_fn1)
+    arclen_spiral  u = 1 + A / (1 + k r^2 cos^2(theta - w r^2)), r and theta polar coordinates
+                   about c                                             (Sec. 4.1, eq. test_fn2)
+    arclen_spheres u = sum_b tanh(k (|x - c_b|^2 - r0^2))   (Sec. 4.2, eqs. test_fn3d1/test_fn3d2)
+    """
+    kind = mon["kind"]
+    d = X.shape[-1]
+    G = np.zeros(X.shape)
+    if kind == "arclen_front":
+        eps, s0 = float(mon["eps"]), float(mon.get("offset", 1.0))
+        s = (X[..., 0] + X[..., 1] - s0) / (2.0 * eps)
+        u = scipy.special.expit(-s)
+        du = -u * (1.0 - u) / (2.0 * eps)       # du/dx_0 = du/dx_1
+        G[..., 0] = du
+        G[..., 1] = du
+        return G
+    if kind == "arclen_spiral":
+        A, k, w = float(mon["amp"]), float(mon["k"]), float(mon["twist"])
+        dx, dy = X[..., 0] - mon["c"][0], X[..., 1] - mon["c"][1]
+        r = np.hypot(dx, dy)
+        th = np.arctan2(dy, dx)
+        phi = th - w * r * r
+        q = k * r * r * np.cos(phi) ** 2
+        # q = k r^2 cos^2(phi), phi = theta - w r^2:
+        #   dq/dr = 2 k r (cos^2 phi + w r^2 sin 2 phi),  (1/r) dq/dtheta = -k r sin 2 phi
+        dq_dr = 2.0 * k * r * (np.cos(phi) ** 2 + w * r * r * np.sin(2.0 * phi))
+        dq_t = -k * r * np.sin(2.0 * phi)
+        f = -A / (1.0 + q) ** 2
+        G[..., 0] = f * (dq_dr * np.cos(th) - dq_t * np.sin(th))
+        G[..., 1] = f * (dq_dr * np.sin(th) + dq_t * np.cos(th))
+        return G
+    if kind == "arclen_spheres":
+        k, r02 = float(mon["k"]), float(mon["r0"]) ** 2
+        for c in mon["bc"]:
+            D = X - np.asarray(c, dtype=np.float64)[:d]
+            g = 2.0 * k * _sech2(k * (np.sum(D * D, axis=-1) - r02))
+            G = G + g[..., None] * D
+        return G
+    raise ValueError(f"no solution u for monitor kind {kind!r}")
 
 
 # ----------------------------------------------------------------------------------------
@@ -123,6 +174,14 @@ def _panels_for(mon: dict, lo, hi) -> int:
         scale = min(mon["bw"])
     elif kind == "separable_sech2":
         scale = math.pi / (2.0 * max(mon["k_axes"]))
+    elif kind == "arclen_front":
+        scale = math.pi * mon["eps"]
+    elif kind == "arclen_spiral":
+        # the ridges of u narrow to ~ 1 / (sqrt(k) 2 w r^2) away from the centre
+        rmax = max(math.hypot(x - mon["c"][0], y - mon["c"][1]) for x in (lo[0], hi[0]) for y in (lo[1], hi[1]))
+        scale = 1.0 / (math.sqrt(mon["k"]) * 2.0 * mon["twist"] * rmax * rmax)
+    elif kind == "arclen_spheres":
+        scale = math.pi / (4.0 * mon["k"] * max(mon["r0"], 0.05))
     else:
         scale = L
     return int(min(4096, max(8, math.ceil(2.0 * L / scale))))
@@ -183,11 +242,59 @@ def theta_closed_form(mon: dict, lo, hi) -> float | None:
     return None
 
 
+def theta_reduced(mon: dict, lo, hi) -> float | None:
+    """int_box rho reduced to one dimension where the monitor allows it (adaptive quadrature):
+      * arclen_front depends on s = x_0 + x_1 only: int rho = int rho(s) m(s) ds, m(s) the
+        length of the segment {x_0 + x_1 = s} inside the box (the trapezoid density of the sum);
+      * arclen_spheres with one centre whose shell, out to where rho - 1 < 1e-30, lies inside the
+        box: vol + int_0^R (rho(r) - 1) |S^{d-1}| r^{d-1} dr.
+    None where neither applies."""
+    import scipy.integrate
+    d = len(lo)
+    vol = float(np.prod([b - a for a, b in zip(lo, hi)]))
+    kind = mon["kind"]
+    if kind == "arclen_front" and d == 2:
+        s0 = float(mon.get("offset", 1.0))
+
+        def m(s):
+            return max(0.0, min(hi[0], s - lo[1]) - max(lo[0], s - hi[1]))
+
+        def f(s):
+            X = np.array([[s - 0.5 * s0, 0.5 * s0]])  # any point with x_0 + x_1 = s
+            return float(rho(mon, X)[0]) * m(s)
+
+        a, b = lo[0] + lo[1], hi[0] + hi[1]
+        pts = sorted({a, b, lo[0] + hi[1], hi[0] + lo[1], min(max(s0, a), b)})
+        tot = 0.0
+        for u, v in zip(pts[:-1], pts[1:]):
+            if v > u:
+                tot += scipy.integrate.quad(f, u, v, epsabs=1e-14, epsrel=1e-13, limit=400,
+                                            points=[s0] if u < s0 < v else None)[0]
+        return tot
+    if kind == "arclen_spheres" and len(mon["bc"]) == 1:
+        k, r0 = float(mon["k"]), float(mon["r0"])
+        c = np.asarray(mon["bc"][0], dtype=np.float64)[:d]
+        R = math.sqrt(r0 * r0 + 40.0 / k)   # k (R^2 - r0^2) = 40: sech^2 < 1e-34 beyond R
+        if not all(lo[q] <= c[q] - R and c[q] + R <= hi[q] for q in range(d)):
+            return None
+        area = 2.0 * math.pi if d == 2 else 4.0 * math.pi
+
+        def g(r):
+            X = np.zeros((1, d))
+            X[0, 0] = r
+            return (float(rho(dict(mon, bc=[[0.0] * d]), X)[0]) - 1.0) * area * r ** (d - 1)
+
+        return vol + scipy.integrate.quad(g, 0.0, R, epsabs=1e-14, epsrel=1e-13, limit=400, points=[r0])[0]
+    return None
+
+
 def theta(mon: dict, lo, hi) -> float:
     """The normalisation constant used by the oracle's solves."""
     if "theta" in mon and mon["theta"]:
         return float(mon["theta"])
     cf = theta_closed_form(mon, lo, hi)
+    if cf is None:
+        cf = theta_reduced(mon, lo, hi)
     return cf if cf is not None else theta_quadrature(mon, lo, hi)
 
 

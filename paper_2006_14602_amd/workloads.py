@@ -13,6 +13,9 @@ Workloads follow the paper's experiments in kind (analytic monitors on box domai
               rho = 1 + 15 sech^2(30(|x - c|^2 - 0.09)), c = (1/2,1/2,1/2), 200 steps
   bumps_batch 256 single-domain 2D instances, sides U{33..257}, 1..4 Gaussian bumps
   stream      Poisson request stream, 70% 2D (65..1025 per side), 30% 3D (33..193 per side)
+The paper's own examples use the arc-length monitor rho = sqrt(1 + |grad u|^2) of given
+functions u (Sec. 4): burgers_front (Sec. 4.1, 65^2, 4 slabs / 2 x 2 blocks, overlap 3 points),
+spiral (Sec. 4.1), sphere_3d and spheres9_3d (Sec. 4.2, eight blocks).
 
 Subdomain runs use gamma = 4 h^2 and dt = gamma / 5 (the largest h over axes); single-domain runs
 use gamma = 1 and dt = 1e-3.
@@ -57,6 +60,73 @@ def const_monitor(amp=1.0):
 
 def separable_monitor(amps, ks, cs):
     return {"kind": "separable_sech2", "amp_axes": list(amps), "k_axes": list(ks), "c": list(cs)}
+
+
+def front_monitor(eps=0.01, offset=1.0):
+    """Arc-length monitor of the 2D Burgers front u = 1 / (1 + exp((x + y - offset) / (2 eps)))
+    (Sec. 4.1, first example)."""
+    return {"kind": "arclen_front", "eps": eps, "offset": offset}
+
+
+def spiral_monitor(amp=9.0, k=100.0, twist=20.0, c=(0.7, 0.5)):
+    """Arc-length monitor of u = 1 + amp / (1 + k r^2 cos^2(theta - twist r^2)), polar
+    coordinates about c (Sec. 4.1, second example)."""
+    return {"kind": "arclen_spiral", "amp": amp, "k": k, "twist": twist, "c": list(c)}
+
+
+def spheres_monitor(k, r0, centres):
+    """Arc-length monitor of u = sum_b tanh(k (|x - c_b|^2 - r0^2)) (Sec. 4.2)."""
+    return {"kind": "arclen_spheres", "k": k, "r0": r0, "bc": [list(map(float, c)) for c in centres]}
+
+
+# Sec. 4.2, second example: nine spheres of radius^2 0.1875
+NINE_CENTRES = [(0.0, 0.0, 0.0), (0.5, 0.5, 0.5), (0.5, -0.5, 0.5), (-0.5, 0.5, 0.5), (-0.5, -0.5, 0.5),
+                (0.5, 0.5, -0.5), (0.5, -0.5, -0.5), (-0.5, 0.5, -0.5), (-0.5, -0.5, -0.5)]
+
+
+def _arclen_time(g: dict, dd, dt_frac: float, steps: int) -> dict:
+    if dd:
+        t = dd_defaults(g)
+        t["dt"] = dt_frac * t["gamma"]
+    else:
+        t = {"dt": 1e-3, "gamma": 1.0}
+    t["steps"] = steps
+    return t
+
+
+def burgers_front(n=65, parts=(4, 1), overlap=2, mode="alternating", steps=300):
+    """Sec. 4.1, first example: 65^2 on the unit square, 4 slabs or 2 x 2 blocks overlapping by
+    three grid points (2 cells), alternating sweeps."""
+    g = grid([n, n])
+    dd = {"parts": list(parts), "overlap": [overlap] * 2, "mode": mode} if parts and max(parts) > 1 else None
+    return {"name": f"burgers_front_{n}", "grid": g, "dd": dd, "monitor": front_monitor(),
+            "time": _arclen_time(g, dd, 0.2, steps)}
+
+
+def spiral(n=257, parts=(4, 4), overlap=4, mode="parallel", steps=300):
+    """Sec. 4.1, second example.  Its ridges need dt = gamma / 50 on decomposed runs."""
+    g = grid([n, n])
+    dd = {"parts": list(parts), "overlap": [overlap] * 2, "mode": mode} if parts and max(parts) > 1 else None
+    return {"name": f"spiral_{n}", "grid": g, "dd": dd, "monitor": spiral_monitor(),
+            "time": _arclen_time(g, dd, 0.02, steps)}
+
+
+def sphere_3d(n=81, parts=(2, 2, 2), overlap=2, mode="alternating", steps=150):
+    """Sec. 4.2, first example: u = tanh(100(|x|^2 - 0.125)) on (-1,1)^3, eight blocks."""
+    g = grid([n] * 3, [-1.0] * 3, [1.0] * 3)
+    dd = {"parts": list(parts), "overlap": [overlap] * 3, "mode": mode} if parts and max(parts) > 1 else None
+    return {"name": f"sphere_{n}", "grid": g, "dd": dd,
+            "monitor": spheres_monitor(100.0, math.sqrt(0.125), [(0.0, 0.0, 0.0)]),
+            "time": _arclen_time(g, dd, 0.02, steps)}
+
+
+def spheres9_3d(n=81, parts=(2, 2, 2), overlap=2, mode="alternating", steps=150):
+    """Sec. 4.2, second example: nine tanh spheres on (-2,2)^3, eight blocks."""
+    g = grid([n] * 3, [-2.0] * 3, [2.0] * 3)
+    dd = {"parts": list(parts), "overlap": [overlap] * 3, "mode": mode} if parts and max(parts) > 1 else None
+    return {"name": f"spheres9_{n}", "grid": g, "dd": dd,
+            "monitor": spheres_monitor(50.0, math.sqrt(0.1875), NINE_CENTRES),
+            "time": _arclen_time(g, dd, 0.02, steps)}
 
 
 def ring(steps=200):

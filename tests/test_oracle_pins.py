@@ -482,3 +482,112 @@ def test_alternating_1d_matches_bruteforce(parts, mode):
     order = O.sweep_order(O.Decomposition(g1, (parts,), (ov,)), mode)
     want = _alternating_1d_bruteforce(n, parts, ov, A, K, C, dt, gamma, steps, order)
     assert np.max(np.abs(r.psi - want)) < 1e-13
+
+
+# --- Arc-length monitors of the paper's test functions (Sec. 4, eq. monitfn) -----------------
+
+def _u_front(X, eps, s0):
+    return 1.0 / (1.0 + np.exp((X[..., 0] + X[..., 1] - s0) / (2.0 * eps)))
+
+
+def _u_spiral(X, A, k, w, c):
+    dx, dy = X[..., 0] - c[0], X[..., 1] - c[1]
+    r2 = dx * dx + dy * dy
+    return 1.0 + A / (1.0 + k * r2 * np.cos(np.arctan2(dy, dx) - w * r2) ** 2)
+
+
+def _u_spheres(X, k, r0, centres):
+    out = np.zeros(X.shape[:-1])
+    for c in centres:
+        out = out + np.tanh(k * (np.sum((X - np.asarray(c)) ** 2, axis=-1) - r0 * r0))
+    return out
+
+
+def _fd_gradient(u, X, h):
+    """Fourth-order central differences of u at the points X[..., d]."""
+    G = np.zeros(X.shape)
+    for q in range(X.shape[-1]):
+        e = np.zeros(X.shape[-1])
+        e[q] = h
+        G[..., q] = (-u(X + 2 * e) + 8 * u(X + e) - 8 * u(X - e) + u(X - 2 * e)) / (12 * h)
+    return G
+
+
+@pytest.mark.parametrize("case", ["front", "spiral", "sphere", "spheres9"])
+def test_arclen_gradient_matches_finite_differences(case):
+    # the monitor's grad u is derived by hand; u itself is the paper's formula
+    rng = np.random.default_rng(7)
+    if case == "front":
+        mon = W.front_monitor(eps=0.05)
+        X = rng.uniform(0.0, 1.0, (400, 2))
+        u = lambda Y: _u_front(Y, 0.05, 1.0)
+    elif case == "spiral":
+        mon = W.spiral_monitor()
+        X = rng.uniform(0.0, 1.0, (400, 2))
+        u = lambda Y: _u_spiral(Y, 9.0, 100.0, 20.0, (0.7, 0.5))
+    elif case == "sphere":
+        mon = W.spheres_monitor(100.0, math.sqrt(0.125), [(0.0, 0.0, 0.0)])
+        X = rng.uniform(-0.6, 0.6, (400, 3))
+        u = lambda Y: _u_spheres(Y, 100.0, math.sqrt(0.125), [(0.0, 0.0, 0.0)])
+    else:
+        mon = W.spheres_monitor(50.0, math.sqrt(0.1875), W.NINE_CENTRES)
+        X = rng.uniform(-1.2, 1.2, (400, 3))
+        u = lambda Y: _u_spheres(Y, 50.0, math.sqrt(0.1875), W.NINE_CENTRES)
+    G = O.grad_u(mon, X)
+    F = _fd_gradient(u, X, 3e-5)
+    scale = np.max(np.abs(F), axis=-1, keepdims=True) + 1.0
+    assert np.max(np.abs(G - F) / scale) < 1e-6
+    np.testing.assert_allclose(O.rho(mon, X), np.sqrt(1.0 + np.sum(F * F, axis=-1)), rtol=1e-6)
+
+
+def test_arclen_front_theta_reduction_equals_tensor_quadrature():
+    mon = W.front_monitor(eps=0.01)
+    for lo, hi in (((0.0, 0.0), (1.0, 1.0)), ((-0.2, 0.1), (1.3, 0.9))):
+        red = O.theta_reduced(mon, lo, hi)
+        quad = O.theta_quadrature(mon, lo, hi)
+        assert abs(red - quad) < 1e-11 * quad, (red, quad)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_arclen_sphere_theta_radial_reduction_equals_tensor_quadrature(d):
+    # a broad shell so that the tensor rule converges quickly; the reduction needs the shell's
+    # tail inside the box
+    mon = W.spheres_monitor(10.0, 0.4, [(0.1, -0.2, 0.05)[:d]])
+    lo, hi = (-3.0,) * d, (3.2,) * d
+    red = O.theta_reduced(mon, lo, hi)
+    assert red is not None
+    quad = O.theta_quadrature(mon, lo, hi, panels=48 if d == 3 else 200)
+    assert abs(red - quad) < 1e-9 * quad, (red, quad)
+    assert O.theta_reduced(mon, (-1.0,) * d, (1.0,) * d) is None  # tail leaves the box
+
+
+def test_arclen_spiral_theta_converged():
+    # the ridges of the spiral reach rho ~ 1.7e3 over widths ~ 3e-3 near the far corner; the
+    # tensor rule settles to ~1e-7 relative (theta only adds a constant to F)
+    mon = W.spiral_monitor()
+    a = O.theta_quadrature(mon, (0.0, 0.0), (1.0, 1.0))
+    b = O.theta_quadrature(mon, (0.0, 0.0), (1.0, 1.0), panels=int(1.5 * O.pma_oracle._panels_for(mon, (0.0, 0.0), (1.0, 1.0))))
+    assert abs(a - b) < 3e-7 * a, (a, b)
+
+
+def test_arclen_front_mesh_symmetries():
+    # u depends on x + y and is odd about the line x + y = 1, so rho is invariant under the swap
+    # of axes and under (x, y) -> (1 - y, 1 - x): the mesh inherits both
+    g = grid2(33)
+    r = O.solve_single(g, W.front_monitor(eps=0.03), 1e-3, 1.0, 60)
+    x, y = r.mesh
+    assert np.max(np.abs(x - y.T)) < 1e-12
+    assert np.max(np.abs(x - (1.0 - y[::-1, ::-1].T))) < 1e-12
+    assert r.min_det > 0 and r.min_cell > 0
+
+
+def test_arclen_nine_spheres_mesh_cube_symmetry():
+    # the nine centres are invariant under every permutation and sign flip of the axes
+    g = O.GridSpec((13, 13, 13), (-2.0,) * 3, (2.0,) * 3)
+    mon = dict(W.spheres_monitor(5.0, math.sqrt(0.1875), W.NINE_CENTRES), theta=70.0)
+    r = O.solve_single(g, mon, 1e-3, 1.0, 20)
+    x = r.mesh
+    assert np.max(np.abs(x[0] - np.transpose(x[1], (1, 0, 2)))) < 1e-12
+    assert np.max(np.abs(x[0] - np.transpose(x[2], (2, 1, 0)))) < 1e-12
+    assert np.max(np.abs(x[0] + x[0][::-1, :, :])) < 1e-12
+    assert r.min_det > 0
