@@ -46,7 +46,8 @@ enum {
   PMA_E_INVAL = -1,     /* invalid argument or shape */
   PMA_E_NOMEM = -2,     /* device arena exhausted or allocation failed */
   PMA_E_HIP = -3,       /* a HIP runtime call failed */
-  PMA_E_TANGLED = -4,   /* det D^2_h Psi <= 0 reached (the mesh folded) */
+  PMA_E_TANGLED = -4,   /* the mesh folded: det D^2_h Psi <= 0 at a node during a step, or a
+                           cell of the final mesh with non-positive measure */
   PMA_E_NONFINITE = -5, /* a non-finite right-hand side or update */
   PMA_E_BUDGET = -6,    /* request larger than the whole HBM budget */
   PMA_E_NOTFOUND = -7,  /* unknown or retired ticket */
@@ -85,8 +86,18 @@ enum {
   PMA_MON_SECH2_RADIAL = 1,   /* rho = 1 + amp sech^2(k (|x - c|^2 - r0^2)) */
   PMA_MON_SECH2_SINE = 2,     /* rho = 1 + amp sech^2(k (x_1 - c[1] - r0 sin(2 pi x_0))) */
   PMA_MON_GAUSS_SUM = 3,      /* rho = 1 + sum_b bamp[b] exp(-|x - bc[b]|^2 / (2 bw[b]^2)) */
-  PMA_MON_SEPARABLE_SECH2 = 4 /* rho = prod_k (1 + amp_axes[k] sech^2(k_axes[k] (x_k - c[k]))) */
+  PMA_MON_SEPARABLE_SECH2 = 4, /* rho = prod_k (1 + amp_axes[k] sech^2(k_axes[k] (x_k - c[k]))) */
+  /* arc-length monitors rho = sqrt(1 + |grad u|^2) of given solutions u (Sec. 4, eq. monitfn):  */
+  PMA_MON_ARCLEN_FRONT = 5,   /* 2D: u = 1 / (1 + exp((x_0 + x_1 - r0) / (2 k)))  (eq. test_fn1;
+                                 the paper takes k = 0.01, r0 = 1) */
+  PMA_MON_ARCLEN_SPIRAL = 6,  /* 2D: u = 1 + amp / (1 + k r^2 cos^2(t - twist r^2)), r and t the
+                                 polar coordinates about c (eq. test_fn2: amp 9, k 100, twist 20,
+                                 c = (0.7, 0.5)) */
+  PMA_MON_ARCLEN_SPHERES = 7  /* u = sum_{b < nbumps} tanh(k (|x - bc[b]|^2 - r0^2))
+                                 (eqs. test_fn3d1, test_fn3d2); nbumps 1..9 */
 };
+
+#define PMA_MAX_BUMPS 9
 
 /* request states */
 enum { PMA_PENDING = 0, PMA_RUNNING = 1, PMA_DONE = 2, PMA_FAILED = 3 };
@@ -102,11 +113,12 @@ typedef struct {
 
 typedef struct {
   int kind;         /* PMA_MON_* */
-  int nbumps;       /* PMA_MON_GAUSS_SUM: 1..4 */
+  int nbumps;       /* PMA_MON_GAUSS_SUM: 1..4; PMA_MON_ARCLEN_SPHERES: 1..9 */
   double amp, k, r0;
   double c[3];
   double amp_axes[3], k_axes[3];
-  double bamp[4], bw[4], bc[4][3];
+  double bamp[PMA_MAX_BUMPS], bw[PMA_MAX_BUMPS], bc[PMA_MAX_BUMPS][3];
+  double twist;     /* PMA_MON_ARCLEN_SPIRAL */
   double theta;     /* int_Omega rho; 0 -> computed by the library (FP64 quadrature) */
 } pma_monitor;
 

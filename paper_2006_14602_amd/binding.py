@@ -22,7 +22,8 @@ PMA_OK, PMA_E_INVAL, PMA_E_NOMEM, PMA_E_HIP, PMA_E_TANGLED, PMA_E_NONFINITE, PMA
 PRECISION = {"fp64": 0, "fp32": 1, "split16": 2}
 EXEC = {"batched": 0, "plain": 1}
 PENDING, RUNNING, DONE, FAILED = 0, 1, 2, 3
-MON_KIND = {"const": 0, "sech2_radial": 1, "sech2_sine": 2, "gauss_sum": 3, "separable_sech2": 4}
+MON_KIND = {"const": 0, "sech2_radial": 1, "sech2_sine": 2, "gauss_sum": 3, "separable_sech2": 4,
+            "arclen_front": 5, "arclen_spiral": 6, "arclen_spheres": 7}
 
 
 class PmaError(RuntimeError):
@@ -38,7 +39,8 @@ class Grid(ctypes.Structure):
 class Monitor(ctypes.Structure):
     _fields_ = [("kind", c_int), ("nbumps", c_int), ("amp", c_double), ("k", c_double), ("r0", c_double),
                 ("c", c_double * 3), ("amp_axes", c_double * 3), ("k_axes", c_double * 3),
-                ("bamp", c_double * 4), ("bw", c_double * 4), ("bc", (c_double * 3) * 4), ("theta", c_double)]
+                ("bamp", c_double * 9), ("bw", c_double * 9), ("bc", (c_double * 3) * 9), ("twist", c_double),
+                ("theta", c_double)]
 
 
 class Time(ctypes.Structure):
@@ -138,9 +140,19 @@ def make_grid(g: dict) -> Grid:
 def make_monitor(m: dict, theta: float = 0.0) -> Monitor:
     M = Monitor()
     M.kind = MON_KIND[m["kind"]]
-    M.amp = float(m.get("amp", 1.0)) if m["kind"] in ("const", "sech2_radial", "sech2_sine") else 0.0
+    M.amp = float(m.get("amp", 1.0)) if m["kind"] in ("const", "sech2_radial", "sech2_sine", "arclen_spiral") else 0.0
     M.k = float(m.get("k", 0.0))
     M.r0 = float(m.get("r0", 0.0))
+    if m["kind"] == "arclen_front":
+        M.k = float(m["eps"])
+        M.r0 = float(m.get("offset", 1.0))
+    if m["kind"] == "arclen_spiral":
+        M.twist = float(m["twist"])
+    if m["kind"] == "arclen_spheres":
+        M.nbumps = len(m["bc"])
+        for b in range(M.nbumps):
+            for i, v in enumerate(m["bc"][b][:3]):
+                M.bc[b][i] = float(v)
     for i, v in enumerate(m.get("c", [])[:3]):
         M.c[i] = float(v)
     if m["kind"] == "separable_sech2":

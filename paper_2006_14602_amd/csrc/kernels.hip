@@ -176,6 +176,90 @@ template <typename T> struct MonReg<T, MON_SEPARABLE> {
   }
 };
 
+// Arc-length monitors rho = sqrt(1 + g2), g2 = |grad u|^2 (Sec. 4, eq. monitfn):
+// excess = rho - 1 = g2 / (1 + sqrt(1 + g2)), free of cancellation where g2 is small.
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double fsqrt(double x) { return sqrt(x); }
+template <typename T>
+__device__ inline T arclen_excess(T g2) { return g2 * frcp(T(1) + fsqrt(T(1) + g2)); }
+
+// sine and cosine of an angle given as a * r2: FP32 takes the hardware sine and cosine, whose
+// argument is in revolutions (a pre-divided by 2 pi); FP64 calls sincos on radians.
+template <typename T> struct Turn;
+template <> struct Turn<float> {
+  static constexpr float kScale = 0.159154943091895336f;  // 1 / (2 pi)
+  static __device__ inline void sc(float a, float& s, float& c) {
+    s = __builtin_amdgcn_sinf(a);
+    c = __builtin_amdgcn_cosf(a);
+  }
+};
+template <> struct Turn<double> {
+  static constexpr double kScale = 1.0;
+  static __device__ inline void sc(double a, double& s, double& c) { sincos(a, &s, &c); }
+};
+
+// u = 1 / (1 + exp((x_0 + x_1 - r0) / (2 eps))): grad u = -(1, 1) sech^2(a) / (8 eps),
+// a = (x_0 + x_1 - r0) / (4 eps), so g2 = 2 sech^4(a) / (8 eps)^2
+template <typename T> struct MonReg<T, MON_ARC_FRONT> {
+  T a4, nk, s0;
+  __device__ explicit MonReg(const MonP<T>& m)
+      : a4(T(4) * T(1.41421356237309505) / (T(8) * m.k)), nk(T(-0.5) / m.k * ExpK<T>::kLog2e), s0(m.r0) {}
+  template <int DIM> __device__ T excess(T x0, T x1, T) const {
+    const T g = sech2_of(a4, ExpK<T>::ex(nk * fabs(x0 + x1 - s0)));
+    return arclen_excess(g * g);
+  }
+};
+
+// u = 1 + amp / (1 + q), q = k r^2 cos^2(t - w r^2) about c.  With d = x - c,
+// P = d_0 cos(w r^2) + d_1 sin(w r^2) (= r cos(t - w r^2)) and Q = d_1 cos(w r^2) - d_0 sin(w r^2),
+// q = k P^2 and grad q = 2 k P ((cos, sin)(w r^2) + 2 w Q d): no angle and no division by r.
+template <typename T> struct MonReg<T, MON_ARC_SPIRAL> {
+  T amp, kq, w2, wt, c0, c1;
+  __device__ explicit MonReg(const MonP<T>& m)
+      : amp(m.amp), kq(m.k), w2(T(2) * m.tw), wt(m.tw * Turn<T>::kScale), c0(m.c[0]), c1(m.c[1]) {}
+  template <int DIM> __device__ T excess(T x0, T x1, T) const {
+    const T d0 = x0 - c0, d1 = x1 - c1;
+    const T r2 = d0 * d0 + d1 * d1;
+    T S, C;
+    Turn<T>::sc(wt * r2, S, C);
+    const T P = d0 * C + d1 * S, Q = d1 * C - d0 * S;
+    const T q1 = T(1) + kq * P * P;
+    const T f = T(2) * amp * kq * P * frcp(q1 * q1);
+    const T g0 = f * (C + w2 * Q * d0), g1 = f * (S + w2 * Q * d1);
+    return arclen_excess(g0 * g0 + g1 * g1);
+  }
+};
+
+// u = sum_b tanh(k (|x - c_b|^2 - r0^2)): grad u = sum_b 2 k sech^2(k (|x - c_b|^2 - r0^2)) (x - c_b)
+template <typename T> struct MonReg<T, MON_ARC_SPHERES> {
+  int nb;
+  T a4, nk, r02;
+  T c0[kMaxBumps], c1[kMaxBumps], c2[kMaxBumps];
+  __device__ explicit MonReg(const MonP<T>& m)
+      : nb(m.nb), a4(T(8) * m.k), nk(T(-2) * m.k * ExpK<T>::kLog2e), r02(m.r02) {
+#pragma unroll
+    for (int b = 0; b < kMaxBumps; ++b) {
+      c0[b] = m.bc[b][0];
+      c1[b] = m.bc[b][1];
+      c2[b] = m.bc[b][2];
+    }
+  }
+  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
+    T g0 = T(0), g1 = T(0), g2 = T(0);
+#pragma unroll
+    for (int b = 0; b < kMaxBumps; ++b)
+      if (b < nb) {
+        const T d0 = x0 - c0[b], d1 = x1 - c1[b], d2 = DIM == 3 ? x2 - c2[b] : T(0);
+        const T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const T s = sech2_of(a4, ExpK<T>::ex(nk * fabs(r2 - r02)));
+        g0 += s * d0;
+        g1 += s * d1;
+        g2 += s * d2;
+      }
+    return arclen_excess(g0 * g0 + g1 * g1 + g2 * g2);
+  }
+};
+
 // Status of the nodes of a block, folded into two registers per thread: the least 1 + e seen
 // (det(I + D^2 phi) <= 0 is a tangled mesh) and a sum of 0 * F (inf or NaN stays non-finite).
 template <typename T>
@@ -535,6 +619,9 @@ __global__ __launch_bounds__(256) void stencil2_kernel(const int4* __restrict__ 
     case MON_RADIAL: stencil_march2<T, MON_RADIAL>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
     case MON_SINE: stencil_march2<T, MON_SINE>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
     case MON_GAUSS: stencil_march2<T, MON_GAUSS>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+    case MON_ARC_FRONT: stencil_march2<T, MON_ARC_FRONT>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+    case MON_ARC_SPIRAL: stencil_march2<T, MON_ARC_SPIRAL>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
+    case MON_ARC_SPHERES: stencil_march2<T, MON_ARC_SPHERES>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
     default: stencil_march2<T, MON_SEPARABLE>(K, *mp, phi, F, sm, row0, nrows, col0, W, bad); break;
   }
   if (bad) atomicOr(&sa.status[K.inst], bad);
@@ -558,6 +645,9 @@ __global__ __launch_bounds__(256) void stencil3_kernel(const int4* __restrict__ 
     case MON_RADIAL: stencil_march3<T, MON_RADIAL>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
     case MON_SINE: stencil_march3<T, MON_SINE>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
     case MON_GAUSS: stencil_march3<T, MON_GAUSS>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+    case MON_ARC_FRONT: stencil_march3<T, MON_ARC_FRONT>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+    case MON_ARC_SPIRAL: stencil_march3<T, MON_ARC_SPIRAL>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
+    case MON_ARC_SPHERES: stencil_march3<T, MON_ARC_SPHERES>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
     default: stencil_march3<T, MON_SEPARABLE>(K, *mp, phi, F, sm, p0, np, row0, col0, W, bad); break;
   }
   if (bad) atomicOr(&sa.status[K.inst], bad);
@@ -1361,6 +1451,9 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
     case MON_RADIAL: fused_nodes2<KIND, MON_RADIAL>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
     case MON_SINE: fused_nodes2<KIND, MON_SINE>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
     case MON_GAUSS: fused_nodes2<KIND, MON_GAUSS>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
+    case MON_ARC_FRONT: fused_nodes2<KIND, MON_ARC_FRONT>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
+    case MON_ARC_SPIRAL: fused_nodes2<KIND, MON_ARC_SPIRAL>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
+    case MON_ARC_SPHERES: fused_nodes2<KIND, MON_ARC_SPHERES>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
     default: fused_nodes2<KIND, MON_SEPARABLE>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
   }
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;

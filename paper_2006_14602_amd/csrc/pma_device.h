@@ -14,7 +14,11 @@ namespace pma {
 
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_SPLIT16 = 2 };
 
-enum MonKind { MON_CONST = 0, MON_RADIAL = 1, MON_SINE = 2, MON_GAUSS = 3, MON_SEPARABLE = 4 };
+enum MonKind {
+  MON_CONST = 0, MON_RADIAL = 1, MON_SINE = 2, MON_GAUSS = 3, MON_SEPARABLE = 4,
+  MON_ARC_FRONT = 5, MON_ARC_SPIRAL = 6, MON_ARC_SPHERES = 7
+};
+constexpr int kMaxBumps = 9;
 
 // status bits raised by kernels (per instance)
 enum { ST_TANGLED = 1, ST_NONFINITE = 2 };
@@ -25,12 +29,16 @@ enum { ST_TANGLED = 1, ST_NONFINITE = 2 };
 //   rho = 1 + amp sech^2(k (x_1 - c_1 - r0 sin(2 pi x_0)))  (MON_SINE)
 //   rho = 1 + sum_b bamp_b exp(bnh_b |x - bc_b|^2)          (MON_GAUSS, bnh = -1 / (2 w^2))
 //   rho = prod_k (1 + aa_k sech^2(ka_k (x_k - c_k)))        (MON_SEPARABLE)
+// and the arc-length monitors rho = sqrt(1 + |grad u|^2) (Sec. 4, eq. monitfn) of
+//   u = 1 / (1 + exp((x_0 + x_1 - r0) / (2 k)))             (MON_ARC_FRONT, k = eps)
+//   u = 1 + amp / (1 + k r^2 cos^2(t - tw r^2)), polar about c  (MON_ARC_SPIRAL)
+//   u = sum_b tanh(k (|x - bc_b|^2 - r02))                  (MON_ARC_SPHERES)
 template <typename T>
 struct MonP {
   int kind, nb;
-  T amp, k, r0, r02;
+  T amp, k, r0, r02, tw;
   T c[3], aa[3], ka[3];
-  T bamp[4], bnh[4], bc[4][3];
+  T bamp[kMaxBumps], bnh[kMaxBumps], bc[kMaxBumps][3];
 };
 
 // DCT-I basis of one axis of a subdomain, in the precision of the solve.  Matrices have

@@ -212,6 +212,35 @@ static double sech2_h(double z) {
   return 4.0 * e / ((1.0 + e) * (1.0 + e));
 }
 
+// gradient of the solution u behind an arc-length monitor (Cartesian form: with
+// P = d_0 cos(w r^2) + d_1 sin(w r^2) = r cos(t - w r^2) and Q = d_1 cos(w r^2) - d_0 sin(w r^2),
+// the spiral's q = k P^2 has grad q = 2 k P ((cos, sin)(w r^2) + 2 w Q d))
+static void grad_u_host(const pma_monitor& m, int dim, const double* x, double* g) {
+  g[0] = g[1] = g[2] = 0.0;
+  if (m.kind == PMA_MON_ARCLEN_FRONT) {
+    // u(1 - u) = sech^2(s / 2) / 4, s = (x_0 + x_1 - r0) / (2 eps)
+    const double du = -0.25 * sech2_h((x[0] + x[1] - m.r0) / (4.0 * m.k)) / (2.0 * m.k);
+    g[0] = g[1] = du;
+  } else if (m.kind == PMA_MON_ARCLEN_SPIRAL) {
+    const double d0 = x[0] - m.c[0], d1 = x[1] - m.c[1], r2 = d0 * d0 + d1 * d1;
+    const double C = std::cos(m.twist * r2), S = std::sin(m.twist * r2);
+    const double P = d0 * C + d1 * S, Q = d1 * C - d0 * S, q = m.k * P * P;
+    const double f = -m.amp * 2.0 * m.k * P / ((1.0 + q) * (1.0 + q));
+    g[0] = f * (C + 2.0 * m.twist * Q * d0);
+    g[1] = f * (S + 2.0 * m.twist * Q * d1);
+  } else if (m.kind == PMA_MON_ARCLEN_SPHERES) {
+    for (int b = 0; b < m.nbumps; ++b) {
+      double d[3] = {0, 0, 0}, r2 = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        d[k] = x[k] - m.bc[b][k];
+        r2 += d[k] * d[k];
+      }
+      const double s = 2.0 * m.k * sech2_h(m.k * (r2 - m.r0 * m.r0));
+      for (int k = 0; k < dim; ++k) g[k] += s * d[k];
+    }
+  }
+}
+
 static double rho_host(const pma_monitor& m, int dim, const double* x) {
   switch (m.kind) {
     case PMA_MON_CONST:
@@ -237,6 +266,15 @@ static double rho_host(const pma_monitor& m, int dim, const double* x) {
       for (int k = 0; k < dim; ++k) p *= 1.0 + m.amp_axes[k] * sech2_h(m.k_axes[k] * (x[k] - m.c[k]));
       return p;
     }
+    case PMA_MON_ARCLEN_FRONT:
+    case PMA_MON_ARCLEN_SPIRAL:
+    case PMA_MON_ARCLEN_SPHERES: {
+      double g[3];
+      grad_u_host(m, dim, x, g);
+      double g2 = 0.0;
+      for (int k = 0; k < dim; ++k) g2 += g[k] * g[k];
+      return std::sqrt(1.0 + g2);
+    }
   }
   return NAN;
 }
@@ -258,6 +296,45 @@ static void gl8(double a, double b, int panels, std::vector<double>& x, std::vec
       w.push_back(half * wt[q]);
     }
   }
+}
+
+// int over [lo, hi] of rho - 1 by tensor Gauss-Legendre (`panels` panels of 8 nodes per axis),
+// the first axis split over host threads
+static double excess_integral(const pma_monitor& m, int d, const double* lo, const double* hi, int panels) {
+  std::vector<double> xs[3], ws[3];
+  for (int k = 0; k < d; ++k) gl8(lo[k], hi[k], panels, xs[k], ws[k]);
+  const size_t n0 = xs[0].size();
+  const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<double> part(nth, 0.0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t]() {
+      double acc = 0.0;
+      double x[3] = {0, 0, 0};
+      for (size_t i = t; i < n0; i += nth) {
+        x[0] = xs[0][i];
+        double a1 = 0.0;
+        for (size_t j = 0; j < xs[1].size(); ++j) {
+          x[1] = xs[1][j];
+          if (d == 2) {
+            a1 += ws[1][j] * (rho_host(m, 2, x) - 1.0);
+          } else {
+            double a2 = 0.0;
+            for (size_t k = 0; k < xs[2].size(); ++k) {
+              x[2] = xs[2][k];
+              a2 += ws[2][k] * (rho_host(m, 3, x) - 1.0);
+            }
+            a1 += ws[1][j] * a2;
+          }
+        }
+        acc += ws[0][i] * a1;
+      }
+      part[t] = acc;
+    });
+  for (auto& t : th) t.join();
+  double s = 0.0;
+  for (double p : part) s += p;
+  return s;
 }
 
 static double theta_host(const pma_grid& g, const pma_monitor& m) {
@@ -307,40 +384,78 @@ static double theta_host(const pma_grid& g, const pma_monitor& m) {
       double L = 0;
       for (int k = 0; k < d; ++k) L = std::max(L, g.hi[k] - g.lo[k]);
       const int panels = (int)std::ceil(3.0 * m.k * std::max(m.r0, 0.1) * L) + 8;
-      std::vector<double> xs[3], ws[3];
-      for (int k = 0; k < d; ++k) gl8(g.lo[k], g.hi[k], panels, xs[k], ws[k]);
-      const size_t n0 = xs[0].size();
-      const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
-      std::vector<double> part(nth, 0.0);
-      std::vector<std::thread> th;
-      for (int t = 0; t < nth; ++t)
-        th.emplace_back([&, t]() {
-          double acc = 0.0;
-          double x[3];
-          for (size_t i = t; i < n0; i += nth) {
-            x[0] = xs[0][i];
-            double a1 = 0.0;
-            for (size_t j = 0; j < xs[1].size(); ++j) {
-              x[1] = xs[1][j];
-              if (d == 2) {
-                a1 += ws[1][j] * (rho_host(m, 2, x) - 1.0);
-              } else {
-                double a2 = 0.0;
-                for (size_t k = 0; k < xs[2].size(); ++k) {
-                  x[2] = xs[2][k];
-                  a2 += ws[2][k] * (rho_host(m, 3, x) - 1.0);
-                }
-                a1 += ws[1][j] * a2;
-              }
+      return vol + excess_integral(m, d, g.lo, g.hi, panels);
+    }
+    case PMA_MON_ARCLEN_FRONT: {
+      // rho depends on s = x_0 + x_1 only: int rho = int rho(s) len(s) ds with len(s) the length
+      // of the segment x_0 + x_1 = s inside the box; Gauss-Legendre between the kinks of len(s)
+      double br[5] = {g.lo[0] + g.lo[1], g.lo[0] + g.hi[1], g.hi[0] + g.lo[1], g.hi[0] + g.hi[1],
+                      std::min(std::max(m.r0, g.lo[0] + g.lo[1]), g.hi[0] + g.hi[1])};
+      std::sort(br, br + 5);
+      double tot = 0.0;
+      std::vector<double> xs, ws;
+      for (int q = 0; q < 4; ++q) {
+        if (!(br[q + 1] > br[q])) continue;
+        const int panels = (int)std::ceil(2.0 * (br[q + 1] - br[q]) / (M_PI * m.k)) + 16;
+        gl8(br[q], br[q + 1], panels, xs, ws);
+        for (size_t i = 0; i < xs.size(); ++i) {
+          const double sv = xs[i];
+          const double len = std::max(0.0, std::min(g.hi[0], sv - g.lo[1]) - std::max(g.lo[0], sv - g.hi[1]));
+          const double x[3] = {sv - 0.5 * m.r0, 0.5 * m.r0, 0.0};
+          tot += ws[i] * rho_host(m, 2, x) * len;
+        }
+      }
+      return tot;
+    }
+    case PMA_MON_ARCLEN_SPIRAL: {
+      // ridges of u narrow to ~ 1 / (sqrt(k) 2 twist r^2) far from the centre
+      double rmax = 0.0;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          rmax = std::max(rmax, std::hypot((a ? g.hi[0] : g.lo[0]) - m.c[0], (b ? g.hi[1] : g.lo[1]) - m.c[1]));
+      const double scale = 1.0 / (std::sqrt(std::max(m.k, 1.0)) * 2.0 * std::max(m.twist, 1.0) * rmax * rmax);
+      const double L = std::max(g.hi[0] - g.lo[0], g.hi[1] - g.lo[1]);
+      const int panels = std::min(2048, (int)std::ceil(2.0 * L / scale) + 16);
+      return vol + excess_integral(m, d, g.lo, g.hi, panels);
+    }
+    case PMA_MON_ARCLEN_SPHERES: {
+      // rho - 1 < 1e-30 farther than R from every centre, R^2 = r0^2 + 40 / k
+      const double R = std::sqrt(m.r0 * m.r0 + 40.0 / std::max(m.k, 1e-300));
+      if (m.nbumps == 1) {
+        bool inside = true;
+        for (int k = 0; k < d; ++k) inside &= g.lo[k] <= m.bc[0][k] - R && m.bc[0][k] + R <= g.hi[k];
+        if (inside) {  // radial integral: vol + |S^{d-1}| int_0^R (rho(r) - 1) r^{d-1} dr
+          std::vector<double> xs, ws;
+          const int panels = (int)std::ceil(8.0 * m.k * std::max(m.r0, 0.05) * R) + 64;
+          double tot = 0.0;
+          const double br[3] = {0.0, std::min(m.r0, R), R};
+          for (int q = 0; q < 2; ++q) {
+            if (!(br[q + 1] > br[q])) continue;
+            gl8(br[q], br[q + 1], panels, xs, ws);
+            for (size_t i = 0; i < xs.size(); ++i) {
+              double x[3] = {m.bc[0][0] + xs[i], m.bc[0][1], m.bc[0][2]};
+              tot += ws[i] * (rho_host(m, d, x) - 1.0) * (d == 2 ? xs[i] : xs[i] * xs[i]);
             }
-            acc += ws[0][i] * a1;
           }
-          part[t] = acc;
-        });
-      for (auto& t : th) t.join();
-      double s = 0.0;
-      for (double p : part) s += p;
-      return vol + s;
+          return vol + (d == 2 ? 2.0 * M_PI : 4.0 * M_PI) * tot;
+        }
+      }
+      double lo[3], hi[3];
+      for (int k = 0; k < d; ++k) {
+        lo[k] = hi[k] = m.bc[0][k];
+        for (int b = 0; b < m.nbumps; ++b) {
+          lo[k] = std::min(lo[k], m.bc[b][k] - R);
+          hi[k] = std::max(hi[k], m.bc[b][k] + R);
+        }
+        lo[k] = std::max(lo[k], g.lo[k]);
+        hi[k] = std::min(hi[k], g.hi[k]);
+        if (!(hi[k] > lo[k])) return vol;
+      }
+      double L = 0;
+      for (int k = 0; k < d; ++k) L = std::max(L, hi[k] - lo[k]);
+      const double scale = M_PI / (4.0 * m.k * std::max(m.r0, 0.05));
+      const int panels = std::min(d == 2 ? 2048 : 72, (int)std::ceil(2.0 * L / scale) + 8);
+      return vol + excess_integral(m, d, lo, hi, panels);
     }
   }
   return NAN;
@@ -385,9 +500,16 @@ static void validate_grid(const pma_grid& g) {
 }
 
 static void validate_monitor(const pma_monitor& m, int dim) {
-  if (m.kind < PMA_MON_CONST || m.kind > PMA_MON_SEPARABLE_SECH2) thr(PMA_E_INVAL, "unknown monitor kind");
+  if (m.kind < PMA_MON_CONST || m.kind > PMA_MON_ARCLEN_SPHERES) thr(PMA_E_INVAL, "unknown monitor kind");
   if (m.kind == PMA_MON_GAUSS_SUM && (m.nbumps < 1 || m.nbumps > 4)) thr(PMA_E_INVAL, "nbumps must be 1..4");
+  if (m.kind == PMA_MON_ARCLEN_SPHERES && (m.nbumps < 1 || m.nbumps > PMA_MAX_BUMPS))
+    thr(PMA_E_INVAL, "nbumps must be 1..9");
   if (m.kind == PMA_MON_SECH2_SINE && dim < 2) thr(PMA_E_INVAL, "sine monitor needs dim >= 2");
+  if ((m.kind == PMA_MON_ARCLEN_FRONT || m.kind == PMA_MON_ARCLEN_SPIRAL) && dim != 2)
+    thr(PMA_E_INVAL, "the front and spiral monitors are two-dimensional");
+  if (m.kind == PMA_MON_ARCLEN_FRONT && !(m.k > 0)) thr(PMA_E_INVAL, "front monitor needs k = eps > 0");
+  if ((m.kind == PMA_MON_ARCLEN_SPIRAL || m.kind == PMA_MON_ARCLEN_SPHERES) && !(m.k >= 0))
+    thr(PMA_E_INVAL, "monitor needs k >= 0");
   if (m.kind == PMA_MON_CONST && !(m.amp > 0)) thr(PMA_E_INVAL, "constant monitor must be positive");
 }
 
@@ -926,9 +1048,10 @@ static void fill_monitor(const pma_monitor& m, MonP<T>& p) {
     p.aa[q] = (T)m.amp_axes[q];
     p.ka[q] = (T)m.k_axes[q];
   }
-  for (int b = 0; b < 4; ++b) {
+  p.tw = (T)m.twist;
+  for (int b = 0; b < kMaxBumps; ++b) {
     p.bamp[b] = (T)m.bamp[b];
-    p.bnh[b] = b < m.nbumps ? (T)(-1.0 / (2.0 * m.bw[b] * m.bw[b])) : (T)0;
+    p.bnh[b] = (m.kind == PMA_MON_GAUSS_SUM && b < m.nbumps) ? (T)(-1.0 / (2.0 * m.bw[b] * m.bw[b])) : (T)0;
     for (int q = 0; q < 3; ++q) p.bc[b][q] = (T)m.bc[b][q];
   }
 }
@@ -2028,7 +2151,8 @@ static void collect(pma_ctx* c, const std::vector<Instance*>& v, double* const* 
 }
 
 static int status_fail(int code) {
-  return fail(code, code == PMA_E_TANGLED ? "mesh folded (det <= 0)" : "non-finite update");
+  return fail(code, code == PMA_E_TANGLED ? "mesh folded (det D^2 Psi <= 0 during a step, or a final cell of "
+                                           "non-positive measure)" : "non-finite update");
 }
 
 int pma_dd_mesh(pma_ctx* c, const pma_grid* grid, const pma_dd* dd, const pma_monitor* mon, const pma_time* tm,

@@ -129,3 +129,23 @@ def test_sweep_level_counts(L):
     assert list(lv) == [0, 1, 0, 1]
     lv = B.sweep_levels(W.grid([49, 49, 49]), {"parts": [2, 2, 2], "overlap": [6, 6, 6], "mode": "alternating"})
     assert list(lv) == list(range(8))
+
+
+@pytest.mark.parametrize("case", ["front", "front_box", "spiral", "sphere2d", "sphere3d", "spheres9_small"])
+def test_arclen_theta_matches_oracle(L, case):
+    if case == "front":
+        g, mon, tol = W.grid([65, 65]), W.front_monitor(), 1e-12
+    elif case == "front_box":
+        g, mon, tol = W.grid([65, 49], [-0.2, 0.1], [1.3, 0.9]), W.front_monitor(eps=0.02, offset=0.8), 1e-12
+    elif case == "spiral":
+        g, mon, tol = W.grid([65, 65]), W.spiral_monitor(), 3e-7
+    elif case == "sphere2d":
+        g, mon, tol = W.grid([65, 65], [-1.0, -1.0], [1.0, 1.0]), W.spheres_monitor(100.0, 0.35, [(0.1, 0.0)]), 1e-11
+    elif case == "sphere3d":
+        g, mon, tol = W.sphere_3d(n=33)["grid"], W.sphere_3d()["monitor"], 1e-11
+    else:  # nine spheres with broad shells: the tensor rules of both sides converge
+        g = W.grid([17, 17, 17], [-2.0] * 3, [2.0] * 3)
+        mon, tol = W.spheres_monitor(5.0, math.sqrt(0.1875), W.NINE_CENTRES), 1e-7
+    got = B.theta(g, mon)
+    want = O.theta(mon, g["lo"], g["hi"])
+    assert abs(got - want) <= tol * want, (got, want)
