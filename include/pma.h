@@ -149,6 +149,11 @@ typedef struct {
   double theta;         /* normalisation used */
   double ms_total;      /* wall time of the solve; for served requests: submit -> done */
   double ms_queue;      /* served requests: submit -> admission */
+  double quality_e2;    /* mesh quality (Sec. 4.5): E = |Omega_c| (rho(x) / theta) J at every node,
+                           J = det(dx/dxi) by second-order differences of the glued mesh;
+                           E_2 = (int E^2 / |Omega_c|)^(1/2) by the trapezoid rule (1 on an
+                           equidistributing mesh); FP64 */
+  double quality_emax;  /* max over nodes of E */
 } pma_stats;
 
 typedef struct {

@@ -802,13 +802,17 @@ def rel_errors(ref: np.ndarray, approx: np.ndarray, h) -> dict:
 
 
 def quality(psi: np.ndarray, grid: GridSpec, mon: dict, theta_val=None) -> dict:
+    """Quality of the mesh x = grad_h Psi (see quality_of_mesh)."""
+    return quality_of_mesh(mesh_from_psi(psi, grid.whole_box()), grid, mon, theta_val)
+
+
+def quality_of_mesh(mesh: np.ndarray, grid: GridSpec, mon: dict, theta_val=None) -> dict:
     """E_adp = |Omega_c| (rho / theta) J at every node (eq. quality_measure with rho
-    normalised), J the Jacobian of the mesh x = grad_h Psi by second-order finite differences of
-    x (one-sided at the boundary).  Returns E_2 (trapezoid L2 over Omega_c / |Omega_c|) and
+    normalised), J the Jacobian of the mesh x[d, *n] by second-order finite differences of x
+    (one-sided at the boundary).  Returns E_2 (trapezoid L2 over Omega_c / |Omega_c|) and
     E_max."""
     box = grid.whole_box()
     th = theta(mon, grid.lo, grid.hi) if theta_val is None else theta_val
-    mesh = mesh_from_psi(psi, box)
     d = grid.d
     Jm = np.empty((d, d) + tuple(grid.n))
     for i in range(d):

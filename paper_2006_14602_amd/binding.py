@@ -54,7 +54,8 @@ class DD(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("steps_done", c_int), ("status", c_int), ("final_resid", c_double), ("min_det", c_double),
-                ("min_cell", c_double), ("theta", c_double), ("ms_total", c_double), ("ms_queue", c_double)]
+                ("min_cell", c_double), ("theta", c_double), ("ms_total", c_double), ("ms_queue", c_double),
+                ("quality_e2", c_double), ("quality_emax", c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

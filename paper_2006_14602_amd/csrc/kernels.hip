@@ -1951,6 +1951,97 @@ hipError_t launch_cells(const double* mesh, int dim, const int* n, double* minpa
   return hipGetLastError();
 }
 
+// Mesh quality (Sec. 4.5): E = |Omega_c| (rho(x) / theta) J at every node of the glued mesh, J the
+// Jacobian det(dx / dxi) from second-order differences of the mesh (one-sided three-point at the
+// box faces).  Each block leaves sum w E^2 (w: trapezoid weight times prod h) and max E.
+template <int MK>
+__global__ __launch_bounds__(256) void quality_kernel(const double* __restrict__ mesh, int dim, int n0, int n1,
+                                                      int n2, double h0, double h1, double h2, MonP<double> mp,
+                                                      double vol_theta, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int n[3] = {n0, n1, dim == 3 ? n2 : 1};
+  const double h[3] = {h0, h1, h2};
+  const long tot = (long)n[0] * n[1] * n[2];
+  const long v = blockIdx.x * 256L + threadIdx.x;
+  double sum = 0.0, mx = -1e300;
+  if (v < tot) {
+    const int i[3] = {(int)(v / ((long)n[1] * n[2])), (int)((v / n[2]) % n[1]), (int)(v % n[2])};
+    const long st[3] = {(long)n[1] * n[2], n[2], 1};
+    double Jm[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, x[3] = {0, 0, 0};
+    double w = 1.0;
+    for (int c = 0; c < dim; ++c) x[c] = mesh[c * tot + v];
+    for (int k = 0; k < dim; ++k) {
+      const int a = i[k], nk = n[k];
+      w *= (a == 0 || a == nk - 1 ? 0.5 : 1.0) * h[k];
+      for (int c = 0; c < dim; ++c) {
+        const double* X = mesh + c * tot + v;
+        double d;
+        if (a == 0) d = (-3.0 * X[0] + 4.0 * X[st[k]] - X[2 * st[k]]) / (2.0 * h[k]);
+        else if (a == nk - 1) d = (3.0 * X[0] - 4.0 * X[-st[k]] + X[-2 * st[k]]) / (2.0 * h[k]);
+        else d = (X[st[k]] - X[-st[k]]) / (2.0 * h[k]);
+        Jm[c][k] = d;
+      }
+    }
+    const double J = Jm[0][0] * (Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1]) -
+                     Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0]) +
+                     Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
+    const MonReg<double, MK> M(mp);
+    const double rho = 1.0 + (dim == 3 ? M.template excess<3>(x[0], x[1], x[2]) : M.template excess<2>(x[0], x[1], 0.0));
+    const double E = vol_theta * rho * J;
+    sum = w * E * E;
+    mx = E;
+  }
+  const double s = block_sum256(sum, red);
+  __syncthreads();
+  const double m = -block_min256(-mx, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s;
+    part[2 * blockIdx.x + 1] = m;
+  }
+}
+
+// E_2 = sqrt(sum w E^2 / |Omega_c|) and E_max from the per-block pairs
+__global__ __launch_bounds__(256) void quality_reduce_kernel(const double* __restrict__ part, long nb, double vol,
+                                                             double* out) {
+  __shared__ double red[4];
+  double s = 0.0, m = -1e300;
+  for (long b = threadIdx.x; b < nb; b += 256) {
+    s += part[2 * b];
+    m = fmax(m, part[2 * b + 1]);
+  }
+  const double ts = block_sum256(s, red);
+  __syncthreads();
+  const double tm = -block_min256(-m, red);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(ts / vol);
+    out[1] = tm;
+  }
+}
+
+hipError_t launch_quality(const double* mesh, int dim, const int* n, const double* h, const MonP<double>& mp,
+                          double vol, double theta, double* part, double* out, hipStream_t s) {
+  const long tot = (long)n[0] * n[1] * (dim == 3 ? n[2] : 1);
+  const long nb = nblk(tot, 256);
+  const double vt = vol / theta;
+  const double h2 = dim == 3 ? h[2] : 1.0;
+#define PMA_QUALITY(MK)                                                                                          \
+  hipLaunchKernelGGL(quality_kernel<MK>, dim3(nb), dim3(256), 0, s, mesh, dim, n[0], n[1], n[2], h[0], h[1], h2, \
+                     mp, vt, part)
+  switch (mp.kind) {
+    case MON_CONST: PMA_QUALITY(MON_CONST); break;
+    case MON_RADIAL: PMA_QUALITY(MON_RADIAL); break;
+    case MON_SINE: PMA_QUALITY(MON_SINE); break;
+    case MON_GAUSS: PMA_QUALITY(MON_GAUSS); break;
+    case MON_SEPARABLE: PMA_QUALITY(MON_SEPARABLE); break;
+    case MON_ARC_FRONT: PMA_QUALITY(MON_ARC_FRONT); break;
+    case MON_ARC_SPIRAL: PMA_QUALITY(MON_ARC_SPIRAL); break;
+    default: PMA_QUALITY(MON_ARC_SPHERES); break;
+  }
+#undef PMA_QUALITY
+  hipLaunchKernelGGL(quality_reduce_kernel, dim3(1), dim3(256), 0, s, part, nb, vol, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_min_reduce(const double* x, long n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(min_reduce_kernel, dim3(1), dim3(256), 0, s, x, n, out);
   return hipGetLastError();

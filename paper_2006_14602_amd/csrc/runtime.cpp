@@ -63,6 +63,8 @@ hipError_t launch_glue(int prec, const GlueArgs& g, hipStream_t s);
 long cell_blocks(int dim, const int* n);
 hipError_t launch_cells(const double* mesh, int dim, const int* n, double* minpart, hipStream_t s);
 hipError_t launch_min_reduce(const double* x, long n, double* out, hipStream_t s);
+hipError_t launch_quality(const double* mesh, int dim, const int* n, const double* h, const MonP<double>& mp,
+                          double vol, double theta, double* part, double* out, hipStream_t s);
 
 // ------------------------------------------------------------------------------------------
 // errors
@@ -618,7 +620,7 @@ struct Instance {
   double* psi_dev = nullptr;
   double* minpart = nullptr;
   long minpart_n = 0;
-  double* stats_dev = nullptr;  // [min det, min cell]
+  double* stats_dev = nullptr;  // [min det, min cell, quality E_2, quality E_max]
   // progress
   int steps_done = 0;
   int status = PMA_OK;
@@ -634,7 +636,7 @@ struct Instance {
   bool initialized = false;
   double shift_acc = 0;          // constant removed from phi so far (FP64)
   double min_det = 0, min_cell = 0;
-  double stats_host[2] = {0, 0};
+  double stats_host[4] = {0, 0, 0, 0};
   const double* psi0_dev = nullptr;  // warm start (global layout, device)
   double* user_psi = nullptr;        // single-subdomain mode: caller's device buffer
   size_t elem() const { return prec == PMA_FP64 ? 8 : 4; }
@@ -744,6 +746,12 @@ static void build_coupling(Instance& I) {
   }
 }
 
+// per-block partial results of the final checks, one buffer reused in turn: the glue's minima
+// (one per block), the cell minima (one per block), the quality sums and maxima (two per block)
+static long partials_count(const Instance& I) {
+  return std::max(2 * glue_blocks(I.gnodes()), cell_blocks(I.dim, I.grid.n));
+}
+
 // bytes of the instance block (state arrays + glue buffers)
 static size_t instance_bytes(const Instance& I) {
   size_t b = 0;
@@ -752,10 +760,9 @@ static size_t instance_bytes(const Instance& I) {
     for (int k = 0; k < I.dim; ++k) b += Arena::round(I.grid.n[k] * sizeof(int));
     b += Arena::round(I.dim * I.gnodes() * sizeof(double));   // mesh
     b += Arena::round(I.gnodes() * sizeof(double));           // psi (in/out)
-    const long mp = std::max(glue_blocks(I.gnodes()), cell_blocks(I.dim, I.grid.n));
-    b += Arena::round(mp * sizeof(double));
+    b += Arena::round(partials_count(I) * sizeof(double));
   }
-  b += Arena::round(2 * sizeof(double));
+  b += Arena::round(4 * sizeof(double));
   return b;
 }
 
@@ -971,13 +978,13 @@ static void alloc_instance(pma_ctx* c, Instance& I) {
     for (int k = 0; k < I.dim; ++k) I.own_dev[k] = (int*)take(I.grid.n[k] * sizeof(int));
     I.mesh_dev = (double*)take(I.dim * I.gnodes() * sizeof(double));
     I.psi_dev = (double*)take(I.gnodes() * sizeof(double));
-    I.minpart_n = std::max(glue_blocks(I.gnodes()), cell_blocks(I.dim, I.grid.n));
+    I.minpart_n = partials_count(I);
     I.minpart = (double*)take(I.minpart_n * sizeof(double));
     for (int k = 0; k < I.dim; ++k)
       HIPCHK(hipMemcpyAsync(I.own_dev[k], I.own[k].data(), I.grid.n[k] * sizeof(int),
                             hipMemcpyHostToDevice, c->stream));
   }
-  I.stats_dev = (double*)take(2 * sizeof(double));
+  I.stats_dev = (double*)take(4 * sizeof(double));
   I.bases_used.clear();
   if (I.tm.gamma > 0) {
     try {
@@ -1708,6 +1715,16 @@ static void finalize_instance(pma_ctx* c, Instance& I, Batch& B, int q, bool wan
   HIPCHK(launch_min_reduce(I.minpart, glue_blocks(I.gnodes()), I.stats_dev, st));
   HIPCHK(launch_cells(I.mesh_dev, I.dim, I.grid.n, I.minpart, st));
   HIPCHK(launch_min_reduce(I.minpart, cell_blocks(I.dim, I.grid.n), I.stats_dev + 1, st));
+  MonP<double> mp;
+  fill_monitor(I.mon, mp);
+  double vol = 1.0, h[3] = {1, 1, 1};
+  for (int k = 0; k < I.dim; ++k) {
+    vol *= I.grid.hi[k] - I.grid.lo[k];
+    h[k] = (I.grid.hi[k] - I.grid.lo[k]) / (I.grid.n[k] - 1);
+  }
+  if (2 * glue_blocks(I.gnodes()) > I.minpart_n || cell_blocks(I.dim, I.grid.n) > I.minpart_n)
+    thr(PMA_E_HIP, "internal: partial-result buffer too small");
+  HIPCHK(launch_quality(I.mesh_dev, I.dim, I.grid.n, h, mp, vol, I.theta, I.minpart, I.stats_dev + 2, st));
 }
 
 static double now_s() {
@@ -1941,7 +1958,7 @@ struct Server {
         finalize_instance(ctx, *I, B, q, false);
         I->mesh_host.resize((size_t)I->dim * I->gnodes());
         HIPCHK(hipMemcpyAsync(I->mesh_host.data(), I->mesh_dev, I->mesh_host.size() * 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(I->stats_host, I->stats_dev, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(I->stats_host, I->stats_dev, 32, hipMemcpyDeviceToHost, st));
       }
       HIPCHK(hipStreamSynchronize(st));
       for (auto* I : done) {
@@ -2112,6 +2129,8 @@ static void fill_stats(pma_stats* st, const Instance& I, double ms) {
   st->final_resid = I.resid;
   st->min_det = I.min_det;
   st->min_cell = I.min_cell;
+  st->quality_e2 = I.stats_host[2];
+  st->quality_emax = I.stats_host[3];
   st->theta = I.theta;
   st->ms_total = ms;
   st->ms_queue = 0;
@@ -2139,7 +2158,7 @@ static void collect(pma_ctx* c, const std::vector<Instance*>& v, double* const* 
       HIPCHK(hipMemcpyAsync(mesh_outs[q], I.mesh_dev, (size_t)I.dim * I.gnodes() * 8, hipMemcpyDeviceToHost, c->stream));
     if (psi_outs && psi_outs[q])
       HIPCHK(hipMemcpyAsync(psi_outs[q], I.psi_dev, I.gnodes() * 8, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(I.stats_host, I.stats_dev, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(I.stats_host, I.stats_dev, 32, hipMemcpyDeviceToHost, c->stream));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   for (auto* I : v) {
