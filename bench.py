@@ -30,10 +30,9 @@ MFMA_PEAK = {"split16": PEAK["fp16_TF"], "fp32": PEAK["fp32_TF"], "fp64": PEAK["
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
-def traffic_of(workload, phase):
-    """HBM bytes per launch of a step phase's kernel on `workload` from the committed rocprofv3 counters
-    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
-    calibration), or None when the kernel source has changed since they were taken."""
+def profile_entry(workload, key):
+    """An entry of the committed rocprofv3 summary (profiles/traffic.json), or None when the
+    kernel source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -41,8 +40,19 @@ def traffic_of(workload, phase):
     with open(os.path.join(ROOT, "paper_2006_14602_amd", "csrc", "kernels.hip"), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec.get("kernels_hip_sha256"):
             return None
-    e = rec.get("entries", {}).get(workload, {}).get(phase)
+    return rec.get("entries", {}).get(workload, {}).get(key)
+
+
+def traffic_of(workload, phase):
+    """HBM bytes per launch of a step phase's kernel on `workload` from the committed rocprofv3 counters
+    (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy calibration), or None."""
+    e = profile_entry(workload, phase)
     return None if e is None else e["fetch_bytes"] + e["write_bytes"]
+
+
+# vector-ALU issue: a wave64 FP32 instruction holds a 16-lane SIMD for 4 cycles (transcendentals 16),
+# 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0   # full-rate wave instructions per second
 KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil_fwd2_kernel / stencil2_kernel / stencil3_kernel",
           "euler": "euler_kernel",
           "fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel<single>", "pair0": "strip_kernel<pair>",
@@ -75,12 +85,54 @@ def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0, tune=
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         phases = plan.phase_times(phase_reps) if phase_reps > 0 else None
-        mesh, st = plan.mesh(0)
+        try:
+            mesh, st = plan.mesh(0)
+        except binding.PmaError as e:  # a folded mesh still has a measured step rate
+            st = {"min_det": float("nan"), "min_cell": float("nan"), "quality_e2": float("nan"),
+                  "quality_emax": float("nan"), "error": str(e)}
     finally:
         plan.close()
-    return {"updates_per_s": nodes_of(ws) * steps / dt, "ms_per_step": 1e3 * dt / steps, "seconds": dt,
-            "steps": steps, "min_det": st["min_det"], "min_cell": st["min_cell"], "stencil_march": march,
-            "phases": phases}
+    out = {"updates_per_s": nodes_of(ws) * steps / dt, "ms_per_step": 1e3 * dt / steps, "seconds": dt,
+           "steps": steps, "min_det": st["min_det"], "min_cell": st["min_cell"],
+           "quality_e2": st["quality_e2"], "quality_emax": st["quality_emax"], "stencil_march": march,
+           "phases": phases}
+    if "error" in st:
+        out["error"] = st["error"]
+    return out
+
+
+def paper_workloads(ctx, binding, workloads):
+    """The paper's own examples (Sec. 4): arc-length monitors of its test functions, alternating
+    sweeps (Algorithm 1) as the paper ran them, and the alternating form of the headline case.
+    Step rate from a resident plan; mesh statistics (min det, min cell, quality E_2 / E_max of the
+    glued mesh) after the timed steps."""
+    sd = workloads.sine_dd(steps=200)
+    sd["dd"]["mode"] = "alternating"
+    cases = [
+        ("burgers_front_65_slabs4_alternating", workloads.burgers_front(parts=(4, 1), steps=300), 300),
+        ("burgers_front_65_blocks2x2_alternating", workloads.burgers_front(parts=(2, 2), steps=300), 300),
+        ("spiral_257_4x4_parallel", workloads.spiral(steps=300), 300),
+        ("sphere_81_blocks8_alternating", workloads.sphere_3d(n=81, steps=150), 150),
+        ("spheres9_81_blocks8_alternating", workloads.spheres9_3d(n=81, steps=150), 150),
+        ("sine_dd_513_4x4_alternating", sd, 200),
+    ]
+    out = {}
+    for name, w, steps in cases:
+        r = timed_plan(ctx, binding, [w], "split16", "batched", steps, 5, tune=True)
+        e = {k: r[k] for k in ("updates_per_s", "ms_per_step", "steps", "min_det", "min_cell", "quality_e2",
+                               "quality_emax", "stencil_march")}
+        if "error" in r:
+            e["error"] = r["error"]
+        if name.startswith("burgers_front_65_slabs4"):
+            p = timed_plan(ctx, binding, [w], "fp64", "plain", 100, 2)
+            e["plain_fp64_updates_per_s"] = p["updates_per_s"]
+            e["speedup_over_plain_fp64"] = r["updates_per_s"] / p["updates_per_s"]
+        if w.get("dd") and w["dd"].get("mode", "parallel") != "parallel":
+            e["sweep_levels"] = int(max(binding.sweep_levels(w["grid"], w["dd"])) + 1)
+        out[name] = e
+        log(f"{name}: {r['updates_per_s']:.3e} updates/s, {r['ms_per_step']:.4f} ms/step, "
+            f"E2 {r['quality_e2']:.4f}")
+    return out
 
 
 def roofline_of(phases, prec, workload=None):
@@ -114,11 +166,23 @@ def stencil_roofline(ctx, binding, workloads):
         plan.close()
     st = ph["stencil"]
     gbs = st["bytes"] / (st["ms"] * 1e-3) / 1e9
-    return {"kernel": "stencil2_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-            "frac": gbs / PEAK["hbm_GBs"], "traffic": traffic_of("stencil_large", f"stencil@march={march}"),
-            "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
-            "stencil_march": march, "autotune_ms": [round(t, 4) for t in cand],
-            "workload": "2 x 8193^2 sine layer, 32x32 parts, FP32 (8 B per node)"}
+    out = {"kernel": "stencil2_kernel", "bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+           "frac": gbs / PEAK["hbm_GBs"], "traffic": traffic_of("stencil_large", f"stencil@march={march}"),
+           "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
+           "stencil_march": march, "autotune_ms": [round(t, 4) for t in cand],
+           "workload": "2 x 8193^2 sine layer, 32x32 parts, FP32 (8 B per node)"}
+    # the vector-ALU view of the same launch: issue cycles per node from the committed SQ counters
+    a = profile_entry("stencil_large_alu", f"stencil@march={march}")
+    if a is not None:
+        nodes_s = st["bytes"] / 8.0 / (st["ms"] * 1e-3)
+        issued = nodes_s * (a["valu_wave_insts_per_node"] + 3.0 * a["trans_wave_insts_per_node"])
+        out["alu"] = {"bound": "alu", "achieved": issued, "peak": VALU_ISSUE_PEAK,
+                      "unit": "full-rate wave instructions/s", "frac": issued / VALU_ISSUE_PEAK,
+                      "valu_wave_insts_per_node": a["valu_wave_insts_per_node"],
+                      "trans_wave_insts_per_node": a["trans_wave_insts_per_node"],
+                      "node_rate_ceiling_per_s": a["node_rate_ceiling"],
+                      "hbm_equivalent_of_ceiling_GBs": a["node_rate_ceiling"] * 8 / 1e9}
+    return out
 
 
 def serve_stream(binding, workloads, count, budget):
@@ -192,7 +256,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", type=int, default=600, help="requests in the serving stream (0: skip)")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["split16", "fp32", "fp64plain", "stencil_large"], default=None,
+    ap.add_argument("--only", choices=["split16", "fp32", "fp64plain", "stencil_large", "paper"], default=None,
                     help="time one form of the headline workload only (profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 10 times (calibrates HBM byte counters)")
@@ -213,6 +277,11 @@ def main():
     import torch
     from paper_2006_14602_amd import binding, workloads
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only == "paper":
+        ctx = binding.Context(0, budget_bytes=12 << 30)
+        print(json.dumps({"paper_workloads": paper_workloads(ctx, binding, workloads)}))
+        ctx.close()
+        return
     if args.only == "stencil_large":
         ctx = binding.Context(0, budget_bytes=12 << 30)
         print(json.dumps({"stencil_hbm_large": stencil_roofline(ctx, binding, workloads)}))
@@ -275,6 +344,7 @@ def main():
         extra["stencil_hbm_large"] = stencil_roofline(ctx, binding, workloads)
         log(f"stencil large: {extra['stencil_hbm_large']['achieved']:.0f} GB/s")
         out["other_workloads"] = extra
+        out["paper_workloads"] = paper_workloads(ctx, binding, workloads)
     ctx.close()
     if args.serve > 0 and not args.quick and not args.only:
         s8 = serve_stream(binding, workloads, args.serve, 8 << 30)
