@@ -2,8 +2,15 @@
 
 Calls only the FP64 oracle on the seeded workloads and stores, per workload, a strided
 subsample of the glued mesh plus a seeded random sample of nodes (numpy .npz, no pickles):
-  sine_dd_513.npz   513 x 513, 4 x 4 subdomains, overlap 8 cells, 500 steps
-  shell_dd_129.npz  129^3, 2 x 2 x 2 subdomains, overlap 6 cells, 200 steps
+  sine_dd_513.npz          513 x 513, 4 x 4 subdomains, overlap 8 cells, 500 steps
+  shell_dd_129.npz         129^3, 2 x 2 x 2 subdomains, overlap 6 cells, 200 steps
+  sine_dd_513_alt.npz      the same 513 x 513 split, alternating sweeps (Algorithm 1), 200 steps
+  burgers_front_65.npz     Burgers-front arc-length monitor, 4 slabs, alternating, 300 steps
+  spiral_257.npz           spiral arc-length monitor, 257 x 257, 4 x 4, 300 steps
+  sphere_81.npz            one-sphere arc-length monitor, 81^3 on (-1,1)^3, 8 blocks, alternating
+  spheres9_81.npz          nine-sphere arc-length monitor, 81^3 on (-2,2)^3, 8 blocks, alternating
+The arc-length workloads also store the theta the oracle used (tensor Gauss-Legendre where no
+reduction applies), which the tests hand to the library so both solve the same problem.
 Run from the repository root:  python tests/golden/make_golden.py [name ...]
 """
 import os
@@ -19,7 +26,20 @@ import oracle as O  # noqa: E402
 from paper_2006_14602_amd import workloads as W  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-CASES = {"sine_dd_513": (W.sine_dd, 8), "shell_dd_129": (W.shell_dd, 8)}
+def _sine_alt():
+    w = W.sine_dd(steps=200)
+    w["dd"]["mode"] = "alternating"
+    return w
+
+
+CASES = {"sine_dd_513": (W.sine_dd, 8), "shell_dd_129": (W.shell_dd, 8),
+         "sine_dd_513_alt": (_sine_alt, 8),
+         "burgers_front_65": (lambda: W.burgers_front(parts=(4, 1), steps=300), 2),
+         "spiral_257": (lambda: W.spiral(steps=300), 4),
+         "sphere_81": (lambda: W.sphere_3d(n=81, steps=150), 4),
+         "spheres9_81": (lambda: W.spheres9_3d(n=81, steps=150), 4)}
+# theta by a coarser tensor rule where the default one is too slow (the nine spheres)
+THETA_PANELS = {"spheres9_81": 40}
 
 
 def sample_index(n, stride, count, seed):
@@ -37,11 +57,16 @@ def make(name):
     gs = O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"]))
     t = w["time"]
     t0 = time.time()
-    r = O.solve_dd(gs, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], t["steps"])
+    if name in THETA_PANELS:
+        th = O.theta_quadrature(w["monitor"], g["lo"], g["hi"], panels=THETA_PANELS[name])
+    else:
+        th = O.theta(w["monitor"], g["lo"], g["hi"])
+    r = O.solve_dd(gs, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], t["steps"],
+                   mode=w["dd"].get("mode", "parallel"), theta_val=th)
     idx = sample_index(g["n"], stride, 4000, 20060146)
     vals = np.stack([r.mesh[k][tuple(idx.T)] for k in range(gs.d)], -1)
     np.savez_compressed(os.path.join(HERE, name + ".npz"), idx=idx.astype(np.int32), mesh=vals,
-                        min_det=np.float64(r.min_det), min_cell=np.float64(r.min_cell),
+                        min_det=np.float64(r.min_det), min_cell=np.float64(r.min_cell), theta=np.float64(th),
                         steps=np.int32(t["steps"]), seconds=np.float64(time.time() - t0))
     print(f"{name}: {time.time() - t0:.1f} s, min det {r.min_det:.6f}, {len(idx)} samples")
 

@@ -89,3 +89,35 @@ def test_bumps_batch_256_full(ctx):
         err = float(np.max(np.abs(outs[i] - ref.mesh)))
         print(f"bump {i} n={g['n'][0]}: err {err:.3e}")
         assert err <= TOL["split16"]
+
+
+PAPER = {
+    "sine_dd_513_alt": lambda: dict(W.sine_dd(steps=200), dd={"parts": [4, 4], "overlap": [8, 8],
+                                                               "mode": "alternating"}),
+    "burgers_front_65": lambda: W.burgers_front(parts=(4, 1), steps=300),
+    "spiral_257": lambda: W.spiral(steps=300),
+    "sphere_81": lambda: W.sphere_3d(n=81, steps=150),
+    "spheres9_81": lambda: W.spheres9_3d(n=81, steps=150),
+}
+
+
+@pytest.mark.parametrize("prec", ["split16", "fp64"])
+@pytest.mark.parametrize("name", list(PAPER))
+def test_paper_workload_full(ctx, name, prec):
+    # the paper's examples and the alternating headline split, at the benchmarked sizes and launch
+    # configuration, against oracle samples; the oracle's theta is handed to the library
+    w = PAPER[name]()
+    gd = golden(name)
+    w["monitor"] = dict(w["monitor"], theta=float(gd["theta"]))
+    print(f"case {name} {prec}", flush=True)
+    mesh, st = plan_mesh(ctx, w, prec)
+    d = w["grid"]["dim"]
+    idx = gd["idx"]
+    got = np.stack([mesh[k][tuple(idx.T)] for k in range(d)], -1)
+    ext = max(b - a for a, b in zip(w["grid"]["lo"], w["grid"]["hi"]))
+    err = float(np.max(np.abs(got - gd["mesh"]))) / ext
+    print(f"{name} {prec}: max err over {len(idx)} sampled nodes {err:.3e}, min det {st['min_det']:.6f} "
+          f"(oracle {float(gd['min_det']):.6f}), E2 {st['quality_e2']:.4f}")
+    assert err <= TOL[prec]
+    assert abs(st["min_det"] - float(gd["min_det"])) <= (1e-9 if prec == "fp64" else 2e-3)
+    assert st["min_cell"] > 0
