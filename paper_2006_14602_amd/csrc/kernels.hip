@@ -95,6 +95,16 @@ __device__ inline int mirror_clamp(int i, int n) {
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
 
+// Tile handled by this workgroup.  Workgroups are dispatched round-robin over the eight XCDs
+// (workgroup b runs on XCD b % 8), each XCD with its own L2.  The tiles are handed out so that
+// XCD x takes one contiguous run of the launch table: the tiles of one subdomain, which share
+// halo rows and DCT matrices, then meet in the same L2.  A bijection of [0, gridDim.x).
+__device__ inline int xcd_tile() {
+  const int b = blockIdx.x, n = gridDim.x;
+  const int q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
+}
+
 // mirror index for the Neumann ghost of phi: -1 -> 1, n -> n - 2
 __device__ inline int mlo(int i) { return i > 0 ? i - 1 : 1; }
 __device__ inline int mhi(int i, int n) { return i < n - 1 ? i + 1 : n - 2; }
@@ -606,8 +616,9 @@ __device__ inline const MonP<T>* load_ctx(const StepArgs& sa, int sub, StencilCt
 template <typename T>
 __global__ __launch_bounds__(256) void stencil2_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
   __shared__ T sm[kStHR * kStS];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
   StencilCtx<T> K;
   const T* phi;
   T* F;
@@ -632,8 +643,9 @@ __global__ __launch_bounds__(256) void stencil2_kernel(const int4* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(256) void stencil3_kernel(const int4* __restrict__ tiles, int ntiles, StepArgs sa) {
   __shared__ T sm[3 * kStHR * kStS];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
   StencilCtx<T> K;
   const T* phi;
   T* F;
@@ -999,8 +1011,9 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   typedef Op<KIND> O;
   typedef typename O::T T;
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
   const SubDev& S = sa.subs[tl.x];
   const int la = S.dim - 1;
   const int R = S.dim == 2 ? S.n[0] : S.n[0] * S.n[1];
@@ -1075,8 +1088,9 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   extern __shared__ __attribute__((aligned(16))) char lds[];
   __shared__ double red[4];
   __shared__ T stash[16][64];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
   const SubDev& S = sa.subs[tl.x];
   const InstDev& I = sa.insts[S.inst];
   const int la = S.dim - 1;
@@ -1099,7 +1113,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const BoxReg box = box_of(S);
   const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
   const int inst = S.inst;
-  const int pf0 = push_first[blockIdx.x], pf1 = push_first[blockIdx.x + 1];
+  const int pf0 = push_first[tix], pf1 = push_first[tix + 1];
   double part = 0.0;
   if (cb * 16 < C) {
     gmem<T>* __restrict__ phi = gpw<T>(S.phi);
@@ -1149,7 +1163,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   }
   const double tot = block_sum256(part, red);
   if (threadIdx.x == 0) {
-    sa.partials[part_base + blockIdx.x] = tot * hs;
+    sa.partials[part_base + tix] = tot * hs;
     if (I.pin && tl.x == I.first_sub && row0 == 0 && col0 == 0) sa.shift_acc[inst] += (double)dt * (double)shift;
   }
 }
@@ -1171,8 +1185,9 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   typedef typename O::T T;
   constexpr int MAXRB = 9;  // row blocks per wave: n <= 9 * 4 * 16 = 576
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
   const SubDev& S = sa.subs[tl.x];
   const int K = S.n[axis];
   const AxisDev& A = S.ax[axis];
@@ -1395,8 +1410,9 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
   typedef typename O::T T;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   __shared__ float red[4];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
   StencilCtx<T> K;
   const T* phi_;
   T* F_;
@@ -1501,8 +1517,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void euler_kernel(const int4* __restrict__ tiles, int ntiles,
                                                     int part_base, StepArgs sa) {
   __shared__ double red[4];
-  if ((int)blockIdx.x >= ntiles) return;
-  const int4 tl = tiles[blockIdx.x];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
   const SubDev& S = sa.subs[tl.x];
   const InstDev& I = sa.insts[S.inst];
   const int d = S.dim;
@@ -1530,7 +1547,7 @@ __global__ __launch_bounds__(256) void euler_kernel(const int4* __restrict__ til
   }
   double hs = S.h[0] * S.h[1] * (d == 3 ? S.h[2] : 1.0);
   double tot = block_sum256(acc, red);
-  if (threadIdx.x == 0) sa.partials[part_base + blockIdx.x] = tot * hs;
+  if (threadIdx.x == 0) sa.partials[part_base + tix] = tot * hs;
 }
 
 // ------------------------------------------------------------------------------------------
