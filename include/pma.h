@@ -278,6 +278,14 @@ int pma_plan_set_march(pma_plan* plan, int march);
  * Errors: PMA_E_INVAL for a NULL plan or a plan that has already stepped. */
 int pma_plan_set_fusion(pma_plan* plan, int on);
 
+/* Allow (on != 0, the default) or forbid the 64-column strip kernel of the axis products, which a
+ * plan uses when its 16-column strip tables would exceed 512 strips (FP32 and split forms, axes up
+ * to 320 padded nodes): each DCT matrix fragment is then read once for four column blocks.
+ * Results are bitwise the same either way (each column block keeps its own block scale and
+ * accumulation order); the switch exists to time and test both.  Only before the first step:
+ * PMA_E_INVAL afterwards. */
+int pma_plan_set_wide_strips(pma_plan* plan, int on);
+
 /* Glue request i's mesh (dim * prod(n) doubles) into host memory; st may be NULL. */
 int pma_plan_mesh(pma_plan* plan, int i, double* mesh_out, pma_stats* st);
 

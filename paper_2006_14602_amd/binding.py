@@ -108,6 +108,7 @@ def load():
     L.pma_plan_autotune.argtypes = [c_void_p, c_int, POINTER(c_int), POINTER(c_double), c_int, POINTER(c_int)]
     L.pma_plan_set_march.argtypes = [c_void_p, c_int]
     L.pma_plan_set_fusion.argtypes = [c_void_p, c_int]
+    L.pma_plan_set_wide_strips.argtypes = [c_void_p, c_int]
     L.pma_plan_mesh.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(Stats)]
     L.pma_plan_destroy.argtypes = [c_void_p]
     for f in declared_symbols():
@@ -423,6 +424,9 @@ class Plan:
 
     def set_fusion(self, on: bool):
         _check(self._L.pma_plan_set_fusion(self.h, 1 if on else 0))
+
+    def set_wide_strips(self, on: bool):
+        _check(self._L.pma_plan_set_wide_strips(self.h, 1 if on else 0))
 
     def mesh(self, i: int = 0):
         w = self.ws[i]

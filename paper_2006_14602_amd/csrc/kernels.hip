@@ -714,11 +714,47 @@ template <> struct Op<PREC_SPLIT16> {
   typedef float4_t acc_t;
   enum { KB = 32, LDS_BYTES = 4, SCALED = 1 };
   struct frag { half8_t hi, lo; };
-  // LDS holds the data operand in fp32; a fragment is scaled by the tile's power of two and
-  // split into fp16 hi + lo when it is read (block floating point: small entries keep their
-  // absolute accuracy relative to the tile's largest one instead of falling to fp16 subnormals)
+  // The data operand is staged in LDS in fp32; once its block scale is known, presplit turns it
+  // in place into fp16 hi + lo of x * 2^t (block floating point: small entries keep their absolute
+  // accuracy relative to the tile's largest one instead of falling to fp16 subnormals).  Each
+  // group of 8 fp32 entries (32 bytes) becomes 8 hi then 8 lo halves, so a fragment is two 16-byte
+  // reads and every entry is converted once, not once per product that reads it.
   static __device__ inline void put(char* lds, int ld, int r, int k, float x) { ((float*)lds)[r * ld + k] = x; }
-  static __device__ inline frag lds_frag(const char* lds, int ld, int r, int k0, int g, float sc) {
+  // rows [0, rows) of stride ld entries, k in [0, kend) (kend a multiple of 8); row r takes the
+  // scale sc[r / rows_per_scale].  All threads of the workgroup take part; a barrier must follow.
+  static __device__ inline void presplit(char* lds, int ld, int rows, int kend, const float* sc,
+                                         int rows_per_scale) {
+    const int groups = kend >> 3;
+    for (int idx = threadIdx.x; idx < rows * groups; idx += blockDim.x) {
+      const int r = idx / groups, k = (idx - r * groups) * 8;
+      const float s = sc[r / rows_per_scale];
+      float4_t* p = (float4_t*)((float*)lds + r * ld + k);
+      const float4_t u = p[0], v = p[1];
+      half8_t hi, lo;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float x = u[i] * s, y = v[i] * s;
+        const _Float16 hx = (_Float16)x, hy = (_Float16)y;
+        hi[i] = hx;
+        hi[4 + i] = hy;
+        lo[i] = (_Float16)(x - (float)hx);
+        lo[4 + i] = (_Float16)(y - (float)hy);
+      }
+      half8_t* q = (half8_t*)p;
+      q[0] = hi;
+      q[1] = lo;
+    }
+  }
+  static __device__ inline frag lds_frag(const char* lds, int ld, int r, int k0, int g, float) {
+    const half8_t* p = (const half8_t*)((const float*)lds + r * ld + k0 + 8 * g);
+    frag f;
+    f.hi = p[0];
+    f.lo = p[1];
+    return f;
+  }
+  // a fragment of an operand still in fp32, split on the fly: the products with a basis copy in
+  // LDS read each data fragment once per wave, where a separate pass would only add latency
+  static __device__ inline frag lds_frag_cvt(const char* lds, int ld, int r, int k0, int g, float sc) {
     const float4_t* p = (const float4_t*)((const float*)lds + r * ld + k0 + 8 * g);
     const float4_t u = p[0], v = p[1];
     frag f;
@@ -770,8 +806,12 @@ template <> struct Op<PREC_F32> {
   enum { KB = 4, LDS_BYTES = 4, SCALED = 0 };
   typedef float frag;
   static __device__ inline void put(char* lds, int ld, int r, int k, float x) { ((float*)lds)[r * ld + k] = x; }
+  static __device__ inline void presplit(char*, int, int, int, const float*, int) {}
   static __device__ inline frag lds_frag(const char* lds, int ld, int r, int k0, int g, float) {
     return ((const float*)lds)[r * ld + k0 + g];
+  }
+  static __device__ inline frag lds_frag_cvt(const char* lds, int ld, int r, int k0, int g, float sc) {
+    return lds_frag(lds, ld, r, k0, g, sc);
   }
   static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
     return gp<float>(p)[(long)r * ld + k0 + g];
@@ -793,8 +833,12 @@ template <> struct Op<PREC_F64> {
   enum { KB = 4, LDS_BYTES = 8, SCALED = 0 };
   typedef double frag;
   static __device__ inline void put(char* lds, int ld, int r, int k, double x) { ((double*)lds)[r * ld + k] = x; }
+  static __device__ inline void presplit(char*, int, int, int, const float*, int) {}
   static __device__ inline frag lds_frag(const char* lds, int ld, int r, int k0, int g, float) {
     return ((const double*)lds)[r * ld + k0 + g];
+  }
+  static __device__ inline frag lds_frag_cvt(const char* lds, int ld, int r, int k0, int g, float sc) {
+    return lds_frag(lds, ld, r, k0, g, sc);
   }
   static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
     return gp<double>(p)[(long)r * ld + k0 + g];
@@ -878,7 +922,7 @@ __device__ inline void mma_lbasis_rows(typename Op<KIND>::acc_t (&acc)[kLdsRb], 
     typename O::frag a[kLdsRb];
 #pragma unroll
     for (int t = 0; t < kLdsRb; ++t) a[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
-    const typename O::frag b = O::lds_frag(lds, ldo, l16, k0, g, sc);
+    const typename O::frag b = O::lds_frag_cvt(lds, ldo, l16, k0, g, sc);
 #pragma unroll
     for (int t = 0; t < kLdsRb; ++t) O::mma(acc[t], a[t], b);
   }
@@ -897,7 +941,7 @@ __device__ inline void mma_rows_lbasis(typename Op<KIND>::acc_t (&acc)[kLdsRb], 
     typename O::frag b[kLdsRb];
 #pragma unroll
     for (int t = 0; t < kLdsRb; ++t) b[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
-    const typename O::frag a = O::lds_frag(lds, ldo, l16, k0, g, sc);
+    const typename O::frag a = O::lds_frag_cvt(lds, ldo, l16, k0, g, sc);
 #pragma unroll
     for (int t = 0; t < kLdsRb; ++t) O::mma(acc[t], a, b[t]);
   }
@@ -1027,6 +1071,10 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   const float amax = stage_rows16<KIND>(lds, ld, ldo, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   __syncthreads();
+  if (O::SCALED) {
+    O::presplit(lds, ldo, 16, ld, &sc, 16);
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
   const int cb = (col0 >> 4) + wave;
   if (cb * 16 >= C) return;
@@ -1105,6 +1153,10 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const float amax = stage_rows16<KIND>(lds, ld, ldo, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale(amax, redf) : 1.f;
   __syncthreads();
+  if (O::SCALED) {
+    O::presplit(lds, ldo, 16, ld, &sc, 16);
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
   const int cb = (col0 >> 4) + wave;
   const T shift = instance_shift<T>(sa, I);
@@ -1248,6 +1300,10 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   if (lbasis) vmem_drain();
   __syncthreads();
+  if (O::SCALED && !lbasis) {  // the LDS-basis products split each fragment on the fly
+    O::presplit(lds, ldo, 16, ld, &sc, 16);
+    __syncthreads();
+  }
   typename O::acc_t acc[MAXRB];
   const T us1 = ((PAIR || !inv) ? T(A.fwd_unscale) : T(1)) / T(sc);
 #pragma unroll
@@ -1313,6 +1369,10 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
       O::put(lds, ldo, cc, k, T(0));
     }
     __syncthreads();
+    if (O::SCALED && !lbasis) {
+      O::presplit(lds, ldo, 16, ld, &sy, 16);
+      __syncthreads();
+    }
     // store scale: 1 / sy, and on the LDS path (N / 2) D^-1 and the split form's 2^-s
     const T half_n = T(K - 1) / T(2);
     const T os = lbasis ? T(A.fwd_unscale) * half_n / T(sy) : T(1) / T(sy);
@@ -1339,6 +1399,278 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
         if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][q] * ((lbasis && (i == 0 || i == K - 1)) ? T(2) * os : os);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Wide strips for large batches: four 16-column blocks [col0, col0 + 64) per workgroup.  With
+// thousands of strips the DCT matrices, read whole by every workgroup, dominate the traffic; here
+// each basis fragment is fetched once and multiplied into all four blocks.  Every column block
+// keeps its own block scale and its own accumulation order, so each output equals the 16-column
+// kernel's (global-basis path) bit for bit.  Padded axis length at most kWideMaxLd.
+// ------------------------------------------------------------------------------------------
+
+constexpr int kWideMaxLd = 320;
+constexpr int kWideNc = 4;                          // 16-column blocks per workgroup
+constexpr int kWideRb = (kWideMaxLd / 16 + 3) / 4;  // row blocks per wave
+
+// per-column-block power-of-two scales (as tile_scale, one per 16 columns): lane l of every wave
+// holds column block l / 16's running maximum
+__device__ inline void tile_scale4(float amax, float* red, float* out) {
+  for (int o = 8; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if ((lane & 15) == 0) red[wave * 4 + (lane >> 4)] = amax;
+  __syncthreads();
+#pragma unroll
+  for (int cb = 0; cb < kWideNc; ++cb) {
+    const float m = fmaxf(fmaxf(red[cb], red[4 + cb]), fmaxf(red[8 + cb], red[12 + cb]));
+    float sc = 1.f;
+    if (m > 0.f && isfinite(m)) {
+      int e;
+      frexpf(m, &e);
+      sc = ldexpf(1.f, 14 - e);
+    }
+    out[cb] = sc;
+  }
+  __syncthreads();
+}
+
+template <int KIND, bool PAIR>
+__global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
+                                                     int src_sel, StepArgs sa) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  constexpr int NC = kWideNc, MAXRB = kWideRb;
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  __shared__ float red[16];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
+  const SubDev& S = sa.subs[tl.x];
+  const int K = S.n[axis];
+  const AxisDev& A = S.ax[axis];
+  const int ld = A.ld, ldb = A.ldb, ldo = ld + O::OPAD;
+  int ncol;
+  long base;
+  if (axis == 0) {
+    ncol = S.dim == 2 ? S.n[1] : S.n[1] * S.n[2];
+    base = 0;
+  } else {
+    ncol = S.n[2];
+    base = (long)tl.y * S.n[1] * S.n[2];
+  }
+  const int col0 = tl.z;
+  const gmem<T>* __restrict__ src = gp<T>(src_sel ? S.T : S.F) + base;
+  gmem<T>* __restrict__ dst = gpw<T>(src_sel ? S.F : S.T) + base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int nrb = (K + 15) >> 4;
+  const void* b1h = (PAIR || !inv) ? A.fwd : A.inv;
+  const void* b1l = (PAIR || !inv) ? A.fwdl : A.invl;
+  // PAIR: spectral factors, requested before the products
+  T sig0[PAIR ? MAXRB * 4 : 1];
+  T rest[NC];
+#pragma unroll
+  for (int cb = 0; cb < NC; ++cb) rest[cb] = T(0);
+  if constexpr (PAIR) {
+    const gmem<T>* s0 = gp<T>(S.ax[0].sig);
+    const gmem<T>* s1 = gp<T>(S.ax[1].sig);
+    const gmem<T>* s2 = gp<T>(S.ax[2].sig);
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+      const int c = col0 + cb * 16 + l16;
+      if (c < ncol) {
+        if (S.dim == 2) rest[cb] = T(S.gh2[1]) * s1[c];
+        else {
+          const int k1 = c / S.n[2], k2 = c - (c / S.n[2]) * S.n[2];
+          rest[cb] = T(S.gh2[1]) * s1[k1] + T(S.gh2[2]) * s2[k2];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t)
+      for (int q = 0; q < 4; ++q) {
+        const int i = (wave + 4 * t) * 16 + O::crow(g, q);
+        sig0[t * 4 + q] = i < K ? s0[i] : T(0);
+      }
+  }
+  // stage the 64 columns transposed (operand row = column within the tile); thread t takes column
+  // t % 64 and rows t / 64 + 4 j, twelve loads in flight per batch
+  float amax = 0.f;
+  {
+    constexpr int B = 12;
+    const int c = threadIdx.x & 63, k0 = threadIdx.x >> 6;
+    const bool cok = col0 + c < ncol;
+    for (int kb = 0; kb < ld; kb += 4 * B) {
+      T v[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int k = kb + k0 + 4 * j;
+        v[j] = (cok && k < K) ? src[(long)k * ncol + col0 + c] : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int k = kb + k0 + 4 * j;
+        if (k < ld) {
+          O::put(lds, ldo, c, k, v[j]);
+          if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j]));
+        }
+      }
+    }
+  }
+  float sc[NC];
+  if (O::SCALED) tile_scale4(amax, red, sc);
+  else {
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) sc[cb] = 1.f;
+  }
+  __syncthreads();
+  if (O::SCALED) {
+    O::presplit(lds, ldo, 64, ld, sc, 16);
+    __syncthreads();
+  }
+  typename O::acc_t acc[MAXRB][NC];
+#pragma unroll
+  for (int t = 0; t < MAXRB; ++t)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) acc[t][cb] = typename O::acc_t{0, 0, 0, 0};
+  // acc[t][cb] += basis rows of row block wave + 4 t x column block cb; each basis fragment is
+  // loaded once (four k steps ahead) and used for the four blocks
+  auto products = [&](const void* bh, const void* bl, const float* scl) {
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb >= nrb) continue;
+      const int arow = rb * 16 + l16;
+      constexpr int U = 4;
+      for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
+        typename O::frag a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * O::KB;
+          a[u] = k < ld ? O::glob_frag(bh, bl, ldb, arow, k, g) : O::zero_frag();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + u * O::KB;
+#pragma unroll
+          for (int cb = 0; cb < NC; ++cb)
+            O::mma(acc[t][cb], a[u], O::lds_frag(lds, ldo, cb * 16 + l16, k < ld ? k : k0, g, scl[cb]));
+        }
+      }
+    }
+  };
+  products(b1h, b1l, sc);
+  if constexpr (!PAIR) {
+    const T fu = (!inv) ? T(A.fwd_unscale) : T(1);
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb >= nrb) continue;
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        const int c = col0 + cb * 16 + l16;
+        const T us = fu / T(sc[cb]);
+        for (int q = 0; q < 4; ++q) {
+          const int i = rb * 16 + O::crow(g, q);
+          if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][cb][q] * us;
+        }
+      }
+    }
+  } else {
+    const T g0 = T(S.gh2[0]);
+    float ym[NC];  // largest |y| this lane holds in each column block
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) ym[cb] = 0.f;
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        const int c = col0 + cb * 16 + l16;
+        const T us1 = T(A.fwd_unscale) / T(sc[cb]);
+        for (int q = 0; q < 4; ++q) {
+          const int i = rb * 16 + O::crow(g, q);
+          T y = T(0);
+          if (rb < nrb && i < K && c < ncol) {
+            const T val = acc[t][cb][q] * us1;
+            if (i == 0 && c == 0) gpw<T>(sa.dc)[tl.x] = val;
+            y = val / (T(1) + g0 * sig0[t * 4 + q] + rest[cb]);
+          }
+          acc[t][cb][q] = y;
+          if (O::SCALED) ym[cb] = fmaxf(ym[cb], fabsf((float)y));
+        }
+      }
+    }
+    __syncthreads();  // every wave is done reading the staged columns
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb >= nrb) continue;
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb)
+        for (int q = 0; q < 4; ++q) O::put(lds, ldo, cb * 16 + l16, rb * 16 + O::crow(g, q), acc[t][cb][q]);
+    }
+    // zero the padding rows nrb*16 .. ld of the operand
+    for (int idx = threadIdx.x; idx < 64 * (ld - nrb * 16); idx += 256) {
+      const int k = nrb * 16 + idx / 64, cc = idx & 63;
+      O::put(lds, ldo, cc, k, T(0));
+    }
+    float sy[NC];
+    if (O::SCALED) {
+      // block maxima: lane l's values all belong to column block (its own) cb for each cb slot;
+      // reduce each slot over the 16 lanes of a column group, then over waves and lane groups
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        float m = ym[cb];
+        for (int o = 8; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));  // over l16
+        m = fmaxf(m, __shfl_xor(m, 16, 64));                                   // over g
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+        ym[cb] = m;
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) red[wave * 4 + cb] = ym[cb];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        const float m = fmaxf(fmaxf(red[cb], red[4 + cb]), fmaxf(red[8 + cb], red[12 + cb]));
+        float v = 1.f;
+        if (m > 0.f && isfinite(m)) {
+          int e;
+          frexpf(m, &e);
+          v = ldexpf(1.f, 14 - e);
+        }
+        sy[cb] = v;
+      }
+    } else {
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) sy[cb] = 1.f;
+    }
+    __syncthreads();
+    if (O::SCALED) {
+      O::presplit(lds, ldo, 64, ld, sy, 16);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t)
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) acc[t][cb] = typename O::acc_t{0, 0, 0, 0};
+    products(A.inv, A.invl, sy);
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t) {
+      const int rb = wave + 4 * t;
+      if (rb >= nrb) continue;
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) {
+        const int c = col0 + cb * 16 + l16;
+        const T os = T(1) / T(sy[cb]);
+        for (int q = 0; q < 4; ++q) {
+          const int i = rb * 16 + O::crow(g, q);
+          if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][cb][q] * os;
+        }
       }
     }
   }
@@ -1475,6 +1807,10 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
   const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
   if (lbasis) vmem_drain();
   __syncthreads();
+  if (O::SCALED && !lbasis) {  // the LDS-basis products split each fragment on the fly
+    O::presplit(lds, ldo, 16, ld, &sc, 16);
+    __syncthreads();
+  }
   gmem<T>* out = gpw<T>(S.T);
   const T us = T(A.fwd_unscale) / T(sc);
   constexpr int NT = (kFuseMaxLd / 16 + 3) / 4;
@@ -1888,6 +2224,22 @@ hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int 
   return hipGetLastError();
 }
 
+hipError_t launch_strip4(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
+                         int src_sel, const StepArgs& sa, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (prec == PREC_F64 || maxld > kWideMaxLd) return hipErrorInvalidValue;
+  const size_t sh = (size_t)64 * (maxld + Op<PREC_F32>::OPAD) * 4;
+#define PMA_STRIP4(K, P) \
+  hipLaunchKernelGGL((strip4_kernel<K, P>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, axis, inv, src_sel, sa)
+  if (prec == PREC_F32) {
+    if (pair) PMA_STRIP4(PREC_F32, true); else PMA_STRIP4(PREC_F32, false);
+  } else {
+    if (pair) PMA_STRIP4(PREC_SPLIT16, true); else PMA_STRIP4(PREC_SPLIT16, false);
+  }
+#undef PMA_STRIP4
+  return hipGetLastError();
+}
+
 // kernels using more than 64 KiB of dynamic LDS must say so once per process
 hipError_t enable_large_lds() {
   static hipError_t rc = [] {
@@ -1901,7 +2253,9 @@ hipError_t enable_large_lds() {
                         (const void*)strip_kernel<PREC_F32, true>, (const void*)strip_kernel<PREC_F32, false>,
                         (const void*)strip_kernel<PREC_SPLIT16, true>, (const void*)strip_kernel<PREC_SPLIT16, false>,
                         (const void*)stencil_fwd2_kernel<PREC_F64>, (const void*)stencil_fwd2_kernel<PREC_F32>,
-                        (const void*)stencil_fwd2_kernel<PREC_SPLIT16>};
+                        (const void*)stencil_fwd2_kernel<PREC_SPLIT16>, (const void*)strip4_kernel<PREC_F32, true>,
+                        (const void*)strip4_kernel<PREC_F32, false>, (const void*)strip4_kernel<PREC_SPLIT16, true>,
+                        (const void*)strip4_kernel<PREC_SPLIT16, false>};
     for (const void* k : ks) {
       // whatever the kernel's static LDS leaves of the 160 KiB (at most lim)
       hipFuncAttributes fa{};

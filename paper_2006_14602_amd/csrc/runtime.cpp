@@ -35,6 +35,8 @@ hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, c
 hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const int* push_first,
                            const int4* push, const StepArgs& sa,
                            hipStream_t s);
+hipError_t launch_strip4(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
+                         int src_sel, const StepArgs& sa, hipStream_t s);
 hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
                         int src_sel, const StepArgs& sa, hipStream_t s);
 hipError_t enable_large_lds();
@@ -1023,6 +1025,7 @@ static constexpr int kLdsBasisCap = 160 * 1024 - 4096;  // dynamic LDS a workgro
 // leaves room for one workgroup per CU: worth it while a launch has at most about two
 // workgroups per CU (latency-bound), not for large batches that rely on occupancy.
 static constexpr int kLdsBasisMaxTiles = 512;
+static constexpr int kWideMaxLd = 320;  // widest padded axis of the 64-column strip kernel
 
 struct SubRange {
   int first, count;
@@ -1204,6 +1207,40 @@ struct Batch {
 
   static int lds_basis(const Table& t, int count) { return count <= kLdsBasisMaxTiles ? t.lneed : 0; }
 
+  // 64-column strips (phases 4-6) when a 16-column table would exceed kLdsBasisMaxTiles strips:
+  // every strip then reads its axis' DCT matrices from L2, and four blocks per workgroup read them
+  // a quarter as often.  Bitwise the same results; FP32 and split forms, axes up to kWideMaxLd.
+  bool wide_ok = true;
+  bool wide_[kPhases] = {};
+  void choose_wide() {
+    long cnt[kPhases] = {0}, cols[kPhases] = {0}, cols64[kPhases] = {0};
+    int mld[kPhases] = {0};
+    for (auto& w : wide_) w = false;
+    if (!wide_ok || prec == PMA_FP64) return;
+    for (const SubDev& sd : h_subs) {
+      if (insts[sd.inst]->tm.gamma == 0.0) continue;
+      const int rest = sd.dim == 2 ? sd.n[1] : sd.n[1] * sd.n[2];
+      cnt[5] += (rest + kStrip - 1) / kStrip;
+      cols[5] += rest;
+      cols64[5] += (rest + 63) / 64 * 64;
+      mld[5] = std::max(mld[5], sd.ax[0].ld);
+      if (sd.dim == 3) {
+        const long c = (long)sd.n[0] * ((sd.n[2] + kStrip - 1) / kStrip);
+        cnt[4] += c;
+        cnt[6] += c;
+        for (int ph : {4, 6}) {
+          cols[ph] += (long)sd.n[0] * sd.n[2];
+          cols64[ph] += (long)sd.n[0] * ((sd.n[2] + 63) / 64 * 64);
+        }
+        mld[4] = std::max(mld[4], sd.ax[1].ld);
+        mld[6] = std::max(mld[6], sd.ax[1].ld);
+      }
+    }
+    // and only where 64-column tiles are mostly full (a 68-wide slab would waste half its second tile)
+    for (int ph = 4; ph <= 6; ++ph)
+      wide_[ph] = cnt[ph] > kLdsBasisMaxTiles && mld[ph] <= kWideMaxLd && 5 * cols[ph] >= 4 * cols64[ph];
+  }
+
   // strip launches copy an axis' basis into LDS when strip + basis fit in a workgroup's LDS:
   // 16 x ld operand entries and round_up(n, 16) x ld basis entries (split form: hi + lo)
   void note_lds(Table& t, int n, int ld) const {
@@ -1349,6 +1386,8 @@ struct Batch {
       }
     }
     // tiles, subdomain by subdomain in launch order
+    choose_wide();
+    const int sw4 = wide_[4] ? 4 * kStrip : kStrip, sw5 = wide_[5] ? 4 * kStrip : kStrip;
     for (int ph = 1; ph < kPhases; ++ph) tab[ph].rng.assign(h_subs.size(), SubRange{0, 0});
     {
       for (int gs : order) {
@@ -1375,7 +1414,7 @@ struct Batch {
           }
           if (I.dim == 3) {
             for (int i0 = 0; i0 < n0; ++i0)
-              for (int c = 0; c < n2; c += kStrip) {
+              for (int c = 0; c < n2; c += sw4) {  // phases 4 and 6 share the width
                 tab[4].h.push_back(int4{gs, i0, c, 0});
                 tab[6].h.push_back(int4{gs, i0, c, 0});
               }
@@ -1385,7 +1424,7 @@ struct Batch {
             note_lds(tab[6], n1, sd.ax[1].ld);
           }
           const int rest = I.dim == 2 ? n1 : n1 * n2;
-          for (int c = 0; c < rest; c += kStrip) tab[5].h.push_back(int4{gs, 0, c, 0});
+          for (int c = 0; c < rest; c += sw5) tab[5].h.push_back(int4{gs, 0, c, 0});
           tab[5].maxld = std::max(tab[5].maxld, sd.ax[0].ld);
           note_lds(tab[5], n0, sd.ax[0].ld);
           for (int r = 0; r < R; r += kRows)
@@ -1501,11 +1540,18 @@ struct Batch {
         break;
       case 2: HIPCHK(launch_euler(prec, t.d + first, count, part_base_eu + first, sa, st)); break;
       case 3: HIPCHK(launch_fwd_last(prec, t.d + first, count, t.maxld, sa, st)); break;
-      case 4: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 0, 1, sa, st)); break;
-      case 5:  // 2D: T -> F;  3D: F -> T (pair_src_ set by launch_phase)
-        HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, lds_basis(t, count), 0, 0, pair_src_, sa, st));
+      case 4:
+        if (wide_[4]) HIPCHK(launch_strip4(prec, false, t.d + first, count, t.maxld, 1, 0, 1, sa, st));
+        else HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 0, 1, sa, st));
         break;
-      case 6: HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 1, 1, sa, st)); break;
+      case 5:  // 2D: T -> F;  3D: F -> T (pair_src_ set by launch_phase)
+        if (wide_[5]) HIPCHK(launch_strip4(prec, true, t.d + first, count, t.maxld, 0, 0, pair_src_, sa, st));
+        else HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, lds_basis(t, count), 0, 0, pair_src_, sa, st));
+        break;
+      case 6:
+        if (wide_[6]) HIPCHK(launch_strip4(prec, false, t.d + first, count, t.maxld, 1, 1, 1, sa, st));
+        else HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 1, 1, sa, st));
+        break;
       case 7:
         HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, d_pfirst + first, d_push, sa, st));
         break;
@@ -2477,6 +2523,18 @@ int pma_plan_set_fusion(pma_plan* P, int on) {
   for (auto& I : P->insts)
     if (I->steps_done > 0) return fail(PMA_E_INVAL, "fusion can only be changed before the first step");
   P->batch->fuse = on != 0;
+  P->batch->build();
+  return PMA_OK;
+  API_END
+}
+
+int pma_plan_set_wide_strips(pma_plan* P, int on) {
+  API_BEGIN
+  if (!P) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  for (auto& I : P->insts)
+    if (I->steps_done > 0) return fail(PMA_E_INVAL, "strip width can only be changed before the first step");
+  P->batch->wide_ok = on != 0;
   P->batch->build();
   return PMA_OK;
   API_END

@@ -174,6 +174,23 @@ def test_fused_stencil_equals_separate_launches_bitwise(ctx, B, prec):
         np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["split16", "fp32"])
+@pytest.mark.parametrize("wl", ["bumps96", "shell129"])
+def test_wide_strips_equal_narrow_bitwise(ctx, B, prec, wl):
+    # large strip tables switch the axis products to 64-column workgroups; each column block keeps
+    # its own block scale and accumulation order, so the meshes are identical
+    ws = W.bumps_batch(count=96, steps=12) if wl == "bumps96" else [W.shell_dd(steps=6)]
+    meshes = []
+    for wide in (True, False):
+        with B.Plan(ctx, ws, prec) as p:
+            p.set_wide_strips(wide)
+            p.step(ws[0]["time"]["steps"])
+            p.sync()
+            meshes.append([p.mesh(i)[0] for i in range(0, len(ws), max(1, len(ws) // 6))])
+    for a, b in zip(*meshes):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_warm_start_and_psi_out(ctx):
     # 30 steps, then 20 more from the oracle's Psi, against 50 oracle steps; Psi itself is
     # returned with the constants the FP32 path removed added back
