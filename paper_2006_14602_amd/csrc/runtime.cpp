@@ -1207,18 +1207,23 @@ struct Batch {
 
   static int lds_basis(const Table& t, int count) { return count <= kLdsBasisMaxTiles ? t.lneed : 0; }
 
-  // 64-column strips (phases 4-6) when a 16-column table would exceed kLdsBasisMaxTiles strips:
-  // every strip then reads its axis' DCT matrices from L2, and four blocks per workgroup read them
-  // a quarter as often.  Bitwise the same results; FP32 and split forms, axes up to kWideMaxLd.
+  // 64-column strips (phases 4-6) when every launch of a 16-column table would exceed
+  // kLdsBasisMaxTiles strips: every strip then reads its axis' DCT matrices from L2, and four
+  // blocks per workgroup read them a quarter as often.  A launch of fewer strips (a sweep level of
+  // an alternating request) is latency-bound and keeps the narrow strips.  Bitwise the same
+  // results; FP32 and split forms, axes up to kWideMaxLd.
   bool wide_ok = true;
   bool wide_[kPhases] = {};
   void choose_wide() {
-    long cnt[kPhases] = {0}, cols[kPhases] = {0}, cols64[kPhases] = {0};
+    long cols[kPhases] = {0}, cols64[kPhases] = {0};
+    std::vector<long> lcnt((size_t)nlev * kPhases, 0);  // strips per sweep level and phase
     int mld[kPhases] = {0};
     for (auto& w : wide_) w = false;
     if (!wide_ok || prec == PMA_FP64) return;
-    for (const SubDev& sd : h_subs) {
+    for (size_t gs = 0; gs < h_subs.size(); ++gs) {
+      const SubDev& sd = h_subs[gs];
       if (insts[sd.inst]->tm.gamma == 0.0) continue;
+      long* cnt = &lcnt[(size_t)glevel[gs] * kPhases];
       const int rest = sd.dim == 2 ? sd.n[1] : sd.n[1] * sd.n[2];
       cnt[5] += (rest + kStrip - 1) / kStrip;
       cols[5] += rest;
@@ -1237,8 +1242,14 @@ struct Batch {
       }
     }
     // and only where 64-column tiles are mostly full (a 68-wide slab would waste half its second tile)
-    for (int ph = 4; ph <= 6; ++ph)
-      wide_[ph] = cnt[ph] > kLdsBasisMaxTiles && mld[ph] <= kWideMaxLd && 5 * cols[ph] >= 4 * cols64[ph];
+    for (int ph = 4; ph <= 6; ++ph) {
+      long least = -1;
+      for (int L = 0; L < nlev; ++L) {
+        const long c = lcnt[(size_t)L * kPhases + ph];
+        if (c > 0) least = least < 0 ? c : std::min(least, c);
+      }
+      wide_[ph] = least > kLdsBasisMaxTiles && mld[ph] <= kWideMaxLd && 5 * cols[ph] >= 4 * cols64[ph];
+    }
   }
 
   // strip launches copy an axis' basis into LDS when strip + basis fit in a workgroup's LDS:
