@@ -1891,17 +1891,28 @@ struct Server {
   size_t request_bytes(const Instance& I) { return Arena::round(instance_bytes(I)) + new_basis_bytes(ctx, I); }
 
   // admit queued requests in arrival order while they fit (no overtaking); caller holds mu
+  // true while the head of the queue waits for memory: nothing can be admitted before a running
+  // request finishes, so a tick may run until the first of them does
+  bool blocked = false;
+
   void admit_locked() {
+    blocked = false;
     while (!queue.empty()) {
       Instance* I = queue.front();
       const size_t need = request_bytes(*I);
       std::lock_guard<std::recursive_mutex> cg(ctx->mu);
       try {
         ensure_arena(ctx);
-        if (ctx->arena.used() + need > ctx->arena.size()) break;
+        if (ctx->arena.used() + need > ctx->arena.size()) {
+          blocked = true;
+          break;
+        }
         alloc_instance(ctx, *I);
       } catch (Err& e) {
-        if (e.code == PMA_E_NOMEM) break;  // fragmented or full: wait for frees
+        if (e.code == PMA_E_NOMEM) {  // fragmented or full: wait for frees
+          blocked = true;
+          break;
+        }
         I->status = e.code;
         I->t_done = now_s();
         state[I->ticket] = PMA_FAILED;
@@ -1929,8 +1940,13 @@ struct Server {
           continue;
         }
       }
+      bool wait_for_memory;
+      {
+        std::lock_guard<std::mutex> g(mu);
+        wait_for_memory = blocked;
+      }
       try {
-        tick();
+        tick(wait_for_memory ? kLongTick : kShortTick);
       } catch (Err& e) {
         std::lock_guard<std::recursive_mutex> cg(ctx->mu);
         std::lock_guard<std::mutex> g(mu);
@@ -1949,8 +1965,12 @@ struct Server {
     }
   }
 
-  // membership changed: rebuild the launch tables in place (direct launches, no graph: the set of
-  // requests changes every few milliseconds under load)
+  // steps per tick: short while arrivals could be admitted, long (ending when the first running
+  // request finishes) while the queue waits for memory
+  static constexpr int kShortTick = 8, kLongTick = 64;
+
+  // membership changed: rebuild the launch tables in place; the step is captured as a graph and
+  // replayed for the rest of the membership
   void rebuild() {
     hipStream_t st = ctx->stream;
     for (int p = 0; p < 3; ++p) {
@@ -1968,7 +1988,7 @@ struct Server {
       if (!batch[p]) batch[p].reset(new Batch);
       batch[p]->ctx = ctx;
       batch[p]->prec = p;
-      batch[p]->use_graph = false;
+      batch[p]->use_graph = true;
       batch[p]->insts = v;
       batch[p]->build();
       for (size_t q = 0; q < v.size(); ++q)
@@ -1979,13 +1999,19 @@ struct Server {
   }
 
   // advance every running request a few steps in shared launches; finish the ones that end
-  void tick() {
+  void tick(int max_chunk) {
     std::lock_guard<std::recursive_mutex> cg(ctx->mu);
     hipStream_t st = ctx->stream;
     if (dirty) rebuild();
     int chunk = 1 << 30;
-    for (auto* I : running) chunk = std::min(chunk, I->tm.max_steps - I->steps_done);
-    chunk = std::max(0, std::min(chunk, 8));  // bounded so arrivals are admitted promptly
+    for (auto* I : running) {
+      chunk = std::min(chunk, I->tm.max_steps - I->steps_done);
+      if (I->tm.tol > 0) {  // a TOL request is checked on its residual cadence
+        const int R = std::max(1, I->tm.resid_every);
+        chunk = std::min(chunk, R - I->steps_done % R);
+      }
+    }
+    chunk = std::max(0, std::min(chunk, max_chunk));
     for (int k = 0; k < chunk; ++k)
       for (int p = 0; p < 3; ++p)
         if (batch[p] && !batch[p]->insts.empty()) batch[p]->step(false);
