@@ -6,9 +6,11 @@ streams.  There is no fallback: if the built library is missing, load() raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import weakref
 from ctypes import POINTER, c_double, c_int, c_size_t, c_uint64, c_void_p
 
 import numpy as np
@@ -253,6 +255,19 @@ def theta(grid: dict, mon: dict) -> float:
 # context
 # ---------------------------------------------------------------------------------------------
 
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    # release device memory while torch's allocator is still alive
+    for c in list(_LIVE):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A library context on one GPU.  The device arena (budget bytes) comes from torch's caching
     allocator unless use_torch_allocator is False."""
@@ -267,18 +282,24 @@ class Context:
         self._cbs = None
         if use_torch_allocator:
             import torch
+            alloc = torch.cuda.caching_allocator_alloc
+            delete = torch.cuda.caching_allocator_delete
 
             def _alloc(size, stream, user):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(size), device=device)
+                    return alloc(int(size), device=device)
                 except Exception:
                     return None
 
             def _free(ptr, stream, user):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                try:
+                    delete(int(ptr))
+                except Exception:  # interpreter shutdown: torch may already be torn down
+                    pass
 
             self._cbs = (ALLOC_CB(_alloc), FREE_CB(_free))
             _check(L.pma_set_allocator(self.h, self._cbs[0], self._cbs[1], None))
+        _LIVE.add(self)
 
     def close(self):
         if self.h:
