@@ -101,6 +101,24 @@ def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0, tune=
     return out
 
 
+def glued_vs_single(ctx, binding, w, prec):
+    """The glued DD mesh against the whole-domain mesh of the same problem (same gamma, dt and
+    steps): the decomposition error at the headline size (Sec. 4.4)."""
+    import numpy as np
+    meshes = []
+    for ww in (w, dict(w, dd=None)):
+        plan = binding.Plan(ctx, [ww], prec, "batched")
+        try:
+            plan.step(ww["time"]["steps"])
+            plan.sync()
+            meshes.append(plan.mesh(0)[0])
+        finally:
+            plan.close()
+    d = np.abs(meshes[0] - meshes[1])
+    return {"max_mesh_diff": float(d.max()), "rms_mesh_diff": float(np.sqrt(np.mean(d * d))),
+            "steps": w["time"]["steps"], "precision": prec}
+
+
 def paper_workloads(ctx, binding, workloads):
     """The paper's own examples (Sec. 4): arc-length monitors of its test functions, alternating
     sweeps (Algorithm 1) as the paper ran them, and the alternating form of the headline case.
@@ -318,6 +336,8 @@ def main():
     }
     if "fp64plain" in forms and main_form != "fp64plain":
         out["batched_fp32_over_plain_fp64"] = m["updates_per_s"] / forms["fp64plain"]["updates_per_s"]
+    if not args.only:
+        out["glued_vs_single_domain"] = glued_vs_single(ctx, binding, w, prec)
     if not args.quick and not args.only:
         extra = {}
         ring = workloads.ring()

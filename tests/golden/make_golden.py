@@ -4,6 +4,7 @@ Calls only the FP64 oracle on the seeded workloads and stores, per workload, a s
 subsample of the glued mesh plus a seeded random sample of nodes (numpy .npz, no pickles):
   sine_dd_513.npz          513 x 513, 4 x 4 subdomains, overlap 8 cells, 500 steps
   shell_dd_129.npz         129^3, 2 x 2 x 2 subdomains, overlap 6 cells, 200 steps
+  sine_single_513.npz      the same 513 x 513 problem on the whole domain (same gamma, dt, steps)
   sine_dd_513_alt.npz      the same 513 x 513 split, alternating sweeps (Algorithm 1), 200 steps
   burgers_front_65.npz     Burgers-front arc-length monitor, 4 slabs, alternating, 300 steps
   spiral_257.npz           spiral arc-length monitor, 257 x 257, 4 x 4, 300 steps
@@ -32,7 +33,13 @@ def _sine_alt():
     return w
 
 
-CASES = {"sine_dd_513": (W.sine_dd, 8), "shell_dd_129": (W.shell_dd, 8),
+def _sine_single():
+    w = W.sine_dd()
+    w["dd"] = None  # the same grid, monitor, gamma and dt on the whole domain
+    return w
+
+
+CASES = {"sine_dd_513": (W.sine_dd, 8), "shell_dd_129": (W.shell_dd, 8), "sine_single_513": (_sine_single, 8),
          "sine_dd_513_alt": (_sine_alt, 8),
          "burgers_front_65": (lambda: W.burgers_front(parts=(4, 1), steps=300), 2),
          "spiral_257": (lambda: W.spiral(steps=300), 4),
@@ -61,8 +68,11 @@ def make(name):
         th = O.theta_quadrature(w["monitor"], g["lo"], g["hi"], panels=THETA_PANELS[name])
     else:
         th = O.theta(w["monitor"], g["lo"], g["hi"])
-    r = O.solve_dd(gs, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], t["steps"],
-                   mode=w["dd"].get("mode", "parallel"), theta_val=th)
+    if w.get("dd"):
+        r = O.solve_dd(gs, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], t["steps"],
+                       mode=w["dd"].get("mode", "parallel"), theta_val=th)
+    else:
+        r = O.solve_single(gs, w["monitor"], t["dt"], t["gamma"], t["steps"], theta_val=th)
     idx = sample_index(g["n"], stride, 4000, 20060146)
     vals = np.stack([r.mesh[k][tuple(idx.T)] for k in range(gs.d)], -1)
     np.savez_compressed(os.path.join(HERE, name + ".npz"), idx=idx.astype(np.int32), mesh=vals,

@@ -121,3 +121,25 @@ def test_paper_workload_full(ctx, name, prec):
     assert err <= TOL[prec]
     assert abs(st["min_det"] - float(gd["min_det"])) <= (1e-9 if prec == "fp64" else 2e-3)
     assert st["min_cell"] > 0
+
+
+@pytest.mark.parametrize("prec", ["split16", "fp64"])
+def test_sine_513_glued_dd_vs_single_domain(ctx, prec):
+    # the glued 4 x 4 mesh against the whole-domain mesh of the same problem (same gamma, dt and
+    # steps): the GPU's whole-domain mesh matches the oracle's, and the gap between the two meshes
+    # on the GPU is the oracle's gap (the decomposition error of Sec. 4.4, not a GPU artefact)
+    w = W.sine_dd()
+    ws = dict(w, dd=None)
+    gd, gs = golden("sine_dd_513"), golden("sine_single_513")
+    idx = gs["idx"]
+    assert np.array_equal(idx, gd["idx"])
+    single, st = plan_mesh(ctx, ws, prec)
+    dd, _ = plan_mesh(ctx, w, prec)
+    pick = lambda m: np.stack([m[k][tuple(idx.T)] for k in range(2)], -1)
+    err = float(np.max(np.abs(pick(single) - gs["mesh"])))
+    gap_gpu = float(np.max(np.abs(pick(dd) - pick(single))))
+    gap_oracle = float(np.max(np.abs(gd["mesh"] - gs["mesh"])))
+    print(f"sine 513 {prec}: single-domain err {err:.3e}; glued DD - single: GPU {gap_gpu:.4e}, oracle {gap_oracle:.4e}")
+    assert err <= TOL[prec]
+    assert abs(gap_gpu - gap_oracle) <= 2 * TOL[prec]
+    assert st["min_det"] > 0 and st["min_cell"] > 0
