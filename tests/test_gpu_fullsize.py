@@ -26,6 +26,11 @@ def ctx(lib):
     c.close()
 
 
+def gspec(w):
+    g = w["grid"]
+    return O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"]))
+
+
 def golden(name):
     return np.load(os.path.join(HERE, "golden", name + ".npz"))
 
@@ -143,3 +148,43 @@ def test_sine_513_glued_dd_vs_single_domain(ctx, prec):
     assert err <= TOL[prec]
     assert abs(gap_gpu - gap_oracle) <= 2 * TOL[prec]
     assert st["min_det"] > 0 and st["min_cell"] > 0
+
+
+def test_serving_stream_requests_full_size(ctx):
+    # requests of the Poisson stream itself, at their own sizes, served in a mix with their stream
+    # neighbours: the smallest 2D and 3D ones of each kind (single domain and decomposed) against
+    # the oracle; every request of the mix completes with a valid mesh
+    from paper_2006_14602_amd import binding
+    import time
+    ws = W.stream(count=2000)
+    picks = [747, 887, 1062, 1687]          # 65^2 single, 33^3 single, 258^2 2x2, 66^3 2x2x2
+    mix = picks + list(range(10))           # plus the first arrivals of the stream
+    with binding.Context(0, budget_bytes=4 << 30) as c:
+        tickets = [c.submit(ws[i], "split16") for i in mix]
+        res = {}
+        t0 = time.time()
+        while len(res) < len(mix):
+            for i, t in zip(mix, tickets):
+                if i in res:
+                    continue
+                shape = (ws[i]["grid"]["dim"],) + tuple(ws[i]["grid"]["n"])
+                state, mesh, st = c.poll(t, shape=shape)
+                if state in (binding.DONE, binding.FAILED):
+                    res[i] = (state, mesh, st)
+            assert time.time() - t0 < 240, "serving did not finish"
+            time.sleep(0.002)
+    for i in mix:
+        assert res[i][0] == binding.DONE, (i, res[i][2])
+        assert res[i][2]["min_det"] > 0 and res[i][2]["min_cell"] > 0
+    for i in picks:
+        w = ws[i]
+        t = w["time"]
+        g = gspec(w)
+        print(f"case stream request {i} n={w['grid']['n'][0]} dd={w['dd']}", flush=True)
+        if w["dd"]:
+            ref = O.solve_dd(g, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], t["steps"])
+        else:
+            ref = O.solve_single(g, w["monitor"], t["dt"], t["gamma"], t["steps"])
+        err = float(np.max(np.abs(res[i][1] - ref.mesh)))
+        print(f"stream request {i}: max mesh err {err:.3e}")
+        assert err <= TOL["split16"]
