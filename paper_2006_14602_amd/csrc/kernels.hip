@@ -909,51 +909,54 @@ constexpr int kLdsRb = 3;
 // fragments of all row blocks are requested before the first product, and the independent
 // accumulators keep the matrix cores busy.  All kLdsRb products are issued every k step (no branch
 // in the accumulator chains); the caller uses the row blocks that exist.
-template <int KIND>
-__device__ inline void mma_lbasis_rows(typename Op<KIND>::acc_t (&acc)[kLdsRb], const char* bh, const char* bl,
+template <int KIND, int NW, int RB>
+__device__ inline void mma_lbasis_rows(typename Op<KIND>::acc_t (&acc)[RB], const char* bh, const char* bl,
                                        int ldb, const char* lds, int ld, int ldo, float sc, int wave, int nrb,
                                        int l16, int g) {
   typedef Op<KIND> O;
   // a row block beyond the axis reads the last basis row (valid memory); its result is unused
-  int row[kLdsRb];
+  int row[RB];
 #pragma unroll
-  for (int t = 0; t < kLdsRb; ++t) row[t] = min((wave + 4 * t) * 16 + l16, nrb * 16 - 1);
+  for (int t = 0; t < RB; ++t) row[t] = min((wave + NW * t) * 16 + l16, nrb * 16 - 1);
   for (int k0 = 0; k0 < ld; k0 += O::KB) {
-    typename O::frag a[kLdsRb];
+    typename O::frag a[RB];
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) a[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
+    for (int t = 0; t < RB; ++t) a[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
     const typename O::frag b = O::lds_frag_cvt(lds, ldo, l16, k0, g, sc);
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) O::mma(acc[t], a[t], b);
+    for (int t = 0; t < RB; ++t) O::mma(acc[t], a[t], b);
   }
 }
 
-// acc[t] += LDS data rows x basis rows (column block wave + 4 t) of a basis copy in LDS, k outermost
-template <int KIND>
-__device__ inline void mma_rows_lbasis(typename Op<KIND>::acc_t (&acc)[kLdsRb], const char* lds, int ld, int ldo,
-                                       float sc, const char* bh, const char* bl, int ldb, int wave, int nrb, int l16,
-                                       int g) {
+// acc[t] += LDS data rows x basis rows (column block wave + NW t) of a basis copy in LDS, k
+// outermost; NW waves take RB column blocks each
+template <int KIND, int NW, int RB>
+__device__ inline void mma_rows_lbasis_w(typename Op<KIND>::acc_t (&acc)[RB], const char* lds, int ld, int ldo,
+                                         float sc, const char* bh, const char* bl, int ldb, int wave, int nrb, int l16,
+                                         int g) {
   typedef Op<KIND> O;
-  int row[kLdsRb];
+  int row[RB];
 #pragma unroll
-  for (int t = 0; t < kLdsRb; ++t) row[t] = min((wave + 4 * t) * 16 + l16, nrb * 16 - 1);
+  for (int t = 0; t < RB; ++t) row[t] = min((wave + NW * t) * 16 + l16, nrb * 16 - 1);
   for (int k0 = 0; k0 < ld; k0 += O::KB) {
-    typename O::frag b[kLdsRb];
+    typename O::frag b[RB];
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) b[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
+    for (int t = 0; t < RB; ++t) b[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
     const typename O::frag a = O::lds_frag_cvt(lds, ldo, l16, k0, g, sc);
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) O::mma(acc[t], a, b[t]);
+    for (int t = 0; t < RB; ++t) O::mma(acc[t], a, b[t]);
   }
 }
 
+
 // Copy `bytes` (a multiple of 16) from global memory into LDS with direct-to-LDS loads, which
-// need no registers and are all in flight together: wave w copies the 1 KiB chunks w, w + 4, ..,
+// need no registers and are all in flight together: wave w of nwaves copies the 1 KiB chunks w,
+// w + nwaves, ..,
 // lane l bytes [16 l, 16 l + 16) of a chunk.  Complete after vmem_drain() and a barrier.
-__device__ inline void lds_dma(char* dst, const void* src, int bytes) {
+__device__ inline void lds_dma(char* dst, const void* src, int bytes, int nwaves = 4) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  for (int ch = wave; ch * 1024 < bytes; ch += 4)
+  for (int ch = wave; ch * 1024 < bytes; ch += nwaves)
     if (ch * 1024 + lane * 16 < bytes)
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)((const char*)src + ch * 1024 + lane * 16),
                                        (__attribute__((address_space(3))) void*)(dst + ch * 1024), 16, 0, 0);
@@ -1005,27 +1008,28 @@ __device__ inline float stage_rows16(char* lds, int ld, int ldo, const gmem<type
 
 // Stage the 16-column strip [col0, col0 + 16) of a row-major K x ncol array transposed into LDS
 // (operand row c = strip column, k = index along the axis, row stride ldo; zero beyond K and
-// ncol); returns this thread's largest magnitude.  Thread t takes column t % 16 and rows
-// t / 16 + 16 j; twelve loads are in flight per batch.
-template <int KIND>
+// ncol); returns this thread's largest magnitude.  With NTH threads, thread t takes column t % 16
+// and rows t / 16 + (NTH / 16) j; 192 rows are in flight per batch.
+template <int KIND, int NTH = 256>
 __device__ inline float stage_strip16(char* lds, int ld, int ldo, const gmem<typename Op<KIND>::T>* src, int K,
                                       int ncol, int col0) {
   typedef Op<KIND> O;
   typedef typename O::T T;
-  constexpr int B = 12;
+  constexpr int RS = NTH / 16;       // rows per pass
+  constexpr int B = 192 / RS;        // loads in flight per thread per batch (192 rows per batch)
   const int c = threadIdx.x & 15, k0 = threadIdx.x >> 4;
   const bool cok = col0 + c < ncol;
   float amax = 0.f;
-  for (int kb = 0; kb < ld; kb += 16 * B) {
+  for (int kb = 0; kb < ld; kb += RS * B) {
     T v[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      const int k = kb + k0 + 16 * j;
+      const int k = kb + k0 + RS * j;
       v[j] = (cok && k < K) ? src[(long)k * ncol + col0 + c] : T(0);
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      const int k = kb + k0 + 16 * j;
+      const int k = kb + k0 + RS * j;
       if (k < ld) {
         O::put(lds, ldo, c, k, v[j]);
         if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j]));
@@ -1046,6 +1050,22 @@ __device__ inline float tile_scale(float amax, float* red) {
   if (!(m > 0.f) || !isfinite(m)) return 1.f;
   int e;
   frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  return ldexpf(1.f, 14 - e);
+}
+
+// tile_scale for a workgroup of NW waves (red holds NW floats)
+template <int NW>
+__device__ inline float tile_scale_w(float amax, float* red) {
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  float m = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) m = fmaxf(m, red[w]);
+  __syncthreads();
+  if (!(m > 0.f) || !isfinite(m)) return 1.f;
+  int e;
+  frexpf(m, &e);
   return ldexpf(1.f, 14 - e);
 }
 
@@ -1220,6 +1240,10 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   }
 }
 
+// NW waves per workgroup: latency-bound launches (one workgroup per compute unit or fewer) take 8,
+// so each wave's chain of row blocks, which is the launch's duration, is halved; launches of many
+// strips take 4, which keeps more workgroups resident per compute unit.
+
 // 16-column strip of the [n_axis][rest] view (axis 0), or of one [n1][n2] slab (axis 1, 3D;
 // tile.y = slab index i0).  src / dst: 0 = F, 1 = T.
 //   PAIR = false: dst = Bas * src, Bas the forward (inv = 0) or inverse (inv = 1) basis
@@ -1230,12 +1254,13 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
 // The pair then reuses the forward matrix for the inverse: with D = diag(w) (w = 1/2 at both ends,
 // else 1) the DCT-I matrices satisfy B = (N / 2) D^-1 A D^-1, and the powers of two D^-1 and N / 2
 // fold exactly into the spectral scale and the store.
-template <int KIND, bool PAIR>
-__global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
-                                                    int src_sel, int lcap, StepArgs sa) {
+template <int KIND, bool PAIR, int NW>
+__global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
+                                                        int src_sel, int lcap, StepArgs sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
-  constexpr int MAXRB = 9;  // row blocks per wave: n <= 9 * 4 * 16 = 576
+  constexpr int MAXRB = (36 + NW - 1) / NW;       // row blocks per wave: n <= 36 * 16 = 576
+  constexpr int RBL = (4 * kLdsRb + NW - 1) / NW;  // the same with the basis in LDS (n <= 192)
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int tix = xcd_tile();
   if (tix >= ntiles) return;
@@ -1256,7 +1281,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   const int col0 = tl.z;
   const gmem<T>* __restrict__ src = gp<T>(src_sel ? S.T : S.F) + base;
   gmem<T>* __restrict__ dst = gpw<T>(src_sel ? S.F : S.T) + base;
-  __shared__ float red[4];
+  __shared__ float red[NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
   const int uwave = __builtin_amdgcn_readfirstlane(wave);  // the same, known uniform
   const int nrb = (K + 15) >> 4;
@@ -1268,11 +1293,12 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
   const int dbytes = 16 * ldo * O::LDS_BYTES;
   const int bbytes = nrb * 16 * ldb * (O::BASIS_BYTES / (O::SCALED ? 2 : 1));
   const bool lbasis = nrb <= 4 * kLdsRb && dbytes + (O::SCALED ? 2 : 1) * bbytes <= lcap;
+  static_assert(RBL <= MAXRB, "LDS-basis row blocks fit the accumulators");
   char* lbh = lds + dbytes;
   char* lbl = lbh + bbytes;
   if (lbasis) {
-    lds_dma(lbh, b1h, bbytes);
-    if (O::SCALED) lds_dma(lbl, b1l, bbytes);
+    lds_dma(lbh, b1h, bbytes, NW);
+    if (O::SCALED) lds_dma(lbl, b1l, bbytes, NW);
   }
   // PAIR: spectral factors of this lane's coefficients, requested before the products
   T sig0[PAIR ? MAXRB * 4 : 1];
@@ -1291,13 +1317,13 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t)
       for (int q = 0; q < 4; ++q) {
-        const int i = (wave + 4 * t) * 16 + O::crow(g, q);
+        const int i = (wave + NW * t) * 16 + O::crow(g, q);
         sig0[t * 4 + q] = i < K ? s0[i] : T(0);
       }
   }
   // strip transposed into LDS: operand row c = strip column, k = index along the axis
-  const float amax = stage_strip16<KIND>(lds, ld, ldo, src, K, ncol, col0);
-  const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
+  const float amax = stage_strip16<KIND, 64 * NW>(lds, ld, ldo, src, K, ncol, col0);
+  const float sc = O::SCALED ? tile_scale_w<NW>(amax, red) : 1.f;
   if (lbasis) vmem_drain();
   __syncthreads();
   if (O::SCALED && !lbasis) {  // the LDS-basis products split each fragment on the fly
@@ -1309,23 +1335,23 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
 #pragma unroll
   for (int t = 0; t < MAXRB; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
   if (lbasis) {
-    typename O::acc_t a3[kLdsRb];
+    typename O::acc_t a3[RBL];
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
-    mma_lbasis_rows<KIND>(a3, lbh, lbl, ldb, lds, ld, ldo, sc, uwave, nrb, l16, g);
+    for (int t = 0; t < RBL; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
+    mma_lbasis_rows<KIND, NW, RBL>(a3, lbh, lbl, ldb, lds, ld, ldo, sc, uwave, nrb, l16, g);
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) acc[t] = a3[t];
+    for (int t = 0; t < RBL; ++t) acc[t] = a3[t];
   } else {
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
-      const int rb = wave + 4 * t;
+      const int rb = wave + NW * t;
       if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, ld, ldo, sc, rb * 16 + l16, l16, g);
     }
   }
   if constexpr (!PAIR) {
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
-      const int rb = wave + 4 * t;
+      const int rb = wave + NW * t;
       if (rb >= nrb) continue;
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
@@ -1338,7 +1364,7 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
     const T g0 = T(S.gh2[0]);
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
-      const int rb = wave + 4 * t;
+      const int rb = wave + NW * t;
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
         T y = T(0);
@@ -1355,16 +1381,16 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
     float ymax = 0.f;
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
-      const int rb = wave + 4 * t;
+      const int rb = wave + NW * t;
       if (rb >= nrb) continue;
       for (int q = 0; q < 4; ++q) {
         O::put(lds, ldo, l16, rb * 16 + O::crow(g, q), acc[t][q]);
         if (O::SCALED) ymax = fmaxf(ymax, fabsf((float)acc[t][q]));
       }
     }
-    const float sy = O::SCALED ? tile_scale(ymax, red) : 1.f;
+    const float sy = O::SCALED ? tile_scale_w<NW>(ymax, red) : 1.f;
     // zero the padding rows nrb*16 .. ld of the operand
-    for (int idx = threadIdx.x; idx < 16 * (ld - nrb * 16); idx += 256) {
+    for (int idx = threadIdx.x; idx < 16 * (ld - nrb * 16); idx += 64 * NW) {
       const int k = nrb * 16 + idx / 16, cc = idx & 15;
       O::put(lds, ldo, cc, k, T(0));
     }
@@ -1379,22 +1405,22 @@ __global__ __launch_bounds__(256) void strip_kernel(const int4* __restrict__ til
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
     if (lbasis) {
-      typename O::acc_t a3[kLdsRb];
+      typename O::acc_t a3[RBL];
 #pragma unroll
-      for (int t = 0; t < kLdsRb; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
-      mma_lbasis_rows<KIND>(a3, lbh, lbl, ldb, lds, ld, ldo, sy, uwave, nrb, l16, g);
+      for (int t = 0; t < RBL; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
+      mma_lbasis_rows<KIND, NW, RBL>(a3, lbh, lbl, ldb, lds, ld, ldo, sy, uwave, nrb, l16, g);
 #pragma unroll
-      for (int t = 0; t < kLdsRb; ++t) acc[t] = a3[t];
+      for (int t = 0; t < RBL; ++t) acc[t] = a3[t];
     } else {
 #pragma unroll
       for (int t = 0; t < MAXRB; ++t) {
-        const int rb = wave + 4 * t;
+        const int rb = wave + NW * t;
         if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], A.inv, A.invl, ldb, lds, ld, ldo, sy, rb * 16 + l16, l16, g);
       }
     }
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
-      const int rb = wave + 4 * t;
+      const int rb = wave + NW * t;
       if (rb >= nrb) continue;
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
@@ -1685,6 +1711,11 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
 
 constexpr int kFuseMaxLd = 320;           // widest last axis (padded) the fused kernel takes
 constexpr int kFuseU = kFuseMaxLd / 64;   // column groups per lane
+// Eight waves per workgroup: at the sizes where this kernel is latency-bound (one workgroup per
+// compute unit) two waves per SIMD hide each other's LDS and transcendental latencies in the
+// stencil, and the product's column blocks spread over twice as many waves.
+constexpr int kFuseWaves = 8;
+constexpr int kFuseRb = (4 * kLdsRb + kFuseWaves - 1) / kFuseWaves;  // LDS-basis column blocks per wave
 
 // LDS layout of the fused kernel: operand [16][ld + OPAD] | halo [18][ld + 4] (rounded to 1 KiB)
 // | basis copy (rows of stride ldb)
@@ -1706,8 +1737,8 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K, c
   const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int rr = wave + 4 * k, i = row0 + rr;
+  for (int k = 0; k < 16 / kFuseWaves; ++k) {
+    const int rr = wave + kFuseWaves * k, i = row0 + rr;
     const bool rlive = i < n0 && !is_artificial(K.art, 0, i, n0);
     const T x0b = K.a0 + T(K.off0 + i) * h0;
 #pragma unroll
@@ -1736,12 +1767,13 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K, c
 
 // tile = (sub, row0, 0, 0)
 template <int KIND>
-__global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restrict__ tiles, int ntiles, int lcap,
-                                                           StepArgs sa) {
+__global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int4* __restrict__ tiles, int ntiles,
+                                                                       int lcap, StepArgs sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
+  constexpr int NW = kFuseWaves;
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  __shared__ float red[4];
+  __shared__ float red[NW];
   const int tix = xcd_tile();
   if (tix >= ntiles) return;
   const int4 tl = tiles[tix];
@@ -1762,18 +1794,19 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
   const bool lbasis =
       nrb <= 4 * kLdsRb && 16 * ldo * O::LDS_BYTES + fused_halo_bytes<KIND>(ld) + (O::SCALED ? 2 : 1) * bbytes <= lcap;
   if (lbasis) {
-    lds_dma(lbh, A.fwd, bbytes);
-    if (O::SCALED) lds_dma(lbl, A.fwdl, bbytes);
+    lds_dma(lbh, A.fwd, bbytes, NW);
+    if (O::SCALED) lds_dma(lbl, A.fwdl, bbytes, NW);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
-  // halo rows row0 - 1 .. row0 + 16, columns -1 .. n1 (mirror ghosts): wave w rows w + 4 k, lane
+  // halo rows row0 - 1 .. row0 + 16, columns -1 .. n1 (mirror ghosts): wave w rows w + NW k, lane
   // columns lane + 64 u, all loads in flight before the first LDS write
   {
+    constexpr int HR = (18 + NW - 1) / NW;  // halo rows per wave
     const gmem<T>* phi = (const gmem<T>*)phi_;
-    T v[5][kFuseU];
+    T v[HR][kFuseU];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int r = wave + 4 * k;
+    for (int k = 0; k < HR; ++k) {
+      const int r = wave + NW * k;
       const gmem<T>* row = phi + (long)mirror_clamp(row0 + r - 1, n0) * n1;
 #pragma unroll
       for (int u = 0; u < kFuseU; ++u) {
@@ -1782,8 +1815,8 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
       }
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int r = wave + 4 * k;
+    for (int k = 0; k < HR; ++k) {
+      const int r = wave + NW * k;
 #pragma unroll
       for (int u = 0; u < kFuseU; ++u) {
         const int c = lane + 64 * u;
@@ -1804,7 +1837,7 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
     case MON_ARC_SPHERES: fused_nodes2<KIND, MON_ARC_SPHERES>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
     default: fused_nodes2<KIND, MON_SEPARABLE>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
   }
-  const float sc = O::SCALED ? tile_scale(amax, red) : 1.f;
+  const float sc = O::SCALED ? tile_scale_w<NW>(amax, red) : 1.f;
   if (lbasis) vmem_drain();
   __syncthreads();
   if (O::SCALED && !lbasis) {  // the LDS-basis products split each fragment on the fly
@@ -1813,27 +1846,28 @@ __global__ __launch_bounds__(256) void stencil_fwd2_kernel(const int4* __restric
   }
   gmem<T>* out = gpw<T>(S.T);
   const T us = T(A.fwd_unscale) / T(sc);
-  constexpr int NT = (kFuseMaxLd / 16 + 3) / 4;
+  constexpr int NT = (kFuseMaxLd / 16 + NW - 1) / NW;
   typename O::acc_t acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
   if (lbasis) {
-    typename O::acc_t a3[kLdsRb];
+    typename O::acc_t a3[kFuseRb];
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
-    mma_rows_lbasis<KIND>(a3, op, ld, ldo, sc, lbh, lbl, ldb, __builtin_amdgcn_readfirstlane(wave), nrb, l16, g);
+    for (int t = 0; t < kFuseRb; ++t) a3[t] = typename O::acc_t{0, 0, 0, 0};
+    mma_rows_lbasis_w<KIND, NW, kFuseRb>(a3, op, ld, ldo, sc, lbh, lbl, ldb, __builtin_amdgcn_readfirstlane(wave),
+                                         nrb, l16, g);
 #pragma unroll
-    for (int t = 0; t < kLdsRb; ++t) acc[t] = a3[t];
+    for (int t = 0; t < kFuseRb; ++t) acc[t] = a3[t];
   } else {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int cb = wave + 4 * t;
+      const int cb = wave + NW * t;
       if (cb < nrb) mma_lds_by_basis<KIND>(acc[t], op, ld, ldo, sc, A.fwd, A.fwdl, ldb, cb * 16 + l16, l16, g);
     }
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int cb = wave + 4 * t;
+    const int cb = wave + NW * t;
     if (cb >= nrb) break;
     const int c = cb * 16 + l16;
     for (int q = 0; q < 4; ++q) {
@@ -2187,11 +2221,11 @@ hipError_t launch_stencil_fwd2(int prec, const int4* tiles, int ntiles, int lnee
   if (ntiles <= 0) return hipSuccess;
   const size_t sh = (size_t)lneed;
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_F64>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, lneed, sa);
+    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_F64>, dim3(ntiles), dim3(64 * kFuseWaves), sh, s, tiles, ntiles, lneed, sa);
   else if (prec == PREC_F32)
-    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_F32>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, lneed, sa);
+    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_F32>, dim3(ntiles), dim3(64 * kFuseWaves), sh, s, tiles, ntiles, lneed, sa);
   else
-    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_SPLIT16>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, lneed, sa);
+    hipLaunchKernelGGL(stencil_fwd2_kernel<PREC_SPLIT16>, dim3(ntiles), dim3(64 * kFuseWaves), sh, s, tiles, ntiles, lneed, sa);
   return hipGetLastError();
 }
 
@@ -2211,8 +2245,16 @@ hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int 
   if (ntiles <= 0) return hipSuccess;
   const size_t sh = std::max<size_t>(op_lds(prec, maxld), (size_t)lneed);
   const int lcap = (int)sh;
-#define PMA_STRIP(K, P) \
-  hipLaunchKernelGGL((strip_kernel<K, P>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, axis, inv, src_sel, lcap, sa)
+  const bool eight = ntiles <= 512;  // latency-bound: at most two workgroups per compute unit
+#define PMA_STRIP(K, P)                                                                                         \
+  do {                                                                                                          \
+    if (eight)                                                                                                  \
+      hipLaunchKernelGGL((strip_kernel<K, P, 8>), dim3(ntiles), dim3(512), sh, s, tiles, ntiles, axis, inv,     \
+                         src_sel, lcap, sa);                                                                    \
+    else                                                                                                        \
+      hipLaunchKernelGGL((strip_kernel<K, P, 4>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, axis, inv,     \
+                         src_sel, lcap, sa);                                                                    \
+  } while (0)
   if (prec == PREC_F64) {
     if (pair) PMA_STRIP(PREC_F64, true); else PMA_STRIP(PREC_F64, false);
   } else if (prec == PREC_F32) {
@@ -2249,9 +2291,12 @@ hipError_t enable_large_lds() {
     const void* ks[] = {(const void*)fwd_last_kernel<PREC_F64>, (const void*)fwd_last_kernel<PREC_F32>,
                         (const void*)fwd_last_kernel<PREC_SPLIT16>, (const void*)inv_last_kernel<PREC_F64>,
                         (const void*)inv_last_kernel<PREC_F32>, (const void*)inv_last_kernel<PREC_SPLIT16>,
-                        (const void*)strip_kernel<PREC_F64, true>, (const void*)strip_kernel<PREC_F64, false>,
-                        (const void*)strip_kernel<PREC_F32, true>, (const void*)strip_kernel<PREC_F32, false>,
-                        (const void*)strip_kernel<PREC_SPLIT16, true>, (const void*)strip_kernel<PREC_SPLIT16, false>,
+                        (const void*)strip_kernel<PREC_F64, true, 4>, (const void*)strip_kernel<PREC_F64, false, 4>,
+                        (const void*)strip_kernel<PREC_F32, true, 4>, (const void*)strip_kernel<PREC_F32, false, 4>,
+                        (const void*)strip_kernel<PREC_SPLIT16, true, 4>, (const void*)strip_kernel<PREC_SPLIT16, false, 4>,
+                        (const void*)strip_kernel<PREC_F64, true, 8>, (const void*)strip_kernel<PREC_F64, false, 8>,
+                        (const void*)strip_kernel<PREC_F32, true, 8>, (const void*)strip_kernel<PREC_F32, false, 8>,
+                        (const void*)strip_kernel<PREC_SPLIT16, true, 8>, (const void*)strip_kernel<PREC_SPLIT16, false, 8>,
                         (const void*)stencil_fwd2_kernel<PREC_F64>, (const void*)stencil_fwd2_kernel<PREC_F32>,
                         (const void*)stencil_fwd2_kernel<PREC_SPLIT16>, (const void*)strip4_kernel<PREC_F32, true>,
                         (const void*)strip4_kernel<PREC_F32, false>, (const void*)strip4_kernel<PREC_SPLIT16, true>,
