@@ -679,6 +679,19 @@ __device__ inline double block_sum256(double v, double* red) {
   return r;
 }
 
+// block_sum256 for a workgroup of NW waves (red holds NW doubles); NW = 4 adds in the same order
+template <int NW>
+__device__ inline double block_sum_w(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double r = (red[0] + red[1]) + (red[2] + red[3]);
+  if (NW == 8) r += (red[4] + red[5]) + (red[6] + red[7]);
+  __syncthreads();
+  return r;
+}
+
 __device__ inline double block_min256(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
   const int w = threadIdx.x >> 6;
@@ -861,24 +874,31 @@ template <> struct Op<PREC_F64> {
 // of the axis multiplies a zero basis fragment with valid data, so the accumulator chain has no
 // branch (a conditional product would make the compiler copy the accumulator out and back,
 // waiting for each product to finish).
+// (over the k range [kb, ke), kb a multiple of the k step)
 template <int KIND>
-__device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, int ldo, float sc,
-                                        const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
+__device__ inline void mma_lds_by_basis_k(typename Op<KIND>::acc_t& acc, const char* lds, int kb, int ke, int ldo,
+                                          float sc, const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
   typedef Op<KIND> O;
   constexpr int U = 4;
-  for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
+  for (int k0 = kb; k0 < ke; k0 += U * O::KB) {
     typename O::frag b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * O::KB;
-      b[u] = k < ld ? O::glob_frag(bh, bl, ldb, brow, k, g) : O::zero_frag();
+      b[u] = k < ke ? O::glob_frag(bh, bl, ldb, brow, k, g) : O::zero_frag();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * O::KB;
-      O::mma(acc, O::lds_frag(lds, ldo, l16, k < ld ? k : k0, g, sc), b[u]);
+      O::mma(acc, O::lds_frag(lds, ldo, l16, k < ke ? k : k0, g, sc), b[u]);
     }
   }
+}
+
+template <int KIND>
+__device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, int ldo, float sc,
+                                        const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
+  mma_lds_by_basis_k<KIND>(acc, lds, 0, ld, ldo, sc, bh, bl, ldb, brow, l16, g);
 }
 
 template <int KIND>
@@ -966,22 +986,23 @@ constexpr int kMaxLd = 576;            // widest padded axis (9 row blocks of 64
 constexpr int kColU = kMaxLd / 64;      // column loads per row and lane
 
 // Stage rows [row0, row0 + 16) x columns [0, ld) of a row-major R x C array into LDS as the data
-// operand (row stride ldo; zero beyond R and C); returns this thread's largest magnitude.  Wave w
-// takes rows w + 4 j, lane l columns l + 64 u; the loads of two rows are issued before any is
-// used, so a tile costs two memory round trips rather than one per element.
-template <int KIND>
+// operand (row stride ldo; zero beyond R and C); returns this thread's largest magnitude.  With NW
+// waves, wave w takes rows w + NW j, lane l columns l + 64 u; the loads of two rows are issued
+// before any is used, so a tile costs 8 / NW memory round trips rather than one per element.
+template <int KIND, int NW = 4>
 __device__ inline float stage_rows16(char* lds, int ld, int ldo, const gmem<typename Op<KIND>::T>* src, int row0,
                                      int R, int C) {
   typedef Op<KIND> O;
   typedef typename O::T T;
+  static_assert(NW == 4 || NW == 8, "16 rows over 4 or 8 waves");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float amax = 0.f;
 #pragma unroll
-  for (int jp = 0; jp < 2; ++jp) {
+  for (int jp = 0; jp < 8 / NW; ++jp) {
     T v[2][kColU];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int r = wave + 4 * (2 * jp + j);
+      const int r = wave + NW * (2 * jp + j);
       const bool rok = row0 + r < R;
       const gmem<T>* rp = src + (long)(rok ? row0 + r : 0) * C;
 #pragma unroll
@@ -992,7 +1013,7 @@ __device__ inline float stage_rows16(char* lds, int ld, int ldo, const gmem<type
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int r = wave + 4 * (2 * jp + j);
+      const int r = wave + NW * (2 * jp + j);
 #pragma unroll
       for (int u = 0; u < kColU; ++u) {
         const int k = lane + 64 * u;
@@ -1147,15 +1168,24 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 // In an alternating sweep a destination that is updated later in the same step has not removed
 // this step's shift yet: later = 1 entries add dt * shift back, so every subdomain sees its
 // neighbours' values relative to the same constant.
-template <int KIND>
-__global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
-                                                       const int* __restrict__ push_first,
-                                                       const int4* __restrict__ push, StepArgs sa) {
+// NW = 4: wave w computes column block w over the whole axis.  NW = 8 (launches of few tiles,
+// where a wave's chain of dependent basis loads is the launch's duration): waves w and w + 4 take
+// the two halves of the contraction for column block w, and wave w adds its partner's half
+// through LDS before the update.
+template <int KIND, int NW>
+__global__ __launch_bounds__(64 * NW) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
+                                                           const int* __restrict__ push_first,
+                                                           const int4* __restrict__ push, StepArgs sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
+  typedef typename O::acc_t acc_t;
+  static_assert(NW == 4 || NW == 8, "four column blocks, one or two waves each");
+  constexpr int KS = NW / 4;  // waves per column block
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  __shared__ double red[4];
+  __shared__ double red[NW];
+  __shared__ float redf[NW];
   __shared__ T stash[16][64];
+  __shared__ acc_t xch[KS > 1 ? 4 : 1][64];
   const int tix = xcd_tile();
   if (tix >= ntiles) return;
   const int4 tl = tiles[tix];
@@ -1167,18 +1197,19 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const AxisDev& A = S.ax[la];
   const int ld = A.ld;
   const int row0 = tl.y, col0 = tl.z;
-  __shared__ float redf[4];
   const gmem<T>* __restrict__ src = gp<T>(S.F);
   const int ldo = ld + O::OPAD;
-  const float amax = stage_rows16<KIND>(lds, ld, ldo, src, row0, R, C);
-  const float sc = O::SCALED ? tile_scale(amax, redf) : 1.f;
+  const float amax = stage_rows16<KIND, NW>(lds, ld, ldo, src, row0, R, C);
+  const float sc = O::SCALED ? tile_scale_w<NW>(amax, redf) : 1.f;
   __syncthreads();
   if (O::SCALED) {
     O::presplit(lds, ldo, 16, ld, &sc, 16);
     __syncthreads();
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
-  const int cb = (col0 >> 4) + wave;
+  const int cw = wave & 3, kh = wave >> 2;  // column block within the tile; half of the contraction
+  const int cb = (col0 >> 4) + cw;
+  const bool active = cb * 16 < C;
   const T shift = instance_shift<T>(sa, I);
   const T dt = T(I.dt);
   const T isc = T(1) / T(sc);
@@ -1186,18 +1217,33 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
   const int inst = S.inst;
   const int pf0 = push_first[tix], pf1 = push_first[tix + 1];
-  double part = 0.0;
-  if (cb * 16 < C) {
-    gmem<T>* __restrict__ phi = gpw<T>(S.phi);
-    const int c = cb * 16 + l16;
+  // first half: the first ceil(steps / 2) k steps
+  const int ksplit = KS > 1 ? min(ld, ((ld + 2 * O::KB - 1) / (2 * O::KB)) * O::KB) : ld;
+  gmem<T>* __restrict__ phi = gpw<T>(S.phi);
+  const int c = cb * 16 + l16;
+  acc_t acc = {0, 0, 0, 0};
+  T old[4];
+  if (active) {
     // the update's phi values are requested before the product so their latency overlaps it
-    T old[4];
-    for (int q = 0; q < 4; ++q) {
-      const int r = row0 + O::crow(g, q);
-      old[q] = (r < R && c < C) ? phi[(long)r * C + c] : T(0);
+    if (kh == 0) {
+      for (int q = 0; q < 4; ++q) {
+        const int r = row0 + O::crow(g, q);
+        old[q] = (r < R && c < C) ? phi[(long)r * C + c] : T(0);
+      }
     }
-    typename O::acc_t acc = {0, 0, 0, 0};
-    mma_lds_by_basis<KIND>(acc, lds, ld, ldo, sc, A.inv, A.invl, A.ldb, cb * 16 + l16, l16, g);
+    mma_lds_by_basis_k<KIND>(acc, lds, kh ? ksplit : 0, kh ? ld : ksplit, ldo, sc, A.inv, A.invl, A.ldb, c, l16,
+                             g);
+  }
+  if (KS > 1) {
+    if (kh == 1 && active) xch[cw][lane] = acc;
+    __syncthreads();
+  }
+  double part = 0.0;
+  if (kh == 0 && active) {
+    if (KS > 1) {
+      const acc_t o = xch[cw][lane];
+      for (int q = 0; q < 4; ++q) acc[q] += o[q];
+    }
     bool bad = false;
     for (int q = 0; q < 4; ++q) {
       const int r = row0 + O::crow(g, q);
@@ -1216,7 +1262,7 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
           const T u = dt * val;
           const T nv = old[q] + dt * (val - shift);
           phi[(long)r * C + c] = nv;
-          if (pf1 > pf0) stash[O::crow(g, q)][wave * 16 + l16] = nv;
+          if (pf1 > pf0) stash[O::crow(g, q)][cw * 16 + l16] = nv;
           part += w * (double)u * (double)u;
           bad |= !finite_(u);
         }
@@ -1226,14 +1272,14 @@ __global__ __launch_bounds__(256) void inv_last_kernel(const int4* __restrict__ 
   }
   if (pf1 > pf0) {
     __syncthreads();
-    for (int e = pf0 + (int)threadIdx.x; e < pf1; e += 256) {
+    for (int e = pf0 + (int)threadIdx.x; e < pf1; e += 64 * NW) {
       const int4 P = push[e];
       T v = stash[P.z & 0xFF][P.w];
       if (P.z >> 8) v += dt * shift;
       gpw<T>(sa.subs[P.x].phi)[P.y] = v;
     }
   }
-  const double tot = block_sum256(part, red);
+  const double tot = block_sum_w<NW>(part, red);
   if (threadIdx.x == 0) {
     sa.partials[part_base + tix] = tot * hs;
     if (I.pin && tl.x == I.first_sub && row0 == 0 && col0 == 0) sa.shift_acc[inst] += (double)dt * (double)shift;
@@ -2204,8 +2250,16 @@ hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, i
                            const int4* push, const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const size_t sh = op_lds(prec, maxld);
-#define PMA_INV(K) \
-  hipLaunchKernelGGL(inv_last_kernel<K>, dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, push_first, push, sa)
+  const bool eight = ntiles <= 512;  // latency-bound: at most two workgroups per compute unit
+#define PMA_INV(K)                                                                                                    \
+  do {                                                                                                                \
+    if (eight)                                                                                                        \
+      hipLaunchKernelGGL((inv_last_kernel<K, 8>), dim3(ntiles), dim3(512), sh, s, tiles, ntiles, part_base,          \
+                         push_first, push, sa);                                                                       \
+    else                                                                                                              \
+      hipLaunchKernelGGL((inv_last_kernel<K, 4>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base,          \
+                         push_first, push, sa);                                                                       \
+  } while (0)
   if (prec == PREC_F64)
     PMA_INV(PREC_F64);
   else if (prec == PREC_F32)
@@ -2289,8 +2343,10 @@ hipError_t enable_large_lds() {
     const int lim = 160 * 1024 - 4096;
     hipError_t e = hipSuccess;
     const void* ks[] = {(const void*)fwd_last_kernel<PREC_F64>, (const void*)fwd_last_kernel<PREC_F32>,
-                        (const void*)fwd_last_kernel<PREC_SPLIT16>, (const void*)inv_last_kernel<PREC_F64>,
-                        (const void*)inv_last_kernel<PREC_F32>, (const void*)inv_last_kernel<PREC_SPLIT16>,
+                        (const void*)fwd_last_kernel<PREC_SPLIT16>, (const void*)inv_last_kernel<PREC_F64, 4>,
+                        (const void*)inv_last_kernel<PREC_F32, 4>, (const void*)inv_last_kernel<PREC_SPLIT16, 4>,
+                        (const void*)inv_last_kernel<PREC_F64, 8>, (const void*)inv_last_kernel<PREC_F32, 8>,
+                        (const void*)inv_last_kernel<PREC_SPLIT16, 8>,
                         (const void*)strip_kernel<PREC_F64, true, 4>, (const void*)strip_kernel<PREC_F64, false, 4>,
                         (const void*)strip_kernel<PREC_F32, true, 4>, (const void*)strip_kernel<PREC_F32, false, 4>,
                         (const void*)strip_kernel<PREC_SPLIT16, true, 4>, (const void*)strip_kernel<PREC_SPLIT16, false, 4>,
