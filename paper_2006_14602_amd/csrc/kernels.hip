@@ -1132,14 +1132,25 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
 
 // shift removed from phi each step: mean of the DC coefficient over the instance's first I.pin
 // subdomains (all of them in the parallel form; the first one, which opens every sweep, in the
-// alternating forms, so that every subdomain of a sweep removes the same constant)
+// alternating forms, so that every subdomain of a sweep removes the same constant).
+// The coefficients are summed across a wave: lane l adds those of subdomains l, l + 64, .. in that
+// order, then a butterfly adds the lanes, which leaves the same bits in every lane, wave and
+// workgroup.  dc_first_load requests the first of them early (before the tile is staged), so that
+// round trip overlaps the staging instead of following it.
 template <typename T>
-__device__ inline T instance_shift(const StepArgs& sa, const InstDev& I) {
-  if (!I.pin) return T(0);
+__device__ inline T dc_first_load(const StepArgs& sa, int pin, int first_sub) {
+  return pin ? gp<T>(sa.dc)[first_sub + min((int)threadIdx.x & 63, pin - 1)] : T(0);
+}
+
+template <typename T>
+__device__ inline T instance_shift(const StepArgs& sa, int pin, int first_sub, T d0) {
+  if (!pin) return T(0);
+  const int lane = threadIdx.x & 63;
   const gmem<T>* dc = gp<T>(sa.dc);
-  T s = T(0);
-  for (int q = 0; q < I.pin; ++q) s += dc[I.first_sub + q];
-  return s / T(I.pin);
+  T s = lane < pin ? d0 : T(0);
+  for (int q = lane + 64; q < pin; q += 64) s += dc[first_sub + q];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s / T(pin);
 }
 
 // shape and artificial faces of a subdomain, copied into registers (stores to the state arrays
@@ -1161,8 +1172,9 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 
 // inverse transform along the last axis for 16 rows x up to 64 columns, fused with the update
 // phi += dt (delta - shift) and the residual partial sum.  Input: F.
-// Push transmission: push_first[tile] .. push_first[tile + 1] index the entries (dst sub, dst
-// node, row | later << 8, column within the tile) of push[] whose source node lies in the tile;
+// Push transmission: push_first[tile] .. push_first[tile + 1] index the entries (destination
+// node's device address as low and high words, row | later << 8, column within the tile) of
+// push[] whose source node lies in the tile;
 // after the update each such node's new value is written into the artificial node of the other
 // subdomain, which is the owner's value the transmission condition gives it for the next step.
 // In an alternating sweep a destination that is updated later in the same step has not removed
@@ -1172,8 +1184,10 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 // where a wave's chain of dependent basis loads is the launch's duration): waves w and w + 4 take
 // the two halves of the contraction for column block w, and wave w adds its partner's half
 // through LDS before the update.
+// (four waves: at least seven workgroups per compute unit, which the register budget allows, for
+// the launches of many tiles that take this form)
 template <int KIND, int NW>
-__global__ __launch_bounds__(64 * NW) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
                                                            const int* __restrict__ push_first,
                                                            const int4* __restrict__ push, StepArgs sa) {
   typedef Op<KIND> O;
@@ -1199,6 +1213,19 @@ __global__ __launch_bounds__(64 * NW) void inv_last_kernel(const int4* __restric
   const int row0 = tl.y, col0 = tl.z;
   const gmem<T>* __restrict__ src = gp<T>(S.F);
   const int ldo = ld + O::OPAD;
+  // every descriptor field is read into registers before the first barrier: later reads could not
+  // use the scalar cache and would wait for all earlier vector memory operations
+  const T dt = T(I.dt);
+  const int pin = I.pin, first_sub = I.first_sub;
+  const BoxReg box = box_of(S);
+  const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
+  const int inst = S.inst;
+  const void* invh = A.inv;
+  const void* invl = A.invl;
+  const int ldb = A.ldb;
+  gmem<T>* __restrict__ phi = gpw<T>(S.phi);
+  const int pf0 = push_first[tix], pf1 = push_first[tix + 1];
+  const T d0 = dc_first_load<T>(sa, pin, first_sub);
   const float amax = stage_rows16<KIND, NW>(lds, ld, ldo, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale_w<NW>(amax, redf) : 1.f;
   __syncthreads();
@@ -1210,16 +1237,9 @@ __global__ __launch_bounds__(64 * NW) void inv_last_kernel(const int4* __restric
   const int cw = wave & 3, kh = wave >> 2;  // column block within the tile; half of the contraction
   const int cb = (col0 >> 4) + cw;
   const bool active = cb * 16 < C;
-  const T shift = instance_shift<T>(sa, I);
-  const T dt = T(I.dt);
   const T isc = T(1) / T(sc);
-  const BoxReg box = box_of(S);
-  const double hs = S.h[0] * S.h[1] * (S.dim == 3 ? S.h[2] : 1.0);
-  const int inst = S.inst;
-  const int pf0 = push_first[tix], pf1 = push_first[tix + 1];
   // first half: the first ceil(steps / 2) k steps
   const int ksplit = KS > 1 ? min(ld, ((ld + 2 * O::KB - 1) / (2 * O::KB)) * O::KB) : ld;
-  gmem<T>* __restrict__ phi = gpw<T>(S.phi);
   const int c = cb * 16 + l16;
   acc_t acc = {0, 0, 0, 0};
   T old[4];
@@ -1231,9 +1251,9 @@ __global__ __launch_bounds__(64 * NW) void inv_last_kernel(const int4* __restric
         old[q] = (r < R && c < C) ? phi[(long)r * C + c] : T(0);
       }
     }
-    mma_lds_by_basis_k<KIND>(acc, lds, kh ? ksplit : 0, kh ? ld : ksplit, ldo, sc, A.inv, A.invl, A.ldb, c, l16,
-                             g);
+    mma_lds_by_basis_k<KIND>(acc, lds, kh ? ksplit : 0, kh ? ld : ksplit, ldo, sc, invh, invl, ldb, c, l16, g);
   }
+  const T shift = instance_shift<T>(sa, pin, first_sub, d0);
   if (KS > 1) {
     if (kh == 1 && active) xch[cw][lane] = acc;
     __syncthreads();
@@ -1276,14 +1296,42 @@ __global__ __launch_bounds__(64 * NW) void inv_last_kernel(const int4* __restric
       const int4 P = push[e];
       T v = stash[P.z & 0xFF][P.w];
       if (P.z >> 8) v += dt * shift;
-      gpw<T>(sa.subs[P.x].phi)[P.y] = v;
+      const unsigned long long a = ((unsigned long long)(unsigned)P.y << 32) | (unsigned)P.x;
+      *gpw<T>((void*)(uintptr_t)a) = v;
     }
   }
   const double tot = block_sum_w<NW>(part, red);
   if (threadIdx.x == 0) {
     sa.partials[part_base + tix] = tot * hs;
-    if (I.pin && tl.x == I.first_sub && row0 == 0 && col0 == 0) sa.shift_acc[inst] += (double)dt * (double)shift;
+    if (pin && tl.x == first_sub && row0 == 0 && col0 == 0) sa.shift_acc[inst] += (double)dt * (double)shift;
   }
+}
+
+// Spectral factors of axes 1 and 2 for column c of the [n0][rest] view of a pair product: the
+// axis-1 factor, the axis-2 factor (3D) and their weights gamma_1 h_1^-2, gamma_2 h_2^-2.  Loaded
+// without a branch (c clamped into range; a 2D view reads axis 1 twice and weights the second by 0)
+// so the loads stay in flight with the rest of the prologue; value() combines them in one fixed
+// rounding order, shared by every kernel that applies the spectral scale.
+template <typename T>
+struct RestSig {
+  T r1, r2, g1, g2;
+  __device__ inline T value() const { return fma(g1, r1, g2 * r2); }
+};
+
+template <typename T>
+__device__ inline RestSig<T> rest_sig(const SubDev& S, int c, int ncol) {
+  const bool three = S.dim == 3;
+  const gmem<T>* s1 = gp<T>(S.ax[1].sig);
+  const gmem<T>* s2 = three ? gp<T>(S.ax[2].sig) : s1;
+  const int cc = min(c, ncol - 1);
+  const int n2 = three ? S.n[2] : 1;
+  const int k1 = three ? cc / n2 : cc, k2 = three ? cc - k1 * n2 : 0;
+  RestSig<T> r;
+  r.r1 = s1[k1];
+  r.r2 = s2[k2];
+  r.g1 = T(S.gh2[1]);
+  r.g2 = three ? T(S.gh2[2]) : T(0);
+  return r;
 }
 
 // NW waves per workgroup: latency-bound launches (one workgroup per compute unit or fewer) take 8,
@@ -1342,30 +1390,36 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
   static_assert(RBL <= MAXRB, "LDS-basis row blocks fit the accumulators");
   char* lbh = lds + dbytes;
   char* lbl = lbh + bbytes;
+  // PAIR: spectral factors of this lane's coefficients, requested before the products.  The loads
+  // are unconditional (clamped indices; out-of-range values are discarded afterwards): a load under
+  // a branch would make each one wait for all earlier loads, one memory round trip per factor.
+  // The factors of axes 1 and 2 are combined only when the scale is applied.
+  T sig0[PAIR ? MAXRB * 4 : 1];
+  RestSig<T> rs{T(0), T(0), T(0), T(0)};
+  if constexpr (PAIR) {
+    const gmem<T>* s0 = gp<T>(S.ax[0].sig);
+    rs = rest_sig<T>(S, c, ncol);
+    T raw[MAXRB * 4];
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) raw[t * 4 + q] = s0[min((wave + NW * t) * 16 + O::crow(g, q), K - 1)];
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        sig0[t * 4 + q] = (wave + NW * t) * 16 + O::crow(g, q) < K ? raw[t * 4 + q] : T(0);
+  }
+  // every descriptor field is read before the basis copy is issued: loads after it would be
+  // vector loads (the copy may write memory, as far as the compiler knows), and each of their
+  // waits would also wait for the copy
+  const T fwd_unscale = T(A.fwd_unscale);
+  const void* invh = A.inv;
+  const void* invl = A.invl;
+  const T g0 = T(S.gh2[0]);
   if (lbasis) {
     lds_dma(lbh, b1h, bbytes, NW);
     if (O::SCALED) lds_dma(lbl, b1l, bbytes, NW);
-  }
-  // PAIR: spectral factors of this lane's coefficients, requested before the products
-  T sig0[PAIR ? MAXRB * 4 : 1];
-  T rest = T(0);
-  if constexpr (PAIR) {
-    const gmem<T>* s0 = gp<T>(S.ax[0].sig);
-    const gmem<T>* s1 = gp<T>(S.ax[1].sig);
-    const gmem<T>* s2 = gp<T>(S.ax[2].sig);
-    if (c < ncol) {
-      if (S.dim == 2) rest = T(S.gh2[1]) * s1[c];
-      else {
-        const int k1 = c / S.n[2], k2 = c - (c / S.n[2]) * S.n[2];
-        rest = T(S.gh2[1]) * s1[k1] + T(S.gh2[2]) * s2[k2];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < MAXRB; ++t)
-      for (int q = 0; q < 4; ++q) {
-        const int i = (wave + NW * t) * 16 + O::crow(g, q);
-        sig0[t * 4 + q] = i < K ? s0[i] : T(0);
-      }
   }
   // strip transposed into LDS: operand row c = strip column, k = index along the axis
   const float amax = stage_strip16<KIND, 64 * NW>(lds, ld, ldo, src, K, ncol, col0);
@@ -1377,7 +1431,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
     __syncthreads();
   }
   typename O::acc_t acc[MAXRB];
-  const T us1 = ((PAIR || !inv) ? T(A.fwd_unscale) : T(1)) / T(sc);
+  const T us1 = ((PAIR || !inv) ? fwd_unscale : T(1)) / T(sc);
 #pragma unroll
   for (int t = 0; t < MAXRB; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
   if (lbasis) {
@@ -1407,7 +1461,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
   } else {
     // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2.
     // LDS path: also D^-1 (x 2 at i = 0 and i = K - 1) ahead of the forward matrix reused.
-    const T g0 = T(S.gh2[0]);
+    const T rest = rs.value();
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
       const int rb = wave + NW * t;
@@ -1447,7 +1501,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
     }
     // store scale: 1 / sy, and on the LDS path (N / 2) D^-1 and the split form's 2^-s
     const T half_n = T(K - 1) / T(2);
-    const T os = lbasis ? T(A.fwd_unscale) * half_n / T(sy) : T(1) / T(sy);
+    const T os = lbasis ? fwd_unscale * half_n / T(sy) : T(1) / T(sy);
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
     if (lbasis) {
@@ -1461,7 +1515,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
 #pragma unroll
       for (int t = 0; t < MAXRB; ++t) {
         const int rb = wave + NW * t;
-        if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], A.inv, A.invl, ldb, lds, ld, ldo, sy, rb * 16 + l16, l16, g);
+        if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], invh, invl, ldb, lds, ld, ldo, sy, rb * 16 + l16, l16, g);
       }
     }
 #pragma unroll
@@ -1542,30 +1596,24 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
   const void* b1l = (PAIR || !inv) ? A.fwdl : A.invl;
   // PAIR: spectral factors, requested before the products
   T sig0[PAIR ? MAXRB * 4 : 1];
-  T rest[NC];
+  RestSig<T> rs[NC];
 #pragma unroll
-  for (int cb = 0; cb < NC; ++cb) rest[cb] = T(0);
+  for (int cb = 0; cb < NC; ++cb) rs[cb] = RestSig<T>{T(0), T(0), T(0), T(0)};
   if constexpr (PAIR) {
     const gmem<T>* s0 = gp<T>(S.ax[0].sig);
-    const gmem<T>* s1 = gp<T>(S.ax[1].sig);
-    const gmem<T>* s2 = gp<T>(S.ax[2].sig);
 #pragma unroll
-    for (int cb = 0; cb < NC; ++cb) {
-      const int c = col0 + cb * 16 + l16;
-      if (c < ncol) {
-        if (S.dim == 2) rest[cb] = T(S.gh2[1]) * s1[c];
-        else {
-          const int k1 = c / S.n[2], k2 = c - (c / S.n[2]) * S.n[2];
-          rest[cb] = T(S.gh2[1]) * s1[k1] + T(S.gh2[2]) * s2[k2];
-        }
-      }
-    }
+    for (int cb = 0; cb < NC; ++cb) rs[cb] = rest_sig<T>(S, col0 + cb * 16 + l16, ncol);
+    // unconditional loads (clamped indices): see the 16-column kernel
+    T raw[MAXRB * 4];
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t)
-      for (int q = 0; q < 4; ++q) {
-        const int i = (wave + 4 * t) * 16 + O::crow(g, q);
-        sig0[t * 4 + q] = i < K ? s0[i] : T(0);
-      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) raw[t * 4 + q] = s0[min((wave + 4 * t) * 16 + O::crow(g, q), K - 1)];
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        sig0[t * 4 + q] = (wave + 4 * t) * 16 + O::crow(g, q) < K ? raw[t * 4 + q] : T(0);
   }
   // stage the 64 columns transposed (operand row = column within the tile); thread t takes column
   // t % 64 and rows t / 64 + 4 j, twelve loads in flight per batch
@@ -1652,6 +1700,9 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
     }
   } else {
     const T g0 = T(S.gh2[0]);
+    T rest[NC];
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) rest[cb] = rs[cb].value();
     float ym[NC];  // largest |y| this lane holds in each column block
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) ym[cb] = 0.f;
@@ -1771,12 +1822,12 @@ __host__ __device__ inline int fused_halo_bytes(int ld) {
 }
 
 template <int KIND, int MK>
-__device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K, const MonP<typename Op<KIND>::T>& mp,
-                                    const typename Op<KIND>::T* halo, int HS, char* op, int ld, int ldo, int row0,
+__device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K,
+                                    const MonReg<typename Op<KIND>::T, MK>& M, const typename Op<KIND>::T* halo,
+                                    int HS, char* op, int ld, int ldo, int row0,
                                     NodeCheck<typename Op<KIND>::T>& chk, float& amax) {
   typedef Op<KIND> O;
   typedef typename O::T T;
-  const MonReg<T, MK> M(mp);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = K.n0, n1 = K.n1;
   const T h0 = K.h0, h1 = K.h1;
@@ -1811,25 +1862,27 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K, c
   }
 }
 
-// tile = (sub, row0, 0, 0)
-template <int KIND>
-__global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int4* __restrict__ tiles, int ntiles,
-                                                                       int lcap, StepArgs sa) {
+// One tile of the fused kernel for monitor kind MK.  Every descriptor and monitor field is read
+// into registers first: a read after the basis copy or a barrier could not use the scalar cache
+// (either may write memory, as far as the compiler knows) and would wait for all earlier vector
+// memory operations, the copy included.
+template <int KIND, int MK>
+__device__ inline void stencil_fwd2_tile(const int4 tl, const StencilCtx<typename Op<KIND>::T>& K,
+                                         const MonP<typename Op<KIND>::T>* mp, const typename Op<KIND>::T* phi_,
+                                         int lcap, const StepArgs& sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   constexpr int NW = kFuseWaves;
   extern __shared__ __attribute__((aligned(16))) char lds[];
   __shared__ float red[NW];
-  const int tix = xcd_tile();
-  if (tix >= ntiles) return;
-  const int4 tl = tiles[tix];
-  StencilCtx<T> K;
-  const T* phi_;
-  T* F_;
-  const MonP<T>* mp = load_ctx(sa, tl.x, K, phi_, F_);
+  const MonReg<T, MK> M(*mp);
   const SubDev& S = sa.subs[tl.x];
   const AxisDev& A = S.ax[1];
   const int ld = A.ld, ldo = ld + O::OPAD, ldb = A.ldb, n0 = K.n0, n1 = K.n1, row0 = tl.y;
+  const void* fwdh = A.fwd;
+  const void* fwdl = A.fwdl;
+  const T fwd_unscale = T(A.fwd_unscale);
+  gmem<T>* out = gpw<T>(S.T);
   const int HS = ld + 4;
   char* op = lds;
   T* halo = (T*)(lds + 16 * ldo * O::LDS_BYTES);
@@ -1840,8 +1893,8 @@ __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int
   const bool lbasis =
       nrb <= 4 * kLdsRb && 16 * ldo * O::LDS_BYTES + fused_halo_bytes<KIND>(ld) + (O::SCALED ? 2 : 1) * bbytes <= lcap;
   if (lbasis) {
-    lds_dma(lbh, A.fwd, bbytes, NW);
-    if (O::SCALED) lds_dma(lbl, A.fwdl, bbytes, NW);
+    lds_dma(lbh, fwdh, bbytes, NW);
+    if (O::SCALED) lds_dma(lbl, fwdl, bbytes, NW);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
   // halo rows row0 - 1 .. row0 + 16, columns -1 .. n1 (mirror ghosts): wave w rows w + NW k, lane
@@ -1873,16 +1926,7 @@ __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int
   __syncthreads();
   NodeCheck<T> chk;
   float amax = 0.f;
-  switch (mp->kind) {
-    case MON_CONST: fused_nodes2<KIND, MON_CONST>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-    case MON_RADIAL: fused_nodes2<KIND, MON_RADIAL>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-    case MON_SINE: fused_nodes2<KIND, MON_SINE>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-    case MON_GAUSS: fused_nodes2<KIND, MON_GAUSS>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-    case MON_ARC_FRONT: fused_nodes2<KIND, MON_ARC_FRONT>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-    case MON_ARC_SPIRAL: fused_nodes2<KIND, MON_ARC_SPIRAL>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-    case MON_ARC_SPHERES: fused_nodes2<KIND, MON_ARC_SPHERES>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-    default: fused_nodes2<KIND, MON_SEPARABLE>(K, *mp, halo, HS, op, ld, ldo, row0, chk, amax); break;
-  }
+  fused_nodes2<KIND, MK>(K, M, halo, HS, op, ld, ldo, row0, chk, amax);
   const float sc = O::SCALED ? tile_scale_w<NW>(amax, red) : 1.f;
   if (lbasis) vmem_drain();
   __syncthreads();
@@ -1890,8 +1934,7 @@ __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int
     O::presplit(lds, ldo, 16, ld, &sc, 16);
     __syncthreads();
   }
-  gmem<T>* out = gpw<T>(S.T);
-  const T us = T(A.fwd_unscale) / T(sc);
+  const T us = fwd_unscale / T(sc);
   constexpr int NT = (kFuseMaxLd / 16 + NW - 1) / NW;
   typename O::acc_t acc[NT];
 #pragma unroll
@@ -1908,7 +1951,7 @@ __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int cb = wave + NW * t;
-      if (cb < nrb) mma_lds_by_basis<KIND>(acc[t], op, ld, ldo, sc, A.fwd, A.fwdl, ldb, cb * 16 + l16, l16, g);
+      if (cb < nrb) mma_lds_by_basis<KIND>(acc[t], op, ld, ldo, sc, fwdh, fwdl, ldb, cb * 16 + l16, l16, g);
     }
   }
 #pragma unroll
@@ -1923,6 +1966,30 @@ __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int
   }
   const int bad = chk.bits();
   if (bad) atomicOr(&sa.status[K.inst], bad);
+}
+
+// tile = (sub, row0, 0, 0)
+template <int KIND>
+__global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int4* __restrict__ tiles, int ntiles,
+                                                                       int lcap, StepArgs sa) {
+  typedef typename Op<KIND>::T T;
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
+  StencilCtx<T> K;
+  const T* phi_;
+  T* F_;
+  const MonP<T>* mp = load_ctx(sa, tl.x, K, phi_, F_);
+  switch (mp->kind) {
+    case MON_CONST: stencil_fwd2_tile<KIND, MON_CONST>(tl, K, mp, phi_, lcap, sa); break;
+    case MON_RADIAL: stencil_fwd2_tile<KIND, MON_RADIAL>(tl, K, mp, phi_, lcap, sa); break;
+    case MON_SINE: stencil_fwd2_tile<KIND, MON_SINE>(tl, K, mp, phi_, lcap, sa); break;
+    case MON_GAUSS: stencil_fwd2_tile<KIND, MON_GAUSS>(tl, K, mp, phi_, lcap, sa); break;
+    case MON_ARC_FRONT: stencil_fwd2_tile<KIND, MON_ARC_FRONT>(tl, K, mp, phi_, lcap, sa); break;
+    case MON_ARC_SPIRAL: stencil_fwd2_tile<KIND, MON_ARC_SPIRAL>(tl, K, mp, phi_, lcap, sa); break;
+    case MON_ARC_SPHERES: stencil_fwd2_tile<KIND, MON_ARC_SPHERES>(tl, K, mp, phi_, lcap, sa); break;
+    default: stencil_fwd2_tile<KIND, MON_SEPARABLE>(tl, K, mp, phi_, lcap, sa); break;
+  }
 }
 
 // ------------------------------------------------------------------------------------------

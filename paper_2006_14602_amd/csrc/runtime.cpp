@@ -1285,7 +1285,11 @@ struct Batch {
         const int nct = (C + kCols - 1) / kCols;
         const int tile = tab[7].rng[t.z].first + (r / kRows) * nct + c / kCols;
         const int later = glevel[t.x] > glevel[t.z] ? 1 : 0;  // destination updated later this step
-        ent.push_back(int4{t.x, t.y, (r % kRows) | (later << 8), c % kCols});
+        // the destination node's device address (its subdomain's phi, element t.y), as two words
+        const size_t esz = insts[h_subs[t.x].inst]->prec == PREC_F64 ? 8 : 4;
+        const unsigned long long addr = (unsigned long long)(uintptr_t)h_subs[t.x].phi + esz * (size_t)t.y;
+        ent.push_back(int4{(int)(unsigned)(addr & 0xffffffffull), (int)(unsigned)(addr >> 32),
+                           (r % kRows) | (later << 8), c % kCols});
         tile_of.push_back(tile);
         ++cnt[tile + 1];
       }
