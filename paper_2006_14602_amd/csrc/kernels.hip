@@ -924,50 +924,74 @@ __device__ inline void mma_basis_by_lds(typename Op<KIND>::acc_t& acc, const voi
 // Products with a basis copy in LDS take at most 12 row (column) blocks: three per wave.
 constexpr int kLdsRb = 3;
 
-// acc[t] += basis rows (row block wave + 4 t, a basis copy in LDS) x the LDS data operand, k
+// acc[t] += basis rows (row block wave + NW t, a basis copy in LDS) x the LDS data operand, k
 // outermost: the data fragment of a k step is read (and split) once for all row blocks, the basis
 // fragments of all row blocks are requested before the first product, and the independent
-// accumulators keep the matrix cores busy.  All kLdsRb products are issued every k step (no branch
-// in the accumulator chains); the caller uses the row blocks that exist.
-template <int KIND, int NW, int RB>
+// accumulators keep the matrix cores busy.  Only the row blocks below nrb are computed: the wave's
+// count of them is uniform, so the choice is made once, outside the k loop, and each accumulator
+// chain stays free of branches.  Accumulators of missing row blocks are left untouched.
+template <int KIND, int NW, int RB, int N>
+__device__ inline void mma_lbasis_rows_n(typename Op<KIND>::acc_t (&acc)[RB], const char* bh, const char* bl,
+                                         int ldb, const char* lds, int ld, int ldo, float sc, int wave, int l16,
+                                         int g) {
+  typedef Op<KIND> O;
+  int row[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) row[t] = (wave + NW * t) * 16 + l16;
+  for (int k0 = 0; k0 < ld; k0 += O::KB) {
+    typename O::frag a[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) a[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
+    const typename O::frag b = O::lds_frag_cvt(lds, ldo, l16, k0, g, sc);
+#pragma unroll
+    for (int t = 0; t < N; ++t) O::mma(acc[t], a[t], b);
+  }
+}
+
+template <int KIND, int NW, int RB, int N = RB>
 __device__ inline void mma_lbasis_rows(typename Op<KIND>::acc_t (&acc)[RB], const char* bh, const char* bl,
                                        int ldb, const char* lds, int ld, int ldo, float sc, int wave, int nrb,
                                        int l16, int g) {
-  typedef Op<KIND> O;
-  // a row block beyond the axis reads the last basis row (valid memory); its result is unused
-  int row[RB];
-#pragma unroll
-  for (int t = 0; t < RB; ++t) row[t] = min((wave + NW * t) * 16 + l16, nrb * 16 - 1);
-  for (int k0 = 0; k0 < ld; k0 += O::KB) {
-    typename O::frag a[RB];
-#pragma unroll
-    for (int t = 0; t < RB; ++t) a[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
-    const typename O::frag b = O::lds_frag_cvt(lds, ldo, l16, k0, g, sc);
-#pragma unroll
-    for (int t = 0; t < RB; ++t) O::mma(acc[t], a[t], b);
+  if constexpr (N > 0) {
+    if (wave + NW * (N - 1) < nrb)  // row blocks 0 .. N - 1 of this wave exist
+      mma_lbasis_rows_n<KIND, NW, RB, N>(acc, bh, bl, ldb, lds, ld, ldo, sc, wave, l16, g);
+    else
+      mma_lbasis_rows<KIND, NW, RB, N - 1>(acc, bh, bl, ldb, lds, ld, ldo, sc, wave, nrb, l16, g);
   }
 }
 
 // acc[t] += LDS data rows x basis rows (column block wave + NW t) of a basis copy in LDS, k
-// outermost; NW waves take RB column blocks each
-template <int KIND, int NW, int RB>
-__device__ inline void mma_rows_lbasis_w(typename Op<KIND>::acc_t (&acc)[RB], const char* lds, int ld, int ldo,
-                                         float sc, const char* bh, const char* bl, int ldb, int wave, int nrb, int l16,
+// outermost; NW waves take RB column blocks each, and only the column blocks below nrb are
+// computed (chosen once per wave, as above)
+template <int KIND, int NW, int RB, int N>
+__device__ inline void mma_rows_lbasis_n(typename Op<KIND>::acc_t (&acc)[RB], const char* lds, int ld, int ldo,
+                                         float sc, const char* bh, const char* bl, int ldb, int wave, int l16,
                                          int g) {
   typedef Op<KIND> O;
-  int row[RB];
+  int row[N];
 #pragma unroll
-  for (int t = 0; t < RB; ++t) row[t] = min((wave + NW * t) * 16 + l16, nrb * 16 - 1);
+  for (int t = 0; t < N; ++t) row[t] = (wave + NW * t) * 16 + l16;
   for (int k0 = 0; k0 < ld; k0 += O::KB) {
-    typename O::frag b[RB];
+    typename O::frag b[N];
 #pragma unroll
-    for (int t = 0; t < RB; ++t) b[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
+    for (int t = 0; t < N; ++t) b[t] = O::lbasis_frag(bh, bl, ldb, row[t], k0, g);
     const typename O::frag a = O::lds_frag_cvt(lds, ldo, l16, k0, g, sc);
 #pragma unroll
-    for (int t = 0; t < RB; ++t) O::mma(acc[t], a, b[t]);
+    for (int t = 0; t < N; ++t) O::mma(acc[t], a, b[t]);
   }
 }
 
+template <int KIND, int NW, int RB, int N = RB>
+__device__ inline void mma_rows_lbasis_w(typename Op<KIND>::acc_t (&acc)[RB], const char* lds, int ld, int ldo,
+                                         float sc, const char* bh, const char* bl, int ldb, int wave, int nrb, int l16,
+                                         int g) {
+  if constexpr (N > 0) {
+    if (wave + NW * (N - 1) < nrb)
+      mma_rows_lbasis_n<KIND, NW, RB, N>(acc, lds, ld, ldo, sc, bh, bl, ldb, wave, l16, g);
+    else
+      mma_rows_lbasis_w<KIND, NW, RB, N - 1>(acc, lds, ld, ldo, sc, bh, bl, ldb, wave, nrb, l16, g);
+  }
+}
 
 // Copy `bytes` (a multiple of 16) from global memory into LDS with direct-to-LDS loads, which
 // need no registers and are all in flight together: wave w of nwaves copies the 1 KiB chunks w,
