@@ -1196,9 +1196,10 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 
 // inverse transform along the last axis for 16 rows x up to 64 columns, fused with the update
 // phi += dt (delta - shift) and the residual partial sum.  Input: F.
-// Push transmission: push_first[tile] .. push_first[tile + 1] index the entries (destination
-// node's device address as low and high words, row | later << 8, column within the tile) of
-// push[] whose source node lies in the tile;
+// Push transmission: the subdomain's entries S.pfirst[t] .. S.pfirst[t + 1] of S.push, t = tile.w
+// the tile's index among the subdomain's inverse-last tiles (destination node's device address as
+// low and high words, row | later << 8, column within the tile), are those whose source node lies
+// in the tile;
 // after the update each such node's new value is written into the artificial node of the other
 // subdomain, which is the owner's value the transmission condition gives it for the next step.
 // In an alternating sweep a destination that is updated later in the same step has not removed
@@ -1212,8 +1213,7 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 // the launches of many tiles that take this form)
 template <int KIND, int NW>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
-                                                           const int* __restrict__ push_first,
-                                                           const int4* __restrict__ push, StepArgs sa) {
+                                                                           StepArgs sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   typedef typename O::acc_t acc_t;
@@ -1248,7 +1248,9 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(cons
   const void* invl = A.invl;
   const int ldb = A.ldb;
   gmem<T>* __restrict__ phi = gpw<T>(S.phi);
-  const int pf0 = push_first[tix], pf1 = push_first[tix + 1];
+  const int4* __restrict__ push = S.push;
+  const int* __restrict__ pfirst = S.pfirst;
+  const int pf0 = pfirst ? pfirst[tl.w] : 0, pf1 = pfirst ? pfirst[tl.w + 1] : 0;
   const T d0 = dc_first_load<T>(sa, pin, first_sub);
   const float amax = stage_rows16<KIND, NW>(lds, ld, ldo, src, row0, R, C);
   const float sc = O::SCALED ? tile_scale_w<NW>(amax, redf) : 1.f;
@@ -2337,19 +2339,17 @@ hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, c
   return hipGetLastError();
 }
 
-hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const int* push_first,
-                           const int4* push, const StepArgs& sa, hipStream_t s) {
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
+                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const size_t sh = op_lds(prec, maxld);
   const bool eight = ntiles <= 512;  // latency-bound: at most two workgroups per compute unit
 #define PMA_INV(K)                                                                                                    \
   do {                                                                                                                \
     if (eight)                                                                                                        \
-      hipLaunchKernelGGL((inv_last_kernel<K, 8>), dim3(ntiles), dim3(512), sh, s, tiles, ntiles, part_base,          \
-                         push_first, push, sa);                                                                       \
+      hipLaunchKernelGGL((inv_last_kernel<K, 8>), dim3(ntiles), dim3(512), sh, s, tiles, ntiles, part_base, sa);     \
     else                                                                                                              \
-      hipLaunchKernelGGL((inv_last_kernel<K, 4>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base,          \
-                         push_first, push, sa);                                                                       \
+      hipLaunchKernelGGL((inv_last_kernel<K, 4>), dim3(ntiles), dim3(256), sh, s, tiles, ntiles, part_base, sa);     \
   } while (0)
   if (prec == PREC_F64)
     PMA_INV(PREC_F64);

@@ -66,6 +66,13 @@ struct SubDev {
   void* phi;
   void* F;
   void* T;
+  // push transmission (preconditioned steps; null without artificial nodes owned elsewhere):
+  // entries (destination node's device address as low and high words, row | later << 8, column)
+  // of the nodes this subdomain owns for its neighbours, grouped by the inverse-last tile that
+  // holds the node; pfirst[t] .. pfirst[t + 1] are those of local tile t (row block t / nct,
+  // column block t % nct of the [rows][last axis] view, 16 x 64 nodes)
+  const int4* push;
+  const int* pfirst;
   double a[3];         // global box lower corner
   double h[3];         // grid spacing
   double gh2[3];       // gamma / h_k^2

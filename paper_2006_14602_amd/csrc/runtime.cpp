@@ -32,8 +32,7 @@ int fused_lds_bytes(int prec, int ld, int ldb, int n, bool basis);
 hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
                         hipStream_t s);
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
-hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const int* push_first,
-                           const int4* push, const StepArgs& sa,
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
                            hipStream_t s);
 hipError_t launch_strip4(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
                          int src_sel, const StepArgs& sa, hipStream_t s);
@@ -609,6 +608,7 @@ struct Instance {
   std::vector<SubHost> subs;
   std::vector<int> own[3];
   std::vector<int4> trans;  // (dst local sub, dst elem, src local sub, src elem)
+  std::vector<int> push_cnt;  // push entries per source subdomain (preconditioned DD requests)
   std::vector<int> trans_first;  // per dst sub, into trans (size nsub + 1)
   std::vector<int> level;        // sweep level per subdomain (all 0 in the parallel form)
   int nlevels = 1;
@@ -617,6 +617,11 @@ struct Instance {
   char* block = nullptr;
   size_t bytes = 0;
   std::vector<void*> phi, F, T;
+  int4* trans_dev = nullptr;     // the transmission list on the device (in the block)
+  std::vector<int4*> push_dev;   // per subdomain, in the block (see SubDev::push)
+  std::vector<int*> pfirst_dev;
+  std::vector<int4> push_host;   // their sources, kept while the copies may be in flight
+  std::vector<int> pfirst_host;
   int* own_dev[3] = {nullptr, nullptr, nullptr};
   double* mesh_dev = nullptr;
   double* psi_dev = nullptr;
@@ -646,6 +651,18 @@ struct Instance {
 };
 
 static long sub_nodes(const SubHost& s) { return (long)s.n[0] * s.n[1] * s.n[2]; }
+
+static constexpr int kRows = 16, kCols = 64, kStrip = 16;  // mode-product tiles
+
+// inverse-last tiles of a subdomain: kRows x kCols blocks of its [rows][last axis] view (rows =
+// n0 in 2D, n0 n1 in 3D); nct = column blocks per row block
+static int inv_tiles(const int n[3], int dim, int& nct) {
+  const int R = dim == 2 ? n[0] : n[0] * n[1], C = n[dim - 1];
+  nct = (C + kCols - 1) / kCols;
+  return ((R + kRows - 1) / kRows) * nct;
+}
+
+static bool uses_push(const Instance& I) { return I.tm.gamma > 0 && !I.push_cnt.empty(); }
 
 static void build_coupling(Instance& I);
 
@@ -713,6 +730,11 @@ static void build_coupling(Instance& I) {
       }
   }
   I.trans_first[ns] = (int)I.trans.size();
+  I.push_cnt.assign(ns, 0);
+  for (const int4& t : I.trans) I.push_cnt[t.z]++;
+  bool any = false;
+  for (int c : I.push_cnt) any |= c > 0;
+  if (!any) I.push_cnt.clear();
   // Sweep levels of the alternating forms (Algorithm 1).  The subdomains are visited one at a
   // time in the sweep order; a subdomain's level is one more than the highest level among the
   // subdomains it exchanges values with that come before it in the sweep.  Two subdomains of
@@ -765,6 +787,14 @@ static size_t instance_bytes(const Instance& I) {
     b += Arena::round(partials_count(I) * sizeof(double));
   }
   b += Arena::round(4 * sizeof(double));
+  if (!I.trans.empty()) b += Arena::round(I.trans.size() * sizeof(int4));
+  if (uses_push(I))
+    for (size_t s = 0; s < I.subs.size(); ++s)
+      if (I.push_cnt[s]) {
+        int nct;
+        b += Arena::round((size_t)I.push_cnt[s] * sizeof(int4)) +
+             Arena::round((size_t)(inv_tiles(I.subs[s].n, I.dim, nct) + 1) * sizeof(int));
+      }
   return b;
 }
 
@@ -958,6 +988,58 @@ static size_t all_basis_bytes(const Instance& I) {
   return b;
 }
 
+// Push transmission of a preconditioned DD request, once per allocation: for every transmission
+// entry, the inverse-last kernel of the tile holding the source node writes the node's new value
+// into the destination (an artificial node of another subdomain of the request).  Entries carry
+// the destination's device address, so the tables depend on the request alone and batches of
+// any membership use them as they are.
+template <typename Take>
+static void build_push_tables(pma_ctx* c, Instance& I, Take& take) {
+  const int ns = (int)I.subs.size();
+  std::vector<int> ebase(ns + 1, 0), tbase(ns + 1, 0), nct(ns, 1);
+  for (int s = 0; s < ns; ++s) {
+    ebase[s + 1] = ebase[s] + I.push_cnt[s];
+    tbase[s + 1] = tbase[s] + (I.push_cnt[s] ? inv_tiles(I.subs[s].n, I.dim, nct[s]) + 1 : 0);
+  }
+  auto tile_of = [&](const int4& t, int& r, int& col) {
+    const SubHost& S = I.subs[t.z];
+    const int C = S.n[I.dim - 1];
+    r = t.w / C;
+    col = t.w - r * C;
+    return (r / kRows) * nct[t.z] + col / kCols;
+  };
+  // counts per local tile, then each entry in its tile's slot (list order kept within a tile)
+  I.pfirst_host.assign(tbase[ns], 0);
+  for (const int4& t : I.trans) {
+    int r, col;
+    I.pfirst_host[tbase[t.z] + tile_of(t, r, col) + 1]++;
+  }
+  for (int s = 0; s < ns; ++s)
+    for (int k = tbase[s] + 1; k < tbase[s + 1]; ++k) I.pfirst_host[k] += I.pfirst_host[k - 1];
+  std::vector<int> fill(I.pfirst_host);
+  I.push_host.assign(ebase[ns], int4{0, 0, 0, 0});
+  for (const int4& t : I.trans) {
+    int r, col;
+    const int lt = tile_of(t, r, col);
+    const int later = I.level[t.x] > I.level[t.z] ? 1 : 0;  // destination updated later this step
+    const unsigned long long addr = (unsigned long long)(uintptr_t)I.phi[t.x] + I.elem() * (size_t)t.y;
+    I.push_host[ebase[t.z] + fill[tbase[t.z] + lt]++] =
+        int4{(int)(unsigned)(addr & 0xffffffffull), (int)(unsigned)(addr >> 32), (r % kRows) | (later << 8),
+             col % kCols};
+  }
+  I.push_dev.assign(ns, nullptr);
+  I.pfirst_dev.assign(ns, nullptr);
+  for (int s = 0; s < ns; ++s) {
+    if (!I.push_cnt[s]) continue;
+    I.push_dev[s] = (int4*)take((size_t)I.push_cnt[s] * sizeof(int4));
+    I.pfirst_dev[s] = (int*)take((size_t)(tbase[s + 1] - tbase[s]) * sizeof(int));
+    HIPCHK(hipMemcpyAsync(I.push_dev[s], I.push_host.data() + ebase[s], (size_t)I.push_cnt[s] * sizeof(int4),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(I.pfirst_dev[s], I.pfirst_host.data() + tbase[s],
+                          (size_t)(tbase[s + 1] - tbase[s]) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  }
+}
+
 static void alloc_instance(pma_ctx* c, Instance& I) {
   I.bytes = instance_bytes(I);
   I.block = (char*)arena_alloc(c, I.bytes);
@@ -987,6 +1069,13 @@ static void alloc_instance(pma_ctx* c, Instance& I) {
                             hipMemcpyHostToDevice, c->stream));
   }
   I.stats_dev = (double*)take(4 * sizeof(double));
+  I.trans_dev = nullptr;
+  if (!I.trans.empty()) {
+    I.trans_dev = (int4*)take(I.trans.size() * sizeof(int4));
+    HIPCHK(hipMemcpyAsync(I.trans_dev, I.trans.data(), I.trans.size() * sizeof(int4), hipMemcpyHostToDevice,
+                          c->stream));
+  }
+  if (uses_push(I)) build_push_tables(c, I, take);
   I.bases_used.clear();
   if (I.tm.gamma > 0) {
     try {
@@ -1018,7 +1107,6 @@ static void free_instance(pma_ctx* c, Instance& I) {
 
 static constexpr int kStRows = 4, kStCols = 64;     // forward-Euler tiles
 static constexpr int kStChunk = 16, kStWmax = 72;  // stencil: rows per chunk, widest block
-static constexpr int kRows = 16, kCols = 64, kStrip = 16;  // mode-product tiles
 static constexpr int kPhases = 8;
 static constexpr int kLdsBasisCap = 160 * 1024 - 4096;  // dynamic LDS a workgroup may take
 // Copying the basis into LDS removes the basis loads from a strip workgroup's critical path but
@@ -1079,26 +1167,21 @@ struct Batch {
   std::vector<Instance*> insts;
   std::vector<SubDev> h_subs;
   std::vector<InstDev> h_insts;
-  std::vector<int4> h_trans;
-  std::vector<SubRange> tr_rng;
   // a step's transmission: pushed by the inverse-last kernel of the owner (gamma > 0), or pulled
   // by the gather before the stencil (forward-Euler instances)
-  std::vector<int4> h_push, h_pull;
-  std::vector<int> h_pfirst;
+  std::vector<int4> h_pull;
   std::vector<SubRange> pull_rng;
   // launch order: subdomains sorted by sweep level (stable); level L holds positions
   // lvl_first[L] .. lvl_first[L + 1] - 1 of `order`, and every launch table and the pull list
   // are laid out in this order, so one level is one contiguous range of each
   std::vector<int> glevel, order, lvl_first;
   int nlev = 1;
-  int4 *d_push = nullptr, *d_pull = nullptr;
-  int* d_pfirst = nullptr;
+  int4* d_pull = nullptr;
   Table tab[kPhases];  // tab[0] unused (transmission has its own list)
   int part_base_eu = 0, part_base_inv = 0, npartials = 0;
   char* dmem = nullptr;
   SubDev* d_subs = nullptr;
   InstDev* d_insts = nullptr;
-  int4* d_tr = nullptr;
   void* d_dc = nullptr;
   double *d_partials = nullptr, *d_shift = nullptr, *d_resid = nullptr;
   int* d_status = nullptr;
@@ -1261,46 +1344,23 @@ struct Batch {
     if (need <= kLdsBasisCap) t.lneed = std::max(t.lneed, need);
   }
 
-  // Split the transmission list: entries of instances that take the preconditioned update are
-  // pushed by the inverse-last tile holding the source node (bucketed per tile, with the node's
-  // row and column inside the tile); forward-Euler instances keep the gather.
-  void build_push_lists() {
-    const int nt = tab[7].size();
-    std::vector<int> cnt(nt + 1, 0);
-    std::vector<int4> ent;
-    std::vector<int> tile_of;
+  // The gather lists of forward-Euler requests (the preconditioned ones push their transmission
+  // from the inverse-last kernel, with per-request tables made at allocation).
+  void build_pull_lists() {
     pull_rng.assign(h_subs.size(), SubRange{0, 0});
     for (int gs : order) {
-      const bool euler = insts[h_subs[gs].inst]->tm.gamma == 0.0;
       SubRange pr{(int)h_pull.size(), 0};
-      for (int e = tr_rng[gs].first; e < tr_rng[gs].first + tr_rng[gs].count; ++e) {
-        const int4 t = h_trans[e];  // (dst sub, dst node, src sub, src node)
-        if (euler) {
-          h_pull.push_back(t);
-          continue;
+      const Instance& I = *insts[h_subs[gs].inst];
+      if (I.tm.gamma == 0.0) {
+        const int first = h_insts[h_subs[gs].inst].first_sub, s = gs - first;
+        for (int e = I.trans_first[s]; e < I.trans_first[s + 1]; ++e) {
+          const int4 t = I.trans[e];
+          h_pull.push_back(int4{first + t.x, t.y, first + t.z, t.w});
         }
-        const SubDev& src = h_subs[t.z];
-        const int C = src.dim == 2 ? src.n[1] : src.n[2];
-        const int r = t.w / C, c = t.w - (t.w / C) * C;
-        const int nct = (C + kCols - 1) / kCols;
-        const int tile = tab[7].rng[t.z].first + (r / kRows) * nct + c / kCols;
-        const int later = glevel[t.x] > glevel[t.z] ? 1 : 0;  // destination updated later this step
-        // the destination node's device address (its subdomain's phi, element t.y), as two words
-        const size_t esz = insts[h_subs[t.x].inst]->prec == PREC_F64 ? 8 : 4;
-        const unsigned long long addr = (unsigned long long)(uintptr_t)h_subs[t.x].phi + esz * (size_t)t.y;
-        ent.push_back(int4{(int)(unsigned)(addr & 0xffffffffull), (int)(unsigned)(addr >> 32),
-                           (r % kRows) | (later << 8), c % kCols});
-        tile_of.push_back(tile);
-        ++cnt[tile + 1];
       }
       pr.count = (int)h_pull.size() - pr.first;
       pull_rng[gs] = pr;
     }
-    for (int i = 0; i < nt; ++i) cnt[i + 1] += cnt[i];
-    h_pfirst = cnt;
-    h_push.assign(ent.size(), int4{0, 0, 0, 0});
-    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (size_t i = 0; i < ent.size(); ++i) h_push[pos[tile_of[i]]++] = ent[i];
   }
 
   void build() {
@@ -1308,11 +1368,7 @@ struct Batch {
     clear_device();
     h_subs.clear();
     h_insts.clear();
-    h_trans.clear();
-    tr_rng.clear();
-    h_push.clear();
     h_pull.clear();
-    h_pfirst.clear();
     pull_rng.clear();
     for (auto& t : tab) t = Table();
     for (size_t q = 0; q < insts.size(); ++q) {
@@ -1356,6 +1412,9 @@ struct Batch {
         sd.phi = I.phi[s];
         sd.F = I.F[s];
         sd.T = I.T[s];
+        const bool push = uses_push(I) && I.push_dev[s];
+        sd.push = push ? I.push_dev[s] : nullptr;
+        sd.pfirst = push ? I.pfirst_dev[s] : nullptr;
         h_subs.push_back(sd);
       }
     }
@@ -1387,19 +1446,6 @@ struct Batch {
       st_cap = tmp.size();
     }
     // transmission lists, subdomain by subdomain (an instance's entries stay contiguous)
-    for (size_t q = 0; q < insts.size(); ++q) {
-      Instance& I = *insts[q];
-      const int first = h_insts[q].first_sub;
-      for (size_t s = 0; s < I.subs.size(); ++s) {
-        SubRange tr{(int)h_trans.size(), 0};
-        for (int e = I.trans_first[s]; e < I.trans_first[s + 1]; ++e) {
-          const int4 t = I.trans[e];
-          h_trans.push_back(int4{first + t.x, t.y, first + t.z, t.w});
-        }
-        tr.count = (int)h_trans.size() - tr.first;
-        tr_rng.push_back(tr);
-      }
-    }
     // tiles, subdomain by subdomain in launch order
     choose_wide();
     const int sw4 = wide_[4] ? 4 * kStrip : kStrip, sw5 = wide_[5] ? 4 * kStrip : kStrip;
@@ -1442,8 +1488,10 @@ struct Batch {
           for (int c = 0; c < rest; c += sw5) tab[5].h.push_back(int4{gs, 0, c, 0});
           tab[5].maxld = std::max(tab[5].maxld, sd.ax[0].ld);
           note_lds(tab[5], n0, sd.ax[0].ld);
+          // (w: the tile's index among the subdomain's inverse-last tiles, for its push entries)
+          const int nct = (C + kCols - 1) / kCols;
           for (int r = 0; r < R; r += kRows)
-            for (int c = 0; c < C; c += kCols) tab[7].h.push_back(int4{gs, r, c, 0});
+            for (int c = 0; c < C; c += kCols) tab[7].h.push_back(int4{gs, r, c, (r / kRows) * nct + c / kCols});
           tab[7].maxld = std::max(tab[7].maxld, sd.ax[la].ld);
         }
         for (int ph = 1; ph < kPhases; ++ph) tab[ph].end_sub(gs);
@@ -1464,13 +1512,12 @@ struct Batch {
         sd.nparts = tab[7].rng[gs].count;
       }
     }
-    build_push_lists();
+    build_pull_lists();
     // device block
     const size_t nsub = h_subs.size(), ninst = h_insts.size();
     const size_t el = prec == PMA_FP64 ? 8 : 4;
     size_t bytes = Arena::round(nsub * sizeof(SubDev)) + Arena::round(ninst * sizeof(InstDev)) +
-                   Arena::round(h_trans.size() * 16 + 16) + Arena::round(h_push.size() * 16 + 16) +
-                   Arena::round(h_pull.size() * 16 + 16) + Arena::round(h_pfirst.size() * 4 + 16) + Arena::round(nsub * el) +
+                   Arena::round(h_pull.size() * 16 + 16) + Arena::round(nsub * el) +
                    Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4);
     for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
     if (bytes > dcap) {
@@ -1498,10 +1545,7 @@ struct Batch {
     };
     d_subs = (SubDev*)take(nsub * sizeof(SubDev));
     d_insts = (InstDev*)take(ninst * sizeof(InstDev));
-    d_tr = (int4*)take(h_trans.size() * 16 + 16);
-    d_push = (int4*)take(h_push.size() * 16 + 16);
     d_pull = (int4*)take(h_pull.size() * 16 + 16);
-    d_pfirst = (int*)take(h_pfirst.size() * 4 + 16);
     for (int ph = 1; ph < kPhases; ++ph) tab[ph].d = (int4*)take((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
     d_dc = take(nsub * el);
     d_partials = (double*)take((size_t)(npartials + 1) * 8);
@@ -1510,10 +1554,7 @@ struct Batch {
     d_status = (int*)take(ninst * 4);
     up(d_subs, h_subs.data(), nsub * sizeof(SubDev));
     up(d_insts, h_insts.data(), ninst * sizeof(InstDev));
-    up(d_tr, h_trans.data(), h_trans.size() * 16);
-    up(d_push, h_push.data(), h_push.size() * 16);
     up(d_pull, h_pull.data(), h_pull.size() * 16);
-    up(d_pfirst, h_pfirst.data(), h_pfirst.size() * 4);
     for (int ph = 1; ph < kPhases; ++ph) up(tab[ph].d, tab[ph].h.data(), tab[ph].h.size() * 16);
     HIPCHK(hipMemsetAsync(d_dc, 0, nsub * el, st));
     HIPCHK(hipMemsetAsync(d_partials, 0, (size_t)(npartials + 1) * 8, st));
@@ -1568,7 +1609,7 @@ struct Batch {
         else HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 1, 1, sa, st));
         break;
       case 7:
-        HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, d_pfirst + first, d_push, sa, st));
+        HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, sa, st));
         break;
     }
   }
@@ -1578,12 +1619,20 @@ struct Batch {
   // one phase of a step over sweep level L (-1: every level in turn): the level's subdomains in
   // one launch, or one subdomain per launch (plain)
   void launch_phase(int ph, bool plain, hipStream_t st, int L = -1) {
-    const int nsub = (int)h_subs.size();
-    if (ph == 0) {
-      if (!plain) HIPCHK(launch_transmit(prec, d_subs, d_tr, (int)h_trans.size(), st));
-      else
-        for (int s = 0; s < nsub; ++s)
-          if (tr_rng[s].count) HIPCHK(launch_transmit(prec, d_subs, d_tr + tr_rng[s].first, tr_rng[s].count, st));
+    if (ph == 0) {  // every request's whole transmission list as a gather (timed on its own)
+      for (size_t q = 0; q < insts.size(); ++q) {
+        const Instance& I = *insts[q];
+        const int first = h_insts[q].first_sub;
+        if (I.trans.empty()) continue;
+        if (!plain) {
+          HIPCHK(launch_transmit(prec, d_subs + first, I.trans_dev, (int)I.trans.size(), st));
+        } else {
+          for (size_t s = 0; s < I.subs.size(); ++s) {
+            const int f = I.trans_first[s], n = I.trans_first[s + 1] - f;
+            if (n) HIPCHK(launch_transmit(prec, d_subs + first, I.trans_dev + f, n, st));
+          }
+        }
+      }
       return;
     }
     if (L < 0) {
@@ -1654,7 +1703,7 @@ struct Batch {
   void phase_work(double* flops, double* bytes) const {
     const double el = prec == PMA_FP64 ? 8.0 : 4.0;
     for (int ph = 0; ph < kPhases; ++ph) flops[ph] = bytes[ph] = 0.0;
-    bytes[0] = (double)h_trans.size() * 2 * el;
+    for (const Instance* I : insts) bytes[0] += (double)I->trans.size() * 2 * el;
     for (size_t q = 0; q < h_subs.size(); ++q) {
       const SubDev& s = h_subs[q];
       const double n0 = s.n[0], n1 = s.n[1], n2 = s.n[2];
@@ -1752,10 +1801,7 @@ static void finalize_instance(pma_ctx* c, Instance& I, Batch& B, int q, bool wan
     return;
   }
   // refresh the artificial nodes so owned nodes next to them see current neighbours
-  const int nsub = (int)I.subs.size();
-  const int t0 = B.tr_rng[first].first;
-  const int t1 = B.tr_rng[first + nsub - 1].first + B.tr_rng[first + nsub - 1].count;
-  if (t1 > t0) HIPCHK(launch_transmit(I.prec, B.d_subs, B.d_tr + t0, t1 - t0, st));
+  if (!I.trans.empty()) HIPCHK(launch_transmit(I.prec, B.d_subs + first, I.trans_dev, (int)I.trans.size(), st));
   GlueArgs g{};
   g.subs = B.d_subs;
   g.first_sub = first;
