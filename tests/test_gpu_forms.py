@@ -327,6 +327,25 @@ def test_served_requests_equal_alone(B):
         assert info["queued"] == 0 and info["running"] == 0
 
 
+def test_served_sweep_forms_equal_alone(B):
+    # alternating and coloured sweeps (transmission pushed with the later-level correction) next
+    # to parallel requests, 2D and 3D, through the server: each equals the same request alone
+    def mode(w, m):
+        w["dd"]["mode"] = m
+        return w
+    ws = [mode(W.sine_dd(n=97, parts=(4, 4), overlap=4, steps=30), "alternating"),
+          W.sine_dd(n=65, parts=(2, 2), overlap=4, steps=25),
+          mode(W.shell_dd(n=25, parts=(2, 2, 2), overlap=4, steps=20), "alternating"),
+          mode(W.sine_dd(n=65, parts=(4, 1), overlap=2, steps=40), "coloured"),
+          W.shell_dd(n=29, parts=(2, 2, 1), overlap=4, steps=12)]
+    with B.Context(0, budget_bytes=1 << 30) as c:
+        out = serve_all(c, ws)
+        for w, (state, mesh, st) in zip(ws, out):
+            assert state == B.DONE, st
+            alone, _, _ = c.dd_mesh(w, precision="split16")
+            np.testing.assert_array_equal(mesh, alone)
+
+
 def test_small_budget_queues_but_completes(B):
     ws = small_stream(6)
     with B.Context(0, budget_bytes=24 << 20) as c:
