@@ -895,6 +895,32 @@ __device__ inline void mma_lds_by_basis_k(typename Op<KIND>::acc_t& acc, const c
   }
 }
 
+// the two halves [0, ks) and [ks, ld) at once, into lo and hi: each half's k steps in ascending
+// order as mma_lds_by_basis_k takes them (products with a zero basis fragment past a half's end
+// add exact zeros), with the basis fragments of both halves in flight together
+template <int KIND>
+__device__ inline void mma_lds_by_basis_2h(typename Op<KIND>::acc_t& lo, typename Op<KIND>::acc_t& hi,
+                                           const char* lds, int ks, int ld, int ldo, float sc, const void* bh,
+                                           const void* bl, int ldb, int brow, int l16, int g) {
+  typedef Op<KIND> O;
+  constexpr int U = 2;
+  for (int k0 = 0; k0 < ks; k0 += U * O::KB) {
+    typename O::frag a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * O::KB, kh = ks + k;
+      a[u] = k < ks ? O::glob_frag(bh, bl, ldb, brow, k, g) : O::zero_frag();
+      b[u] = kh < ld ? O::glob_frag(bh, bl, ldb, brow, kh, g) : O::zero_frag();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * O::KB, kh = ks + k;
+      O::mma(lo, O::lds_frag(lds, ldo, l16, k < ks ? k : k0, g, sc), a[u]);
+      O::mma(hi, O::lds_frag(lds, ldo, l16, kh < ld ? kh : k0, g, sc), b[u]);
+    }
+  }
+}
+
 template <int KIND>
 __device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, int ldo, float sc,
                                         const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
@@ -1205,10 +1231,11 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 // In an alternating sweep a destination that is updated later in the same step has not removed
 // this step's shift yet: later = 1 entries add dt * shift back, so every subdomain sees its
 // neighbours' values relative to the same constant.
-// NW = 4: wave w computes column block w over the whole axis.  NW = 8 (launches of few tiles,
-// where a wave's chain of dependent basis loads is the launch's duration): waves w and w + 4 take
-// the two halves of the contraction for column block w, and wave w adds its partner's half
-// through LDS before the update.
+// The contraction is summed as two halves, lo (the first ceil(steps / 2) k steps) + hi, in every
+// form, so the result does not depend on the form a launch takes.  NW = 4: wave w computes both
+// halves of column block w.  NW = 8 (launches of few tiles, where a wave's chain of dependent
+// basis loads is the launch's duration): waves w and w + 4 take the two halves for column block w,
+// and wave w adds its partner's half through LDS before the update.
 // (four waves: at least seven workgroups per compute unit, which the register budget allows, for
 // the launches of many tiles that take this form)
 template <int KIND, int NW>
@@ -1265,7 +1292,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(cons
   const bool active = cb * 16 < C;
   const T isc = T(1) / T(sc);
   // first half: the first ceil(steps / 2) k steps
-  const int ksplit = KS > 1 ? min(ld, ((ld + 2 * O::KB - 1) / (2 * O::KB)) * O::KB) : ld;
+  const int ksplit = min(ld, ((ld + 2 * O::KB - 1) / (2 * O::KB)) * O::KB);
   const int c = cb * 16 + l16;
   acc_t acc = {0, 0, 0, 0};
   T old[4];
@@ -1277,7 +1304,13 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(cons
         old[q] = (r < R && c < C) ? phi[(long)r * C + c] : T(0);
       }
     }
-    mma_lds_by_basis_k<KIND>(acc, lds, kh ? ksplit : 0, kh ? ld : ksplit, ldo, sc, invh, invl, ldb, c, l16, g);
+    if (KS > 1) {
+      mma_lds_by_basis_k<KIND>(acc, lds, kh ? ksplit : 0, kh ? ld : ksplit, ldo, sc, invh, invl, ldb, c, l16, g);
+    } else {
+      acc_t hi = {0, 0, 0, 0};
+      mma_lds_by_basis_2h<KIND>(acc, hi, lds, ksplit, ld, ldo, sc, invh, invl, ldb, c, l16, g);
+      for (int q = 0; q < 4; ++q) acc[q] += hi[q];
+    }
   }
   const T shift = instance_shift<T>(sa, pin, first_sub, d0);
   if (KS > 1) {
@@ -1371,9 +1404,11 @@ __device__ inline RestSig<T> rest_sig(const SubDev& S, int c, int ncol) {
 //                         1 / (1 + sum_k gamma mu_k); the DC coefficient is recorded
 // When the strip and the basis fit in the launch's LDS (lcap bytes), the basis is copied into LDS
 // once (direct-to-LDS loads, in flight together with the strip) and every product reads LDS only.
-// The pair then reuses the forward matrix for the inverse: with D = diag(w) (w = 1/2 at both ends,
-// else 1) the DCT-I matrices satisfy B = (N / 2) D^-1 A D^-1, and the powers of two D^-1 and N / 2
-// fold exactly into the spectral scale and the store.
+// The pair reuses the forward matrix for the inverse, on both paths: with D = diag(w) (w = 1/2 at
+// both ends, else 1) the DCT-I matrices satisfy B = (N / 2) D^-1 A D^-1, and the powers of two D^-1
+// and N / 2 fold exactly into the spectral scale and the store.  The LDS path needs only A in LDS;
+// the global path doing the same keeps the two bitwise equal, so a request's result does not
+// depend on which path its launch takes.
 template <int KIND, bool PAIR, int NW>
 __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
                                                         int src_sel, int lcap, StepArgs sa) {
@@ -1440,8 +1475,6 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
   // vector loads (the copy may write memory, as far as the compiler knows), and each of their
   // waits would also wait for the copy
   const T fwd_unscale = T(A.fwd_unscale);
-  const void* invh = A.inv;
-  const void* invl = A.invl;
   const T g0 = T(S.gh2[0]);
   if (lbasis) {
     lds_dma(lbh, b1h, bbytes, NW);
@@ -1485,8 +1518,8 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
       }
     }
   } else {
-    // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2.
-    // LDS path: also D^-1 (x 2 at i = 0 and i = K - 1) ahead of the forward matrix reused.
+    // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2,
+    // and D^-1 (x 2 at i = 0 and i = K - 1) ahead of the forward matrix reused.
     const T rest = rs.value();
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
@@ -1498,7 +1531,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
           const T val = acc[t][q] * us1;
           if (i == 0 && c == 0) gpw<T>(sa.dc)[tl.x] = val;
           y = val / (T(1) + g0 * sig0[t * 4 + q] + rest);
-          if (lbasis && (i == 0 || i == K - 1)) y *= T(2);
+          if (i == 0 || i == K - 1) y *= T(2);
         }
         acc[t][q] = y;
       }
@@ -1525,9 +1558,9 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
       O::presplit(lds, ldo, 16, ld, &sy, 16);
       __syncthreads();
     }
-    // store scale: 1 / sy, and on the LDS path (N / 2) D^-1 and the split form's 2^-s
+    // store scale: (N / 2) D^-1, the split form's 2^-s and 1 / sy
     const T half_n = T(K - 1) / T(2);
-    const T os = lbasis ? fwd_unscale * half_n / T(sy) : T(1) / T(sy);
+    const T os = fwd_unscale * half_n / T(sy);
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) acc[t] = typename O::acc_t{0, 0, 0, 0};
     if (lbasis) {
@@ -1541,7 +1574,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
 #pragma unroll
       for (int t = 0; t < MAXRB; ++t) {
         const int rb = wave + NW * t;
-        if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], invh, invl, ldb, lds, ld, ldo, sy, rb * 16 + l16, l16, g);
+        if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, ld, ldo, sy, rb * 16 + l16, l16, g);
       }
     }
 #pragma unroll
@@ -1550,7 +1583,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
       if (rb >= nrb) continue;
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
-        if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][q] * ((lbasis && (i == 0 || i == K - 1)) ? T(2) * os : os);
+        if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][q] * ((i == 0 || i == K - 1) ? T(2) * os : os);
       }
     }
   }
@@ -1746,6 +1779,7 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
             const T val = acc[t][cb][q] * us1;
             if (i == 0 && c == 0) gpw<T>(sa.dc)[tl.x] = val;
             y = val / (T(1) + g0 * sig0[t * 4 + q] + rest[cb]);
+            if (i == 0 || i == K - 1) y *= T(2);
           }
           acc[t][cb][q] = y;
           if (O::SCALED) ym[cb] = fmaxf(ym[cb], fabsf((float)y));
@@ -1807,7 +1841,8 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
     for (int t = 0; t < MAXRB; ++t)
 #pragma unroll
       for (int cb = 0; cb < NC; ++cb) acc[t][cb] = typename O::acc_t{0, 0, 0, 0};
-    products(A.inv, A.invl, sy);
+    products(A.fwd, A.fwdl, sy);  // the inverse from the forward matrix, as the 16-column kernel
+    const T fwd_unscale = T(A.fwd_unscale), half_n = T(K - 1) / T(2);
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
       const int rb = wave + 4 * t;
@@ -1815,10 +1850,10 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
 #pragma unroll
       for (int cb = 0; cb < NC; ++cb) {
         const int c = col0 + cb * 16 + l16;
-        const T os = T(1) / T(sy[cb]);
+        const T os = fwd_unscale * half_n / T(sy[cb]);
         for (int q = 0; q < 4; ++q) {
           const int i = rb * 16 + O::crow(g, q);
-          if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][cb][q] * os;
+          if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][cb][q] * ((i == 0 || i == K - 1) ? T(2) * os : os);
         }
       }
     }

@@ -110,6 +110,17 @@ def test_batch_equals_alone_and_oracle(ctx, prec):
         assert err <= TOL[prec]
 
 
+def test_large_batch_equals_alone(ctx):
+    # 160 requests: the batch's launches exceed 512 tiles (four-wave inverse products, global-basis
+    # and 64-column pair strips), each request alone stays below (eight waves, bases in LDS); the
+    # arithmetic is the same either way
+    ws = bump_batch(count=160, steps=8)
+    outs, stats = ctx.dd_mesh_batch(ws, precision="split16")
+    for i in (0, 37, 81, 123, 159):
+        alone, _, _ = ctx.dd_mesh(ws[i], precision="split16")
+        np.testing.assert_array_equal(outs[i], alone)
+
+
 def test_batch_uneven_steps(ctx):
     ws = bump_batch(count=4)
     for i, w in enumerate(ws):
