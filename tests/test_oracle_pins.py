@@ -210,6 +210,40 @@ def test_dd_error_falls_with_overlap():
     assert errs[0] < 3e-3
 
 
+# --- P13: the DD fixed point is the whole-domain discrete steady state (Sec. 3, Sec. 4.4) ---------
+
+@pytest.mark.parametrize("mode", ["parallel", "alternating"])
+def test_dd_fixed_point_is_single_domain_steady_state(mode):
+    # The discrete steady state of the whole-domain scheme has F equal to a constant c (the discrete
+    # integral of rho det differs from theta by O(h^2)), and Psi then drifts by dt*c per step. With
+    # theta scaled by exp(c) the steady state has F = 0 and no drift. A converged DD solve must then
+    # satisfy the whole-domain equation F = 0 at every node of the glued Psi, and its mesh must be
+    # the whole-domain steady mesh: the artificial-face values, the preconditioner's Neumann faces
+    # and the F := 0 rows leave no trace in the fixed point.
+    g = grid2(33)
+    mon = W.ring_monitor(amp=5.0, k=10.0)
+    box = g.whole_box()
+    th = O.theta(mon, g.lo, g.hi)
+    sd0 = O.solve_single(g, mon, 0.05, 1.0, 4000, tol=1e-14)
+    c = float(np.mean(O.rhs_F(sd0.psi, box, mon, th, g.vol)))
+    assert abs(c) > 1e-3     # the drift is real, so the rescaling below is not a no-op
+    th0 = th * math.exp(c)
+    sd = O.solve_single(g, mon, 0.05, 1.0, 4000, tol=1e-15, theta_val=th0)
+    assert np.abs(O.rhs_F(sd.psi, box, mon, th0, g.vol)).max() < 1e-10
+    gam = 4.0 / 32 ** 2
+    dt = 0.2 * gam
+    dd = O.solve_dd(g, (2, 2), (4, 4), mon, dt, gam, 20000, tol=1e-12, mode=mode, theta_val=th0)
+    assert dd.res_hist[-1] <= 1e-12 and dd.steps < 20000
+    F = O.rhs_F(dd.psi, box, mon, th0, g.vol)
+    assert np.abs(F).max() < 1e-7
+    assert np.max(np.abs(dd.mesh - sd.mesh)) < 1e-8
+    # With the unscaled theta the DD iteration also stalls into a uniform drift, but its stationary
+    # state is not the whole-domain one: F then varies near the artificial faces.
+    dd_drift = O.solve_dd(g, (2, 2), (4, 4), mon, dt, gam, 1500, mode=mode, theta_val=th)
+    F1 = O.rhs_F(dd_drift.psi, box, mon, th, g.vol)
+    assert F1.max() - F1.min() > 1e-4
+
+
 # --- P7 / P8 / P9: boundary, symmetry, positivity ---------------------------------------------
 
 def test_ring_mesh_boundary_symmetry_positivity():
