@@ -181,3 +181,27 @@ def test_dd_error_falls_with_overlap_on_gpu(ctx, prec):
     print(prec, "DD - single by overlap 4/8/16:", errs)
     assert errs[0] > errs[1] > errs[2] > 0
     assert errs[0] / errs[2] > 3.0
+
+
+@pytest.mark.parametrize("mode", ["parallel", "alternating"])
+@pytest.mark.parametrize("prec", ["fp64", "split16"])
+def test_dd_fixed_point_is_whole_domain_steady_state_on_gpu(ctx, mode, prec):
+    # Sec. 3 / Sec. 4.4: with theta scaled so that the whole-domain steady state has F = 0 (no
+    # drift), the converged DD mesh of the GPU is the oracle's whole-domain steady mesh; the
+    # artificial faces leave no trace in the fixed point
+    n = 33
+    g = O.GridSpec((n, n), (0.0, 0.0), (1.0, 1.0))
+    mon = W.ring_monitor(amp=5.0, k=10.0)
+    box = g.whole_box()
+    th = O.theta(mon, g.lo, g.hi)
+    sd0 = O.solve_single(g, mon, 0.05, 1.0, 4000, tol=1e-14)
+    th0 = th * math.exp(float(np.mean(O.rhs_F(sd0.psi, box, mon, th, g.vol))))
+    sd = O.solve_single(g, mon, 0.05, 1.0, 4000, tol=1e-15, theta_val=th0)
+    gam = 4.0 / (n - 1) ** 2
+    w = {"name": "ring33", "grid": W.grid([n, n]), "monitor": mon,
+         "dd": {"parts": [2, 2], "overlap": [4, 4], "mode": mode},
+         "time": {"dt": 0.2 * gam, "gamma": gam, "steps": 1500}}
+    mesh, _, st = ctx.dd_mesh(w, precision=prec, theta_override=th0)
+    err = float(np.max(np.abs(mesh - sd.mesh)))
+    print(f"{mode} {prec}: |DD mesh - whole-domain steady mesh| = {err:.3e}")
+    assert err <= (1e-8 if prec == "fp64" else 1e-5)
