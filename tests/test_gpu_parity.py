@@ -110,3 +110,43 @@ def test_shell_3d_dd_vs_oracle(ctx, prec):
     print(f"shell25 2x2x2 {prec}: max mesh err {err:.3e}")
     assert err <= TOL[prec], err
     assert st["min_det"] > 0 and st["min_cell"] > 0
+
+
+# --- edge shapes: the longest subdomain axis the kernels take (545 nodes, a ragged 34 x 16 + 1)
+# along each axis in turn, against a short one; and the smallest subdomains (4 cells, overlap 2)
+
+def smooth_ring(n, steps):
+    return {"name": "ring_" + "x".join(map(str, n)), "grid": W.grid(list(n)), "dd": None,
+            "monitor": W.ring_monitor(d=len(n), amp=5.0, k=10.0),
+            "time": {"dt": 1e-3, "gamma": 1.0, "steps": steps}}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
+@pytest.mark.parametrize("n", [(545, 37), (37, 545), (545, 9, 9), (9, 545, 9), (9, 9, 545)])
+def test_longest_axis_vs_oracle(ctx, n, prec):
+    w = smooth_ring(n, 100)
+    mesh, _, st = ctx.dd_mesh(w, precision=prec)
+    ref = oracle_of(w["name"], w)
+    err = np.max(np.abs(mesh - ref.mesh)) / extent(w)
+    print(f"{w['name']} {prec}: max mesh err {err:.3e}")
+    assert err <= TOL[prec], err
+    assert st["min_det"] > 0 and st["min_cell"] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
+@pytest.mark.parametrize("shape", [((13, 13), "parallel"), ((13, 13), "alternating"), ((13, 13, 13), "parallel")])
+def test_smallest_subdomains_vs_oracle(ctx, shape, prec):
+    # 12 cells in 4 parts with overlap 2: subdomains of 4, 5, 5 and 4 cells per axis
+    n, mode = shape
+    d = len(n)
+    g = W.grid(list(n))
+    w = {"name": f"min_{d}d_{mode}", "grid": g, "monitor": W.ring_monitor(d=d, amp=5.0, k=10.0),
+         "dd": {"parts": [4] * d, "overlap": [2] * d, "mode": mode},
+         "time": dict(W.dd_defaults(g), steps=40 if d == 2 else 30)}
+    mesh, _, st = ctx.dd_mesh(w, precision=prec)
+    t = w["time"]
+    ref = O.solve_dd(gspec(w), w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], t["steps"],
+                     mode=mode)
+    err = np.max(np.abs(mesh - ref.mesh)) / extent(w)
+    print(f"{w['name']} {prec}: max mesh err {err:.3e}")
+    assert err <= TOL[prec], err
