@@ -217,6 +217,27 @@ def test_warm_start_and_psi_out(ctx):
         assert np.max(np.abs(psi - ref.psi)) <= (1e-11 if prec == "fp64" else 2e-6)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
+def test_degenerate_inputs(ctx, prec):
+    # an empty batch is a no-op; zero steps return the mesh of Psi^0 itself: the identity from the
+    # default start (bitwise, single domain and decomposed, 2D and 3D), the warm start's gradient
+    outs, stats = ctx.dd_mesh_batch([], precision=prec)
+    assert outs == [] and stats == []
+    ring = W.ring(steps=0)
+    ring["grid"] = W.grid([33, 33])
+    cases = [ring, W.sine_dd(n=65, parts=(2, 2), overlap=4, steps=0), W.shell_dd(n=17, parts=(2, 2, 2), overlap=4, steps=0)]
+    for w in cases:
+        mesh, _, st = ctx.dd_mesh(w, precision=prec)
+        assert st["steps_done"] == 0
+        np.testing.assert_array_equal(mesh, np.moveaxis(gspec(w).whole_box().coords(), -1, 0))
+    w = W.ring(steps=30)
+    w["grid"] = W.grid([49, 49])
+    psi0 = oracle_run(w).psi
+    mesh, _, st = ctx.dd_mesh(dict(w, time=dict(w["time"], steps=0)), precision=prec, psi0=psi0)
+    assert st["steps_done"] == 0
+    assert np.max(np.abs(mesh - O.mesh_from_psi(psi0, gspec(w).whole_box()))) <= TOL[prec]
+
+
 def test_psi_out_dd_matches_oracle(ctx):
     w = W.sine_dd(n=65, parts=(2, 2), overlap=4, steps=40)
     ref = oracle_run(w)
