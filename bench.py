@@ -55,7 +55,8 @@ def traffic_of(workload, phase):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0   # full-rate wave instructions per second
 KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil_fwd2_kernel / stencil2_kernel / stencil3_kernel",
           "euler": "euler_kernel",
-          "fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel<single>", "pair0": "strip_kernel<pair>",
+          "fwd_last": "fwd_last_kernel", "fwd_mid": "strip_kernel<single>",
+          "pair0": "strip_kernel<pair> (16-column strips) / strip4_kernel<pair> (64-column strips)",
           "inv_mid": "strip_kernel<single>", "inv_last": "inv_last_kernel"}
 
 
@@ -171,6 +172,33 @@ def roofline_of(phases, prec, workload=None):
             "algorithmic_per_launch": ph["bytes"], "avg_launch_ms": ph["ms"]}
 
 
+def shell_bench(ctx, binding, workloads, steps, warmup):
+    """129^3 spherical shell, 2x2x2 subdomains, overlap 6 cells, batched split form."""
+    r = timed_plan(ctx, binding, [workloads.shell_dd()], "split16", "batched", steps, warmup, phase_reps=10,
+                   tune=True)
+    log(f"shell 129^3 split16: {r['updates_per_s']:.3e}")
+    return {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"], "stencil_march": r["stencil_march"],
+            "roofline": roofline_of(r["phases"], "split16", "shell_dd_129_split16"),
+            "phases_ms_per_launch": {p: round(v["ms"], 5) for p, v in r["phases"].items()}}
+
+
+def batch_bench(ctx, binding, workloads, steps, warmup, plain):
+    """256 single-domain instances of uneven sides (33..257) with Gaussian-bump monitors, batched
+    split form; plain: also the plain FP64 method on the same instances."""
+    batch = workloads.bumps_batch()
+    rb = timed_plan(ctx, binding, batch, "split16", "batched", steps, warmup, phase_reps=10, tune=True)
+    out = {"batched_split16_updates_per_s": rb["updates_per_s"], "batched_ms_per_step": rb["ms_per_step"],
+           "stencil_march": rb["stencil_march"],
+           "roofline": roofline_of(rb["phases"], "split16", "bumps_batch_256_split16"),
+           "phases_ms_per_launch": {p: round(v["ms"], 5) for p, v in rb["phases"].items()}}
+    if plain:
+        rp = timed_plan(ctx, binding, batch, "fp64", "plain", 10, 1)
+        out.update({"plain_fp64_updates_per_s": rp["updates_per_s"], "plain_ms_per_step": rp["ms_per_step"],
+                    "speedup": rb["updates_per_s"] / rp["updates_per_s"]})
+        log(f"batch 256: {rb['updates_per_s']:.3e} vs plain fp64 {rp['updates_per_s']:.3e}")
+    return out
+
+
 def stencil_roofline(ctx, binding, workloads):
     """Stencil phase alone over two 8193^2 DD requests (32 x 32 parts): 134 M nodes, 1.07 GB of
     compulsory FP32 traffic per launch, far beyond the 256 MB last-level cache."""
@@ -274,8 +302,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve", type=int, default=600, help="requests in the serving stream (0: skip)")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["split16", "fp32", "fp64plain", "stencil_large", "paper"], default=None,
-                    help="time one form of the headline workload only (profiler runs)")
+    ap.add_argument("--only", choices=["split16", "fp32", "fp64plain", "stencil_large", "paper", "shell", "batch"], default=None,
+                    help="one form of the headline workload, or one other workload, only (profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 10 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -298,6 +326,15 @@ def main():
     if args.only == "paper":
         ctx = binding.Context(0, budget_bytes=12 << 30)
         print(json.dumps({"paper_workloads": paper_workloads(ctx, binding, workloads)}))
+        ctx.close()
+        return
+    if args.only in ("shell", "batch"):
+        ctx = binding.Context(0, budget_bytes=12 << 30)
+        if args.only == "shell":
+            r = {"shell_dd_129_split16": shell_bench(ctx, binding, workloads, args.steps, args.warmup)}
+        else:
+            r = {"bumps_batch_256": batch_bench(ctx, binding, workloads, args.steps, args.warmup, plain=False)}
+        print(json.dumps(r))
         ctx.close()
         return
     if args.only == "stencil_large":
@@ -344,23 +381,8 @@ def main():
         r = timed_plan(ctx, binding, [ring], "fp64", "batched", 200, 10)
         extra["ring_65_fp64"] = {k: r[k] for k in ("updates_per_s", "ms_per_step")}
         log(f"ring 65^2 fp64: {r['updates_per_s']:.3e}")
-        shell = workloads.shell_dd()
-        r = timed_plan(ctx, binding, [shell], "split16", "batched", 200, 5, phase_reps=10, tune=True)
-        extra["shell_dd_129_split16"] = {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"],
-                                         "stencil_march": r["stencil_march"],
-                                         "roofline": roofline_of(r["phases"], "split16")}
-        log(f"shell 129^3 split16: {r['updates_per_s']:.3e}")
-        batch = workloads.bumps_batch()
-        rb = timed_plan(ctx, binding, batch, "split16", "batched", 200, 5, phase_reps=10, tune=True)
-        rp = timed_plan(ctx, binding, batch, "fp64", "plain", 10, 1)
-        extra["bumps_batch_256"] = {"batched_split16_updates_per_s": rb["updates_per_s"],
-                                    "batched_ms_per_step": rb["ms_per_step"],
-                                    "plain_fp64_updates_per_s": rp["updates_per_s"],
-                                    "plain_ms_per_step": rp["ms_per_step"],
-                                    "speedup": rb["updates_per_s"] / rp["updates_per_s"],
-                                    "stencil_march": rb["stencil_march"],
-                                    "roofline": roofline_of(rb["phases"], "split16")}
-        log(f"batch 256: {rb['updates_per_s']:.3e} vs plain fp64 {rp['updates_per_s']:.3e}")
+        extra["shell_dd_129_split16"] = shell_bench(ctx, binding, workloads, 200, 5)
+        extra["bumps_batch_256"] = batch_bench(ctx, binding, workloads, 200, 5, plain=True)
         extra["stencil_hbm_large"] = stencil_roofline(ctx, binding, workloads)
         log(f"stencil large: {extra['stencil_hbm_large']['achieved']:.0f} GB/s")
         out["other_workloads"] = extra
