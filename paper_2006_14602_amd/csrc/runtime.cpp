@@ -1190,7 +1190,12 @@ struct Batch {
   size_t pinned_cap = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  bool use_graph = true;  // replay one captured step; false: launch the phases directly
+  // kGraphSteps steps captured back to back in one graph: runs of steps replay it, so the host
+  // submits one graph per kGraphSteps steps; the remainder replays the one-step graph
+  static constexpr int kGraphSteps = 8;
+  hipGraph_t graph_n = nullptr;
+  hipGraphExec_t gexec_n = nullptr;
+  bool use_graph = true;  // replay captured steps; false: launch the phases directly
   StepArgs sa{};
 
   size_t dcap = 0;  // capacity of dmem: launch tables live outside the request arena
@@ -1204,11 +1209,19 @@ struct Batch {
 
   // forget the launch set (the table buffer is kept for the next build)
   void clear_device() {
+    drop_graphs();
+    built = false;
+  }
+
+  void drop_graphs() {
     if (gexec) hipGraphExecDestroy(gexec);
     if (graph) hipGraphDestroy(graph);
+    if (gexec_n) hipGraphExecDestroy(gexec_n);
+    if (graph_n) hipGraphDestroy(graph_n);
     gexec = nullptr;
     graph = nullptr;
-    built = false;
+    gexec_n = nullptr;
+    graph_n = nullptr;
   }
   bool built = false;
 
@@ -1281,10 +1294,7 @@ struct Batch {
     if (t.h.size() > st_cap) thr(PMA_E_HIP, "stencil table exceeds its buffer");
     HIPCHK(hipMemcpyAsync(t.d, t.h.data(), t.h.size() * 16, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (graph) hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
+    drop_graphs();
   }
   size_t st_cap = 0;
 
@@ -1733,19 +1743,20 @@ struct Batch {
     }
   }
 
-  void capture() {
+  // nsteps steps of the batched launches, captured in order into one graph
+  void capture(int nsteps, hipGraph_t& g_out, hipGraphExec_t& e_out) {
     hipStream_t st = ctx->stream;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
-      launch_step(false, st);
+      for (int k = 0; k < nsteps; ++k) launch_step(false, st);
     } catch (...) {
       hipGraph_t g = nullptr;
       hipStreamEndCapture(st, &g);
       if (g) hipGraphDestroy(g);
       throw;
     }
-    HIPCHK(hipStreamEndCapture(st, &graph));
-    HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    HIPCHK(hipStreamEndCapture(st, &g_out));
+    HIPCHK(hipGraphInstantiate(&e_out, g_out, nullptr, nullptr, 0));
   }
 
   void step(bool plain) {
@@ -1753,9 +1764,20 @@ struct Batch {
     if (plain || !use_graph) {
       launch_step(plain, st);
     } else {
-      if (!gexec) capture();
+      if (!gexec) capture(1, graph, gexec);
       HIPCHK(hipGraphLaunch(gexec, st));
     }
+  }
+
+  // nsteps steps: the same launches in the same order as nsteps calls of step()
+  void steps(bool plain, int nsteps) {
+    if (!plain && use_graph) {
+      for (; nsteps >= kGraphSteps; nsteps -= kGraphSteps) {
+        if (!gexec_n) capture(kGraphSteps, graph_n, gexec_n);
+        HIPCHK(hipGraphLaunch(gexec_n, ctx->stream));
+      }
+    }
+    for (; nsteps > 0; --nsteps) step(plain);
   }
 
   // residual + status to pinned host memory (asynchronous)
@@ -1870,7 +1892,7 @@ static void run_to_end(pma_ctx* c, const std::vector<Instance*>& all, int prec, 
         if (I->tm.tol > 0) R = std::min(R, std::max(1, I->tm.resid_every) - I->steps_done % std::max(1, I->tm.resid_every));
       }
       chunk = std::max(0, std::min(chunk, R));
-      for (int k = 0; k < chunk; ++k) B.step(plain);
+      B.steps(plain, chunk);
       for (auto* I : live) I->steps_done += chunk;
       B.read_progress();
       HIPCHK(hipStreamSynchronize(st));
@@ -2062,9 +2084,8 @@ struct Server {
       }
     }
     chunk = std::max(0, std::min(chunk, max_chunk));
-    for (int k = 0; k < chunk; ++k)
-      for (int p = 0; p < 3; ++p)
-        if (batch[p] && !batch[p]->insts.empty()) batch[p]->step(false);
+    for (int p = 0; p < 3; ++p)  // the batches share no data: each takes its run of steps in turn
+      if (batch[p] && !batch[p]->insts.empty()) batch[p]->steps(false, chunk);
     for (auto* I : running) I->steps_done += chunk;
     for (int p = 0; p < 3; ++p)
       if (batch[p] && !batch[p]->insts.empty()) batch[p]->read_progress();
@@ -2515,7 +2536,7 @@ int pma_plan_step(pma_plan* P, int nsteps) {
   API_BEGIN
   if (!P || nsteps < 0) return fail(PMA_E_INVAL, "bad arguments");
   std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
-  for (int k = 0; k < nsteps; ++k) P->batch->step(P->plain);
+  P->batch->steps(P->plain, nsteps);
   for (auto& I : P->insts) I->steps_done += nsteps;
   return PMA_OK;
   API_END
