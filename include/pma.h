@@ -256,7 +256,7 @@ int pma_plan_phase_times(pma_plan* plan, int nsteps, double* ms, double* flops, 
  * in flight, shorter ones give more workgroups.  Candidates march = 1, 2, 4, .. 64 (capped at
  * the longest useful value) are each timed over `reps` back-to-back launches on the plan's own
  * state between two HIP events; the fastest is kept for every later step (the captured step
- * graph is rebuilt).  The stencil reads phi and writes only F, which every step recomputes,
+ * graphs are rebuilt).  The stencil reads phi and writes only F, which every step recomputes,
  * so the results of the plan do not change (bitwise).  *march receives the choice; ms[k]
  * (may be NULL, cap entries) the mean milliseconds per launch of candidate k; *ncand (may be
  * NULL) the number of candidates timed.  Errors: PMA_E_INVAL for a NULL plan or march, or

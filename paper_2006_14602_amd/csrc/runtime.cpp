@@ -1280,7 +1280,7 @@ struct Batch {
     return (int)std::max<size_t>(1, std::min<size_t>(64, t1 / 8192));
   }
   // the stencil tile table rebuilt for another march length (same device buffer: march 1 is the
-  // largest table); the captured step is dropped
+  // largest table); the captured step graphs are dropped
   void set_stencil_march(int march) {
     st_march = march;
     Table& t = tab[1];
@@ -2041,7 +2041,7 @@ struct Server {
   // request finishes) while the queue waits for memory
   static constexpr int kShortTick = 8, kLongTick = 64;
 
-  // membership changed: rebuild the launch tables in place; the step is captured as a graph and
+  // membership changed: rebuild the launch tables in place; the steps are captured as graphs and
   // replayed for the rest of the membership
   void rebuild() {
     hipStream_t st = ctx->stream;
