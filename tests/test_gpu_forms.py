@@ -298,6 +298,35 @@ def test_boundary_nodes_exact_and_ring_symmetry(ctx, prec):
     assert st["min_det"] > 0 and st["min_cell"] > 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "split16"])
+@pytest.mark.parametrize("parts", [None, (2, 2, 2)])
+def test_shell_3d_boundary_and_cube_symmetry(ctx, prec, parts):
+    # the spherical shell about the cube's centre: boundary nodes stay on their faces, and the mesh
+    # keeps the cube's symmetries (reflections, exchange of two axes), single domain and on a
+    # mirror-symmetric 2 x 2 x 2 decomposition
+    n = 25
+    w = W.shell_dd(n=n, parts=parts or (2, 2, 2), overlap=6, steps=30)
+    if parts is None:
+        w["dd"] = None
+        w["time"] = {"dt": 1e-3, "gamma": 1.0, "steps": 30}
+    mesh, _, st = ctx.dd_mesh(w, precision=prec)
+    x, y, z = mesh
+    assert np.all(x[0] == 0.0) and np.all(x[-1] == 1.0)
+    assert np.all(y[:, 0] == 0.0) and np.all(y[:, -1] == 1.0)
+    assert np.all(z[:, :, 0] == 0.0) and np.all(z[:, :, -1] == 1.0)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    refl = np.abs(x - (1.0 - x[::-1]))
+    if parts:
+        # the middle plane i = 12 is owned by the upper part, so its x is that part's value, not the
+        # mean of the two mirrored parts: the reflection holds on every other plane
+        refl = np.delete(refl, (n - 1) // 2, axis=0)
+    assert np.max(refl) < tol
+    assert np.max(np.abs(x - np.transpose(y, (1, 0, 2)))) < tol
+    assert np.max(np.abs(x - np.transpose(z, (2, 1, 0)))) < tol
+    assert np.max(np.abs(x - x[:, ::-1, :])) < tol
+    assert st["min_det"] > 0 and st["min_cell"] > 0
+
+
 def test_tangled_mesh_reports_error(ctx, B):
     w = W.ring(steps=100)
     w["time"] = {"dt": 10.0 / 64 ** 2, "gamma": 0.0, "steps": 100}
