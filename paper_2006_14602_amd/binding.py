@@ -86,6 +86,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} not found: build it with __graft_entry__.build()")
+    # torch first: it brings its own HIP runtime under the same soname as the one the library links,
+    # and a process holds one of them, whichever loads first; torch's CUDA state fails to come up on
+    # the other one
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.pma_last_error.restype = ctypes.c_char_p
     L.pma_create.argtypes = [c_int, c_size_t, POINTER(c_void_p)]
@@ -276,12 +280,16 @@ class Context:
         L = load()
         self._L = L
         self.device = device
+        if use_torch_allocator:
+            import torch
+            # torch's CUDA state is set up here, on the caller's thread: the library's serving
+            # thread may be the first to allocate through the callbacks below
+            torch.cuda.init()
         h = c_void_p()
         _check(L.pma_create(device, budget_bytes, ctypes.byref(h)))
         self.h = h
         self._cbs = None
         if use_torch_allocator:
-            import torch
             alloc = torch.cuda.caching_allocator_alloc
             delete = torch.cuda.caching_allocator_delete
 

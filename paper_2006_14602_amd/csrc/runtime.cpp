@@ -1981,7 +1981,9 @@ struct Server {
         }
         alloc_instance(ctx, *I);
       } catch (Err& e) {
-        if (e.code == PMA_E_NOMEM) {  // fragmented or full: wait for frees
+        // fragmented or full: wait for running requests to free memory; with none running no
+        // memory will come free (the arena itself could not be had), so the request fails
+        if (e.code == PMA_E_NOMEM && !running.empty()) {
           blocked = true;
           break;
         }

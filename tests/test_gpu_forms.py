@@ -9,6 +9,7 @@ Exact (bitwise) checks where the arithmetic is the same by construction:
 Oracle checks (tolerance per precision) for everything else.
 """
 import math
+import os
 import time
 
 import numpy as np
@@ -405,6 +406,34 @@ def test_served_sweep_forms_equal_alone(B):
             assert state == B.DONE, st
             alone, _, _ = c.dd_mesh(w, precision="split16")
             np.testing.assert_array_equal(mesh, alone)
+
+
+def test_serving_as_first_gpu_use_in_a_process():
+    # a fresh process whose first GPU work is the serving thread's arena allocation through torch's
+    # allocator: the requests complete (no torch use before the context is created)
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, time\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "from paper_2006_14602_amd import binding, workloads as W\n"
+        "c = binding.Context(0, budget_bytes=1 << 28)\n"
+        "ws = [W.ring(steps=20), W.sine_dd(n=65, parts=(2, 2), overlap=4, steps=20)]\n"
+        "ts = [c.submit(w, 'split16') for w in ws]\n"
+        "left, t0 = set(range(len(ts))), time.time()\n"
+        "while left and time.time() - t0 < 60:\n"
+        "    for i in list(left):\n"
+        "        st, _, _ = c.poll(ts[i])\n"
+        "        if st in (2, 3):\n"
+        "            assert st == 2, (i, st)\n"
+        "            left.discard(i)\n"
+        "    time.sleep(0.002)\n"
+        "assert not left, left\n"
+        "c.close()\n"
+        "print('served', flush=True)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=150)
+    assert r.returncode == 0 and "served" in r.stdout, r.stderr[-2000:]
 
 
 def test_small_budget_queues_but_completes(B):
