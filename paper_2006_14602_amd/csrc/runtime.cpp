@@ -2041,7 +2041,7 @@ struct Server {
 
   // steps per tick: short while arrivals could be admitted, long (ending when the first running
   // request finishes) while the queue waits for memory
-  static constexpr int kShortTick = 16, kLongTick = 64;
+  static constexpr int kShortTick = 32, kLongTick = 64;
 
   // membership changed: rebuild the launch tables in place; the steps are captured as graphs and
   // replayed for the rest of the membership
