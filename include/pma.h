@@ -305,8 +305,17 @@ int pma_submit(pma_ctx* ctx, const pma_request* req, uint64_t* ticket);
  * FAILED also retires it (st->status holds the cause). */
 int pma_poll(pma_ctx* ctx, uint64_t ticket, int* state, double* mesh_out, pma_stats* st);
 
-/* Server counters: requests queued, running, finished; device bytes in use by requests. */
+/* Server counters: requests queued, running, finished (done or failed, retired or not); device
+ * bytes of the context's arena in use (request state and cached DCT bases) as of the server's
+ * last admission or release. */
 int pma_server_info(pma_ctx* ctx, int* queued, int* running, int* finished, size_t* bytes_in_use);
+
+/* Device bytes a request occupies in a context's arena while it runs: its state arrays, mesh,
+ * Psi and reduction partials, plus every DCT basis it uses (bases are shared between requests of
+ * the same axis lengths and precision, and kept as an evictable cache afterwards).  pma_submit
+ * refuses requests above the budget by this count (PMA_E_BUDGET).  Host only.  Errors:
+ * PMA_E_INVAL for a NULL argument or an invalid request (as pma_dd_mesh). */
+int pma_request_bytes(const pma_request* req, size_t* bytes);
 
 /* ---- host-only helpers (no GPU needed) ------------------------------------------------------ */
 

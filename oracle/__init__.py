@@ -4,7 +4,7 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg use this pa
 product library never imports it and shares no code with it.
 """
 from .pma_oracle import (  # noqa: F401
-    Box, Decomposition, GridSpec, Result, TangledError, assemble_neumann_laplacian_1d,
+    Box, Decomposition, GridSpec, NonFiniteError, Result, TangledError, assemble_neumann_laplacian_1d,
     derivatives, det_sym, equidistribution_exact_sech2, ghost_pad, initial_psi, mesh_from_psi,
     min_cell_measure, min_det_hessian, neumann_mu, owner_axis, partition_axis, precondition,
     grad_u, quality, quality_of_mesh, rel_errors, rhs_F, rho, solve_dd, solve_single, step_box, sweep_order, theta,

@@ -52,6 +52,11 @@ class TangledError(ArithmeticError):
     """det D^2_h Psi <= 0 somewhere: log of a non-positive number (the mesh has folded)."""
 
 
+class NonFiniteError(ArithmeticError):
+    """The right-hand side of eq. pmae is not a finite real number somewhere (a monitor that is
+    not positive, or an overflow): the log has no real value."""
+
+
 # ----------------------------------------------------------------------------------------
 # Monitor functions rho(x).  A monitor is a plain dict (see the workload generators).
 # ----------------------------------------------------------------------------------------
@@ -421,7 +426,7 @@ def det_sym(hess, d: int) -> np.ndarray:
 def rhs_F(psi: np.ndarray, box: Box, mon: dict, theta_val: float, vol: float):
     """F = log(|Omega_c| rho(grad_h Psi) det D^2_h Psi / theta)  (eq. pmae with the
     normalisation of eq. edp), F := 0 on artificial-boundary nodes.  Raises TangledError where
-    the determinant is not positive."""
+    the determinant is not positive, NonFiniteError where F is not a finite real number."""
     grad, hess = derivatives(psi, box)
     det = det_sym(hess, box.d)
     art = box.artificial_mask()
@@ -430,7 +435,10 @@ def rhs_F(psi: np.ndarray, box: Box, mon: dict, theta_val: float, vol: float):
         raise TangledError("det D^2_h Psi <= 0")
     X = np.stack(grad, axis=-1)
     F = np.zeros(psi.shape)
-    F[live] = np.log(vol * rho(mon, X[live]) * det[live] / theta_val)
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        F[live] = np.log(vol * rho(mon, X[live]) * det[live] / theta_val)
+    if not np.all(np.isfinite(F)):
+        raise NonFiniteError("F is not finite")
     return F
 
 

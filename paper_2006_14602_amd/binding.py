@@ -103,6 +103,7 @@ def load():
     L.pma_submit.argtypes = [c_void_p, POINTER(Request), POINTER(c_uint64)]
     L.pma_poll.argtypes = [c_void_p, c_uint64, POINTER(c_int), POINTER(c_double), POINTER(Stats)]
     L.pma_server_info.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_size_t)]
+    L.pma_request_bytes.argtypes = [POINTER(Request), POINTER(c_size_t)]
     L.pma_partition.argtypes = [POINTER(Grid), POINTER(DD), c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
     L.pma_sweep_levels.argtypes = [POINTER(Grid), POINTER(DD), c_int, POINTER(c_int), POINTER(c_int)]
     L.pma_theta.argtypes = [POINTER(Grid), POINTER(Monitor), POINTER(c_double)]
@@ -245,6 +246,15 @@ def sweep_levels(grid: dict, dd: dict) -> np.ndarray:
     out = (c_int * n.value)()
     _check(L.pma_sweep_levels(ctypes.byref(G), ctypes.byref(D), n.value, ctypes.byref(n), out))
     return np.array(out[:], dtype=np.int64)
+
+
+def request_bytes(w: dict, precision="fp32") -> int:
+    """Device bytes the request occupies while served (state plus every DCT basis it uses)."""
+    L = load()
+    R = make_request(w, precision, "batched")
+    out = c_size_t()
+    _check(L.pma_request_bytes(ctypes.byref(R), ctypes.byref(out)))
+    return out.value
 
 
 def theta(grid: dict, mon: dict) -> float:

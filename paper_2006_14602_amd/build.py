@@ -25,15 +25,21 @@ def _run(cmd):
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    objs, procs = [], []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    # the two translation units compile concurrently
     for src, dev in (("kernels.hip", True), ("runtime.cpp", False)):
         obj = os.path.join(HERE, "_build", src + ".o")
         cmd = [HIPCC] + COMMON + (DEVICE_FLAGS if dev else []) + ["-c", os.path.join(CSRC, src), "-o", obj]
-        out = _run(cmd)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    for cmd, p in procs:
+        raw, _ = p.communicate()
+        out = "\n".join(l for l in raw.splitlines() if "packed-fp32-ops" not in l)
+        if p.returncode != 0:
+            raise RuntimeError(f"build failed: {' '.join(cmd)}\n{out}")
         if verbose and out:
             print(out)
-        objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)

@@ -981,6 +981,21 @@ static size_t new_basis_bytes(pma_ctx* c, const Instance& I) {
   return b;
 }
 
+// bytes of cached bases that no request uses and the request I does not need: arena_alloc
+// evicts them when it runs out of room, so they count as free when admitting I
+static size_t evictable_basis_bytes(pma_ctx* c, const Instance& I) {
+  std::vector<int> mine;
+  if (I.tm.gamma != 0.0) mine = distinct_axis_sizes(I);
+  size_t b = 0;
+  for (auto& kv : c->bases) {
+    const Basis* B = kv.second;
+    if (B->refs != 0) continue;
+    if (B->prec == I.prec && std::find(mine.begin(), mine.end(), B->n) != mine.end()) continue;
+    b += Arena::round(B->bytes);
+  }
+  return b;
+}
+
 static size_t all_basis_bytes(const Instance& I) {
   if (I.tm.gamma == 0.0) return 0;
   size_t b = 0;
@@ -1938,6 +1953,7 @@ struct Server {
   std::unordered_map<uint64_t, Instance*> all; // every live ticket
   std::unordered_map<uint64_t, int> state;
   int finished = 0;
+  size_t arena_used = 0;                       // arena bytes in use, published under mu
   std::unique_ptr<Batch> batch[3];             // per precision
   bool dirty = true;
 
@@ -1975,24 +1991,30 @@ struct Server {
       std::lock_guard<std::recursive_mutex> cg(ctx->mu);
       try {
         ensure_arena(ctx);
-        if (ctx->arena.used() + need > ctx->arena.size()) {
+        // cached bases nobody uses are evicted by the allocation itself, so they do not block
+        if (ctx->arena.used() - evictable_basis_bytes(ctx, *I) + need > ctx->arena.size()) {
           blocked = true;
+          arena_used = ctx->arena.used();
           break;
         }
         alloc_instance(ctx, *I);
       } catch (Err& e) {
         // fragmented or full: wait for running requests to free memory; with none running no
-        // memory will come free (the arena itself could not be had), so the request fails
+        // memory will come free (the allocation has already evicted every unused basis), so
+        // the request fails
         if (e.code == PMA_E_NOMEM && !running.empty()) {
           blocked = true;
+          arena_used = ctx->arena.used();
           break;
         }
         I->status = e.code;
         I->t_done = now_s();
         state[I->ticket] = PMA_FAILED;
         queue.pop_front();
+        finished++;
         continue;
       }
+      arena_used = ctx->arena.used();
       queue.pop_front();
       I->t_admit = now_s();
       running.push_back(I);
@@ -2032,6 +2054,7 @@ struct Server {
           free_instance(ctx, *I);
           finished++;
         }
+        arena_used = ctx->arena.used();
         running.clear();
         for (auto& b : batch) b.reset();
         dirty = true;
@@ -2139,6 +2162,7 @@ struct Server {
       free_instance(ctx, *I);
       finished++;
     }
+    arena_used = ctx->arena.used();
     if (!queue.empty()) admit_locked();
   }
 };
@@ -2744,9 +2768,8 @@ int pma_plan_destroy(pma_plan* P) {
   API_END
 }
 
-int pma_submit(pma_ctx* c, const pma_request* req, uint64_t* ticket) {
-  API_BEGIN
-  if (!c || !req || !ticket) return fail(PMA_E_INVAL, "NULL argument");
+// a request's instance with its plan built (validates the request)
+static std::unique_ptr<Instance> planned_request(const pma_request* req) {
   std::unique_ptr<Instance> I(new Instance);
   I->grid = req->grid;
   I->dd = req->dd;
@@ -2755,6 +2778,22 @@ int pma_submit(pma_ctx* c, const pma_request* req, uint64_t* ticket) {
   I->tm = req->time;
   I->arrival_s = req->arrival_s;
   build_plan(*I);
+  return I;
+}
+
+int pma_request_bytes(const pma_request* req, size_t* bytes) {
+  API_BEGIN
+  if (!req || !bytes) return fail(PMA_E_INVAL, "NULL argument");
+  std::unique_ptr<Instance> I = planned_request(req);
+  *bytes = Arena::round(instance_bytes(*I)) + all_basis_bytes(*I);
+  return PMA_OK;
+  API_END
+}
+
+int pma_submit(pma_ctx* c, const pma_request* req, uint64_t* ticket) {
+  API_BEGIN
+  if (!c || !req || !ticket) return fail(PMA_E_INVAL, "NULL argument");
+  std::unique_ptr<Instance> I = planned_request(req);
   // budget check without the context lock (the server thread holds it while it steps): the
   // bound counts every DCT basis the request uses, cached or not
   const size_t need = Arena::round(instance_bytes(*I)) + all_basis_bytes(*I);
@@ -2821,7 +2860,7 @@ int pma_server_info(pma_ctx* c, int* queued, int* running, int* finished, size_t
   if (queued) *queued = (int)s->queue.size();
   if (running) *running = (int)s->running.size();
   if (finished) *finished = s->finished;
-  if (bytes) *bytes = c->arena.used();
+  if (bytes) *bytes = s->arena_used;
   return PMA_OK;
   API_END
 }

@@ -149,3 +149,19 @@ def test_arclen_theta_matches_oracle(L, case):
     got = B.theta(g, mon)
     want = O.theta(mon, g["lo"], g["hi"])
     assert abs(got - want) <= tol * want, (got, want)
+
+
+@pytest.mark.parametrize("name,tol", [("burgers_front_65", 1e-12), ("spiral_257", 5e-7), ("sphere_81", 1e-12),
+                                      ("spheres9_81", 1e-5), ("sine_dd_513", 1e-12)])
+def test_library_theta_at_full_size_matches_golden(L, name, tol):
+    # the library's own theta for the benchmarked workloads against the theta the oracle used
+    # for the golden meshes (the nine spheres' golden theta came from a coarser tensor rule)
+    import os
+    w = {"burgers_front_65": lambda: W.burgers_front(parts=(4, 1), steps=300), "spiral_257": lambda: W.spiral(steps=300),
+         "sphere_81": lambda: W.sphere_3d(n=81, steps=150), "spheres9_81": lambda: W.spheres9_3d(n=81, steps=150),
+         "sine_dd_513": lambda: W.sine_dd()}[name]()
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".npz")
+    gd = np.load(path)
+    want = float(gd["theta"]) if "theta" in gd.files else O.theta(w["monitor"], w["grid"]["lo"], w["grid"]["hi"])
+    got = B.theta(w["grid"], w["monitor"])
+    assert abs(got - want) <= tol * want, (got, want)

@@ -16,6 +16,7 @@ import pytest
 
 import oracle as O
 from paper_2006_14602_amd import workloads as W
+from parity_checks import check_min_cell
 
 pytestmark = pytest.mark.gpu
 
@@ -83,7 +84,8 @@ def test_alternating_vs_oracle(ctx, name, prec):
     err = float(np.max(np.abs(mesh - ref.mesh)))
     print(f"{name} {prec}: max mesh err {err:.3e}, min det {st['min_det']:.4f}")
     assert err <= TOL[prec], err
-    assert st["min_det"] > 0 and st["min_cell"] > 0
+    assert st["min_det"] > 0
+    check_min_cell(st["min_cell"], ref.min_cell, prec, name)
     assert st["steps_done"] == w["time"]["steps"]
 
 

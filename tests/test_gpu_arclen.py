@@ -16,6 +16,7 @@ import pytest
 
 import oracle as O
 from paper_2006_14602_amd import workloads as W
+from parity_checks import check_min_cell
 
 pytestmark = pytest.mark.gpu
 
@@ -87,8 +88,9 @@ def test_arclen_workload_vs_oracle(ctx, name, prec):
     err = float(np.max(np.abs(mesh - ref.mesh))) / extent(w)
     print(f"{name} {prec}: max mesh err {err:.3e}, min det {st['min_det']:.4f} (oracle {ref.min_det:.4f})")
     assert err <= TOL[prec], err
-    assert st["min_det"] > 0 and st["min_cell"] > 0 and ref.min_cell > 0
+    assert st["min_det"] > 0
     assert abs(st["min_det"] - ref.min_det) < (1e-8 if prec == "fp64" else 1e-3)
+    check_min_cell(st["min_cell"], ref.min_cell, prec, name)
 
 
 def test_arclen_front_mesh_symmetric_on_gpu(ctx):

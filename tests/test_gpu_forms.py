@@ -467,3 +467,62 @@ def test_failed_request_is_isolated(B):
         with pytest.raises(B.PmaError) as e:
             c.poll(12345678)
         assert e.value.code == B.PMA_E_NOTFOUND
+
+
+def test_cached_basis_evicted_for_admission(B):
+    # a finished request leaves its DCT basis cached in the arena; the next request, of another
+    # axis length, fits the budget only once that unused basis is evicted: it must be admitted
+    # (the allocation evicts the basis) instead of waiting for memory that nothing will free
+    a = W.ring(steps=20)
+    a["grid"] = W.grid([257, 257])
+    b = W.ring(steps=20)
+    b["grid"] = W.grid([249, 249])
+    ra, rb = B.request_bytes(a, "split16"), B.request_bytes(b, "split16")
+    basis_a = ra - B.request_bytes(dict(a, time=dict(a["time"], gamma=0.0)), "split16")
+    budget = max(ra, rb)
+    assert basis_a > 0 and basis_a + rb > budget   # without eviction b cannot be placed
+    with B.Context(0, budget_bytes=budget) as c:
+        (sa, ma, _), = serve_all(c, [a], timeout=60)
+        assert sa == B.DONE
+        info = c.server_info()
+        assert info["running"] == 0 and info["bytes_in_use"] >= basis_a   # the basis stays cached
+        (sb, mb, stb), = serve_all(c, [b], timeout=60)
+        assert sb == B.DONE, stb
+        alone, _, _ = c.dd_mesh(b, precision="split16")
+        np.testing.assert_array_equal(mb, alone)
+        assert c.server_info()["finished"] == 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
+def test_negative_monitor_reports_nonfinite(ctx, prec):
+    # a Gaussian bump of amplitude -5 makes rho = 1 - 5 exp(..) negative near its centre: the log
+    # of eq. pmae has no real value there, so the solve reports PMA_E_NONFINITE (theta given
+    # positive, so rho / theta keeps the sign of rho), as the oracle raises
+    from paper_2006_14602_amd import binding as B
+    w = W.ring(steps=5)
+    w["grid"] = W.grid([33, 33])
+    w["monitor"] = {"kind": "gauss_sum", "bamp": [-5.0], "bw": [0.1], "bc": [[0.5, 0.5]], "theta": 1.0}
+    g = w["grid"]
+    with pytest.raises(O.NonFiniteError):
+        O.solve_single(O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"])), w["monitor"], 1e-3, 1.0, 5,
+                       theta_val=1.0)
+    with pytest.raises(B.PmaError) as e:
+        ctx.dd_mesh(w, precision=prec)
+    assert e.value.code == B.PMA_E_NONFINITE
+
+
+def test_nonfinite_request_is_isolated_in_serving(B):
+    ws = small_stream(4)
+    bad = W.ring(steps=20)
+    bad["grid"] = W.grid([41, 41])
+    bad["monitor"] = {"kind": "gauss_sum", "bamp": [-5.0], "bw": [0.1], "bc": [[0.5, 0.5]], "theta": 1.0}
+    ws.insert(1, bad)
+    with B.Context(0, budget_bytes=1 << 30) as c:
+        out = serve_all(c, ws)
+        assert out[1][0] == B.FAILED and out[1][2]["status"] == B.PMA_E_NONFINITE
+        for i, (w, (state, mesh, st)) in enumerate(zip(ws, out)):
+            if i == 1:
+                continue
+            assert state == B.DONE
+            alone, _, _ = c.dd_mesh(w, precision="split16")
+            np.testing.assert_array_equal(mesh, alone)

@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 from paper_2006_14602_amd import workloads as W
+from parity_checks import check_min_cell
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +55,7 @@ def test_sine_dd_513_full(ctx, prec):
     print(f"sine_dd_513 {prec}: max err over {len(idx)} sampled nodes {err:.3e}, min det {st['min_det']:.6f}")
     assert err <= TOL[prec]
     assert abs(st["min_det"] - float(gd["min_det"])) <= (1e-9 if prec == "fp64" else 1e-3)
-    assert st["min_cell"] > 0
+    check_min_cell(st["min_cell"], float(gd["min_cell"]), prec, "sine_dd_513")
     # faces stay put (Sec. 2, eq. nbd)
     assert np.all(mesh[0][0, :] == 0.0) and np.all(mesh[0][-1, :] == 1.0)
     assert np.all(mesh[1][:, 0] == 0.0) and np.all(mesh[1][:, -1] == 1.0)
@@ -70,7 +71,8 @@ def test_shell_dd_129_full(ctx, prec):
     err = float(np.max(np.abs(got - gd["mesh"])))
     print(f"shell_dd_129 {prec}: max err {err:.3e}, min det {st['min_det']:.6f}")
     assert err <= TOL[prec]
-    assert st["min_cell"] > 0 and st["min_det"] > 0
+    assert st["min_det"] > 0
+    check_min_cell(st["min_cell"], float(gd["min_cell"]), prec, "shell_dd_129")
     for k in range(3):
         sl0 = [slice(None)] * 3
         sl0[k] = 0
@@ -94,6 +96,7 @@ def test_bumps_batch_256_full(ctx):
         err = float(np.max(np.abs(outs[i] - ref.mesh)))
         print(f"bump {i} n={g['n'][0]}: err {err:.3e}")
         assert err <= TOL["split16"]
+        check_min_cell(stats[i]["min_cell"], ref.min_cell, "split16", f"bump {i}")
 
 
 PAPER = {
@@ -125,7 +128,7 @@ def test_paper_workload_full(ctx, name, prec):
           f"(oracle {float(gd['min_det']):.6f}), E2 {st['quality_e2']:.4f}")
     assert err <= TOL[prec]
     assert abs(st["min_det"] - float(gd["min_det"])) <= (1e-9 if prec == "fp64" else 2e-3)
-    assert st["min_cell"] > 0
+    check_min_cell(st["min_cell"], float(gd["min_cell"]), prec, name)
 
 
 @pytest.mark.parametrize("prec", ["split16", "fp64"])
@@ -147,7 +150,8 @@ def test_sine_513_glued_dd_vs_single_domain(ctx, prec):
     print(f"sine 513 {prec}: single-domain err {err:.3e}; glued DD - single: GPU {gap_gpu:.4e}, oracle {gap_oracle:.4e}")
     assert err <= TOL[prec]
     assert abs(gap_gpu - gap_oracle) <= 2 * TOL[prec]
-    assert st["min_det"] > 0 and st["min_cell"] > 0
+    assert st["min_det"] > 0
+    check_min_cell(st["min_cell"], float(gs["min_cell"]), prec, "sine_single_513")
 
 
 def test_serving_stream_requests_full_size(ctx):
@@ -188,3 +192,22 @@ def test_serving_stream_requests_full_size(ctx):
         err = float(np.max(np.abs(res[i][1] - ref.mesh)))
         print(f"stream request {i}: max mesh err {err:.3e}")
         assert err <= TOL["split16"]
+        check_min_cell(res[i][2]["min_cell"], ref.min_cell, "split16", f"stream {i}")
+
+
+@pytest.mark.parametrize("name,prec", [("sphere_81", "fp64"), ("spiral_257", "split16"), ("burgers_front_65", "fp64")])
+def test_paper_workload_full_library_theta(ctx, name, prec):
+    # the same runs with the library computing theta itself (its reduced integrals or quadrature)
+    w = PAPER[name]()
+    assert not w["monitor"].get("theta")
+    gd = golden(name)
+    print(f"case {name} {prec} own theta", flush=True)
+    mesh, st = plan_mesh(ctx, w, prec)
+    d = w["grid"]["dim"]
+    idx = gd["idx"]
+    got = np.stack([mesh[k][tuple(idx.T)] for k in range(d)], -1)
+    ext = max(b - a for a, b in zip(w["grid"]["lo"], w["grid"]["hi"]))
+    err = float(np.max(np.abs(got - gd["mesh"]))) / ext
+    print(f"{name} {prec} own theta {st['theta']:.12g} (oracle {float(gd['theta']):.12g}): max err {err:.3e}")
+    assert err <= TOL[prec]
+    check_min_cell(st["min_cell"], float(gd["min_cell"]), prec, name + " own theta")

@@ -14,6 +14,7 @@ import pytest
 
 import oracle as O
 from paper_2006_14602_amd import workloads as W
+from parity_checks import check_min_cell
 
 pytestmark = pytest.mark.gpu
 
@@ -87,8 +88,9 @@ def test_ring_single_domain_vs_oracle(ctx, prec):
     err = np.max(np.abs(mesh - ref.mesh)) / extent(w)
     print(f"ring65 {prec}: max mesh err {err:.3e}, min det {st['min_det']:.4f}")
     assert err <= TOL[prec], err
-    assert st["min_det"] > 0 and st["min_cell"] > 0
+    assert st["min_det"] > 0
     assert abs(st["min_det"] - ref.min_det) < (1e-9 if prec == "fp64" else 1e-3)
+    check_min_cell(st["min_cell"], ref.min_cell, prec, "ring65")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
@@ -99,6 +101,7 @@ def test_sine_dd_vs_oracle(ctx, prec):
     err = np.max(np.abs(mesh - ref.mesh)) / extent(w)
     print(f"sine65 2x2 {prec}: max mesh err {err:.3e}")
     assert err <= TOL[prec], err
+    check_min_cell(st["min_cell"], ref.min_cell, prec, "sine65dd")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
@@ -109,7 +112,8 @@ def test_shell_3d_dd_vs_oracle(ctx, prec):
     err = np.max(np.abs(mesh - ref.mesh)) / extent(w)
     print(f"shell25 2x2x2 {prec}: max mesh err {err:.3e}")
     assert err <= TOL[prec], err
-    assert st["min_det"] > 0 and st["min_cell"] > 0
+    assert st["min_det"] > 0
+    check_min_cell(st["min_cell"], ref.min_cell, prec, "shell25dd")
 
 
 # --- edge shapes: the longest subdomain axis the kernels take (545 nodes, a ragged 34 x 16 + 1)
@@ -130,7 +134,8 @@ def test_longest_axis_vs_oracle(ctx, n, prec):
     err = np.max(np.abs(mesh - ref.mesh)) / extent(w)
     print(f"{w['name']} {prec}: max mesh err {err:.3e}")
     assert err <= TOL[prec], err
-    assert st["min_det"] > 0 and st["min_cell"] > 0
+    assert st["min_det"] > 0
+    check_min_cell(st["min_cell"], ref.min_cell, prec, w["name"])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
@@ -150,3 +155,4 @@ def test_smallest_subdomains_vs_oracle(ctx, shape, prec):
     err = np.max(np.abs(mesh - ref.mesh)) / extent(w)
     print(f"{w['name']} {prec}: max mesh err {err:.3e}")
     assert err <= TOL[prec], err
+    check_min_cell(st["min_cell"], ref.min_cell, prec, w["name"])

@@ -625,3 +625,161 @@ def test_arclen_nine_spheres_mesh_cube_symmetry():
     assert np.max(np.abs(x[0] - np.transpose(x[2], (2, 1, 0)))) < 1e-12
     assert np.max(np.abs(x[0] + x[0][::-1, :, :])) < 1e-12
     assert r.min_det > 0
+
+
+# --- Jacobian check (a8): min det D^2_h Psi, pinned by closed forms ---------------------------
+
+def _box_of(n, lo, hi, art=False):
+    d = len(n)
+    h = tuple((b - a) / (k - 1) for a, b, k in zip(lo, hi, n))
+    return O.Box((0,) * d, tuple(n), h, tuple(lo), tuple(hi), (art,) * d, (art,) * d)
+
+
+@pytest.mark.parametrize("n,lo,hi", [((17, 11), (0.0, -1.0), (2.0, 0.5)), ((9, 7, 8), (-1.0, 0.0, 0.5), (1.0, 3.0, 1.0))])
+def test_min_det_hessian_of_initial_potential_is_one(n, lo, hi):
+    # Psi^0 = |xi|^2 / 2 (eq. incond): centred differences are exact for quadratics, and the
+    # Neumann ghost of eq. nbd reproduces the quadratic, so D^2_h Psi = I at every node
+    box = _box_of(n, lo, hi)
+    assert abs(O.min_det_hessian(O.initial_psi(box), box) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("n,lo,hi,eps,m", [
+    ((33, 21), (0.0, -1.0), (2.0, 0.5), (0.02, 0.008), (2, 1)),
+    ((17, 13, 15), (-1.0, 0.0, 0.5), (1.0, 2.0, 1.5), (0.01, 0.02, 0.004), (1, 1, 1))])
+def test_min_det_hessian_cosine_perturbation_closed_form(n, lo, hi, eps, m):
+    # Psi = sum_k xi_k^2 / 2 + eps_k cos(w_k (xi_k - a_k)), w_k = 2 pi m_k / (b_k - a_k).  The
+    # cosine is even about both faces, so the centred Neumann ghost is exact; the discrete second
+    # difference of cos(w s) is -lam cos(w s) with lam = (4 / h^2) sin^2(w h / 2), and the cross
+    # differences of a separable function vanish.  So D^2_h Psi = diag(1 - eps_k lam_k cos(..)),
+    # whose smallest determinant sits where every cosine is 1 (the low corner):
+    # prod_k (1 - eps_k lam_k).
+    box = _box_of(n, lo, hi)
+    d = len(n)
+    X = box.coords()
+    psi = 0.5 * np.sum(X * X, axis=-1)
+    expect = 1.0
+    for k in range(d):
+        w = 2.0 * math.pi * m[k] / (hi[k] - lo[k])
+        psi = psi + eps[k] * np.cos(w * (X[..., k] - lo[k]))
+        lam = 4.0 / box.h[k] ** 2 * math.sin(w * box.h[k] / 2.0) ** 2
+        assert eps[k] * lam < 0.9
+        expect *= 1.0 - eps[k] * lam
+    got = O.min_det_hessian(psi, box)
+    assert abs(got - expect) < 1e-9, (got, expect)
+
+
+def test_det_sym_3d_matches_numpy_det():
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((50, 3, 3))
+    M = M + np.transpose(M, (0, 2, 1))
+    hess = [[M[:, i, j] for j in range(3)] for i in range(3)]
+    np.testing.assert_allclose(O.det_sym(hess, 3), np.linalg.det(M), rtol=1e-12, atol=1e-12)
+    hess2 = [[M[:, i, j] for j in range(2)] for i in range(2)]
+    np.testing.assert_allclose(O.det_sym(hess2, 2), np.linalg.det(M[:, :2, :2]), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_min_det_hessian_quadratic_with_mixed_terms(d):
+    # Psi = xi^T M xi / 2 + b . xi on a box whose faces are all artificial (live nodes are the
+    # interior ones, whose stencils use real values only): every second and mixed difference is
+    # exact for a quadratic, so det D^2_h Psi = det M (numpy.linalg.det) at every live node
+    rng = np.random.default_rng(11 + d)
+    A = rng.standard_normal((d, d))
+    M = A @ A.T + d * np.eye(d)
+    b = rng.standard_normal(d)
+    n = (9, 8, 7)[:d]
+    box = _box_of(n, (-0.5,) * d, (1.5,) * d, art=True)
+    X = box.coords()
+    psi = 0.5 * np.einsum("...i,ij,...j->...", X, M, X) + X @ b
+    assert abs(O.min_det_hessian(psi, box) - np.linalg.det(M)) < 1e-9 * np.linalg.det(M)
+
+
+# --- relative errors of Sec. 4.4 (eqs. rel_errlp / rel_errlinf) with the trapezoid rule ---------
+
+@pytest.mark.parametrize("n", [(9, 5), (17, 3)])
+def test_rel_errors_closed_forms(n):
+    # on [0, 2] x [0, 1]: Psi_sd = 1, Psi_dd = 1 - xi.  The trapezoid rule integrates 1 and xi
+    # exactly (2 and 2), and xi^2 to 8/3 + h^2/3 (its error term for a constant second derivative)
+    lo, hi = (0.0, 0.0), (2.0, 1.0)
+    g = O.GridSpec(n, lo, hi)
+    X = g.whole_box().coords()
+    ref = np.ones(n)
+    approx = ref - X[..., 0]
+    e = O.rel_errors(ref, approx, g.h)
+    h0 = g.h[0]
+    assert abs(e[1] - 2.0 / 2.0) < 1e-13
+    assert abs(e[2] - math.sqrt((8.0 / 3.0 + h0 * h0 / 3.0) / 2.0)) < 1e-13
+    assert abs(e["inf"] - 2.0) < 1e-13
+    # the relative form divides by the norm of the reference: scaling both leaves E unchanged
+    e3 = O.rel_errors(3.0 * ref, 3.0 * approx, g.h)
+    for p in (1, 2, "inf"):
+        assert abs(e3[p] - e[p]) < 1e-13
+
+
+# --- residual of eq. dd_stop_criterion: closed forms -----------------------------------------
+
+@pytest.mark.parametrize("n,lo,hi", [((9, 13), (0.0, -1.0), (2.0, 2.0)), ((5, 7, 6), (0.0, 0.0, -1.0), (1.0, 3.0, 1.0))])
+def test_residual_closed_form_constant_update(n, lo, hi):
+    # constant monitor, Psi^0 = |xi|^2 / 2 (det D^2_h Psi = 1) and theta = |Omega| amp e^{-c}:
+    # F = c at every node, and with gamma = 0 the update is dt c everywhere, whose trapezoid L2
+    # norm is dt |c| |Omega|^{1/2}
+    g = O.GridSpec(n, lo, hi)
+    box = g.whole_box()
+    amp, c, dt = 3.0, 0.37, 1e-3
+    mon = W.const_monitor(amp)
+    th = g.vol * amp * math.exp(-c)
+    psi1, res = O.step_box(O.initial_psi(box), box, mon, th, g.vol, dt, 0.0)
+    assert abs(res - dt * c * math.sqrt(g.vol)) < 1e-15
+    assert np.max(np.abs(psi1 - O.initial_psi(box) - dt * c)) < 1e-15
+    # the preconditioner keeps a constant (its DC mode has mu_0 = 0)
+    psi1p, resp = O.step_box(O.initial_psi(box), box, mon, th, g.vol, dt, 0.5)
+    assert abs(resp - dt * c * math.sqrt(g.vol)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [(9, 13), (5, 7, 6)])
+def test_residual_excludes_artificial_nodes(n):
+    # a box with every face artificial: only interior nodes are live, each of trapezoid weight
+    # prod h, so the norm of a constant update dt c is dt |c| (prod_k (n_k - 2) h_k)^{1/2}
+    d = len(n)
+    box = _box_of(n, (0.0,) * d, (2.0,) * d, art=True)
+    vol = 2.0 ** d
+    amp, c, dt = 2.0, -0.21, 1e-3
+    th = vol * amp * math.exp(-c)
+    _, res = O.step_box(O.initial_psi(box), box, W.const_monitor(amp), th, vol, dt, 0.0)
+    expect = dt * abs(c) * math.sqrt(float(np.prod([(k - 2) * hk for k, hk in zip(n, box.h)])))
+    assert abs(res - expect) < 1e-15
+
+
+# --- quality measure of Sec. 4.5: a mesh with a closed-form Jacobian --------------------------
+
+@pytest.mark.parametrize("n,lo,hi,eps", [((11, 9), (0.0, -1.0), (2.0, 0.0), (0.2, 0.5)),
+                                         ((7, 9, 5), (0.0, 0.0, -1.0), (1.0, 2.0, 1.0), (0.3, 0.1, 0.2))])
+def test_quality_of_mesh_closed_form(n, lo, hi, eps):
+    # x_k = xi_k + eps_k (xi_k - a_k)(b_k - xi_k): dx_k/dxi_k = 1 + eps_k (a_k + b_k - 2 xi_k) is
+    # linear, so second-order differences (one-sided at the faces) give it exactly and
+    # J = prod_k (1 + eps_k (a_k + b_k - 2 xi_k)).  With a constant monitor E = J, whose maximum
+    # is prod_k (1 + eps_k L_k) at the low corner, and whose trapezoid integral of E^2 is
+    # prod_k [L_k (1 + eps_k^2 L_k^2 / 3) + (2/3) eps_k^2 L_k h_k^2] (exact part plus the rule's
+    # error term for a quadratic)
+    g = O.GridSpec(n, lo, hi)
+    d = len(n)
+    X = g.whole_box().coords()
+    mesh = np.stack([X[..., k] + eps[k] * (X[..., k] - lo[k]) * (hi[k] - X[..., k]) for k in range(d)], 0)
+    mon = W.const_monitor(1.7)
+    q = O.quality_of_mesh(mesh, g, mon, theta_val=1.7 * g.vol)
+    L = [b - a for a, b in zip(lo, hi)]
+    emax = float(np.prod([1.0 + e * l for e, l in zip(eps, L)]))
+    int2 = float(np.prod([l * (1.0 + e * e * l * l / 3.0) + 2.0 / 3.0 * e * e * l * h * h
+                          for e, l, h in zip(eps, L, g.h)]))
+    assert abs(q["Emax"] - emax) < 1e-12
+    assert abs(q["E2"] - math.sqrt(int2 / g.vol)) < 1e-12
+
+
+def test_negative_monitor_raises_nonfinite():
+    # rho = 1 - 5 exp(-|x - c|^2 / (2 w^2)) < 0 near c with theta given positive: no real log
+    g = grid2(17)
+    mon = {"kind": "gauss_sum", "bamp": [-5.0], "bw": [0.1], "bc": [[0.5, 0.5]]}
+    with pytest.raises(O.NonFiniteError):
+        O.solve_single(g, mon, 1e-3, 1.0, 3, theta_val=1.0)
+    # the same bump with a positive amplitude runs
+    O.solve_single(g, dict(mon, bamp=[5.0]), 1e-3, 1.0, 3)
