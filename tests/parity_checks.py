@@ -4,12 +4,14 @@ The minimum signed cell measure (2D: quadrilateral area by the shoelace formula;
 corner Jacobian of each hexahedron) is computed in FP64 on the GPU from the glued mesh, and by
 the oracle from its own mesh.  Its difference follows from the mesh difference: each edge of a
 cell moves by at most twice the mesh error, so the relative change of the measure is bounded by
-about 2 d (mesh error) / h.  The bounds below hold that with margin: FP64 meshes agree to
-~1e-13, the FP32 forms to ~1e-7 at h >= 1/512.  A wrong corner, orientation or index changes the
+about 2 d (mesh error) / h.  The bounds below hold that with margin.  Measured on MI355X: FP64
+up to 2e-10 relative (the 545-node axes, h = 1/544, where the FP64 mesh error is ~1e-13 of a
+cell of ~2e-3 x 0.11); the FP32 forms up to 1.6e-3 (FP32 at the 545-node axes: mesh error
+~4e-6, skinny cells), below 1e-3 elsewhere.  A wrong corner, orientation or index changes the
 measure by O(1) relative and fails them.
 """
 
-CELL_RTOL = {"fp64": 1e-8, "fp32": 2e-3, "split16": 2e-3}
+CELL_RTOL = {"fp64": 1e-8, "fp32": 5e-3, "split16": 5e-3}
 
 
 def check_min_cell(got: float, ref: float, prec: str, label: str = "") -> float:
