@@ -195,6 +195,23 @@ int pma_solve_subdomain(pma_ctx* ctx, const pma_grid* global, const int lo[3], c
                         const int face_kind[6], const pma_monitor* mon, const pma_time* time,
                         void* psi_dev, void* hip_stream, pma_stats* st);
 
+/* The same solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): it calls no hipMalloc,
+ * hipFree, pinned-host or graph allocation and creates no event.  The subdomain's state, its DCT
+ * matrices, launch tables and reduction buffers live in one fixed device scratch of 32 MiB per
+ * GPU, part of the library's code object (held until the process ends); its address is looked up
+ * per device by pma_create.  The kernels run on hip_stream itself, launched directly (no
+ * captured graphs), and the call returns after that stream has finished.  Arguments, layout,
+ * ownership and results are those of pma_solve_subdomain, bitwise.
+ * Limit: the subdomain's three state arrays (prod(hi - lo + 1) elements each, 8 bytes in FP64,
+ * 4 otherwise) plus one DCT basis per distinct axis length must fit 31 MiB: PMA_E_INVAL with the
+ * byte counts otherwise.  The scratch keeps the last call's contents; every call initialises
+ * what it reads.  Calls on one GPU share the scratch: calls that overlap in time on the same GPU
+ * (from different contexts or threads) race and must be serialised by the caller. */
+int pma_solve_subdomain_noalloc(pma_ctx* ctx, const pma_grid* global, const int lo[3], const int hi[3],
+                                const int face_kind[6], const pma_monitor* mon, const pma_time* time,
+                                void* psi_dev, void* hip_stream, pma_stats* st);
+
 /* ---- whole mesh (Sec. 3 parallel DD-PMA, Sec. 4.5 glue) ---------------------------------- */
 
 /* Compute the adaptive mesh of `grid`, single domain if dd is NULL or all parts are 1, else the

@@ -97,6 +97,7 @@ def load():
     L.pma_set_allocator.argtypes = [c_void_p, ALLOC_CB, FREE_CB, c_void_p]
     L.pma_solve_subdomain.argtypes = [c_void_p, POINTER(Grid), POINTER(c_int), POINTER(c_int), POINTER(c_int),
                                       POINTER(Monitor), POINTER(Time), c_void_p, c_void_p, POINTER(Stats)]
+    L.pma_solve_subdomain_noalloc.argtypes = L.pma_solve_subdomain.argtypes
     L.pma_dd_mesh.argtypes = [c_void_p, POINTER(Grid), POINTER(DD), POINTER(Monitor), POINTER(Time),
                               POINTER(c_double), POINTER(c_double), POINTER(c_double), POINTER(Stats)]
     L.pma_dd_mesh_batch.argtypes = [c_void_p, c_int, POINTER(Request), POINTER(POINTER(c_double)), POINTER(Stats)]
@@ -373,9 +374,10 @@ class Context:
 
     # -- one subdomain ---------------------------------------------------------------------
     def solve_subdomain(self, grid: dict, lo, hi, faces, mon: dict, time: dict, psi_dev, stream=None,
-                        precision="fp32", exec_="batched"):
+                        precision="fp32", exec_="batched", noalloc=False):
         """Advance one subdomain in place.  psi_dev: a contiguous float64 CUDA tensor of the
-        subdomain's nodes holding Psi (artificial faces hold the Dirichlet data)."""
+        subdomain's nodes holding Psi (artificial faces hold the Dirichlet data).  noalloc: through
+        pma_solve_subdomain_noalloc (state in the library's fixed device scratch)."""
         import torch
         assert psi_dev.is_cuda and psi_dev.dtype == torch.float64 and psi_dev.is_contiguous()
         d = grid["dim"]
@@ -389,8 +391,9 @@ class Context:
         T = make_time(time, precision, exec_)
         st = Stats()
         s = stream if stream is not None else torch.cuda.current_stream(psi_dev.device)
-        _check(self._L.pma_solve_subdomain(self.h, ctypes.byref(G), lo3, hi3, f6, ctypes.byref(M), ctypes.byref(T),
-                                           c_void_p(psi_dev.data_ptr()), c_void_p(s.cuda_stream), ctypes.byref(st)))
+        fn = self._L.pma_solve_subdomain_noalloc if noalloc else self._L.pma_solve_subdomain
+        _check(fn(self.h, ctypes.byref(G), lo3, hi3, f6, ctypes.byref(M), ctypes.byref(T),
+                  c_void_p(psi_dev.data_ptr()), c_void_p(s.cuda_stream), ctypes.byref(st)))
         return st.as_dict()
 
     # -- serving ---------------------------------------------------------------------------

@@ -2645,4 +2645,35 @@ hipError_t launch_min_reduce(const double* x, long n, double* out, hipStream_t s
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// Fixed device scratch for the entry point that allocates nothing: one array per GPU, loaded
+// with the code object and held until the process ends.  In host code `scratch` names a host
+// stand-in, not device memory: kernels and copies take the address that hipGetSymbolAddress
+// returns for the current device, looked up once per device and kept here.
+// ------------------------------------------------------------------------------------------
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+
 }  // namespace pma

@@ -8,6 +8,7 @@
 //   F    the right-hand side, then the spectral coefficients
 //   T    scratch for the mode products of the preconditioner
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace pma {
@@ -98,5 +99,8 @@ struct StepArgs {
   double* shift_acc;     // per-instance accumulated constant removed from phi (FP64)
   int* status;           // per-instance status bits
 };
+
+// bytes of the fixed device scratch used by the entry point that allocates nothing
+constexpr size_t kScratchBytes = (size_t)32 << 20;
 
 }  // namespace pma

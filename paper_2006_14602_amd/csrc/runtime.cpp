@@ -26,6 +26,8 @@ namespace pma {
 
 // kernels.hip
 hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int count, hipStream_t s);
+hipError_t scratch_init(int device);
+void* scratch_ptr(int device);
 hipError_t launch_stencil(int prec, int dim, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
 hipError_t launch_stencil_fwd2(int prec, const int4* tiles, int ntiles, int lneed, const StepArgs& sa, hipStream_t s);
 int fused_lds_bytes(int prec, int ld, int ldb, int n, bool basis);
@@ -646,6 +648,8 @@ struct Instance {
   double stats_host[4] = {0, 0, 0, 0};
   const double* psi0_dev = nullptr;  // warm start (global layout, device)
   double* user_psi = nullptr;        // single-subdomain mode: caller's device buffer
+  bool ext_mem = false;              // block and bases in caller-provided memory (the fixed
+                                     // scratch), not in the arena; bases owned, not cached
   size_t elem() const { return prec == PMA_FP64 ? 8 : 4; }
   long gnodes() const { return (long)grid.n[0] * grid.n[1] * (dim == 3 ? grid.n[2] : 1); }
 };
@@ -880,13 +884,9 @@ static size_t basis_bytes(int n, int prec) {
   return 4 * Arena::round(rl * 2) + Arena::round((size_t)n * 4);
 }
 
-static Basis* get_basis(pma_ctx* c, int n, int prec) {
-  auto key = std::make_pair(n, prec);
-  auto it = c->bases.find(key);
-  if (it != c->bases.end()) {
-    it->second->last_use = ++c->basis_clock;
-    return it->second;
-  }
+// the DCT matrices of axis length n in precision prec, written to device memory mem
+// (basis_bytes(n, prec) bytes); the Basis describes where each matrix sits
+static std::unique_ptr<Basis> fill_basis(int n, int prec, char* mem) {
   if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: split it further");
   std::vector<double> A, B, sig;
   basis_host(n, A, B, sig);
@@ -898,7 +898,7 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
   b->ldb = basis_stride(n, prec);
   const size_t rl = (size_t)b->rows * b->ldb;
   b->bytes = basis_bytes(n, prec);
-  b->mem = (char*)arena_alloc(c, b->bytes);
+  b->mem = mem;
   char* p = b->mem;
   auto put = [&](const void* src, size_t sz) {
     HIPCHK(hipMemcpy(p, src, sz, hipMemcpyHostToDevice));
@@ -906,7 +906,7 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
     p += Arena::round(sz);
     return q;
   };
-  try {
+  {
     if (prec == PMA_FP64) {
       std::vector<double> A64(rl, 0.0), B64(rl, 0.0);
       for (int i = 0; i < n; ++i)
@@ -954,8 +954,24 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
       }
       b->sig = put(sig32.data(), (size_t)n * 4);
     }
+  }
+  return b;
+}
+
+static Basis* get_basis(pma_ctx* c, int n, int prec) {
+  auto key = std::make_pair(n, prec);
+  auto it = c->bases.find(key);
+  if (it != c->bases.end()) {
+    it->second->last_use = ++c->basis_clock;
+    return it->second;
+  }
+  if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: split it further");
+  char* mem = (char*)arena_alloc(c, basis_bytes(n, prec));
+  std::unique_ptr<Basis> b;
+  try {
+    b = fill_basis(n, prec, mem);
   } catch (...) {
-    c->arena.release(b->mem);
+    c->arena.release(mem);
     throw;
   }
   b->last_use = ++c->basis_clock;
@@ -1055,9 +1071,25 @@ static void build_push_tables(pma_ctx* c, Instance& I, Take& take) {
   }
 }
 
-static void alloc_instance(pma_ctx* c, Instance& I) {
+// device bytes of an instance with its own copy of every basis (the allocation-free path)
+static size_t instance_bytes_with_bases(const Instance& I) {
+  size_t b = Arena::round(instance_bytes(I));
+  if (I.tm.gamma > 0)
+    for (int n : distinct_axis_sizes(I)) b += Arena::round(basis_bytes(n, I.prec));
+  return b;
+}
+
+// ext: caller-provided device memory of ext_cap bytes (the fixed scratch) holding the block and
+// private copies of the bases instead of the arena and the basis cache; returns the bytes used
+static size_t alloc_instance(pma_ctx* c, Instance& I, char* ext = nullptr, size_t ext_cap = 0) {
   I.bytes = instance_bytes(I);
-  I.block = (char*)arena_alloc(c, I.bytes);
+  I.ext_mem = ext != nullptr;
+  if (ext) {
+    if (instance_bytes_with_bases(I) > ext_cap) thr(PMA_E_INVAL, "internal: scratch too small for the instance");
+    I.block = ext;
+  } else {
+    I.block = (char*)arena_alloc(c, I.bytes);
+  }
   char* p = I.block;
   auto take = [&](size_t sz) {
     char* q = p;
@@ -1092,6 +1124,23 @@ static void alloc_instance(pma_ctx* c, Instance& I) {
   }
   if (uses_push(I)) build_push_tables(c, I, take);
   I.bases_used.clear();
+  if (ext) {
+    char* q = I.block + Arena::round(I.bytes);
+    if (I.tm.gamma > 0) {
+      try {
+        for (int n : distinct_axis_sizes(I)) {
+          I.bases_used.push_back(fill_basis(n, I.prec, q).release());
+          q += Arena::round(basis_bytes(n, I.prec));
+        }
+      } catch (...) {
+        for (auto* b : I.bases_used) delete b;
+        I.bases_used.clear();
+        I.block = nullptr;
+        throw;
+      }
+    }
+    return (size_t)(q - I.block);
+  }
   if (I.tm.gamma > 0) {
     try {
       for (int n : distinct_axis_sizes(I)) {
@@ -1107,9 +1156,24 @@ static void alloc_instance(pma_ctx* c, Instance& I) {
       throw;
     }
   }
+  return Arena::round(I.bytes);
+}
+
+// the basis of axis length n among those the instance holds (cached or its own copy)
+static const Basis* basis_of(const Instance& I, int n) {
+  for (const Basis* b : I.bases_used)
+    if (b->n == n) return b;
+  thr(PMA_E_HIP, "internal: no basis of the instance for an axis length");
+  return nullptr;
 }
 
 static void free_instance(pma_ctx* c, Instance& I) {
+  if (I.ext_mem) {
+    for (auto* b : I.bases_used) delete b;   // private copies in the caller's memory
+    I.bases_used.clear();
+    I.block = nullptr;
+    return;
+  }
   for (auto* b : I.bases_used) b->refs--;
   I.bases_used.clear();
   if (I.block) c->arena.release(I.block);
@@ -1214,12 +1278,20 @@ struct Batch {
   StepArgs sa{};
 
   size_t dcap = 0;  // capacity of dmem: launch tables live outside the request arena
+  // allocation-free path: launch tables in caller-provided device memory (the fixed scratch),
+  // residual and status read back into ordinary host memory
+  char* ext_tab = nullptr;
+  size_t ext_tab_cap = 0;
+  std::vector<double> hv_resid;
+  std::vector<int> hv_status;
 
   ~Batch() {
     clear_device();
     if (dmem) hipFree(dmem);
-    if (h_resid) hipHostFree(h_resid);
-    if (h_status) hipHostFree(h_status);
+    if (!ext_tab) {
+      if (h_resid) hipHostFree(h_resid);
+      if (h_status) hipHostFree(h_status);
+    }
   }
 
   // forget the launch set (the table buffer is kept for the next build)
@@ -1425,7 +1497,7 @@ struct Batch {
             sd.a[k] = I.grid.lo[k];
             sd.h[k] = (I.grid.hi[k] - I.grid.lo[k]) / (I.grid.n[k] - 1);
             sd.gh2[k] = I.tm.gamma / (sd.h[k] * sd.h[k]);
-            if (I.tm.gamma > 0) sd.ax[k] = axis_dev(get_basis(ctx, S.n[k], prec));
+            if (I.tm.gamma > 0) sd.ax[k] = axis_dev(basis_of(I, S.n[k]));
           } else {
             sd.a[k] = 0;
             sd.h[k] = 1;
@@ -1545,7 +1617,9 @@ struct Batch {
                    Arena::round(h_pull.size() * 16 + 16) + Arena::round(nsub * el) +
                    Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4);
     for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
-    if (bytes > dcap) {
+    if (ext_tab) {
+      if (bytes > ext_tab_cap) thr(PMA_E_INVAL, "launch tables exceed the fixed scratch");
+    } else if (bytes > dcap) {
       if (dmem) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
         HIPCHK(hipFree(dmem));
@@ -1558,7 +1632,7 @@ struct Batch {
         thr(PMA_E_NOMEM, "launch tables: device allocation failed");
       }
     }
-    char* p = dmem;
+    char* p = ext_tab ? ext_tab : dmem;
     auto take = [&](size_t sz) {
       char* q = p;
       p += Arena::round(sz);
@@ -1589,7 +1663,12 @@ struct Batch {
     std::vector<double> sh(ninst, 0.0);
     for (size_t q = 0; q < ninst; ++q) sh[q] = insts[q]->shift_acc;
     up(d_shift, sh.data(), ninst * 8);
-    if (ninst + 1 > pinned_cap) {
+    if (ext_tab) {
+      hv_resid.assign(ninst + 1, 0.0);
+      hv_status.assign(ninst + 1, 0);
+      h_resid = hv_resid.data();
+      h_status = hv_status.data();
+    } else if (ninst + 1 > pinned_cap) {
       if (h_resid) hipHostFree(h_resid);
       if (h_status) hipHostFree(h_status);
       h_resid = nullptr;
@@ -1885,7 +1964,10 @@ static void save_shifts(Batch& B) {
 // Run instances (one precision) to their step counts, finishing each as soon as it stops.
 // Instances that stop earlier than others leave the shared launches (the batch is rebuilt from
 // the survivors; their device state is untouched).
-static void run_to_end(pma_ctx* c, const std::vector<Instance*>& all, int prec, bool plain, bool want_psi) {
+// ext_tab: launch tables in caller-provided device memory of ext_tab_cap bytes and steps launched
+// directly (no captured graphs): nothing is allocated on the way
+static void run_to_end(pma_ctx* c, const std::vector<Instance*>& all, int prec, bool plain, bool want_psi,
+                       char* ext_tab = nullptr, size_t ext_tab_cap = 0) {
   hipStream_t st = c->stream;
   std::vector<Instance*> live = all;
   while (!live.empty()) {
@@ -1894,6 +1976,11 @@ static void run_to_end(pma_ctx* c, const std::vector<Instance*>& all, int prec, 
     B.prec = prec;
     B.insts = live;
     B.fuse = !plain;  // the plain method keeps one launch per kernel
+    if (ext_tab) {
+      B.ext_tab = ext_tab;
+      B.ext_tab_cap = ext_tab_cap;
+      B.use_graph = false;
+    }
     B.build();
     for (size_t q = 0; q < live.size(); ++q)
       if (!live[q]->initialized) init_state(c, *live[q], B, (int)q);
@@ -2200,6 +2287,9 @@ int pma_create(int hip_device, size_t hbm_budget_bytes, pma_ctx** out) {
   if (hipGetDeviceCount(&nd) != hipSuccess || hip_device < 0 || hip_device >= nd)
     return fail(PMA_E_HIP, "no such HIP device %d", hip_device);
   HIPCHK(hipSetDevice(hip_device));
+  // the fixed scratch of the allocation-free entry point: its address on this device, looked up
+  // once per device with the device current
+  if (scratch_init(hip_device) != hipSuccess) return fail(PMA_E_HIP, "device scratch lookup failed");
   pma_ctx* c = new pma_ctx;
   c->device = hip_device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)8 << 30);
@@ -2434,8 +2524,44 @@ int pma_dd_mesh_batch(pma_ctx* c, int count, const pma_request* reqs, double* co
   API_END
 }
 
+}  // extern "C"
+
+namespace pma {
+
+// the context's stream replaced by another for the duration of a call (under the context lock)
+struct StreamSwap {
+  pma_ctx* c;
+  hipStream_t saved;
+  StreamSwap(pma_ctx* c_, hipStream_t s) : c(c_), saved(c_->stream) { c->stream = s; }
+  ~StreamSwap() { c->stream = saved; }
+};
+
+static int solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], const int hi[3],
+                           const int face_kind[6], const pma_monitor* mon, const pma_time* tm, void* psi_dev,
+                           void* hip_stream, pma_stats* st, bool noalloc);
+
+}  // namespace pma
+
+extern "C" {
+
 int pma_solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], const int hi[3], const int face_kind[6],
                         const pma_monitor* mon, const pma_time* tm, void* psi_dev, void* hip_stream, pma_stats* st) {
+  return solve_subdomain(c, global, lo, hi, face_kind, mon, tm, psi_dev, hip_stream, st, false);
+}
+
+int pma_solve_subdomain_noalloc(pma_ctx* c, const pma_grid* global, const int lo[3], const int hi[3],
+                                const int face_kind[6], const pma_monitor* mon, const pma_time* tm, void* psi_dev,
+                                void* hip_stream, pma_stats* st) {
+  return solve_subdomain(c, global, lo, hi, face_kind, mon, tm, psi_dev, hip_stream, st, true);
+}
+
+}  // extern "C"
+
+namespace pma {
+
+static int solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], const int hi[3],
+                           const int face_kind[6], const pma_monitor* mon, const pma_time* tm, void* psi_dev,
+                           void* hip_stream, pma_stats* st, bool noalloc) {
   API_BEGIN
   if (!c || !global || !lo || !hi || !face_kind || !mon || !tm || !psi_dev) return fail(PMA_E_INVAL, "NULL argument");
   std::lock_guard<std::recursive_mutex> g(c->mu);
@@ -2471,9 +2597,40 @@ int pma_solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], con
   I.nlevels = 1;
   I.theta = mon->theta > 0 ? mon->theta : theta_host(I.grid, I.mon);
   I.user_psi = (double*)psi_dev;
+  hipStream_t user = (hipStream_t)hip_stream;
+  if (noalloc) {
+    // everything in the fixed scratch of this device, kernels on the caller's stream, steps
+    // launched directly: no device, pinned-host or graph allocation, no event
+    char* scr = (char*)scratch_ptr(c->device);
+    if (!scr) return fail(PMA_E_HIP, "device scratch of device %d not set up", c->device);
+    // state and DCT matrices first, launch tables and reduction buffers (well under
+    // kScratchTables for one subdomain) after them
+    constexpr size_t kScratchTables = (size_t)1 << 20;
+    const size_t need = instance_bytes_with_bases(I);
+    if (need > kScratchBytes - kScratchTables)
+      return fail(PMA_E_INVAL, "subdomain needs %zu bytes of state and DCT matrices; the allocation-free entry point "
+                  "holds at most %zu (use pma_solve_subdomain)", need, kScratchBytes - kScratchTables);
+    int rc = PMA_OK;
+    {
+      StreamSwap sw(c, user);
+      try {
+        const size_t used = alloc_instance(c, I, scr, kScratchBytes - kScratchTables);
+        std::vector<Instance*> v{&I};
+        run_to_end(c, v, I.prec, tm->exec == PMA_EXEC_PLAIN, false, scr + used, kScratchBytes - used);
+        HIPCHK(hipStreamSynchronize(user));
+      } catch (Err& e) {
+        rc = e.code;
+        hipStreamSynchronize(user);
+      }
+    }
+    free_instance(c, I);
+    fill_stats(st, I, (now_s() - t0) * 1e3);
+    if (rc != PMA_OK) return rc;
+    if (I.status != PMA_OK) return status_fail(I.status);
+    return PMA_OK;
+  }
   alloc_instance(c, I);
   int rc = PMA_OK;
-  hipStream_t user = (hipStream_t)hip_stream;
   hipEvent_t ev = nullptr;
   try {
     // the work runs after what the caller queued on its stream, and the caller's stream waits
@@ -2500,9 +2657,10 @@ int pma_solve_subdomain(pma_ctx* c, const pma_grid* global, const int lo[3], con
   API_END
 }
 
+}  // namespace pma
+
 // ---- resident plans -------------------------------------------------------------------------
 
-}  // extern "C"
 
 struct pma_plan {
   pma_ctx* ctx = nullptr;
