@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the DD-PMA hot path on one MI355X.
 
-Headline workload (one "step" = one pseudo-time step of the whole hot path over every subdomain):
-513 x 513 grid on [0,1]^2, 4 x 4 overlapping subdomains (overlap 8 cells, 133/137 nodes per
-side), sine-layer monitor rho = 1 + 20 sech^2(40 (y - 1/2 - sin(2 pi x)/4)), gamma = 4 h^2,
-dt = gamma / 5.  State stays resident in HBM; exactly --steps steps are timed.
+Headline workload (one "step" = one pseudo-time step of the whole hot path over every instance):
+256 independent single-domain 2D meshes of uneven sides (U{33..257}, PCG64 seed 20060146),
+monitors 1 + a sum of 1-4 Gaussian bumps, gamma = 1, dt = 1e-3, 200 steps (6.46 M nodes per
+step).  State stays resident in HBM; exactly --steps steps are timed.
 
-value = global grid nodes x steps / wall time of the timed steps (grid-point updates/s) for the
-batched FP32 form (FP32 stencils, fp16-split matrix-core DCT products, graph-replayed shared
-launches).  Beside it, on the same MI355X: the same workload in FP32 matrix-core products and in
-the plain FP64 form (one subdomain per launch, FP64 everywhere, no graph); the 65^2 ring
-(FP64), the 129^3 shell DD, the 256-instance batch (batched FP32 vs plain FP64), a Poisson
-serving stream (meshes/s, p50/p99 latency), and the stencil at a >= 1 GB working set.
+value = grid nodes x steps / wall time of the timed steps (grid-point updates/s) for the batched
+FP64 form (the paper's precision: FP64 stencils, FP64 matrix-core DCT products, every instance
+in the same launches, graph-replayed steps).  Beside it, on the same MI355X and workload: the
+batched FP32 form with fp16-split DCT products, the batched FP32 form, and the plain FP64 method
+(one instance per launch, no graph); the max mesh error against the FP64 oracle and the FP64
+final residual of every instance; the oracle itself timed on the host's cores.  Other lines: the
+513^2 4x4 sine-layer DD (all forms), the 65^2 ring, the 129^3 shell DD, the stencil at a >= 1 GB
+working set, the paper's own workloads, and a Poisson serving stream (continuous batching
+against the plain method serving the same stream).
 """
 import argparse
 import hashlib
@@ -157,15 +160,19 @@ def paper_workloads(ctx, binding, workloads):
 def roofline_of(phases, prec, workload=None):
     """Dominant kernel of a step: algorithmic work per launch / mean launch duration; traffic from
     the committed counters of `workload` when they are current."""
-    name, ph = max(((k, v) for k, v in phases.items() if v["flops"] > 0 or v["bytes"] > 0),
+    name, ph = max(((k, v) for k, v in phases.items() if k != "resid" and (v["flops"] > 0 or v["bytes"] > 0)),
                    key=lambda kv: kv[1]["ms"])
     sec = ph["ms"] * 1e-3
     if ph["flops"] > 0:
         ach = ph["flops"] / sec / 1e12
         peak = MFMA_PEAK[prec]
-        return {"kernel": KERNEL[name], "phase": name, "bound": "mfma", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_of(workload, name),
-                "algorithmic_per_launch": ph["flops"], "avg_launch_ms": ph["ms"]}
+        out = {"kernel": KERNEL[name], "phase": name, "bound": "mfma", "achieved": ach, "peak": peak,
+               "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_of(workload, name),
+               "algorithmic_per_launch": ph["flops"], "avg_launch_ms": ph["ms"]}
+        if prec == "split16":  # three fp16 products per useful one (hi*hi, hi*lo, lo*hi)
+            out["raw_mfma_flops_per_launch"] = 3 * ph["flops"]
+            out["raw_mfma_TFLOPs"] = 3 * ach
+        return out
     ach = ph["bytes"] / sec / 1e9
     return {"kernel": KERNEL[name], "phase": name, "bound": "hbm", "achieved": ach, "peak": PEAK["hbm_GBs"],
             "unit": "GB/s", "frac": ach / PEAK["hbm_GBs"], "traffic": traffic_of(workload, name),
@@ -180,23 +187,6 @@ def shell_bench(ctx, binding, workloads, steps, warmup):
     return {"updates_per_s": r["updates_per_s"], "ms_per_step": r["ms_per_step"], "stencil_march": r["stencil_march"],
             "roofline": roofline_of(r["phases"], "split16", "shell_dd_129_split16"),
             "phases_ms_per_launch": {p: round(v["ms"], 5) for p, v in r["phases"].items()}}
-
-
-def batch_bench(ctx, binding, workloads, steps, warmup, plain):
-    """256 single-domain instances of uneven sides (33..257) with Gaussian-bump monitors, batched
-    split form; plain: also the plain FP64 method on the same instances."""
-    batch = workloads.bumps_batch()
-    rb = timed_plan(ctx, binding, batch, "split16", "batched", steps, warmup, phase_reps=10, tune=True)
-    out = {"batched_split16_updates_per_s": rb["updates_per_s"], "batched_ms_per_step": rb["ms_per_step"],
-           "stencil_march": rb["stencil_march"],
-           "roofline": roofline_of(rb["phases"], "split16", "bumps_batch_256_split16"),
-           "phases_ms_per_launch": {p: round(v["ms"], 5) for p, v in rb["phases"].items()}}
-    if plain:
-        rp = timed_plan(ctx, binding, batch, "fp64", "plain", 10, 1)
-        out.update({"plain_fp64_updates_per_s": rp["updates_per_s"], "plain_ms_per_step": rp["ms_per_step"],
-                    "speedup": rb["updates_per_s"] / rp["updates_per_s"]})
-        log(f"batch 256: {rb['updates_per_s']:.3e} vs plain fp64 {rp['updates_per_s']:.3e}")
-    return out
 
 
 def stencil_roofline(ctx, binding, workloads):
@@ -231,9 +221,14 @@ def stencil_roofline(ctx, binding, workloads):
     return out
 
 
+def _pct(lat, p):
+    return lat[min(len(lat) - 1, int(round(p / 100 * (len(lat) - 1))))]
+
+
 def serve_stream(binding, workloads, count, budget):
-    """Open-loop Poisson stream (mean 200 req/s) through pma_submit / pma_poll.  Latency is taken
-    on the client: from the request's scheduled arrival to the poll that sees it DONE."""
+    """Open-loop Poisson stream (mean 200 req/s) through pma_submit / pma_poll (continuous
+    batching, batched split form).  Latency is taken on the client: from the request's scheduled
+    arrival to the poll that sees it DONE."""
     ws = workloads.stream(count=count)
     ctx = binding.Context(0, budget_bytes=budget)
     tickets = [None] * len(ws)
@@ -263,7 +258,7 @@ def serve_stream(binding, workloads, count, budget):
             if state in (2, 3):
                 done[i] = (state, st, time.perf_counter() - t_start)
         time.sleep(0.0005)
-        if time.perf_counter() - t_start > 300:
+        if time.perf_counter() - t_start > 600:
             raise RuntimeError("serving stream did not drain")
     th.join()
     wall = max(v[2] for v in done.values())
@@ -271,38 +266,170 @@ def serve_stream(binding, workloads, count, budget):
     ok = [i for i, v in done.items() if v[0] == 2]
     lat = sorted(1e3 * (done[i][2] - ws[i]["arrival_s"]) for i in ok)
     upd = sum(math.prod(ws[i]["grid"]["n"]) * ws[i]["time"]["steps"] for i in ok)
-    pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100 * (len(lat) - 1))))]
     return {"requests": len(ws), "done": len(ok), "failed": len(ws) - len(ok), "wall_s": wall,
-            "meshes_per_s": len(ok) / wall, "updates_per_s": upd / wall, "p50_ms": pct(50), "p99_ms": pct(99),
-            "max_submit_lag_ms": 1e3 * max(late),
+            "meshes_per_s": len(ok) / wall, "updates_per_s": upd / wall, "p50_ms": _pct(lat, 50),
+            "p99_ms": _pct(lat, 99), "max_submit_lag_ms": 1e3 * max(late),
             "mean_server_queue_ms": sum(v[1]["ms_queue"] for v in done.values()) / len(done),
-            "budget_bytes": budget, "offered_rate_per_s": 200.0,
-            "arrival_window_s": ws[-1]["arrival_s"]}
+            "budget_bytes": budget, "offered_rate_per_s": 200.0, "arrival_window_s": ws[-1]["arrival_s"],
+            "form": "continuous batching, batched split16, graph-replayed ticks"}
 
 
-def cpu_baseline(w, steps):
+def serve_plain(binding, workloads, count, prec="fp64"):
+    """The plain per-subdomain method serving the same stream: requests taken one at a time in
+    arrival order (FIFO), each solved alone by pma_dd_mesh in the plain form (one subdomain per
+    launch, no graph), waiting for its arrival time when the queue is empty.  Latency from the
+    scheduled arrival to the end of its solve."""
+    ws = workloads.stream(count=count)
+    ctx = binding.Context(0, budget_bytes=8 << 30)
+    lat, upd = [], 0
+    t_start = time.perf_counter()
+    for w in ws:
+        d = w["arrival_s"] - (time.perf_counter() - t_start)
+        if d > 0:
+            time.sleep(d)
+        ctx.dd_mesh(w, precision=prec, exec_="plain")
+        lat.append(1e3 * (time.perf_counter() - t_start - w["arrival_s"]))
+        upd += math.prod(w["grid"]["n"]) * w["time"]["steps"]
+    wall = time.perf_counter() - t_start
+    ctx.close()
+    lat.sort()
+    return {"requests": len(ws), "wall_s": wall, "meshes_per_s": len(ws) / wall, "updates_per_s": upd / wall,
+            "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "offered_rate_per_s": 200.0,
+            "form": f"plain {prec}: one request at a time, one subdomain per launch, no graph"}
+
+
+# ---- the oracle on the host's cores ----------------------------------------------------------
+
+def _oracle_worker_init():
+    # one thread per worker process: the pool supplies the parallelism
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    import oracle  # noqa: F401  (imported once per worker, outside the timed tasks)
+
+
+def _oracle_instance(w):
     import oracle as O
     g = w["grid"]
     gs = O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"]))
     t = w["time"]
     t0 = time.perf_counter()
-    O.solve_dd(gs, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], steps)
-    dt = time.perf_counter() - t0
-    return {"value": math.prod(g["n"]) * steps / dt, "unit": "grid-point updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the same 513^2 4x4 DD workload (FP64 NumPy oracle, one thread), "
-                      f"{dt:.1f} s"}
+    r = O.solve_single(gs, w["monitor"], t["dt"], t["gamma"], t["steps"])
+    return r.mesh, r.min_det, r.min_cell, (r.res_hist[-1] if r.res_hist else 0.0), time.perf_counter() - t0
+
+
+def _noop(_):
+    return os.getpid()
+
+
+def host_cores():
+    """Logical CPUs visible to this process (capped at the 16 a one-GPU share of the box has)
+    and the CPU model from lscpu."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return min(n, 16), os.cpu_count(), model
+
+
+def cpu_baseline_batch(ws):
+    """The FP64 oracle on every instance of the batch workload, one single-threaded process per
+    host core (multiprocessing, spawn: the workers import only the oracle), all 200 steps of all
+    256 instances; the pool is started and warmed before the clock.  Returns the baseline and the
+    oracle's meshes (the reference for the per-result errors)."""
+    import multiprocessing as mp
+    cores, ncpu, model = host_cores()
+    ctxm = mp.get_context("spawn")
+    with ctxm.Pool(cores, initializer=_oracle_worker_init) as pool:
+        pool.map(_noop, range(4 * cores))
+        order = sorted(range(len(ws)), key=lambda i: -math.prod(ws[i]["grid"]["n"]))  # largest first
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_instance, [ws[i] for i in order], chunksize=1)
+        dt = time.perf_counter() - t0
+    out = [None] * len(ws)
+    for k, i in enumerate(order):
+        out[i] = res[k]
+    upd = sum(math.prod(w["grid"]["n"]) * w["time"]["steps"] for w in ws)
+    base = {"value": upd / dt, "unit": "grid-point updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole workload: all {len(ws)} instances x {ws[0]['time']['steps']} steps, "
+                      f"FP64 NumPy/SciPy oracle, {cores} single-threaded processes (largest instances first), "
+                      f"{dt:.1f} s wall, {sum(r[4] for r in res):.1f} s of CPU",
+            "os_cpu_count": ncpu, "cpu_model": model}
+    return base, out
+
+
+def batch_accuracy(ctx, binding, ws, ref, prec):
+    """Every instance solved by pma_dd_mesh_batch in `prec`, against the oracle's meshes: max node
+    error / domain size per result, FP64 final residual, min det and min cell."""
+    import numpy as np
+    outs, stats = ctx.dd_mesh_batch(ws, precision=prec)
+    err, res, dets, cells, cell_rel = [], [], [], [], []
+    for i, w in enumerate(ws):
+        ext = max(b - a for a, b in zip(w["grid"]["lo"], w["grid"]["hi"]))
+        err.append(float(np.max(np.abs(outs[i] - ref[i][0]))) / ext)
+        res.append(stats[i]["final_resid"])
+        dets.append(stats[i]["min_det"])
+        cells.append(stats[i]["min_cell"])
+        cell_rel.append(abs(stats[i]["min_cell"] - ref[i][2]) / abs(ref[i][2]))
+    r3 = lambda v: [float(f"{x:.3g}") for x in v]
+    return {"precision": prec, "max_mesh_err_over_results": max(err), "median_mesh_err": float(np.median(err)),
+            "tolerance": 1e-10 if prec == "fp64" else 1e-5,
+            "max_min_cell_rel_diff": max(cell_rel),
+            "max_final_resid_rel_diff": max(abs(a - b[3]) / b[3] for a, b in zip(res, ref)),
+            "per_result": {"mesh_err": r3(err), "final_resid": r3(res), "min_det": r3(dets)}}
+
+
+def cpu_baseline_sine(w, steps):
+    """The oracle on the 513^2 4x4 DD workload, one process, scipy.fft over all cores."""
+    import oracle as O
+    import scipy.fft
+    cores, _, _ = host_cores()
+    g = w["grid"]
+    gs = O.GridSpec(tuple(g["n"]), tuple(g["lo"]), tuple(g["hi"]))
+    t = w["time"]
+    with scipy.fft.set_workers(cores):
+        t0 = time.perf_counter()
+        O.solve_dd(gs, w["dd"]["parts"], w["dd"]["overlap"], w["monitor"], t["dt"], t["gamma"], steps)
+        dt = time.perf_counter() - t0
+    return {"value": math.prod(g["n"]) * steps / dt, "unit": "grid-point updates/s", "cores": cores,
+            "sample": f"{steps} steps of the 513^2 4x4 DD workload, scipy.fft workers = {cores}, {dt:.1f} s"}
+
+
+def sine_forms(ctx, binding, workloads, steps, warmup):
+    w = workloads.sine_dd()
+    forms = {}
+    for f in ["split16", "fp32", "fp64plain", "fp64"]:
+        prec, ex = ("fp64", "plain") if f == "fp64plain" else (f, "batched")
+        st = steps if f != "fp64plain" else max(1, min(steps, 100))
+        forms[f] = timed_plan(ctx, binding, [w], prec, ex, st, min(warmup, st), phase_reps=50, tune=ex == "batched")
+        log(f"sine 513 {f}: {forms[f]['updates_per_s']:.4e} updates/s, {forms[f]['ms_per_step']:.4f} ms/step")
+    out = {"workload": "sine-layer DD 513x513, 4x4 subdomains, overlap 8 cells, gamma = 4 h^2, dt = gamma / 5",
+           "forms": {k: {kk: vv for kk, vv in v.items() if kk != "phases"} for k, v in forms.items()},
+           "phases_ms_per_launch": {k: {p: round(v["ms"], 5) for p, v in f["phases"].items()}
+                                    for k, f in forms.items()},
+           "roofline_split16": roofline_of(forms["split16"]["phases"], "split16", "sine_dd_513_split16"),
+           "batched_split16_over_plain_fp64": forms["split16"]["updates_per_s"] / forms["fp64plain"]["updates_per_s"],
+           "glued_vs_single_domain": glued_vs_single(ctx, binding, w, "split16")}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve", type=int, default=600, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve", type=int, default=2000, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-small", type=int, default=500, help="requests in the 512 MiB serving stream")
+    ap.add_argument("--serve-plain", type=int, default=40, help="requests of the stream served by the plain method")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["split16", "fp32", "fp64plain", "stencil_large", "paper", "shell", "batch"], default=None,
+    ap.add_argument("--only", choices=["fp64", "split16", "fp32", "fp64plain", "sine", "stencil_large", "paper",
+                                       "shell", "serve"], default=None,
                     help="one form of the headline workload, or one other workload, only (profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 10 times (calibrates HBM byte counters)")
@@ -323,79 +450,98 @@ def main():
     import torch
     from paper_2006_14602_amd import binding, workloads
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.only == "paper":
+    if args.only in ("paper", "shell", "stencil_large", "sine"):
         ctx = binding.Context(0, budget_bytes=12 << 30)
-        print(json.dumps({"paper_workloads": paper_workloads(ctx, binding, workloads)}))
-        ctx.close()
-        return
-    if args.only in ("shell", "batch"):
-        ctx = binding.Context(0, budget_bytes=12 << 30)
-        if args.only == "shell":
+        if args.only == "paper":
+            r = {"paper_workloads": paper_workloads(ctx, binding, workloads)}
+        elif args.only == "shell":
             r = {"shell_dd_129_split16": shell_bench(ctx, binding, workloads, args.steps, args.warmup)}
+        elif args.only == "sine":
+            r = {"sine_dd_513": sine_forms(ctx, binding, workloads, args.steps, args.warmup)}
         else:
-            r = {"bumps_batch_256": batch_bench(ctx, binding, workloads, args.steps, args.warmup, plain=False)}
+            r = {"stencil_hbm_large": stencil_roofline(ctx, binding, workloads)}
         print(json.dumps(r))
         ctx.close()
         return
-    if args.only == "stencil_large":
-        ctx = binding.Context(0, budget_bytes=12 << 30)
-        print(json.dumps({"stencil_hbm_large": stencil_roofline(ctx, binding, workloads)}))
-        ctx.close()
+    if args.only == "serve":
+        r = {"budget_8GiB": serve_stream(binding, workloads, args.serve, 8 << 30)}
+        if args.serve_small > 0:
+            r["budget_512MiB"] = serve_stream(binding, workloads, args.serve_small, 512 << 20)
+        if args.serve_plain > 0:
+            r["plain_fp64_same_stream"] = serve_plain(binding, workloads, args.serve_plain)
+            r["batched_same_prefix"] = serve_stream(binding, workloads, args.serve_plain, 8 << 30)
+        print(json.dumps({"serving": r}))
         return
-    w = workloads.sine_dd()
+
+    batch = workloads.bumps_batch()
     ctx = binding.Context(0, budget_bytes=12 << 30)
     forms = {}
-    todo = [args.only] if args.only else ["split16", "fp32", "fp64plain"]
+    todo = [args.only] if args.only else ["fp64", "split16", "fp32", "fp64plain"]
     for f in todo:
         prec, ex = ("fp64", "plain") if f == "fp64plain" else (f, "batched")
-        steps = args.steps if f != "fp64plain" else max(1, min(args.steps, 100))
-        forms[f] = timed_plan(ctx, binding, [w], prec, ex, steps, min(args.warmup, steps), phase_reps=50,
-                              tune=ex == "batched")
-        log(f"{f}: {forms[f]['updates_per_s']:.4e} updates/s, {forms[f]['ms_per_step']:.4f} ms/step")
-    main_form = args.only or "split16"
+        steps = args.steps if f != "fp64plain" else max(1, min(args.steps, 10))
+        forms[f] = timed_plan(ctx, binding, batch, prec, ex, steps, min(args.warmup, steps) if ex == "batched" else 1,
+                              phase_reps=10 if ex == "batched" else 0, tune=ex == "batched")
+        log(f"batch {f}: {forms[f]['updates_per_s']:.4e} updates/s, {forms[f]['ms_per_step']:.4f} ms/step")
+    main_form = args.only or "fp64"
     m = forms[main_form]
     prec = "fp64" if main_form == "fp64plain" else main_form
     out = {
         "metric": "PMA grid-point updates/s, batched FP32 vs plain FP64, p50/p99 mesh latency",
         "value": m["updates_per_s"], "unit": "grid-point updates/s", "n_gpus": 1, "steps": m["steps"],
         "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp64" if prec == "fp64" else "fp32", "data": "synthetic",
-        "config": {"workload": "sine-layer DD 513x513, 4x4 subdomains, overlap 8 cells", "grid": w["grid"]["n"],
-                   "parts": w["dd"]["parts"], "overlap_cells": w["dd"]["overlap"][0],
-                   "gamma": w["time"]["gamma"], "dt": w["time"]["dt"],
+        "vs_baseline": None, "dtype": {"fp64": "f64", "split16": "f32", "fp32": "f32"}[prec], "data": "synthetic",
+        "config": {"workload": "256 single-domain 2D meshes, sides U{33..257} (seed 20060146), 1-4 Gaussian bumps, "
+                               "gamma = 1, dt = 1e-3, 200 steps",
+                   "instances": len(batch), "nodes_per_step": nodes_of(batch),
                    "precision": {"split16": "fp32 state/stencil, fp16 hi+lo matrix-core DCT, fp32 accumulate",
-                                 "fp32": "fp32 everywhere", "fp64": "fp64 everywhere"}[prec],
+                                 "fp32": "fp32 everywhere", "fp64": "fp64 everywhere (the paper's precision)"}[prec],
                    "exec": "plain" if main_form == "fp64plain" else "batched (graph replay)"},
-        "roofline": roofline_of(m["phases"], prec, "sine_dd_513_" + main_form),
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "phases"} for k, v in forms.items()},
         "phases_ms_per_launch": {k: {p: round(v["ms"], 5) for p, v in f["phases"].items()}
-                                 for k, f in forms.items()},
+                                 for k, f in forms.items() if f["phases"]},
     }
-    if "fp64plain" in forms and main_form != "fp64plain":
-        out["batched_fp32_over_plain_fp64"] = m["updates_per_s"] / forms["fp64plain"]["updates_per_s"]
-    if not args.only:
-        out["glued_vs_single_domain"] = glued_vs_single(ctx, binding, w, prec)
+    if m["phases"]:
+        out["roofline"] = roofline_of(m["phases"], prec, "bumps_batch_256_" + prec)
+        ksum = sum(v["ms"] for k, v in m["phases"].items() if k != "resid")
+        out["kernel_ms_per_step"] = ksum
+    if "split16" in forms and forms["split16"]["phases"]:
+        out["roofline_split16"] = roofline_of(forms["split16"]["phases"], "split16", "bumps_batch_256_split16")
+    if "fp64plain" in forms:
+        for f in ("fp64", "split16", "fp32"):
+            if f in forms:
+                out[f"batched_{f}_over_plain_fp64"] = forms[f]["updates_per_s"] / forms["fp64plain"]["updates_per_s"]
+    if not args.no_cpu and not args.only:
+        base, ref = cpu_baseline_batch(batch)
+        out["cpu_baseline"] = base
+        log(f"oracle on {base['cores']} cores: {base['value']:.3e} updates/s")
+        out["accuracy_vs_oracle"] = {p: batch_accuracy(ctx, binding, batch, ref, p) for p in ("fp64", "split16")}
     if not args.quick and not args.only:
         extra = {}
+        extra["sine_dd_513"] = sine_forms(ctx, binding, workloads, 500, 20)
         ring = workloads.ring()
         r = timed_plan(ctx, binding, [ring], "fp64", "batched", 200, 10)
         extra["ring_65_fp64"] = {k: r[k] for k in ("updates_per_s", "ms_per_step")}
         log(f"ring 65^2 fp64: {r['updates_per_s']:.3e}")
         extra["shell_dd_129_split16"] = shell_bench(ctx, binding, workloads, 200, 5)
-        extra["bumps_batch_256"] = batch_bench(ctx, binding, workloads, 200, 5, plain=True)
         extra["stencil_hbm_large"] = stencil_roofline(ctx, binding, workloads)
         log(f"stencil large: {extra['stencil_hbm_large']['achieved']:.0f} GB/s")
+        if not args.no_cpu:
+            extra["sine_dd_513"]["cpu_baseline"] = cpu_baseline_sine(workloads.sine_dd(), 300)
         out["other_workloads"] = extra
         out["paper_workloads"] = paper_workloads(ctx, binding, workloads)
     ctx.close()
     if args.serve > 0 and not args.quick and not args.only:
-        s8 = serve_stream(binding, workloads, args.serve, 8 << 30)
-        log(f"serve 8GB: {s8}")
-        s512 = serve_stream(binding, workloads, max(50, args.serve // 4), 512 << 20)
-        log(f"serve 512MB: {s512}")
-        out["serving"] = {"budget_8GiB": s8, "budget_512MiB": s512}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        sv = {"budget_8GiB": serve_stream(binding, workloads, args.serve, 8 << 30)}
+        log(f"serve 8GB: {sv['budget_8GiB']}")
+        if args.serve_small > 0:
+            sv["budget_512MiB"] = serve_stream(binding, workloads, args.serve_small, 512 << 20)
+            log(f"serve 512MB: {sv['budget_512MiB']}")
+        if args.serve_plain > 0:
+            sv["plain_fp64_same_stream"] = serve_plain(binding, workloads, args.serve_plain)
+            sv["batched_same_prefix"] = serve_stream(binding, workloads, args.serve_plain, 8 << 30)
+            log(f"serve plain: {sv['plain_fp64_same_stream']}")
+        out["serving"] = sv
     print(json.dumps(out))
 
 

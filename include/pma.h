@@ -262,8 +262,10 @@ int pma_plan_sync(pma_plan* plan);
  * Times each phase on its own: nsteps launches back to back between two HIP events on the
  * stream the kernels run on; ms[ph] receives the mean device milliseconds per launch (cap >= 8
  * entries).  flops[] and bytes[] (may be NULL) receive each phase's algorithmic floating-point
- * operations and compulsory HBM bytes per launch.  The plan's state is saved before and
- * restored after (the call needs device memory for one copy of it).  *nphases receives 8. */
+ * operations and compulsory HBM bytes per launch.  With cap >= 9, entry 8 is the FP64 residual
+ * reduction that runs every R steps (flops: partial sums added; bytes: partial sums read).  The
+ * plan's state is saved before and restored after (the call needs device memory for one copy of
+ * it).  *nphases receives 8, or 9 with cap >= 9. */
 int pma_plan_phase_times(pma_plan* plan, int nsteps, double* ms, double* flops, double* bytes, int cap,
                          int* nphases);
 

@@ -421,7 +421,7 @@ class Context:
         return {"queued": q.value, "running": r.value, "finished": f.value, "bytes_in_use": b.value}
 
 
-PHASES = ["transmit", "stencil", "euler", "fwd_last", "fwd_mid", "pair0", "inv_mid", "inv_last"]
+PHASES = ["transmit", "stencil", "euler", "fwd_last", "fwd_mid", "pair0", "inv_mid", "inv_last", "resid"]
 
 
 class Plan:
@@ -445,11 +445,11 @@ class Plan:
         _check(self._L.pma_plan_sync(self.h))
 
     def phase_times(self, n: int):
-        ms = (c_double * 8)()
-        fl = (c_double * 8)()
-        by = (c_double * 8)()
+        ms = (c_double * 9)()
+        fl = (c_double * 9)()
+        by = (c_double * 9)()
         nph = c_int()
-        _check(self._L.pma_plan_phase_times(self.h, int(n), ms, fl, by, 8, ctypes.byref(nph)))
+        _check(self._L.pma_plan_phase_times(self.h, int(n), ms, fl, by, 9, ctypes.byref(nph)))
         return {PHASES[i]: {"ms": ms[i], "flops": fl[i], "bytes": by[i]} for i in range(nph.value)}
 
     def autotune(self, reps: int = 10):

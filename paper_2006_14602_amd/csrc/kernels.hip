@@ -2112,18 +2112,24 @@ __global__ __launch_bounds__(256) void transmit_kernel(const SubDev* __restrict_
 // K8: residual per instance = max over subdomains of sqrt(sum of partials) (fixed order)
 // ------------------------------------------------------------------------------------------
 
-__global__ void resid_kernel(const SubDev* __restrict__ subs, const InstDev* __restrict__ insts,
-                             int ninst, const double* __restrict__ partials, double* out) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < ninst; q += gridDim.x * blockDim.x) {
-    const InstDev& I = insts[q];
-    double best = 0.0;
-    for (int s = I.first_sub; s < I.first_sub + I.nsub; ++s) {
-      double acc = 0.0;
-      for (int p = 0; p < subs[s].nparts; ++p) acc += partials[subs[s].part0 + p];
-      best = fmax(best, acc);
-    }
-    out[q] = sqrt(best);
+__global__ __launch_bounds__(256) void resid_kernel(const SubDev* __restrict__ subs,
+                                                    const InstDev* __restrict__ insts, int ninst,
+                                                    const double* __restrict__ partials, double* out) {
+  // one workgroup per instance: each subdomain's partial sums are added in a fixed order (lane
+  // strided, a butterfly within each wave, the four waves in a fixed pairing), the same for any
+  // number of instances; the instance's residual is the largest subdomain's
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  if (q >= ninst) return;
+  const InstDev& I = insts[q];
+  double best = 0.0;
+  for (int s = I.first_sub; s < I.first_sub + I.nsub; ++s) {
+    const int p0 = subs[s].part0, np = subs[s].nparts;
+    double acc = 0.0;
+    for (int p = threadIdx.x; p < np; p += 256) acc += partials[p0 + p];
+    best = fmax(best, block_sum256(acc, red));
   }
+  if (threadIdx.x == 0) out[q] = sqrt(best);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2501,7 +2507,7 @@ hipError_t enable_large_lds() {
 hipError_t launch_resid(const SubDev* subs, const InstDev* insts, int ninst, const double* partials,
                         double* out, hipStream_t s) {
   if (ninst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(resid_kernel, dim3(nblk(ninst, 256)), dim3(256), 0, s, subs, insts, ninst, partials, out);
+  hipLaunchKernelGGL(resid_kernel, dim3(ninst), dim3(256), 0, s, subs, insts, ninst, partials, out);
   return hipGetLastError();
 }
 

@@ -1274,6 +1274,10 @@ struct Batch {
   static constexpr int kGraphSteps = 8;
   hipGraph_t graph_n = nullptr;
   hipGraphExec_t gexec_n = nullptr;
+  // the remainder of a run (1 .. kGraphSteps - 1 steps) as one graph per length, captured on
+  // first use, so a run of any length submits ceil(steps / kGraphSteps) graphs
+  hipGraph_t graph_r[kGraphSteps] = {};
+  hipGraphExec_t gexec_r[kGraphSteps] = {};
   bool use_graph = true;  // replay captured steps; false: launch the phases directly
   StepArgs sa{};
 
@@ -1309,6 +1313,12 @@ struct Batch {
     graph = nullptr;
     gexec_n = nullptr;
     graph_n = nullptr;
+    for (int r = 0; r < kGraphSteps; ++r) {
+      if (gexec_r[r]) hipGraphExecDestroy(gexec_r[r]);
+      if (graph_r[r]) hipGraphDestroy(graph_r[r]);
+      gexec_r[r] = nullptr;
+      graph_r[r] = nullptr;
+    }
   }
   bool built = false;
 
@@ -1869,6 +1879,11 @@ struct Batch {
       for (; nsteps >= kGraphSteps; nsteps -= kGraphSteps) {
         if (!gexec_n) capture(kGraphSteps, graph_n, gexec_n);
         HIPCHK(hipGraphLaunch(gexec_n, ctx->stream));
+      }
+      if (nsteps > 1) {
+        if (!gexec_r[nsteps]) capture(nsteps, graph_r[nsteps], gexec_r[nsteps]);
+        HIPCHK(hipGraphLaunch(gexec_r[nsteps], ctx->stream));
+        nsteps = 0;
       }
     }
     for (; nsteps > 0; --nsteps) step(plain);
@@ -2786,6 +2801,17 @@ int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, dou
       HIPCHK(hipEventElapsedTime(&t, e0, e1));
       ms[ph] = t / nsteps;
     }
+    if (cap > kPhases) {  // the FP64 residual reduction (every R steps, and at the end)
+      const int ni = (int)B.h_insts.size();
+      HIPCHK(launch_resid(B.d_subs, B.d_insts, ni, B.d_partials, B.d_resid, st));
+      HIPCHK(hipEventRecord(e0, st));
+      for (int k = 0; k < nsteps; ++k) HIPCHK(launch_resid(B.d_subs, B.d_insts, ni, B.d_partials, B.d_resid, st));
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      ms[kPhases] = t / nsteps;
+    }
     copy_state(false);
     HIPCHK(hipStreamSynchronize(st));
   } catch (Err&) {
@@ -2803,6 +2829,11 @@ int pma_plan_phase_times(pma_plan* P, int nsteps, double* ms, double* flops, dou
   for (int ph = 0; ph < kPhases; ++ph) {
     if (flops) flops[ph] = fl[ph];
     if (bytes) bytes[ph] = by[ph];
+  }
+  if (cap > kPhases) {
+    *nph = kPhases + 1;
+    if (flops) flops[kPhases] = (double)B.npartials;
+    if (bytes) bytes[kPhases] = (double)B.npartials * 8.0;
   }
   return PMA_OK;
   API_END
