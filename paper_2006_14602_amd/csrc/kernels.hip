@@ -722,6 +722,15 @@ __device__ inline double block_min256(double v, double* red) {
 
 template <int KIND> struct Op;
 
+// Fragment-major order of a DCT matrix for the 16x16x4 products (FP32 and FP64): entry (r, k) of a
+// matrix with ldb (a multiple of 4) padded columns sits at ((r / 16) (ldb / 4) + k / 4) 64 +
+// (k % 4) 16 + r % 16.  The fragment of row block r / 16 and k steps k0 .. k0 + 3 (k0 a multiple
+// of 4) is then one contiguous run in lane order (lane l = 16 g + l16 takes row l16, k = k0 + g):
+// a wave's load touches 2 (FP32) or 4 (FP64) cache lines instead of 16.
+__device__ inline long frag_index(int ldb, int r, int k0, int g) {
+  return ((long)(r >> 4) * (ldb >> 2) + (k0 >> 2)) * 64 + g * 16 + (r & 15);
+}
+
 template <> struct Op<PREC_SPLIT16> {
   typedef float T;
   typedef float4_t acc_t;
@@ -826,14 +835,16 @@ template <> struct Op<PREC_F32> {
   static __device__ inline frag lds_frag_cvt(const char* lds, int ld, int r, int k0, int g, float sc) {
     return lds_frag(lds, ld, r, k0, g, sc);
   }
-  static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
-    return gp<float>(p)[(long)r * ld + k0 + g];
+  // basis matrices are stored fragment-major (see frag_index): one fragment is 256 contiguous
+  // bytes, one per lane in lane order
+  static __device__ inline frag glob_frag(const void* p, const void*, int ldb, int r, int k0, int g) {
+    return gp<float>(p)[frag_index(ldb, r, k0, g)];
   }
-  static __device__ inline frag lbasis_frag(const char* p, const char*, int ld, int r, int k0, int g) {
-    return ((const float*)p)[r * ld + k0 + g];
+  static __device__ inline frag lbasis_frag(const char* p, const char*, int ldb, int r, int k0, int g) {
+    return ((const float*)p)[frag_index(ldb, r, k0, g)];
   }
   static __device__ inline frag zero_frag() { return 0.f; }
-  enum { BASIS_BYTES = 4, OPAD = 4, BPAD = 4 };
+  enum { BASIS_BYTES = 4, OPAD = 4 };
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -853,14 +864,15 @@ template <> struct Op<PREC_F64> {
   static __device__ inline frag lds_frag_cvt(const char* lds, int ld, int r, int k0, int g, float sc) {
     return lds_frag(lds, ld, r, k0, g, sc);
   }
-  static __device__ inline frag glob_frag(const void* p, const void*, int ld, int r, int k0, int g) {
-    return gp<double>(p)[(long)r * ld + k0 + g];
+  // basis matrices fragment-major (see frag_index): one fragment is 512 contiguous bytes
+  static __device__ inline frag glob_frag(const void* p, const void*, int ldb, int r, int k0, int g) {
+    return gp<double>(p)[frag_index(ldb, r, k0, g)];
   }
-  static __device__ inline frag lbasis_frag(const char* p, const char*, int ld, int r, int k0, int g) {
-    return ((const double*)p)[r * ld + k0 + g];
+  static __device__ inline frag lbasis_frag(const char* p, const char*, int ldb, int r, int k0, int g) {
+    return ((const double*)p)[frag_index(ldb, r, k0, g)];
   }
   static __device__ inline frag zero_frag() { return 0.0; }
-  enum { BASIS_BYTES = 8, OPAD = 2, BPAD = 2 };
+  enum { BASIS_BYTES = 8, OPAD = 2 };
   static __device__ inline void mma(acc_t& c, frag a, frag b) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -1740,6 +1752,7 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
       }
     }
   };
+
   products(b1h, b1l, sc);
   if constexpr (!PAIR) {
     const T fu = (!inv) ? T(A.fwd_unscale) : T(1);

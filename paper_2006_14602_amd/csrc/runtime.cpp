@@ -871,10 +871,18 @@ static void* arena_alloc(pma_ctx* c, size_t b) {
 
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// row stride of the DCT matrices: the padded length plus 16 bytes, so that the 16 rows of a
-// matrix-core fragment start in distinct LDS bank groups when the matrix is copied into LDS
+// row stride of the DCT matrices.  Split form: the padded length plus 16 bytes, so that the 16
+// rows of a matrix-core fragment start in distinct LDS bank groups when the matrix is copied into
+// LDS.  FP32 and FP64: the padded length; these matrices are stored fragment-major (frag_pos), so
+// a fragment is contiguous in memory and in LDS.
 static int basis_stride(int n, int prec) {
-  return round_up(n, 32) + (prec == PMA_FP64 ? 2 : prec == PMA_FP32 ? 4 : 8);
+  return round_up(n, 32) + (prec == PMA_FP32_SPLIT16 ? 8 : 0);
+}
+
+// position of entry (r, k) of an FP32 / FP64 matrix with ldb padded columns, fragment-major: the
+// 16 x 4 fragment of row block r / 16 and k group k / 4 is 64 consecutive entries, k % 4 major
+static size_t frag_pos(int ldb, int r, int k) {
+  return ((size_t)(r / 16) * (ldb / 4) + k / 4) * 64 + (k % 4) * 16 + r % 16;
 }
 
 static size_t basis_bytes(int n, int prec) {
@@ -911,8 +919,8 @@ static std::unique_ptr<Basis> fill_basis(int n, int prec, char* mem) {
       std::vector<double> A64(rl, 0.0), B64(rl, 0.0);
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
-          A64[(size_t)i * b->ldb + j] = A[(size_t)i * n + j];
-          B64[(size_t)i * b->ldb + j] = B[(size_t)i * n + j];
+          A64[frag_pos(b->ldb, i, j)] = A[(size_t)i * n + j];
+          B64[frag_pos(b->ldb, i, j)] = B[(size_t)i * n + j];
         }
       b->fwd = put(A64.data(), rl * 8);
       b->inv = put(B64.data(), rl * 8);
@@ -924,8 +932,8 @@ static std::unique_ptr<Basis> fill_basis(int n, int prec, char* mem) {
         std::vector<float> A32(rl, 0.f), B32(rl, 0.f);
         for (int i = 0; i < n; ++i)
           for (int j = 0; j < n; ++j) {
-            A32[(size_t)i * b->ldb + j] = (float)A[(size_t)i * n + j];
-            B32[(size_t)i * b->ldb + j] = (float)B[(size_t)i * n + j];
+            A32[frag_pos(b->ldb, i, j)] = (float)A[(size_t)i * n + j];
+            B32[frag_pos(b->ldb, i, j)] = (float)B[(size_t)i * n + j];
           }
         b->fwd = put(A32.data(), rl * 4);
         b->inv = put(B32.data(), rl * 4);
@@ -1401,7 +1409,9 @@ struct Batch {
   // kLdsBasisMaxTiles strips: every strip then reads its axis' DCT matrices from L2, and four
   // blocks per workgroup read them a quarter as often.  A launch of fewer strips (a sweep level of
   // an alternating request) is latency-bound and keeps the narrow strips.  Bitwise the same
-  // results; FP32 and split forms, axes up to kWideMaxLd.
+  // results; FP32 and split forms, axes up to kWideMaxLd.  (In FP64 the 64-column operand leaves
+  // room for one workgroup per compute unit, whose staging then no longer overlaps other
+  // workgroups' products: measured 1.45x slower on the 256-instance batch, not used.)
   bool wide_ok = true;
   bool wide_[kPhases] = {};
   void choose_wide() {
