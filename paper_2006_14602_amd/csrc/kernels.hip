@@ -880,83 +880,108 @@ template <> struct Op<PREC_F64> {
   static __device__ inline int crow(int g, int q) { return g + 4 * q; }
 };
 
-// acc += rows of the LDS operand (16 x ld, row stride ldo) times basis rows (as columns of B; row
-// stride ldb), and the mirror image.  Basis fragments come from L2: four k steps are requested
-// before any is used so their latencies overlap.  Every product is issued: a k step past the end
-// of the axis multiplies a zero basis fragment with valid data, so the accumulator chain has no
-// branch (a conditional product would make the compiler copy the accumulator out and back,
-// waiting for each product to finish).
-// (over the k range [kb, ke), kb a multiple of the k step)
+// Basis fragments requested per batch: 8 for the 16x16x4 products (FP32, FP64: one k step per
+// product, 32 k per batch, which divides every padded axis length), 4 for the split form
+template <int KIND>
+struct Depth {
+  static constexpr int U = Op<KIND>::KB == 4 ? 8 : 4;
+};
+
+// N k steps from k0 (all within the contraction): the N basis fragments are requested first,
+// then the N products are issued in ascending k.  BASIS_A: the basis fragment is the A operand
+// (rows of the output), else the B operand (columns).
+template <int KIND, bool BASIS_A, int N>
+__device__ inline void mma_steps(typename Op<KIND>::acc_t& acc, const char* lds, int ldo, float sc, const void* bh,
+                                 const void* bl, int ldb, int brow, int l16, int g, int k0) {
+  typedef Op<KIND> O;
+  typename O::frag b[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) b[u] = O::glob_frag(bh, bl, ldb, brow, k0 + u * O::KB, g);
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    const typename O::frag d = O::lds_frag(lds, ldo, l16, k0 + u * O::KB, g, sc);
+    if constexpr (BASIS_A) O::mma(acc, b[u], d);
+    else O::mma(acc, d, b[u]);
+  }
+}
+
+// the last rem (< Depth) k steps from k0: one unrolled body per count, chosen once (rem is uniform)
+template <int KIND, bool BASIS_A, int R>
+__device__ inline void mma_tail(typename Op<KIND>::acc_t& acc, const char* lds, int ldo, float sc, const void* bh,
+                                const void* bl, int ldb, int brow, int l16, int g, int k0, int rem) {
+  if constexpr (R > 0) {
+    if (rem == R) mma_steps<KIND, BASIS_A, R>(acc, lds, ldo, sc, bh, bl, ldb, brow, l16, g, k0);
+    else mma_tail<KIND, BASIS_A, R - 1>(acc, lds, ldo, sc, bh, bl, ldb, brow, l16, g, k0, rem);
+  }
+}
+
+// acc += the k steps [kb, ke) of (LDS operand rows) x (basis rows as columns), or the mirror
+// image (BASIS_A), in ascending k.  kb and ke are multiples of the k step; ke is the axis length
+// rounded up to the k step, so no product multiplies padding.  Basis fragments come from L2 in
+// batches (Depth) requested before any is used, so their latencies overlap; the accumulator chain
+// has no per-step branch (a conditional product would make the compiler copy the accumulator out
+// and back, waiting for each product to finish).
+template <int KIND, bool BASIS_A>
+__device__ inline void mma_range(typename Op<KIND>::acc_t& acc, const char* lds, int kb, int ke, int ldo, float sc,
+                                 const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
+  typedef Op<KIND> O;
+  constexpr int U = Depth<KIND>::U;
+  int k0 = kb;
+  for (; k0 + U * O::KB <= ke; k0 += U * O::KB)
+    mma_steps<KIND, BASIS_A, U>(acc, lds, ldo, sc, bh, bl, ldb, brow, l16, g, k0);
+  mma_tail<KIND, BASIS_A, U - 1>(acc, lds, ldo, sc, bh, bl, ldb, brow, l16, g, k0, (ke - k0) / O::KB);
+}
+
 template <int KIND>
 __device__ inline void mma_lds_by_basis_k(typename Op<KIND>::acc_t& acc, const char* lds, int kb, int ke, int ldo,
                                           float sc, const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
-  typedef Op<KIND> O;
-  constexpr int U = 4;
-  for (int k0 = kb; k0 < ke; k0 += U * O::KB) {
-    typename O::frag b[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * O::KB;
-      b[u] = k < ke ? O::glob_frag(bh, bl, ldb, brow, k, g) : O::zero_frag();
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * O::KB;
-      O::mma(acc, O::lds_frag(lds, ldo, l16, k < ke ? k : k0, g, sc), b[u]);
-    }
-  }
+  mma_range<KIND, false>(acc, lds, kb, ke, ldo, sc, bh, bl, ldb, brow, l16, g);
 }
 
-// the two halves [0, ks) and [ks, ld) at once, into lo and hi: each half's k steps in ascending
-// order as mma_lds_by_basis_k takes them (products with a zero basis fragment past a half's end
-// add exact zeros), with the basis fragments of both halves in flight together
+// the two halves [0, ks) and [ks, ke) into lo and hi, each in ascending k as mma_lds_by_basis_k
+// takes it, with the basis fragments of both halves in flight together while both have full
+// batches left
 template <int KIND>
 __device__ inline void mma_lds_by_basis_2h(typename Op<KIND>::acc_t& lo, typename Op<KIND>::acc_t& hi,
-                                           const char* lds, int ks, int ld, int ldo, float sc, const void* bh,
+                                           const char* lds, int ks, int ke, int ldo, float sc, const void* bh,
                                            const void* bl, int ldb, int brow, int l16, int g) {
   typedef Op<KIND> O;
-  constexpr int U = 2;
-  for (int k0 = 0; k0 < ks; k0 += U * O::KB) {
+  constexpr int U = Depth<KIND>::U / 2;
+  const int m = min(ks, ke - ks);
+  int k0 = 0;
+  for (; k0 + U * O::KB <= m; k0 += U * O::KB) {
     typename O::frag a[U], b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * O::KB, kh = ks + k;
-      a[u] = k < ks ? O::glob_frag(bh, bl, ldb, brow, k, g) : O::zero_frag();
-      b[u] = kh < ld ? O::glob_frag(bh, bl, ldb, brow, kh, g) : O::zero_frag();
+      a[u] = O::glob_frag(bh, bl, ldb, brow, k0 + u * O::KB, g);
+      b[u] = O::glob_frag(bh, bl, ldb, brow, ks + k0 + u * O::KB, g);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * O::KB, kh = ks + k;
-      O::mma(lo, O::lds_frag(lds, ldo, l16, k < ks ? k : k0, g, sc), a[u]);
-      O::mma(hi, O::lds_frag(lds, ldo, l16, kh < ld ? kh : k0, g, sc), b[u]);
+      O::mma(lo, O::lds_frag(lds, ldo, l16, k0 + u * O::KB, g, sc), a[u]);
+      O::mma(hi, O::lds_frag(lds, ldo, l16, ks + k0 + u * O::KB, g, sc), b[u]);
     }
   }
+  mma_range<KIND, false>(lo, lds, k0, ks, ldo, sc, bh, bl, ldb, brow, l16, g);
+  mma_range<KIND, false>(hi, lds, ks + k0, ke, ldo, sc, bh, bl, ldb, brow, l16, g);
 }
 
 template <int KIND>
-__device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ld, int ldo, float sc,
+__device__ inline void mma_lds_by_basis(typename Op<KIND>::acc_t& acc, const char* lds, int ke, int ldo, float sc,
                                         const void* bh, const void* bl, int ldb, int brow, int l16, int g) {
-  mma_lds_by_basis_k<KIND>(acc, lds, 0, ld, ldo, sc, bh, bl, ldb, brow, l16, g);
+  mma_range<KIND, false>(acc, lds, 0, ke, ldo, sc, bh, bl, ldb, brow, l16, g);
 }
 
 template <int KIND>
 __device__ inline void mma_basis_by_lds(typename Op<KIND>::acc_t& acc, const void* ah, const void* al, int ldb,
-                                        const char* lds, int ld, int ldo, float sc, int arow, int l16, int g) {
-  typedef Op<KIND> O;
-  constexpr int U = 4;
-  for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
-    typename O::frag a[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * O::KB;
-      a[u] = k < ld ? O::glob_frag(ah, al, ldb, arow, k, g) : O::zero_frag();
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + u * O::KB;
-      O::mma(acc, a[u], O::lds_frag(lds, ldo, l16, k < ld ? k : k0, g, sc));
-    }
-  }
+                                        const char* lds, int ke, int ldo, float sc, int arow, int l16, int g) {
+  mma_range<KIND, true>(acc, lds, 0, ke, ldo, sc, ah, al, ldb, arow, l16, g);
+}
+
+// contraction length of an axis of n nodes: n rounded up to the k step of the products
+template <int KIND>
+__device__ inline int kext(int n) {
+  return (n + Op<KIND>::KB - 1) / Op<KIND>::KB * Op<KIND>::KB;
 }
 
 // Products with a basis copy in LDS take at most 12 row (column) blocks: three per wave.
@@ -1182,7 +1207,7 @@ __global__ __launch_bounds__(256) void fwd_last_kernel(const int4* __restrict__ 
   const int cb = (col0 >> 4) + wave;
   if (cb * 16 >= C) return;
   typename O::acc_t acc = {0, 0, 0, 0};
-  mma_lds_by_basis<KIND>(acc, lds, ld, ldo, sc, A.fwd, A.fwdl, A.ldb, cb * 16 + l16, l16, g);
+  mma_lds_by_basis<KIND>(acc, lds, kext<KIND>(C), ldo, sc, A.fwd, A.fwdl, A.ldb, cb * 16 + l16, l16, g);
   gmem<T>* __restrict__ out = gpw<T>(S.T);
   const T us = T(A.fwd_unscale) / T(sc);
   const int c = cb * 16 + l16;
@@ -1304,7 +1329,8 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(cons
   const bool active = cb * 16 < C;
   const T isc = T(1) / T(sc);
   // first half: the first ceil(steps / 2) k steps
-  const int ksplit = min(ld, ((ld + 2 * O::KB - 1) / (2 * O::KB)) * O::KB);
+  const int ke = kext<KIND>(C);  // the contraction stops at the axis length (k-step granularity)
+  const int ksplit = min(ke, ((ke + 2 * O::KB - 1) / (2 * O::KB)) * O::KB);
   const int c = cb * 16 + l16;
   acc_t acc = {0, 0, 0, 0};
   T old[4];
@@ -1317,10 +1343,10 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(cons
       }
     }
     if (KS > 1) {
-      mma_lds_by_basis_k<KIND>(acc, lds, kh ? ksplit : 0, kh ? ld : ksplit, ldo, sc, invh, invl, ldb, c, l16, g);
+      mma_lds_by_basis_k<KIND>(acc, lds, kh ? ksplit : 0, kh ? ke : ksplit, ldo, sc, invh, invl, ldb, c, l16, g);
     } else {
       acc_t hi = {0, 0, 0, 0};
-      mma_lds_by_basis_2h<KIND>(acc, hi, lds, ksplit, ld, ldo, sc, invh, invl, ldb, c, l16, g);
+      mma_lds_by_basis_2h<KIND>(acc, hi, lds, ksplit, ke, ldo, sc, invh, invl, ldb, c, l16, g);
       for (int q = 0; q < 4; ++q) acc[q] += hi[q];
     }
   }
@@ -1516,7 +1542,7 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
       const int rb = wave + NW * t;
-      if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, ld, ldo, sc, rb * 16 + l16, l16, g);
+      if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, kext<KIND>(K), ldo, sc, rb * 16 + l16, l16, g);
     }
   }
   if constexpr (!PAIR) {
@@ -1586,7 +1612,8 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
 #pragma unroll
       for (int t = 0; t < MAXRB; ++t) {
         const int rb = wave + NW * t;
-        if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, ld, ldo, sy, rb * 16 + l16, l16, g);
+        if (rb < nrb)
+          mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, kext<KIND>(K), ldo, sy, rb * 16 + l16, l16, g);
       }
     }
 #pragma unroll
@@ -1632,6 +1659,31 @@ __device__ inline void tile_scale4(float amax, float* red, float* out) {
     out[cb] = sc;
   }
   __syncthreads();
+}
+
+// N k steps from k0 of one row block against NC column blocks: N basis fragments requested
+// first, each multiplied into every block
+template <int KIND, int NC, int N>
+__device__ inline void wide_steps(typename Op<KIND>::acc_t (&acc)[NC], const char* lds, int ldo, const float* scl,
+                                  const void* bh, const void* bl, int ldb, int arow, int l16, int g, int k0) {
+  typedef Op<KIND> O;
+  typename O::frag a[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) a[u] = O::glob_frag(bh, bl, ldb, arow, k0 + u * O::KB, g);
+#pragma unroll
+  for (int u = 0; u < N; ++u)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb)
+      O::mma(acc[cb], a[u], O::lds_frag(lds, ldo, cb * 16 + l16, k0 + u * O::KB, g, scl[cb]));
+}
+
+template <int KIND, int NC, int R>
+__device__ inline void wide_tail(typename Op<KIND>::acc_t (&acc)[NC], const char* lds, int ldo, const float* scl,
+                                 const void* bh, const void* bl, int ldb, int arow, int l16, int g, int k0, int rem) {
+  if constexpr (R > 0) {
+    if (rem == R) wide_steps<KIND, NC, R>(acc, lds, ldo, scl, bh, bl, ldb, arow, l16, g, k0);
+    else wide_tail<KIND, NC, R - 1>(acc, lds, ldo, scl, bh, bl, ldb, arow, l16, g, k0, rem);
+  }
 }
 
 template <int KIND, bool PAIR>
@@ -1726,8 +1778,9 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
   for (int t = 0; t < MAXRB; ++t)
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) acc[t][cb] = typename O::acc_t{0, 0, 0, 0};
-  // acc[t][cb] += basis rows of row block wave + 4 t x column block cb; each basis fragment is
-  // loaded once (four k steps ahead) and used for the four blocks
+  // acc[t][cb] += basis rows of row block wave + 4 t x column block cb over k < kext(K); each
+  // basis fragment is loaded once (four k steps ahead) and used for the four blocks
+  const int ke = kext<KIND>(K);
   auto products = [&](const void* bh, const void* bl, const float* scl) {
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
@@ -1735,21 +1788,10 @@ __global__ __launch_bounds__(256) void strip4_kernel(const int4* __restrict__ ti
       if (rb >= nrb) continue;
       const int arow = rb * 16 + l16;
       constexpr int U = 4;
-      for (int k0 = 0; k0 < ld; k0 += U * O::KB) {
-        typename O::frag a[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int k = k0 + u * O::KB;
-          a[u] = k < ld ? O::glob_frag(bh, bl, ldb, arow, k, g) : O::zero_frag();
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int k = k0 + u * O::KB;
-#pragma unroll
-          for (int cb = 0; cb < NC; ++cb)
-            O::mma(acc[t][cb], a[u], O::lds_frag(lds, ldo, cb * 16 + l16, k < ld ? k : k0, g, scl[cb]));
-        }
-      }
+      int k0 = 0;
+      for (; k0 + U * O::KB <= ke; k0 += U * O::KB)
+        wide_steps<KIND, NC, U>(acc[t], lds, ldo, scl, bh, bl, ldb, arow, l16, g, k0);
+      wide_tail<KIND, NC, U - 1>(acc[t], lds, ldo, scl, bh, bl, ldb, arow, l16, g, k0, (ke - k0) / O::KB);
     }
   };
 
@@ -2025,7 +2067,7 @@ __device__ inline void stencil_fwd2_tile(const int4 tl, const StencilCtx<typenam
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int cb = wave + NW * t;
-      if (cb < nrb) mma_lds_by_basis<KIND>(acc[t], op, ld, ldo, sc, fwdh, fwdl, ldb, cb * 16 + l16, l16, g);
+      if (cb < nrb) mma_lds_by_basis<KIND>(acc[t], op, kext<KIND>(n1), ldo, sc, fwdh, fwdl, ldb, cb * 16 + l16, l16, g);
     }
   }
 #pragma unroll
