@@ -37,7 +37,7 @@ template <typename T>
 __device__ inline gmem<T>* gpw(void* p) { return (gmem<T>*)p; }
 
 // ------------------------------------------------------------------------------------------
-// monitor: log rho(x), computed as log1p of the excess over 1 where rho = 1 + (...)
+// monitor: rho(x) as 1 + its excess, each excess evaluated without cancellation
 // ------------------------------------------------------------------------------------------
 
 // sin(2 pi x): the FP32 form uses the hardware sine, whose argument is in revolutions
@@ -69,9 +69,10 @@ __device__ inline T sech2_of(T a4, T e) {
   return a4 * e * frcp(q * q);
 }
 
-// log(rho (1 + e)): FP64 keeps log1p of both excesses; FP32 takes one hardware log2 of the product
-// (the product stays far from the denormal range while the mesh is untangled)
-__device__ inline double log_rho_det(double rex, double e) { return log1p(rex) + log1p(e); }
+// log(rho (1 + e)) as one log of the product (FP64: libm log; FP32: the hardware log2); the
+// product stays far from the denormal range while the mesh is untangled, and its rounding (one
+// unit in the last place of a number near 1) is an absolute error of the same size in F
+__device__ inline double log_rho_det(double rex, double e) { return log((1.0 + rex) * (1.0 + e)); }
 __device__ inline float log_rho_det(float rex, float e) {
   return __builtin_amdgcn_logf((1.f + rex) * (1.f + e)) * 0.693147180559945309f;
 }
