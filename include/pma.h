@@ -162,6 +162,11 @@ typedef struct {
   pma_monitor mon;
   pma_time time;
   double arrival_s;     /* caller's timestamp, echoed back; not used for scheduling */
+  const double* psi0;   /* optional host array of prod(n) doubles: the initial Psi (warm start,
+                           Sec. 2: resuming a solve, or the previous mesh of a time-dependent
+                           problem); NULL: Psi^0 = |xi|^2/2.  pma_submit copies it; the batch
+                           and plan calls read it during the call */
+  int want_psi;         /* served requests: keep the glued final Psi for pma_poll_psi */
 } pma_request;
 
 /* ---- context -------------------------------------------------------------------------- */
@@ -321,8 +326,13 @@ int pma_submit(pma_ctx* ctx, const pma_request* req, uint64_t* ticket);
 
 /* State of a ticket.  When DONE, copies the mesh into mesh_out (dim * prod(n) doubles, may be
  * NULL) and the stats into st, and retires the ticket: later calls return PMA_E_NOTFOUND.
- * FAILED also retires it (st->status holds the cause). */
+ * FAILED also retires it (st->status holds the cause; pma_last_error() describes it). */
 int pma_poll(pma_ctx* ctx, uint64_t ticket, int* state, double* mesh_out, pma_stats* st);
+
+/* pma_poll that also copies the glued final Psi (prod(n) doubles) into psi_out when DONE: the
+ * warm start of the next solve (Sec. 2), e.g. resubmitted with it as psi0.  The request must
+ * have been submitted with want_psi set: PMA_E_INVAL otherwise (the ticket is not retired). */
+int pma_poll_psi(pma_ctx* ctx, uint64_t ticket, int* state, double* mesh_out, double* psi_out, pma_stats* st);
 
 /* Server counters: requests queued, running, finished (done or failed, retired or not); device
  * bytes of the context's arena in use (request state and cached DCT bases) as of the server's

@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
 
 
 class Request(ctypes.Structure):
-    _fields_ = [("grid", Grid), ("dd", DD), ("mon", Monitor), ("time", Time), ("arrival_s", c_double)]
+    _fields_ = [("grid", Grid), ("dd", DD), ("mon", Monitor), ("time", Time), ("arrival_s", c_double),
+                ("psi0", POINTER(c_double)), ("want_psi", c_int)]
 
 
 ALLOC_CB = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
@@ -103,6 +104,8 @@ def load():
     L.pma_dd_mesh_batch.argtypes = [c_void_p, c_int, POINTER(Request), POINTER(POINTER(c_double)), POINTER(Stats)]
     L.pma_submit.argtypes = [c_void_p, POINTER(Request), POINTER(c_uint64)]
     L.pma_poll.argtypes = [c_void_p, c_uint64, POINTER(c_int), POINTER(c_double), POINTER(Stats)]
+    L.pma_poll_psi.argtypes = [c_void_p, c_uint64, POINTER(c_int), POINTER(c_double), POINTER(c_double),
+                               POINTER(Stats)]
     L.pma_server_info.argtypes = [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_size_t)]
     L.pma_request_bytes.argtypes = [POINTER(Request), POINTER(c_size_t)]
     L.pma_partition.argtypes = [POINTER(Grid), POINTER(DD), c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]
@@ -208,13 +211,19 @@ def make_dd(dd, dim) -> DD:
     return D
 
 
-def make_request(w: dict, precision="fp32", exec_="batched") -> Request:
+def make_request(w: dict, precision="fp32", exec_="batched", psi0=None, want_psi=False) -> Request:
+    """psi0: optional float64 array of the grid's shape (warm start); the caller keeps it alive
+    for the duration of the call that reads it."""
     R = Request()
     R.grid = make_grid(w["grid"])
     R.dd = make_dd(w.get("dd"), w["grid"]["dim"])
     R.mon = make_monitor(w["monitor"])
     R.time = make_time(w["time"], precision, exec_)
     R.arrival_s = float(w.get("arrival_s", 0.0))
+    if psi0 is not None:
+        assert psi0.dtype == np.float64 and psi0.flags.c_contiguous and psi0.shape == tuple(w["grid"]["n"])
+        R.psi0 = _dptr(psi0)
+    R.want_psi = 1 if want_psi else 0
     return R
 
 
@@ -359,13 +368,15 @@ class Context:
                                    _dptr(psi) if psi is not None else None, ctypes.byref(st)))
         return mesh, psi, st.as_dict()
 
-    def dd_mesh_batch(self, ws, precision="fp32", exec_="batched"):
-        """Many meshes advanced together; returns (list of meshes, list of stats dicts)."""
+    def dd_mesh_batch(self, ws, precision="fp32", exec_="batched", psi0s=None):
+        """Many meshes advanced together; returns (list of meshes, list of stats dicts).
+        psi0s: optional list of warm starts (None entries: Psi^0 = |xi|^2/2)."""
         count = len(ws)
         reqs = (Request * count)()
         outs = []
+        keep = [None if p is None else np.ascontiguousarray(p, dtype=np.float64) for p in (psi0s or [None] * count)]
         for i, w in enumerate(ws):
-            reqs[i] = make_request(w, precision, exec_)
+            reqs[i] = make_request(w, precision, exec_, psi0=keep[i])
             outs.append(np.empty((w["grid"]["dim"],) + tuple(w["grid"]["n"]), dtype=np.float64))
         ptrs = (POINTER(c_double) * count)(*[_dptr(o) for o in outs])
         stats = (Stats * count)()
@@ -397,8 +408,12 @@ class Context:
         return st.as_dict()
 
     # -- serving ---------------------------------------------------------------------------
-    def submit(self, w: dict, precision="fp32") -> int:
-        R = make_request(w, precision, "batched")
+    def submit(self, w: dict, precision="fp32", psi0=None, want_psi=False) -> int:
+        """psi0: optional warm start (float64 array of the grid's shape, copied by the call);
+        want_psi: keep the final Psi for poll_psi."""
+        if psi0 is not None:
+            psi0 = np.ascontiguousarray(psi0, dtype=np.float64)
+        R = make_request(w, precision, "batched", psi0=psi0, want_psi=want_psi)
         t = c_uint64()
         _check(self._L.pma_submit(self.h, ctypes.byref(R), ctypes.byref(t)))
         return t.value
@@ -411,8 +426,25 @@ class Context:
         _check(self._L.pma_poll(self.h, ticket, ctypes.byref(stt), _dptr(mesh) if mesh is not None else None,
                                 ctypes.byref(st)))
         if stt.value in (DONE, FAILED):
-            return stt.value, (mesh if stt.value == DONE else None), st.as_dict()
+            d = st.as_dict()
+            if stt.value == FAILED:
+                d["error"] = self._L.pma_last_error().decode()
+            return stt.value, (mesh if stt.value == DONE else None), d
         return stt.value, None, None
+
+    def poll_psi(self, ticket: int, shape):
+        """(state, mesh or None, psi or None, stats or None) of a request submitted with
+        want_psi; shape = (dim, *n)."""
+        stt = c_int()
+        mesh = np.empty(shape, dtype=np.float64)
+        psi = np.empty(shape[1:], dtype=np.float64)
+        st = Stats()
+        _check(self._L.pma_poll_psi(self.h, ticket, ctypes.byref(stt), _dptr(mesh), _dptr(psi), ctypes.byref(st)))
+        if stt.value == DONE:
+            return stt.value, mesh, psi, st.as_dict()
+        if stt.value == FAILED:
+            return stt.value, None, None, st.as_dict()
+        return stt.value, None, None, None
 
     def server_info(self):
         q, r, f = c_int(), c_int(), c_int()

@@ -647,6 +647,10 @@ struct Instance {
   double min_det = 0, min_cell = 0;
   double stats_host[4] = {0, 0, 0, 0};
   const double* psi0_dev = nullptr;  // warm start (global layout, device)
+  std::vector<double> psi0_host;     // served requests: the caller's Psi^0, copied at submit
+  bool want_psi = false;             // served requests: keep the final Psi for the poll
+  std::vector<double> psi_host;      // served requests: the final Psi
+  std::string err;                   // served requests: why the request failed
   double* user_psi = nullptr;        // single-subdomain mode: caller's device buffer
   bool ext_mem = false;              // block and bases in caller-provided memory (the fixed
                                      // scratch), not in the arena; bases owned, not cached
@@ -1165,6 +1169,15 @@ static size_t alloc_instance(pma_ctx* c, Instance& I, char* ext = nullptr, size_
     }
   }
   return Arena::round(I.bytes);
+}
+
+// warm start: the caller's global Psi^0 (host) into the instance's Psi buffer, from which the
+// initial state of every subdomain is taken (on the context's stream)
+static void upload_psi0(pma_ctx* c, Instance& I, const double* psi0) {
+  if (!psi0) return;
+  if (I.single_sub_mode) thr(PMA_E_INVAL, "internal: warm start of a single-subdomain solve");
+  HIPCHK(hipMemcpyAsync(I.psi_dev, psi0, I.gnodes() * 8, hipMemcpyHostToDevice, c->stream));
+  I.psi0_dev = I.psi_dev;
 }
 
 // the basis of axis length n among those the instance holds (cached or its own copy)
@@ -2110,6 +2123,11 @@ struct Server {
           break;
         }
         alloc_instance(ctx, *I);
+        if (!I->psi0_host.empty()) {
+          upload_psi0(ctx, *I, I->psi0_host.data());
+          HIPCHK(hipStreamSynchronize(ctx->stream));  // the host copy may go now
+          std::vector<double>().swap(I->psi0_host);
+        }
       } catch (Err& e) {
         // fragmented or full: wait for running requests to free memory; with none running no
         // memory will come free (the allocation has already evicted every unused basis), so
@@ -2119,6 +2137,7 @@ struct Server {
           arena_used = ctx->arena.used();
           break;
         }
+        I->err = g_err;
         I->status = e.code;
         I->t_done = now_s();
         state[I->ticket] = PMA_FAILED;
@@ -2160,6 +2179,7 @@ struct Server {
         std::lock_guard<std::mutex> g(mu);
         hipStreamSynchronize(ctx->stream);
         for (auto* I : running) {
+          I->err = g_err;
           I->status = e.code;
           I->t_done = now_s();
           state[I->ticket] = PMA_FAILED;
@@ -2246,9 +2266,13 @@ struct Server {
         if (I->status != PMA_OK) continue;
         Batch& B = *batch[I->prec];
         const int q = (int)(std::find(B.insts.begin(), B.insts.end(), I) - B.insts.begin());
-        finalize_instance(ctx, *I, B, q, false);
+        finalize_instance(ctx, *I, B, q, I->want_psi);
         I->mesh_host.resize((size_t)I->dim * I->gnodes());
         HIPCHK(hipMemcpyAsync(I->mesh_host.data(), I->mesh_dev, I->mesh_host.size() * 8, hipMemcpyDeviceToHost, st));
+        if (I->want_psi) {
+          I->psi_host.resize(I->gnodes());
+          HIPCHK(hipMemcpyAsync(I->psi_host.data(), I->psi_dev, I->psi_host.size() * 8, hipMemcpyDeviceToHost, st));
+        }
         HIPCHK(hipMemcpyAsync(I->stats_host, I->stats_dev, 32, hipMemcpyDeviceToHost, st));
       }
       HIPCHK(hipStreamSynchronize(st));
@@ -2528,9 +2552,11 @@ int pma_dd_mesh_batch(pma_ctx* c, int count, const pma_request* reqs, double* co
   int rc = PMA_OK;
   std::vector<Instance*> raw;
   try {
-    for (auto& I : insts) {
-      alloc_instance(c, *I);
-      raw.push_back(I.get());
+    for (size_t i = 0; i < insts.size(); ++i) {
+      Instance& I = *insts[i];
+      alloc_instance(c, I);
+      raw.push_back(&I);
+      upload_psi0(c, I, reqs[i].psi0);
     }
     run_to_end(c, raw, prec, reqs[0].time.exec == PMA_EXEC_PLAIN, false);
     collect(c, raw, mesh_outs, nullptr);
@@ -2718,9 +2744,10 @@ int pma_plan_create(pma_ctx* c, int count, const pma_request* reqs, pma_plan** o
   }
   std::vector<Instance*> raw;
   try {
-    for (auto& I : P->insts) {
-      alloc_instance(c, *I);
-      raw.push_back(I.get());
+    for (size_t i = 0; i < P->insts.size(); ++i) {
+      alloc_instance(c, *P->insts[i]);
+      raw.push_back(P->insts[i].get());
+      upload_psi0(c, *P->insts[i], reqs[i].psi0);
     }
     P->batch.reset(new Batch);
     P->batch->fuse = !P->plain;  // the plain method keeps one launch per kernel
@@ -2997,6 +3024,8 @@ int pma_submit(pma_ctx* c, const pma_request* req, uint64_t* ticket) {
   // bound counts every DCT basis the request uses, cached or not
   const size_t need = Arena::round(instance_bytes(*I)) + all_basis_bytes(*I);
   if (need > c->budget) return fail(PMA_E_BUDGET, "request needs %zu bytes, budget is %zu", need, c->budget);
+  if (req->psi0) I->psi0_host.assign(req->psi0, req->psi0 + I->gnodes());
+  I->want_psi = req->want_psi != 0;
   {
     std::lock_guard<std::mutex> g(c->server_mu);
     if (!c->server) {
@@ -3021,6 +3050,10 @@ int pma_submit(pma_ctx* c, const pma_request* req, uint64_t* ticket) {
 }
 
 int pma_poll(pma_ctx* c, uint64_t ticket, int* state, double* mesh_out, pma_stats* st) {
+  return pma_poll_psi(c, ticket, state, mesh_out, nullptr, st);
+}
+
+int pma_poll_psi(pma_ctx* c, uint64_t ticket, int* state, double* mesh_out, double* psi_out, pma_stats* st) {
   API_BEGIN
   if (!c || !state) return fail(PMA_E_INVAL, "NULL argument");
   Server* s = c->server;
@@ -3028,10 +3061,17 @@ int pma_poll(pma_ctx* c, uint64_t ticket, int* state, double* mesh_out, pma_stat
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->state.find(ticket);
   if (it == s->state.end()) return fail(PMA_E_NOTFOUND, "unknown ticket");
+  if (psi_out && !s->all[ticket]->want_psi) return fail(PMA_E_INVAL, "the request was submitted without want_psi");
   *state = it->second;
   if (*state == PMA_DONE || *state == PMA_FAILED) {
     Instance* I = s->all[ticket];
     if (*state == PMA_DONE && mesh_out) std::memcpy(mesh_out, I->mesh_host.data(), I->mesh_host.size() * 8);
+    if (*state == PMA_DONE && psi_out) std::memcpy(psi_out, I->psi_host.data(), I->psi_host.size() * 8);
+    if (*state == PMA_FAILED)  // the cause, readable through pma_last_error on the caller's thread
+      fail(I->status, "%s", I->err.empty() ? (I->status == PMA_E_TANGLED ? "mesh folded" : I->status == PMA_E_NONFINITE
+                                                                                          ? "non-finite update"
+                                                                                          : "request failed")
+                                           : I->err.c_str());
     if (st) {
       fill_stats(st, *I, (I->t_done - I->t_submit) * 1e3);
       st->ms_queue = (I->t_admit > 0 ? I->t_admit - I->t_submit : 0) * 1e3;

@@ -526,3 +526,67 @@ def test_nonfinite_request_is_isolated_in_serving(B):
             assert state == B.DONE
             alone, _, _ = c.dd_mesh(w, precision="split16")
             np.testing.assert_array_equal(mesh, alone)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split16"])
+def test_served_warm_start_resume(B, prec):
+    # Sec. 2 warm start through the server.  (1) A single-domain request served for 25 steps with
+    # its final Psi kept, resumed from it for 20 more: the oracle's 45 steps (its state is the
+    # whole Psi).  (2) A decomposed request warm-started from that smooth Psi: the oracle's
+    # decomposed run from the same Psi^0, and bitwise the batch call with the same warm start.
+    # (A decomposed solve's own glued Psi is not a resumable state: the subdomains' overlap
+    # values differ from the owners' and the glued field has seams that can fold the mesh, in the
+    # oracle and on the GPU alike.)
+    w = W.sine_dd(n=65, parts=(2, 2), overlap=4, steps=45)
+    single = dict(w, dd=None)
+    g = gspec(w)
+    t = w["time"]
+    ref45 = O.solve_single(g, w["monitor"], t["dt"], t["gamma"], 45)
+    s25 = O.solve_single(g, w["monitor"], t["dt"], t["gamma"], 25)
+    ref_dd = O.solve_dd(g, (2, 2), (4, 4), w["monitor"], t["dt"], t["gamma"], 20, psi0=s25.psi)
+    shape = (2, 65, 65)
+    tol_psi = 1e-11 if prec == "fp64" else 2e-6
+    with B.Context(0, budget_bytes=1 << 30) as c:
+        t1 = c.submit(dict(single, time=dict(t, steps=25)), prec, want_psi=True)
+        t0 = time.time()
+        while True:
+            state, mesh1, psi1, st1 = c.poll_psi(t1, shape)
+            if state in (B.DONE, B.FAILED):
+                break
+            assert time.time() - t0 < 60
+            time.sleep(0.002)
+        assert state == B.DONE, st1
+        assert np.max(np.abs(psi1 - s25.psi)) <= tol_psi
+        assert np.max(np.abs(mesh1 - s25.mesh)) <= TOL[prec]
+        # (1) single-domain resume
+        t2 = c.submit(dict(single, time=dict(t, steps=20)), prec, psi0=psi1)
+        s2, mesh2, st2 = serve_poll(c, t2, shape)
+        assert s2 == B.DONE, (st2.get("status"), st2.get("error"))
+        err = float(np.max(np.abs(mesh2 - ref45.mesh)))
+        print(f"served single-domain resume {prec}: mesh err vs 45 oracle steps {err:.3e}")
+        assert err <= TOL[prec]
+        # (2) decomposed request from the smooth Psi^0
+        w20 = dict(w, time=dict(t, steps=20))
+        t3 = c.submit(w20, prec, psi0=psi1)
+        # a poll asking for Psi of a request submitted without want_psi is refused, the ticket
+        # staying live
+        with pytest.raises(B.PmaError) as e:
+            c.poll_psi(t3, shape)
+        assert e.value.code == B.PMA_E_INVAL
+        s3, mesh3, st3 = serve_poll(c, t3, shape)
+        assert s3 == B.DONE, (st3.get("status"), st3.get("error"))
+        err = float(np.max(np.abs(mesh3 - ref_dd.mesh)))
+        print(f"served DD warm start {prec}: mesh err vs oracle DD from the same Psi0 {err:.3e}")
+        assert err <= TOL[prec]
+        outs, _ = c.dd_mesh_batch([w20], precision=prec, psi0s=[psi1])
+        np.testing.assert_array_equal(outs[0], mesh3)
+
+
+def serve_poll(c, ticket, shape, timeout=60.0):
+    t0 = time.time()
+    while True:
+        state, mesh, st = c.poll(ticket, shape=shape)
+        if state in (2, 3):
+            return state, mesh, st
+        assert time.time() - t0 < timeout, "serving did not finish"
+        time.sleep(0.002)
