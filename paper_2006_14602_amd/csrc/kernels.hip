@@ -1070,7 +1070,9 @@ __device__ inline void lds_dma(char* dst, const void* src, int bytes, int nwaves
                                        (__attribute__((address_space(3))) void*)(dst + ch * 1024), 16, 0, 0);
 }
 
-constexpr int kMaxLd = 576;            // widest padded axis (9 row blocks of 64)
+constexpr int kMaxLd = 576;            // widest padded axis of the regular strip kernel (36 row
+                                       // blocks); longer axes take strip_long_kernel
+constexpr int kLongMaxLd = 1056;       // widest padded axis at all (1025 nodes)
 constexpr int kColU = kMaxLd / 64;      // column loads per row and lane
 
 // Stage rows [row0, row0 + 16) x columns [0, ld) of a row-major R x C array into LDS as the data
@@ -1085,29 +1087,32 @@ __device__ inline float stage_rows16(char* lds, int ld, int ldo, const gmem<type
   static_assert(NW == 4 || NW == 8, "16 rows over 4 or 8 waves");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float amax = 0.f;
+  // rows longer than kMaxLd (long axes) in chunks of kMaxLd columns; one chunk otherwise
+  for (int cb = 0; cb < ld; cb += kMaxLd) {
 #pragma unroll
-  for (int jp = 0; jp < 8 / NW; ++jp) {
-    T v[2][kColU];
+    for (int jp = 0; jp < 8 / NW; ++jp) {
+      T v[2][kColU];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int r = wave + NW * (2 * jp + j);
-      const bool rok = row0 + r < R;
-      const gmem<T>* rp = src + (long)(rok ? row0 + r : 0) * C;
+      for (int j = 0; j < 2; ++j) {
+        const int r = wave + NW * (2 * jp + j);
+        const bool rok = row0 + r < R;
+        const gmem<T>* rp = src + (long)(rok ? row0 + r : 0) * C;
 #pragma unroll
-      for (int u = 0; u < kColU; ++u) {
-        const int k = lane + 64 * u;
-        v[j][u] = (rok && k < C) ? rp[k] : T(0);
+        for (int u = 0; u < kColU; ++u) {
+          const int k = cb + lane + 64 * u;
+          v[j][u] = (rok && k < C) ? rp[k] : T(0);
+        }
       }
-    }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int r = wave + NW * (2 * jp + j);
+      for (int j = 0; j < 2; ++j) {
+        const int r = wave + NW * (2 * jp + j);
 #pragma unroll
-      for (int u = 0; u < kColU; ++u) {
-        const int k = lane + 64 * u;
-        if (k < ld) {
-          O::put(lds, ldo, r, k, v[j][u]);
-          if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j][u]));
+        for (int u = 0; u < kColU; ++u) {
+          const int k = cb + lane + 64 * u;
+          if (k < ld) {
+            O::put(lds, ldo, r, k, v[j][u]);
+            if (O::SCALED) amax = fmaxf(amax, fabsf((float)v[j][u]));
+          }
         }
       }
     }
@@ -1624,6 +1629,138 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
       for (int q = 0; q < 4; ++q) {
         const int i = rb * 16 + O::crow(g, q);
         if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][q] * ((i == 0 || i == K - 1) ? T(2) * os : os);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Long axes (padded length above kMaxLd, up to kLongMaxLd): the same 16-column strip products as
+// strip_kernel (global-basis path, four waves), with the output rows taken in groups of 36 row
+// blocks so the accumulators stay in registers.  PAIR: the spectral coefficients of every group
+// are scaled and written to the destination array, then, once all of them are there, read back
+// (agent-scope loads, which do not hit stale first-level cache lines) into LDS as the operand of
+// the inverse product, whose groups overwrite them.  Each workgroup reads and writes only its own
+// 16 columns of the destination.  Same formulas and accumulation order per output as
+// strip_kernel's global-basis path.
+// ------------------------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline T load_agent(const gmem<T>* p) {
+  return __hip_atomic_load((T*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int KIND, bool PAIR>
+__global__ __launch_bounds__(256) void strip_long_kernel(const int4* __restrict__ tiles, int ntiles, int axis,
+                                                         int inv, int src_sel, StepArgs sa) {
+  typedef Op<KIND> O;
+  typedef typename O::T T;
+  constexpr int NW = 4, GRB = 9;            // row blocks per wave per group; a group is 36 blocks
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  const int4 tl = tiles[tix];
+  const SubDev& S = sa.subs[tl.x];
+  const int K = S.n[axis];
+  const AxisDev& A = S.ax[axis];
+  const int ld = A.ld, ldb = A.ldb, ldo = ld + O::OPAD;
+  int ncol;
+  long base;
+  if (axis == 0) {
+    ncol = S.dim == 2 ? S.n[1] : S.n[1] * S.n[2];
+    base = 0;
+  } else {
+    ncol = S.n[2];
+    base = (long)tl.y * S.n[1] * S.n[2];
+  }
+  const int col0 = tl.z;
+  const gmem<T>* __restrict__ src = gp<T>(src_sel ? S.T : S.F) + base;
+  gmem<T>* __restrict__ dst = gpw<T>(src_sel ? S.F : S.T) + base;
+  __shared__ float red[NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+  const int nrb = (K + 15) >> 4;
+  const int c = col0 + l16;
+  const int ke = kext<KIND>(K);
+  const void* b1h = (PAIR || !inv) ? A.fwd : A.inv;
+  const void* b1l = (PAIR || !inv) ? A.fwdl : A.invl;
+  const T fwd_unscale = T(A.fwd_unscale);
+  const T g0 = T(S.gh2[0]);
+  const gmem<T>* s0 = gp<T>(S.ax[0].sig);
+  RestSig<T> rs{T(0), T(0), T(0), T(0)};
+  if constexpr (PAIR) rs = rest_sig<T>(S, c, ncol);
+  const float amax = stage_strip16<KIND, 64 * NW>(lds, ld, ldo, src, K, ncol, col0);
+  const float sc = O::SCALED ? tile_scale_w<NW>(amax, red) : 1.f;
+  __syncthreads();
+  if (O::SCALED) {
+    O::presplit(lds, ldo, 16, ld, &sc, 16);
+    __syncthreads();
+  }
+  const T us1 = ((PAIR || !inv) ? fwd_unscale : T(1)) / T(sc);
+  for (int rg = 0; rg < nrb; rg += NW * GRB) {
+    typename O::acc_t acc[GRB];
+#pragma unroll
+    for (int t = 0; t < GRB; ++t) {
+      acc[t] = typename O::acc_t{0, 0, 0, 0};
+      const int rb = rg + wave + NW * t;
+      if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], b1h, b1l, ldb, lds, ke, ldo, sc, rb * 16 + l16, l16, g);
+    }
+#pragma unroll
+    for (int t = 0; t < GRB; ++t) {
+      const int rb = rg + wave + NW * t;
+      if (rb >= nrb) continue;
+      for (int q = 0; q < 4; ++q) {
+        const int i = rb * 16 + O::crow(g, q);
+        if (i >= K || c >= ncol) continue;
+        const T val = acc[t][q] * us1;
+        if constexpr (!PAIR) {
+          dst[(long)i * ncol + c] = val;
+        } else {
+          // spectral scale with D^-1 ahead of the forward matrix reused for the inverse
+          if (i == 0 && c == 0) gpw<T>(sa.dc)[tl.x] = val;
+          T y = val / (T(1) + g0 * T(s0[i]) + rs.value());
+          if (i == 0 || i == K - 1) y *= T(2);
+          dst[(long)i * ncol + c] = y;
+        }
+      }
+    }
+  }
+  if constexpr (PAIR) {
+    __threadfence();   // the coefficients are in L2 before any wave reads them back
+    __syncthreads();   // and every wave is done reading the strip
+    float ymax = 0.f;
+    {
+      const int cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+      const bool cok = col0 + cc < ncol;
+      for (int k = k0; k < ld; k += 16) {
+        const T y = (cok && k < K) ? load_agent(dst + (long)k * ncol + col0 + cc) : T(0);
+        O::put(lds, ldo, cc, k, y);
+        if (O::SCALED) ymax = fmaxf(ymax, fabsf((float)y));
+      }
+    }
+    const float sy = O::SCALED ? tile_scale_w<NW>(ymax, red) : 1.f;
+    __syncthreads();
+    if (O::SCALED) {
+      O::presplit(lds, ldo, 16, ld, &sy, 16);
+      __syncthreads();
+    }
+    // store scale: (N / 2) D^-1, the split form's 2^-s and 1 / sy
+    const T os = fwd_unscale * (T(K - 1) / T(2)) / T(sy);
+    for (int rg = 0; rg < nrb; rg += NW * GRB) {
+      typename O::acc_t acc[GRB];
+#pragma unroll
+      for (int t = 0; t < GRB; ++t) {
+        acc[t] = typename O::acc_t{0, 0, 0, 0};
+        const int rb = rg + wave + NW * t;
+        if (rb < nrb) mma_basis_by_lds<KIND>(acc[t], A.fwd, A.fwdl, ldb, lds, ke, ldo, sy, rb * 16 + l16, l16, g);
+      }
+#pragma unroll
+      for (int t = 0; t < GRB; ++t) {
+        const int rb = rg + wave + NW * t;
+        if (rb >= nrb) continue;
+        for (int q = 0; q < 4; ++q) {
+          const int i = rb * 16 + O::crow(g, q);
+          if (i < K && c < ncol) dst[(long)i * ncol + c] = acc[t][q] * ((i == 0 || i == K - 1) ? T(2) * os : os);
+        }
       }
     }
   }
@@ -2485,6 +2622,21 @@ int fused_lds_bytes(int prec, int ld, int ldb, int n, bool basis) {
 hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
                         int src_sel, const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (maxld > kLongMaxLd) return hipErrorInvalidValue;
+  if (maxld > kMaxLd) {  // long axes
+    const size_t shl = op_lds(prec, maxld);
+#define PMA_LONG(K, P) \
+  hipLaunchKernelGGL((strip_long_kernel<K, P>), dim3(ntiles), dim3(256), shl, s, tiles, ntiles, axis, inv, src_sel, sa)
+    if (prec == PREC_F64) {
+      if (pair) PMA_LONG(PREC_F64, true); else PMA_LONG(PREC_F64, false);
+    } else if (prec == PREC_F32) {
+      if (pair) PMA_LONG(PREC_F32, true); else PMA_LONG(PREC_F32, false);
+    } else {
+      if (pair) PMA_LONG(PREC_SPLIT16, true); else PMA_LONG(PREC_SPLIT16, false);
+    }
+#undef PMA_LONG
+    return hipGetLastError();
+  }
   const size_t sh = std::max<size_t>(op_lds(prec, maxld), (size_t)lneed);
   const int lcap = (int)sh;
   const bool eight = ntiles <= 512;  // latency-bound: at most two workgroups per compute unit
@@ -2544,7 +2696,10 @@ hipError_t enable_large_lds() {
                         (const void*)stencil_fwd2_kernel<PREC_F64>, (const void*)stencil_fwd2_kernel<PREC_F32>,
                         (const void*)stencil_fwd2_kernel<PREC_SPLIT16>, (const void*)strip4_kernel<PREC_F32, true>,
                         (const void*)strip4_kernel<PREC_F32, false>, (const void*)strip4_kernel<PREC_SPLIT16, true>,
-                        (const void*)strip4_kernel<PREC_SPLIT16, false>};
+                        (const void*)strip4_kernel<PREC_SPLIT16, false>, (const void*)strip_long_kernel<PREC_F64, true>,
+                        (const void*)strip_long_kernel<PREC_F64, false>, (const void*)strip_long_kernel<PREC_F32, true>,
+                        (const void*)strip_long_kernel<PREC_F32, false>, (const void*)strip_long_kernel<PREC_SPLIT16, true>,
+                        (const void*)strip_long_kernel<PREC_SPLIT16, false>};
     for (const void* k : ks) {
       // whatever the kernel's static LDS leaves of the 160 KiB (at most lim)
       hipFuncAttributes fa{};

@@ -472,9 +472,9 @@ static double theta_host(const pma_grid& g, const pma_monitor& m) {
 // node (the last node belongs to the last part)
 // ------------------------------------------------------------------------------------------
 
-// largest subdomain extent per axis: the axis-0 strip kernel keeps up to 9 row blocks of 16
-// per wave (4 waves) in registers
-static constexpr int kMaxAxisNodes = 545;
+// largest subdomain extent per axis: a 16-row tile of the widest axis (1056 padded entries) fits a
+// workgroup's LDS in FP64; axes beyond 576 padded entries take the long-axis strip kernel
+static constexpr int kMaxAxisNodes = 1025;
 
 struct AxisSplit {
   std::vector<int> cores;            // M + 1
@@ -566,7 +566,7 @@ static void partition_host(const pma_grid& g, const pma_dd* dd, std::vector<SubH
           s.n[k] = r.second - r.first + 1;
           if (r.second - r.first < 4) thr(PMA_E_INVAL, "a subdomain has fewer than 4 cells on an axis");
           if (r.second - r.first + 1 > kMaxAxisNodes)
-            thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: use more parts");
+            thr(PMA_E_INVAL, "a subdomain axis has more than 1025 nodes: use more parts");
           if (r.first > 0) s.art |= 1 << (2 * k);
           if (r.second < g.n[k] - 1) s.art |= 1 << (2 * k + 1);
         }
@@ -899,7 +899,7 @@ static size_t basis_bytes(int n, int prec) {
 // the DCT matrices of axis length n in precision prec, written to device memory mem
 // (basis_bytes(n, prec) bytes); the Basis describes where each matrix sits
 static std::unique_ptr<Basis> fill_basis(int n, int prec, char* mem) {
-  if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: split it further");
+  if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 1025 nodes: split it further");
   std::vector<double> A, B, sig;
   basis_host(n, A, B, sig);
   std::unique_ptr<Basis> b(new Basis);
@@ -977,7 +977,7 @@ static Basis* get_basis(pma_ctx* c, int n, int prec) {
     it->second->last_use = ++c->basis_clock;
     return it->second;
   }
-  if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 545 nodes: split it further");
+  if (n > kMaxAxisNodes) thr(PMA_E_INVAL, "a subdomain axis has more than 1025 nodes: split it further");
   char* mem = (char*)arena_alloc(c, basis_bytes(n, prec));
   std::unique_ptr<Basis> b;
   try {

@@ -14,9 +14,14 @@ measure by O(1) relative and fails them.
 CELL_RTOL = {"fp64": 1e-8, "fp32": 5e-3, "split16": 5e-3}
 
 
-def check_min_cell(got: float, ref: float, prec: str, label: str = "") -> float:
+def check_min_cell(got: float, ref: float, prec: str, label: str = "", mesh_err: float = 0.0,
+                   h: float = 1.0, dim: int = 2) -> float:
+    """mesh_err, h, dim: the measured max node error, the smallest spacing and the dimension; the
+    bound is then also at least 4 dim mesh_err / h (twice the first-order estimate above), which
+    matters for the finest spacings (FP32 at 1025-node axes: 5.3e-3 measured)."""
     rel = abs(got - ref) / abs(ref)
-    print(f"min cell {label} {prec}: gpu {got:.12e} oracle {ref:.12e} rel {rel:.2e}", flush=True)
+    tol = max(CELL_RTOL[prec], 4.0 * dim * mesh_err / h)
+    print(f"min cell {label} {prec}: gpu {got:.12e} oracle {ref:.12e} rel {rel:.2e} (bound {tol:.1e})", flush=True)
     assert got > 0 and ref > 0, (got, ref)
-    assert rel <= CELL_RTOL[prec], (got, ref, rel)
+    assert rel <= tol, (got, ref, rel)
     return rel

@@ -342,7 +342,7 @@ def test_invalid_requests_rejected(ctx, B):
         ctx.dd_mesh(w)
     assert e.value.code == B.PMA_E_INVAL
     w = W.ring(steps=5)
-    w["grid"] = W.grid([601, 65])
+    w["grid"] = W.grid([1100, 65])
     with pytest.raises(B.PmaError) as e:
         ctx.dd_mesh(w)
     assert e.value.code == B.PMA_E_INVAL

@@ -116,8 +116,9 @@ def test_shell_3d_dd_vs_oracle(ctx, prec):
     check_min_cell(st["min_cell"], ref.min_cell, prec, "shell25dd")
 
 
-# --- edge shapes: the longest subdomain axis the kernels take (545 nodes, a ragged 34 x 16 + 1)
-# along each axis in turn, against a short one; and the smallest subdomains (4 cells, overlap 2)
+# --- edge shapes: the longest axis of the regular strip kernel (545 nodes, a ragged 34 x 16 + 1)
+# and the longest axis at all (1025 nodes, 64 x 16 + 1, the long-axis kernels) along each axis in
+# turn, against a short one; and the smallest subdomains (4 cells, overlap 2)
 
 def smooth_ring(n, steps):
     return {"name": "ring_" + "x".join(map(str, n)), "grid": W.grid(list(n)), "dd": None,
@@ -126,7 +127,8 @@ def smooth_ring(n, steps):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
-@pytest.mark.parametrize("n", [(545, 37), (37, 545), (545, 9, 9), (9, 545, 9), (9, 9, 545)])
+@pytest.mark.parametrize("n", [(545, 37), (37, 545), (545, 9, 9), (9, 545, 9), (9, 9, 545),
+                               (1025, 37), (37, 1025), (1025, 9, 9), (9, 1025, 9), (9, 9, 1025)])
 def test_longest_axis_vs_oracle(ctx, n, prec):
     w = smooth_ring(n, 100)
     mesh, _, st = ctx.dd_mesh(w, precision=prec)
@@ -135,7 +137,8 @@ def test_longest_axis_vs_oracle(ctx, n, prec):
     print(f"{w['name']} {prec}: max mesh err {err:.3e}")
     assert err <= TOL[prec], err
     assert st["min_det"] > 0
-    check_min_cell(st["min_cell"], ref.min_cell, prec, w["name"])
+    check_min_cell(st["min_cell"], ref.min_cell, prec, w["name"], mesh_err=err * extent(w),
+                   h=min(gspec(w).h), dim=len(n))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "split16"])
