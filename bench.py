@@ -157,6 +157,45 @@ def paper_workloads(ctx, binding, workloads):
     return out
 
 
+# Sec. 4.3, tables ddpma_efficiency2D / ddpma_efficiency3D: MATLAB FP64 CPU seconds for one complete
+# mesh (single domain; 4- or 8-block DD solved in turn; the same in parallel on 4 or 8 cores), step
+# counts not stated; quoted as context only
+PAPER_SECONDS = {
+    2: {65: (0.2, 0.31, 0.53), 129: (0.38, 0.51, 0.66), 257: (0.8, 1.0, 0.76), 513: (3.53, 2.7, 1.6),
+        1025: (13.51, 10.94, 7.09)},
+    3: {65: (20.0, 18.0, 4.0), 81: (30.0, 29.0, 8.0), 101: (62.0, 58.0, 16.0), 121: (104.0, 94.0, 37.0)},
+}
+
+
+def efficiency_ladder(ctx, binding, workloads, prec="fp64", steps2=200, steps3=100):
+    """The paper's grid ladder (Sec. 4.3): the spiral (Sec. 4.1) at 65^2 .. 1025^2 and the sphere
+    (Sec. 4.2) at 65^3 .. 121^3, each on the whole domain, as 2x2 (2x2x2) blocks swept in turn
+    (Algorithm 1) and as 2x2 (2x2x2) blocks in parallel; the same number of steps at every size."""
+    out = {}
+    for dim, sizes, steps in ((2, (65, 129, 257, 513, 1025), steps2), (3, (65, 81, 101, 121), steps3)):
+        for n in sizes:
+            row = {}
+            for form, parts, mode in (("single", None, None), ("blocks_alternating", (2,) * dim, "alternating"),
+                                      ("blocks_parallel", (2,) * dim, "parallel")):
+                if dim == 2:
+                    w = workloads.spiral(n=n, parts=parts, overlap=4, mode=mode or "parallel", steps=steps)
+                else:
+                    w = workloads.sphere_3d(n=n, parts=parts, overlap=2, mode=mode or "alternating", steps=steps)
+                r = timed_plan(ctx, binding, [w], prec, "batched", steps, 3)
+                e = {"ms_per_step": r["ms_per_step"], "seconds": r["seconds"], "updates_per_s": r["updates_per_s"],
+                     "min_det": r["min_det"], "min_cell": r["min_cell"]}
+                if "error" in r:
+                    e["error"] = r["error"]
+                row[form] = e
+            row["paper_matlab_seconds_single_serialdd_paralleldd"] = PAPER_SECONDS[dim][n]
+            out[f"{'spiral' if dim == 2 else 'sphere'}_{n}{'^2' if dim == 2 else '^3'}"] = row
+            log(f"ladder {dim}D {n}: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms/step" for k, v in row.items()
+                                                   if isinstance(v, dict)))
+    return {"precision": prec, "steps_2d": steps2, "steps_3d": steps3, "rows": out,
+            "note": "GPU seconds are for the stated step counts; the paper's MATLAB seconds (ode113, CPU) state "
+                    "no step counts and are context only"}
+
+
 def roofline_of(phases, prec, workload=None):
     """Dominant kernel of a step: algorithmic work per launch / mean launch duration; traffic from
     the committed counters of `workload` when they are current."""
@@ -429,7 +468,7 @@ def main():
     ap.add_argument("--serve-plain", type=int, default=40, help="requests of the stream served by the plain method")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["fp64", "split16", "fp32", "fp64plain", "sine", "stencil_large", "paper",
-                                       "shell", "serve"], default=None,
+                                       "shell", "serve", "ladder"], default=None,
                     help="one form of the headline workload, or one other workload, only (profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 10 times (calibrates HBM byte counters)")
@@ -450,10 +489,12 @@ def main():
     import torch
     from paper_2006_14602_amd import binding, workloads
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.only in ("paper", "shell", "stencil_large", "sine"):
+    if args.only in ("paper", "shell", "stencil_large", "sine", "ladder"):
         ctx = binding.Context(0, budget_bytes=12 << 30)
         if args.only == "paper":
             r = {"paper_workloads": paper_workloads(ctx, binding, workloads)}
+        elif args.only == "ladder":
+            r = {"efficiency_ladder": efficiency_ladder(ctx, binding, workloads)}
         elif args.only == "shell":
             r = {"shell_dd_129_split16": shell_bench(ctx, binding, workloads, args.steps, args.warmup)}
         elif args.only == "sine":
@@ -530,6 +571,7 @@ def main():
             extra["sine_dd_513"]["cpu_baseline"] = cpu_baseline_sine(workloads.sine_dd(), 300)
         out["other_workloads"] = extra
         out["paper_workloads"] = paper_workloads(ctx, binding, workloads)
+        out["efficiency_ladder"] = efficiency_ladder(ctx, binding, workloads)
     ctx.close()
     if args.serve > 0 and not args.quick and not args.only:
         sv = {"budget_8GiB": serve_stream(binding, workloads, args.serve, 8 << 30)}
