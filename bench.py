@@ -25,6 +25,11 @@ import sys
 import threading
 import time
 
+if __name__ == "__mp_main__":  # the oracle's worker processes: one thread each
+    for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[_v] = "1"
+import numpy as np  # noqa: E402
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -194,6 +199,167 @@ def efficiency_ladder(ctx, binding, workloads, prec="fp64", steps2=200, steps3=1
     return {"precision": prec, "steps_2d": steps2, "steps_3d": steps3, "rows": out,
             "note": "GPU seconds are for the stated step counts; the paper's MATLAB seconds (ode113, CPU) state "
                     "no step counts and are context only"}
+
+
+# ---- the convergence studies of Sec. 4.4 and the quality table of Sec. 4.5, on the GPU ----------
+
+def _trap_weights(shape, h):
+    w = np.ones(shape)
+    for k, n in enumerate(shape):
+        wk = np.ones(n)
+        wk[0] = wk[-1] = 0.5
+        sh = [1] * len(shape)
+        sh[k] = -1
+        w = w * wk.reshape(sh)
+    return w * float(np.prod(h))
+
+
+def rel_errs(ref, approx, h):
+    """Sec. 4.4 eqs. rel_errlp / rel_errlinf (integrals by the trapezoid rule) of one field."""
+    w = _trap_weights(ref.shape, h)
+    d = np.abs(ref - approx)
+    out = {p: float((np.sum(w * d ** p) ** (1.0 / p)) / (np.sum(w * np.abs(ref) ** p) ** (1.0 / p))) for p in (1, 2)}
+    out["inf"] = float(d.max() / np.abs(ref).max())
+    return out
+
+
+def mesh_rel_errs(ref, approx, h):
+    """The relative errors of a mesh: the larger over its coordinate fields."""
+    es = [rel_errs(ref[k], approx[k], h) for k in range(ref.shape[0])]
+    return {p: max(e[p] for e in es) for p in (1, 2, "inf")}
+
+
+def _slope(hs, es):
+    return float(np.polyfit(np.log(hs), np.log(es), 1)[0])
+
+
+def smooth_monitor():
+    """A smooth ring (amplitude 5, sharpness 10 about |x - c| = 1/4): resolved at 21^2 already, so
+    the steady states the studies compare are in the asymptotic range."""
+    return {"kind": "sech2_radial", "amp": 5.0, "k": 10.0, "r0": 0.25, "c": [0.5, 0.5]}
+
+
+def steady_single(ctx, workloads, n, mon, prec="fp64", dt=0.05, steps=1500):
+    """Whole-domain steady state (gamma = 1): the mesh, and c, the value F settles to (the uniform
+    drift of Psi per unit pseudo time, measured over 100 more steps)."""
+    w = {"name": f"single_{n}", "grid": workloads.grid([n, n]), "dd": None, "monitor": dict(mon),
+         "time": {"dt": dt, "gamma": 1.0, "steps": steps}}
+    m, p1, _ = ctx.dd_mesh(w, precision=prec, want_psi=True)
+    _, p2, _ = ctx.dd_mesh(dict(w, time=dict(w["time"], steps=100)), precision=prec, psi0=p1, want_psi=True)
+    drift = (p2 - p1) / (100 * dt)
+    return m, float(np.mean(drift)), float(drift.max() - drift.min())
+
+
+def dd_history(ctx, binding, workloads, n, mon, theta, parts=(2, 2), ov=4, dt_frac=0.2, marks=(1000,), prec="fp64"):
+    """A decomposed solve (gamma = 4 h^2, dt = dt_frac gamma) stepped resident on the device; the
+    glued mesh at each step count in marks."""
+    g = workloads.grid([n, n])
+    t = workloads.dd_defaults(g)
+    t["dt"] = dt_frac * t["gamma"]
+    t["steps"] = max(marks)
+    w = {"name": f"dd_{n}", "grid": g, "dd": {"parts": list(parts), "overlap": [ov, ov]},
+         "monitor": dict(mon, theta=theta), "time": t}
+    out = []
+    with binding.Plan(ctx, [w], prec, "batched") as p:
+        done = 0
+        for k in marks:
+            p.step(k - done)
+            p.sync()
+            done = k
+            out.append(p.mesh(0)[0])
+    return out, t
+
+
+def studies(ctx, binding, workloads):
+    """E4 (space convergence of the DD solution to the fine single-domain one), E6 (history), E7
+    (overlap), E8 (the DD steady state against the pseudo-time step) of Sec. 4.4 and the quality
+    table of Sec. 4.5, as steady-state comparisons on the smooth ring monitor (the paper's spiral
+    has no reachable steady state under the explicit preconditioned step), FP64."""
+    mon0 = smooth_monitor()
+    res = {"monitor": mon0}
+    # whole-domain steady states and their F value c; theta e^c makes the steady state F = 0, the
+    # fixed point the decomposed iteration then reaches exactly (no drift)
+    ns = (33, 65, 129, 257)
+    sd, theta0 = {}, {}
+    th = binding.theta(workloads.grid([33, 33]), mon0)
+    for n in ns + (1025,):
+        m, c, spread = steady_single(ctx, workloads, n, mon0, steps=1500 if n < 1025 else 1200)
+        sd[n] = m
+        theta0[n] = th * math.exp(c)
+        log(f"steady single {n}: c {c:.4e} (spread {spread:.1e})")
+    # E4: decomposed (2x2, overlap 4 cells) steady meshes at N against the 1025^2 whole-domain mesh
+    e4 = {}
+    for n in ns:
+        tau = 3.0
+        steps = int(math.ceil(tau / (0.2 * 4.0 / (n - 1) ** 2)))
+        (m,), _ = dd_history(ctx, binding, workloads, n, mon0, theta0[n], marks=(steps,))
+        s = 1024 // (n - 1)
+        ref = sd[1025][:, ::s, ::s]
+        h = (1.0 / (n - 1),) * 2
+        e4[n] = {"steps": steps, "dd_vs_single_same_n": float(np.abs(m - sd[n]).max()),
+                 "rel_vs_1025": mesh_rel_errs(ref, m, h)}
+        log(f"E4 n {n}: {e4[n]}")
+    hs = [1.0 / (n - 1) for n in ns]
+    res["E4_space"] = {"rows": {str(n): v for n, v in e4.items()},
+                       "slopes": {str(p): _slope(hs, [e4[n]["rel_vs_1025"][p] for n in ns]) for p in (1, 2, "inf")},
+                       "paper_slopes": {"1": 2.01, "2": 1.99, "inf": 1.85}}
+    # E6 / E7: history of the DD mesh against the whole-domain steady mesh at 129^2, overlaps of
+    # 5, 9, 11 and 15 points (4, 8, 10, 14 cells)
+    n = 129
+    marks = (1000, 2000, 4000, 8000, 16000, 32000, 64000)
+    hist = {}
+    for ov in (4, 8, 10, 14):
+        ms, _ = dd_history(ctx, binding, workloads, n, mon0, theta0[n], ov=ov, marks=marks)
+        hist[f"{ov + 1}_points"] = [mesh_rel_errs(sd[n], m, (1.0 / (n - 1),) * 2)["inf"] for m in ms]
+        log(f"E6/E7 overlap {ov}: {hist[f'{ov + 1}_points']}")
+    res["E6_E7_history"] = {"n": n, "steps": list(marks), "linf_rel_by_overlap": hist}
+    # E8: with the exact theta the decomposed iteration settles into a uniform drift; its mesh
+    # against the whole-domain steady mesh (65^2, tau = 2) for pseudo-time steps 1, 2, 4, 8 e-5 at
+    # gamma = 4 h^2, and for gamma = h^2, 2 h^2, 4 h^2 at dt = gamma / 5
+    n = 65
+    h2 = 1.0 / (n - 1) ** 2
+    e8, e8g = {}, {}
+    for mult in (1, 2, 4, 8):
+        dt = mult * 1e-5
+        steps = int(math.ceil(2.0 / dt))
+        (m,), _ = dd_history(ctx, binding, workloads, n, mon0, th, dt_frac=dt / (4.0 * h2), marks=(steps,))
+        e8[f"{mult}e-5"] = {"steps": steps, "rel_vs_single": mesh_rel_errs(sd[n], m, (1.0 / (n - 1),) * 2)}
+        log(f"E8 dt {dt}: {e8[f'{mult}e-5']}")
+    for cg in (1.0, 2.0, 4.0):
+        g = workloads.grid([n, n])
+        t = {"gamma": cg * h2, "dt": 0.2 * cg * h2}
+        t["steps"] = int(math.ceil(2.0 / t["dt"]))
+        w = {"grid": g, "dd": {"parts": [2, 2], "overlap": [4, 4]}, "monitor": dict(mon0, theta=th), "time": t}
+        m, _, _ = ctx.dd_mesh(w, precision="fp64")
+        e8g[f"{cg:g}h^2"] = {"steps": t["steps"], "rel_vs_single": mesh_rel_errs(sd[n], m, (1.0 / (n - 1),) * 2)}
+        log(f"E8 gamma {cg} h^2: {e8g[f'{cg:g}h^2']}")
+    res["E8_dt"] = {"n": n, "tau": 2.0, "by_dt_gamma_4h2": e8, "by_gamma_dt_gamma_over_5": e8g}
+    # quality table (Sec. 4.5): 21^2 and 41^2; 4 slabs, 2x2 blocks, whole domain
+    qt = {}
+    for n in (21, 41):
+        m, c, _ = steady_single(ctx, workloads, n, mon0, steps=1500)
+        thn = th * math.exp(c)
+        row = {}
+        for form, parts in (("slabs4", (4, 1)), ("blocks2x2", (2, 2)), ("whole", None)):
+            g = workloads.grid([n, n])
+            if parts:
+                t = workloads.dd_defaults(g)
+                t["steps"] = int(math.ceil(3.0 / t["dt"]))
+                w = {"grid": g, "dd": {"parts": list(parts), "overlap": [2, 2]}, "monitor": dict(mon0, theta=thn),
+                     "time": t}
+            else:
+                w = {"grid": g, "dd": None, "monitor": dict(mon0, theta=thn),
+                     "time": {"dt": 0.05, "gamma": 1.0, "steps": 1500}}
+            _, _, st = ctx.dd_mesh(w, precision="fp64")
+            # E is reported with theta = int rho (the run used theta e^c): E scales by e^c
+            row[form] = {"E2": st["quality_e2"] * math.exp(c), "Emax": st["quality_emax"] * math.exp(c)}
+        qt[f"{n}^2"] = row
+        log(f"quality {n}: {row}")
+    res["quality_table"] = {"rows": qt, "paper": {"21^2": {"slabs4": (1.0198, 1.1546), "blocks2x2": (1.0194, 1.1590),
+                                                          "whole": (1.0194, 1.1609)},
+                                                 "41^2": {"slabs4": (1.0053, 1.0997), "blocks2x2": (1.0052, 1.0994),
+                                                          "whole": (1.0042, 1.0980)}}}
+    return res
 
 
 def roofline_of(phases, prec, workload=None):
@@ -468,7 +634,7 @@ def main():
     ap.add_argument("--serve-plain", type=int, default=40, help="requests of the stream served by the plain method")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["fp64", "split16", "fp32", "fp64plain", "sine", "stencil_large", "paper",
-                                       "shell", "serve", "ladder"], default=None,
+                                       "shell", "serve", "ladder", "studies"], default=None,
                     help="one form of the headline workload, or one other workload, only (profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized float32 buffer 10 times (calibrates HBM byte counters)")
@@ -489,9 +655,11 @@ def main():
     import torch
     from paper_2006_14602_amd import binding, workloads
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.only in ("paper", "shell", "stencil_large", "sine", "ladder"):
+    if args.only in ("paper", "shell", "stencil_large", "sine", "ladder", "studies"):
         ctx = binding.Context(0, budget_bytes=12 << 30)
-        if args.only == "paper":
+        if args.only == "studies":
+            r = {"studies": studies(ctx, binding, workloads)}
+        elif args.only == "paper":
             r = {"paper_workloads": paper_workloads(ctx, binding, workloads)}
         elif args.only == "ladder":
             r = {"efficiency_ladder": efficiency_ladder(ctx, binding, workloads)}

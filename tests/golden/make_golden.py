@@ -10,6 +10,7 @@ subsample of the glued mesh plus a seeded random sample of nodes (numpy .npz, no
   spiral_257.npz           spiral arc-length monitor, 257 x 257, 4 x 4, 300 steps
   sphere_81.npz            one-sphere arc-length monitor, 81^3 on (-1,1)^3, 8 blocks, alternating
   spheres9_81.npz          nine-sphere arc-length monitor, 81^3 on (-2,2)^3, 8 blocks, alternating
+  quality_table_ring.npz   the quality table of Sec. 4.5 on a smooth ring monitor (E_2, E_max)
 The arc-length workloads also store the theta the oracle used (tensor Gauss-Legendre where no
 reduction applies), which the tests hand to the library so both solve the same problem.
 Run from the repository root:  python tests/golden/make_golden.py [name ...]
@@ -57,7 +58,43 @@ def sample_index(n, stride, count, seed):
     return np.concatenate([strided, rand], 0)
 
 
+# the quality table of Sec. 4.5 (21^2 and 41^2; 4 slabs, 2 x 2 blocks, whole domain) at the
+# steady state, on the smooth ring monitor (amplitude 5, sharpness 10); theta is scaled by e^c,
+# c the value F settles to on the whole domain, so that the decomposed iteration reaches the
+# whole-domain steady state (no drift); E is computed with that theta
+QUALITY_MON = {"kind": "sech2_radial", "amp": 5.0, "k": 10.0, "r0": 0.25, "c": [0.5, 0.5]}
+
+
+def make_quality_table():
+    t0 = time.time()
+    ns, forms = (21, 41), (("slabs4", (4, 1)), ("blocks2x2", (2, 2)), ("whole", None))
+    e2 = np.zeros((2, 3))
+    emax = np.zeros((2, 3))
+    c = np.zeros(2)
+    th0 = np.zeros(2)
+    for a, n in enumerate(ns):
+        gs = O.GridSpec((n, n), (0.0, 0.0), (1.0, 1.0))
+        th = O.theta(QUALITY_MON, gs.lo, gs.hi)
+        sd = O.solve_single(gs, QUALITY_MON, 0.05, 1.0, 1500)
+        c[a] = float(np.mean(O.rhs_F(sd.psi, gs.whole_box(), QUALITY_MON, th, gs.vol)))
+        th0[a] = th * np.exp(c[a])
+        gam = 4.0 / (n - 1) ** 2
+        for b, (name, parts) in enumerate(forms):
+            if parts:
+                dt = 0.2 * gam
+                r = O.solve_dd(gs, parts, (2, 2), QUALITY_MON, dt, gam, int(np.ceil(3.0 / dt)), theta_val=th0[a])
+            else:
+                r = O.solve_single(gs, QUALITY_MON, 0.05, 1.0, 1500, theta_val=th0[a])
+            q = O.quality_of_mesh(r.mesh, gs, QUALITY_MON, theta_val=th0[a])
+            e2[a, b], emax[a, b] = q["E2"], q["Emax"]
+    np.savez_compressed(os.path.join(HERE, "quality_table_ring.npz"), n=np.array(ns, dtype=np.int32), e2=e2,
+                        emax=emax, c=c, theta0=th0)
+    print(f"quality_table_ring: {time.time() - t0:.1f} s\n E2 {e2}\n Emax {emax}")
+
+
 def make(name):
+    if name == "quality_table_ring":
+        return make_quality_table()
     fn, stride = CASES[name]
     w = fn()
     g = w["grid"]
@@ -82,5 +119,5 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CASES)):
+    for n in (sys.argv[1:] or list(CASES) + ["quality_table_ring"]):
         make(n)
