@@ -68,6 +68,35 @@ KERNEL = {"transmit": "transmit_kernel", "stencil": "stencil_fwd2_kernel / stenc
           "inv_mid": "strip_kernel<single>", "inv_last": "inv_last_kernel"}
 
 
+# the launch-configuration tuner's cache (pma_plan_tune): choices keyed by device, precision and
+# shape bucket, reused by later runs on the same machine
+TUNE_CACHE = os.path.join(os.environ.get("TMPDIR", "/tmp"), "pma_tune_cache.txt")
+
+
+def persistent_vs_phases(ctx, binding, w, prec, steps=200):
+    """The same workload stepped with one persistent launch per step and with phase launches."""
+    import torch
+    out = {}
+    for pers in (False, True):
+        p = binding.Plan(ctx, [w], prec, "batched")
+        try:
+            p.autotune(5)
+            if pers:
+                p.set_persistent(True)
+            p.step(10)
+            p.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p.step(steps)
+            p.sync()
+            torch.cuda.synchronize()
+            out["persistent" if pers else "phase_launches"] = 1e3 * (time.perf_counter() - t0) / steps
+        finally:
+            p.close()
+    out["unit"] = "ms per step"
+    return out
+
+
 def log(*a):
     print("#", *a, file=sys.stderr, flush=True)
 
@@ -82,9 +111,11 @@ def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0, tune=
     import torch
     plan = binding.Plan(ctx, ws, prec, exec_)
     march = None
+    tuning = None
     try:
         if tune:
-            march, _ = plan.autotune(10)
+            tuning = plan.tune(5, TUNE_CACHE)
+            march = tuning["march"]
         plan.step(warmup)
         plan.sync()
         torch.cuda.synchronize()
@@ -104,7 +135,7 @@ def timed_plan(ctx, binding, ws, prec, exec_, steps, warmup, phase_reps=0, tune=
     out = {"updates_per_s": nodes_of(ws) * steps / dt, "ms_per_step": 1e3 * dt / steps, "seconds": dt,
            "steps": steps, "min_det": st["min_det"], "min_cell": st["min_cell"],
            "quality_e2": st["quality_e2"], "quality_emax": st["quality_emax"], "stencil_march": march,
-           "phases": phases}
+           "tuning": tuning, "phases": phases}
     if "error" in st:
         out["error"] = st["error"]
     return out
@@ -619,7 +650,8 @@ def sine_forms(ctx, binding, workloads, steps, warmup):
                                     for k, f in forms.items()},
            "roofline_split16": roofline_of(forms["split16"]["phases"], "split16", "sine_dd_513_split16"),
            "batched_split16_over_plain_fp64": forms["split16"]["updates_per_s"] / forms["fp64plain"]["updates_per_s"],
-           "glued_vs_single_domain": glued_vs_single(ctx, binding, w, "split16")}
+           "glued_vs_single_domain": glued_vs_single(ctx, binding, w, "split16"),
+           "persistent_step_split16": persistent_vs_phases(ctx, binding, w, "split16")}
     return out
 
 

@@ -287,6 +287,31 @@ int pma_plan_phase_times(pma_plan* plan, int nsteps, double* ms, double* flops, 
  * reps <= 0. */
 int pma_plan_autotune(pma_plan* plan, int reps, int* march, double* ms, int cap, int* ncand);
 
+/* Result of pma_plan_tune. */
+typedef struct {
+  int march;        /* stencil chunks per workgroup (pma_plan_autotune) */
+  int persistent;   /* 1: one persistent launch per step (pma_plan_set_persistent) */
+  int eight_max;    /* launches of at most this many tiles take eight-wave workgroups (else four) */
+  int lbasis_max;   /* launches of at most this many tiles copy the DCT matrices into LDS where
+                       they fit (else read them from L2) */
+  double step_ms;   /* mean device milliseconds per step of the choice (as timed when cached) */
+  int from_cache;   /* 1: taken from the cache file without timing */
+  int candidates;   /* step configurations timed */
+} pma_tuning;
+
+/* Autotuner of the plan's launch configuration: the stencil's march length (pma_plan_autotune),
+ * then whole steps timed for every combination of the step form (phase launches, or one
+ * persistent launch where the plan allows it), the eight-wave threshold (0, 512, all) and the
+ * LDS-basis threshold (0, 512, all), reps steps each between two HIP events, on a copy of the
+ * plan's state that is restored afterwards; the fastest is kept.  Results of the plan do not
+ * depend on the choice (bitwise).  cache_path (may be NULL): a text file of earlier choices keyed
+ * by the device architecture, the precision and coarse buckets of the plan's shape (subdomain
+ * count and node count rounded up to powers of two, widest padded axis, dimensions, forward
+ * Euler, sweep levels); a matching entry is applied without timing, a new choice is appended.
+ * Errors: PMA_E_INVAL for a NULL plan or out, reps <= 0, or a cache file that cannot be written;
+ * PMA_E_NOMEM if the state copy does not fit the arena. */
+int pma_plan_tune(pma_plan* plan, int reps, const char* cache_path, pma_tuning* out);
+
 /* Fix the stencil's march length (see pma_plan_autotune) for every later step of the plan;
  * values beyond a subdomain's extent cover that subdomain's whole axis 0 in one workgroup.
  * Results do not depend on it (bitwise).  Errors: PMA_E_INVAL for a NULL plan or march outside
@@ -309,6 +334,18 @@ int pma_plan_set_fusion(pma_plan* plan, int on);
  * accumulation order); the switch exists to time and test both.  Only before the first step:
  * PMA_E_INVAL afterwards. */
 int pma_plan_set_wide_strips(pma_plan* plan, int on);
+
+/* Advance each step of the plan in one persistent launch (on != 0) instead of one launch per
+ * phase (form (2) of the method's batched execution): the fused stencil + forward last-axis
+ * product, the axis-0 pair and the inverse last-axis product with the update and the pushed
+ * transmission (Sec. 3: one exchange per step) run in one kernel whose workgroups loop over the
+ * tiles of each phase, with grid-wide barriers between phases.  The grid is sized to the
+ * workgroups the device holds at once; each barrier wait is bounded, and a timeout fails the
+ * requests with PMA_E_HIP instead of hanging.  Results are bitwise those of the phase launches.
+ * Available for plans whose subdomains are all 2D, preconditioned (gamma > 0) and fused (last
+ * axis at most 320 padded), coupled in parallel, with regular axis-0 strips: PMA_E_INVAL
+ * otherwise, with the reason in pma_last_error().  May be switched at any time. */
+int pma_plan_set_persistent(pma_plan* plan, int on);
 
 /* Glue request i's mesh (dim * prod(n) doubles) into host memory; st may be NULL. */
 int pma_plan_mesh(pma_plan* plan, int i, double* mesh_out, pma_stats* st);

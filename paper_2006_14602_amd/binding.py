@@ -63,6 +63,14 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("march", c_int), ("persistent", c_int), ("eight_max", c_int), ("lbasis_max", c_int),
+                ("step_ms", c_double), ("from_cache", c_int), ("candidates", c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Request(ctypes.Structure):
     _fields_ = [("grid", Grid), ("dd", DD), ("mon", Monitor), ("time", Time), ("arrival_s", c_double),
                 ("psi0", POINTER(c_double)), ("want_psi", c_int)]
@@ -120,6 +128,8 @@ def load():
     L.pma_plan_set_march.argtypes = [c_void_p, c_int]
     L.pma_plan_set_fusion.argtypes = [c_void_p, c_int]
     L.pma_plan_set_wide_strips.argtypes = [c_void_p, c_int]
+    L.pma_plan_set_persistent.argtypes = [c_void_p, c_int]
+    L.pma_plan_tune.argtypes = [c_void_p, c_int, ctypes.c_char_p, POINTER(Tuning)]
     L.pma_plan_mesh.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(Stats)]
     L.pma_plan_destroy.argtypes = [c_void_p]
     for f in declared_symbols():
@@ -501,6 +511,17 @@ class Plan:
 
     def set_wide_strips(self, on: bool):
         _check(self._L.pma_plan_set_wide_strips(self.h, 1 if on else 0))
+
+    def tune(self, reps: int = 10, cache_path=None):
+        """Launch configuration picked by timing whole steps (pma_plan_tune); cache_path: the
+        tuning cache file (None: no cache)."""
+        t = Tuning()
+        _check(self._L.pma_plan_tune(self.h, int(reps), None if cache_path is None else str(cache_path).encode(),
+                                     ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_persistent(self, on: bool):
+        _check(self._L.pma_plan_set_persistent(self.h, 1 if on else 0))
 
     def mesh(self, i: int = 0):
         w = self.ws[i]

@@ -1281,9 +1281,9 @@ __device__ inline void node_weight(const BoxReg& B, int i0, int i1, int i2, doub
 // and wave w adds its partner's half through LDS before the update.
 // (four waves: at least seven workgroups per compute unit, which the register budget allows, for
 // the launches of many tiles that take this form)
+// one tile (entry tix of the launch table) of the inverse last-axis product and update
 template <int KIND, int NW>
-__global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles, int part_base,
-                                                                           StepArgs sa) {
+__device__ inline void inv_last_tile(int tix, const int4* __restrict__ tiles, int part_base, const StepArgs& sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   typedef typename O::acc_t acc_t;
@@ -1294,8 +1294,6 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(cons
   __shared__ float redf[NW];
   __shared__ T stash[16][64];
   __shared__ acc_t xch[KS > 1 ? 4 : 1][64];
-  const int tix = xcd_tile();
-  if (tix >= ntiles) return;
   const int4 tl = tiles[tix];
   const SubDev& S = sa.subs[tl.x];
   const InstDev& I = sa.insts[S.inst];
@@ -1410,6 +1408,14 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(cons
   }
 }
 
+template <int KIND, int NW>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 7 : 1) void inv_last_kernel(const int4* __restrict__ tiles, int ntiles,
+                                                                           int part_base, StepArgs sa) {
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  inv_last_tile<KIND, NW>(tix, tiles, part_base, sa);
+}
+
 // Spectral factors of axes 1 and 2 for column c of the [n0][rest] view of a pair product: the
 // axis-1 factor, the axis-2 factor (3D) and their weights gamma_1 h_1^-2, gamma_2 h_2^-2.  Loaded
 // without a branch (c clamped into range; a 2D view reads axis 1 twice and weights the second by 0)
@@ -1453,16 +1459,15 @@ __device__ inline RestSig<T> rest_sig(const SubDev& S, int c, int ncol) {
 // and N / 2 fold exactly into the spectral scale and the store.  The LDS path needs only A in LDS;
 // the global path doing the same keeps the two bitwise equal, so a request's result does not
 // depend on which path its launch takes.
+// one 16-column strip (entry tix of the launch table)
 template <int KIND, bool PAIR, int NW>
-__global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
-                                                        int src_sel, int lcap, StepArgs sa) {
+__device__ inline void strip_tile(int tix, const int4* __restrict__ tiles, int axis, int inv, int src_sel, int lcap,
+                                  const StepArgs& sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
   constexpr int MAXRB = (36 + NW - 1) / NW;       // row blocks per wave: n <= 36 * 16 = 576
   constexpr int RBL = (4 * kLdsRb + NW - 1) / NW;  // the same with the basis in LDS (n <= 192)
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  const int tix = xcd_tile();
-  if (tix >= ntiles) return;
   const int4 tl = tiles[tix];
   const SubDev& S = sa.subs[tl.x];
   const int K = S.n[axis];
@@ -1632,6 +1637,14 @@ __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__
       }
     }
   }
+}
+
+template <int KIND, bool PAIR, int NW>
+__global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
+                                                        int src_sel, int lcap, StepArgs sa) {
+  const int tix = xcd_tile();
+  if (tix >= ntiles) return;
+  strip_tile<KIND, PAIR, NW>(tix, tiles, axis, inv, src_sel, lcap, sa);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2224,12 +2237,20 @@ __device__ inline void stencil_fwd2_tile(const int4 tl, const StencilCtx<typenam
 
 // tile = (sub, row0, 0, 0)
 template <int KIND>
+__device__ inline void stencil_fwd2_dispatch(const int4 tl, int lcap, const StepArgs& sa);
+
+template <int KIND>
 __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int4* __restrict__ tiles, int ntiles,
                                                                        int lcap, StepArgs sa) {
-  typedef typename Op<KIND>::T T;
   const int tix = xcd_tile();
   if (tix >= ntiles) return;
-  const int4 tl = tiles[tix];
+  stencil_fwd2_dispatch<KIND>(tiles[tix], lcap, sa);
+}
+
+// one fused tile: the monitor kind chosen once, the node loop specialised for it
+template <int KIND>
+__device__ inline void stencil_fwd2_dispatch(const int4 tl, int lcap, const StepArgs& sa) {
+  typedef typename Op<KIND>::T T;
   StencilCtx<T> K;
   const T* phi_;
   T* F_;
@@ -2243,6 +2264,92 @@ __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int
     case MON_ARC_SPIRAL: stencil_fwd2_tile<KIND, MON_ARC_SPIRAL>(tl, K, mp, phi_, lcap, sa); break;
     case MON_ARC_SPHERES: stencil_fwd2_tile<KIND, MON_ARC_SPHERES>(tl, K, mp, phi_, lcap, sa); break;
     default: stencil_fwd2_tile<KIND, MON_SEPARABLE>(tl, K, mp, phi_, lcap, sa); break;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// One persistent launch per step (2D, preconditioned, parallel coupling).  The three phases of a
+// step -- fused stencil + forward last-axis product, axis-0 pair, inverse last-axis product with
+// the update and the push transmission -- run in one kernel, separated by grid-wide barriers;
+// each workgroup loops over the tiles of a phase (XCD-aware: the workgroups of XCD x take one
+// contiguous run of every table).  The tile bodies are the per-launch kernels' own, so results
+// are bitwise those of the phase launches.  The host launches at most as many workgroups as the
+// device holds at once (occupancy query), and every barrier wait is bounded: on timeout it sets
+// ST_SYNC in every instance's status and goes on, so the kernel always ends.
+// ------------------------------------------------------------------------------------------
+
+// tiles [first, first + count) of a table of n for this workgroup, stride: the XCD's workgroups
+__device__ inline void persist_range(int n, int& first, int& count, int& stride) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int q = n >> 3, r = n & 7, x = b & 7, j = b >> 3;
+  const int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  const int cnt = q + (x < r ? 1 : 0);
+  first = start + j;
+  count = cnt - j;
+  stride = G >> 3;
+}
+
+// barrier words, each on its own 128-byte line: [0] arrivals of the groups, [32] generation,
+// [64 + 32 j] arrivals within group j (workgroups b with b % 8 == j)
+constexpr int kBarGen = 32, kBarGroup = 64, kBarWords = 64 + 8 * 32;
+
+__device__ inline void grid_barrier(const PersistArgs& pa, const StepArgs& sa) {
+  // each wave's stores of the phase have reached L2 (gfx9: stores count in vmcnt), then one
+  // thread per workgroup publishes them at agent scope (release: L2 write-back), arrives in its
+  // group (the last of a group arrives for it at the top), waits with plain agent-scope polls,
+  // and takes the others' writes (acquire: L1/L2 invalidation)
+  vmem_drain();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned* top = pa.bar;
+    unsigned* gen = pa.bar + kBarGen;
+    const int grp = blockIdx.x & 7;
+    unsigned* mine = pa.bar + kBarGroup + 32 * grp;
+    const unsigned in_grp = (gridDim.x >> 3);  // the grid is a multiple of 8
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool last = false;
+    if (__hip_atomic_fetch_add(mine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1) {
+      __hip_atomic_store(mine, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 7u;
+    }
+    if (last) {
+      __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned it = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++it > pa.spin) {
+          for (int q = 0; q < pa.ninst; ++q) atomicOr(&sa.status[q], ST_SYNC);
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64 * kFuseWaves) void step2_persist_kernel(PersistArgs pa, StepArgs sa) {
+  static_assert(kFuseWaves == 8, "the persistent step runs the eight-wave tile bodies");
+  int first, count, stride;
+  persist_range(pa.n_fused, first, count, stride);
+  for (int t = first, k = 0; k < count; t += stride, k += stride) {
+    stencil_fwd2_dispatch<KIND>(pa.t_fused[t], pa.lcap, sa);
+    __syncthreads();
+  }
+  grid_barrier(pa, sa);
+  persist_range(pa.n_pair, first, count, stride);
+  for (int t = first, k = 0; k < count; t += stride, k += stride) {
+    strip_tile<KIND, true, 8>(t, pa.t_pair, 0, 0, pa.pair_src, pa.lcap, sa);
+    __syncthreads();
+  }
+  grid_barrier(pa, sa);
+  persist_range(pa.n_inv, first, count, stride);
+  for (int t = first, k = 0; k < count; t += stride, k += stride) {
+    inv_last_tile<KIND, 8>(t, pa.t_inv, pa.part_base, sa);
+    __syncthreads();
   }
 }
 
@@ -2573,11 +2680,11 @@ hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, c
   return hipGetLastError();
 }
 
-hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
-                           hipStream_t s) {
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, int eight_max,
+                           const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   const size_t sh = op_lds(prec, maxld);
-  const bool eight = ntiles <= 512;  // latency-bound: at most two workgroups per compute unit
+  const bool eight = ntiles <= eight_max;  // latency-bound: at most two workgroups per compute unit
 #define PMA_INV(K)                                                                                                    \
   do {                                                                                                                \
     if (eight)                                                                                                        \
@@ -2620,7 +2727,7 @@ int fused_lds_bytes(int prec, int ld, int ldb, int n, bool basis) {
 // lneed: the largest LDS footprint (strip + basis copy) among the launch's subdomains whose copy
 // fits in a workgroup's LDS (0: none); such tiles take the LDS-basis path
 hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
-                        int src_sel, const StepArgs& sa, hipStream_t s) {
+                        int src_sel, int eight_max, const StepArgs& sa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (maxld > kLongMaxLd) return hipErrorInvalidValue;
   if (maxld > kMaxLd) {  // long axes
@@ -2639,7 +2746,7 @@ hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int 
   }
   const size_t sh = std::max<size_t>(op_lds(prec, maxld), (size_t)lneed);
   const int lcap = (int)sh;
-  const bool eight = ntiles <= 512;  // latency-bound: at most two workgroups per compute unit
+  const bool eight = ntiles <= eight_max;  // latency-bound: at most two workgroups per compute unit
 #define PMA_STRIP(K, P)                                                                                         \
   do {                                                                                                          \
     if (eight)                                                                                                  \
@@ -2699,7 +2806,8 @@ hipError_t enable_large_lds() {
                         (const void*)strip4_kernel<PREC_SPLIT16, false>, (const void*)strip_long_kernel<PREC_F64, true>,
                         (const void*)strip_long_kernel<PREC_F64, false>, (const void*)strip_long_kernel<PREC_F32, true>,
                         (const void*)strip_long_kernel<PREC_F32, false>, (const void*)strip_long_kernel<PREC_SPLIT16, true>,
-                        (const void*)strip_long_kernel<PREC_SPLIT16, false>};
+                        (const void*)strip_long_kernel<PREC_SPLIT16, false>, (const void*)step2_persist_kernel<PREC_F64>,
+                        (const void*)step2_persist_kernel<PREC_F32>, (const void*)step2_persist_kernel<PREC_SPLIT16>};
     for (const void* k : ks) {
       // whatever the kernel's static LDS leaves of the 160 KiB (at most lim)
       hipFuncAttributes fa{};
@@ -2859,6 +2967,35 @@ hipError_t launch_quality(const double* mesh, int dim, const int* n, const doubl
 
 hipError_t launch_min_reduce(const double* x, long n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(min_reduce_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+// the persistent step: static LDS of the kernel, and how many workgroups of 512 threads with
+// `dyn` bytes of dynamic LDS the device holds at once (0 if none fits)
+int persist_capacity(int prec, size_t dyn, int* static_lds) {
+  const void* k = prec == PREC_F64 ? (const void*)step2_persist_kernel<PREC_F64>
+                  : prec == PREC_F32 ? (const void*)step2_persist_kernel<PREC_F32>
+                                     : (const void*)step2_persist_kernel<PREC_SPLIT16>;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, k) != hipSuccess) return 0;
+  if (static_lds) *static_lds = (int)fa.sharedSizeBytes;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * kFuseWaves, dyn) != hipSuccess) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_step2_persist(int prec, int grid, size_t dyn, const PersistArgs& pa, const StepArgs& sa,
+                                hipStream_t s) {
+  if (grid <= 0 || (grid & 7)) return hipErrorInvalidValue;
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(step2_persist_kernel<PREC_F64>, dim3(grid), dim3(64 * kFuseWaves), dyn, s, pa, sa);
+  else if (prec == PREC_F32)
+    hipLaunchKernelGGL(step2_persist_kernel<PREC_F32>, dim3(grid), dim3(64 * kFuseWaves), dyn, s, pa, sa);
+  else
+    hipLaunchKernelGGL(step2_persist_kernel<PREC_SPLIT16>, dim3(grid), dim3(64 * kFuseWaves), dyn, s, pa, sa);
   return hipGetLastError();
 }
 

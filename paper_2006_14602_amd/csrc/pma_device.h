@@ -22,7 +22,7 @@ enum MonKind {
 constexpr int kMaxBumps = 9;
 
 // status bits raised by kernels (per instance)
-enum { ST_TANGLED = 1, ST_NONFINITE = 2 };
+enum { ST_TANGLED = 1, ST_NONFINITE = 2, ST_SYNC = 4 };  // ST_SYNC: a grid barrier wait timed out
 
 // Monitor parameters, precomputed on the host in the working precision:
 //   rho = amp                                              (MON_CONST)
@@ -98,6 +98,19 @@ struct StepArgs {
   double* partials;      // residual partial sums (FP64)
   double* shift_acc;     // per-instance accumulated constant removed from phi (FP64)
   int* status;           // per-instance status bits
+};
+
+// one persistent launch per step (2D, preconditioned, parallel coupling): the three phases' tile
+// tables, and the grid barrier's words (arrivals, generation)
+struct PersistArgs {
+  const int4* t_fused;
+  const int4* t_pair;
+  const int4* t_inv;
+  unsigned* bar;
+  int n_fused, n_pair, n_inv;
+  int pair_src, part_base, lcap;
+  int ninst;
+  unsigned spin;  // bound on each barrier wait (polls of about 64 cycles)
 };
 
 // bytes of the fixed device scratch used by the entry point that allocates nothing

@@ -28,18 +28,21 @@ namespace pma {
 hipError_t launch_transmit(int prec, const SubDev* subs, const int4* ent, int count, hipStream_t s);
 hipError_t scratch_init(int device);
 void* scratch_ptr(int device);
+int persist_capacity(int prec, size_t dyn, int* static_lds);
+hipError_t launch_step2_persist(int prec, int grid, size_t dyn, const PersistArgs& pa, const StepArgs& sa,
+                                hipStream_t s);
 hipError_t launch_stencil(int prec, int dim, const int4* tiles, int ntiles, const StepArgs& sa, hipStream_t s);
 hipError_t launch_stencil_fwd2(int prec, const int4* tiles, int ntiles, int lneed, const StepArgs& sa, hipStream_t s);
 int fused_lds_bytes(int prec, int ld, int ldb, int n, bool basis);
 hipError_t launch_euler(int prec, const int4* tiles, int ntiles, int part_base, const StepArgs& sa,
                         hipStream_t s);
 hipError_t launch_fwd_last(int prec, const int4* tiles, int ntiles, int maxld, const StepArgs& sa, hipStream_t s);
-hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, const StepArgs& sa,
-                           hipStream_t s);
+hipError_t launch_inv_last(int prec, const int4* tiles, int ntiles, int maxld, int part_base, int eight_max,
+                           const StepArgs& sa, hipStream_t s);
 hipError_t launch_strip4(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int axis, int inv,
                          int src_sel, const StepArgs& sa, hipStream_t s);
 hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int maxld, int lneed, int axis, int inv,
-                        int src_sel, const StepArgs& sa, hipStream_t s);
+                        int src_sel, int eight_max, const StepArgs& sa, hipStream_t s);
 hipError_t enable_large_lds();
 hipError_t launch_resid(const SubDev* subs, const InstDev* insts, int ninst, const double* partials,
                         double* out, hipStream_t s);
@@ -1214,6 +1217,7 @@ static constexpr int kLdsBasisCap = 160 * 1024 - 4096;  // dynamic LDS a workgro
 // workgroups per CU (latency-bound), not for large batches that rely on occupancy.
 static constexpr int kLdsBasisMaxTiles = 512;
 static constexpr int kWideMaxLd = 320;  // widest padded axis of the 64-column strip kernel
+static constexpr size_t kBarBytes = (64 + 8 * 32) * 4;  // the persistent step's barrier words
 
 struct SubRange {
   int first, count;
@@ -1416,7 +1420,11 @@ struct Batch {
   }
   size_t st_cap = 0;
 
-  static int lds_basis(const Table& t, int count) { return count <= kLdsBasisMaxTiles ? t.lneed : 0; }
+  // launch-shape thresholds (tuned by pma_plan_tune; results do not depend on them): launches of
+  // at most eight_max tiles take eight-wave workgroups, of at most lbasis_max tiles copy the DCT
+  // matrices into LDS where they fit
+  int eight_max = 512, lbasis_max = kLdsBasisMaxTiles;
+  int lds_basis(const Table& t, int count) const { return count <= lbasis_max ? t.lneed : 0; }
 
   // 64-column strips (phases 4-6) when every launch of a 16-column table would exceed
   // kLdsBasisMaxTiles strips: every strip then reads its axis' DCT matrices from L2, and four
@@ -1648,7 +1656,8 @@ struct Batch {
     const size_t el = prec == PMA_FP64 ? 8 : 4;
     size_t bytes = Arena::round(nsub * sizeof(SubDev)) + Arena::round(ninst * sizeof(InstDev)) +
                    Arena::round(h_pull.size() * 16 + 16) + Arena::round(nsub * el) +
-                   Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4);
+                   Arena::round((size_t)(npartials + 1) * 8) + 2 * Arena::round(ninst * 8) + Arena::round(ninst * 4) +
+                   Arena::round(kBarBytes);
     for (int ph = 1; ph < kPhases; ++ph) bytes += Arena::round((ph == 1 ? st_cap : tab[ph].h.size()) * 16 + 16);
     if (ext_tab) {
       if (bytes > ext_tab_cap) thr(PMA_E_INVAL, "launch tables exceed the fixed scratch");
@@ -1684,6 +1693,7 @@ struct Batch {
     d_shift = (double*)take(ninst * 8);
     d_resid = (double*)take(ninst * 8);
     d_status = (int*)take(ninst * 4);
+    d_bar = (unsigned*)take(kBarBytes);
     up(d_subs, h_subs.data(), nsub * sizeof(SubDev));
     up(d_insts, h_insts.data(), ninst * sizeof(InstDev));
     up(d_pull, h_pull.data(), h_pull.size() * 16);
@@ -1691,6 +1701,7 @@ struct Batch {
     HIPCHK(hipMemsetAsync(d_dc, 0, nsub * el, st));
     HIPCHK(hipMemsetAsync(d_partials, 0, (size_t)(npartials + 1) * 8, st));
     HIPCHK(hipMemsetAsync(d_status, 0, ninst * 4, st));
+    HIPCHK(hipMemsetAsync(d_bar, 0, kBarBytes, st));
     HIPCHK(hipMemsetAsync(d_resid, 0, ninst * 8, st));
     // accumulated shifts continue across rebuilds
     std::vector<double> sh(ninst, 0.0);
@@ -1716,6 +1727,7 @@ struct Batch {
     sa.partials = d_partials;
     sa.shift_acc = d_shift;
     sa.status = d_status;
+    persist = want_persist && persist_eligible();
     HIPCHK(hipStreamSynchronize(st));
     built = true;
   }
@@ -1727,7 +1739,7 @@ struct Batch {
     switch (ph) {
       case 1:
         if (stencil_kind_ == 4)
-          HIPCHK(launch_stencil_fwd2(prec, t.d + first, count, count <= kLdsBasisMaxTiles ? t.lneed : t.lneed_nb, sa, st));
+          HIPCHK(launch_stencil_fwd2(prec, t.d + first, count, count <= lbasis_max ? t.lneed : t.lneed_nb, sa, st));
         else
           HIPCHK(launch_stencil(prec, stencil_kind_, t.d + first, count, sa, st));
         break;
@@ -1735,23 +1747,91 @@ struct Batch {
       case 3: HIPCHK(launch_fwd_last(prec, t.d + first, count, t.maxld, sa, st)); break;
       case 4:
         if (wide_[4]) HIPCHK(launch_strip4(prec, false, t.d + first, count, t.maxld, 1, 0, 1, sa, st));
-        else HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 0, 1, sa, st));
+        else HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 0, 1, eight_max, sa, st));
         break;
       case 5:  // 2D: T -> F;  3D: F -> T (pair_src_ set by launch_phase)
         if (wide_[5]) HIPCHK(launch_strip4(prec, true, t.d + first, count, t.maxld, 0, 0, pair_src_, sa, st));
-        else HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, lds_basis(t, count), 0, 0, pair_src_, sa, st));
+        else HIPCHK(launch_strip(prec, true, t.d + first, count, t.maxld, lds_basis(t, count), 0, 0, pair_src_, eight_max, sa, st));
         break;
       case 6:
         if (wide_[6]) HIPCHK(launch_strip4(prec, false, t.d + first, count, t.maxld, 1, 1, 1, sa, st));
-        else HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 1, 1, sa, st));
+        else HIPCHK(launch_strip(prec, false, t.d + first, count, t.maxld, lds_basis(t, count), 1, 1, 1, eight_max, sa, st));
         break;
       case 7:
-        HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, sa, st));
+        HIPCHK(launch_inv_last(prec, t.d + first, count, t.maxld, part_base_inv + first, eight_max, sa, st));
         break;
     }
   }
   int pair_src_ = 1;
   int stencil_kind_ = 2;
+
+  // One persistent launch per step (form 2): the fused stencil, the axis-0 pair and the inverse
+  // last-axis kernel's tile bodies in one kernel with grid-wide barriers between them.  Taken
+  // when asked for (want_persist) and the batch allows it: one sweep level, every subdomain 2D,
+  // preconditioned and fused, the pair on 16-column strips of regular axes.  Results are
+  // bitwise those of the phase launches.
+  bool want_persist = false;
+  bool persist = false;
+  int persist_grid = 0;
+  size_t persist_dyn = 0;
+  unsigned* d_bar = nullptr;
+  std::string persist_why;  // why the batch cannot take the persistent step
+  bool persist_eligible() {
+    persist_why.clear();
+    if (nlev != 1) persist_why = "alternating sweeps";
+    for (size_t gs = 0; gs < h_subs.size() && persist_why.empty(); ++gs)
+      if (!fused_[gs]) persist_why = "a subdomain is not a fused 2D preconditioned one (3D, forward Euler, or a last axis above 320)";
+    if (persist_why.empty() && !h_pull.empty()) persist_why = "transmission by gather";
+    if (persist_why.empty() && (wide_[5] || tab[5].maxld > 576)) persist_why = "wide or long axis-0 strips";
+    if (persist_why.empty()) {
+      // dynamic LDS: the largest tile footprint (with LDS basis copies where they fit), capped by
+      // what the kernel's static LDS leaves
+      int stat = 0;
+      persist_capacity(prec, 0, &stat);
+      const size_t cap = (size_t)(160 * 1024 - stat - 4096);
+      const size_t el = prec == PMA_FP64 ? 8 : 4, op = 16 * ((size_t)tab[7].maxld + (prec == PMA_FP64 ? 2 : 4)) * el;
+      const size_t least = std::max({(size_t)tab[1].lneed_nb, op, 16 * ((size_t)tab[5].maxld + (prec == PMA_FP64 ? 2 : 4)) * el});
+      const size_t want = std::max({least, (size_t)tab[1].lneed, (size_t)tab[5].lneed});
+      if (least > cap) {
+        persist_why = "tiles too large for one kernel's LDS";
+      } else {
+        persist_dyn = std::min(want, cap);
+        // as many workgroups as the largest phase has tiles (a multiple of 8), at most what the
+        // device holds at once: fewer arrivals per barrier for small batches
+        int most = 0;
+        for (int ph : {1, 5, 7}) {
+          const Table& t = tab[ph];
+          const int p0 = lvl_first[0], p1 = lvl_first[1];
+          most = std::max(most, t.rng[order[p1 - 1]].first + t.rng[order[p1 - 1]].count - t.rng[order[p0]].first);
+        }
+        persist_grid = std::min(persist_capacity(prec, persist_dyn, nullptr) / 8 * 8, (most + 7) / 8 * 8);
+        if (persist_grid <= 0) persist_why = "no co-resident grid";
+      }
+    }
+    return persist_why.empty();
+  }
+
+  void launch_persist(hipStream_t st) {
+    PersistArgs pa{};
+    auto total = [&](int ph) {
+      const Table& t = tab[ph];
+      const int p0 = lvl_first[0], p1 = lvl_first[1];
+      return t.rng[order[p1 - 1]].first + t.rng[order[p1 - 1]].count - t.rng[order[p0]].first;
+    };
+    pa.t_fused = tab[1].d;
+    pa.t_pair = tab[5].d;
+    pa.t_inv = tab[7].d;
+    pa.n_fused = total(1);
+    pa.n_pair = total(5);
+    pa.n_inv = total(7);
+    pa.bar = d_bar;
+    pa.pair_src = 1;  // 2D: the pair reads T, writes F
+    pa.part_base = part_base_inv;
+    pa.lcap = (int)persist_dyn;
+    pa.ninst = (int)h_insts.size();
+    pa.spin = 1u << 18;  // well under a second per wait: far beyond any phase, still bounded
+    HIPCHK(launch_step2_persist(prec, persist_grid, persist_dyn, pa, sa, st));
+  }
 
   // one phase of a step over sweep level L (-1: every level in turn): the level's subdomains in
   // one launch, or one subdomain per launch (plain)
@@ -1818,6 +1898,10 @@ struct Batch {
   // forward-Euler subdomains (the others received their owners' values from the inverse-last
   // kernels that updated those owners), then the stencil and the update
   void launch_step(bool plain, hipStream_t st) {
+    if (persist && !plain) {
+      launch_persist(st);
+      return;
+    }
     for (int L = 0; L < nlev; ++L) {
       const int p0 = lvl_first[L], p1 = lvl_first[L + 1];
       if (p1 <= p0) continue;
@@ -1924,6 +2008,7 @@ struct Batch {
 static int status_code(int bits) {
   if (bits & ST_TANGLED) return PMA_E_TANGLED;
   if (bits & ST_NONFINITE) return PMA_E_NONFINITE;
+  if (bits & ST_SYNC) return PMA_E_HIP;  // a grid barrier of the persistent step timed out
   return PMA_OK;
 }
 
@@ -2888,6 +2973,20 @@ int pma_plan_set_fusion(pma_plan* P, int on) {
   API_END
 }
 
+int pma_plan_set_persistent(pma_plan* P, int on) {
+  API_BEGIN
+  if (!P) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  if (P->plain) return fail(PMA_E_INVAL, "the plain form launches one subdomain per kernel");
+  Batch& B = *P->batch;
+  if (on && !B.persist_eligible()) return fail(PMA_E_INVAL, "no persistent step for this plan: %s", B.persist_why.c_str());
+  B.want_persist = on != 0;
+  B.persist = B.want_persist;
+  B.drop_graphs();
+  return PMA_OK;
+  API_END
+}
+
 int pma_plan_set_wide_strips(pma_plan* P, int on) {
   API_BEGIN
   if (!P) return fail(PMA_E_INVAL, "bad arguments");
@@ -2954,6 +3053,175 @@ int pma_plan_autotune(pma_plan* P, int reps, int* march, double* ms, int cap, in
   hipEventDestroy(e1);
   *march = best;
   if (ncand) *ncand = k;
+  return PMA_OK;
+  API_END
+}
+
+}  // extern "C"
+
+namespace pma {
+
+// the tuning cache's key: the device, the precision and coarse buckets of the plan's shape
+static std::string tune_key(const pma_plan* P) {
+  const Batch& B = *P->batch;
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, P->ctx->device) != hipSuccess) thr(PMA_E_HIP, "device query failed");
+  long nodes = 0, subs = (long)B.h_subs.size();
+  int maxld = 0, dims = 0, euler = 0;
+  for (const SubDev& sd : B.h_subs) {
+    nodes += (long)sd.n[0] * sd.n[1] * sd.n[2];
+    for (int k = 0; k < sd.dim; ++k) maxld = std::max(maxld, (sd.n[k] + 31) / 32 * 32);
+    dims |= 1 << sd.dim;
+    euler |= P->insts[sd.inst]->tm.gamma == 0.0;
+  }
+  auto pow2 = [](long v) { long p = 1; while (p < v) p <<= 1; return p; };
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|prec%d|%s|subs%ld|nodes%ld|ld%d|dims%d|euler%d|levels%d", prop.gcnArchName, B.prec,
+                P->plain ? "plain" : "batched", pow2(subs), pow2(nodes), maxld, dims, euler, B.nlev);
+  return buf;
+}
+
+struct TuneChoice {
+  int march = 1, persistent = 0, eight_max = 512, lbasis_max = kLdsBasisMaxTiles;
+  double ms = 0;
+};
+
+static bool tune_cache_find(const char* path, const std::string& key, TuneChoice& c) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    char k[300];
+    TuneChoice t;
+    if (std::sscanf(line, "%299[^\t]\t%d\t%d\t%d\t%d\t%lf", k, &t.march, &t.persistent, &t.eight_max,
+                    &t.lbasis_max, &t.ms) == 6 && key == k) {
+      c = t;  // the last entry for the key wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_add(const char* path, const std::string& key, const TuneChoice& c) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) thr(PMA_E_INVAL, "tuning cache: cannot open the file for appending");
+  std::fprintf(f, "%s\t%d\t%d\t%d\t%d\t%.6f\n", key.c_str(), c.march, c.persistent, c.eight_max, c.lbasis_max, c.ms);
+  std::fclose(f);
+}
+
+static void apply_choice(pma_plan* P, const TuneChoice& c) {
+  Batch& B = *P->batch;
+  B.set_stencil_march(c.march);
+  B.eight_max = c.eight_max;
+  B.lbasis_max = c.lbasis_max;
+  B.want_persist = c.persistent != 0 && !P->plain && B.persist_eligible();
+  B.persist = B.want_persist;
+  B.drop_graphs();
+}
+
+}  // namespace pma
+
+extern "C" {
+
+int pma_plan_tune(pma_plan* P, int reps, const char* cache_path, pma_tuning* out) {
+  API_BEGIN
+  if (!P || reps <= 0 || !out) return fail(PMA_E_INVAL, "bad arguments");
+  std::lock_guard<std::recursive_mutex> g(P->ctx->mu);
+  *out = pma_tuning{};
+  const std::string key = tune_key(P);
+  TuneChoice best;
+  if (tune_cache_find(cache_path, key, best)) {
+    apply_choice(P, best);
+    out->march = best.march;
+    out->persistent = P->batch->persist ? 1 : 0;
+    out->eight_max = best.eight_max;
+    out->lbasis_max = best.lbasis_max;
+    out->step_ms = best.ms;
+    out->from_cache = 1;
+    return PMA_OK;
+  }
+  // the stencil's launch shape on its own (it writes only F), then whole steps of every launch
+  // configuration on a copy of the state, restored afterwards
+  int march = 1;
+  const int rc = pma_plan_autotune(P, reps, &march, nullptr, 0, nullptr);
+  if (rc != PMA_OK) return rc;
+  Batch& B = *P->batch;
+  pma_ctx* c = P->ctx;
+  hipStream_t st = c->stream;
+  size_t snap = 0;
+  for (auto& I : P->insts)
+    for (auto& sub : I->subs) snap += Arena::round(sub_nodes(sub) * I->elem());
+  snap += 2 * Arena::round(P->insts.size() * 8);
+  char* save = (char*)arena_alloc(c, snap);
+  auto copy_state = [&](bool out_) {
+    char* q = save;
+    for (auto& I : P->insts)
+      for (size_t s2 = 0; s2 < I->subs.size(); ++s2) {
+        const size_t b = sub_nodes(I->subs[s2]) * I->elem();
+        HIPCHK(hipMemcpyAsync(out_ ? (void*)q : I->phi[s2], out_ ? I->phi[s2] : (void*)q, b, hipMemcpyDeviceToDevice, st));
+        q += Arena::round(b);
+      }
+    HIPCHK(hipMemcpyAsync(out_ ? (void*)q : (void*)B.d_shift, out_ ? (void*)B.d_shift : (void*)q, P->insts.size() * 8,
+                          hipMemcpyDeviceToDevice, st));
+    q += Arena::round(P->insts.size() * 8);
+    HIPCHK(hipMemcpyAsync(out_ ? (void*)q : (void*)B.d_status, out_ ? (void*)B.d_status : (void*)q, P->insts.size() * 4,
+                          hipMemcpyDeviceToDevice, st));
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int ncand = 0;
+  best.ms = 1e300;
+  try {
+    copy_state(true);
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const bool can_persist = !P->plain && B.persist_eligible();
+    for (int pers = 0; pers <= (can_persist ? 1 : 0); ++pers)
+      for (int em : {0, 512, 1 << 30})
+        for (int lm : {0, (int)kLdsBasisMaxTiles, 1 << 30}) {
+          TuneChoice t;
+          t.march = march;
+          t.persistent = pers;
+          t.eight_max = em;
+          t.lbasis_max = lm;
+          apply_choice(P, t);
+          B.launch_step(P->plain, st);  // warm
+          HIPCHK(hipEventRecord(e0, st));
+          for (int r = 0; r < reps; ++r) B.launch_step(P->plain, st);
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          t.ms = (double)ms / reps;
+          ++ncand;
+          if (t.ms < best.ms) best = t;
+          copy_state(false);
+          copy_state(true);
+        }
+    copy_state(false);
+    HIPCHK(hipStreamSynchronize(st));
+  } catch (Err&) {
+    hipStreamSynchronize(st);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    c->arena.release(save);
+    throw;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->arena.release(save);
+  apply_choice(P, best);
+  tune_cache_add(cache_path, key, best);
+  out->march = best.march;
+  out->persistent = B.persist ? 1 : 0;
+  out->eight_max = best.eight_max;
+  out->lbasis_max = best.lbasis_max;
+  out->step_ms = best.ms;
+  out->from_cache = 0;
+  out->candidates = ncand;
   return PMA_OK;
   API_END
 }

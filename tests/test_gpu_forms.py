@@ -590,3 +590,70 @@ def serve_poll(c, ticket, shape, timeout=60.0):
             return state, mesh, st
         assert time.time() - t0 < timeout, "serving did not finish"
         time.sleep(0.002)
+
+
+@pytest.mark.parametrize("prec", ["split16", "fp32", "fp64"])
+@pytest.mark.parametrize("wl", ["sine129_4x4", "ring65", "bumps24"])
+def test_persistent_step_equals_phase_launches_bitwise(ctx, B, prec, wl):
+    # form (2): each step in one persistent launch (grid-wide barriers between the fused stencil,
+    # the axis-0 pair and the inverse last-axis product) gives the meshes of the phase launches
+    if wl == "sine129_4x4":
+        ws = [W.sine_dd(n=129, parts=(4, 4), overlap=8, steps=30)]
+    elif wl == "ring65":
+        ws = [W.ring(steps=30)]
+    else:
+        ws = W.bumps_batch(count=24, steps=20, n_hi=129)
+    steps = ws[0]["time"]["steps"]
+    meshes = []
+    for persistent in (False, True):
+        with B.Plan(ctx, ws, prec) as p:
+            if persistent:
+                p.set_persistent(True)
+            p.step(steps - 3)
+            p.step(3)
+            p.sync()
+            meshes.append([p.mesh(i)[0] for i in range(len(ws))])
+    for a, b in zip(*meshes):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_persistent_step_refused_where_it_does_not_apply(ctx, B):
+    for w, why in ((W.shell_dd(n=25, parts=(2, 2, 2), overlap=4, steps=2), "3D"),
+                   (dict(W.sine_dd(n=65, parts=(2, 2), overlap=4, steps=2),
+                         dd={"parts": [2, 2], "overlap": [4, 4], "mode": "alternating"}), "alternating")):
+        with B.Plan(ctx, [w], "split16") as p:
+            with pytest.raises(B.PmaError) as e:
+                p.set_persistent(True)
+            assert e.value.code == B.PMA_E_INVAL
+            assert why in str(e.value) or "fused" in str(e.value)
+
+
+def test_plan_tune_with_cache_is_bitwise_neutral(ctx, B, tmp_path):
+    # pma_plan_tune times whole steps over the step form and the launch-shape thresholds, keeps
+    # the fastest and records it in the cache file; a second plan of the same shape takes the
+    # cached choice without timing; the meshes equal an untuned plan's bit for bit
+    ws = [W.sine_dd(n=129, parts=(4, 4), overlap=8, steps=25)]
+    cache = tmp_path / "tune.txt"
+    with B.Plan(ctx, ws, "split16") as p:
+        t1 = p.tune(3, cache)
+        p.step(25)
+        p.sync()
+        tuned = p.mesh(0)[0]
+    assert t1["from_cache"] == 0 and t1["candidates"] == 18 and t1["step_ms"] > 0
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and lines[0].split("\t")[0].startswith("gfx")
+    with B.Plan(ctx, ws, "split16") as p:
+        t2 = p.tune(3, cache)
+        p.step(25)
+        p.sync()
+        cached = p.mesh(0)[0]
+    assert t2["from_cache"] == 1
+    assert {k: t2[k] for k in ("march", "persistent", "eight_max", "lbasis_max")} == \
+        {k: t1[k] for k in ("march", "persistent", "eight_max", "lbasis_max")}
+    with B.Plan(ctx, ws, "split16") as p:
+        p.step(25)
+        p.sync()
+        plain = p.mesh(0)[0]
+    np.testing.assert_array_equal(tuned, plain)
+    np.testing.assert_array_equal(cached, plain)
+    print("tuned choice", t1)
