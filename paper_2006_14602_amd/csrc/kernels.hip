@@ -2237,7 +2237,8 @@ __device__ inline void stencil_fwd2_tile(const int4 tl, const StencilCtx<typenam
 
 // tile = (sub, row0, 0, 0)
 template <int KIND>
-__device__ inline void stencil_fwd2_dispatch(const int4 tl, int lcap, const StepArgs& sa);
+__device__ __attribute__((always_inline)) inline void stencil_fwd2_dispatch(const int4 tl, int lcap,
+                                                                           const StepArgs& sa);
 
 template <int KIND>
 __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int4* __restrict__ tiles, int ntiles,
@@ -2247,9 +2248,12 @@ __global__ __launch_bounds__(64 * kFuseWaves) void stencil_fwd2_kernel(const int
   stencil_fwd2_dispatch<KIND>(tiles[tix], lcap, sa);
 }
 
-// one fused tile: the monitor kind chosen once, the node loop specialised for it
+// one fused tile: the monitor kind chosen once, the node loop specialised for it.  Always inlined:
+// as a called function it would read the step descriptors through flat loads of a stack copy and
+// size every caller's registers for its widest monitor specialisation (FP64: 99 -> 248 VGPRs)
 template <int KIND>
-__device__ inline void stencil_fwd2_dispatch(const int4 tl, int lcap, const StepArgs& sa) {
+__device__ __attribute__((always_inline)) inline void stencil_fwd2_dispatch(const int4 tl, int lcap,
+                                                                           const StepArgs& sa) {
   typedef typename Op<KIND>::T T;
   StencilCtx<T> K;
   const T* phi_;
