@@ -2151,6 +2151,11 @@ static void run_to_end(pma_ctx* c, const std::vector<Instance*>& all, int prec, 
 // serving: continuous batching
 // ------------------------------------------------------------------------------------------
 
+// Locks: the context's mutex (ctx->mu: the arena, the basis cache, the stream) and the server's
+// (mu: queue, states, results).  A thread that holds both takes ctx->mu first, everywhere; the
+// caller-side calls (submit, poll, server info) take mu alone.  Admission used to take them in the
+// opposite order (mu, then ctx->mu inside the loop), harmless while only the server thread holds
+// both, but a deadlock against any second thread that finishes requests in the tick's order.
 struct Server {
   pma_ctx* ctx = nullptr;
   std::thread th;
@@ -2188,9 +2193,10 @@ struct Server {
 
   size_t request_bytes(const Instance& I) { return Arena::round(instance_bytes(I)) + new_basis_bytes(ctx, I); }
 
-  // admit queued requests in arrival order while they fit (no overtaking); caller holds mu
-  // true while the head of the queue waits for memory: nothing can be admitted before a running
-  // request finishes, so a tick may run until the first of them does
+  // admit queued requests in arrival order while they fit (no overtaking); caller holds ctx->mu
+  // and mu, in that order.  blocked: true while the head of the queue waits for memory: nothing
+  // can be admitted before a running request finishes, so a tick may run until the first of them
+  // does
   bool blocked = false;
 
   void admit_locked() {
@@ -2198,7 +2204,6 @@ struct Server {
     while (!queue.empty()) {
       Instance* I = queue.front();
       const size_t need = request_bytes(*I);
-      std::lock_guard<std::recursive_mutex> cg(ctx->mu);
       try {
         ensure_arena(ctx);
         // cached bases nobody uses are evicted by the allocation itself, so they do not block
@@ -2245,17 +2250,18 @@ struct Server {
         std::unique_lock<std::mutex> g(mu);
         cv.wait(g, [&] { return stop || !queue.empty() || !running.empty(); });
         if (stop) return;
-        admit_locked();
-        if (running.empty()) {
-          g.unlock();
-          std::this_thread::sleep_for(std::chrono::microseconds(200));
-          continue;
-        }
       }
-      bool wait_for_memory;
+      bool idle, wait_for_memory;
       {
+        std::lock_guard<std::recursive_mutex> cg(ctx->mu);
         std::lock_guard<std::mutex> g(mu);
+        admit_locked();
+        idle = running.empty();
         wait_for_memory = blocked;
+      }
+      if (idle) {
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+        continue;
       }
       try {
         tick(wait_for_memory ? kLongTick : kShortTick);
