@@ -271,19 +271,16 @@ template <typename T> struct MonReg<T, MON_ARC_SPHERES> {
   }
 };
 
-// Status of the nodes of a block, folded into two registers per thread: the least 1 + e seen
-// (det(I + D^2 phi) <= 0 is a tangled mesh) and a sum of 0 * F (inf or NaN stays non-finite).
+// Status of the nodes of a block: whether some 1 + e seen was <= 0 (det(I + D^2 phi) <= 0 is a
+// tangled mesh).  A non-finite F needs no test here: every DCT product
+// carries it (NaN and inf times any coefficient, zero included, stay non-finite) into the update
+// of its line, and the update kernels flag a non-finite update.
 template <typename T>
 struct NodeCheck {
-  T min_det = T(1);
-  T nonfin = T(0);
-  __device__ inline void add(T e, T f) {
-    min_det = fmin(min_det, T(1) + e);
-    nonfin = fma(f, T(0), nonfin);
-  }
-  __device__ inline int bits() const {
-    return (!(min_det > T(0)) ? ST_TANGLED : 0) | (finite_(nonfin) ? 0 : ST_NONFINITE);
-  }
+  bool tangled = false;  // a lane mask: one compare per node, the or on the scalar unit
+  // a NaN (a state already non-finite, flagged by the update) does not count as tangled
+  __device__ inline void add(T one_plus_e) { tangled = tangled || one_plus_e <= T(0); }
+  __device__ inline int bits() const { return tangled ? ST_TANGLED : 0; }
 };
 
 // Per-workgroup constants of a subdomain, copied into registers once.
@@ -388,6 +385,23 @@ __device__ inline int wave_any_bits(int bits) {
   return __builtin_amdgcn_readfirstlane(r);
 }
 
+// The output nodes of a thread in the 2D march (as Slots), in the form the node loop reads with
+// the fewest vector instructions: the LDS byte offset of the node's upper-left neighbour, so the
+// nine stencil reads are immediate offsets from one register; the global row index kept as T
+// (whole numbers, exact) and stepped by kStR per chunk instead of converted per node; the valid
+// and live flags as lane masks in scalar registers, which the selects and the store's branch use
+// as they are.
+template <typename T>
+struct Slots2 {
+  unsigned lds[kStPts];  // LDS byte offset of element (row - 1, column - 1) of the staged block
+  unsigned out[kStPts];  // byte offset in the chunk's output block
+  int row[kStPts];       // row within the chunk (kStR: no node)
+  T xc[kStPts];          // coordinate along the last axis: a + (global index) h
+  T gr[kStPts];          // global row index of the node in the current chunk
+  uint64_t valid[kStPts];  // lanes whose slot m holds a node (wave-uniform lane mask)
+  uint64_t live[kStPts];   // ... whose column is not artificial
+};
+
 // 2D: rows [row0, row0 + nrows) x columns [col0, col0 + W) of a subdomain, 16 rows per chunk.
 // The artificial nodes were filled by the transmission gather before the launch.
 template <typename T, int MK>
@@ -400,22 +414,20 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
   const int n0 = K.n0, n1 = K.n1;
   const HaloCols hc = halo_cols<T>(col0, W, n1);
   const T h0 = K.h0, h1 = K.h1;
-  Slots<T> sl;
-  sl.valid = 0;
-  sl.live = 0;
+  Slots2<T> sl;
 #pragma unroll
   for (int m = 0; m < kStPts; ++m) {
     const int idx = (int)threadIdx.x + 256 * m;
     const int rr = idx / W, cc = idx - rr * W;
     const bool ok = idx < kStR * W;
-    sl.lds[m] = ok ? (rr + 1) * kStS + cc + 1 : kStS + 1;
+    sl.lds[m] = (unsigned)(ok ? rr * kStS + cc : 0) * sizeof(T);
     sl.out[m] = (unsigned)(rr * n1 + cc) * sizeof(T);
     sl.row[m] = ok ? rr : kStR;
     sl.xc[m] = K.a1 + T(K.off1 + col0 + cc) * h1;
-    sl.valid |= ok ? 1 << m : 0;
-    sl.live |= (ok && !is_artificial(K.art, 1, col0 + cc, n1)) ? 1 << m : 0;
+    sl.gr[m] = T(K.off0 + row0 + (ok ? rr : 0));
+    sl.valid[m] = __ballot(ok);
+    sl.live[m] = __ballot(ok && !is_artificial(K.art, 1, col0 + cc, n1));
   }
-  sl.wave = wave_any_bits(sl.valid);
   const T r2h0 = T(1) / (T(2) * h0), r2h1 = T(1) / (T(2) * h1);
   const T rh00 = T(1) / (h0 * h0), rh11 = T(1) / (h1 * h1), r4h01 = T(1) / (T(4) * h0 * h1);
   NodeCheck<T> chk;
@@ -429,7 +441,10 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
     for (int k = 0; k < kStLd; ++k) rowp[k] = phi + (long)mirror_clamp(rb + wv + 4 * k - 1, n0) * n1;
     halo_issue(pre, hc, rowp, phi + (long)mirror_clamp(rb + hc.rE - 1, n0) * n1);
   };
-  auto chunk = [&](T (&pre)[kStPre], int rb) {
+  // EDGE: the first or last chunk of the block, whose rows may lie beyond the block or on an
+  // artificial face; its flags are derived per node, the interior chunks use the block's masks
+  auto chunk = [&](T (&pre)[kStPre], int rb, auto edge_tag) {
+    constexpr bool EDGE = decltype(edge_tag)::value;
     if (rb != row0) __syncthreads();  // every thread is done reading the previous chunk
     halo_commit(sm, hc, pre);
     __syncthreads();
@@ -438,49 +453,51 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
     // before the commit would have to drain the other register set's loads as well
     issue(pre, rb + 2 * kStR);
     gmem<T>* Fc = F + (long)rb * n1 + col0;
-    const int g0 = K.off0 + rb;  // global row index of the chunk's first row
-    // the first and last chunks may hold rows beyond the block or on an artificial face
-    int store = sl.valid, live = sl.live;
     const int rlim = min(kStR, rend - rb);
     const int rlo = (rb == 0 && (K.art & 1)) ? 0 : -1;
     const int rhi = (rb + kStR > n0 - 1 && (K.art & 2)) ? n0 - 1 - rb : -1;
-    if (rlim < kStR || rlo >= 0 || rhi >= 0) {
-#pragma unroll
-      for (int m = 0; m < kStPts; ++m) {
-        const int rr = sl.row[m];
-        if (rr >= rlim) store &= ~(1 << m);
-        if (rr >= rlim || rr == rlo || rr == rhi) live &= ~(1 << m);
-      }
-    }
 #pragma unroll
     for (int m = 0; m < kStPts; ++m) {
-      if (!((sl.wave >> m) & 1)) continue;  // no node of this wave in slot m (uniform branch)
-      const T* c = sm + sl.lds[m];
-      const T c0 = c[0];
-      const T xm = c[-kStS], xp = c[kStS], ym = c[-1], yp = c[1];
-      const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
-      const T hxx = (xp - T(2) * c0 + xm) * rh00;
-      const T hyy = (yp - T(2) * c0 + ym) * rh11;
-      const T hxy = (c[kStS + 1] - c[kStS - 1] - c[-kStS + 1] + c[-kStS - 1]) * r4h01;
-      const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
-      // a + (global index) h, rounded as for any other tiling of the same grid
-      const T x0 = K.a0 + T(g0 + sl.row[m]) * h0 + gx;
-      const T fv = K.lvt + log_rho_det(M.template excess<2>(x0, sl.xc[m] + gy, T(0)), e);
-      const bool lv = (live >> m) & 1;
-      const T f = lv ? fv : T(0);
-      chk.add(lv ? e : T(0), f);
-      if ((store >> m) & 1) *byte_off(Fc, sl.out[m]) = f;
+      if (sl.valid[m] != 0) {  // some node of this wave in slot m (uniform branch)
+        bool lv = __builtin_amdgcn_inverse_ballot_w64(sl.live[m]);
+        bool st = __builtin_amdgcn_inverse_ballot_w64(sl.valid[m]);
+        if constexpr (EDGE) {
+          const int rr = sl.row[m];
+          st = st && rr < rlim;
+          lv = lv && rr < rlim && rr != rlo && rr != rhi;
+        }
+        const T* t = (const T*)((const char*)sm + sl.lds[m]);  // upper-left neighbour
+        const T c0 = t[kStS + 1];
+        const T xm = t[1], xp = t[2 * kStS + 1], ym = t[kStS], yp = t[kStS + 2];
+        const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
+        const T hxx = (xp - T(2) * c0 + xm) * rh00;
+        const T hyy = (yp - T(2) * c0 + ym) * rh11;
+        const T hxy = (t[2 * kStS + 2] - t[2 * kStS] - t[2] + t[0]) * r4h01;
+        const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
+        // a + (global index) h, rounded as for any other tiling of the same grid
+        const T x0 = K.a0 + sl.gr[m] * h0 + gx;
+        const T fv = K.lvt + log_rho_det(M.template excess<2>(x0, sl.xc[m] + gy, T(0)), e);
+        const T f = lv ? fv : T(0);
+        chk.add(lv ? T(1) + e : T(1));
+        if (st) *byte_off(Fc, sl.out[m]) = f;
+      }
+      sl.gr[m] += T(kStR);
     }
+  };
+  auto any_chunk = [&](T (&pre)[kStPre], int rb) {
+    const bool edge = rb + kStR > rend || (rb == 0 && (K.art & 1)) || (rb + kStR > n0 - 1 && (K.art & 2));
+    if (edge) chunk(pre, rb, std::true_type{});
+    else chunk(pre, rb, std::false_type{});
   };
   vmem_drain();
   issue(preA, row0);
   issue(preB, row0 + kStR);
   int rb = row0;
   for (; rb + kStR < rend; rb += 2 * kStR) {  // both chunks of a pair on every path
-    chunk(preA, rb);
-    chunk(preB, rb + kStR);
+    any_chunk(preA, rb);
+    any_chunk(preB, rb + kStR);
   }
-  if (rb < rend) chunk(preA, rb);
+  if (rb < rend) any_chunk(preA, rb);
   bad |= chk.bits();
 }
 
@@ -566,7 +583,7 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
       const T fv = K.lvt + log_rho_det(M.template excess<3>(x0b + gx, x1s[m] + gy, sl.xc[m] + gz), e);
       const bool lv = (live >> m) & 1;
       const T f = lv ? fv : T(0);
-      chk.add(lv ? e : T(0), f);
+      chk.add(lv ? T(1) + e : T(1));
       if ((sl.valid >> m) & 1) *byte_off(Fc, sl.out[m]) = f;
     }
   };
@@ -1500,26 +1517,13 @@ __device__ inline void strip_tile(int tix, const int4* __restrict__ tiles, int a
   static_assert(RBL <= MAXRB, "LDS-basis row blocks fit the accumulators");
   char* lbh = lds + dbytes;
   char* lbl = lbh + bbytes;
-  // PAIR: spectral factors of this lane's coefficients, requested before the products.  The loads
-  // are unconditional (clamped indices; out-of-range values are discarded afterwards): a load under
-  // a branch would make each one wait for all earlier loads, one memory round trip per factor.
-  // The factors of axes 1 and 2 are combined only when the scale is applied.
-  T sig0[PAIR ? MAXRB * 4 : 1];
+  // PAIR: the factors of axes 1 and 2 of this lane's column, requested before the products; the
+  // axis-0 factors are read when the scale is applied (held through the products they would take
+  // 4 MAXRB registers per lane, in FP64 the difference between one and two workgroups per compute
+  // unit for the eight-wave form)
   RestSig<T> rs{T(0), T(0), T(0), T(0)};
-  if constexpr (PAIR) {
-    const gmem<T>* s0 = gp<T>(S.ax[0].sig);
-    rs = rest_sig<T>(S, c, ncol);
-    T raw[MAXRB * 4];
-#pragma unroll
-    for (int t = 0; t < MAXRB; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) raw[t * 4 + q] = s0[min((wave + NW * t) * 16 + O::crow(g, q), K - 1)];
-#pragma unroll
-    for (int t = 0; t < MAXRB; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        sig0[t * 4 + q] = (wave + NW * t) * 16 + O::crow(g, q) < K ? raw[t * 4 + q] : T(0);
-  }
+  const gmem<T>* s0 = gp<T>(S.ax[0].sig);
+  if constexpr (PAIR) rs = rest_sig<T>(S, c, ncol);
   // every descriptor field is read before the basis copy is issued: loads after it would be
   // vector loads (the copy may write memory, as far as the compiler knows), and each of their
   // waits would also wait for the copy
@@ -1568,8 +1572,15 @@ __device__ inline void strip_tile(int tix, const int4* __restrict__ tiles, int a
     }
   } else {
     // spectral scale; coefficient index (k0, k1[, k2]) = (i, c) with c split over axes 1, 2,
-    // and D^-1 (x 2 at i = 0 and i = K - 1) ahead of the forward matrix reused.
+    // and D^-1 (x 2 at i = 0 and i = K - 1) ahead of the forward matrix reused.  The axis-0
+    // factors are loaded unconditionally (clamped indices; out-of-range values discarded), all in
+    // flight together: a load under a branch would wait for every earlier load.
     const T rest = rs.value();
+    T sig0[MAXRB * 4];
+#pragma unroll
+    for (int t = 0; t < MAXRB; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sig0[t * 4 + q] = s0[min((wave + NW * t) * 16 + O::crow(g, q), K - 1)];
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
       const int rb = wave + NW * t;
@@ -2121,7 +2132,7 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K,
         const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
         const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
         f = K.lvt + log_rho_det(M.template excess<2>(x0b + gx, x1, T(0)), e);
-        chk.add(e, f);
+        chk.add(T(1) + e);
       }
       O::put(op, ldo, rr, j, f);
       if (O::SCALED) amax = fmaxf(amax, fabsf((float)f));
