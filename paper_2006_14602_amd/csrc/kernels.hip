@@ -1477,12 +1477,12 @@ __device__ inline RestSig<T> rest_sig(const SubDev& S, int c, int ncol) {
 // the global path doing the same keeps the two bitwise equal, so a request's result does not
 // depend on which path its launch takes.
 // one 16-column strip (entry tix of the launch table)
-template <int KIND, bool PAIR, int NW>
+template <int KIND, bool PAIR, int NW, int RBW = (36 + NW - 1) / NW>
 __device__ inline void strip_tile(int tix, const int4* __restrict__ tiles, int axis, int inv, int src_sel, int lcap,
                                   const StepArgs& sa) {
   typedef Op<KIND> O;
   typedef typename O::T T;
-  constexpr int MAXRB = (36 + NW - 1) / NW;       // row blocks per wave: n <= 36 * 16 = 576
+  constexpr int MAXRB = RBW;                       // row blocks per wave: n <= 16 NW RBW (576 by default)
   constexpr int RBL = (4 * kLdsRb + NW - 1) / NW;  // the same with the basis in LDS (n <= 192)
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const int4 tl = tiles[tix];
@@ -1650,12 +1650,15 @@ __device__ inline void strip_tile(int tix, const int4* __restrict__ tiles, int a
   }
 }
 
-template <int KIND, bool PAIR, int NW>
+// RBW: row blocks per wave; launches whose axes are at most 16 NW RBW long take a form with fewer
+// accumulators (eight waves, RBW = 3: axes up to 384, fewer registers per wave, more workgroups
+// per compute unit)
+template <int KIND, bool PAIR, int NW, int RBW = (36 + NW - 1) / NW>
 __global__ __launch_bounds__(64 * NW) void strip_kernel(const int4* __restrict__ tiles, int ntiles, int axis, int inv,
                                                         int src_sel, int lcap, StepArgs sa) {
   const int tix = xcd_tile();
   if (tix >= ntiles) return;
-  strip_tile<KIND, PAIR, NW>(tix, tiles, axis, inv, src_sel, lcap, sa);
+  strip_tile<KIND, PAIR, NW, RBW>(tix, tiles, axis, inv, src_sel, lcap, sa);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2764,7 +2767,10 @@ hipError_t launch_strip(int prec, bool pair, const int4* tiles, int ntiles, int 
   const bool eight = ntiles <= eight_max;  // latency-bound: at most two workgroups per compute unit
 #define PMA_STRIP(K, P)                                                                                         \
   do {                                                                                                          \
-    if (eight)                                                                                                  \
+    if (eight && maxld <= 16 * 8 * 3)                                                                           \
+      hipLaunchKernelGGL((strip_kernel<K, P, 8, 3>), dim3(ntiles), dim3(512), sh, s, tiles, ntiles, axis, inv,  \
+                         src_sel, lcap, sa);                                                                    \
+    else if (eight)                                                                                             \
       hipLaunchKernelGGL((strip_kernel<K, P, 8>), dim3(ntiles), dim3(512), sh, s, tiles, ntiles, axis, inv,     \
                          src_sel, lcap, sa);                                                                    \
     else                                                                                                        \
@@ -2815,6 +2821,10 @@ hipError_t enable_large_lds() {
                         (const void*)strip_kernel<PREC_F64, true, 8>, (const void*)strip_kernel<PREC_F64, false, 8>,
                         (const void*)strip_kernel<PREC_F32, true, 8>, (const void*)strip_kernel<PREC_F32, false, 8>,
                         (const void*)strip_kernel<PREC_SPLIT16, true, 8>, (const void*)strip_kernel<PREC_SPLIT16, false, 8>,
+                        (const void*)strip_kernel<PREC_F64, true, 8, 3>, (const void*)strip_kernel<PREC_F64, false, 8, 3>,
+                        (const void*)strip_kernel<PREC_F32, true, 8, 3>, (const void*)strip_kernel<PREC_F32, false, 8, 3>,
+                        (const void*)strip_kernel<PREC_SPLIT16, true, 8, 3>,
+                        (const void*)strip_kernel<PREC_SPLIT16, false, 8, 3>,
                         (const void*)stencil_fwd2_kernel<PREC_F64>, (const void*)stencil_fwd2_kernel<PREC_F32>,
                         (const void*)stencil_fwd2_kernel<PREC_SPLIT16>, (const void*)strip4_kernel<PREC_F32, true>,
                         (const void*)strip4_kernel<PREC_F32, false>, (const void*)strip4_kernel<PREC_SPLIT16, true>,
