@@ -2433,21 +2433,35 @@ __global__ __launch_bounds__(256) void transmit_kernel(const SubDev* __restrict_
 __global__ __launch_bounds__(256) void resid_kernel(const SubDev* __restrict__ subs,
                                                     const InstDev* __restrict__ insts, int ninst,
                                                     const double* __restrict__ partials, double* out) {
-  // one workgroup per instance: each subdomain's partial sums are added in a fixed order (lane
-  // strided, a butterfly within each wave, the four waves in a fixed pairing), the same for any
-  // number of instances; the instance's residual is the largest subdomain's
+  // one workgroup per instance, wave w taking subdomains w, w + 4, ..: each subdomain's partial
+  // sums are added in a fixed order (lanes strided by 64 with eight loads in flight per lane, then a
+  // butterfly within the wave, lane 0's result kept), the same for any number of instances; the
+  // instance's residual is the largest subdomain's
   __shared__ double red[4];
   const int q = blockIdx.x;
   if (q >= ninst) return;
   const InstDev& I = insts[q];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double best = 0.0;
-  for (int s = I.first_sub; s < I.first_sub + I.nsub; ++s) {
-    const int p0 = subs[s].part0, np = subs[s].nparts;
+  for (int s = I.first_sub + w; s < I.first_sub + I.nsub; s += 4) {
+    const double* __restrict__ pp = partials + subs[s].part0;
+    const int np = subs[s].nparts;
     double acc = 0.0;
-    for (int p = threadIdx.x; p < np; p += 256) acc += partials[p0 + p];
-    best = fmax(best, block_sum256(acc, red));
+    int p = lane;
+    for (; p + 7 * 64 < np; p += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[p + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; p < np; p += 64) acc += pp[p];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    best = fmax(best, acc);
   }
-  if (threadIdx.x == 0) out[q] = sqrt(best);
+  if (lane == 0) red[w] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) out[q] = sqrt(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
 }
 
 // ------------------------------------------------------------------------------------------
