@@ -2607,7 +2607,9 @@ __global__ __launch_bounds__(256) void cell_kernel(const double* __restrict__ me
   __shared__ double red[4];
   const long c0 = n0 - 1, c1 = n1 - 1, c2 = (dim == 3) ? n2 - 1 : 1;
   const long tot = c0 * c1 * c2;
-  const long v = blockIdx.x * 256L + threadIdx.x;
+  // chunk b of 256 cells from the XCD-aware order: each XCD reads one contiguous run of the mesh
+  const int tix = xcd_tile();
+  const long v = tix * 256L + threadIdx.x;
   double best = 1e300;
   if (v < tot) {
     if (dim == 2) {
@@ -2642,7 +2644,7 @@ __global__ __launch_bounds__(256) void cell_kernel(const double* __restrict__ me
     }
   }
   const double mn = block_min256(best, red);
-  if (threadIdx.x == 0) minpart[blockIdx.x] = mn;
+  if (threadIdx.x == 0) minpart[tix] = mn;
 }
 
 __global__ __launch_bounds__(256) void min_reduce_kernel(const double* __restrict__ x, long n,
@@ -2924,7 +2926,10 @@ __global__ __launch_bounds__(256) void quality_kernel(const double* __restrict__
   const int n[3] = {n0, n1, dim == 3 ? n2 : 1};
   const double h[3] = {h0, h1, h2};
   const long tot = (long)n[0] * n[1] * n[2];
-  const long v = blockIdx.x * 256L + threadIdx.x;
+  // chunk b of 256 nodes from the XCD-aware order: each XCD reads one contiguous run of the mesh
+  // (its planes then stay in one L2); partial b still belongs to chunk b
+  const int tix = xcd_tile();
+  const long v = tix * 256L + threadIdx.x;
   double sum = 0.0, mx = -1e300;
   if (v < tot) {
     const int i[3] = {(int)(v / ((long)n[1] * n[2])), (int)((v / n[2]) % n[1]), (int)(v % n[2])};
@@ -2957,8 +2962,8 @@ __global__ __launch_bounds__(256) void quality_kernel(const double* __restrict__
   __syncthreads();
   const double m = -block_min256(-mx, red);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s;
-    part[2 * blockIdx.x + 1] = m;
+    part[2 * tix] = s;
+    part[2 * tix + 1] = m;
   }
 }
 
