@@ -36,6 +36,43 @@ __device__ inline const gmem<T>* gp(const void* p) { return (const gmem<T>*)p; }
 template <typename T>
 __device__ inline gmem<T>* gpw(void* p) { return (gmem<T>*)p; }
 
+// Raw buffer view of one array (a 128-bit resource in scalar registers).  A load or store through
+// it adds a wave-uniform byte offset (scalar register) to a per-lane one (vector register) in the
+// memory unit, so forming the address costs no vector instruction, where a global access adds a
+// 64-bit base to every lane's offset.  Accesses at byte offsets of `bytes` or more read 0 and
+// write nothing (the memory unit's range check).
+struct BufView {
+  __amdgpu_buffer_rsrc_t r;
+};
+__device__ inline BufView buf_view(const void* p, unsigned bytes) {
+  // word 3 of an untyped gfx9 buffer resource with stride 0: 32-bit data, offsets in bytes
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000)};
+}
+template <typename T>
+__device__ inline T buf_ld(const BufView& b, unsigned voff, unsigned soff);
+template <>
+__device__ inline float buf_ld<float>(const BufView& b, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ inline double buf_ld<double>(const BufView& b, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+}
+__device__ inline void buf_st(const BufView& b, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b.r, (int)voff, (int)soff, 0);
+}
+__device__ inline void buf_st(const BufView& b, unsigned voff, unsigned soff, double v) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b.r, (int)voff, (int)soff, 0);
+}
+
+// The right-hand side F is evaluated by several kernels (the stencil alone, fused with the first
+// product, inside the persistent step) whose results agree to the bit.  In the code that computes
+// it, a multiply and an add are fused only where one expression holds both (explicit fma or
+// contract(on)), never across statements, where the choice would depend on each kernel's code
+// around them.
+#pragma clang fp contract(on)
+
 // ------------------------------------------------------------------------------------------
 // monitor: rho(x) as 1 + its excess, each excess evaluated without cancellation
 // ------------------------------------------------------------------------------------------
@@ -109,13 +146,20 @@ __device__ inline T sech2_of(T a4, T e) {
   const T q = T(1) + e;
   return a4 * e * frcp(q * q);
 }
+// 1 + a sech^2(z), the 1 added in the same fused multiply-add
+template <typename T>
+__device__ inline T one_plus_sech2(T a4, T e) {
+  const T q = T(1) + e;
+  return a4 * e * frcp(q * q) + T(1);
+}
 
-// log(rho (1 + e)) as one log of the product (FP64: log_pos; FP32: the hardware log2); the
-// product stays far from the denormal range while the mesh is untangled, and its rounding (one
-// unit in the last place of a number near 1) is an absolute error of the same size in F
-__device__ inline double log_rho_det(double rex, double e) { return log_pos((1.0 + rex) * (1.0 + e)); }
-__device__ inline float log_rho_det(float rex, float e) {
-  return __builtin_amdgcn_logf((1.f + rex) * (1.f + e)) * 0.693147180559945309f;
+// F = log(vol / theta) + log(rho (1 + e)), the second term as one log of the product (FP64:
+// log_pos; FP32: the hardware log2); the product stays far from the denormal range while the
+// mesh is untangled, and its rounding (one unit in the last place of a number near 1) is an
+// absolute error of the same size in F
+__device__ inline double rhs_of(double lvt, double rho, double e) { return lvt + log_pos(rho * (1.0 + e)); }
+__device__ inline float rhs_of(float lvt, float rho, float e) {
+  return __builtin_amdgcn_logf(rho * (1.f + e)) * 0.693147180559945309f + lvt;
 }
 
 __device__ inline bool is_artificial(int art, int k, int i, int n) {
@@ -153,24 +197,25 @@ __device__ inline int mhi(int i, int n) { return i < n - 1 ? i + 1 : n - 2; }
 
 // Monitor parameters of one kind, held in registers for a whole block so that evaluating rho at
 // a node reads no memory, with the constants of the exponentials pre-scaled (nk = -2 k log2 e for
-// the sech^2 kinds).  excess<DIM>(x) = rho(x) - 1.
+// the sech^2 kinds).  rho<DIM>(x) is 1 plus an excess evaluated without cancellation, the 1 added
+// in the excess's last fused multiply-add.
 template <typename T, int MK> struct MonReg;
 
 template <typename T> struct MonReg<T, MON_CONST> {
-  T ex;
-  __device__ explicit MonReg(const MonP<T>& m) : ex(m.amp - T(1)) {}
-  template <int DIM> __device__ T excess(T, T, T) const { return ex; }
+  T rh;
+  __device__ explicit MonReg(const MonP<T>& m) : rh(m.amp) {}
+  template <int DIM> __device__ T rho(T, T, T) const { return rh; }
 };
 
 template <typename T> struct MonReg<T, MON_RADIAL> {
   T a4, nk, c0, c1, c2, r02;
   __device__ explicit MonReg(const MonP<T>& m)
       : a4(T(4) * m.amp), nk(T(-2) * m.k * ExpK<T>::kLog2e), c0(m.c[0]), c1(m.c[1]), c2(m.c[2]), r02(m.r02) {}
-  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
+  template <int DIM> __device__ T rho(T x0, T x1, T x2) const {
     const T d0 = x0 - c0, d1 = x1 - c1;
     T r2 = d0 * d0 + d1 * d1;
     if (DIM == 3) r2 += (x2 - c2) * (x2 - c2);
-    return sech2_of(a4, ExpK<T>::ex(nk * fabs(r2 - r02)));
+    return one_plus_sech2(a4, ExpK<T>::ex(nk * fabs(r2 - r02)));
   }
 };
 
@@ -178,8 +223,8 @@ template <typename T> struct MonReg<T, MON_SINE> {
   T a4, nk, c1, r0;
   __device__ explicit MonReg(const MonP<T>& m)
       : a4(T(4) * m.amp), nk(T(-2) * m.k * ExpK<T>::kLog2e), c1(m.c[1]), r0(m.r0) {}
-  template <int DIM> __device__ T excess(T x0, T x1, T) const {
-    return sech2_of(a4, ExpK<T>::ex(nk * fabs(x1 - c1 - r0 * sin2pi(x0))));
+  template <int DIM> __device__ T rho(T x0, T x1, T) const {
+    return one_plus_sech2(a4, ExpK<T>::ex(nk * fabs(x1 - c1 - r0 * sin2pi(x0))));
   }
 };
 
@@ -196,8 +241,8 @@ template <typename T> struct MonReg<T, MON_GAUSS> {
       c2[b] = m.bc[b][2];
     }
   }
-  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
-    T acc = T(0);
+  template <int DIM> __device__ T rho(T x0, T x1, T x2) const {
+    T acc = T(1);
 #pragma unroll
     for (int b = 0; b < 4; ++b)
       if (b < nb) {
@@ -220,20 +265,20 @@ template <typename T> struct MonReg<T, MON_SEPARABLE> {
       c[q] = m.c[q];
     }
   }
-  __device__ T factor(int q, T x) const { return T(1) + sech2_of(a4[q], ExpK<T>::ex(nk[q] * fabs(x - c[q]))); }
-  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
+  __device__ T factor(int q, T x) const { return one_plus_sech2(a4[q], ExpK<T>::ex(nk[q] * fabs(x - c[q]))); }
+  template <int DIM> __device__ T rho(T x0, T x1, T x2) const {
     T p = factor(0, x0) * factor(1, x1);
     if (DIM == 3) p *= factor(2, x2);
-    return p - T(1);
+    return p;
   }
 };
 
-// Arc-length monitors rho = sqrt(1 + g2), g2 = |grad u|^2 (Sec. 4, eq. monitfn):
-// excess = rho - 1 = g2 / (1 + sqrt(1 + g2)), free of cancellation where g2 is small.
+// Arc-length monitors rho = sqrt(1 + g2), g2 = |grad u|^2 (Sec. 4, eq. monitfn), as 1 plus the
+// excess g2 / (1 + sqrt(1 + g2)), free of cancellation where g2 is small.
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline double fsqrt(double x) { return sqrt(x); }
 template <typename T>
-__device__ inline T arclen_excess(T g2) { return g2 * frcp(T(1) + fsqrt(T(1) + g2)); }
+__device__ inline T arclen_rho(T g2) { return g2 * frcp(T(1) + fsqrt(T(1) + g2)) + T(1); }
 
 // sine and cosine of an angle given as a * r2: FP32 takes the hardware sine and cosine, whose
 // argument is in revolutions (a pre-divided by 2 pi); FP64 calls sincos on radians.
@@ -256,9 +301,9 @@ template <typename T> struct MonReg<T, MON_ARC_FRONT> {
   T a4, nk, s0;
   __device__ explicit MonReg(const MonP<T>& m)
       : a4(T(4) * T(1.41421356237309505) / (T(8) * m.k)), nk(T(-0.5) / m.k * ExpK<T>::kLog2e), s0(m.r0) {}
-  template <int DIM> __device__ T excess(T x0, T x1, T) const {
+  template <int DIM> __device__ T rho(T x0, T x1, T) const {
     const T g = sech2_of(a4, ExpK<T>::ex(nk * fabs(x0 + x1 - s0)));
-    return arclen_excess(g * g);
+    return arclen_rho(g * g);
   }
 };
 
@@ -269,7 +314,7 @@ template <typename T> struct MonReg<T, MON_ARC_SPIRAL> {
   T amp, kq, w2, wt, c0, c1;
   __device__ explicit MonReg(const MonP<T>& m)
       : amp(m.amp), kq(m.k), w2(T(2) * m.tw), wt(m.tw * Turn<T>::kScale), c0(m.c[0]), c1(m.c[1]) {}
-  template <int DIM> __device__ T excess(T x0, T x1, T) const {
+  template <int DIM> __device__ T rho(T x0, T x1, T) const {
     const T d0 = x0 - c0, d1 = x1 - c1;
     const T r2 = d0 * d0 + d1 * d1;
     T S, C;
@@ -278,7 +323,7 @@ template <typename T> struct MonReg<T, MON_ARC_SPIRAL> {
     const T q1 = T(1) + kq * P * P;
     const T f = T(2) * amp * kq * P * frcp(q1 * q1);
     const T g0 = f * (C + w2 * Q * d0), g1 = f * (S + w2 * Q * d1);
-    return arclen_excess(g0 * g0 + g1 * g1);
+    return arclen_rho(g0 * g0 + g1 * g1);
   }
 };
 
@@ -296,7 +341,7 @@ template <typename T> struct MonReg<T, MON_ARC_SPHERES> {
       c2[b] = m.bc[b][2];
     }
   }
-  template <int DIM> __device__ T excess(T x0, T x1, T x2) const {
+  template <int DIM> __device__ T rho(T x0, T x1, T x2) const {
     T g0 = T(0), g1 = T(0), g2 = T(0);
 #pragma unroll
     for (int b = 0; b < kMaxBumps; ++b)
@@ -308,7 +353,7 @@ template <typename T> struct MonReg<T, MON_ARC_SPHERES> {
         g1 += s * d1;
         g2 += s * d2;
       }
-    return arclen_excess(g0 * g0 + g1 * g1 + g2 * g2);
+    return arclen_rho(g0 * g0 + g1 * g1 + g2 * g2);
   }
 };
 
@@ -318,10 +363,14 @@ template <typename T> struct MonReg<T, MON_ARC_SPHERES> {
 // of its line, and the update kernels flag a non-finite update.
 template <typename T>
 struct NodeCheck {
-  bool tangled = false;  // a lane mask: one compare per node, the or on the scalar unit
-  // a NaN (a state already non-finite, flagged by the update) does not count as tangled
-  __device__ inline void add(T one_plus_e) { tangled = tangled || one_plus_e <= T(0); }
-  __device__ inline int bits() const { return tangled ? ST_TANGLED : 0; }
+  // the least 1 + e this lane has seen, kept by a compare and a select per node (a flag kept per
+  // lane across the store's branch costs two vector instructions more); a NaN never compares
+  // less, so a state already non-finite (flagged by the update) does not count as tangled
+  T lo = T(1);
+  __device__ inline void add(T one_plus_e) { lo = one_plus_e < lo ? one_plus_e : lo; }
+  // only where `on` (a node that is not artificial)
+  __device__ inline void add_if(bool on, T one_plus_e) { lo = on && one_plus_e < lo ? one_plus_e : lo; }
+  __device__ inline int bits() const { return lo <= T(0) ? ST_TANGLED : 0; }
 };
 
 // Per-workgroup constants of a subdomain, copied into registers once.
@@ -331,16 +380,6 @@ struct StencilCtx {
   int n0, n1, n2, off0, off1, off2, art, inst;
 };
 
-// Global-memory view of a pointer taken from a descriptor (see gmem): loads and stores through it
-// are global (not flat), and a wave-uniform base keeps their addresses in scalar registers.
-template <typename T>
-__device__ inline const gmem<T>* byte_off(const gmem<T>* base, unsigned off) {
-  return (const gmem<T>*)((const gmem<char>*)base + off);
-}
-template <typename T>
-__device__ inline gmem<T>* byte_off(gmem<T>* base, unsigned off) {
-  return (gmem<T>*)((gmem<char>*)base + off);
-}
 
 constexpr int kStR = 16;                               // output rows per chunk (2D: i0, 3D: i1)
 constexpr int kStWmax = 72;                            // widest block along the last axis
@@ -377,13 +416,14 @@ __device__ inline HaloCols halo_cols(int col0, int W, int n) {
   return h;
 }
 
-// rowp[k]: base of staged row wave + 4 k; rowE: base of the row of this thread's extra element
+// rowo[k]: byte offset of staged row wave + 4 k (wave-uniform); this thread's extra element sits
+// at byte offset vE (per lane) + sE (wave-uniform)
 template <typename T>
-__device__ inline void halo_issue(T (&pre)[kStPre], const HaloCols& hc, const gmem<T>* const (&rowp)[kStLd],
-                                  const gmem<T>* rowE) {
+__device__ inline void halo_issue(T (&pre)[kStPre], const HaloCols& hc, const BufView& src,
+                                  const unsigned (&rowo)[kStLd], unsigned vE, unsigned sE) {
 #pragma unroll
-  for (int k = 0; k < kStLd; ++k) pre[k] = *byte_off(rowp[k], hc.bA);
-  pre[kStLd] = *byte_off(rowE, hc.bE);
+  for (int k = 0; k < kStLd; ++k) pre[k] = buf_ld<T>(src, hc.bA, rowo[k]);
+  pre[kStLd] = buf_ld<T>(src, vE, sE);
 }
 
 template <typename T>
@@ -448,11 +488,11 @@ struct Slots2 {
 template <typename T, int MK>
 __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp, const T* phi_, T* F_, T* sm,
                                       int row0, int nrows, int col0, int W, int& bad) {
-  const gmem<T>* __restrict__ phi = (const gmem<T>*)phi_;
-  gmem<T>* __restrict__ F = (gmem<T>*)F_;
   const MonReg<T, MK> M(mp);
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int n0 = K.n0, n1 = K.n1;
+  const unsigned rowb = (unsigned)n1 * sizeof(T);  // bytes per row
+  const BufView phi = buf_view(phi_, (unsigned)n0 * rowb), F = buf_view(F_, (unsigned)n0 * rowb);
   const HaloCols hc = halo_cols<T>(col0, W, n1);
   const T h0 = K.h0, h1 = K.h1;
   Slots2<T> sl;
@@ -464,7 +504,7 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
     sl.lds[m] = (unsigned)(ok ? rr * kStS + cc : 0) * sizeof(T);
     sl.out[m] = (unsigned)(rr * n1 + cc) * sizeof(T);
     sl.row[m] = ok ? rr : kStR;
-    sl.xc[m] = K.a1 + T(K.off1 + col0 + cc) * h1;
+    sl.xc[m] = fma(T(K.off1 + col0 + cc), h1, K.a1);
     sl.gr[m] = T(K.off0 + row0 + (ok ? rr : 0));
     sl.valid[m] = __ballot(ok);
     sl.live[m] = __ballot(ok && !is_artificial(K.art, 1, col0 + cc, n1));
@@ -476,11 +516,23 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
   // two chunks' loads in flight: the registers of chunk k are reloaded with chunk k + 2 as soon
   // as chunk k is in LDS (the loop is unrolled by two so each register set has fixed names)
   T preA[kStPre], preB[kStPre];
+  // the row of this thread's extra element, rb + rE - 1, needs no mirror away from the array's
+  // first and last rows: its offset is then a per-block one plus a wave-uniform one
+  const unsigned vEi = hc.bE + (unsigned)hc.rE * rowb;
   auto issue = [&](T (&pre)[kStPre], int rb) {
-    const gmem<T>* rowp[kStLd];
+    unsigned rowo[kStLd];
 #pragma unroll
-    for (int k = 0; k < kStLd; ++k) rowp[k] = phi + (long)mirror_clamp(rb + wv + 4 * k - 1, n0) * n1;
-    halo_issue(pre, hc, rowp, phi + (long)mirror_clamp(rb + hc.rE - 1, n0) * n1);
+    for (int k = 0; k < kStLd; ++k) rowo[k] = (unsigned)mirror_clamp(rb + wv + 4 * k - 1, n0) * rowb;
+    unsigned vE, sE;
+    if (rb >= 1 && rb + kStHR - 2 <= n0 - 1) {
+      vE = vEi;
+      sE = (unsigned)(rb - 1) * rowb;
+    } else {
+      asm volatile("");  // keeps the per-lane mirror in this (rare, uniform) branch
+      vE = hc.bE + (unsigned)mirror_clamp(rb + hc.rE - 1, n0) * rowb;
+      sE = 0;
+    }
+    halo_issue(pre, hc, phi, rowo, vE, sE);
   };
   // EDGE: the first or last chunk of the block, whose rows may lie beyond the block or on an
   // artificial face; its flags are derived per node, the interior chunks use the block's masks
@@ -493,7 +545,7 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
     // memory operations between a load and its use must not depend on the path, or the wait
     // before the commit would have to drain the other register set's loads as well
     issue(pre, rb + 2 * kStR);
-    gmem<T>* Fc = F + (long)rb * n1 + col0;
+    const unsigned Fc = (unsigned)(rb * n1 + col0) * sizeof(T);  // the chunk's output block
     const int rlim = min(kStR, rend - rb);
     const int rlo = (rb == 0 && (K.art & 1)) ? 0 : -1;
     const int rhi = (rb + kStR > n0 - 1 && (K.art & 2)) ? n0 - 1 - rb : -1;
@@ -510,17 +562,17 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
         const T* t = (const T*)((const char*)sm + sl.lds[m]);  // upper-left neighbour
         const T c0 = t[kStS + 1];
         const T xm = t[1], xp = t[2 * kStS + 1], ym = t[kStS], yp = t[kStS + 2];
-        const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
         const T hxx = (xp - T(2) * c0 + xm) * rh00;
         const T hyy = (yp - T(2) * c0 + ym) * rh11;
         const T hxy = (t[2 * kStS + 2] - t[2 * kStS] - t[2] + t[0]) * r4h01;
         const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
-        // a + (global index) h, rounded as for any other tiling of the same grid
-        const T x0 = K.a0 + sl.gr[m] * h0 + gx;
-        const T fv = K.lvt + log_rho_det(M.template excess<2>(x0, sl.xc[m] + gy, T(0)), e);
+        // x + grad phi: the node's coordinate a + (global index) h, then the central difference
+        const T x0 = fma(xp - xm, r2h0, fma(sl.gr[m], h0, K.a0));
+        const T x1 = fma(yp - ym, r2h1, sl.xc[m]);
+        const T fv = rhs_of(K.lvt, M.template rho<2>(x0, x1, T(0)), e);
         const T f = lv ? fv : T(0);
-        chk.add(lv ? T(1) + e : T(1));
-        if (st) *byte_off(Fc, sl.out[m]) = f;
+        chk.add_if(lv, T(1) + e);
+        if (st) buf_st(F, sl.out[m], Fc, f);
       }
       sl.gr[m] += T(kStR);
     }
@@ -548,12 +600,18 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
 template <typename T, int MK>
 __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp, const T* phi_, T* F_, T* sm,
                                       int p0, int np, int row0, int col0, int W, int& bad) {
-  const gmem<T>* __restrict__ phi = (const gmem<T>*)phi_;
-  gmem<T>* __restrict__ F = (gmem<T>*)F_;
   const MonReg<T, MK> M(mp);
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int n0 = K.n0, n1 = K.n1, n2 = K.n2;
+  const unsigned rowb = (unsigned)n2 * sizeof(T), plb = (unsigned)n1 * rowb;  // bytes per row, plane
+  // one buffer view per plane (a subdomain may exceed the 4 GiB reach of a view's offsets)
+  auto plane = [&](const void* a, int p) { return buf_view((const char*)a + (size_t)p * plb, plb); };
   const HaloCols hc = halo_cols<T>(col0, W, n2);
+  // the staged rows of the block are the same on every plane
+  unsigned rowo[kStLd];
+#pragma unroll
+  for (int k = 0; k < kStLd; ++k) rowo[k] = (unsigned)mirror_clamp(row0 + wv + 4 * k - 1, n1) * rowb;
+  const unsigned vE = hc.bE + (unsigned)mirror_clamp(row0 + hc.rE - 1, n1) * rowb;
   constexpr int PL = kStHR * kStS;
   const T h0 = K.h0, h1 = K.h1, h2 = K.h2;
   Slots<T> sl;
@@ -569,8 +627,8 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
     sl.lds[m] = ok ? (rr + 1) * kStS + cc + 1 : kStS + 1;
     sl.out[m] = (unsigned)(rr * n2 + cc) * sizeof(T);
     sl.row[m] = ok ? rr : kStR;
-    sl.xc[m] = K.a2 + T(K.off2 + k) * h2;
-    x1s[m] = K.a1 + T(K.off1 + j) * h1;
+    sl.xc[m] = fma(T(K.off2 + k), h2, K.a2);
+    x1s[m] = fma(T(K.off1 + j), h1, K.a1);
     sl.valid |= ok ? 1 << m : 0;
     sl.live |= (ok && !is_artificial(K.art, 1, j, n1) && !is_artificial(K.art, 2, k, n2)) ? 1 << m : 0;
   }
@@ -582,14 +640,8 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
   // plane p0 - 1 -> LDS slot 0, p0 -> slot 1, p0 + q + 1 -> slot (q + 2) % 3; two planes' loads in
   // flight (register sets A / B alternate, the loop is unrolled by two)
   T preA[kStPre], preB[kStPre];
-  auto issue = [&](T (&pre)[kStPre], int p) {
-    const long pbase = (long)mirror_clamp(p, n0) * n1;
-    const gmem<T>* rowp[kStLd];
-#pragma unroll
-    for (int k = 0; k < kStLd; ++k) rowp[k] = phi + (pbase + mirror_clamp(row0 + wv + 4 * k - 1, n1)) * n2;
-    halo_issue(pre, hc, rowp, phi + (pbase + mirror_clamp(row0 + hc.rE - 1, n1)) * n2);
-  };
-  auto plane = [&](T (&pre)[kStPre], int q) {
+  auto issue = [&](T (&pre)[kStPre], int p) { halo_issue(pre, hc, plane(phi_, mirror_clamp(p, n0)), rowo, vE, 0u); };
+  auto step = [&](T (&pre)[kStPre], int q) {
     const int p = p0 + q;
     __syncthreads();  // the slot about to be refilled is no longer read
     halo_commit(sm + ((q + 2) % 3) * PL, hc, pre);
@@ -597,8 +649,9 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
     issue(pre, p + 3);  // unconditional, as in the 2D march
     const int sp = (q % 3) * PL, scur = ((q + 1) % 3) * PL, sn = ((q + 2) % 3) * PL;
     const int live = is_artificial(K.art, 0, p, n0) ? 0 : sl.live;
-    const T x0b = K.a0 + T(K.off0 + p) * h0;
-    gmem<T>* Fc = F + ((long)p * n1 + row0) * n2 + col0;
+    const T x0b = fma(T(K.off0 + p), h0, K.a0);
+    const BufView Fp = plane(F_, p);
+    const unsigned Fc = (unsigned)(row0 * n2 + col0) * sizeof(T);  // the plane's output block
 #pragma unroll
     for (int m = 0; m < kStPts; ++m) {
       if (!((sl.wave >> m) & 1)) continue;  // no node of this wave in slot m (uniform branch)
@@ -609,7 +662,6 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
       const T xm = a[0], xp = b[0];
       const T ym = c[-kStS], yp = c[kStS];
       const T zm = c[-1], zp = c[1];
-      const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1, gz = (zp - zm) * r2h2;
       const T d00 = (xp - T(2) * c0 + xm) * rh00;
       const T d11 = (yp - T(2) * c0 + ym) * rh11;
       const T d22 = (zp - T(2) * c0 + zm) * rh22;
@@ -621,11 +673,13 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
       const T m2 = (d00 * d11 - d01 * d01) + (d00 * d22 - d02 * d02) + (d11 * d22 - d12 * d12);
       const T d3 = d00 * (d11 * d22 - d12 * d12) - d01 * (d01 * d22 - d12 * d02) + d02 * (d01 * d12 - d11 * d02);
       const T e = tr + m2 + d3;
-      const T fv = K.lvt + log_rho_det(M.template excess<3>(x0b + gx, x1s[m] + gy, sl.xc[m] + gz), e);
+      // x + grad phi (central differences)
+      const T y0 = fma(xp - xm, r2h0, x0b), y1 = fma(yp - ym, r2h1, x1s[m]), y2 = fma(zp - zm, r2h2, sl.xc[m]);
+      const T fv = rhs_of(K.lvt, M.template rho<3>(y0, y1, y2), e);
       const bool lv = (live >> m) & 1;
       const T f = lv ? fv : T(0);
-      chk.add(lv ? T(1) + e : T(1));
-      if ((sl.valid >> m) & 1) *byte_off(Fc, sl.out[m]) = f;
+      chk.add_if(lv, T(1) + e);
+      if ((sl.valid >> m) & 1) buf_st(Fp, sl.out[m], Fc, f);
     }
   };
   vmem_drain();
@@ -637,12 +691,14 @@ __device__ inline void stencil_march3(const StencilCtx<T>& K, const MonP<T>& mp,
   issue(preB, p0 + 2);
   int q = 0;
   for (; q + 1 < np; q += 2) {  // both planes of a pair on every path
-    plane(preA, q);
-    plane(preB, q + 1);
+    step(preA, q);
+    step(preB, q + 1);
   }
-  if (q < np) plane(preA, q);
+  if (q < np) step(preA, q);
   bad |= chk.bits();
 }
+
+#pragma clang fp contract(fast)  // the compiler's default for HIP again
 
 template <typename T>
 __device__ inline const MonP<T>* load_ctx(const StepArgs& sa, int sub, StencilCtx<T>& K, const T*& phi, T*& F) {
@@ -2143,6 +2199,8 @@ __host__ __device__ inline int fused_halo_bytes(int ld) {
   return ((18 * (ld + 4) * (int)sizeof(typename Op<KIND>::T) + 1023) / 1024) * 1024;
 }
 
+// (multiplies and adds fused as in the stencil kernels: see the note above the monitor code)
+#pragma clang fp contract(on)
 template <int KIND, int MK>
 __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K,
                                     const MonReg<typename Op<KIND>::T, MK>& M, const typename Op<KIND>::T* halo,
@@ -2159,7 +2217,7 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K,
   for (int k = 0; k < 16 / kFuseWaves; ++k) {
     const int rr = wave + kFuseWaves * k, i = row0 + rr;
     const bool rlive = i < n0 && !is_artificial(K.art, 0, i, n0);
-    const T x0b = K.a0 + T(K.off0 + i) * h0;
+    const T x0b = fma(T(K.off0 + i), h0, K.a0);
 #pragma unroll
     for (int u = 0; u < kFuseU; ++u) {
       const int j = lane + 64 * u;
@@ -2169,13 +2227,14 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K,
         const T* c = halo + (rr + 1) * HS + j + 1;
         const T c0 = c[0];
         const T xm = c[-HS], xp = c[HS], ym = c[-1], yp = c[1];
-        const T gx = (xp - xm) * r2h0, gy = (yp - ym) * r2h1;
         const T hxx = (xp - T(2) * c0 + xm) * rh00;
         const T hyy = (yp - T(2) * c0 + ym) * rh11;
         const T hxy = (c[HS + 1] - c[HS - 1] - c[-HS + 1] + c[-HS - 1]) * r4h01;
         const T e = hxx + hyy + (hxx * hyy - hxy * hxy);  // det(I + D^2 phi) - 1
-        const T x1 = K.a1 + T(K.off1 + j) * h1 + gy;
-        f = K.lvt + log_rho_det(M.template excess<2>(x0b + gx, x1, T(0)), e);
+        // x + grad phi: the node's coordinate a + (global index) h, then the central difference
+        const T x0 = fma(xp - xm, r2h0, x0b);
+        const T x1 = fma(yp - ym, r2h1, fma(T(K.off1 + j), h1, K.a1));
+        f = rhs_of(K.lvt, M.template rho<2>(x0, x1, T(0)), e);
         chk.add(T(1) + e);
       }
       O::put(op, ldo, rr, j, f);
@@ -2183,6 +2242,8 @@ __device__ inline void fused_nodes2(const StencilCtx<typename Op<KIND>::T>& K,
     }
   }
 }
+
+#pragma clang fp contract(fast)  // the compiler's default for HIP again
 
 // One tile of the fused kernel for monitor kind MK.  Every descriptor and monitor field is read
 // into registers first: a read after the basis copy or a barrier could not use the scalar cache
@@ -2994,7 +3055,7 @@ __global__ __launch_bounds__(256) void quality_kernel(const double* __restrict__
                      Jm[0][1] * (Jm[1][0] * Jm[2][2] - Jm[1][2] * Jm[2][0]) +
                      Jm[0][2] * (Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0]);
     const MonReg<double, MK> M(mp);
-    const double rho = 1.0 + (dim == 3 ? M.template excess<3>(x[0], x[1], x[2]) : M.template excess<2>(x[0], x[1], 0.0));
+    const double rho = dim == 3 ? M.template rho<3>(x[0], x[1], x[2]) : M.template rho<2>(x[0], x[1], 0.0);
     const double E = vol_theta * rho * J;
     sum = w * E * E;
     mx = E;
