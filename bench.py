@@ -425,6 +425,27 @@ def shell_bench(ctx, binding, workloads, steps, warmup):
             "phases_ms_per_launch": {p: round(v["ms"], 5) for p, v in r["phases"].items()}}
 
 
+def copy_bandwidth(mib=1024, reps=20):
+    """Device-to-device copy of a MIB-sized float32 buffer (torch's copy kernel), HIP events around
+    REPS copies: the read + write bandwidth a plain streaming kernel reaches on this GPU, the
+    practical ceiling beside the 8 TB/s peak for a kernel that reads and writes equal amounts."""
+    import torch
+    a = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / sec / 1e9
+
+
 def stencil_roofline(ctx, binding, workloads):
     """Stencil phase alone over two 8193^2 DD requests (32 x 32 parts): 134 M nodes, 1.07 GB of
     compulsory FP32 traffic per launch, far beyond the 256 MB last-level cache."""
@@ -443,6 +464,10 @@ def stencil_roofline(ctx, binding, workloads):
            "bytes_per_launch": st["bytes"], "avg_launch_ms": st["ms"],
            "stencil_march": march, "autotune_ms": [round(t, 4) for t in cand],
            "workload": "2 x 8193^2 sine layer, 32x32 parts, FP32 (8 B per node)"}
+    # the same bytes against what a plain 1 GiB copy reaches on this GPU (read + write, 1:1)
+    cp = copy_bandwidth()
+    out["copy_GBs"] = cp
+    out["frac_of_copy"] = gbs / cp
     # the vector-ALU view of the same launch: issue cycles per node from the committed SQ counters
     a = profile_entry("stencil_large_alu", f"stencil@march={march}")
     if a is not None:
