@@ -36,11 +36,11 @@ __device__ inline const gmem<T>* gp(const void* p) { return (const gmem<T>*)p; }
 template <typename T>
 __device__ inline gmem<T>* gpw(void* p) { return (gmem<T>*)p; }
 
-// Raw buffer view of one array (a 128-bit resource in scalar registers).  A load or store through
-// it adds a wave-uniform byte offset (scalar register) to a per-lane one (vector register) in the
-// memory unit, so forming the address costs no vector instruction, where a global access adds a
-// 64-bit base to every lane's offset.  Accesses at byte offsets of `bytes` or more read 0 and
-// write nothing (the memory unit's range check).
+// Raw buffer view of one array of `bytes` bytes (a 128-bit resource in scalar registers).  A load or
+// store through it adds a wave-uniform byte offset (scalar register) to a per-lane one (vector
+// register) in the memory unit, so forming the address costs no vector instruction, where a global
+// access adds a 64-bit base to every lane's offset.  Callers keep every offset inside the array;
+// the size in the resource is the array's, not a bound they rely on.
 struct BufView {
   __amdgpu_buffer_rsrc_t r;
 };
