@@ -1099,6 +1099,55 @@ __device__ inline int kext(int n) {
   return (n + Op<KIND>::KB - 1) / Op<KIND>::KB * Op<KIND>::KB;
 }
 
+// acc[t] += basis rows (row block wave + NW t, basis from L2) x the LDS data operand over k < ke,
+// k outermost: the N row blocks of the wave advance together, each accumulator in ascending k
+// (the order of mma_basis_by_lds, so the results are the same bits), the data fragment of a k step
+// read once for all of them, and the basis fragments of GU k steps of all N blocks requested
+// before the first product.  N: the wave's count of existing row blocks (uniform), chosen once.
+template <int KIND, int NW, int RB, int N, int GU>
+__device__ inline void mma_gbasis_rows_n(typename Op<KIND>::acc_t (&acc)[RB], const void* bh, const void* bl,
+                                         int ldb, const char* lds, int ke, int ldo, float sc, int wave, int l16,
+                                         int g) {
+  typedef Op<KIND> O;
+  int row[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) row[t] = (wave + NW * t) * 16 + l16;
+  int k0 = 0;
+  for (; k0 + GU * O::KB <= ke; k0 += GU * O::KB) {
+    typename O::frag a[GU][N];
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+#pragma unroll
+      for (int t = 0; t < N; ++t) a[u][t] = O::glob_frag(bh, bl, ldb, row[t], k0 + u * O::KB, g);
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const typename O::frag b = O::lds_frag(lds, ldo, l16, k0 + u * O::KB, g, sc);
+#pragma unroll
+      for (int t = 0; t < N; ++t) O::mma(acc[t], a[u][t], b);
+    }
+  }
+  for (; k0 < ke; k0 += O::KB) {
+    typename O::frag a[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) a[t] = O::glob_frag(bh, bl, ldb, row[t], k0, g);
+    const typename O::frag b = O::lds_frag(lds, ldo, l16, k0, g, sc);
+#pragma unroll
+    for (int t = 0; t < N; ++t) O::mma(acc[t], a[t], b);
+  }
+}
+
+template <int KIND, int NW, int RB, int GU, int N = RB>
+__device__ inline void mma_gbasis_rows(typename Op<KIND>::acc_t (&acc)[RB], const void* bh, const void* bl, int ldb,
+                                       const char* lds, int ke, int ldo, float sc, int wave, int nrb, int l16,
+                                       int g) {
+  if constexpr (N > 0) {
+    if (wave + NW * (N - 1) < nrb)
+      mma_gbasis_rows_n<KIND, NW, RB, N, GU>(acc, bh, bl, ldb, lds, ke, ldo, sc, wave, l16, g);
+    else
+      mma_gbasis_rows<KIND, NW, RB, GU, N - 1>(acc, bh, bl, ldb, lds, ke, ldo, sc, wave, nrb, l16, g);
+  }
+}
+
 // Products with a basis copy in LDS take at most 12 row (column) blocks: three per wave.
 constexpr int kLdsRb = 3;
 
@@ -1650,6 +1699,8 @@ __device__ inline void strip_tile(int tix, const int4* __restrict__ tiles, int a
     mma_lbasis_rows<KIND, NW, RBL>(a3, lbh, lbl, ldb, lds, ld, ldo, sc, uwave, nrb, l16, g);
 #pragma unroll
     for (int t = 0; t < RBL; ++t) acc[t] = a3[t];
+  } else if constexpr (KIND == PREC_F64 && MAXRB <= 3) {  // FP64, three row blocks per wave: k outermost
+    mma_gbasis_rows<KIND, NW, MAXRB, 2>(acc, b1h, b1l, ldb, lds, kext<KIND>(K), ldo, sc, uwave, nrb, l16, g);
   } else {
 #pragma unroll
     for (int t = 0; t < MAXRB; ++t) {
@@ -1727,6 +1778,8 @@ __device__ inline void strip_tile(int tix, const int4* __restrict__ tiles, int a
       mma_lbasis_rows<KIND, NW, RBL>(a3, lbh, lbl, ldb, lds, ld, ldo, sy, uwave, nrb, l16, g);
 #pragma unroll
       for (int t = 0; t < RBL; ++t) acc[t] = a3[t];
+    } else if constexpr (KIND == PREC_F64 && MAXRB <= 3) {
+      mma_gbasis_rows<KIND, NW, MAXRB, 2>(acc, b1h, b1l, ldb, lds, kext<KIND>(K), ldo, sy, uwave, nrb, l16, g);
     } else {
 #pragma unroll
       for (int t = 0; t < MAXRB; ++t) {
