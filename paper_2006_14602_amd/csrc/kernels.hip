@@ -492,6 +492,7 @@ __device__ inline void stencil_march2(const StencilCtx<T>& K, const MonP<T>& mp,
   const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int n0 = K.n0, n1 = K.n1;
   const unsigned rowb = (unsigned)n1 * sizeof(T);  // bytes per row
+  // one view per array: a 2D subdomain (axes of at most 1025 nodes) holds at most 8.4 MB
   const BufView phi = buf_view(phi_, (unsigned)n0 * rowb), F = buf_view(F_, (unsigned)n0 * rowb);
   const HaloCols hc = halo_cols<T>(col0, W, n1);
   const T h0 = K.h0, h1 = K.h1;
